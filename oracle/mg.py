@@ -1,0 +1,102 @@
+"""Geometric multigrid V-cycle (TEST INFRASTRUCTURE ONLY; see ``oracle/__init__``).
+
+Components named in Sec. 1 and Sec. 3.2 (proof of concept): a V(1,1)-cycle
+with an omega-Jacobi smoother, full-weighting restriction and bilinear
+interpolation.  Readings where the paper is silent: coarse operators are
+rediscretised at 2h; the coarsest level is solved exactly by a dense LU
+factorisation (partial pivoting, FP64); the transfer stencils use the
+standard index-space weights, also inside the complex-scaled layer.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+from .grid import Grid1D, Operator, tp_operator
+
+
+def jacobi(op: Operator, u: np.ndarray, f: np.ndarray, omega: float) -> np.ndarray:
+    """One omega-Jacobi sweep u <- u + omega D^{-1} (f - A u) (new array)."""
+    n = op.n
+    r = op.residual(u, f)
+    out = u.copy()
+    out[1:n, 1:n] += omega * r[1:n, 1:n] / op.diag[1:n, 1:n]
+    return out
+
+
+def restrict_fw(r: np.ndarray) -> np.ndarray:
+    """Full weighting (1/16)[1 2 1; 2 4 2; 1 2 1] onto the coarse interior."""
+    n = r.shape[0] - 1
+    nc = n // 2
+    out = np.zeros((nc + 1, nc + 1), r.dtype)
+    K = slice(2, n - 1, 2)                   # fine index 2K for K = 1..nc-1
+    Km, Kp = slice(1, n - 2, 2), slice(3, n, 2)
+    out[1:nc, 1:nc] = (4.0 * r[K, K]
+                       + 2.0 * (r[Km, K] + r[Kp, K] + r[K, Km] + r[K, Kp])
+                       + r[Km, Km] + r[Km, Kp] + r[Kp, Km] + r[Kp, Kp]) / 16.0
+    return out
+
+
+def prolong_bilinear(ec: np.ndarray) -> np.ndarray:
+    """Bilinear interpolation of a coarse field (zero ring) to the fine grid."""
+    nc = ec.shape[0] - 1
+    n = 2 * nc
+    e = np.zeros((n + 1, n + 1), ec.dtype)
+    e[0::2, 0::2] = ec
+    e[0::2, 1::2] = 0.5 * (ec[:, :-1] + ec[:, 1:])
+    e[1::2, 0::2] = 0.5 * (ec[:-1, :] + ec[1:, :])
+    e[1::2, 1::2] = 0.25 * (ec[:-1, :-1] + ec[:-1, 1:] + ec[1:, :-1] + ec[1:, 1:])
+    return e
+
+
+class CoarsestSolver:
+    """Dense LU (partial pivoting) of the coarsest operator."""
+
+    def __init__(self, op: Operator):
+        self.op = op
+        A = op.sparse().toarray()
+        self.lu = sla.lu_factor(A)
+
+    def solve(self, f: np.ndarray) -> np.ndarray:
+        n = self.op.n
+        u = np.zeros_like(f)
+        u[1:n, 1:n] = sla.lu_solve(self.lu, f[1:n, 1:n].ravel()).reshape(n - 1, n - 1)
+        return u
+
+
+class Hierarchy:
+    """Operators on every level: level 0 finest, level ``levels-1`` coarsest.
+
+    ``gammas[l]`` is the interior contour rotation of level l (all zero: every
+    level is the exterior-complex-scaled operator)."""
+
+    def __init__(self, g: Grid1D, Z1: float, Z2: float, lam: float, E: float,
+                 levels: int, omega: float = 2.0 / 3.0, nu1: int = 1, nu2: int = 1,
+                 gammas=None):
+        if levels < 1:
+            raise ValueError("levels >= 1")
+        gammas = [g.gamma] * levels if gammas is None else list(gammas)
+        grids = [Grid1D(g.n, g.L, g.R0, g.theta, gammas[0])]
+        for l in range(1, levels):
+            grids.append(grids[-1].coarsen(gammas[l]))
+        self.ops = [tp_operator(gl, Z1, Z2, lam, E) for gl in grids]
+        self.coarsest = CoarsestSolver(self.ops[-1])
+        self.omega, self.nu1, self.nu2 = omega, nu1, nu2
+
+    @property
+    def levels(self) -> int:
+        return len(self.ops)
+
+    def vcycle(self, u: np.ndarray, f: np.ndarray, level: int = 0) -> np.ndarray:
+        """One V(nu1, nu2)-cycle on ``level`` starting from ``u`` (new array)."""
+        op = self.ops[level]
+        if level == self.levels - 1:
+            return self.coarsest.solve(f)
+        for _ in range(self.nu1):
+            u = jacobi(op, u, f, self.omega)
+        fc = restrict_fw(op.residual(u, f))
+        ec = self.vcycle(np.zeros_like(fc), fc, level + 1)
+        u = u + prolong_bilinear(ec)
+        for _ in range(self.nu2):
+            u = jacobi(op, u, f, self.omega)
+        return u

@@ -1,0 +1,157 @@
+"""Outer iterations around one MG-CCCS cycle (TEST INFRASTRUCTURE ONLY).
+
+* Stationary MG-CCCS: repeat {V-cycle; CCCS} (Sec. 6.1).
+* FGMRES(m) right-preconditioned by one MG-CCCS cycle started from zero
+  (Sec. 6, "only one MG-CCCS V-cycle is used to approximately solve the
+  preconditioning system"; Table 1), classical Gram-Schmidt with one
+  re-orthogonalisation, Givens rotations, true residual at every restart.
+* Iterative refinement: r = f - A u, s = sqrt(N)/||r||_2 (RMS scaling),
+  e = k cycles on A e = s r from zero, u += e/s.  (Reading; the paper has no
+  mixed-precision loop.)
+
+Preconditioning hierarchy.  The cycle may act on the complex-contour operator
+of Sec. 3.1 (interior rotated by ``pc_gamma``) on levels >= ``pc_first_level``
+while the outer iteration solves the exterior-complex-scaled system; with
+``pc_gamma = 0`` the cycle uses the exact operator on every level.
+
+All stop tests use ||f - A u||_2 / ||f||_2 over the interior (Table 1 caption).
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+from .cccs import CCCS
+from .grid import Grid1D, rel_residual, tp_operator, tp_rhs
+from .mg import Hierarchy
+
+
+@dataclasses.dataclass
+class SolveResult:
+    u: np.ndarray
+    relres: float
+    iters: int
+    vcycles: int
+    history: list
+
+
+class MGCCCS:
+    """Multigrid hierarchy plus channel correction for one (grid, potential, E)."""
+
+    def __init__(self, n, L, R0, theta, Z1, Z2, lam, E, levels, M,
+                 omega=2.0 / 3.0, nu1=1, nu2=1, Lch=None, refine_steps=2,
+                 pc_gamma=0.0, pc_first_level=0):
+        self.g = Grid1D(n, L, R0, theta)
+        self.Z1, self.Z2, self.lam, self.E = Z1, Z2, lam, E
+        gammas = [pc_gamma if l >= pc_first_level else 0.0 for l in range(levels)]
+        self.mg = Hierarchy(self.g, Z1, Z2, lam, E, levels, omega, nu1, nu2, gammas)
+        self.op = tp_operator(self.g, Z1, Z2, lam, E)       # exact operator
+        self.pc_op = self.mg.ops[0]                         # level 0 of the hierarchy
+        self.M = M
+        self.cc = CCCS(self.pc_op, M, Lch, refine_steps) if M > 0 else None
+
+    @classmethod
+    def from_workload(cls, w, **kw):
+        return cls(w.n, w.L, w.R0, w.theta, w.Z1, w.Z2, w.lam, w.E, w.levels, w.M,
+                   w.omega, w.nu1, w.nu2, **kw)
+
+    def rhs(self) -> np.ndarray:
+        return tp_rhs(self.g, self.Z1, self.Z2, self.lam, self.E)
+
+    def cycle(self, u: np.ndarray, f: np.ndarray) -> np.ndarray:
+        """One MG-CCCS cycle: V-cycle, then the channel correction."""
+        u = self.mg.vcycle(u, f)
+        if self.cc is not None:
+            u = self.cc.step(u, f)
+        return u
+
+    def precondition(self, v: np.ndarray) -> np.ndarray:
+        """z = one MG-CCCS cycle on A z = v from z = 0 (a fixed linear map)."""
+        return self.cycle(np.zeros_like(v), v)
+
+    # ------------------------------------------------------------------ #
+    def solve_stationary(self, u, f, tol, max_it=200) -> SolveResult:
+        """Repeat the cycle on the exact system (needs an exact level 0)."""
+        if self.pc_op.g.gamma != 0.0:
+            raise ValueError("stationary iteration needs the exact level-0 operator")
+        hist = [rel_residual(self.op, u, f)]
+        it = 0
+        while hist[-1] > tol and it < max_it:
+            u = self.cycle(u, f)
+            it += 1
+            hist.append(rel_residual(self.op, u, f))
+            if not np.isfinite(hist[-1]):
+                break
+        return SolveResult(u, hist[-1], it, it, hist)
+
+    def solve_fgmres(self, u, f, tol, restart=20, max_it=500) -> SolveResult:
+        op = self.op
+        n = op.n
+        fn = np.linalg.norm(f)
+        r = op.residual(u, f)
+        hist = [np.linalg.norm(r) / fn]
+        it = 0
+        while hist[-1] > tol and it < max_it:
+            beta = np.linalg.norm(r)
+            V = [r / beta]
+            Z = []
+            H = np.zeros((restart + 1, restart), np.complex128)
+            cs = np.zeros(restart, np.complex128)
+            sn = np.zeros(restart, np.complex128)
+            gvec = np.zeros(restart + 1, np.complex128)
+            gvec[0] = beta
+            j = 0
+            while j < restart and it < max_it:
+                z = self.precondition(V[j])
+                Z.append(z)
+                w = op.apply(z)
+                w[0, :] = w[-1, :] = w[:, 0] = w[:, -1] = 0
+                for _ in range(2):                      # CGS2
+                    coef = np.array([np.vdot(v, w) for v in V])
+                    H[:j + 1, j] += coef
+                    for v, cf in zip(V, coef):
+                        w = w - cf * v
+                H[j + 1, j] = np.linalg.norm(w)
+                hnext = H[j + 1, j]
+                for i in range(j):                      # earlier Givens rotations
+                    x1, x2 = H[i, j], H[i + 1, j]
+                    H[i, j] = np.conj(cs[i]) * x1 + np.conj(sn[i]) * x2
+                    H[i + 1, j] = -sn[i] * x1 + cs[i] * x2
+                den = np.sqrt(abs(H[j, j]) ** 2 + abs(H[j + 1, j]) ** 2)
+                cs[j] = H[j, j] / den
+                sn[j] = H[j + 1, j] / den
+                H[j, j] = den
+                H[j + 1, j] = 0
+                gvec[j + 1] = -sn[j] * gvec[j]
+                gvec[j] = np.conj(cs[j]) * gvec[j]
+                it += 1
+                j += 1
+                if abs(gvec[j]) / fn <= tol or hnext == 0:
+                    break
+                V.append(w / hnext)
+            y = np.linalg.solve(np.triu(H[:j, :j]), gvec[:j])
+            for zz, yy in zip(Z, y):
+                u = u + yy * zz
+            r = op.residual(u, f)
+            hist.append(np.linalg.norm(r) / fn)
+            if not np.isfinite(hist[-1]):
+                break
+        return SolveResult(u, hist[-1], it, it, hist)
+
+    def solve_ir(self, u, f, tol, inner_cycles=2, max_it=200) -> SolveResult:
+        op = self.op
+        hist = [rel_residual(op, u, f)]
+        it = 0
+        while hist[-1] > tol and it < max_it:
+            r = op.residual(u, f)
+            s = np.sqrt((op.n - 1) ** 2) / np.linalg.norm(r)
+            e = np.zeros_like(r)
+            for _ in range(inner_cycles):
+                e = self.cycle(e, s * r)
+            u = u + e / s
+            it += 1
+            hist.append(rel_residual(op, u, f))
+            if not np.isfinite(hist[-1]):
+                break
+        return SolveResult(u, hist[-1], it, it * inner_cycles, hist)

@@ -1,0 +1,356 @@
+"""Pins of the FP64 CPU oracle against what the paper and the mathematics fix.
+
+Each test names the pin: printed values (tests/golden), closed forms,
+brute-force direct solves, special cases that reduce to textbook results, and
+invariants.  They run on the CPU only.
+"""
+import math
+import os
+import warnings
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse.linalg as spla
+
+from oracle import functional as fn
+from oracle.cccs import CCCS, bound_states, channel_potential
+from oracle.grid import Grid1D, Operator, rel_residual, tp_one_body, tp_operator, tp_rhs
+from oracle.mg import CoarsestSolver, Hierarchy, jacobi, prolong_bilinear, restrict_fw
+from oracle.solvers import MGCCCS
+from paper_1412_1953_amd.workloads import initial_guess, random_field
+
+warnings.simplefilter("ignore")
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rng_field(n, seed):
+    return random_field(n, seed)
+
+
+# ---------------------------------------------------------------- P1 -------
+def test_exponential_model_threshold_matches_printed_value():
+    """Fig. 4 data: the curves start at the single-ionisation threshold
+    lambda_1 = -1.02150069 of -1/2 d2/dx2 - 4.5 exp(-x^2) on the paper's
+    300 + 150 point ECS grid."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "exp_model_threshold.txt"))
+            if l.strip() and not l.startswith("#")]
+    lam1, L, n, R0, theta = map(float, rows[0])
+    g = Grid1D(int(n), L, R0, theta)
+    V = np.zeros(g.n + 1, complex)
+    V[1:g.n] = -4.5 * np.exp(-g.z[1:g.n] ** 2)
+    lam, phi = bound_states(g, V, 2)
+    assert abs(lam[0].real - lam1) < 5e-9
+    assert abs(lam[0].imag) < 1e-10
+    assert lam[1].real > lam[0].real
+
+
+# ---------------------------------------------------------------- P2 / P3 --
+def test_hydrogen_channels_converge_to_closed_form_at_second_order():
+    """-1/2 d2/dx2 - 1/x has lambda_n = -1/(2 n^2); the 3-point scheme is O(h^2)."""
+    errs = []
+    vals = []
+    for n in (128, 256, 512):
+        g = Grid1D(n, 40.0, 30.0, math.pi / 6)
+        lam, _ = bound_states(g, tp_one_body(g, 1.0), 3)
+        vals.append(lam)
+        errs.append(abs(lam[0] - (-0.5)))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.6 < r1 < 4.4 and 3.8 < r2 < 4.2
+    extrap = (4 * vals[2] - vals[1]) / 3
+    assert abs(extrap[0] + 0.5) < 2e-5
+    assert abs(extrap[1] + 0.125) < 2e-5
+    assert abs(extrap[2] + 1 / 18) < 2e-4
+
+
+def test_deep_bound_states_do_not_move_with_the_scaling_angle():
+    g1 = Grid1D(256, 40.0, 30.0, math.pi / 6)
+    g2 = Grid1D(256, 40.0, 30.0, math.pi / 9)
+    l1, _ = bound_states(g1, tp_one_body(g1, 1.0), 2)
+    l2, _ = bound_states(g2, tp_one_body(g2, 1.0), 2)
+    assert np.abs(l1 - l2).max() < 1e-10
+
+
+# ---------------------------------------------------------------- P11 ------
+def test_refined_ground_state_keeps_decaying_below_round_off():
+    """Sec. 5.1: after shift-and-invert the tail of phi_1 follows the analytic
+    decay 2 x e^{-x} far below 1e-16 instead of stagnating; eigen-residual,
+    bilinear normalisation and the sign rule hold."""
+    g = Grid1D(1024, 80.0, 60.0, math.pi / 6)
+    V = tp_one_body(g, 1.0)
+    lam, phi = bound_states(g, V, 1)
+    n = g.n
+    S = g.weighted_hamiltonian_dense(V)
+    v = phi[0, 1:n]
+    res = S @ v - lam[0] * g.w[1:n] * v
+    assert np.linalg.norm(res) / np.linalg.norm(S @ v) < 1e-12
+    assert abs(np.sum(g.w[1:n] * v * v) - 1) < 1e-13
+    assert v[np.argmax(np.abs(v))].real > 0
+    for x in (5.0, 20.0, 40.0, 50.0):
+        j = int(round(x / g.h))
+        ref = 2 * x * math.exp(-x)
+        assert 0.8 < abs(phi[0, j]) / ref < 1.25, (x, abs(phi[0, j]), ref)
+
+
+# ---------------------------------------------------------------- P4 -------
+@pytest.mark.parametrize("gamma", [0.0, math.radians(5)])
+def test_weighted_operator_is_complex_symmetric(gamma):
+    """Sec. 2.5: with absorbing layers the system is complex symmetric; for the
+    non-uniform 3-point scheme the symmetric form is S = (W (x) W) A."""
+    g = Grid1D(32, 10.0, 7.5, math.pi / 6, gamma)
+    op = tp_operator(g, 1.0, 0.7, 1.3, 0.4)
+    v, w = rng_field(32, 1), rng_field(32, 2)
+    W2 = g.w[:, None] * g.w[None, :]
+    a = np.sum(v * W2 * op.apply(w))
+    b = np.sum(w * W2 * op.apply(v))
+    assert abs(a - b) < 1e-12 * abs(a)
+
+
+def test_stencil_matches_assembled_kronecker_matrix():
+    g = Grid1D(16, 6.0, 4.5, math.pi / 5)
+    op = tp_operator(g, 1.1, 0.9, 0.8, 0.25)
+    A = op.sparse().toarray()
+    n = g.n
+    u = rng_field(n, 3)
+    assert np.allclose(op.apply(u)[1:n, 1:n].ravel(), A @ u[1:n, 1:n].ravel(), rtol=0, atol=1e-13)
+
+
+# ---------------------------------------------------------------- P6 -------
+def test_free_operator_has_discrete_sine_eigenvectors():
+    """Z1 = Z2 = lambda = 0, no scaling: sin(p pi x/L) sin(q pi y/L) is an exact
+    eigenvector with eigenvalue (1-cos(p pi h/L))/h^2 + (1-cos(q pi h/L))/h^2 - E."""
+    n, L, E = 64, 10.0, 0.37
+    g = Grid1D(n, L, L, 0.1)          # R0 = L: no complex layer
+    op = tp_operator(g, 0.0, 0.0, 0.0, E)
+    x = g.x
+    for p, q in [(1, 1), (3, 7), (40, 2), (63, 63)]:
+        u = np.outer(np.sin(q * np.pi * x / L), np.sin(p * np.pi * x / L)).astype(complex)
+        h = g.h
+        ev = (1 - np.cos(p * np.pi * h / L)) / h ** 2 + (1 - np.cos(q * np.pi * h / L)) / h ** 2 - E
+        assert np.abs(op.apply(u) - ev * u).max() < 1e-11 * max(1, abs(ev))
+
+
+def test_vcycle_contraction_on_the_positive_definite_case_is_mesh_independent():
+    """Z = lambda = 0, no scaling, E < 0: a Poisson-type problem on which the
+    V(1,1) cycle with omega-Jacobi (2/3), full weighting and bilinear
+    interpolation contracts at a mesh-independent rate.  Local Fourier analysis:
+    the 2D omega-Jacobi smoothing factor is max(|1 - omega(1 - c)|) over the
+    high frequencies, c = (cos t1 + cos t2)/2 in [-1, 1/2], i.e. 2/3 for
+    omega = 2/3, so one pre- and one post-sweep give about (2/3)^2 = 0.44."""
+    rates = []
+    for n in (32, 64, 128):
+        g = Grid1D(n, 10.0, 10.0, 0.1)
+        mg = Hierarchy(g, 0.0, 0.0, 0.0, -1.0, int(math.log2(n)) - 2)
+        op = mg.ops[0]
+        f = rng_field(n, 4)
+        u = np.zeros_like(f)
+        r = [rel_residual(op, u, f)]
+        for _ in range(10):
+            u = mg.vcycle(u, f)
+            r.append(rel_residual(op, u, f))
+        rates.append((r[-1] / r[4]) ** (1 / 6))
+    assert 0.3 < min(rates) and max(rates) < 0.46, rates
+    assert max(rates) - min(rates) < 0.05, rates
+
+
+# ---------------------------------------------------------------- transfers
+def test_full_weighting_is_quarter_transpose_of_bilinear_interpolation():
+    n = 32
+    r = rng_field(n, 5)
+    v = rng_field(n // 2, 6)
+    lhs = np.sum(restrict_fw(r) * v)
+    rhs = 0.25 * np.sum(r * prolong_bilinear(v))
+    assert abs(lhs - rhs) < 1e-13 * abs(lhs)
+
+
+def test_bilinear_interpolation_is_exact_for_bilinear_functions():
+    nc = 8
+    X, Y = np.meshgrid(np.arange(nc + 1) / nc, np.arange(nc + 1) / nc)
+    ec = (2 * X + 3 * Y + X * Y + 1).astype(complex)
+    ec[0, :] = ec[-1, :] = ec[:, 0] = ec[:, -1] = 0
+    e = prolong_bilinear(ec)
+    Xf, Yf = np.meshgrid(np.arange(2 * nc + 1) / (2 * nc), np.arange(2 * nc + 1) / (2 * nc))
+    ref = 2 * Xf + 3 * Yf + Xf * Yf + 1
+    inner = slice(2, 2 * nc - 1)              # away from the zero ring
+    assert np.abs(e[inner, inner] - ref[inner, inner]).max() < 1e-14
+    assert np.array_equal(e[::2, ::2], ec)
+
+
+def test_jacobi_fixed_point_and_coarsest_solver():
+    g = Grid1D(16, 8.0, 6.0, math.pi / 6)
+    op = tp_operator(g, 1.0, 1.0, 1.0, 0.3)
+    f = rng_field(16, 7)
+    u = CoarsestSolver(op).solve(f)
+    assert rel_residual(op, u, f) < 1e-13
+    assert np.abs(jacobi(op, u, f, 2 / 3) - u).max() < 1e-12 * np.abs(u).max()
+
+
+# ---------------------------------------------------------------- P5 -------
+@pytest.mark.parametrize("n,L,E,theta,gdeg,M", [
+    (16, 8.0, 0.3, math.pi / 6, 5.0, 2),
+    (32, 10.0, -0.3, math.pi / 4, 0.0, 3),
+    (32, 12.0, 1.1, math.pi / 8, 10.0, 4),
+    (32, 10.0, 0.05, math.pi / 6, 5.0, 1),
+])
+def test_mgcccs_fgmres_converges_to_the_dense_direct_solution(n, L, E, theta, gdeg, M):
+    s = MGCCCS(n, L, 0.75 * L, theta, 1.0, 1.0, 1.0, E, 3, M, pc_gamma=math.radians(gdeg))
+    f = s.rhs()
+    A = s.op.sparse().toarray()
+    x = np.linalg.solve(A, f[1:n, 1:n].ravel())
+    r = s.solve_fgmres(initial_guess(n, 1), f, 1e-12, restart=10, max_it=500)
+    assert r.relres <= 1e-12
+    assert np.linalg.norm(r.u[1:n, 1:n].ravel() - x) / np.linalg.norm(x) < 1e-9
+    h = np.array(r.history)
+    assert np.all(h[1:] <= h[:-1] * (1 + 1e-12))        # P10: non-increasing per restart
+
+
+def test_fgmres_fixed_point_on_the_129_grid_matches_sparse_lu():
+    from paper_1412_1953_amd.workloads import SMALL_129 as w
+    s = MGCCCS.from_workload(w, pc_gamma=math.radians(5))
+    s.M = 8
+    s.cc = CCCS(s.pc_op, 8)
+    f = s.rhs()
+    n = w.n
+    x = spla.splu(s.op.sparse()).solve(f[1:n, 1:n].ravel())
+    r = s.solve_fgmres(initial_guess(n, w.seed), f, 1e-11, restart=10, max_it=400)
+    assert r.relres <= 1e-11
+    assert np.linalg.norm(r.u[1:n, 1:n].ravel() - x) / np.linalg.norm(x) < 1e-8
+
+
+# ---------------------------------------------------------------- P7 -------
+def test_separable_case_matches_fast_diagonalisation():
+    """lambda = 0: A = H1 (x) I + I (x) H2 - E is separable, solved exactly by
+    the 1D eigendecompositions (no stencil code involved)."""
+    n, L, E = 64, 20.0, 0.2
+    g = Grid1D(n, L, 15.0, math.pi / 6)
+    H1 = g.hamiltonian_dense(tp_one_body(g, 1.0))
+    H2 = g.hamiltonian_dense(tp_one_body(g, 0.8))
+    lx, X = sla.eig(H1)
+    ly, Y = sla.eig(H2)
+    F = rng_field(n, 8)[1:n, 1:n]                      # [k, j]
+    Ft = sla.solve(Y, F) @ sla.inv(X).T
+    U = Y @ (Ft / (ly[:, None] + lx[None, :] - E)) @ X.T
+    s = MGCCCS(n, L, 15.0, math.pi / 6, 1.0, 0.8, 0.0, E, 4, 3, pc_gamma=math.radians(5))
+    f = np.zeros((n + 1, n + 1), complex)
+    f[1:n, 1:n] = F
+    r = s.solve_fgmres(np.zeros_like(f), f, 1e-13, restart=10, max_it=500)
+    assert np.linalg.norm(r.u[1:n, 1:n] - U) / np.linalg.norm(U) < 1e-10
+
+
+# ---------------------------------------------------------------- P8 -------
+def _cc_case(lam):
+    g = Grid1D(64, 20.0, 15.0, math.pi / 6)
+    op = tp_operator(g, 1.0, 0.9, lam, 0.3)
+    return g, op, CCCS(op, 4, 3)
+
+
+def test_cccs_solves_channel_space_residuals_exactly_without_two_body_coupling():
+    """lambda = 0: for a residual in the channel space, the correction e*
+    satisfies A e* = r (the channel equations are then exact)."""
+    g, op, cc = _cc_case(0.0)
+    n = g.n
+    rng = np.random.default_rng(9)
+    rA = np.zeros((n + 1, 4), complex)
+    rB = np.zeros((n + 1, 3), complex)
+    rA[1:n] = rng.standard_normal((n - 1, 4)) + 1j * rng.standard_normal((n - 1, 4))
+    rB[1:n] = rng.standard_normal((n - 1, 3)) + 1j * rng.standard_normal((n - 1, 3))
+    r = cc.expand(rA, rB)
+    e = cc.correction(r)
+    assert np.abs(op.apply(e) - r).max() < 1e-10 * np.abs(r).max()
+
+
+@pytest.mark.parametrize("lam", [0.0, 1.0])
+def test_channel_expansion_is_an_oblique_projector(lam):
+    """Remark 4 / eq. coefficients: r -> r* = sum r^A phi + sum r^B varphi is
+    idempotent and keeps every channel projection of r."""
+    g, op, cc = _cc_case(lam)
+    r = rng_field(g.n, 10)
+    rs = cc.expand(*cc.channel_rhs(r))
+    rss = cc.expand(*cc.channel_rhs(rs))
+    assert np.abs(rss - rs).max() < 1e-12 * np.abs(rs).max()
+    pa, pb, c = cc.project(r)
+    qa, qb, d = cc.project(rs)
+    assert np.abs(pa - qa).max() < 1e-12 * np.abs(pa).max()
+    assert np.abs(pb - qb).max() < 1e-12 * np.abs(pb).max()
+
+
+def test_a_wrong_uniqueness_convention_breaks_the_projector():
+    """Planted mistake (in a copy of the oracle's split): moving the l = i
+    coefficients from a to b double-counts them; the test above must then fail."""
+    g, op, cc = _cc_case(1.0)
+    r = rng_field(g.n, 11)
+    rhoA, rhoB, c = cc.project(r)
+    M, L = c.shape
+    i_idx, l_idx = np.arange(M)[:, None], np.arange(L)[None, :]
+    b = np.where(l_idx >= i_idx, c, 0)
+    a = np.where(l_idx <= i_idx, c, 0).T
+    rA = rhoA - cc.vphi.T @ b.T
+    rB = rhoB - cc.phi.T @ a.T
+    qa, _, _ = cc.project(cc.expand(rA, rB))
+    assert np.abs(qa - rhoA).max() > 1e-3 * np.abs(rhoA).max()
+
+
+def test_channel_potential_prefix_sum_identity():
+    """V^A_im(y_k) = (lambda/z_k) sum_{j<=k} g_im(j) + sum_{j>k} (lambda/z_j) g_im(j)."""
+    g, op, cc = _cc_case(1.3)
+    n = g.n
+    G = g.w[:, None, None] * cc.phi.T[:, :, None] * cc.phi.T[:, None, :]
+    zz = g.z.copy()
+    zz[0] = 1
+    pre = np.cumsum(G, axis=0)
+    suf = np.cumsum(((1.3 / zz)[:, None, None] * G)[::-1], axis=0)[::-1]
+    V = np.zeros_like(cc.VA)
+    for k in range(1, n):
+        V[k] = (1.3 / g.z[k]) * pre[k] + suf[k + 1]
+    assert np.abs(V - cc.VA).max() < 1e-13 * np.abs(cc.VA).max()
+
+
+# ---------------------------------------------------------------- P9 / P15 -
+def test_symmetric_problem_has_a_symmetric_solution():
+    n = 32
+    s = MGCCCS(n, 10.0, 7.5, math.pi / 6, 1.0, 1.0, 1.0, 0.4, 3, 3, pc_gamma=math.radians(5))
+    f = s.rhs()
+    assert np.abs(f - f.T).max() == 0
+    r = s.solve_fgmres(initial_guess(n, 2), f, 1e-13, restart=10, max_it=500)
+    assert np.abs(r.u - r.u.T).max() < 1e-10 * np.abs(r.u).max()
+
+
+def test_rhs_structure():
+    """chi0 = (lambda/z_max - Z2/z2) phi_1s(z1) sin(k0 z2) vanishes for x2 >= x1
+    when Z2 = lambda, and outside the real region; chi = (chi0 + chi0^T)/sqrt 2."""
+    g = Grid1D(64, 20.0, 15.0, math.pi / 6)
+    chi = tp_rhs(g, 1.0, 1.0, 1.0, 0.5) * math.sqrt(2)
+    n, j0 = g.n, g.j0
+    k, j = np.meshgrid(np.arange(n + 1), np.arange(n + 1), indexing="ij")
+    # chi*sqrt2 = chi0 + chi0^T with chi0[k,j] = 0 for k >= j: below the diagonal only chi0^T
+    low = chi[k > j]
+    up = chi.T[k > j]
+    assert np.array_equal(low, up)
+    assert np.all(chi[j0 + 1:, :] == 0) and np.all(chi[:, j0 + 1:] == 0)
+    assert np.all(np.diag(chi) == 0)
+    chi2 = tp_rhs(g, 1.0, 0.6, 1.0, 0.5)
+    assert np.abs(np.diag(chi2)).max() > 0
+
+
+# ---------------------------------------------------------------- P14 ------
+def test_free_test_function_is_a_normalised_discrete_sine():
+    """Z1 = 0: phi_j = h sin(kappa j h)/sin(kappa h) with cos(kappa h) = 1 - (kh)^2/2,
+    scaled so that phi(R0)^2 + (phi'(R0)/k)^2 = 1/k (central difference)."""
+    g = Grid1D(256, 40.0, 30.0, math.pi / 6)
+    k = 0.9
+    ph = fn.test_function(g, 0.0, k)
+    h = g.h
+    kap = math.acos(1 - (k * h) ** 2 / 2) / h
+    raw = h * np.sin(kap * np.arange(len(ph)) * h) / math.sin(kap * h)
+    R0 = g.j0 * h
+    amp2 = (h * math.sin(kap * R0) / math.sin(kap * h)) ** 2 + (math.cos(kap * R0) / k) ** 2
+    ref = raw / math.sqrt(amp2 * k)
+    assert np.abs(ph - ref).max() < 1e-12
+
+
+def test_zeta_is_affine_in_u():
+    g = Grid1D(64, 20.0, 15.0, math.pi / 6)
+    chi = tp_rhs(g, 1.0, 1.0, 1.0, 0.5)
+    u1, u2 = rng_field(64, 12), rng_field(64, 13)
+    z = lambda u: fn.zeta(g, 1.0, 1.0, u, chi, 0.7, 0.7)
+    assert abs(z(u1 + 2 * u2) - (z(u1) + 2 * z(u2) - 2 * z(0 * u1))) < 1e-12 * abs(z(u1))
