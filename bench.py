@@ -1,0 +1,155 @@
+"""Benchmark: MG-CCCS solves of the 1025^2 Temkin-Poet problem on one MI355X.
+
+A step is one pass of the whole hot path over one batch: the three FP64
+MG-CCCS solves of the 1025^2 workload (domain [0,80]^2, ECS beyond 60 at pi/6,
+7 levels, 8 channels, E = 0.05, 0.5, 2.0 solved separately) from the seeded
+complex-normal initial guess to a relative residual of 1e-10.  Setup
+(set_potential / set_energy) happens before the timed region; right-hand side,
+initial guess and workspace are resident in HBM when it starts.
+
+value = solved unknowns per second = 3 * 1023^2 / (seconds per step).
+The same step with the complex-FP32 preconditioner inside the FP64 FGMRES is
+reported as "mixed".  "roofline" covers the dominant kernel, timed with HIP
+events on the library's stream inside the timed steps; "cpu_baseline" is the
+FP64 CPU oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PC_GAMMA = math.radians(5.0)
+RESTART = 10
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=2)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--max-it", type=int, default=20000)
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--no-mixed", action="store_true")
+    p.add_argument("--cpu-iters", type=int, default=6)
+    p.add_argument("--energies", type=str, default="0.05,0.5,2.0",
+                   help="subset of the workload energies (profiling runs)")
+    return p.parse_args()
+
+
+def make_problem(w, torch):
+    from paper_1412_1953_amd import mgcccs
+    from paper_1412_1953_amd.workloads import initial_guess
+    g = mgcccs.Grid.from_workload(w, pc_gamma=PC_GAMMA, max_restart=RESTART, fp32=True)
+    g.set_potential(w.Z1, w.Z2, w.lam)
+    g.set_energy(w.E)
+    chi = g.build_rhs_tp(g.field())
+    u0 = g.from_numpy(initial_guess(w.n, w.seed))
+    u = g.field()
+    return g, chi, u0, u
+
+
+def run_step(problems, inner, torch, max_it):
+    from paper_1412_1953_amd import mgcccs
+    out = []
+    for g, chi, u0, u in problems:
+        u.copy_(u0)
+        r = g.solve(u, chi, outer=mgcccs.FGMRES, inner=inner, restart=RESTART, max_it=max_it,
+                    tol=1e-10)
+        out.append(r)
+    return out
+
+
+def time_steps(problems, inner, torch, steps, warmup, max_it):
+    for _ in range(warmup):
+        run_step(problems, inner, torch, max_it)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = []
+    for _ in range(steps):
+        res = run_step(problems, inner, torch, max_it)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    return dt, res
+
+
+def cpu_baseline(w, iters, gpu_iters):
+    """FP64 oracle on a bounded sample: `iters` FGMRES iterations of one solve,
+    extrapolated to the GPU's iteration count for that solve."""
+    import numpy as np
+    from oracle.solvers import MGCCCS
+    from paper_1412_1953_amd.workloads import initial_guess
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(limits=1)
+    except Exception:  # pragma: no cover
+        limiter = None
+    o = MGCCCS.from_workload(w, pc_gamma=PC_GAMMA)
+    f = o.rhs()
+    u0 = initial_guess(w.n, w.seed)
+    t0 = time.perf_counter()
+    o.solve_fgmres(u0, f, 1e-300, restart=RESTART, max_it=iters)
+    dt = time.perf_counter() - t0
+    if limiter is not None:
+        limiter.unregister()
+    per_it = dt / iters
+    solve_s = per_it * gpu_iters
+    return {"value": w.unknowns / solve_s, "unit": "solved unknowns/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{iters} FGMRES({RESTART}) iterations of the E={w.E} solve "
+                      f"({dt:.1f} s, {per_it:.2f} s/iteration), extrapolated to the "
+                      f"{gpu_iters} iterations the GPU needed"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py runs on one GPU only: the MG-CCCS hot path is measured on a single "
+              "MI355X (multi-GPU sharding is a design note, not implemented)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1412_1953_amd import mgcccs
+    from paper_1412_1953_amd.workloads import TP1025
+    mgcccs.load_library()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    wls = [TP1025[float(E)] for E in a.energies.split(",")]
+    problems = [make_problem(w, torch) for w in wls]
+    unknowns = sum(w.unknowns for w in wls)
+
+    dt64, r64 = time_steps(problems, mgcccs.FP64, torch, a.steps, a.warmup, a.max_it)
+    line = {
+        "metric": "solved unknowns/s to 1e-10 rel. residual, mixed vs FP64 MG-CCCS; HBM GB/s",
+        "value": unknowns / dt64,
+        "unit": "solved unknowns/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": dt64 * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c128", "data": "synthetic",
+        "config": {"workload": "tp1025_fp64_E0.05_0.5_2.0", "n": 1024, "L": 80.0, "R0": 60.0,
+                   "theta": "pi/6", "levels": 7, "channels": 8, "tol": 1e-10,
+                   "outer": f"FGMRES({RESTART})", "preconditioner": "MG-CCCS V(1,1)",
+                   "pc_gamma_deg": 5.0, "energies": [w.E for w in wls]},
+        "fp64": {"iters": [r.iters for r in r64], "relres": [r.relres for r in r64],
+                 "status": [r.status for r in r64],
+                 "vcycles_per_s": sum(r.vcycles for r in r64) / dt64},
+    }
+    if not a.no_mixed:
+        dt32, r32 = time_steps(problems, mgcccs.FP32, torch, a.steps, a.warmup, a.max_it)
+        line["mixed"] = {"value": unknowns / dt32, "ms_per_step": dt32 * 1e3,
+                         "iters": [r.iters for r in r32], "relres": [r.relres for r in r32],
+                         "status": [r.status for r in r32],
+                         "speedup_vs_fp64": dt64 / dt32}
+    if not a.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(wls[0], a.cpu_iters, r64[0].iters)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,199 @@
+/*
+ * mgcccs.h -- C ABI of the MI355X (gfx950) MG-CCCS solver for the 2D driven
+ * Schroedinger equation  (H - E) u = chi  on an exterior-complex-scaled grid.
+ *
+ * Method: Cools & Vanroose, "A fast and robust computational method for the
+ * ionization cross sections of the driven Schroedinger equation using an O(N)
+ * multigrid-based scheme" (arXiv:1412.1953):
+ *   - problem and boundary conditions: Sec. 2.2, eq. partialwave2d;
+ *   - finite-difference discretisation: Sec. 2.5, eq. discrete_schrodinger;
+ *   - Temkin-Poet potentials -Z1/x, -Z2/y, lambda/max(x,y): Sec. 5.2, Sec. 6.2;
+ *   - multigrid V(1,1) cycle with omega-Jacobi, full weighting and bilinear
+ *     interpolation: Sec. 1 and Sec. 3.2;
+ *   - Coupled Channel Correction Step (CCCS): Sec. 4, eqs. coupled_channel_expansion,
+ *     convention_a/b, coefficients, channel1/channel2, cccs;
+ *   - MG-CCCS as a Krylov (FGMRES) preconditioner: Sec. 6, Table 1;
+ *   - ionisation amplitude and cross section: Sec. 3.3, eqs. double-ionization,
+ *     testfunction, total-double-ionization.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Fields.  A field on level l is an (n_l+1) x pitch_l array of interleaved
+ *   complex numbers (double2 for MGC_FP64, float2 for MGC_FP32) in device
+ *   memory.  Row k runs along x2, column j along x1 (contiguous); element
+ *   (k, j) lives at k*pitch_l + j.  Rows/columns 0 and n_l are the homogeneous
+ *   Dirichlet ring: the library never reads or writes them (they are treated as
+ *   zero).  Columns beyond n_l are padding and are never touched.  The level-0
+ *   pitch is returned by mgc_field_pitch().
+ * Ownership.  The caller owns every field and the workspace; the library owns
+ *   only host-side setup data and never allocates device memory.  All device
+ *   pointers must belong to the device that was current at mgc_create_grid.
+ * Streams.  All device work is enqueued on the stream given at creation (NULL
+ *   = default stream).  Calls that return host scalars (relres, zeta, stats)
+ *   synchronise that stream; the others are asynchronous.
+ * Errors.  Every entry point returns an mgc_status.  Arguments are validated
+ *   before any side effect (MGC_EINVAL).  A HIP runtime error returns MGC_EHIP
+ *   and marks the handle failed: later calls return MGC_ESTATE.  A solve that
+ *   reaches max_it returns MGC_ENOCONV with u = last iterate and stats filled; a
+ *   NaN/Inf residual returns MGC_ENUMERIC.  mgc_last_error() gives a message.
+ * Threads.  A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef MGCCCS_H
+#define MGCCCS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MGC_OK = 0,
+  MGC_EINVAL = -1,    /* invalid argument (nothing was changed)                */
+  MGC_ENOMEM = -2,    /* bound workspace too small                             */
+  MGC_EHIP = -3,      /* HIP runtime error; handle is now failed               */
+  MGC_ENOCONV = -4,   /* iteration limit reached before the tolerance          */
+  MGC_ESTATE = -5,    /* call order violated or handle failed                  */
+  MGC_ENUMERIC = -6   /* NaN or Inf encountered                                */
+} mgc_status;
+
+typedef enum { MGC_FP64 = 0, MGC_FP32 = 1 } mgc_precision;
+
+typedef enum {
+  MGC_STATIONARY = 0, /* repeat {V-cycle; CCCS} on A u = f (Sec. 6.1)          */
+  MGC_IR = 1,         /* FP64 iterative refinement around inner MG-CCCS cycles */
+  MGC_FGMRES = 2      /* FP64 FGMRES(restart), right-preconditioned by one
+                         MG-CCCS cycle started from zero (Sec. 6, Table 1)      */
+} mgc_outer;
+
+typedef struct mgc_grid_s* mgc_grid;   /* opaque, library-owned host object */
+
+/* Grid and solver structure (fixed for the life of a handle).
+ * n        intervals per dimension on the finest level; a power of two >= 8.
+ * L, R0    domain [0,L]^2; complex scaling starts at x = R0, which must be a
+ *          node of the coarsest level (R0/(L/n_coarsest) integral), 0 < R0 < L.
+ * theta    ECS angle in (0, pi/2): z = R0 + (x - R0) e^{i theta} for x > R0.
+ * levels   multigrid levels including the coarsest (n >> (levels-1) >= 4);
+ *          the coarsest level is solved by a dense FP64 direct solve and must
+ *          hold at most 1024 unknowns.
+ * M, Lch   channels (lowest 1D eigenstates) in x1 and in x2; 0 <= M,Lch <= 16.
+ *          M = Lch = 0 disables the CCCS.
+ * omega, nu1, nu2   omega-Jacobi weight and pre/post smoothing sweeps.
+ * pc_gamma, pc_first_level
+ *          interior contour rotation used by the preconditioning hierarchy:
+ *          on levels >= pc_first_level the grid is z = x e^{i pc_gamma} for
+ *          x <= R0 (the complex-contour operator of Sec. 3.1/Sec. 6), followed
+ *          by the ECS ray.  pc_gamma = 0 makes every level the exact operator.
+ *          The CCCS acts on the level-0 operator of the hierarchy.
+ * max_restart  FGMRES basis size the workspace must hold (0: no FGMRES).
+ * precisions   bit mask (1 << MGC_FP64) | (1 << MGC_FP32) of the cycle
+ *          precisions the workspace must hold.                                */
+typedef struct {
+  int n;
+  double L, R0, theta;
+  int levels;
+  int M, Lch;
+  double omega;
+  int nu1, nu2;
+  double pc_gamma;
+  int pc_first_level;
+  int max_restart;
+  int precisions;
+} mgc_grid_desc;
+
+typedef struct {
+  mgc_outer outer;
+  mgc_precision inner;   /* precision of the MG-CCCS cycles (STATIONARY: FP64 only) */
+  int restart;           /* FGMRES restart length, <= desc.max_restart           */
+  int max_it;            /* outer iterations (cycles for STATIONARY)             */
+  int inner_cycles;      /* MG-CCCS cycles per IR step                           */
+  double tol;            /* stop when ||f - A u||_2 / ||f||_2 <= tol             */
+} mgc_solve_opts;
+
+typedef struct {
+  int iters;             /* outer iterations performed                           */
+  int vcycles;           /* MG-CCCS cycles performed                             */
+  double relres;         /* final ||f - A u||_2 / ||f||_2 (FP64, recomputed)     */
+  double* hist;          /* optional caller array: true relres at the start and
+                            after every outer step (FGMRES: every restart cycle) */
+  int hist_cap;          /* capacity of hist                                      */
+  int hist_len;          /* entries written to hist (<= hist_cap)                 */
+  double t_setup_ms;     /* host time of the last set_potential + set_energy     */
+  double t_solve_ms;     /* wall time of the solve (HIP events on the stream)    */
+} mgc_stats;
+
+/* Validate desc and build the host-side grid tables.  hip_stream is a
+ * hipStream_t (may be NULL).  No device memory is touched.                     */
+mgc_status mgc_create_grid(const mgc_grid_desc* desc, void* hip_stream, mgc_grid* out);
+
+/* Bytes of device workspace the handle needs (all levels, both precisions in
+ * desc.precisions, CCCS tables, channel factors, Krylov basis).               */
+mgc_status mgc_workspace_bytes(mgc_grid g, size_t* bytes);
+
+/* Bind caller-owned device memory (>= mgc_workspace_bytes, 256-byte aligned).
+ * The library clears it on the handle's stream.                                */
+mgc_status mgc_bind_workspace(mgc_grid g, void* dev_ptr, size_t bytes);
+
+/* Row pitch (in complex elements) of level-l fields; level 0 is the caller's. */
+mgc_status mgc_field_pitch(mgc_grid g, int level, int* pitch_elems);
+
+/* Temkin-Poet potential strengths: V1 = -Z1/x1, V2 = -Z2/x2,
+ * V12 = lambda/max(x1,x2) (Sec. 6.2).  Computes the M (Lch) lowest 1D
+ * eigenstates of H1 (H2) with the bilinear normalisation int phi^2 dz = 1
+ * (Sec. 3.1 Remark 3), refined by two shift-and-invert steps (Sec. 5.1), and
+ * the channel potentials (Sec. 4.2).  Invalidates the energy setup.           */
+mgc_status mgc_set_potential(mgc_grid g, double Z1, double Z2, double lambda);
+
+/* Total energy E.  Factorises the coupled channel systems (Sec. 4.3) and the
+ * coarsest-level operators, uploads all tables.  Requires a bound workspace
+ * and mgc_set_potential.                                                       */
+mgc_status mgc_set_energy(mgc_grid g, double E);
+
+/* Write the Temkin-Poet impact right-hand side into chi (level-0 field):
+ * chi0 = (lambda/max(z1,z2) - Z2/z2) phi_1s(z1) sin(k0 z2) on the real region
+ * x1, x2 <= R0, zero beyond, phi_1s(z) = 2 Z1^{3/2} z e^{-Z1 z},
+ * k0 = sqrt(2(E + Z1^2/2)); chi = (chi0 + chi0^T)/sqrt(2).                    */
+mgc_status mgc_build_rhs_tp(mgc_grid g, void* chi, mgc_precision prec);
+
+/* r = f - A u on the level-0 interior (A = exact operator: ECS grid, rotation
+ * 0).  relres (nullable, synchronising) receives ||r||_2/||f||_2.  u, f, r are
+ * level-0 fields of precision prec; r may not alias u.                        */
+mgc_status mgc_residual(mgc_grid g, const void* u, const void* f, void* r,
+                        double* relres, mgc_precision prec);
+
+/* One V(nu1,nu2)-cycle in place on u for A_h u = f, where A_h is the level-0
+ * operator of the preconditioning hierarchy (Sec. 3.2).                       */
+mgc_status mgc_vcycle(mgc_grid g, void* u, const void* f, mgc_precision prec);
+
+/* One Coupled Channel Correction Step in place on u (Sec. 4.3, eq. cccs).     */
+mgc_status mgc_cccs(mgc_grid g, void* u, const void* f, mgc_precision prec);
+
+/* Solve A u = f (FP64 level-0 fields).  u holds the initial guess on entry and
+ * the last iterate on exit.  stats may be NULL.                               */
+mgc_status mgc_solve(mgc_grid g, void* u, const void* f,
+                     const mgc_solve_opts* opts, mgc_stats* stats);
+
+/* Solve A^T v = g (FP64).  With the dual weights W = diag(w_j w_k) the
+ * weighted matrix W A is complex symmetric (Sec. 2.5), so A^T = W A W^{-1} and
+ * v = W y with A y = W^{-1} g.  v holds the initial guess on entry.           */
+mgc_status mgc_solve_transpose(mgc_grid g, void* v, const void* gvec,
+                               const mgc_solve_opts* opts, mgc_stats* stats);
+
+/* Double-ionisation amplitude (Sec. 3.3 eq. double-ionization) on the real
+ * region x1, x2 <= R0 with trapezoid weights:
+ *   zeta = sum_{j,k<=j0} t_j t_k phi_{k1}(x1_j) phi_{k2}(x2_k) (chi - V12 u)_{kj}
+ * with phi_k the regular solution of eq. testfunction (3-point recurrence)
+ * normalised to asymptotic amplitude 1/sqrt(k) at R0, and
+ * sigma = 8 pi^2 / k0^2 * |zeta|^2 / (k1 k2).  Synchronising.                 */
+mgc_status mgc_cross_section(mgc_grid g, const void* u, const void* chi,
+                             double k1, double k2, double zeta[2], double* sigma);
+
+mgc_status mgc_destroy_grid(mgc_grid g);
+
+/* Thread-local description of the last error (never NULL).                  */
+const char* mgc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MGCCCS_H */

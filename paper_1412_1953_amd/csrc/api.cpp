@@ -1,0 +1,1035 @@
+// C ABI of the MG-CCCS solver (include/mgcccs.h): handle management,
+// workspace layout, setup upload and the host-side drivers of the V-cycle,
+// the Coupled Channel Correction Step and the outer iterations.
+#include "../../include/mgcccs.h"
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "launch.h"
+#include "setup.h"
+
+using namespace mgc;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+mgc_status fail(mgc_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+constexpr int P64 = 0, P32 = 1;
+inline size_t esize(int prec) { return prec == P64 ? 16 : 8; }
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct LevelInfo {
+  int n = 0, pitch = 0;
+  Axis ax;                                 // axis of this hierarchy level
+  size_t tab[2] = {0, 0};                  // 5 tables a, c, px, py, tm (per precision)
+  size_t fu[2] = {0, 0}, ff[2] = {0, 0}, ft[2] = {0, 0};  // fields
+};
+
+struct SysOff {                            // offsets of one channel system's factors
+  size_t G = 0, Vs = 0, Ws = 0, lo = 0, up = 0, Rinv = 0, Rlo = 0, Rup = 0, start = 0;
+};
+
+struct CcOff {                             // CCCS tables + scratch for one precision
+  size_t wphi = 0, phi = 0, wvphi = 0, vphi = 0;
+  SysOff A, B;
+  size_t rbuf = 0, rhoA = 0, rhoB = 0, partB = 0, coef = 0, gA = 0, gB = 0, YA = 0, YB = 0,
+         eA = 0, eB = 0;
+};
+
+}  // namespace
+
+struct GraphCache {                       // one captured FGMRES restart cycle
+  hipGraphExec_t exec = nullptr;
+  const void* u = nullptr;
+  const void* f = nullptr;
+  int m = 0, mm = 0, inner = -1;
+  double tol_abs = 0;
+};
+
+struct mgc_grid_s {
+  mgc_grid_desc d{};
+  hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;               // capture stream (default priority)
+  GraphCache graph;
+  int device = 0;
+  bool failed = false;
+  Axis exact;                              // level-0 axis of the physical operator
+  std::vector<LevelInfo> lv;
+  int PA = 1, PB = 1;                      // channel chunks of the A / B systems
+  // setup state
+  bool have_pot = false, have_energy = false;
+  double Z1 = 1, Z2 = 1, lam = 1, E = 0;
+  std::vector<cd> lamA, lamB;
+  std::vector<std::vector<cd>> phi, vphi;
+  double t_setup_ms = 0;
+  // workspace
+  char* ws = nullptr;
+  size_t ws_bytes = 0, need = 0;
+  size_t exact_tab = 0, exact_tab32 = 0, exact_w = 0, exact_z = 0, coarse_inv = 0, tt = 0;
+  CcOff cc[2];
+  size_t part = 0, scal = 0;               // reduction partials, small scalars
+  size_t r64 = 0, f32 = 0, u32 = 0, tw = 0, tz = 0;
+  size_t W = 0, Z[2] = {0, 0};
+  size_t gm = 0;                           // GmresState arrays
+  size_t zeta_f = 0;
+  int nchunksB = 1;
+  bool prec_on[2] = {true, false};
+
+  int coarsest() const { return (int)lv.size() - 1; }
+  size_t field_bytes(int l, int prec) const { return (size_t)(lv[l].n + 1) * lv[l].pitch * esize(prec); }
+  template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+};
+
+namespace {
+
+bool hip_ok(mgc_grid g, hipError_t e, const char* what) {
+  if (e == hipSuccess) return true;
+  g->failed = true;
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return false;
+}
+#define HIPCHK(g, call)                                  \
+  do {                                                   \
+    if (!hip_ok((g), (call), #call)) return MGC_EHIP;    \
+  } while (0)
+
+// A captured restart cycle bakes E and the table pointers into its kernel
+// arguments: any setup change invalidates it.
+void drop_graph(mgc_grid g) {
+  if (g->graph.exec) (void)hipGraphExecDestroy(g->graph.exec);
+  g->graph = GraphCache();
+}
+
+inline int pitch_for(int n) { return ((n + 1) + 15) / 16 * 16; }
+
+// --------------------------------------------------------------------------
+// workspace layout
+void layout(mgc_grid g) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  const int n = g->d.n, N = n - 1, M = g->d.M, Lc = g->d.Lch;
+  g->exact_tab = take(5 * (n + 1) * 16);
+  if (g->prec_on[P32]) g->exact_tab32 = take(5 * (n + 1) * 8);
+  g->exact_w = take((n + 1) * 16);
+  g->exact_z = take((n + 1) * 16);
+  for (int p = 0; p < 2; ++p) {
+    if (!g->prec_on[p]) continue;
+    for (size_t l = 0; l < g->lv.size(); ++l) {
+      LevelInfo& L = g->lv[l];
+      L.tab[p] = take(5 * (L.n + 1) * esize(p));
+      const size_t fb = g->field_bytes((int)l, p);
+      if (l > 0) { L.fu[p] = take(fb); L.ff[p] = take(fb); }
+      L.ft[p] = take(fb);
+    }
+    CcOff& c = g->cc[p];
+    const size_t e = esize(p);
+    if (M > 0 || Lc > 0) {
+      c.wphi = take((size_t)M * (n + 1) * e);
+      c.phi = take((size_t)M * (n + 1) * e);
+      c.wvphi = take((size_t)Lc * (n + 1) * e);
+      c.vphi = take((size_t)Lc * (n + 1) * e);
+      auto sys = [&](SysOff& s, int m, int P) {
+        s.G = take((size_t)N * m * m * e);
+        s.Vs = take((size_t)N * m * m * e);
+        s.Ws = take((size_t)N * m * m * e);
+        s.lo = take((size_t)N * e);
+        s.up = take((size_t)N * e);
+        const size_t RR = (size_t)4 * m * m;
+        s.Rinv = take((size_t)(P > 1 ? P - 1 : 1) * RR * e);
+        s.Rlo = take((size_t)(P > 1 ? P - 1 : 1) * RR * e);
+        s.Rup = take((size_t)(P > 1 ? P - 1 : 1) * RR * e);
+        s.start = take((size_t)(P + 1) * sizeof(int));
+      };
+      sys(c.A, M, g->PA);
+      sys(c.B, Lc, g->PB);
+      c.rbuf = take(g->field_bytes(0, p));
+      c.rhoA = take((size_t)(n + 1) * M * e);
+      c.rhoB = take((size_t)(n + 1) * Lc * e);
+      c.partB = take((size_t)g->nchunksB * (n + 1) * Lc * e);
+      c.coef = take((size_t)M * Lc * e + e);
+      c.gA = take((size_t)N * M * e);
+      c.gB = take((size_t)N * Lc * e);
+      c.YA = take((size_t)g->PA * 2 * M * e);
+      c.YB = take((size_t)g->PB * 2 * Lc * e);
+      c.eA = take((size_t)(n + 1) * M * e);
+      c.eB = take((size_t)(n + 1) * Lc * e);
+    }
+  }
+  const int nc = g->lv.back().n, Nc = (nc - 1) * (nc - 1);
+  g->coarse_inv = take((size_t)Nc * Nc * 16);
+  const int nb = std::max(launch_stencil_blocks(n), launch_vec_blocks(n));
+  g->part = take((size_t)nb * 64 * sizeof(double));
+  g->scal = take(256 * sizeof(double));
+  g->r64 = take(g->field_bytes(0, P64));
+  g->tw = take(g->field_bytes(0, P64));
+  g->tz = take(g->field_bytes(0, P64));
+  g->tt = take(g->field_bytes(0, P64));
+  if (g->prec_on[P32]) {
+    g->f32 = take(g->field_bytes(0, P32));
+    g->u32 = take(g->field_bytes(0, P32));
+  }
+  const int m = g->d.max_restart;
+  if (m > 0) {
+    g->W = take((size_t)(m + 1) * g->field_bytes(0, P64));
+    for (int p = 0; p < 2; ++p)
+      if (g->prec_on[p]) g->Z[p] = take((size_t)m * g->field_bytes(0, p));
+  }
+  g->gm = take((size_t)(16 * (m + 2) + 2 * (m + 1) * (m + 1) + 64) * sizeof(double));
+  g->zeta_f = take(2 * (n + 1) * sizeof(double));
+  g->need = off;
+}
+
+GmresState gmres_state(mgc_grid g) {
+  const int m = std::max(g->d.max_restart, 1);
+  double* b = g->at<double>(g->gm);
+  GmresState s;
+  size_t o = 0;
+  auto take = [&](size_t cnt) { double* p = b + o; o += cnt; return p; };
+  s.dots = take(2 * (m + 1));
+  s.hcol = take(2 * (m + 1));
+  s.axcoef = reinterpret_cast<double2*>(take(2 * (m + 1)));
+  s.nrm2 = take(2);
+  s.scale = take(m + 2);
+  s.H = take(2 * (m + 1) * m);
+  s.cs = take(2 * m);
+  s.sn = take(2 * m);
+  s.g = take(2 * (m + 1));
+  s.est = take(m);
+  s.y = take(2 * m);
+  s.upcoef = reinterpret_cast<double2*>(take(2 * m));
+  s.beta = take(2);
+  s.kstar = reinterpret_cast<int*>(take(2));
+  s.kused = reinterpret_cast<int*>(take(2));
+  return s;
+}
+
+template <typename T> Level<T> level_of(mgc_grid g, int l) {
+  const int p = sizeof(T) == 8 ? P64 : P32;
+  const LevelInfo& L = g->lv[l];
+  const size_t e = esize(p), sz = (size_t)(L.n + 1) * e;
+  Level<T> out;
+  const char* base = g->ws + L.tab[p];
+  out.a = (const v2<T>*)(base);
+  out.c = (const v2<T>*)(base + sz);
+  out.px = (const v2<T>*)(base + 2 * sz);
+  out.py = (const v2<T>*)(base + 3 * sz);
+  out.tm = (const v2<T>*)(base + 4 * sz);
+  out.n = L.n;
+  out.pitch = L.pitch;
+  out.E = (T)g->E;
+  return out;
+}
+
+template <typename T = double> Level<T> exact_level(mgc_grid g) {
+  const int n = g->d.n;
+  const size_t sz = (size_t)(n + 1) * sizeof(v2<T>);
+  const char* base = g->ws + (sizeof(T) == 8 ? g->exact_tab : g->exact_tab32);
+  Level<T> out;
+  out.a = (const v2<T>*)(base);
+  out.c = (const v2<T>*)(base + sz);
+  out.px = (const v2<T>*)(base + 2 * sz);
+  out.py = (const v2<T>*)(base + 3 * sz);
+  out.tm = (const v2<T>*)(base + 4 * sz);
+  out.n = n;
+  out.pitch = g->lv[0].pitch;
+  out.E = (T)g->E;
+  return out;
+}
+
+template <typename T> ChanTab<T> chan_of(mgc_grid g) {
+  const int p = sizeof(T) == 8 ? P64 : P32;
+  const CcOff& c = g->cc[p];
+  ChanTab<T> t;
+  t.wphi = g->at<const v2<T>>(c.wphi);
+  t.phi = g->at<const v2<T>>(c.phi);
+  t.wvphi = g->at<const v2<T>>(c.wvphi);
+  t.vphi = g->at<const v2<T>>(c.vphi);
+  t.M = g->d.M;
+  t.L = g->d.Lch;
+  return t;
+}
+
+template <typename T> ChanSys<T> sys_of(mgc_grid g, bool A) {
+  const int p = sizeof(T) == 8 ? P64 : P32;
+  const SysOff& s = A ? g->cc[p].A : g->cc[p].B;
+  ChanSys<T> o;
+  o.G = g->at<const v2<T>>(s.G);
+  o.Vs = g->at<const v2<T>>(s.Vs);
+  o.Ws = g->at<const v2<T>>(s.Ws);
+  o.lo = g->at<const v2<T>>(s.lo);
+  o.up = g->at<const v2<T>>(s.up);
+  o.Rinv = g->at<const v2<T>>(s.Rinv);
+  o.Rlo = g->at<const v2<T>>(s.Rlo);
+  o.Rup = g->at<const v2<T>>(s.Rup);
+  o.start = g->at<const int>(s.start);
+  o.N = g->d.n - 1;
+  o.M = A ? g->d.M : g->d.Lch;
+  o.P = A ? g->PA : g->PB;
+  return o;
+}
+
+CccsScratch scratch_of(mgc_grid g, int p) {
+  const CcOff& c = g->cc[p];
+  CccsScratch w;
+  w.rbuf = g->ws + c.rbuf;
+  w.rhoA = g->ws + c.rhoA;
+  w.rhoB = g->ws + c.rhoB;
+  w.partB = g->ws + c.partB;
+  w.coef = g->ws + c.coef;
+  w.gA = g->ws + c.gA;
+  w.gB = g->ws + c.gB;
+  w.YA = g->ws + c.YA;
+  w.YB = g->ws + c.YB;
+  w.eA = g->ws + c.eA;
+  w.eB = g->ws + c.eB;
+  return w;
+}
+
+// --------------------------------------------------------------------------
+// uploads
+template <typename T> std::vector<v2<T>> cast_vec(const std::vector<cd>& v) {
+  std::vector<v2<T>> o(v.size());
+  for (size_t i = 0; i < v.size(); ++i) { o[i].x = (T)v[i].real(); o[i].y = (T)v[i].imag(); }
+  return o;
+}
+
+mgc_status upload(mgc_grid g, size_t off, const void* src, size_t bytes) {
+  HIPCHK(g, hipMemcpyAsync(g->ws + off, src, bytes, hipMemcpyHostToDevice, g->stream));
+  HIPCHK(g, hipStreamSynchronize(g->stream));   // host vectors are temporaries
+  return MGC_OK;
+}
+
+template <typename T> mgc_status upload_cplx(mgc_grid g, size_t off, const std::vector<cd>& v) {
+  auto c = cast_vec<T>(v);
+  return upload(g, off, c.data(), c.size() * sizeof(v2<T>));
+}
+
+std::vector<cd> one_body(const Axis& ax, double Z) {
+  std::vector<cd> V(ax.n + 1, 0.0);
+  for (int j = 1; j < ax.n; ++j) V[j] = -Z / ax.z[j];
+  return V;
+}
+
+// a, c, px, py, tm for an axis (concatenated)
+std::vector<cd> level_tables(const Axis& ax, double Z1, double Z2, double lam) {
+  const int n = ax.n;
+  std::vector<cd> t(5 * (n + 1), 0.0);
+  for (int j = 1; j < n; ++j) {
+    t[j] = ax.a[j];
+    t[(n + 1) + j] = ax.c[j];
+    t[2 * (n + 1) + j] = ax.b[j] - Z1 / ax.z[j];
+    t[3 * (n + 1) + j] = ax.b[j] - Z2 / ax.z[j];
+    t[4 * (n + 1) + j] = lam / ax.z[j];
+  }
+  return t;
+}
+
+mgc_status check_ready(mgc_grid g, bool need_energy = true) {
+  if (!g) return fail(MGC_EINVAL, "null handle");
+  if (g->failed) return fail(MGC_ESTATE, "handle failed after an earlier HIP error: " + g_err);
+  if (!g->ws) return fail(MGC_ESTATE, "no workspace bound");
+  if (need_energy && !g->have_energy) return fail(MGC_ESTATE, "set_potential and set_energy required");
+  return MGC_OK;
+}
+
+// --------------------------------------------------------------------------
+// V-cycle and CCCS drivers
+template <typename T>
+void vcycle_level(mgc_grid g, int l, void* u, const void* f, bool zero_guess, const double* fs = nullptr) {
+  const int p = sizeof(T) == 8 ? P64 : P32;
+  hipStream_t s = g->stream;
+  Level<T> L = level_of<T>(g, l);
+  if (l == g->coarsest()) {
+    launch_coarse_solve<T>(s, g->at<const double2>(g->coarse_inv), L.n, L.pitch, f, u);
+    return;
+  }
+  const LevelInfo& LI = g->lv[l];
+  const LevelInfo& LC = g->lv[l + 1];
+  const double om = g->d.omega;
+  if (zero_guess && g->d.nu1 == 1 && g->d.nu2 == 1) {
+    // fused passes: u' = omega f/d is recomputed, never stored
+    launch_s1_zero<T>(s, L, f, fs, om, g->ws + LC.ff[p], LC.pitch);
+    vcycle_level<T>(g, l + 1, g->ws + LC.fu[p], g->ws + LC.ff[p], true);
+    launch_s2_zero<T>(s, L, f, fs, om, g->ws + LC.fu[p], LC.pitch, u);
+    return;
+  }
+  void* bufs[2] = {u, g->ws + LI.ft[p]};
+  int cur = 0;
+  bool zero = zero_guess;
+  for (int it = 0; it < g->d.nu1; ++it) {
+    launch_jacobi<T>(s, L, zero ? nullptr : bufs[cur], f, bufs[1 - cur], om);
+    zero = false;
+    cur = 1 - cur;
+  }
+  if (zero) launch_fill_zero(s, bufs[cur], g->field_bytes(l, p));  // nu1 == 0 with a zero guess
+  launch_resid_restrict<T>(s, L, bufs[cur], f, g->ws + LC.ff[p], LC.pitch);
+  vcycle_level<T>(g, l + 1, g->ws + LC.fu[p], g->ws + LC.ff[p], true);
+  launch_prolong_add<T>(s, L.n, L.pitch, bufs[cur], g->ws + LC.fu[p], LC.pitch);
+  for (int it = 0; it < g->d.nu2; ++it) {
+    launch_jacobi<T>(s, L, bufs[cur], f, bufs[1 - cur], om);
+    cur = 1 - cur;
+  }
+  if (cur != 0) launch_scale_copy<T, T>(s, L.n, L.pitch, L.pitch, bufs[cur], nullptr, u);
+}
+
+template <typename T> void cccs_apply(mgc_grid g, void* u, const void* f, const double* fs = nullptr) {
+  if (g->d.M == 0 && g->d.Lch == 0) return;
+  const int p = sizeof(T) == 8 ? P64 : P32;
+  launch_cccs<T>(g->stream, level_of<T>(g, 0), u, f, fs, chan_of<T>(g), sys_of<T>(g, true),
+                 sys_of<T>(g, false), scratch_of(g, p));
+}
+
+// One MG-CCCS cycle.  fs (nullable device scalar) scales f; the fused
+// zero-guess path applies it on the fly, otherwise f is scaled into scratch.
+template <typename T>
+void mgcccs_cycle(mgc_grid g, void* u, const void* f, bool zero_guess, const double* fs = nullptr) {
+  if (fs && !(zero_guess && g->d.nu1 == 1 && g->d.nu2 == 1)) {
+    const int p = sizeof(T) == 8 ? P64 : P32;
+    void* tmp = p == P64 ? (void*)(g->ws + g->tw) : (void*)(g->ws + g->f32);
+    launch_scale_copy<T, T>(g->stream, g->d.n, g->lv[0].pitch, g->lv[0].pitch, f, fs, tmp);
+    f = tmp;
+    fs = nullptr;
+  }
+  vcycle_level<T>(g, 0, u, f, zero_guess, fs);
+  cccs_apply<T>(g, u, f, fs);
+}
+
+// relres of (u, f) with the exact operator; r written to r64.  Synchronises.
+mgc_status exact_residual(mgc_grid g, const void* u, const void* f, void* r, double* rr2, double* ff2) {
+  const int nb = launch_stencil_blocks(g->d.n);
+  double* part = g->at<double>(g->part);
+  double* out = g->at<double>(g->scal);
+  launch_stencil<double, double, double, double>(g->stream, exact_level(g), u, f, r, 0, part);
+  launch_sum_partials(g->stream, nb, 2, part, out);
+  double h[2];
+  HIPCHK(g, hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, g->stream));
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  *rr2 = h[0];
+  *ff2 = h[1];
+  return MGC_OK;
+}
+
+void record(mgc_stats* st, int idx, double v) {
+  if (!st) return;
+  if (st->hist && idx < st->hist_cap) {
+    st->hist[idx] = v;
+    st->hist_len = idx + 1;
+  }
+}
+
+mgc_status finish_status(double relres, double tol) {
+  if (!std::isfinite(relres)) return fail(MGC_ENUMERIC, "non-finite residual");
+  if (relres > tol) return fail(MGC_ENOCONV, "iteration limit reached");
+  return MGC_OK;
+}
+
+// ---- stationary -----------------------------------------------------------
+mgc_status solve_stationary(mgc_grid g, void* u, const void* f, const mgc_solve_opts* o, mgc_stats* st) {
+  double rr, ff;
+  mgc_status rc = exact_residual(g, u, f, g->ws + g->r64, &rr, &ff);
+  if (rc) return rc;
+  const double fn = std::sqrt(ff);
+  double rel = std::sqrt(rr) / fn;
+  record(st, 0, rel);
+  int it = 0;
+  while (rel > o->tol && it < o->max_it && std::isfinite(rel)) {
+    mgcccs_cycle<double>(g, u, f, false);
+    ++it;
+    rc = exact_residual(g, u, f, g->ws + g->r64, &rr, &ff);
+    if (rc) return rc;
+    rel = std::sqrt(rr) / fn;
+    record(st, it, rel);
+  }
+  if (st) { st->iters = it; st->vcycles = it; st->relres = rel; }
+  return finish_status(rel, o->tol);
+}
+
+// ---- iterative refinement ---------------------------------------------------
+mgc_status solve_ir(mgc_grid g, void* u, const void* f, const mgc_solve_opts* o, mgc_stats* st) {
+  const int n = g->d.n, pitch = g->lv[0].pitch;
+  double rr, ff;
+  void* r = g->ws + g->r64;
+  mgc_status rc = exact_residual(g, u, f, r, &rr, &ff);
+  if (rc) return rc;
+  const double fn = std::sqrt(ff);
+  double rel = std::sqrt(rr) / fn;
+  record(st, 0, rel);
+  int it = 0, cyc = 0;
+  double* sc = g->at<double>(g->scal) + 8;
+  double* nr = g->at<double>(g->scal);
+  const double Nn = (double)(n - 1) * (n - 1);
+  while (rel > o->tol && it < o->max_it && std::isfinite(rel)) {
+    launch_ir_scale(g->stream, nr, Nn, sc);
+    if (o->inner == MGC_FP32) {
+      launch_scale_copy<double, float>(g->stream, n, pitch, pitch, r, sc, g->ws + g->f32);
+      for (int c = 0; c < o->inner_cycles; ++c) mgcccs_cycle<float>(g, g->ws + g->u32, g->ws + g->f32, c == 0);
+      launch_update<float>(g->stream, n, pitch, 0, g->ws + g->u32, 1, (const double2*)(sc + 1), (double2*)u);
+    } else {
+      launch_scale_copy<double, double>(g->stream, n, pitch, pitch, r, sc, g->ws + g->tw);
+      for (int c = 0; c < o->inner_cycles; ++c) mgcccs_cycle<double>(g, g->ws + g->tz, g->ws + g->tw, c == 0);
+      launch_update<double>(g->stream, n, pitch, 0, g->ws + g->tz, 1, (const double2*)(sc + 1), (double2*)u);
+    }
+    cyc += o->inner_cycles;
+    ++it;
+    rc = exact_residual(g, u, f, r, &rr, &ff);
+    if (rc) return rc;
+    rel = std::sqrt(rr) / fn;
+    record(st, it, rel);
+  }
+  if (st) { st->iters = it; st->vcycles = cyc; st->relres = rel; }
+  return finish_status(rel, o->tol);
+}
+
+// ---- FGMRES -------------------------------------------------------------------
+mgc_status solve_fgmres(mgc_grid g, void* u, const void* f, const mgc_solve_opts* o, mgc_stats* st) {
+  const int n = g->d.n, pitch = g->lv[0].pitch, m = o->restart;
+  const bool f32 = o->inner == MGC_FP32;
+  const size_t fb = g->field_bytes(0, P64), fbz = g->field_bytes(0, f32 ? P32 : P64);
+  const size_t stride64 = fb / 16, stridez = fbz / (f32 ? 8 : 16);
+  hipStream_t s = g->stream;
+  GmresState gs = gmres_state(g);
+  double2* W = g->at<double2>(g->W);
+  char* Z = g->ws + g->Z[f32 ? P32 : P64];
+  double* part = g->at<double>(g->part);
+  const int nbv = launch_vec_blocks(n);
+  Level<double> EX = exact_level(g);
+
+  // W_0 = f - A u
+  double rr, ff;
+  mgc_status rc = exact_residual(g, u, f, W, &rr, &ff);
+  if (rc) return rc;
+  const double fn = std::sqrt(ff);
+  double rel = std::sqrt(rr) / fn;
+  record(st, 0, rel);
+  launch_copy_scalar(s, g->at<double>(g->scal), gs.nrm2);
+  int it = 0, cycles = 0, rs = 0;
+  const bool use_graph = std::getenv("MGC_NO_GRAPH") == nullptr;
+  while (rel > o->tol && it < o->max_it && std::isfinite(rel)) {
+    const int mm = std::min(m, o->max_it - it);
+    auto enqueue_cycle = [&](hipStream_t st) {
+      hipStream_t saved = g->stream;
+      g->stream = st;                       // the cycle drivers launch on g->stream
+      launch_gmres_begin(st, gs, m);
+      for (int j = 0; j < mm; ++j) {
+        double2* Wj = W + (size_t)j * stride64;
+        double2* Wn = W + (size_t)(j + 1) * stride64;
+        char* Zj = Z + (size_t)j * fbz;
+        // preconditioner on the normalised basis vector v_j = s_j W_j
+        if (f32) {
+          launch_scale_copy<double, float>(st, n, pitch, pitch, Wj, gs.scale + j, g->ws + g->f32);
+          mgcccs_cycle<float>(g, Zj, g->ws + g->f32, true);
+          launch_stencil<double, float, double, double>(st, EX, Zj, nullptr, Wn, 1, nullptr);
+        } else {
+          mgcccs_cycle<double>(g, Zj, Wj, true, gs.scale + j);
+          launch_stencil<double, double, double, double>(st, EX, Zj, nullptr, Wn, 1, nullptr);
+        }
+        // classical Gram-Schmidt with one re-orthogonalisation
+        for (int pass = 0; pass < 2; ++pass) {
+          launch_multidot(st, n, pitch, stride64, W, j + 1, Wn, part);
+          launch_sum_partials(st, nbv, 2 * (j + 1), part, gs.dots);
+          launch_gmres_coef(st, gs, j, pass);
+          launch_multiaxpy(st, n, pitch, stride64, W, j + 1, gs.axcoef, Wn, part);
+        }
+        launch_sum_partials(st, nbv, 1, part, gs.nrm2);
+        launch_gmres_step(st, gs, j, m, o->tol * fn);
+      }
+      launch_gmres_solve(st, gs, m, mm);
+      if (f32) launch_update<float>(st, n, pitch, stridez, Z, mm, gs.upcoef, (double2*)u);
+      else launch_update<double>(st, n, pitch, stridez, Z, mm, gs.upcoef, (double2*)u);
+      g->stream = saved;
+    };
+    if (use_graph) {
+      GraphCache& gc = g->graph;
+      if (!gc.exec || gc.u != u || gc.f != f || gc.m != m || gc.mm != mm || gc.inner != (int)o->inner ||
+          gc.tol_abs != o->tol * fn) {
+        if (gc.exec) { (void)hipGraphExecDestroy(gc.exec); gc.exec = nullptr; }
+        hipGraph_t graph;
+        HIPCHK(g, hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal));
+        enqueue_cycle(g->cap);
+        HIPCHK(g, hipStreamEndCapture(g->cap, &graph));
+        hipError_t e = hipGraphInstantiate(&gc.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIPCHK(g, e);
+        gc.u = u; gc.f = f; gc.m = m; gc.mm = mm; gc.inner = (int)o->inner; gc.tol_abs = o->tol * fn;
+      }
+      HIPCHK(g, hipGraphLaunch(gc.exec, s));
+    } else {
+      enqueue_cycle(s);
+    }
+    ++cycles;
+    rc = exact_residual(g, u, f, W, &rr, &ff);
+    if (rc) return rc;
+    launch_copy_scalar(s, g->at<double>(g->scal), gs.nrm2);
+    int kused = mm;
+    HIPCHK(g, hipMemcpyAsync(&kused, gs.kused, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(g, hipStreamSynchronize(s));
+    it += std::min(kused, mm);
+    rel = std::sqrt(rr) / fn;
+    record(st, ++rs, rel);
+  }
+  if (st) { st->iters = it; st->vcycles = it; st->relres = rel; }
+  return finish_status(rel, o->tol);
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+const char* mgc_last_error(void) { return g_err.c_str(); }
+
+mgc_status mgc_create_grid(const mgc_grid_desc* d, void* hip_stream, mgc_grid* out) {
+  if (!d || !out) return fail(MGC_EINVAL, "null argument");
+  *out = nullptr;
+  const int n = d->n;
+  if (n < 8 || (n & (n - 1))) return fail(MGC_EINVAL, "n must be a power of two >= 8");
+  if (n > 16384) return fail(MGC_EINVAL, "n too large");
+  if (!(d->L > 0) || !(d->R0 > 0) || !(d->R0 <= d->L)) return fail(MGC_EINVAL, "need 0 < R0 <= L");
+  if (!(d->theta > 0) || !(d->theta < M_PI / 2)) return fail(MGC_EINVAL, "theta must lie in (0, pi/2)");
+  if (d->levels < 1 || (n >> (d->levels - 1)) < 4) return fail(MGC_EINVAL, "too many levels");
+  const int nc = n >> (d->levels - 1);
+  if ((nc - 1) * (nc - 1) > 1024) return fail(MGC_EINVAL, "coarsest level holds more than 1024 unknowns");
+  const double hc = d->L / nc;
+  const double jc = d->R0 / hc;
+  if (std::abs(jc - std::round(jc)) > 1e-9 * std::max(1.0, jc)) return fail(MGC_EINVAL, "R0 must be a node of the coarsest level");
+  if (d->M < 0 || d->Lch < 0 || d->M > 16 || d->Lch > 16) return fail(MGC_EINVAL, "channel counts must lie in [0, 16]");
+  if ((d->M == 0) != (d->Lch == 0)) return fail(MGC_EINVAL, "M and Lch must both be zero or both positive");
+  if (d->M >= n - 1 || d->Lch >= n - 1) return fail(MGC_EINVAL, "too many channels for the grid");
+  if (!(d->omega > 0) || !(d->omega < 2)) return fail(MGC_EINVAL, "omega must lie in (0, 2)");
+  if (d->nu1 < 0 || d->nu2 < 0 || d->nu1 + d->nu2 < 1 || d->nu1 > 8 || d->nu2 > 8) return fail(MGC_EINVAL, "bad smoothing counts");
+  if (!(d->pc_gamma >= 0) || !(d->pc_gamma < M_PI / 4)) return fail(MGC_EINVAL, "pc_gamma must lie in [0, pi/4)");
+  if (d->pc_first_level < 0) return fail(MGC_EINVAL, "pc_first_level must be >= 0");
+  if (d->max_restart < 0 || d->max_restart > 32) return fail(MGC_EINVAL, "max_restart must lie in [0, 32]");
+  if ((d->precisions & 1) == 0 || (d->precisions & ~3)) return fail(MGC_EINVAL, "precisions must include MGC_FP64");
+
+  mgc_grid g = new mgc_grid_s();
+  g->d = *d;
+  g->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&g->device) != hipSuccess) g->device = 0;
+  if (hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking) != hipSuccess) {
+    delete g;
+    return fail(MGC_EHIP, "could not create the capture stream");
+  }
+  g->prec_on[P64] = true;
+  g->prec_on[P32] = (d->precisions & 2) != 0;
+  g->exact = make_axis(n, d->L, d->R0, d->theta, 0.0);
+  for (int l = 0; l < d->levels; ++l) {
+    LevelInfo L;
+    L.n = n >> l;
+    L.pitch = pitch_for(L.n);
+    const double gam = (l >= d->pc_first_level) ? d->pc_gamma : 0.0;
+    L.ax = make_axis(L.n, d->L, d->R0, d->theta, gam);
+    g->lv.push_back(L);
+  }
+  const int N = n - 1;
+  auto chunks = [&](int) {
+    int P = (int)std::lround(std::sqrt(N / 2.0));
+    return std::max(1, std::min(64, P));
+  };
+  g->PA = chunks(d->M);
+  g->PB = chunks(d->Lch);
+  g->nchunksB = (N + 63) / 64;
+  layout(g);
+  *out = g;
+  return MGC_OK;
+}
+
+mgc_status mgc_workspace_bytes(mgc_grid g, size_t* bytes) {
+  if (!g || !bytes) return fail(MGC_EINVAL, "null argument");
+  *bytes = g->need;
+  return MGC_OK;
+}
+
+mgc_status mgc_bind_workspace(mgc_grid g, void* ptr, size_t bytes) {
+  if (!g) return fail(MGC_EINVAL, "null handle");
+  if (g->failed) return fail(MGC_ESTATE, "handle failed");
+  if (!ptr || ((uintptr_t)ptr & 255)) return fail(MGC_EINVAL, "workspace must be non-null and 256-byte aligned");
+  if (bytes < g->need) return fail(MGC_ENOMEM, "workspace too small");
+  g->ws = (char*)ptr;
+  g->ws_bytes = bytes;
+  HIPCHK(g, hipMemsetAsync(g->ws, 0, g->need, g->stream));
+  // exact-operator dual weights (for the transpose solve)
+  mgc_status rc = upload_cplx<double>(g, g->exact_w, g->exact.w);
+  if (rc) return rc;
+  if ((rc = upload_cplx<double>(g, g->exact_z, g->exact.z))) return rc;
+  g->have_pot = g->have_energy = false;
+  return MGC_OK;
+}
+
+mgc_status mgc_field_pitch(mgc_grid g, int level, int* pitch) {
+  if (!g || !pitch) return fail(MGC_EINVAL, "null argument");
+  if (level < 0 || level >= (int)g->lv.size()) return fail(MGC_EINVAL, "level out of range");
+  *pitch = g->lv[level].pitch;
+  return MGC_OK;
+}
+
+mgc_status mgc_set_potential(mgc_grid g, double Z1, double Z2, double lambda) {
+  mgc_status rc = check_ready(g, false);
+  if (rc) return rc;
+  if (!std::isfinite(Z1) || !std::isfinite(Z2) || !std::isfinite(lambda) || Z1 < 0)
+    return fail(MGC_EINVAL, "potential strengths must be finite, Z1 >= 0");
+  auto t0 = std::chrono::steady_clock::now();
+  drop_graph(g);
+  g->have_pot = g->have_energy = false;
+  g->Z1 = Z1; g->Z2 = Z2; g->lam = lambda;
+  const int n = g->d.n, M = g->d.M, Lc = g->d.Lch;
+  std::string err;
+  // level tables of the exact operator and of the hierarchy
+  {
+    auto t = level_tables(g->exact, Z1, Z2, lambda);
+    if ((rc = upload_cplx<double>(g, g->exact_tab, t))) return rc;
+    if (g->prec_on[P32] && (rc = upload_cplx<float>(g, g->exact_tab32, t))) return rc;
+  }
+  for (size_t l = 0; l < g->lv.size(); ++l) {
+    auto t = level_tables(g->lv[l].ax, Z1, Z2, lambda);
+    if ((rc = upload_cplx<double>(g, g->lv[l].tab[P64], t))) return rc;
+    if (g->prec_on[P32] && (rc = upload_cplx<float>(g, g->lv[l].tab[P32], t))) return rc;
+  }
+  // bound states of the hierarchy's level-0 one-body Hamiltonians
+  const Axis& ax = g->lv[0].ax;
+  if (M > 0) {
+    if (!bound_states(ax, one_body(ax, Z1), M, 2, g->lamA, g->phi, err)) return fail(MGC_ENUMERIC, err);
+    if (!bound_states(ax, one_body(ax, Z2), Lc, 2, g->lamB, g->vphi, err)) return fail(MGC_ENUMERIC, err);
+    std::vector<cd> wphi((size_t)M * (n + 1)), phi((size_t)M * (n + 1)),
+        wvphi((size_t)Lc * (n + 1)), vphi((size_t)Lc * (n + 1));
+    for (int i = 0; i < M; ++i)
+      for (int j = 0; j <= n; ++j) {
+        phi[(size_t)i * (n + 1) + j] = g->phi[i][j];
+        wphi[(size_t)i * (n + 1) + j] = ax.w[j] * g->phi[i][j];
+      }
+    for (int l = 0; l < Lc; ++l)
+      for (int k = 0; k <= n; ++k) {
+        vphi[(size_t)l * (n + 1) + k] = g->vphi[l][k];
+        wvphi[(size_t)l * (n + 1) + k] = ax.w[k] * g->vphi[l][k];
+      }
+    for (int p = 0; p < 2; ++p) {
+      if (!g->prec_on[p]) continue;
+      const CcOff& c = g->cc[p];
+      auto up = [&](size_t off, const std::vector<cd>& v) {
+        return p == P64 ? upload_cplx<double>(g, off, v) : upload_cplx<float>(g, off, v);
+      };
+      if ((rc = up(c.wphi, wphi)) || (rc = up(c.phi, phi)) || (rc = up(c.wvphi, wvphi)) ||
+          (rc = up(c.vphi, vphi)))
+        return rc;
+    }
+  }
+  g->have_pot = true;
+  g->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return MGC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// Channel potential V[node][i][m] = sum_j w_j (lam / z_max(j,node)) f_i(j) f_m(j)
+// evaluated with prefix sums:  (lam/z_node) sum_{j<=node} g_im(j) + sum_{j>node} (lam/z_j) g_im(j).
+std::vector<cd> channel_potential(const Axis& ax, double lam, const std::vector<std::vector<cd>>& f) {
+  const int n = ax.n, M = (int)f.size(), MM = M * M;
+  std::vector<cd> V((size_t)(n + 1) * MM, 0.0), pre(MM, 0.0), suf((size_t)(n + 2) * MM, 0.0);
+  for (int j = n - 1; j >= 1; --j)
+    for (int i = 0; i < M; ++i)
+      for (int m = 0; m < M; ++m)
+        suf[(size_t)j * MM + i * M + m] = suf[(size_t)(j + 1) * MM + i * M + m] +
+                                          (lam / ax.z[j]) * ax.w[j] * f[i][j] * f[m][j];
+  for (int k = 1; k < n; ++k) {
+    for (int i = 0; i < M; ++i)
+      for (int m = 0; m < M; ++m) pre[i * M + m] += ax.w[k] * f[i][k] * f[m][k];
+    for (int q = 0; q < MM; ++q)
+      V[(size_t)k * MM + q] = (lam / ax.z[k]) * pre[q] + suf[(size_t)(k + 1) * MM + q];
+  }
+  return V;
+}
+
+template <typename T>
+mgc_status upload_factors(mgc_grid g, int p, const SysOff& so, const ChannelFactors& f) {
+  mgc_status rc;
+  auto up = [&](size_t off, const std::vector<cd>& v) { return upload_cplx<T>(g, off, v); };
+  if ((rc = up(so.G, f.G)) || (rc = up(so.Vs, f.Vs)) || (rc = up(so.Ws, f.Ws)) || (rc = up(so.lo, f.lo)) ||
+      (rc = up(so.up, f.up)))
+    return rc;
+  if (f.P > 1) {
+    if ((rc = up(so.Rinv, f.Rinv)) || (rc = up(so.Rlo, f.Rlo)) || (rc = up(so.Rup, f.Rup))) return rc;
+  }
+  (void)p;
+  return upload(g, so.start, f.start.data(), f.start.size() * sizeof(int));
+}
+}  // namespace
+
+extern "C" {
+
+mgc_status mgc_set_energy(mgc_grid g, double E) {
+  mgc_status rc = check_ready(g, false);
+  if (rc) return rc;
+  if (!g->have_pot) return fail(MGC_ESTATE, "set_potential required before set_energy");
+  if (!std::isfinite(E)) return fail(MGC_EINVAL, "E must be finite");
+  auto t0 = std::chrono::steady_clock::now();
+  drop_graph(g);
+  g->have_energy = false;
+  g->E = E;
+  std::string err;
+  const int n = g->d.n, N = n - 1, M = g->d.M, Lc = g->d.Lch;
+  // coupled channel systems on the hierarchy's level-0 axis
+  if (M > 0) {
+    const Axis& ax = g->lv[0].ax;
+    for (int sys = 0; sys < 2; ++sys) {
+      const bool isA = sys == 0;
+      const int m = isA ? M : Lc;
+      const auto& basis = isA ? g->phi : g->vphi;
+      const auto& lamv = isA ? g->lamA : g->lamB;
+      const double Zo = isA ? g->Z2 : g->Z1;      // one-body potential of the free coordinate
+      std::vector<cd> V = channel_potential(ax, g->lam, basis);
+      std::vector<cd> lo(N), upv(N), D((size_t)N * m * m, 0.0);
+      for (int t = 0; t < N; ++t) {
+        const int node = t + 1;
+        lo[t] = ax.a[node];
+        upv[t] = ax.c[node];
+        for (int q = 0; q < m * m; ++q) D[(size_t)t * m * m + q] = V[(size_t)node * m * m + q];
+        const cd dd = ax.b[node] - Zo / ax.z[node] - E;
+        for (int i = 0; i < m; ++i) D[(size_t)t * m * m + i * m + i] += dd + lamv[i];
+      }
+      ChannelFactors f;
+      if (!factor_channels(N, m, isA ? g->PA : g->PB, lo, upv, D, f, err)) return fail(MGC_ENUMERIC, err);
+      if ((rc = upload_factors<double>(g, P64, isA ? g->cc[P64].A : g->cc[P64].B, f))) return rc;
+      if (g->prec_on[P32] && (rc = upload_factors<float>(g, P32, isA ? g->cc[P32].A : g->cc[P32].B, f)))
+        return rc;
+    }
+  }
+  // coarsest level: dense inverse of the rediscretised operator
+  {
+    const LevelInfo& C = g->lv.back();
+    const int nc = C.n, m = nc - 1, Nc = m * m;
+    const Axis& ax = C.ax;
+    std::vector<cd> A((size_t)Nc * Nc, 0.0);
+    for (int k = 1; k < nc; ++k)
+      for (int j = 1; j < nc; ++j) {
+        const int r = (k - 1) * m + (j - 1);
+        const cd d = ax.b[j] - g->Z1 / ax.z[j] + ax.b[k] - g->Z2 / ax.z[k] + g->lam / ax.z[std::max(j, k)] - E;
+        A[(size_t)r * Nc + r] = d;
+        if (j > 1) A[(size_t)r * Nc + r - 1] = ax.a[j];
+        if (j < m) A[(size_t)r * Nc + r + 1] = ax.c[j];
+        if (k > 1) A[(size_t)r * Nc + r - m] = ax.a[k];
+        if (k < m) A[(size_t)r * Nc + r + m] = ax.c[k];
+      }
+    std::vector<cd> inv;
+    if (!dense_inverse(Nc, A, inv, err)) return fail(MGC_ENUMERIC, "coarsest operator: " + err);
+    if ((rc = upload_cplx<double>(g, g->coarse_inv, inv))) return rc;
+  }
+  g->have_energy = true;
+  g->t_setup_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return MGC_OK;
+}
+
+mgc_status mgc_build_rhs_tp(mgc_grid g, void* chi, mgc_precision prec) {
+  mgc_status rc = check_ready(g, false);
+  if (rc) return rc;
+  if (!g->have_pot) return fail(MGC_ESTATE, "set_potential required");
+  if (!chi) return fail(MGC_EINVAL, "null field");
+  if (prec != MGC_FP64) return fail(MGC_EINVAL, "right-hand side is built in FP64");
+  if (!(g->E + 0.5 * g->Z1 * g->Z1 > 0))
+    return fail(MGC_EINVAL, "impact right-hand side needs E above the 1s threshold -Z1^2/2");
+  const double k0 = std::sqrt(2.0 * (g->E + 0.5 * g->Z1 * g->Z1));
+  launch_rhs_tp(g->stream, g->d.n, g->lv[0].pitch, g->exact.j0, g->at<const double2>(g->exact_z), g->Z1, g->Z2,
+                g->lam, k0, (double2*)chi);
+  HIPCHK(g, hipGetLastError());
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  return MGC_OK;
+}
+
+mgc_status mgc_residual(mgc_grid g, const void* u, const void* f, void* r, double* relres, mgc_precision prec) {
+  mgc_status rc = check_ready(g);
+  if (rc) return rc;
+  if (!u || !f || !r || r == u) return fail(MGC_EINVAL, "bad field pointers");
+  if (prec == MGC_FP64) {
+    if (relres) {
+      double rr, ff;
+      if ((rc = exact_residual(g, u, f, r, &rr, &ff))) return rc;
+      *relres = std::sqrt(rr / ff);
+    } else {
+      launch_stencil<double, double, double, double>(g->stream, exact_level(g), u, f, r, 0, nullptr);
+    }
+  } else {
+    if (!g->prec_on[P32]) return fail(MGC_EINVAL, "FP32 not enabled in the descriptor");
+    double* part = g->at<double>(g->part);
+    launch_stencil<float, float, float, float>(g->stream, exact_level<float>(g), u, f, r, 0, relres ? part : nullptr);
+    if (relres) {
+      double* out = g->at<double>(g->scal);
+      launch_sum_partials(g->stream, launch_stencil_blocks(g->d.n), 2, part, out);
+      double h[2];
+      HIPCHK(g, hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, g->stream));
+      HIPCHK(g, hipStreamSynchronize(g->stream));
+      *relres = std::sqrt(h[0] / h[1]);
+    }
+  }
+  HIPCHK(g, hipGetLastError());
+  return MGC_OK;
+}
+
+mgc_status mgc_vcycle(mgc_grid g, void* u, const void* f, mgc_precision prec) {
+  mgc_status rc = check_ready(g);
+  if (rc) return rc;
+  if (!u || !f || u == f) return fail(MGC_EINVAL, "bad field pointers");
+  if (prec == MGC_FP64) vcycle_level<double>(g, 0, u, f, false);
+  else if (g->prec_on[P32]) vcycle_level<float>(g, 0, u, f, false);
+  else return fail(MGC_EINVAL, "FP32 not enabled in the descriptor");
+  HIPCHK(g, hipGetLastError());
+  return MGC_OK;
+}
+
+mgc_status mgc_cccs(mgc_grid g, void* u, const void* f, mgc_precision prec) {
+  mgc_status rc = check_ready(g);
+  if (rc) return rc;
+  if (!u || !f || u == f) return fail(MGC_EINVAL, "bad field pointers");
+  if (prec == MGC_FP64) cccs_apply<double>(g, u, f);
+  else if (g->prec_on[P32]) cccs_apply<float>(g, u, f);
+  else return fail(MGC_EINVAL, "FP32 not enabled in the descriptor");
+  HIPCHK(g, hipGetLastError());
+  return MGC_OK;
+}
+
+static mgc_status validate_opts(mgc_grid g, const mgc_solve_opts* o) {
+  if (!o) return fail(MGC_EINVAL, "null options");
+  if (!(o->tol > 0) || o->max_it < 1) return fail(MGC_EINVAL, "need tol > 0 and max_it >= 1");
+  if (o->inner != MGC_FP64 && o->inner != MGC_FP32) return fail(MGC_EINVAL, "bad inner precision");
+  if (o->inner == MGC_FP32 && !g->prec_on[P32]) return fail(MGC_EINVAL, "FP32 not enabled in the descriptor");
+  switch (o->outer) {
+    case MGC_STATIONARY:
+      if (o->inner != MGC_FP64) return fail(MGC_EINVAL, "stationary iteration runs in FP64");
+      if (g->d.pc_first_level == 0 && g->d.pc_gamma != 0.0)
+        return fail(MGC_EINVAL, "stationary iteration needs the exact level-0 operator (pc_first_level >= 1 or pc_gamma = 0)");
+      break;
+    case MGC_IR:
+      if (o->inner_cycles < 1 || o->inner_cycles > 16) return fail(MGC_EINVAL, "inner_cycles must lie in [1, 16]");
+      break;
+    case MGC_FGMRES:
+      if (o->restart < 1 || o->restart > g->d.max_restart) return fail(MGC_EINVAL, "restart must lie in [1, max_restart]");
+      break;
+    default:
+      return fail(MGC_EINVAL, "bad outer method");
+  }
+  return MGC_OK;
+}
+
+mgc_status mgc_solve(mgc_grid g, void* u, const void* f, const mgc_solve_opts* o, mgc_stats* st) {
+  mgc_status rc = check_ready(g);
+  if (rc) return rc;
+  if (!u || !f || u == f) return fail(MGC_EINVAL, "bad field pointers");
+  if ((rc = validate_opts(g, o))) return rc;
+  hipEvent_t e0, e1;
+  HIPCHK(g, hipEventCreate(&e0));
+  HIPCHK(g, hipEventCreate(&e1));
+  HIPCHK(g, hipEventRecord(e0, g->stream));
+  switch (o->outer) {
+    case MGC_STATIONARY: rc = solve_stationary(g, u, f, o, st); break;
+    case MGC_IR: rc = solve_ir(g, u, f, o, st); break;
+    default: rc = solve_fgmres(g, u, f, o, st); break;
+  }
+  if (rc == MGC_EHIP) return rc;
+  mgc_status rc2 = MGC_OK;
+  std::string keep = g_err;
+  if (!hip_ok(g, hipEventRecord(e1, g->stream), "hipEventRecord") ||
+      !hip_ok(g, hipEventSynchronize(e1), "hipEventSynchronize"))
+    rc2 = MGC_EHIP;
+  float ms = 0;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) { st->t_solve_ms = ms; st->t_setup_ms = g->t_setup_ms; }
+  if (rc2) return rc2;
+  g_err = keep;
+  if (!hip_ok(g, hipGetLastError(), "kernel launch")) return MGC_EHIP;
+  return rc;
+}
+
+mgc_status mgc_solve_transpose(mgc_grid g, void* v, const void* gv, const mgc_solve_opts* o, mgc_stats* st) {
+  mgc_status rc = check_ready(g);
+  if (rc) return rc;
+  if (!v || !gv || v == gv) return fail(MGC_EINVAL, "bad field pointers");
+  if ((rc = validate_opts(g, o))) return rc;
+  const int n = g->d.n, pitch = g->lv[0].pitch;
+  const double2* w = g->at<const double2>(g->exact_w);
+  double2* rhs = g->at<double2>(g->tt);                                // private to the transpose
+  launch_weight(g->stream, n, pitch, w, 1, (const double2*)gv, rhs);   // W^{-1} g
+  launch_weight(g->stream, n, pitch, w, 1, (const double2*)v, (double2*)v);   // y0 = W^{-1} v0
+  rc = mgc_solve(g, v, rhs, o, st);
+  if (rc == MGC_EHIP || rc == MGC_ESTATE || rc == MGC_EINVAL) return rc;
+  launch_weight(g->stream, n, pitch, w, 0, (const double2*)v, (double2*)v);   // v = W y
+  HIPCHK(g, hipGetLastError());
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  return rc;
+}
+
+mgc_status mgc_cross_section(mgc_grid g, const void* u, const void* chi, double k1, double k2,
+                             double zeta[2], double* sigma) {
+  mgc_status rc = check_ready(g);
+  if (rc) return rc;
+  if (!u || !chi || !zeta || !(k1 > 0) || !(k2 > 0)) return fail(MGC_EINVAL, "bad arguments");
+  const Axis& ax = g->exact;
+  const int n = ax.n, j0 = ax.j0;
+  const double h = ax.h;
+  // regular solution of (-1/2 d2/dx2 + V1 - k^2/2) phi = 0 by the 3-point
+  // recurrence on the real nodes, scaled to asymptotic amplitude 1/sqrt(k)
+  auto testfn = [&](double k, std::vector<double>& out) {
+    const int top = std::min(j0 + 1, n);
+    std::vector<double> ph(top + 1, 0.0);
+    ph[0] = 0.0;
+    ph[1] = h;
+    for (int j = 1; j < top; ++j) {
+      const double V1 = -g->Z1 / (j * h);
+      ph[j + 1] = 2 * ph[j] - ph[j - 1] + 2 * h * h * (V1 - 0.5 * k * k) * ph[j];
+    }
+    const int jr = std::min(j0, top - 1);
+    const double p = std::sqrt(k * k - 2.0 * (-g->Z1 / (jr * h)));
+    const double dphi = (ph[jr + 1] - ph[jr - 1]) / (2 * h);
+    const double amp = std::sqrt(ph[jr] * ph[jr] + (dphi / p) * (dphi / p));
+    const double sc = 1.0 / (amp * std::sqrt(p));
+    out.assign(2 * (n + 1), 0.0);
+    for (int j = 1; j <= std::min(j0, n - 1); ++j) out[j] = ph[j] * sc * (j == j0 ? 0.5 * h : h);
+  };
+  std::vector<double> f1, f2;
+  testfn(k1, f1);
+  testfn(k2, f2);
+  std::vector<double> both(2 * (n + 1));
+  for (int j = 0; j <= n; ++j) { both[j] = f1[j]; both[n + 1 + j] = f2[j]; }
+  if ((rc = upload(g, g->zeta_f, both.data(), both.size() * sizeof(double)))) return rc;
+  const double* d1 = g->at<const double>(g->zeta_f);
+  double* part = g->at<double>(g->part);
+  double* out = g->at<double>(g->scal);
+  launch_zeta_part(g->stream, n, g->lv[0].pitch, j0, exact_level(g).tm, d1, d1 + (n + 1), (const double2*)u,
+                   (const double2*)chi, part);
+  launch_sum_partials(g->stream, VEC_BLOCKS, 2, part, out);
+  double hz[2];
+  HIPCHK(g, hipMemcpyAsync(hz, out, sizeof(hz), hipMemcpyDeviceToHost, g->stream));
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  zeta[0] = hz[0];
+  zeta[1] = hz[1];
+  const double k0sq = 2.0 * (g->E + 0.5 * g->Z1 * g->Z1);
+  if (sigma) *sigma = 8.0 * M_PI * M_PI / k0sq * (hz[0] * hz[0] + hz[1] * hz[1]) / (k1 * k2);
+  return MGC_OK;
+}
+
+mgc_status mgc_destroy_grid(mgc_grid g) {
+  if (!g) return fail(MGC_EINVAL, "null handle");
+  if (g->graph.exec) (void)hipGraphExecDestroy(g->graph.exec);
+  if (g->cap) (void)hipStreamDestroy(g->cap);
+  delete g;
+  return MGC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,53 @@
+// Device-side types shared by the HIP kernels and the host launch code.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace mgc {
+
+template <typename T> struct vec2;
+template <> struct vec2<double> { using type = double2; };
+template <> struct vec2<float> { using type = float2; };
+template <typename T> using v2 = typename vec2<T>::type;
+
+// One multigrid level as seen by a stencil kernel.  All tables have n+1
+// entries indexed by node; entries 0 and n are never used.
+//   a, c : 3-point coefficients of -1/2 d^2/dz^2 (sub / super)
+//   px   : b_j + V1_j   (x1 diagonal part)
+//   py   : b_k + V2_k   (x2 diagonal part)
+//   tm   : lambda / z_m (two-body part, evaluated at m = max(j,k))
+// Diagonal of the operator: px[j] + py[k] + tm[max(j,k)] - E.
+template <typename T> struct Level {
+  const v2<T>* a;
+  const v2<T>* c;
+  const v2<T>* px;
+  const v2<T>* py;
+  const v2<T>* tm;
+  int n;
+  int pitch;
+  T E;
+};
+
+// CCCS tables of one precision on level 0.
+template <typename T> struct ChanTab {
+  const v2<T>* wphi;   // [M][n+1]  w_j phi_i(z_j)       (x1 channels)
+  const v2<T>* phi;    // [M][n+1]  phi_i(z_j)
+  const v2<T>* wvphi;  // [L][n+1]  w_k varphi_l(z_k)    (x2 channels)
+  const v2<T>* vphi;   // [L][n+1]  varphi_l(z_k)
+  int M, L;
+};
+
+// Factors of one coupled channel system (see ChannelFactors on the host).
+template <typename T> struct ChanSys {
+  const v2<T>* G;      // [N][M][M]
+  const v2<T>* Vs;     // [N][M][M]
+  const v2<T>* Ws;     // [N][M][M]
+  const v2<T>* lo;     // [N]
+  const v2<T>* up;     // [N]
+  const v2<T>* Rinv;   // [P-1][2M][2M]
+  const v2<T>* Rlo;    // [P-1][2M][2M]
+  const v2<T>* Rup;    // [P-1][2M][2M]
+  const int* start;    // [P+1]
+  int N, M, P;
+};
+
+}  // namespace mgc

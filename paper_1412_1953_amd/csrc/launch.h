@@ -1,0 +1,98 @@
+// Host-callable launchers of the gfx950 kernels (kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+
+namespace mgc {
+
+// Grid size of the grid-stride vector kernels (dots, axpys, copies).
+constexpr int VEC_BLOCKS = 1024;
+
+// Scratch of one CCCS application (device pointers, precision-agnostic).
+struct CccsScratch {
+  void* rbuf;    // level-0 field: residual
+  void* rhoA;    // [n+1][M]
+  void* rhoB;    // [n+1][L]
+  void* partB;   // [nchunks][n+1][L]
+  void* coef;    // [M][L]
+  void* gA;      // [N][M]   local solutions
+  void* gB;      // [N][L]
+  void* YA;      // [P-1][2M] interface solution
+  void* YB;      // [P-1][2L]
+  void* eA;      // [n+1][M] channel corrections
+  void* eB;      // [n+1][L]
+};
+
+// Device-resident FGMRES bookkeeping (all pointers into the workspace).
+struct GmresState {
+  double* dots;    // [2*(m+1)]     raw multi-dot results
+  double* hcol;    // [2*(m+1)]     accumulated projections of the current column
+  double2* axcoef; // [m+1]         multi-axpy coefficients
+  double* nrm2;    // [1]           squared norm
+  double* scale;   // [m+2]         1/||W_i|| of the unscaled basis
+  double* H;       // [2*(m+1)*m]   Hessenberg, column-major, rotated in place
+  double* cs;      // [2*m]
+  double* sn;      // [2*m]
+  double* g;       // [2*(m+1)]
+  double* est;     // [m]           residual estimate after each step
+  double* y;       // [2*m]
+  double2* upcoef; // [m]           update coefficients y_i
+  double* beta;    // [1]
+  int* kstar;      // [1]           first step meeting the tolerance (-1: none)
+  int* kused;      // [1]
+};
+
+int launch_stencil_blocks(int n);
+int launch_vec_blocks(int n);
+
+template <typename T, typename TU, typename TF, typename TO>
+void launch_stencil(hipStream_t s, const Level<T>& L, const void* u, const void* f, void* out,
+                    int mode, double* part);
+template <typename T>
+void launch_jacobi(hipStream_t s, const Level<T>& L, const void* u, const void* f, void* out, double omega);
+template <typename T>
+void launch_resid_restrict(hipStream_t s, const Level<T>& L, const void* u, const void* f, void* fc,
+                           int pitch_c);
+template <typename T>
+void launch_prolong_add(hipStream_t s, int n, int pitch, void* u, const void* ec, int pitch_c);
+template <typename T>
+void launch_coarse_solve(hipStream_t s, const double2* Ainv, int nc, int pitch, const void* f, void* u);
+// fused zero-guess passes (nu1 = nu2 = 1); fs: optional device scale of f
+template <typename T>
+void launch_s1_zero(hipStream_t s, const Level<T>& L, const void* f, const double* fs, double omega,
+                    void* fc, int pitch_c);
+template <typename T>
+void launch_s2_zero(hipStream_t s, const Level<T>& L, const void* f, const double* fs, double omega,
+                    const void* ec, int pitch_c, void* u);
+template <typename T>
+void launch_cccs(hipStream_t s, const Level<T>& L, void* u, const void* f, const double* fs,
+                 const ChanTab<T>& ch, const ChanSys<T>& SA, const ChanSys<T>& SB,
+                 const CccsScratch& w);
+
+void launch_multidot(hipStream_t s, int n, int pitch, size_t stride, const double2* W, int J,
+                     const double2* Y, double* part);
+void launch_multiaxpy(hipStream_t s, int n, int pitch, size_t stride, const double2* W, int J,
+                      const double2* coef, double2* Y, double* part);
+template <typename TZ>
+void launch_update(hipStream_t s, int n, int pitch, size_t stride, const void* Z, int J,
+                   const double2* coef, double2* u);
+template <typename TI, typename TO>
+void launch_scale_copy(hipStream_t s, int n, int pitch_in, int pitch_out, const void* in,
+                       const double* sc, void* out);
+void launch_weight(hipStream_t s, int n, int pitch, const double2* w, int divide, const double2* in,
+                   double2* out);
+void launch_sum_partials(hipStream_t s, int nb, int nq, const double* part, double* out);
+void launch_gmres_coef(hipStream_t s, const GmresState& st, int j, int pass);
+void launch_gmres_step(hipStream_t s, const GmresState& st, int j, int m, double tol_abs);
+void launch_gmres_begin(hipStream_t s, const GmresState& st, int m);
+void launch_gmres_solve(hipStream_t s, const GmresState& st, int m, int mm);
+void launch_ir_scale(hipStream_t s, const double* nrm2, double Nn, double* sc);
+void launch_copy_scalar(hipStream_t s, const double* src, double* dst);
+void launch_fill_zero(hipStream_t s, void* p, size_t bytes);   // bytes: multiple of 16
+void launch_rhs_tp(hipStream_t s, int n, int pitch, int j0, const double2* z, double Z1, double Z2,
+                   double lam, double k0, double2* chi);
+void launch_zeta_part(hipStream_t s, int n, int pitch, int j0, const double2* tm, const double* f1,
+                      const double* f2, const double2* u, const double2* chi, double* part);
+
+}  // namespace mgc

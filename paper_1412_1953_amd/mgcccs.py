@@ -1,0 +1,224 @@
+"""Thin Python binding of ``libmgcccs.so`` (C ABI in ``include/mgcccs.h``).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+PyTorch provides device memory (fields, workspace) and the HIP stream.  The
+library must be built (``__graft_entry__.build()``); importing this module
+without it raises immediately -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmgcccs.so")
+
+MGC_OK, MGC_EINVAL, MGC_ENOMEM, MGC_EHIP, MGC_ENOCONV, MGC_ESTATE, MGC_ENUMERIC = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "MGC_OK", -1: "MGC_EINVAL", -2: "MGC_ENOMEM", -3: "MGC_EHIP", -4: "MGC_ENOCONV",
+                -5: "MGC_ESTATE", -6: "MGC_ENUMERIC"}
+FP64, FP32 = 0, 1
+STATIONARY, IR, FGMRES = 0, 1, 2
+
+EXPORTED = ["mgc_create_grid", "mgc_workspace_bytes", "mgc_bind_workspace", "mgc_field_pitch",
+            "mgc_set_potential", "mgc_set_energy", "mgc_build_rhs_tp", "mgc_residual", "mgc_vcycle",
+            "mgc_cccs", "mgc_solve", "mgc_solve_transpose", "mgc_cross_section", "mgc_destroy_grid",
+            "mgc_last_error"]
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("L", ctypes.c_double), ("R0", ctypes.c_double),
+                ("theta", ctypes.c_double), ("levels", ctypes.c_int), ("M", ctypes.c_int),
+                ("Lch", ctypes.c_int), ("omega", ctypes.c_double), ("nu1", ctypes.c_int),
+                ("nu2", ctypes.c_int), ("pc_gamma", ctypes.c_double), ("pc_first_level", ctypes.c_int),
+                ("max_restart", ctypes.c_int), ("precisions", ctypes.c_int)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("outer", ctypes.c_int), ("inner", ctypes.c_int), ("restart", ctypes.c_int),
+                ("max_it", ctypes.c_int), ("inner_cycles", ctypes.c_int), ("tol", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("vcycles", ctypes.c_int), ("relres", ctypes.c_double),
+                ("hist", ctypes.POINTER(ctypes.c_double)), ("hist_cap", ctypes.c_int),
+                ("hist_len", ctypes.c_int), ("t_setup_ms", ctypes.c_double),
+                ("t_solve_ms", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not found: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    sig = {
+        "mgc_create_grid": [ctypes.POINTER(GridDesc), vp, ctypes.POINTER(vp)],
+        "mgc_workspace_bytes": [vp, ctypes.POINTER(ctypes.c_size_t)],
+        "mgc_bind_workspace": [vp, vp, ctypes.c_size_t],
+        "mgc_field_pitch": [vp, i, ctypes.POINTER(i)],
+        "mgc_set_potential": [vp, d, d, d],
+        "mgc_set_energy": [vp, d],
+        "mgc_build_rhs_tp": [vp, vp, i],
+        "mgc_residual": [vp, vp, vp, vp, ctypes.POINTER(d), i],
+        "mgc_vcycle": [vp, vp, vp, i],
+        "mgc_cccs": [vp, vp, vp, i],
+        "mgc_solve": [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(Stats)],
+        "mgc_solve_transpose": [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(Stats)],
+        "mgc_cross_section": [vp, vp, vp, d, d, ctypes.POINTER(d), ctypes.POINTER(d)],
+        "mgc_destroy_grid": [vp],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.mgc_last_error.argtypes = []
+    lib.mgc_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+class MGCError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(rc: int, allow=()):
+    if rc != MGC_OK and rc not in allow:
+        raise MGCError(rc, load_library().mgc_last_error().decode())
+    return rc
+
+
+@dataclasses.dataclass
+class SolveResult:
+    status: int
+    iters: int
+    vcycles: int
+    relres: float
+    history: list
+    t_setup_ms: float
+    t_solve_ms: float
+
+
+class Grid:
+    """One MG-CCCS handle with a torch-allocated workspace on a CUDA device."""
+
+    def __init__(self, n, L, R0, theta, levels, M, Lch=None, omega=2.0 / 3.0, nu1=1, nu2=1,
+                 pc_gamma=0.0, pc_first_level=0, max_restart=20, fp32=True, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        self.device = torch.device(device)
+        Lch = M if Lch is None else Lch
+        self.desc = GridDesc(n, L, R0, theta, levels, M, Lch, omega, nu1, nu2, pc_gamma,
+                             pc_first_level, max_restart, 1 | (2 if fp32 else 0))
+        self.n, self.levels, self.M, self.Lch = n, levels, M, Lch
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            h = ctypes.c_void_p()
+            _check(self.lib.mgc_create_grid(ctypes.byref(self.desc), ctypes.c_void_p(self.stream.cuda_stream),
+                                            ctypes.byref(h)))
+            self.h = h
+            nb = ctypes.c_size_t()
+            _check(self.lib.mgc_workspace_bytes(self.h, ctypes.byref(nb)))
+            self.workspace_bytes = nb.value
+            self._ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
+            base = self._ws.data_ptr()
+            off = (-base) % 256
+            _check(self.lib.mgc_bind_workspace(self.h, ctypes.c_void_p(base + off), nb.value))
+        p = ctypes.c_int()
+        _check(self.lib.mgc_field_pitch(self.h, 0, ctypes.byref(p)))
+        self.pitch = p.value
+
+    @classmethod
+    def from_workload(cls, w, **kw):
+        return cls(w.n, w.L, w.R0, w.theta, w.levels, w.M, omega=w.omega, nu1=w.nu1, nu2=w.nu2, **kw)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self.lib.mgc_destroy_grid(h)
+            self.h = None
+
+    # ---- fields --------------------------------------------------------------
+    def field(self, fp32: bool = False):
+        """Zero level-0 field: an (n+1) x (n+1) view of an (n+1) x pitch buffer."""
+        t = self.torch
+        buf = t.zeros((self.n + 1, self.pitch), dtype=t.complex64 if fp32 else t.complex128,
+                      device=self.device)
+        return buf[:, : self.n + 1]
+
+    def from_numpy(self, a, fp32: bool = False):
+        out = self.field(fp32)
+        out.copy_(self.torch.from_numpy(a).to(out.dtype))
+        return out
+
+    @staticmethod
+    def _ptr(x):
+        return ctypes.c_void_p(x.data_ptr())
+
+    def _prec(self, x):
+        return FP32 if x.dtype == self.torch.complex64 else FP64
+
+    # ---- entry points (same names as the C ABI) -------------------------------
+    def set_potential(self, Z1, Z2, lam):
+        _check(self.lib.mgc_set_potential(self.h, Z1, Z2, lam))
+
+    def set_energy(self, E):
+        _check(self.lib.mgc_set_energy(self.h, E))
+
+    def build_rhs_tp(self, chi):
+        _check(self.lib.mgc_build_rhs_tp(self.h, self._ptr(chi), FP64))
+        return chi
+
+    def residual(self, u, f, r, want_relres=True):
+        rel = ctypes.c_double()
+        _check(self.lib.mgc_residual(self.h, self._ptr(u), self._ptr(f), self._ptr(r),
+                                     ctypes.byref(rel) if want_relres else None, self._prec(u)))
+        return rel.value if want_relres else None
+
+    def vcycle(self, u, f):
+        _check(self.lib.mgc_vcycle(self.h, self._ptr(u), self._ptr(f), self._prec(u)))
+
+    def cccs(self, u, f):
+        _check(self.lib.mgc_cccs(self.h, self._ptr(u), self._ptr(f), self._prec(u)))
+
+    def _solve(self, fn, u, f, outer, inner, restart, max_it, inner_cycles, tol, hist_cap):
+        opts = SolveOpts(outer, inner, restart, max_it, inner_cycles, tol)
+        hist = (ctypes.c_double * hist_cap)()
+        st = Stats(0, 0, 0.0, ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)), hist_cap, 0,
+                   0.0, 0.0)
+        rc = _check(fn(self.h, self._ptr(u), self._ptr(f), ctypes.byref(opts), ctypes.byref(st)),
+                    allow=(MGC_ENOCONV, MGC_ENUMERIC))
+        hv = [hist[i] for i in range(st.hist_len)]
+        return SolveResult(rc, st.iters, st.vcycles, st.relres, hv, st.t_setup_ms, st.t_solve_ms)
+
+    def solve(self, u, f, outer=FGMRES, inner=FP64, restart=10, max_it=1000, inner_cycles=2,
+              tol=1e-10, hist_cap=4096):
+        return self._solve(self.lib.mgc_solve, u, f, outer, inner, restart, max_it, inner_cycles,
+                           tol, hist_cap)
+
+    def solve_transpose(self, v, g, outer=FGMRES, inner=FP64, restart=10, max_it=1000,
+                        inner_cycles=2, tol=1e-10, hist_cap=4096):
+        return self._solve(self.lib.mgc_solve_transpose, v, g, outer, inner, restart, max_it,
+                           inner_cycles, tol, hist_cap)
+
+    def cross_section(self, u, chi, k1, k2):
+        z = (ctypes.c_double * 2)()
+        sig = ctypes.c_double()
+        _check(self.lib.mgc_cross_section(self.h, self._ptr(u), self._ptr(chi), k1, k2, z,
+                                          ctypes.byref(sig)))
+        return complex(z[0], z[1]), sig.value
+
+
+def k0_of(E: float, Z1: float = 1.0) -> float:
+    """Incoming momentum sqrt(2(E + Z1^2/2)) of the 1s target."""
+    return math.sqrt(2.0 * (E + 0.5 * Z1 * Z1))

@@ -1,0 +1,221 @@
+"""GPU parity of the HIP MG-CCCS path against the FP64 CPU oracle.
+
+Every test calls the C ABI through the thin binding and compares element by
+element with the oracle on the same seeded inputs.  Tolerances: FP64 kernels
+1e-12 relative (max-norm over the field) -- a few hundred ulps of rounding-order
+difference; FP32 kernels 2e-5; converged solves 1e-10 relative solution error
+against the oracle's direct solve.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from helpers import Case, rel2, rel_err, to_np
+from oracle.grid import rel_residual, tp_rhs
+
+pytestmark = pytest.mark.gpu
+
+GAM = math.radians(5.0)
+
+SMALL = [
+    Case(32, 10.0, 0.3, 3, 2),
+    Case(64, 20.0, 0.1, 4, 4, pc_gamma=GAM),
+    Case(128, 40.0, 0.1, 5, 4),          # the 129^2 workload grid
+]
+
+
+@pytest.mark.parametrize("c", SMALL, ids=lambda c: f"n{c.n}")
+def test_rhs(c):
+    g = c.grid()
+    chi = to_np(g.build_rhs_tp(g.field()))
+    o = c.oracle()
+    ref = tp_rhs(o.g, c.Z1, c.Z2, c.lam, c.E)
+    assert rel_err(chi, ref) < 1e-14
+
+
+@pytest.mark.parametrize("c", SMALL, ids=lambda c: f"n{c.n}")
+@pytest.mark.parametrize("fp32", [False, True], ids=["fp64", "fp32"])
+def test_residual(c, fp32):
+    g = c.grid()
+    u, f = c.rand(1), c.rand(2)
+    ut, ft, rt = g.from_numpy(u, fp32), g.from_numpy(f, fp32), g.field(fp32)
+    rel = g.residual(ut, ft, rt)
+    o = c.oracle()
+    ref = o.op.residual(u.astype(np.complex64).astype(complex) if fp32 else u,
+                        f.astype(np.complex64).astype(complex) if fp32 else f)
+    tol = 2e-5 if fp32 else 1e-13
+    assert rel_err(to_np(rt), ref) < tol
+    assert abs(rel - np.linalg.norm(ref) / np.linalg.norm(f)) < 1e-5 * rel
+
+
+@pytest.mark.parametrize("c", SMALL + [Case(64, 20.0, 0.5, 4, 4, pc_gamma=GAM, pc_first_level=1)],
+                         ids=lambda c: f"n{c.n}_g{c.pc_gamma:.2f}_f{c.pc_first_level}")
+@pytest.mark.parametrize("fp32", [False, True], ids=["fp64", "fp32"])
+def test_vcycle(c, fp32):
+    g = c.grid()
+    o = c.oracle()
+    chi = tp_rhs(o.g, c.Z1, c.Z2, c.lam, c.E)
+    u = c.u0()
+    ut, ft = g.from_numpy(u, fp32), g.from_numpy(chi, fp32)
+    g.vcycle(ut, ft)
+    ref = o.mg.vcycle(u, chi)
+    assert rel_err(to_np(ut), ref) < (5e-5 if fp32 else 1e-12)
+
+
+@pytest.mark.parametrize("c", SMALL + [Case(64, 20.0, 0.5, 4, 1), Case(64, 20.0, -0.3, 4, 16),
+                                       Case(64, 24.0, 0.7, 4, 5, pc_gamma=GAM)],
+                         ids=lambda c: f"n{c.n}_M{c.M}_g{c.pc_gamma:.2f}")
+@pytest.mark.parametrize("fp32", [False, True], ids=["fp64", "fp32"])
+def test_cccs(c, fp32):
+    g = c.grid()
+    o = c.oracle()
+    chi = tp_rhs(o.g, c.Z1, c.Z2, c.lam, c.E)
+    u = c.u0()
+    ut, ft = g.from_numpy(u, fp32), g.from_numpy(chi, fp32)
+    g.cccs(ut, ft)
+    ref = o.cc.step(u, chi)
+    # compare the correction (u* - u), the part the step computes
+    corr = to_np(ut) - (u.astype(np.complex64).astype(complex) if fp32 else u)
+    assert rel_err(corr, ref - u) < (1e-4 if fp32 else 1e-10)
+
+
+@pytest.mark.parametrize("c", [Case(64, 20.0, -0.4, 4, 4), Case(128, 40.0, 0.1, 5, 4)],
+                         ids=lambda c: f"n{c.n}_E{c.E}")
+def test_stationary_trajectory(c):
+    """K cycles of stationary MG-CCCS from the same seed (exact operator on
+    every level): identical iterates up to rounding, whether or not the
+    iteration contracts for this energy."""
+    from paper_1412_1953_amd import mgcccs
+    K = 3
+    g = c.grid()
+    o = c.oracle()
+    chi = tp_rhs(o.g, c.Z1, c.Z2, c.lam, c.E)
+    u = c.u0()
+    ut, ft = g.from_numpy(u), g.from_numpy(chi)
+    res = g.solve(ut, ft, outer=mgcccs.STATIONARY, max_it=K, tol=1e-300)
+    assert res.iters == K and res.status == mgcccs.MGC_ENOCONV
+    ref = u
+    for _ in range(K):
+        ref = o.cycle(ref, chi)
+    assert rel2(to_np(ut), ref) < 1e-10
+    hist_o = [rel_residual(o.op, u, chi)]
+    assert abs(res.history[0] - hist_o[0]) < 1e-12 * hist_o[0]
+
+
+@pytest.mark.parametrize("c", [Case(64, 20.0, 0.3, 4, 4, pc_gamma=GAM),
+                               Case(128, 40.0, 0.1, 5, 8, pc_gamma=GAM)],
+                         ids=lambda c: f"n{c.n}")
+@pytest.mark.parametrize("fp32", [False, True], ids=["fp64", "fp32"])
+def test_fgmres_trajectory(c, fp32):
+    """The first FGMRES(10) restart cycle from the same seed: same iterate."""
+    from paper_1412_1953_amd import mgcccs
+    g = c.grid()
+    o = c.oracle()
+    chi = tp_rhs(o.g, c.Z1, c.Z2, c.lam, c.E)
+    u = c.u0()
+    ut, ft = g.from_numpy(u), g.from_numpy(chi)
+    res = g.solve(ut, ft, outer=mgcccs.FGMRES, inner=mgcccs.FP32 if fp32 else mgcccs.FP64,
+                  restart=10, max_it=10, tol=1e-300)
+    ref = o.solve_fgmres(u, chi, 1e-300, restart=10, max_it=10)
+    assert res.iters == 10
+    err = rel2(to_np(ut), ref.u)
+    assert err < (1e-4 if fp32 else 1e-10), err
+    assert abs(res.relres - ref.relres) < (1e-3 if fp32 else 1e-8) * ref.relres
+
+
+@pytest.mark.parametrize("c", [Case(64, 20.0, 0.3, 4, 4, pc_gamma=GAM),
+                               Case(128, 40.0, 0.1, 5, 8, pc_gamma=GAM, seed=0)],
+                         ids=lambda c: f"n{c.n}")
+@pytest.mark.parametrize("fp32", [False, True], ids=["fp64", "fp32"])
+def test_fgmres_solution_matches_direct_solve(c, fp32):
+    from paper_1412_1953_amd import mgcccs
+    g = c.grid()
+    o = c.oracle()
+    n = c.n
+    chi = tp_rhs(o.g, c.Z1, c.Z2, c.lam, c.E)
+    ut, ft = g.from_numpy(c.u0()), g.from_numpy(chi)
+    res = g.solve(ut, ft, outer=mgcccs.FGMRES, inner=mgcccs.FP32 if fp32 else mgcccs.FP64,
+                  restart=10, max_it=2000, tol=1e-12)
+    assert res.status == mgcccs.MGC_OK, res
+    assert res.relres <= 1e-12
+    x = spla.spsolve(o.op.sparse(), chi[1:n, 1:n].ravel()).reshape(n - 1, n - 1)
+    err = rel2(to_np(ut)[1:n, 1:n], x)
+    assert err < 1e-10, err
+    # the oracle's own residual of the GPU solution
+    assert rel_residual(o.op, to_np(ut), chi) < 2e-12
+
+
+def test_coarsest_only_grid_is_a_direct_solve():
+    c = Case(8, 4.0, 0.2, 1, 1)
+    g = c.grid()
+    o = c.oracle()
+    chi = tp_rhs(o.g, c.Z1, c.Z2, c.lam, c.E)
+    ut, ft = g.from_numpy(c.u0()), g.from_numpy(chi)
+    g.vcycle(ut, ft)
+    assert rel_residual(o.op, to_np(ut), chi) < 1e-13
+
+
+def test_solves_are_bitwise_reproducible():
+    from paper_1412_1953_amd import mgcccs
+    c = Case(64, 20.0, 0.3, 4, 4, pc_gamma=GAM)
+    g = c.grid()
+    o = c.oracle()
+    chi = tp_rhs(o.g, c.Z1, c.Z2, c.lam, c.E)
+    outs = []
+    for _ in range(2):
+        ut, ft = g.from_numpy(c.u0()), g.from_numpy(chi)
+        g.solve(ut, ft, outer=mgcccs.FGMRES, restart=10, max_it=25, tol=1e-300)
+        outs.append(to_np(ut))
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_error_paths():
+    from paper_1412_1953_amd import mgcccs
+    with pytest.raises(mgcccs.MGCError) as e:
+        mgcccs.Grid(48, 10.0, 7.5, math.pi / 6, 3, 2)          # n not a power of two
+    assert e.value.status == mgcccs.MGC_EINVAL
+    with pytest.raises(mgcccs.MGCError) as e:
+        mgcccs.Grid(64, 10.0, 7.0, math.pi / 6, 3, 2)          # R0 off the coarse grid
+    assert e.value.status == mgcccs.MGC_EINVAL
+    g = mgcccs.Grid(32, 10.0, 7.5, math.pi / 6, 3, 2)
+    u, f = g.field(), g.field()
+    with pytest.raises(mgcccs.MGCError) as e:
+        g.vcycle(u, f)                                          # no set_energy yet
+    assert e.value.status == mgcccs.MGC_ESTATE
+    g.set_potential(1.0, 1.0, 1.0)
+    g.set_energy(0.3)
+    g.build_rhs_tp(f)
+    res = g.solve(u, f, outer=mgcccs.FGMRES, restart=5, max_it=1, tol=1e-12)
+    assert res.status == mgcccs.MGC_ENOCONV and res.iters == 1
+    assert res.relres < res.history[0]                        # a truncated cycle still helps
+    g.set_energy(-0.6)                                          # below the 1s threshold
+    with pytest.raises(mgcccs.MGCError) as e:
+        g.build_rhs_tp(f)
+    assert e.value.status == mgcccs.MGC_EINVAL
+    g.set_energy(0.3)
+    with pytest.raises(mgcccs.MGCError) as e:
+        g.solve(u, f, outer=mgcccs.STATIONARY, max_it=3, tol=1e-8, inner=mgcccs.FP32)
+    assert e.value.status == mgcccs.MGC_EINVAL
+
+
+def test_graph_replays_match_eager_launches(monkeypatch):
+    """The FGMRES restart cycle runs as a captured hipGraph; several replays
+    (with host work and synchronisation between them) must give exactly the
+    iterate of the eagerly launched kernels."""
+    from paper_1412_1953_amd import mgcccs
+    c = Case(64, 20.0, 0.3, 4, 4, pc_gamma=GAM)
+    g = c.grid()
+    o = c.oracle()
+    chi = tp_rhs(o.g, c.Z1, c.Z2, c.lam, c.E)
+    outs = {}
+    for mode in ("eager", "graph"):
+        if mode == "eager":
+            monkeypatch.setenv("MGC_NO_GRAPH", "1")
+        else:
+            monkeypatch.delenv("MGC_NO_GRAPH", raising=False)
+        ut, ft = g.from_numpy(c.u0()), g.from_numpy(chi)
+        g.solve(ut, ft, outer=mgcccs.FGMRES, restart=10, max_it=40, tol=1e-300)
+        outs[mode] = to_np(ut)
+    assert np.array_equal(outs["eager"], outs["graph"])
