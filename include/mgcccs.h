@@ -188,6 +188,23 @@ mgc_status mgc_solve_transpose(mgc_grid g, void* v, const void* gvec,
 mgc_status mgc_cross_section(mgc_grid g, const void* u, const void* chi,
                              double k1, double k2, double zeta[2], double* sigma);
 
+/* Gradient of sigma(k1, k2) with respect to (Z1, Z2, lambda) for u = A^{-1} chi,
+ * chi the Temkin-Poet right-hand side of mgc_build_rhs_tp (call order:
+ * set_potential, set_energy, build_rhs_tp, solve, then this).  The complex
+ * symmetry of Sec. 2.5 gives the adjoint: A^T v = d zeta/du is solved with
+ * mgc_solve_transpose (opts, stats; v: initial guess in, adjoint solution out,
+ * an FP64 level-0 field), then
+ *   d zeta/dp = sum F' (chi - V12 u) + sum F (dchi/dp - dV12/dp u)
+ *             + sum v (dchi/dp - dA/dp u)            (no complex conjugation),
+ *   d sigma/dp = 2 C Re(conj(zeta) d zeta/dp) + |zeta|^2 dC/dp,
+ * C = 8 pi^2 / (k0^2 k1 k2), k0^2 = 2E + Z1^2; F = weighted phi_{k2} x phi_{k1}
+ * with F' from forward-mode differentiation of the test-function recurrence.
+ * Needs Z1 > 0.  Returns MGC_ENOCONV if the adjoint solve did not converge
+ * (dsigma is still filled).  Synchronising.                                   */
+mgc_status mgc_cross_section_grad(mgc_grid g, const void* u, const void* chi, double k1, double k2,
+                                  const mgc_solve_opts* opts, void* v, double dsigma[3],
+                                  double zeta[2], double* sigma, mgc_stats* stats);
+
 mgc_status mgc_destroy_grid(mgc_grid g);
 
 /* Thread-local description of the last error (never NULL).                  */

@@ -76,3 +76,85 @@ def sigma(z: complex, E: float, Z1: float, k1: float, k2: float) -> float:
     """sigma = 8 pi^2 / k0^2 |zeta|^2 / (k1 k2), k0^2 = 2 (E + Z1^2/2)."""
     k0sq = 2.0 * (E + 0.5 * Z1 * Z1)
     return 8.0 * math.pi ** 2 / k0sq * abs(z) ** 2 / (k1 * k2)
+
+
+# ---------------------------------------------------------------------------
+# Objective J(p) = sigma(k1, k2) of u = A(p)^{-1} chi(p), p = (Z1, Z2, lambda),
+# and its gradient (test infrastructure for the adjoint of the HIP library).
+def objective(g: Grid1D, p, E: float, k1: float, k2: float):
+    """J and the pieces it is built from, with an exact sparse direct solve."""
+    import scipy.sparse.linalg as spla
+    from .grid import tp_operator, tp_rhs
+    Z1, Z2, lam = p
+    n = g.n
+    op = tp_operator(g, Z1, Z2, lam, E)
+    chi = tp_rhs(g, Z1, Z2, lam, E)
+    lu = spla.splu(op.sparse())
+    u = np.zeros_like(chi)
+    u[1:n, 1:n] = lu.solve(chi[1:n, 1:n].ravel()).reshape(n - 1, n - 1)
+    z = zeta(g, Z1, lam, u, chi, k1, k2)
+    return sigma(z, E, Z1, k1, k2), dict(op=op, chi=chi, u=u, zeta=z, lu=lu)
+
+
+def grad_central(g: Grid1D, p, E, k1, k2, step=1e-5):
+    """Central differences of J with exact solves."""
+    out = np.zeros(3)
+    for q in range(3):
+        pp, pm = list(p), list(p)
+        pp[q] += step
+        pm[q] -= step
+        out[q] = (objective(g, pp, E, k1, k2)[0] - objective(g, pm, E, k1, k2)[0]) / (2 * step)
+    return out
+
+
+def grad_adjoint(g: Grid1D, p, E, k1, k2, fd_step=1e-6):
+    """dJ/dp through the holomorphic adjoint A^T v = d zeta/du.  The explicit
+    partial derivatives of chi, V12 and the test functions are taken by central
+    differences of their (closed-form) builders, which are cheap and exact to
+    O(fd_step^2)."""
+    import scipy.sparse.linalg as spla
+    from .grid import tp_rhs, tp_two_body
+    Z1, Z2, lam = p
+    n = g.n
+    J, s = objective(g, p, E, k1, k2)
+    u, chi, zt = s["u"], s["chi"], s["zeta"]
+    t = trapezoid_weights(g)
+    top = min(g.j0, n - 1)
+
+    def weights(Z):
+        f1, f2 = np.zeros(n + 1), np.zeros(n + 1)
+        f1[1:top + 1] = t[1:top + 1] * test_function(g, Z, k1)[1:top + 1]
+        f2[1:top + 1] = t[1:top + 1] * test_function(g, Z, k2)[1:top + 1]
+        return np.outer(f2, f1)                          # F[k, j]
+
+    F = weights(Z1)
+    V12 = tp_two_body(g, lam)
+    gu = -F * V12                                        # d zeta / du (holomorphic)
+    AT = s["op"].sparse().T.tocsc()
+    v = np.zeros_like(u)
+    v[1:n, 1:n] = spla.spsolve(AT, gu[1:n, 1:n].ravel()).reshape(n - 1, n - 1)
+    zz = g.z.copy()
+    zz[0] = 1.0
+    inv = 1.0 / zz
+    dA = [np.zeros_like(u) for _ in range(3)]
+    dA[0][1:n, 1:n] = -np.broadcast_to(inv[None, 1:n], (n - 1, n - 1))
+    dA[1][1:n, 1:n] = -np.broadcast_to(inv[1:n, None], (n - 1, n - 1))
+    idx = np.arange(n + 1)
+    dA[2] = np.where((idx[:, None] > 0) & (idx[None, :] > 0) & (idx[:, None] < n) & (idx[None, :] < n),
+                     inv[np.maximum(idx[:, None], idx[None, :])], 0)
+    dJ = np.zeros(3)
+    k0sq = 2 * E + Z1 ** 2
+    C = 8 * np.pi ** 2 / (k0sq * k1 * k2)
+    for q in range(3):
+        pp, pm = list(p), list(p)
+        pp[q] += fd_step
+        pm[q] -= fd_step
+        dchi = (tp_rhs(g, *pp, E) - tp_rhs(g, *pm, E)) / (2 * fd_step)
+        dF = (weights(pp[0]) - weights(pm[0])) / (2 * fd_step) if q == 0 else 0.0
+        dV12 = dA[2] if q == 2 else 0.0
+        explicit = np.sum(dF * (chi - V12 * u)) + np.sum(F * (dchi - dV12 * u))
+        adjoint = np.sum(v * (dchi - dA[q] * u))
+        dz = explicit + adjoint
+        dJ[q] = 2 * C * np.real(np.conj(zt) * dz)
+    dJ[0] += -J * 2 * Z1 / k0sq
+    return dJ, dict(J=J, v=v, zeta=zt)

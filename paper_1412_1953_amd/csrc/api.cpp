@@ -45,8 +45,8 @@ struct SysOff {                            // offsets of one channel system's fa
 struct CcOff {                             // CCCS tables + scratch for one precision
   size_t wphi = 0, phi = 0, wvphi = 0, vphi = 0;
   SysOff A, B;
-  size_t rbuf = 0, rhoA = 0, rhoB = 0, partB = 0, coef = 0, gA = 0, gB = 0, YA = 0, YB = 0,
-         eA = 0, eB = 0;
+  size_t partA = 0, partB = 0, rhoA = 0, rhoB = 0, partC = 0, coef = 0, tickets = 0, gA = 0, gB = 0,
+         YA = 0, YB = 0, HA = 0, HB = 0, eA = 0, eB = 0;
 };
 
 }  // namespace
@@ -80,11 +80,11 @@ struct mgc_grid_s {
   size_t ws_bytes = 0, need = 0;
   size_t exact_tab = 0, exact_tab32 = 0, exact_w = 0, exact_z = 0, coarse_inv = 0, tt = 0;
   CcOff cc[2];
-  size_t part = 0, scal = 0;               // reduction partials, small scalars
+  size_t part = 0, scal = 0, ticket = 0;   // reduction partials, small scalars, last-block ticket
   size_t r64 = 0, f32 = 0, u32 = 0, tw = 0, tz = 0;
   size_t W = 0, Z[2] = {0, 0};
   size_t gm = 0;                           // GmresState arrays
-  size_t zeta_f = 0;
+  size_t zeta_f = 0, adj = 0;
   int nchunksB = 1;
   bool prec_on[2] = {true, false};
 
@@ -159,15 +159,19 @@ void layout(mgc_grid g) {
       };
       sys(c.A, M, g->PA);
       sys(c.B, Lc, g->PB);
-      c.rbuf = take(g->field_bytes(0, p));
+      c.partA = take((size_t)g->nchunksB * (n + 1) * M * e);
+      c.partB = take((size_t)g->nchunksB * (n + 1) * Lc * e);
       c.rhoA = take((size_t)(n + 1) * M * e);
       c.rhoB = take((size_t)(n + 1) * Lc * e);
-      c.partB = take((size_t)g->nchunksB * (n + 1) * Lc * e);
+      c.partC = take((size_t)g->nchunksB * M * Lc * e);
       c.coef = take((size_t)M * Lc * e + e);
+      c.tickets = take(4 * sizeof(unsigned));
       c.gA = take((size_t)N * M * e);
       c.gB = take((size_t)N * Lc * e);
       c.YA = take((size_t)g->PA * 2 * M * e);
       c.YB = take((size_t)g->PB * 2 * Lc * e);
+      c.HA = take((size_t)g->PA * 4 * M * e);
+      c.HB = take((size_t)g->PB * 4 * Lc * e);
       c.eA = take((size_t)(n + 1) * M * e);
       c.eB = take((size_t)(n + 1) * Lc * e);
     }
@@ -177,6 +181,7 @@ void layout(mgc_grid g) {
   const int nb = std::max(launch_stencil_blocks(n), launch_vec_blocks(n));
   g->part = take((size_t)nb * 64 * sizeof(double));
   g->scal = take(256 * sizeof(double));
+  g->ticket = take(256);
   g->r64 = take(g->field_bytes(0, P64));
   g->tw = take(g->field_bytes(0, P64));
   g->tz = take(g->field_bytes(0, P64));
@@ -192,7 +197,8 @@ void layout(mgc_grid g) {
       if (g->prec_on[p]) g->Z[p] = take((size_t)m * g->field_bytes(0, p));
   }
   g->gm = take((size_t)(16 * (m + 2) + 2 * (m + 1) * (m + 1) + 64) * sizeof(double));
-  g->zeta_f = take(2 * (n + 1) * sizeof(double));
+  g->zeta_f = take(4 * (n + 1) * sizeof(double));
+  g->adj = take(g->field_bytes(0, P64));
   g->need = off;
 }
 
@@ -288,15 +294,19 @@ template <typename T> ChanSys<T> sys_of(mgc_grid g, bool A) {
 CccsScratch scratch_of(mgc_grid g, int p) {
   const CcOff& c = g->cc[p];
   CccsScratch w;
-  w.rbuf = g->ws + c.rbuf;
+  w.partA = g->ws + c.partA;
+  w.partB = g->ws + c.partB;
   w.rhoA = g->ws + c.rhoA;
   w.rhoB = g->ws + c.rhoB;
-  w.partB = g->ws + c.partB;
+  w.partC = g->ws + c.partC;
   w.coef = g->ws + c.coef;
+  w.tickets = (unsigned*)(g->ws + c.tickets);
   w.gA = g->ws + c.gA;
   w.gB = g->ws + c.gB;
   w.YA = g->ws + c.YA;
   w.YB = g->ws + c.YB;
+  w.HA = g->ws + c.HA;
+  w.HB = g->ws + c.HB;
   w.eA = g->ws + c.eA;
   w.eB = g->ws + c.eB;
   return w;
@@ -412,12 +422,15 @@ void mgcccs_cycle(mgc_grid g, void* u, const void* f, bool zero_guess, const dou
 }
 
 // relres of (u, f) with the exact operator; r written to r64.  Synchronises.
-mgc_status exact_residual(mgc_grid g, const void* u, const void* f, void* r, double* rr2, double* ff2) {
-  const int nb = launch_stencil_blocks(g->d.n);
+mgc_status exact_residual(mgc_grid g, const void* u, const void* f, void* r, double* rr2, double* ff2,
+                          double* copy_to = nullptr) {
   double* part = g->at<double>(g->part);
   double* out = g->at<double>(g->scal);
-  launch_stencil<double, double, double, double>(g->stream, exact_level(g), u, f, r, 0, part);
-  launch_sum_partials(g->stream, nb, 2, part, out);
+  Finish fin;
+  fin.ticket = g->at<unsigned>(g->ticket);
+  fin.out = out;
+  fin.copy_to = copy_to;
+  launch_stencil<double, double, double, double>(g->stream, exact_level(g), u, f, r, 0, part, fin);
   double h[2];
   HIPCHK(g, hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, g->stream));
   HIPCHK(g, hipStreamSynchronize(g->stream));
@@ -508,17 +521,16 @@ mgc_status solve_fgmres(mgc_grid g, void* u, const void* f, const mgc_solve_opts
   double2* W = g->at<double2>(g->W);
   char* Z = g->ws + g->Z[f32 ? P32 : P64];
   double* part = g->at<double>(g->part);
-  const int nbv = launch_vec_blocks(n);
+  unsigned* ticket = g->at<unsigned>(g->ticket);
   Level<double> EX = exact_level(g);
 
-  // W_0 = f - A u
+  // W_0 = f - A u  (||W_0||^2 lands in gs.nrm2 for the next cycle's start)
   double rr, ff;
-  mgc_status rc = exact_residual(g, u, f, W, &rr, &ff);
+  mgc_status rc = exact_residual(g, u, f, W, &rr, &ff, gs.nrm2);
   if (rc) return rc;
   const double fn = std::sqrt(ff);
   double rel = std::sqrt(rr) / fn;
   record(st, 0, rel);
-  launch_copy_scalar(s, g->at<double>(g->scal), gs.nrm2);
   int it = 0, cycles = 0, rs = 0;
   const bool use_graph = std::getenv("MGC_NO_GRAPH") == nullptr;
   while (rel > o->tol && it < o->max_it && std::isfinite(rel)) {
@@ -540,15 +552,13 @@ mgc_status solve_fgmres(mgc_grid g, void* u, const void* f, const mgc_solve_opts
           mgcccs_cycle<double>(g, Zj, Wj, true, gs.scale + j);
           launch_stencil<double, double, double, double>(st, EX, Zj, nullptr, Wn, 1, nullptr);
         }
-        // classical Gram-Schmidt with one re-orthogonalisation
+        // classical Gram-Schmidt with one re-orthogonalisation; the reductions
+        // and the Hessenberg / Givens updates finish inside the last blocks
         for (int pass = 0; pass < 2; ++pass) {
-          launch_multidot(st, n, pitch, stride64, W, j + 1, Wn, part);
-          launch_sum_partials(st, nbv, 2 * (j + 1), part, gs.dots);
-          launch_gmres_coef(st, gs, j, pass);
-          launch_multiaxpy(st, n, pitch, stride64, W, j + 1, gs.axcoef, Wn, part);
+          launch_multidot(st, n, pitch, stride64, W, j + 1, Wn, part, ticket, gs, j, pass);
+          launch_multiaxpy(st, n, pitch, stride64, W, j + 1, gs.axcoef, Wn, part, ticket, gs, j, m,
+                           o->tol * fn, pass == 1);
         }
-        launch_sum_partials(st, nbv, 1, part, gs.nrm2);
-        launch_gmres_step(st, gs, j, m, o->tol * fn);
       }
       launch_gmres_solve(st, gs, m, mm);
       if (f32) launch_update<float>(st, n, pitch, stridez, Z, mm, gs.upcoef, (double2*)u);
@@ -574,9 +584,8 @@ mgc_status solve_fgmres(mgc_grid g, void* u, const void* f, const mgc_solve_opts
       enqueue_cycle(s);
     }
     ++cycles;
-    rc = exact_residual(g, u, f, W, &rr, &ff);
+    rc = exact_residual(g, u, f, W, &rr, &ff, gs.nrm2);
     if (rc) return rc;
-    launch_copy_scalar(s, g->at<double>(g->scal), gs.nrm2);
     int kused = mm;
     HIPCHK(g, hipMemcpyAsync(&kused, gs.kused, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(g, hipStreamSynchronize(s));
@@ -586,6 +595,56 @@ mgc_status solve_fgmres(mgc_grid g, void* u, const void* f, const mgc_solve_opts
   }
   if (st) { st->iters = it; st->vcycles = it; st->relres = rel; }
   return finish_status(rel, o->tol);
+}
+
+}  // namespace
+
+namespace {
+// ----------------------------------------------------------------------------
+// Test functions of eq. testfunction with forward-mode derivatives in Z1.
+struct Dual {
+  double v, d;
+};
+inline Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}; }
+inline Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.d - b.d}; }
+inline Dual operator*(Dual a, Dual b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+inline Dual operator/(Dual a, Dual b) { return {a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v)}; }
+inline Dual dsqrt(Dual a) {
+  const double s = std::sqrt(a.v);
+  return {s, 0.5 * a.d / s};
+}
+inline Dual cst(double x) { return {x, 0.0}; }
+
+// Regular solution of (-1/2 d2/dx2 - Z1/x - k^2/2) phi = 0 by the 3-point
+// recurrence on the real nodes, scaled to local amplitude 1/sqrt(p) at R0,
+// p = sqrt(k^2 - 2 V1(R0)); out[j] = t_j phi(x_j) with trapezoid weights t
+// (h, h/2 at j0) for 1 <= j <= min(j0, n-1), zero elsewhere; dout = d out / d Z1.
+void test_function(const Axis& ax, double Z1, double k, std::vector<double>& out,
+                   std::vector<double>& dout) {
+  const int n = ax.n, j0 = ax.j0;
+  const double h = ax.h;
+  const Dual z1 = {Z1, 1.0};
+  const int top = std::min(j0 + 1, n);
+  std::vector<Dual> ph(top + 1, cst(0.0));
+  ph[1] = cst(h);
+  for (int j = 1; j < top; ++j) {
+    const Dual V1 = cst(0.0) - z1 / cst(j * h);
+    ph[j + 1] = cst(2.0) * ph[j] - ph[j - 1] + cst(2.0 * h * h) * (V1 - cst(0.5 * k * k)) * ph[j];
+  }
+  const int jr = std::min(j0, top - 1);
+  const Dual p = dsqrt(cst(k * k) - cst(2.0) * (cst(0.0) - z1 / cst(jr * h)));
+  const Dual dphi = (ph[jr + 1] - ph[jr - 1]) / cst(2.0 * h);
+  const Dual q = dphi / p;
+  const Dual amp = dsqrt(ph[jr] * ph[jr] + q * q);
+  const Dual sc = cst(1.0) / (amp * dsqrt(p));
+  out.assign(n + 1, 0.0);
+  dout.assign(n + 1, 0.0);
+  for (int j = 1; j <= std::min(j0, n - 1); ++j) {
+    const double t = (j == j0 ? 0.5 * h : h);
+    const Dual v = ph[j] * sc;
+    out[j] = t * v.v;
+    dout[j] = t * v.d;
+  }
 }
 
 }  // namespace
@@ -982,29 +1041,9 @@ mgc_status mgc_cross_section(mgc_grid g, const void* u, const void* chi, double 
   if (!u || !chi || !zeta || !(k1 > 0) || !(k2 > 0)) return fail(MGC_EINVAL, "bad arguments");
   const Axis& ax = g->exact;
   const int n = ax.n, j0 = ax.j0;
-  const double h = ax.h;
-  // regular solution of (-1/2 d2/dx2 + V1 - k^2/2) phi = 0 by the 3-point
-  // recurrence on the real nodes, scaled to asymptotic amplitude 1/sqrt(k)
-  auto testfn = [&](double k, std::vector<double>& out) {
-    const int top = std::min(j0 + 1, n);
-    std::vector<double> ph(top + 1, 0.0);
-    ph[0] = 0.0;
-    ph[1] = h;
-    for (int j = 1; j < top; ++j) {
-      const double V1 = -g->Z1 / (j * h);
-      ph[j + 1] = 2 * ph[j] - ph[j - 1] + 2 * h * h * (V1 - 0.5 * k * k) * ph[j];
-    }
-    const int jr = std::min(j0, top - 1);
-    const double p = std::sqrt(k * k - 2.0 * (-g->Z1 / (jr * h)));
-    const double dphi = (ph[jr + 1] - ph[jr - 1]) / (2 * h);
-    const double amp = std::sqrt(ph[jr] * ph[jr] + (dphi / p) * (dphi / p));
-    const double sc = 1.0 / (amp * std::sqrt(p));
-    out.assign(2 * (n + 1), 0.0);
-    for (int j = 1; j <= std::min(j0, n - 1); ++j) out[j] = ph[j] * sc * (j == j0 ? 0.5 * h : h);
-  };
-  std::vector<double> f1, f2;
-  testfn(k1, f1);
-  testfn(k2, f2);
+  std::vector<double> f1, f2, d1v, d2v;
+  test_function(ax, g->Z1, k1, f1, d1v);
+  test_function(ax, g->Z1, k2, f2, d2v);
   std::vector<double> both(2 * (n + 1));
   for (int j = 0; j <= n; ++j) { both[j] = f1[j]; both[n + 1 + j] = f2[j]; }
   if ((rc = upload(g, g->zeta_f, both.data(), both.size() * sizeof(double)))) return rc;
@@ -1013,7 +1052,7 @@ mgc_status mgc_cross_section(mgc_grid g, const void* u, const void* chi, double 
   double* out = g->at<double>(g->scal);
   launch_zeta_part(g->stream, n, g->lv[0].pitch, j0, exact_level(g).tm, d1, d1 + (n + 1), (const double2*)u,
                    (const double2*)chi, part);
-  launch_sum_partials(g->stream, VEC_BLOCKS, 2, part, out);
+  launch_sum_partials(g->stream, launch_vec_blocks(n), 2, part, out);
   double hz[2];
   HIPCHK(g, hipMemcpyAsync(hz, out, sizeof(hz), hipMemcpyDeviceToHost, g->stream));
   HIPCHK(g, hipStreamSynchronize(g->stream));
@@ -1022,6 +1061,65 @@ mgc_status mgc_cross_section(mgc_grid g, const void* u, const void* chi, double 
   const double k0sq = 2.0 * (g->E + 0.5 * g->Z1 * g->Z1);
   if (sigma) *sigma = 8.0 * M_PI * M_PI / k0sq * (hz[0] * hz[0] + hz[1] * hz[1]) / (k1 * k2);
   return MGC_OK;
+}
+
+mgc_status mgc_cross_section_grad(mgc_grid g, const void* u, const void* chi, double k1, double k2,
+                                  const mgc_solve_opts* opts, void* v, double dsigma[3], double zeta[2],
+                                  double* sigma, mgc_stats* st) {
+  mgc_status rc = check_ready(g);
+  if (rc) return rc;
+  if (!u || !chi || !v || !dsigma || !(k1 > 0) || !(k2 > 0) || v == u || v == chi)
+    return fail(MGC_EINVAL, "bad arguments");
+  if (!(g->Z1 > 0)) return fail(MGC_EINVAL, "gradient needs Z1 > 0");
+  if ((rc = validate_opts(g, opts))) return rc;
+  const Axis& ax = g->exact;
+  const int n = ax.n, j0 = ax.j0, pitch = g->lv[0].pitch;
+  std::vector<double> f1, f2, d1, d2;
+  test_function(ax, g->Z1, k1, f1, d1);
+  test_function(ax, g->Z1, k2, f2, d2);
+  std::vector<double> all(4 * (n + 1));
+  for (int j = 0; j <= n; ++j) {
+    all[j] = f1[j];
+    all[(n + 1) + j] = f2[j];
+    all[2 * (n + 1) + j] = d1[j];
+    all[3 * (n + 1) + j] = d2[j];
+  }
+  if ((rc = upload(g, g->zeta_f, all.data(), all.size() * sizeof(double)))) return rc;
+  const double* F = g->at<const double>(g->zeta_f);
+  const double2* tm = exact_level(g).tm;
+  double* part = g->at<double>(g->part);
+  double* out = g->at<double>(g->scal);
+  // zeta
+  launch_zeta_part(g->stream, n, pitch, j0, tm, F, F + (n + 1), (const double2*)u, (const double2*)chi, part);
+  launch_sum_partials(g->stream, launch_vec_blocks(n), 2, part, out);
+  double hz[2];
+  HIPCHK(g, hipMemcpyAsync(hz, out, sizeof(hz), hipMemcpyDeviceToHost, g->stream));
+  // adjoint: A^T v = d zeta / du
+  launch_adj_rhs(g->stream, n, pitch, j0, tm, F, F + (n + 1), g->at<double2>(g->adj));
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  rc = mgc_solve_transpose(g, v, g->ws + g->adj, opts, st);
+  if (rc != MGC_OK && rc != MGC_ENOCONV) return rc;
+  const mgc_status solve_rc = rc;
+  launch_sens_part(g->stream, n, pitch, j0, g->at<const double2>(g->exact_z), tm, F, F + (n + 1),
+                   F + 2 * (n + 1), F + 3 * (n + 1), (const double2*)u, (const double2*)v,
+                   (const double2*)chi, g->Z1, g->Z2, g->lam, g->E, part);
+  launch_sum_partials(g->stream, launch_vec_blocks(n), 12, part, out);
+  double s12[12];
+  HIPCHK(g, hipMemcpyAsync(s12, out, sizeof(s12), hipMemcpyDeviceToHost, g->stream));
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  HIPCHK(g, hipGetLastError());
+  const cd zt(hz[0], hz[1]);
+  const double k0sq = 2.0 * g->E + g->Z1 * g->Z1;
+  const double C = 8.0 * M_PI * M_PI / (k0sq * k1 * k2);
+  const double sig = C * std::norm(zt);
+  for (int q = 0; q < 3; ++q) {
+    const cd dz(s12[2 * q] + s12[6 + 2 * q], s12[2 * q + 1] + s12[6 + 2 * q + 1]);
+    dsigma[q] = 2.0 * C * std::real(std::conj(zt) * dz);
+  }
+  dsigma[0] += -sig * 2.0 * g->Z1 / k0sq;   // k0 depends on Z1
+  if (zeta) { zeta[0] = hz[0]; zeta[1] = hz[1]; }
+  if (sigma) *sigma = sig;
+  return solve_rc;
 }
 
 mgc_status mgc_destroy_grid(mgc_grid g) {

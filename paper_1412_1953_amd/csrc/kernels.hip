@@ -71,6 +71,48 @@ __device__ __forceinline__ v2<T> apply_at(const Level<T>& L, const VU* u, int k,
   return acc;
 }
 
+
+// Column-resident 5-point stencil for a thread that walks down one column j:
+// keeps u(k-1, j), u(k, j) in registers (one new load per row) and the x1
+// tables of its column; the x2 tables of the current row are wave-uniform.
+template <typename T, typename VU>
+struct ColumnStencil {
+  const Level<T>& L;
+  const VU* u;
+  int j;
+  v2<T> aj, cj, pxj, um, uc;
+  __device__ ColumnStencil(const Level<T>& L_, const VU* u_, int j_, int k0)
+      : L(L_), u(u_), j(j_) {
+    const bool ok = j > 0 && j < L.n;
+    aj = ok ? L.a[j] : mk<T>(0, 0);
+    cj = ok ? L.c[j] : mk<T>(0, 0);
+    pxj = ok ? L.px[j] : mk<T>(0, 0);
+    um = ldf<T>(u, L.pitch, k0 - 1, j, L.n);
+    uc = ldf<T>(u, L.pitch, k0, j, L.n);
+  }
+  // (A u)(k, j) for k = current row; then advance to row k+1
+  __device__ __forceinline__ v2<T> step(int k) {
+    const int n = L.n, p = L.pitch;
+    const v2<T> up = ldf<T>(u, p, k + 1, j, n);
+    if (j <= 0 || j >= n) {          // column outside the grid: no table access
+      um = uc;
+      uc = up;
+      return mk<T>(0, 0);
+    }
+    const v2<T> uw = ldf<T>(u, p, k, j - 1, n), ue = ldf<T>(u, p, k, j + 1, n);
+    v2<T> d = cadd(cadd(pxj, L.py[k]), L.tm[j > k ? j : k]);
+    d.x -= L.E;
+    v2<T> acc = cmul(d, uc);
+    acc = cfma(acc, aj, uw);
+    acc = cfma(acc, cj, ue);
+    acc = cfma(acc, L.a[k], um);
+    acc = cfma(acc, L.c[k], up);
+    um = uc;
+    uc = up;
+    return acc;
+  }
+};
+
 // Block-level reduction of NV doubles held per thread; thread 0 of the block
 // ends with the totals in out[].  blockDim.x * blockDim.y must be a multiple
 // of 64 and at most 1024.
@@ -96,6 +138,58 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* out) {
   __syncthreads();
 }
 
+// Last-block completion of a two-stage reduction.  Every block has written
+// its partial sums; exactly one block (the last to take a ticket) sees true,
+// after which all partials are visible to it.  That block resets the ticket,
+// so the counter is clean for the next launch or graph replay.  The order of
+// the final summation is fixed (by block index), hence deterministic.
+__device__ __forceinline__ bool last_block(unsigned* ticket) {
+  __shared__ int is_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0 && threadIdx.y == 0) {
+    const unsigned nb = gridDim.x * gridDim.y;
+    const unsigned t = atomicAdd(ticket, 1u);
+    is_last = (t == nb - 1);
+    if (is_last) atomicExch(ticket, 0u);
+  }
+  __syncthreads();
+  if (is_last) __threadfence();
+  return is_last != 0;
+}
+
+// In the last block: out[q] = sum_b part[b*nq + q] (b ascending in slices,
+// slices combined in ascending order).  blockDim = 256 threads, nq <= 256.
+__device__ void finish_sum(const double* part, int nb, int nq, double* out) {
+  __shared__ double red[256];
+  const int t = threadIdx.x + blockDim.x * threadIdx.y;
+  const int ns = 256 / nq;
+  const int q = t % nq, sl = t / nq;
+  double s = 0.0;
+  if (sl < ns) {
+    // plain loads: last_block() ended with an agent-scope fence, so the other
+    // blocks' partials are visible; four independent chains keep loads in flight
+    double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int b = sl;
+    for (; b + 3 * ns < nb; b += 4 * ns) {
+      s += part[(size_t)b * nq + q];
+      s1 += part[(size_t)(b + ns) * nq + q];
+      s2 += part[(size_t)(b + 2 * ns) * nq + q];
+      s3 += part[(size_t)(b + 3 * ns) * nq + q];
+    }
+    for (; b < nb; b += ns) s += part[(size_t)b * nq + q];
+    s = (s + s1) + (s2 + s3);
+  }
+  red[t] = s;
+  __syncthreads();
+  if (t < nq) {
+    double tot = 0.0;
+    for (int w = 0; w < ns; ++w) tot += red[w * nq + t];
+    out[t] = tot;
+  }
+  __syncthreads();
+}
+
 // ----------------------------------------------------------------------------
 // Stencil kernels: block (64, 4), each thread one column and ROWS rows.
 constexpr int SX = 64, SY = 4, ROWS = 4;
@@ -106,16 +200,17 @@ template <typename T, typename TU, typename TF, typename TO>
 __global__ void __launch_bounds__(256) k_stencil(Level<T> L, const v2<TU>* __restrict__ u,
                                                  const v2<TF>* __restrict__ f,
                                                  v2<TO>* __restrict__ out, int mode,
-                                                 double* __restrict__ part) {
+                                                 double* __restrict__ part, Finish fin) {
   const int j = 1 + blockIdx.x * SX + threadIdx.x;
   const int k0 = 1 + (blockIdx.y * SY + threadIdx.y) * ROWS;
   const int n = L.n, p = L.pitch;
   double acc[2] = {0.0, 0.0};
   if (j < n) {
+    ColumnStencil<T, v2<TU>> cs(L, u, j, __builtin_amdgcn_readfirstlane(k0));
     for (int r = 0; r < ROWS; ++r) {
-      const int k = k0 + r;
+      const int k = __builtin_amdgcn_readfirstlane(k0 + r);
       if (k >= n) break;
-      v2<T> Au = apply_at<T>(L, u, k, j);
+      v2<T> Au = cs.step(k);
       v2<T> o;
       if (mode == 0) {
         v2<T> fv = cvt<T>(f[(size_t)k * p + j]);
@@ -135,6 +230,10 @@ __global__ void __launch_bounds__(256) k_stencil(Level<T> L, const v2<TU>* __res
       const int b = blockIdx.x + gridDim.x * blockIdx.y;
       part[2 * b] = tot[0];
       part[2 * b + 1] = tot[1];
+    }
+    if (fin.ticket && last_block(fin.ticket)) {
+      finish_sum(part, gridDim.x * gridDim.y, 2, fin.out);
+      if (fin.copy_to && threadIdx.x == 0 && threadIdx.y == 0) *fin.copy_to = fin.out[0];
     }
   }
 }
@@ -260,12 +359,24 @@ __global__ void __launch_bounds__(256) k_s1_zero(Level<T> L, const v2<T>* __rest
   const int J0 = 1 + blockIdx.x * S1CX, K0 = 1 + blockIdx.y * S1CY;
   const int c0 = 2 * J0 - 2, r0 = 2 * K0 - 2;             // fine origin of the u' tile
   const T sc = fs ? (T)*fs : T(1);
-  for (int idx = tid; idx < S1H * S1W; idx += 256) {
+  constexpr int NL1 = (S1H * S1W + 255) / 256;
+  v2<T> fr[NL1];
+#pragma unroll
+  for (int q = 0; q < NL1; ++q) {          // issue every tile load first
+    const int idx = tid + 256 * q;
+    const int rr = idx / S1W, cc = idx % S1W;
+    const int k = r0 + rr, j = c0 + cc;
+    fr[q] = (idx < S1H * S1W && j > 0 && j < n && k > 0 && k < n) ? f[(size_t)k * p + j] : mk<T>(0, 0);
+  }
+#pragma unroll
+  for (int q = 0; q < NL1; ++q) {
+    const int idx = tid + 256 * q;
+    if (idx >= S1H * S1W) break;
     const int rr = idx / S1W, cc = idx % S1W;
     const int k = r0 + rr, j = c0 + cc;
     v2<T> fv = mk<T>(0, 0), uv = mk<T>(0, 0);
     if (j > 0 && j < n && k > 0 && k < n) {
-      fv = cscale(f[(size_t)k * p + j], sc);
+      fv = cscale(fr[q], sc);
       uv = cscale(cdiv(fv, diag_at(L, k, j)), omega);
     }
     up[rr][cc] = uv;
@@ -317,17 +428,33 @@ __global__ void __launch_bounds__(256) k_s2_zero(Level<T> L, const v2<T>* __rest
   const int tid = threadIdx.x + 64 * threadIdx.y;
   const int j0 = 1 + blockIdx.x * S2TX - 1, k0 = 1 + blockIdx.y * S2TY - 1;   // tile origin (halo)
   const T sc = fs ? (T)*fs : T(1);
-  for (int idx = tid; idx < S2H * S2W; idx += 256) {
+  constexpr int NL2 = (S2H * S2W + 255) / 256;
+  v2<T> fr[NL2], er[NL2];
+#pragma unroll
+  for (int q = 0; q < NL2; ++q) {          // issue every tile load first
+    const int idx = tid + 256 * q;
+    const int rr = idx / S2W, cc = idx % S2W;
+    const int k = k0 + rr, j = j0 + cc;
+    const bool in = idx < S2H * S2W && j > 0 && j < n && k > 0 && k < n;
+    fr[q] = in ? f[(size_t)k * p + j] : mk<T>(0, 0);
+    if (in) {
+      const int Ja = j >> 1, Jb = (j + 1) >> 1, Ka = k >> 1, Kb = (k + 1) >> 1;
+      er[q] = cadd(cadd(ldf<T>(ec, pitch_c, Ka, Ja, nc), ldf<T>(ec, pitch_c, Ka, Jb, nc)),
+                   cadd(ldf<T>(ec, pitch_c, Kb, Ja, nc), ldf<T>(ec, pitch_c, Kb, Jb, nc)));
+    } else {
+      er[q] = mk<T>(0, 0);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NL2; ++q) {
+    const int idx = tid + 256 * q;
+    if (idx >= S2H * S2W) break;
     const int rr = idx / S2W, cc = idx % S2W;
     const int k = k0 + rr, j = j0 + cc;
     v2<T> fv = mk<T>(0, 0), wv = mk<T>(0, 0);
     if (j > 0 && j < n && k > 0 && k < n) {
-      fv = cscale(f[(size_t)k * p + j], sc);
-      wv = cscale(cdiv(fv, diag_at(L, k, j)), omega);
-      const int Ja = j >> 1, Jb = (j + 1) >> 1, Ka = k >> 1, Kb = (k + 1) >> 1;
-      v2<T> s = cadd(cadd(ldf<T>(ec, pitch_c, Ka, Ja, nc), ldf<T>(ec, pitch_c, Ka, Jb, nc)),
-                     cadd(ldf<T>(ec, pitch_c, Kb, Ja, nc), ldf<T>(ec, pitch_c, Kb, Jb, nc)));
-      wv = cadd(wv, cscale(s, T(0.25)));
+      fv = cscale(fr[q], sc);
+      wv = cadd(cscale(cdiv(fv, diag_at(L, k, j)), omega), cscale(er[q], T(0.25)));
     }
     wl[rr][cc] = wv;
     fl[rr][cc] = fv;
@@ -352,237 +479,406 @@ __global__ void __launch_bounds__(256) k_s2_zero(Level<T> L, const v2<T>* __rest
 }
 
 // ----------------------------------------------------------------------------
-// CCCS.  Step 1: residual r = f - A u written to rbuf, together with
-// rho^A[k][i] = sum_j w_j phi_i(j) r[k][j] -- one wave per row k.
+// CCCS.  Step 1: residual r = f - A u and both channel projections on 64x64
+// tiles; r is never stored.
+//   rho^A[k][i] = sum_j w_j phi_i(j) r[k][j]   -> partA[tile_x][k][i]
+//   rho^B[j][l] = sum_k w_k varphi_l(k) r[k][j] -> partB[tile_y][j][l]
+// Thread = one column, 16 rows; the block's 4 waves cover 64 rows.  The row
+// sums use a transposed butterfly: MC values over 64 lanes in
+// (MC - 1) + (6 - log2 MC) shuffle rounds instead of 6 MC.
+constexpr int PT = 64;
+
+template <int MC> constexpr int log2c() { return MC <= 1 ? 0 : 1 + log2c<MC / 2>(); }
+
 template <typename T, int MC>
-__global__ void __launch_bounds__(64) k_cccs_resid_rhoA(Level<T> L, const v2<T>* __restrict__ u,
-                                                        const v2<T>* __restrict__ f,
-                                                        const double* __restrict__ fs,
-                                                        v2<T>* __restrict__ rbuf, ChanTab<T> ch,
-                                                        v2<T>* __restrict__ rhoA) {
-  const int k = 1 + blockIdx.x;
-  const int n = L.n, p = L.pitch, M = ch.M;
-  const T sc = fs ? (T)*fs : T(1);
-  v2<T> acc[MC];
+__device__ __forceinline__ void butterfly_sum(v2<T> (&v)[MC]) {
+  const int lane = threadIdx.x & 63;
+  constexpr int LV = log2c<MC>();
 #pragma unroll
-  for (int i = 0; i < MC; ++i) acc[i] = mk<T>(0, 0);
-  for (int j = 1 + threadIdx.x; j < n; j += 64) {
-    v2<T> r = csub(cscale(f[(size_t)k * p + j], sc), apply_at<T>(L, u, k, j));
-    rbuf[(size_t)k * p + j] = r;
+  for (int lev = 0; lev < LV; ++lev) {
+    const int half = MC >> (lev + 1);
+    const int o = 32 >> lev;
+    const bool up = (lane & o) != 0;
 #pragma unroll
-    for (int i = 0; i < MC; ++i)
-      if (i < M) acc[i] = cfma(acc[i], ch.wphi[(size_t)i * (n + 1) + j], r);
-  }
-#pragma unroll
-  for (int i = 0; i < MC; ++i) {
-    if (i < M) {
-      T x = acc[i].x, y = acc[i].y;
-      for (int m = 32; m >= 1; m >>= 1) { x += shfl_xor_t(x, m); y += shfl_xor_t(y, m); }
-      if (threadIdx.x == 0) rhoA[(size_t)k * M + i] = mk<T>(x, y);
+    for (int i = 0; i < MC / 2; ++i) {
+      if (i < half) {
+        const v2<T> lo = v[i], hi = v[i + half];
+        const T sx = up ? lo.x : hi.x, sy = up ? lo.y : hi.y;
+        const T kx = up ? hi.x : lo.x, ky = up ? hi.y : lo.y;
+        v[i] = mk<T>(kx + shfl_xor_t(sx, o), ky + shfl_xor_t(sy, o));
+      }
     }
   }
-}
-
-// Step 2: column projections rho^B[j][l] = sum_k w_k varphi_l(k) r[k][j],
-// partial over row chunks of CHR rows: partB[chunk][j][l].
-constexpr int CHR = 64;
-template <typename T, int LC>
-__global__ void __launch_bounds__(64) k_cccs_rhoB_part(int n, int pitch, const v2<T>* __restrict__ rbuf,
-                                                       ChanTab<T> ch, v2<T>* __restrict__ partB) {
-  const int j = 1 + blockIdx.x * 64 + threadIdx.x;
-  const int kb = 1 + blockIdx.y * CHR;
-  const int Lc = ch.L;
-  if (j >= n) return;
-  v2<T> acc[LC];
 #pragma unroll
-  for (int l = 0; l < LC; ++l) acc[l] = mk<T>(0, 0);
-  const int ke = min(kb + CHR, n);
-  for (int k = kb; k < ke; ++k) {
-    v2<T> r = rbuf[(size_t)k * pitch + j];
-#pragma unroll
-    for (int l = 0; l < LC; ++l)
-      if (l < Lc) acc[l] = cfma(acc[l], ch.wvphi[(size_t)l * (n + 1) + k], r);
+  for (int lev = LV; lev < 6; ++lev) {
+    const int o = 32 >> lev;
+    v[0].x += shfl_xor_t(v[0].x, o);
+    v[0].y += shfl_xor_t(v[0].y, o);
   }
-  v2<T>* out = partB + ((size_t)blockIdx.y * (n + 1) + j) * Lc;
+}
+template <typename T, int MC>
+__global__ void __launch_bounds__(256) k_cccs_project(Level<T> L, const v2<T>* __restrict__ u,
+                                                      const v2<T>* __restrict__ f,
+                                                      const double* __restrict__ fs, ChanTab<T> ch,
+                                                      v2<T>* __restrict__ partA,
+                                                      v2<T>* __restrict__ partB) {
+  __shared__ v2<T> wv[PT][MC];
+  __shared__ v2<T> red[PT][MC];
+  const int n = L.n, p = L.pitch, M = ch.M, Lc = ch.L;
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + 64 * ty;
+  const int j = 1 + blockIdx.x * PT + tx;
+  const int kb = 1 + blockIdx.y * PT;
+  const T sc = fs ? (T)*fs : T(1);
+  for (int idx = tid; idx < PT * MC; idx += 256) {
+    const int r = idx / MC, l = idx % MC, k = kb + r;
+    wv[r][l] = (l < Lc && k < n) ? ch.wvphi[(size_t)l * (n + 1) + k] : mk<T>(0, 0);
+  }
+  v2<T> wp[MC], accB[MC];
 #pragma unroll
-  for (int l = 0; l < LC; ++l)
-    if (l < Lc) out[l] = acc[l];
+  for (int i = 0; i < MC; ++i) {
+    wp[i] = (i < M && j < n) ? ch.wphi[(size_t)i * (n + 1) + j] : mk<T>(0, 0);
+    accB[i] = mk<T>(0, 0);
+  }
+  __syncthreads();
+  constexpr int SH = 6 - log2c<MC>();
+  const int kw = __builtin_amdgcn_readfirstlane(kb + (PT / 4) * ty);
+  ColumnStencil<T, v2<T>> cs(L, u, j, kw);
+#pragma unroll 4
+  for (int q = 0; q < PT / 4; ++q) {
+    const int k = kw + q;                               // wave-uniform row
+    const int rr = k - kb;
+    if (k >= n) break;
+    v2<T> r = mk<T>(0, 0);
+    const v2<T> Au = cs.step(k);
+    if (j < n) r = csub(cscale(f[(size_t)k * p + j], sc), Au);
+    v2<T> pa[MC];
+#pragma unroll
+    for (int i = 0; i < MC; ++i) {
+      accB[i] = cfma(accB[i], wv[rr][i], r);
+      pa[i] = cmul(wp[i], r);
+    }
+    butterfly_sum<T, MC>(pa);
+    const int idx = tx >> SH;
+    if ((tx & ((1 << SH) - 1)) == 0 && idx < M)
+      partA[((size_t)blockIdx.x * (n + 1) + k) * M + idx] = pa[0];
+  }
+  // rho^B over the block's 64 rows: waves 1..3 hand their sums to wave 0
+  for (int w = 1; w < 4; ++w) {
+    if (ty == w)
+#pragma unroll
+      for (int l = 0; l < MC; ++l) red[tx][l] = accB[l];
+    __syncthreads();
+    if (ty == 0)
+#pragma unroll
+      for (int l = 0; l < MC; ++l) accB[l] = cadd(accB[l], red[tx][l]);
+    __syncthreads();
+  }
+  if (ty == 0 && j < n) {
+#pragma unroll
+    for (int l = 0; l < MC; ++l)
+      if (l < Lc) partB[((size_t)blockIdx.y * (n + 1) + j) * Lc + l] = accB[l];
+  }
 }
 
-// Step 3: rho^B from the partials (fixed order).
+// Step 2: rho^A, rho^B from the tile partials (fixed order) and the coupling
+// coefficients c[i][l] = sum_k w_k varphi_l(k) rho^A[k][i] (eq. coefficients):
+// per-block sums over 64 rows, finished by the last block.
 template <typename T>
-__global__ void k_cccs_rhoB_sum(int n, int nchunks, int Lc, const v2<T>* __restrict__ partB,
-                                v2<T>* __restrict__ rhoB) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;   // (j-1)*Lc + l
-  if (idx >= (n - 1) * Lc) return;
-  const int j = 1 + idx / Lc, l = idx % Lc;
-  v2<T> s = mk<T>(0, 0);
-  for (int c = 0; c < nchunks; ++c) s = cadd(s, partB[((size_t)c * (n + 1) + j) * Lc + l]);
-  rhoB[(size_t)j * Lc + l] = s;
-}
-
-// Step 4: coupling coefficients c[i][l] = sum_k w_k varphi_l(k) rho^A[k][i]
-// (eq. coefficients).  One block; thread per (i, l) pair, then LDS partial
-// reduction over k-slices.
-template <typename T>
-__global__ void __launch_bounds__(256) k_cccs_coef(int n, ChanTab<T> ch, const v2<T>* __restrict__ rhoA,
-                                                   v2<T>* __restrict__ coef) {
-  const int M = ch.M, Lc = ch.L, P = M * Lc;
-  const int nslice = 256 / P;                    // >= 1 because P <= 256
-  const int t = threadIdx.x;
-  const int pair = t % P, slice = t / P;
-  __shared__ double sre[256], sim[256];
-  double xr = 0, xi = 0;
-  if (slice < nslice) {
-    const int i = pair / Lc, l = pair % Lc;
-    for (int k = 1 + slice; k < n; k += nslice) {
-      v2<T> a = ch.wvphi[(size_t)l * (n + 1) + k], b = rhoA[(size_t)k * M + i];
+__global__ void __launch_bounds__(256) k_cccs_reduce(int n, int ntiles, ChanTab<T> ch,
+                                                     const v2<T>* __restrict__ partA,
+                                                     const v2<T>* __restrict__ partB,
+                                                     v2<T>* __restrict__ rhoA, v2<T>* __restrict__ rhoB,
+                                                     v2<T>* __restrict__ partC, unsigned* ticket,
+                                                     v2<T>* __restrict__ coef) {
+  __shared__ v2<T> ra[PT][16];
+  const int M = ch.M, Lc = ch.L, tid = threadIdx.x;
+  const int kb = 1 + blockIdx.x * PT;
+  for (int idx = tid; idx < PT * 16; idx += 256) {
+    const int r = idx / 16, i = idx % 16, k = kb + r;
+    v2<T> sa = mk<T>(0, 0), sb = mk<T>(0, 0);
+    if (k < n) {
+      if (i < M) {
+#pragma unroll 8
+        for (int t = 0; t < ntiles; ++t) sa = cadd(sa, partA[((size_t)t * (n + 1) + k) * M + i]);
+        rhoA[(size_t)k * M + i] = sa;
+      }
+      if (i < Lc) {
+#pragma unroll 8
+        for (int t = 0; t < ntiles; ++t) sb = cadd(sb, partB[((size_t)t * (n + 1) + k) * Lc + i]);
+        rhoB[(size_t)k * Lc + i] = sb;
+      }
+    }
+    ra[r][i] = sa;
+  }
+  __syncthreads();
+  const int P = M * Lc;                      // <= 256 pairs
+  if (tid < P) {
+    const int i = tid / Lc, l = tid % Lc;
+    double xr = 0, xi = 0;
+    const int rmax = min(PT, n - kb);
+#pragma unroll 8
+    for (int r = 0; r < rmax; ++r) {
+      v2<T> a = ch.wvphi[(size_t)l * (n + 1) + kb + r], b = ra[r][i];
       xr += (double)a.x * b.x - (double)a.y * b.y;
       xi += (double)a.x * b.y + (double)a.y * b.x;
     }
+    partC[(size_t)blockIdx.x * P + tid] = mk<T>((T)xr, (T)xi);
   }
-  sre[t] = xr;
-  sim[t] = xi;
-  __syncthreads();
-  if (t < P) {
-    double sr = 0, si = 0;
-    for (int s = 0; s < nslice; ++s) { sr += sre[s * P + t]; si += sim[s * P + t]; }
-    coef[t] = mk<T>((T)sr, (T)si);
-  }
-}
-
-// Wave-level dense mat-vec y = A x for an R x R row-major matrix (R <= 32),
-// x and y in LDS.  g = 64 / next_pow2(R) lanes share a row.
-template <typename T>
-__device__ __forceinline__ void wave_matvec(int R, int gsh, const v2<T>* __restrict__ A,
-                                            const v2<T>* x, v2<T>* y) {
-  const int lane = threadIdx.x & 63;
-  const int g = 1 << gsh;
-  const int i = lane >> gsh, part = lane & (g - 1);
-  T sr = 0, si = 0;
-  if (i < R) {
-    for (int m = part; m < R; m += g) {
-      v2<T> a = A[i * R + m], b = x[m];
-      sr += a.x * b.x - a.y * b.y;
-      si += a.x * b.y + a.y * b.x;
+  if (last_block(ticket)) {
+    if (tid < P) {
+      double xr = 0, xi = 0;
+#pragma unroll 8
+      for (int b = 0; b < (int)gridDim.x; ++b) {
+        const v2<T> c = partC[(size_t)b * P + tid];
+        xr += c.x;
+        xi += c.y;
+      }
+      coef[tid] = mk<T>((T)xr, (T)xi);
     }
   }
-  for (int s = 1; s < g; s <<= 1) { sr += shfl_xor_t(sr, s); si += shfl_xor_t(si, s); }
-  __syncthreads();   // every lane finished reading x (x may alias y's buffer)
-  if (i < R && part == 0) y[i] = mk<T>(sr, si);
-  __syncthreads();
 }
 
-__device__ __forceinline__ int pow2_shift_for(int R) {
+// Wave-level mat-vec for the chains.  Lane = (row i, part): g = 2^gsh lanes
+// share a row, the lane holds the NE matrix entries A[i][part + g e] and the
+// matching vector entries in registers.  A vector y distributed by rows (every
+// lane of row group m holds y[m]) is gathered with one bpermute per entry; no
+// LDS and no barrier are involved.
+template <typename T, int NE>
+__device__ __forceinline__ void load_row(v2<T> (&a)[NE], const v2<T>* A, int R, int gsh) {
+  const int lane = threadIdx.x & 63, g = 1 << gsh, i = lane >> gsh, part = lane & (g - 1);
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    const int m = part + g * e;
+    a[e] = (i < R && m < R) ? A[i * R + m] : mk<T>(0, 0);
+  }
+}
+// x[e] = y[part + g e] (zero beyond R); y[m] lives in lane m << ysh, offset yo
+template <typename T, int NE>
+__device__ __forceinline__ void gather(v2<T> (&x)[NE], v2<T> y, int R, int gsh, int ysh, int lo_m,
+                                       int hi_m) {
+  const int lane = threadIdx.x & 63, g = 1 << gsh, part = lane & (g - 1);
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    const int m = part + g * e;
+    const bool in = m < R && m >= lo_m && m < hi_m;
+    const int src = (in ? m - lo_m : 0) << ysh;
+    const T xr = __shfl(y.x, src, 64), xi = __shfl(y.y, src, 64);
+    x[e] = in ? mk<T>(xr, xi) : mk<T>(0, 0);
+  }
+}
+template <typename T, int NE>
+__device__ __forceinline__ v2<T> rowsum(const v2<T> (&a)[NE], const v2<T> (&x)[NE], int gsh) {
+  T sr = 0, si = 0;
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    sr += a[e].x * x[e].x - a[e].y * x[e].y;
+    si += a[e].x * x[e].y + a[e].y * x[e].x;
+  }
+  for (int s = 1; s < (1 << gsh); s <<= 1) { sr += shfl_xor_t(sr, s); si += shfl_xor_t(si, s); }
+  return mk<T>(sr, si);
+}
+
+__device__ __forceinline__ int lane_shift_for(int R) {
   int r2 = 1;
   while (r2 < R) r2 <<= 1;
-  int g = 64 / r2;
   int s = 0;
-  while ((1 << s) < g) ++s;
-  return s;
+  while ((1 << (s + 1)) * r2 <= 64) ++s;
+  return s;                      // g = 2^s lanes per row, g * r2 <= 64
 }
 
-// Step 5: chunk-local block LU solves of both channel systems.  Block = one
-// wave; blockIdx.x = chunk, blockIdx.y = system (0: A, functions of x2 with
-// x1 channels; 1: B, functions of x1 with x2 channels).  The right-hand sides
-// follow the uniqueness convention (Remark 4):
+constexpr int PD = 4;            // prefetch distance of the chains (steps)
+
+// Step 3: channel right-hand sides, chunk-local block LU solves and, in the
+// last chunk of each system, the interface system.  Block = one wave;
+// blockIdx.x = chunk, blockIdx.y = system (0: A, functions of x2 with the x1
+// channels; 1: B, functions of x1 with the x2 channels).  Right-hand sides
+// (Remark 4 convention):
 //   r^A_i(k) = rho^A_i(k) - sum_{l > i} c_il varphi_l(k)
 //   r^B_l(j) = rho^B_l(j) - sum_{m >= l} c_ml phi_m(j)
-template <typename T>
-__global__ void __launch_bounds__(64) k_cccs_local(ChanSys<T> SA, ChanSys<T> SB, ChanTab<T> ch,
+template <typename T, int NE, int NEI, int MC>
+__global__ void __launch_bounds__(64) k_cccs_chain(ChanSys<T> SA, ChanSys<T> SB, ChanTab<T> ch,
                                                    int n, const v2<T>* __restrict__ rhoA,
                                                    const v2<T>* __restrict__ rhoB,
                                                    const v2<T>* __restrict__ coef,
-                                                   v2<T>* __restrict__ gA, v2<T>* __restrict__ gB) {
+                                                   v2<T>* __restrict__ gA, v2<T>* __restrict__ gB,
+                                                   v2<T>* __restrict__ YA, v2<T>* __restrict__ YB,
+                                                   v2<T>* __restrict__ HA, v2<T>* __restrict__ HB,
+                                                   unsigned* tickets) {
   const bool isA = blockIdx.y == 0;
   const ChanSys<T>& S = isA ? SA : SB;
   const int p = blockIdx.x;
   if (p >= S.P) return;
-  const int M = S.M, MM = M * M, Mo = isA ? ch.L : ch.M;  // Mo: channel count of the other axis
+  const int M = S.M, MM = M * M, Mo = isA ? ch.L : ch.M;
   const int s = S.start[p], e = S.start[p + 1] - 1;
   const int lane = threadIdx.x;
-  const int gsh = pow2_shift_for(M);
-  __shared__ v2<T> xv[32], yv[32];
   v2<T>* g = isA ? gA : gB;
   const v2<T>* rho = isA ? rhoA : rhoB;
-  // forward sweep: Z_t = G_t (rhs_t - lo_t Z_{t-1})
-  for (int t = s; t <= e; ++t) {
-    const int node = t + 1;
-    if (lane < M) {
-      v2<T> v = rho[(size_t)node * M + lane];
-      if (isA) {
-        for (int l = lane + 1; l < Mo; ++l)   // b_il = c_il for l > i
-          v = csub(v, cmul(coef[lane * Mo + l], ch.vphi[(size_t)l * (n + 1) + node]));
+  // (a) right-hand sides of the chunk rows, written into g
+  for (int idx = lane; idx < (e - s + 1) * M; idx += 64) {
+    const int t = s + idx / M, i = idx % M, node = t + 1;
+    v2<T> v = rho[(size_t)node * M + i];
+    v2<T> cf[MC], bs[MC];
+#pragma unroll
+    for (int l = 0; l < MC; ++l) {
+      const bool use = isA ? (l > i && l < Mo) : (l >= i && l < Mo);
+      cf[l] = use ? (isA ? coef[i * Mo + l] : coef[l * M + i]) : mk<T>(0, 0);
+      bs[l] = use ? (isA ? ch.vphi[(size_t)l * (n + 1) + node] : ch.phi[(size_t)l * (n + 1) + node])
+                  : mk<T>(0, 0);
+    }
+#pragma unroll
+    for (int l = 0; l < MC; ++l) v = csub(v, cmul(cf[l], bs[l]));
+    g[(size_t)t * M + i] = v;
+  }
+  __syncthreads();                    // single wave: orders the g writes before the reads below
+  const int gsh = lane_shift_for(M), row = lane >> gsh, part = lane & ((1 << gsh) - 1);
+  const bool owner = (row < M) && part == 0;
+  // (b) forward sweep  Z_t = G_t (r_t - lo_t Z_{t-1})  with a PD-deep prefetch;
+  //     rq holds r_t at the lane's columns
+  v2<T> A[PD][NE], rq[PD][NE], cq[PD];
+  auto load_fwd = [&](int d, int t) {
+    load_row<T, NE>(A[d], S.G + (size_t)t * MM, M, gsh);
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+      const int m = part + (1 << gsh) * q;
+      rq[d][q] = m < M ? g[(size_t)t * M + m] : mk<T>(0, 0);
+    }
+    cq[d] = S.lo[t];
+  };
+#pragma unroll
+  for (int d = 0; d < PD; ++d)
+    if (s + d <= e) load_fwd(d, s + d);
+  v2<T> y = mk<T>(0, 0);
+  for (int t0 = s; t0 <= e; t0 += PD) {
+#pragma unroll
+    for (int d = 0; d < PD; ++d) {
+      const int t = t0 + d;
+      if (t > e) break;
+      v2<T> x[NE];
+      if (t > s) {
+        gather<T, NE>(x, y, M, gsh, gsh, 0, M);
+#pragma unroll
+        for (int q = 0; q < NE; ++q) x[q] = csub(rq[d][q], cmul(cq[d], x[q]));
       } else {
-        for (int m = lane; m < Mo; ++m)       // a_lm = c_ml for l <= m
-          v = csub(v, cmul(coef[m * M + lane], ch.phi[(size_t)m * (n + 1) + node]));
+#pragma unroll
+        for (int q = 0; q < NE; ++q) x[q] = rq[d][q];
       }
-      if (t > s) v = csub(v, cmul(S.lo[t], yv[lane]));
-      xv[lane] = v;
+      y = rowsum<T, NE>(A[d], x, gsh);
+      if (t + PD <= e) load_fwd(d, t + PD);
+      if (owner) g[(size_t)t * M + row] = y;
     }
-    __syncthreads();
-    wave_matvec<T>(M, gsh, S.G + (size_t)t * MM, xv, yv);
-    if (lane < M) g[(size_t)t * M + lane] = yv[lane];
-    __syncthreads();
   }
-  // backward sweep: g_t = Z_t - up_t G_t g_{t+1}
-  for (int t = e - 1; t >= s; --t) {
-    if (lane < M) xv[lane] = yv[lane];
-    __syncthreads();
-    wave_matvec<T>(M, gsh, S.G + (size_t)t * MM, xv, yv);
-    if (lane < M) {
-      v2<T> z = g[(size_t)t * M + lane];
-      v2<T> r = csub(z, cmul(S.up[t], yv[lane]));
-      g[(size_t)t * M + lane] = r;
-      yv[lane] = r;
+  __syncthreads();                    // forward results written by other lanes become visible
+  // (c) backward sweep  g_t = Z_t - up_t G_t g_{t+1};  zq holds Z_t at the lane's row
+  v2<T> zq[PD];
+  auto load_bwd = [&](int d, int t) {
+    load_row<T, NE>(A[d], S.G + (size_t)t * MM, M, gsh);
+    zq[d] = row < M ? g[(size_t)t * M + row] : mk<T>(0, 0);
+    cq[d] = S.up[t];
+  };
+#pragma unroll
+  for (int d = 0; d < PD; ++d)
+    if (e - 1 - d >= s) load_bwd(d, e - 1 - d);
+  const v2<T> gs = y;                 // g at the chunk's last row
+  for (int t0 = e - 1; t0 >= s; t0 -= PD) {
+#pragma unroll
+    for (int d = 0; d < PD; ++d) {
+      const int t = t0 - d;
+      if (t < s) break;
+      v2<T> x[NE];
+      gather<T, NE>(x, y, M, gsh, gsh, 0, M);
+      const v2<T> acc = rowsum<T, NE>(A[d], x, gsh);
+      const v2<T> z = zq[d], cu = cq[d];
+      if (t - PD >= s) load_bwd(d, t - PD);
+      y = csub(z, cmul(cu, acc));
+      if (owner) g[(size_t)t * M + row] = y;
     }
-    __syncthreads();
   }
-}
-
-// Step 6: interface systems (one wave per system), unknowns Y_q = [B_q; T_{q+1}].
-template <typename T>
-__global__ void __launch_bounds__(64) k_cccs_iface(ChanSys<T> SA, ChanSys<T> SB,
-                                                   const v2<T>* __restrict__ gA,
-                                                   const v2<T>* __restrict__ gB,
-                                                   v2<T>* __restrict__ YA, v2<T>* __restrict__ YB) {
-  const bool isA = blockIdx.x == 0;
-  const ChanSys<T>& S = isA ? SA : SB;
-  const v2<T>* g = isA ? gA : gB;
-  v2<T>* Y = isA ? YA : YB;
-  const int M = S.M, R = 2 * M, RR = R * R, Q = S.P - 1;
+  // y = g at the chunk's first row, gs = g at its last row (row-distributed)
+  const int Q = S.P - 1;
   if (Q <= 0) return;
-  const int lane = threadIdx.x;
-  const int gsh = pow2_shift_for(R);
-  __shared__ v2<T> xv[32], yv[32], zp[32];
-  for (int q = 0; q < Q; ++q) {
-    const int e_q = S.start[q + 1] - 1, s_n = S.start[q + 1];
-    if (lane < M) {
-      xv[lane] = g[(size_t)e_q * M + lane];
-      xv[M + lane] = g[(size_t)s_n * M + lane];
-    }
-    __syncthreads();
-    wave_matvec<T>(R, gsh, S.Rinv + (size_t)q * RR, xv, yv);     // Rinv_q rhs_q
-    if (q > 0) {
-      wave_matvec<T>(R, gsh, S.Rlo + (size_t)q * RR, zp, xv);    // Rlo_q Z_{q-1}
-      if (lane < R) yv[lane] = csub(yv[lane], xv[lane]);
-      __syncthreads();
-    }
-    if (lane < R) { Y[(size_t)q * R + lane] = yv[lane]; zp[lane] = yv[lane]; }
-    __syncthreads();
+  const int R = 2 * M, RR = R * R;
+  const int gsi = lane_shift_for(R), rowi = lane >> gsi;
+  const bool own = (rowi < R) && (lane & ((1 << gsi) - 1)) == 0;
+  v2<T>* Y = isA ? YA : YB;
+  v2<T>* H = isA ? HA : HB;           // [Q][2][R]: halves of Rinv_q [g(e_q); g(s_{q+1})]
+  // (d) this chunk's contributions to the interface right-hand sides
+  if (p < Q) {                        // interface p, from the last row: x = [gs; 0]
+    v2<T> a[NEI], x[NEI];
+    load_row<T, NEI>(a, S.Rinv + (size_t)p * RR, R, gsi);
+    gather<T, NEI>(x, gs, R, gsi, gsh, 0, M);
+    const v2<T> acc = rowsum<T, NEI>(a, x, gsi);
+    if (own) H[((size_t)p * 2) * R + rowi] = acc;
   }
-  for (int q = Q - 2; q >= 0; --q) {
-    wave_matvec<T>(R, gsh, S.Rup + (size_t)q * RR, zp, xv);      // Rup_q Y_{q+1}
-    if (lane < R) {
-      v2<T> v = csub(Y[(size_t)q * R + lane], xv[lane]);
-      Y[(size_t)q * R + lane] = v;
-      zp[lane] = v;
+  if (p > 0) {                        // interface p-1, from the first row: x = [0; y]
+    v2<T> a[NEI], x[NEI];
+    load_row<T, NEI>(a, S.Rinv + (size_t)(p - 1) * RR, R, gsi);
+    gather<T, NEI>(x, y, R, gsi, gsh, M, 2 * M);
+    const v2<T> acc = rowsum<T, NEI>(a, x, gsi);
+    if (own) H[((size_t)(p - 1) * 2 + 1) * R + rowi] = acc;
+  }
+  // (e) the last chunk of this system to finish solves the interface system
+  __shared__ int is_last;
+  __threadfence();
+  __syncthreads();
+  if (lane == 0) {
+    const unsigned t = atomicAdd(&tickets[isA ? 0 : 1], 1u);
+    is_last = (t == (unsigned)S.P - 1);
+    if (is_last) atomicExch(&tickets[isA ? 0 : 1], 0u);
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  // forward: Z_q = H_q - Rlo_q Z_{q-1}
+  v2<T> B[PD][NEI], hq[PD];
+  auto load_ifw = [&](int d, int q) {
+    load_row<T, NEI>(B[d], S.Rlo + (size_t)q * RR, R, gsi);
+    hq[d] = rowi < R ? cadd(H[((size_t)q * 2) * R + rowi], H[((size_t)q * 2 + 1) * R + rowi]) : mk<T>(0, 0);
+  };
+#pragma unroll
+  for (int d = 0; d < PD; ++d)
+    if (1 + d < Q) load_ifw(d, 1 + d);
+  v2<T> zz = rowi < R ? cadd(H[rowi], H[R + rowi]) : mk<T>(0, 0);
+  if (own) Y[rowi] = zz;
+  for (int q0 = 1; q0 < Q; q0 += PD) {
+#pragma unroll
+    for (int d = 0; d < PD; ++d) {
+      const int q = q0 + d;
+      if (q >= Q) break;
+      v2<T> x[NEI];
+      gather<T, NEI>(x, zz, R, gsi, gsi, 0, R);
+      const v2<T> acc = rowsum<T, NEI>(B[d], x, gsi);
+      const v2<T> h = hq[d];
+      if (q + PD < Q) load_ifw(d, q + PD);
+      zz = csub(h, acc);
+      if (own) Y[(size_t)q * R + rowi] = zz;
     }
-    __syncthreads();
+  }
+  __syncthreads();                    // forward interface results visible to every lane
+  // backward: Y_q = Z_q - Rup_q Y_{q+1}
+  auto load_ibw = [&](int d, int q) {
+    load_row<T, NEI>(B[d], S.Rup + (size_t)q * RR, R, gsi);
+    hq[d] = rowi < R ? Y[(size_t)q * R + rowi] : mk<T>(0, 0);
+  };
+#pragma unroll
+  for (int d = 0; d < PD; ++d)
+    if (Q - 2 - d >= 0) load_ibw(d, Q - 2 - d);
+  for (int q0 = Q - 2; q0 >= 0; q0 -= PD) {
+#pragma unroll
+    for (int d = 0; d < PD; ++d) {
+      const int q = q0 - d;
+      if (q < 0) break;
+      v2<T> x[NEI];
+      gather<T, NEI>(x, zz, R, gsi, gsi, 0, R);
+      const v2<T> acc = rowsum<T, NEI>(B[d], x, gsi);
+      const v2<T> h = hq[d];
+      if (q - PD >= 0) load_ibw(d, q - PD);
+      zz = csub(h, acc);
+      if (own) Y[(size_t)q * R + rowi] = zz;
+    }
   }
 }
 
-// Step 7: retrieval e_t = g_t - V_t T_{p+1} - W_t B_{p-1}; thread per (t, i).
+// Step 4: retrieval e_t = g_t - V_t T_{p+1} - W_t B_{p-1}; thread per (t, i).
 template <typename T>
 __global__ void __launch_bounds__(256) k_cccs_retrieve(ChanSys<T> SA, ChanSys<T> SB,
                                                        const v2<T>* __restrict__ gA,
@@ -613,7 +909,7 @@ __global__ void __launch_bounds__(256) k_cccs_retrieve(ChanSys<T> SA, ChanSys<T>
   e[(size_t)(t + 1) * M + i] = v;   // node index t+1
 }
 
-// Step 8: expansion u += sum_m eA[k][m] phi_m(j) + sum_l eB[j][l] varphi_l(k)
+// Step 5: expansion u += sum_m eA[k][m] phi_m(j) + sum_l eB[j][l] varphi_l(k)
 template <typename T, int MC>
 __global__ void __launch_bounds__(256) k_cccs_expand(int n, int pitch, v2<T>* __restrict__ u,
                                                      ChanTab<T> ch, const v2<T>* __restrict__ eA,
@@ -629,7 +925,7 @@ __global__ void __launch_bounds__(256) k_cccs_expand(int n, int pitch, v2<T>* __
     eb[m] = (m < Lc) ? eB[(size_t)j * Lc + m] : mk<T>(0, 0);
   }
   for (int r = 0; r < ROWS; ++r) {
-    const int k = k0 + r;
+    const int k = __builtin_amdgcn_readfirstlane(k0 + r);   // wave-uniform row
     if (k >= n) break;
     const size_t idx = (size_t)k * pitch + j;
     v2<T> v = u[idx];
@@ -644,150 +940,22 @@ __global__ void __launch_bounds__(256) k_cccs_expand(int n, int pitch, v2<T>* __
 
 // ----------------------------------------------------------------------------
 // Vector kernels for the FP64 outer loop (grid-stride over interior nodes).
-__device__ __forceinline__ void node_of(long t, int m, int& k, int& j) {
-  k = (int)(t / m) + 1;
-  j = (int)(t % m) + 1;
-}
-
-// part[b][q] = sum conj(W_q) Y over the block's nodes, q < J (J <= 32).
-template <int JMAX>
-__global__ void __launch_bounds__(256) k_multidot(int n, int pitch, size_t stride,
-                                                  const double2* __restrict__ W, int J,
-                                                  const double2* __restrict__ Y,
-                                                  double* __restrict__ part) {
-  const int m = n - 1;
-  const long N = (long)m * m;
-  double acc[2 * JMAX];
-#pragma unroll
-  for (int q = 0; q < 2 * JMAX; ++q) acc[q] = 0;
-  for (long t = blockIdx.x * 256L + threadIdx.x; t < N; t += (long)gridDim.x * 256) {
-    int k, j;
-    node_of(t, m, k, j);
-    const size_t idx = (size_t)k * pitch + j;
-    double2 y = Y[idx];
-#pragma unroll
-    for (int q = 0; q < JMAX; ++q) {
-      if (q < J) {
-        double2 w = W[q * stride + idx];
-        acc[2 * q] += w.x * y.x + w.y * y.y;
-        acc[2 * q + 1] += w.x * y.y - w.y * y.x;
-      }
-    }
-  }
-  double tot[2 * JMAX];
-  block_sum<2 * JMAX>(acc, tot);
-  if (threadIdx.x == 0)
-    for (int q = 0; q < 2 * J; ++q) part[(size_t)blockIdx.x * 2 * J + q] = tot[q];
-}
-
-// Y -= sum_q coef_q W_q  (coef on the device, complex), then per-block
-// partial ||Y||^2 into part[b].
-template <int JMAX>
-__global__ void __launch_bounds__(256) k_multiaxpy(int n, int pitch, size_t stride,
-                                                   const double2* __restrict__ W, int J,
-                                                   const double2* __restrict__ coef,
-                                                   double2* __restrict__ Y,
-                                                   double* __restrict__ part) {
-  const int m = n - 1;
-  const long N = (long)m * m;
-  __shared__ double2 cf[JMAX];
-  if (threadIdx.x < J) cf[threadIdx.x] = coef[threadIdx.x];
-  __syncthreads();
-  double acc[1] = {0};
-  for (long t = blockIdx.x * 256L + threadIdx.x; t < N; t += (long)gridDim.x * 256) {
-    int k, j;
-    node_of(t, m, k, j);
-    const size_t idx = (size_t)k * pitch + j;
-    double2 y = Y[idx];
-#pragma unroll
-    for (int q = 0; q < JMAX; ++q) {
-      if (q < J) {
-        double2 w = W[q * stride + idx], c = cf[q];
-        y.x -= c.x * w.x - c.y * w.y;
-        y.y -= c.x * w.y + c.y * w.x;
-      }
-    }
-    Y[idx] = y;
-    acc[0] += y.x * y.x + y.y * y.y;
-  }
-  double tot[1];
-  block_sum<1>(acc, tot);
-  if (threadIdx.x == 0) part[blockIdx.x] = tot[0];
-}
-
-// u += sum_q coef_q Z_q with Z stored in precision TZ.
-template <typename TZ, int JMAX>
-__global__ void __launch_bounds__(256) k_update(int n, int pitch, size_t stride,
-                                                const v2<TZ>* __restrict__ Z, int J,
-                                                const double2* __restrict__ coef,
-                                                double2* __restrict__ u) {
-  const int m = n - 1;
-  const long N = (long)m * m;
-  __shared__ double2 cf[JMAX];
-  if (threadIdx.x < J) cf[threadIdx.x] = coef[threadIdx.x];
-  __syncthreads();
-  for (long t = blockIdx.x * 256L + threadIdx.x; t < N; t += (long)gridDim.x * 256) {
-    int k, j;
-    node_of(t, m, k, j);
-    const size_t idx = (size_t)k * pitch + j;
-    double2 v = u[idx];
-    for (int q = 0; q < J; ++q) {
-      v2<double> z = cvt<double>(Z[q * stride + idx]);
-      double2 c = cf[q];
-      v.x += c.x * z.x - c.y * z.y;
-      v.y += c.x * z.y + c.y * z.x;
-    }
-    u[idx] = v;
-  }
-}
-
-// out = s * in with precision conversion; s read from the device (nullable = 1).
-template <typename TI, typename TO>
-__global__ void __launch_bounds__(256) k_scale_copy(int n, int pitch_in, int pitch_out,
-                                                    const v2<TI>* __restrict__ in,
-                                                    const double* __restrict__ s,
-                                                    v2<TO>* __restrict__ out) {
-  const int m = n - 1;
-  const long N = (long)m * m;
-  const double sc = s ? *s : 1.0;
-  for (long t = blockIdx.x * 256L + threadIdx.x; t < N; t += (long)gridDim.x * 256) {
-    int k, j;
-    node_of(t, m, k, j);
-    v2<TI> v = in[(size_t)k * pitch_in + j];
-    out[(size_t)k * pitch_out + j] = mk<TO>((TO)(sc * v.x), (TO)(sc * v.y));
-  }
-}
-
-// Weighted copy for the transpose solve: out = w_j w_k in  or in / (w_j w_k).
-__global__ void __launch_bounds__(256) k_weight(int n, int pitch, const double2* __restrict__ w,
-                                                int divide, const double2* __restrict__ in,
-                                                double2* __restrict__ out) {
-  const int m = n - 1;
-  const long N = (long)m * m;
-  for (long t = blockIdx.x * 256L + threadIdx.x; t < N; t += (long)gridDim.x * 256) {
-    int k, j;
-    node_of(t, m, k, j);
-    v2<double> ww = cmul(w[j], w[k]);
-    v2<double> v = in[(size_t)k * pitch + j];
-    out[(size_t)k * pitch + j] = divide ? cdiv(v, ww) : cmul(v, ww);
-  }
-}
-
-// Sum of per-block partials in fixed order: out[q] = sum_b part[b*nq + q].
-__global__ void k_sum_partials(int nb, int nq, const double* __restrict__ part, double* __restrict__ out) {
-  const int q = threadIdx.x;
-  if (q >= nq) return;
-  double s = 0;
-  for (int b = 0; b < nb; ++b) s += part[(size_t)b * nq + q];
-  out[q] = s;
-}
+// Interior-node loop of the vector kernels: 256-thread blocks = 64 columns x
+// 4 row groups; blockIdx.x selects a 64-column tile, blockIdx.y strides the
+// rows.  No integer division; independent rows are unrolled so that their
+// loads are in flight together.
+#define MGC_NODE_LOOP(n, k, j)                                                  \
+  const int j = 1 + (int)blockIdx.x * 64 + ((int)threadIdx.x & 63);             \
+  const int k##_first = 1 + (int)blockIdx.y * 4 + ((int)threadIdx.x >> 6);      \
+  const int k##_step = (int)gridDim.y * 4;                                      \
+  if (j < (n))                                                                  \
+    _Pragma("unroll 4") for (int k = k##_first; k < (n); k += k##_step)
+__device__ __forceinline__ int flat_block() { return blockIdx.x + gridDim.x * blockIdx.y; }
 
 // ----------------------------------------------------------------------------
-// FGMRES bookkeeping on the device (single thread).  State layout in `st`
-// (doubles):  see GmresState in launch.h.
-__global__ void k_gmres_coef(GmresState st, int j, int pass) {
+// FGMRES bookkeeping on the device (run by one thread of the last block).
+__device__ void gmres_coef_dev(const GmresState& st, int j, int pass) {
   // after a multi-dot over W_0..W_j: c_i -> h_i += s_i c_i ; axpy coefficient s_i^2 c_i
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
   for (int i = 0; i <= j; ++i) {
     double s = st.scale[i];
     double cr = st.dots[2 * i], ci = st.dots[2 * i + 1];
@@ -798,9 +966,8 @@ __global__ void k_gmres_coef(GmresState st, int j, int pass) {
   }
 }
 
-__global__ void k_gmres_step(GmresState st, int j, int m, double tol_abs) {
+__device__ void gmres_step_dev(const GmresState& st, int j, int m, double tol_abs) {
   // after the final norm: nrm = sqrt(st.nrm2[0]); column j of H, Givens, residual estimate
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const int R = m + 1;
   double nrm = sqrt(st.nrm2[0]);
   const double sj = 1.0;   // z_j = P(v_j) with the normalised v_j
@@ -842,6 +1009,133 @@ __global__ void k_gmres_step(GmresState st, int j, int m, double tol_abs) {
   if (st.kstar[0] < 0 && (est <= tol_abs || !(nrm > 0))) st.kstar[0] = j + 1;
 }
 
+// part[b][q] = sum conj(W_q) Y over the block's nodes, q < J (J <= 32).
+template <int JMAX>
+__global__ void __launch_bounds__(256) k_multidot(int n, int pitch, size_t stride,
+                                                  const double2* __restrict__ W, int J,
+                                                  const double2* __restrict__ Y,
+                                                  double* __restrict__ part, unsigned* ticket,
+                                                  GmresState st, int jcol, int pass) {
+  double acc[2 * JMAX];
+#pragma unroll
+  for (int q = 0; q < 2 * JMAX; ++q) acc[q] = 0;
+  MGC_NODE_LOOP(n, k, j) {
+    const size_t idx = (size_t)k * pitch + j;
+    double2 y = Y[idx];
+#pragma unroll
+    for (int q = 0; q < JMAX; ++q) {
+      if (q < J) {
+        double2 w = W[q * stride + idx];
+        acc[2 * q] += w.x * y.x + w.y * y.y;
+        acc[2 * q + 1] += w.x * y.y - w.y * y.x;
+      }
+    }
+  }
+  double tot[2 * JMAX];
+  block_sum<2 * JMAX>(acc, tot);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < 2 * JMAX; ++q)
+      if (q < 2 * J) part[(size_t)flat_block() * 2 * J + q] = tot[q];
+  }
+  if (last_block(ticket)) {
+    finish_sum(part, gridDim.x * gridDim.y, 2 * J, st.dots);
+    if (threadIdx.x == 0) gmres_coef_dev(st, jcol, pass);
+  }
+}
+
+// Y -= sum_q coef_q W_q  (coef on the device, complex), then per-block
+// partial ||Y||^2 into part[b].
+template <int JMAX>
+__global__ void __launch_bounds__(256) k_multiaxpy(int n, int pitch, size_t stride,
+                                                   const double2* __restrict__ W, int J,
+                                                   const double2* __restrict__ coef,
+                                                   double2* __restrict__ Y,
+                                                   double* __restrict__ part, unsigned* ticket,
+                                                   GmresState st, int jcol, int mrest, double tol_abs,
+                                                   int final_pass) {
+  __shared__ double2 cf[JMAX];
+  if (threadIdx.x < J) cf[threadIdx.x] = coef[threadIdx.x];
+  __syncthreads();
+  double acc[1] = {0};
+  MGC_NODE_LOOP(n, k, j) {
+    const size_t idx = (size_t)k * pitch + j;
+    double2 y = Y[idx];
+#pragma unroll
+    for (int q = 0; q < JMAX; ++q) {
+      if (q < J) {
+        double2 w = W[q * stride + idx], c = cf[q];
+        y.x -= c.x * w.x - c.y * w.y;
+        y.y -= c.x * w.y + c.y * w.x;
+      }
+    }
+    Y[idx] = y;
+    acc[0] += y.x * y.x + y.y * y.y;
+  }
+  double tot[1];
+  block_sum<1>(acc, tot);
+  if (threadIdx.x == 0) part[flat_block()] = tot[0];
+  if (final_pass && last_block(ticket)) {
+    finish_sum(part, gridDim.x * gridDim.y, 1, st.nrm2);
+    if (threadIdx.x == 0) gmres_step_dev(st, jcol, mrest, tol_abs);
+  }
+}
+
+// u += sum_q coef_q Z_q with Z stored in precision TZ.
+template <typename TZ, int JMAX>
+__global__ void __launch_bounds__(256) k_update(int n, int pitch, size_t stride,
+                                                const v2<TZ>* __restrict__ Z, int J,
+                                                const double2* __restrict__ coef,
+                                                double2* __restrict__ u) {
+  __shared__ double2 cf[JMAX];
+  if (threadIdx.x < J) cf[threadIdx.x] = coef[threadIdx.x];
+  __syncthreads();
+  MGC_NODE_LOOP(n, k, j) {
+    const size_t idx = (size_t)k * pitch + j;
+    double2 v = u[idx];
+    for (int q = 0; q < J; ++q) {
+      v2<double> z = cvt<double>(Z[q * stride + idx]);
+      double2 c = cf[q];
+      v.x += c.x * z.x - c.y * z.y;
+      v.y += c.x * z.y + c.y * z.x;
+    }
+    u[idx] = v;
+  }
+}
+
+// out = s * in with precision conversion; s read from the device (nullable = 1).
+template <typename TI, typename TO>
+__global__ void __launch_bounds__(256) k_scale_copy(int n, int pitch_in, int pitch_out,
+                                                    const v2<TI>* __restrict__ in,
+                                                    const double* __restrict__ s,
+                                                    v2<TO>* __restrict__ out) {
+  const double sc = s ? *s : 1.0;
+  MGC_NODE_LOOP(n, k, j) {
+    v2<TI> v = in[(size_t)k * pitch_in + j];
+    out[(size_t)k * pitch_out + j] = mk<TO>((TO)(sc * v.x), (TO)(sc * v.y));
+  }
+}
+
+// Weighted copy for the transpose solve: out = w_j w_k in  or in / (w_j w_k).
+__global__ void __launch_bounds__(256) k_weight(int n, int pitch, const double2* __restrict__ w,
+                                                int divide, const double2* __restrict__ in,
+                                                double2* __restrict__ out) {
+  MGC_NODE_LOOP(n, k, j) {
+    v2<double> ww = cmul(w[j], w[k]);
+    v2<double> v = in[(size_t)k * pitch + j];
+    out[(size_t)k * pitch + j] = divide ? cdiv(v, ww) : cmul(v, ww);
+  }
+}
+
+// Sum of per-block partials in fixed order: out[q] = sum_b part[b*nq + q].
+__global__ void __launch_bounds__(256) k_sum_partials(int nb, int nq, const double* __restrict__ part,
+                                                      double* __restrict__ out) {
+  finish_sum(part, nb, nq, out);
+}
+
+// ----------------------------------------------------------------------------
+// FGMRES bookkeeping on the device (single thread).  State layout in `st`
+// (doubles):  see GmresState in launch.h.
 __global__ void k_gmres_begin(GmresState st, int m) {
   // start of a restart cycle: beta = sqrt(nrm2), scale_0 = 1/beta, g = (beta, 0, ...)
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -896,12 +1190,8 @@ __global__ void k_fill_zero(size_t n16, double2* p) {
 __global__ void __launch_bounds__(256) k_rhs_tp(int n, int pitch, int j0, const double2* __restrict__ z,
                                                 double Z1, double Z2, double lam, double k0,
                                                 double2* __restrict__ chi) {
-  const int m = n - 1;
-  const long N = (long)m * m;
   const double pref = 2.0 * Z1 * sqrt(Z1);
-  for (long t = blockIdx.x * 256L + threadIdx.x; t < N; t += (long)gridDim.x * 256) {
-    int k, j;
-    node_of(t, m, k, j);
+  MGC_NODE_LOOP(n, k, j) {
     double v = 0.0;
     // chi0(k, j) + chi0(j, k); z is real on nodes <= j0
     if (k <= j0 && j <= j0) {
@@ -922,11 +1212,9 @@ __global__ void __launch_bounds__(256) k_zeta_part(int n, int pitch, int j0, con
                                                    const double2* __restrict__ u,
                                                    const double2* __restrict__ chi,
                                                    double* __restrict__ part) {
-  const long N = (long)j0 * j0;
   double acc[2] = {0, 0};
-  for (long t = blockIdx.x * 256L + threadIdx.x; t < N; t += (long)gridDim.x * 256) {
-    const int k = (int)(t / j0) + 1, j = (int)(t % j0) + 1;
-    if (k >= n || j >= n) continue;
+  MGC_NODE_LOOP(n, k, j) {
+    if (k > j0 || j > j0) continue;
     const size_t idx = (size_t)k * pitch + j;
     v2<double> v12 = tm[j > k ? j : k];
     v2<double> src = csub(chi[idx], cmul(v12, u[idx]));
@@ -936,7 +1224,97 @@ __global__ void __launch_bounds__(256) k_zeta_part(int n, int pitch, int j0, con
   }
   double tot[2];
   block_sum<2>(acc, tot);
-  if (threadIdx.x == 0) { part[2 * blockIdx.x] = tot[0]; part[2 * blockIdx.x + 1] = tot[1]; }
+  if (threadIdx.x == 0) { part[2 * flat_block()] = tot[0]; part[2 * flat_block() + 1] = tot[1]; }
+}
+
+
+// ----------------------------------------------------------------------------
+// Sensitivities of the ionisation amplitude zeta (eq. double-ionization) with
+// respect to p = (Z1, Z2, lambda).  With F = f2[k] f1[j] (trapezoid-weighted
+// test functions on the real region) and u = A^{-1} chi:
+//   d zeta/dp = sum F' (chi - V12 u) + sum F (dchi/dp - dV12/dp u)        (explicit)
+//             + sum v (dchi/dp - dA/dp u),     A^T v = d zeta/du = -F V12  (adjoint)
+// Adjoint right-hand side:
+__global__ void __launch_bounds__(256) k_adj_rhs(int n, int pitch, int j0, const double2* __restrict__ tm,
+                                                 const double* __restrict__ f1,
+                                                 const double* __restrict__ f2,
+                                                 double2* __restrict__ out) {
+  MGC_NODE_LOOP(n, k, j) {
+    v2<double> v = mk<double>(0, 0);
+    if (k <= j0 && j <= j0) {
+      const double w = -f2[k] * f1[j];
+      v2<double> t12 = tm[j > k ? j : k];
+      v = mk<double>(w * t12.x, w * t12.y);
+    }
+    out[(size_t)k * pitch + j] = v;
+  }
+}
+
+struct TPParams { double Z1, Z2, lam, E, k0; };
+
+// analytic d chi / d p at a real-region node (chi as built by k_rhs_tp)
+__device__ __forceinline__ void dchi_dp(const TPParams& P, double xj, double xk, bool jk_max_is_j,
+                                        double out[3]) {
+  const double xm = jk_max_is_j ? xj : xk;
+  const double pref = 2.0 * P.Z1 * sqrt(P.Z1);
+  const double phj = pref * xj * exp(-P.Z1 * xj), phk = pref * xk * exp(-P.Z1 * xk);
+  const double Sj = sin(P.k0 * xj), Sk = sin(P.k0 * xk);
+  const double Cj = cos(P.k0 * xj), Ck = cos(P.k0 * xk);
+  const double a1 = P.lam / xm - P.Z2 / xk, a2 = P.lam / xm - P.Z2 / xj;
+  const double r2 = 0.70710678118654752440;
+  const double dk0 = P.Z1 / P.k0;
+  const double dphj = phj * (1.5 / P.Z1 - xj), dphk = phk * (1.5 / P.Z1 - xk);
+  out[0] = r2 * (a1 * (dphj * Sk + phj * Ck * xk * dk0) + a2 * (dphk * Sj + phk * Cj * xj * dk0));
+  out[1] = r2 * (-phj * Sk / xk - phk * Sj / xj);
+  out[2] = r2 * (phj * Sk + phk * Sj) / xm;
+}
+
+// per-block partials (12 doubles): [explicit dZ1, dZ2, dlam | adjoint dZ1, dZ2, dlam], complex each
+__global__ void __launch_bounds__(256) k_sens_part(int n, int pitch, int j0, const double2* __restrict__ z,
+                                                   const double2* __restrict__ tm, const double* __restrict__ f1,
+                                                   const double* __restrict__ f2, const double* __restrict__ df1,
+                                                   const double* __restrict__ df2, const double2* __restrict__ u,
+                                                   const double2* __restrict__ v, const double2* __restrict__ chi,
+                                                   TPParams P, double* __restrict__ part) {
+  double acc[12];
+#pragma unroll
+  for (int q = 0; q < 12; ++q) acc[q] = 0;
+  MGC_NODE_LOOP(n, k, j) {
+    const size_t idx = (size_t)k * pitch + j;
+    const v2<double> uu = u[idx], vv = v[idx];
+    const int mx = j > k ? j : k;
+    // dA/dp u : (-u/z_j, -u/z_k, u/z_max)
+    const v2<double> ij = cdiv(mk<double>(1, 0), z[j]), ik = cdiv(mk<double>(1, 0), z[k]),
+                     im = cdiv(mk<double>(1, 0), z[mx]);
+    v2<double> dAu[3] = {cmul(mk<double>(-ij.x, -ij.y), uu), cmul(mk<double>(-ik.x, -ik.y), uu), cmul(im, uu)};
+    double dc[3] = {0, 0, 0};
+    const bool real_region = (k <= j0 && j <= j0);
+    if (real_region) dchi_dp(P, z[j].x, z[k].x, j > k, dc);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      // adjoint part: v (dchi - dA u), no conjugation
+      const v2<double> w = mk<double>(dc[q] - dAu[q].x, -dAu[q].y);
+      const v2<double> pr = cmul(vv, w);
+      acc[6 + 2 * q] += pr.x;
+      acc[6 + 2 * q + 1] += pr.y;
+    }
+    if (real_region) {
+      const double F = f2[k] * f1[j];
+      const double dF = df2[k] * f1[j] + f2[k] * df1[j];
+      const v2<double> src = csub(chi[idx], cmul(tm[mx], uu));
+      // Z1: dF src + F dchi/dZ1 ; Z2: F dchi/dZ2 ; lambda: F (dchi/dlam - u/z_max)
+      acc[0] += dF * src.x + F * dc[0];
+      acc[1] += dF * src.y;
+      acc[2] += F * dc[1];
+      acc[4] += F * (dc[2] - dAu[2].x);
+      acc[5] += F * (-dAu[2].y);
+    }
+  }
+  double tot[12];
+  block_sum<12>(acc, tot);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < 12; ++q) part[(size_t)flat_block() * 12 + q] = tot[q];
 }
 
 // ============================================================================
@@ -952,13 +1330,13 @@ int launch_stencil_blocks(int n) { return stencil_blocks(n); }
 
 template <typename T, typename TU, typename TF, typename TO>
 void launch_stencil(hipStream_t s, const Level<T>& L, const void* u, const void* f, void* out,
-                    int mode, double* part) {
+                    int mode, double* part, Finish fin) {
   hipLaunchKernelGGL((k_stencil<T, TU, TF, TO>), stencil_grid(L.n), dim3(SX, SY), 0, s, L,
-                     (const v2<TU>*)u, (const v2<TF>*)f, (v2<TO>*)out, mode, part);
+                     (const v2<TU>*)u, (const v2<TF>*)f, (v2<TO>*)out, mode, part, fin);
 }
-template void launch_stencil<double, double, double, double>(hipStream_t, const Level<double>&, const void*, const void*, void*, int, double*);
-template void launch_stencil<double, float, double, double>(hipStream_t, const Level<double>&, const void*, const void*, void*, int, double*);
-template void launch_stencil<float, float, float, float>(hipStream_t, const Level<float>&, const void*, const void*, void*, int, double*);
+template void launch_stencil<double, double, double, double>(hipStream_t, const Level<double>&, const void*, const void*, void*, int, double*, Finish);
+template void launch_stencil<double, float, double, double>(hipStream_t, const Level<double>&, const void*, const void*, void*, int, double*, Finish);
+template void launch_stencil<float, float, float, float>(hipStream_t, const Level<float>&, const void*, const void*, void*, int, double*, Finish);
 
 template <typename T>
 void launch_jacobi(hipStream_t s, const Level<T>& L, const void* u, const void* f, void* out, double omega) {
@@ -1016,12 +1394,13 @@ template <typename T>
 void launch_cccs(hipStream_t s, const Level<T>& L, void* u, const void* f, const double* fs,
                  const ChanTab<T>& ch, const ChanSys<T>& SA, const ChanSys<T>& SB,
                  const CccsScratch& w) {
-  const int n = L.n, pitch = L.pitch;
+  const int n = L.n;
   const int MC = ch.M > ch.L ? ch.M : ch.L;
-  v2<T>* rbuf = (v2<T>*)w.rbuf;
+  v2<T>* partA = (v2<T>*)w.partA;
+  v2<T>* partB = (v2<T>*)w.partB;
   v2<T>* rhoA = (v2<T>*)w.rhoA;
   v2<T>* rhoB = (v2<T>*)w.rhoB;
-  v2<T>* partB = (v2<T>*)w.partB;
+  v2<T>* partC = (v2<T>*)w.partC;
   v2<T>* coef = (v2<T>*)w.coef;
   v2<T>* gA = (v2<T>*)w.gA;
   v2<T>* gB = (v2<T>*)w.gB;
@@ -1029,27 +1408,29 @@ void launch_cccs(hipStream_t s, const Level<T>& L, void* u, const void* f, const
   v2<T>* YB = (v2<T>*)w.YB;
   v2<T>* eA = (v2<T>*)w.eA;
   v2<T>* eB = (v2<T>*)w.eB;
-#define MGC_CC_DISPATCH(KERNEL, GRID, BLOCK, ...)                                   \
-  if (MC <= 4) hipLaunchKernelGGL((KERNEL<T, 4>), GRID, BLOCK, 0, s, __VA_ARGS__);   \
+  const int nt = (n - 1 + PT - 1) / PT;
+#define MGC_CC_DISPATCH(KERNEL, GRID, BLOCK, ...)                                      \
+  if (MC <= 4) hipLaunchKernelGGL((KERNEL<T, 4>), GRID, BLOCK, 0, s, __VA_ARGS__);      \
   else if (MC <= 8) hipLaunchKernelGGL((KERNEL<T, 8>), GRID, BLOCK, 0, s, __VA_ARGS__); \
   else hipLaunchKernelGGL((KERNEL<T, 16>), GRID, BLOCK, 0, s, __VA_ARGS__);
-  MGC_CC_DISPATCH(k_cccs_resid_rhoA, dim3(n - 1), dim3(64), L, (const v2<T>*)u, (const v2<T>*)f,
-                  fs, rbuf, ch, rhoA);
-  const int nchunks = (n - 1 + CHR - 1) / CHR;
-  MGC_CC_DISPATCH(k_cccs_rhoB_part, dim3((n - 1 + 63) / 64, nchunks), dim3(64), n, pitch,
-                  (const v2<T>*)rbuf, ch, partB);
-  hipLaunchKernelGGL((k_cccs_rhoB_sum<T>), dim3(((n - 1) * ch.L + 255) / 256), dim3(256), 0, s, n,
-                     nchunks, ch.L, (const v2<T>*)partB, rhoB);
-  hipLaunchKernelGGL((k_cccs_coef<T>), dim3(1), dim3(256), 0, s, n, ch, (const v2<T>*)rhoA, coef);
+  MGC_CC_DISPATCH(k_cccs_project, dim3(nt, nt), dim3(64, 4), L, (const v2<T>*)u, (const v2<T>*)f,
+                  fs, ch, partA, partB);
+  hipLaunchKernelGGL((k_cccs_reduce<T>), dim3(nt), dim3(256), 0, s, n, nt, ch, (const v2<T>*)partA,
+                     (const v2<T>*)partB, rhoA, rhoB, partC, w.tickets, coef);
   const int P = SA.P > SB.P ? SA.P : SB.P;
-  hipLaunchKernelGGL((k_cccs_local<T>), dim3(P, 2), dim3(64), 0, s, SA, SB, ch, n,
-                     (const v2<T>*)rhoA, (const v2<T>*)rhoB, (const v2<T>*)coef, gA, gB);
-  hipLaunchKernelGGL((k_cccs_iface<T>), dim3(2), dim3(64), 0, s, SA, SB, (const v2<T>*)gA,
-                     (const v2<T>*)gB, YA, YB);
+  // entries per lane: chains over M x M blocks, interface over 2M x 2M blocks
+#define MGC_CHAIN(NE, NEI, MCC)                                                                 \
+  hipLaunchKernelGGL((k_cccs_chain<T, NE, NEI, MCC>), dim3(P, 2), dim3(64), 0, s, SA, SB, ch, n, \
+                     (const v2<T>*)rhoA, (const v2<T>*)rhoB, (const v2<T>*)coef, gA, gB, YA, YB,    \
+                     (v2<T>*)w.HA, (v2<T>*)w.HB, w.tickets + 1)
+  if (MC <= 4) MGC_CHAIN(1, 2, 4);
+  else if (MC <= 8) MGC_CHAIN(1, 4, 8);
+  else MGC_CHAIN(4, 16, 16);
+#undef MGC_CHAIN
   const int NM = (SA.N * SA.M > SB.N * SB.M) ? SA.N * SA.M : SB.N * SB.M;
   hipLaunchKernelGGL((k_cccs_retrieve<T>), dim3((NM + 255) / 256, 2), dim3(256), 0, s, SA, SB,
                      (const v2<T>*)gA, (const v2<T>*)gB, (const v2<T>*)YA, (const v2<T>*)YB, eA, eB);
-  MGC_CC_DISPATCH(k_cccs_expand, stencil_grid(n), dim3(SX, SY), n, pitch, (v2<T>*)u, ch,
+  MGC_CC_DISPATCH(k_cccs_expand, stencil_grid(n), dim3(SX, SY), n, L.pitch, (v2<T>*)u, ch,
                   (const v2<T>*)eA, (const v2<T>*)eB);
 #undef MGC_CC_DISPATCH
 }
@@ -1060,31 +1441,44 @@ template void launch_cccs<float>(hipStream_t, const Level<float>&, void*, const 
                                  const ChanTab<float>&, const ChanSys<float>&, const ChanSys<float>&,
                                  const CccsScratch&);
 
+static inline dim3 vec_grid(int n) {
+  const int gx = (n - 1 + 63) / 64;
+  int gy = VEC_BLOCKS / gx;
+  const int rows4 = (n - 1 + 3) / 4;
+  if (gy > rows4) gy = rows4;
+  if (gy < 1) gy = 1;
+  return dim3(gx, gy);
+}
 static inline int vec_blocks(int n) {
-  long N = (long)(n - 1) * (n - 1);
-  long b = (N + 255) / 256;
-  return (int)(b < VEC_BLOCKS ? b : VEC_BLOCKS);
+  dim3 g = vec_grid(n);
+  return g.x * g.y;
 }
 int launch_vec_blocks(int n) { return vec_blocks(n); }
 
 void launch_multidot(hipStream_t s, int n, int pitch, size_t stride, const double2* W, int J,
-                     const double2* Y, double* part) {
-  const int nb = vec_blocks(n);
-  if (J <= 8) hipLaunchKernelGGL((k_multidot<8>), dim3(nb), dim3(256), 0, s, n, pitch, stride, W, J, Y, part);
-  else if (J <= 16) hipLaunchKernelGGL((k_multidot<16>), dim3(nb), dim3(256), 0, s, n, pitch, stride, W, J, Y, part);
-  else hipLaunchKernelGGL((k_multidot<32>), dim3(nb), dim3(256), 0, s, n, pitch, stride, W, J, Y, part);
+                     const double2* Y, double* part, unsigned* ticket, const GmresState& st, int j,
+                     int pass) {
+  const dim3 nb = vec_grid(n);
+#define MGC_MD(JM) hipLaunchKernelGGL((k_multidot<JM>), nb, dim3(256), 0, s, n, pitch, stride, W, J, Y, part, ticket, st, j, pass)
+  if (J <= 8) MGC_MD(8);
+  else if (J <= 16) MGC_MD(16);
+  else MGC_MD(32);
+#undef MGC_MD
 }
 void launch_multiaxpy(hipStream_t s, int n, int pitch, size_t stride, const double2* W, int J,
-                      const double2* coef, double2* Y, double* part) {
-  const int nb = vec_blocks(n);
-  if (J <= 8) hipLaunchKernelGGL((k_multiaxpy<8>), dim3(nb), dim3(256), 0, s, n, pitch, stride, W, J, coef, Y, part);
-  else if (J <= 16) hipLaunchKernelGGL((k_multiaxpy<16>), dim3(nb), dim3(256), 0, s, n, pitch, stride, W, J, coef, Y, part);
-  else hipLaunchKernelGGL((k_multiaxpy<32>), dim3(nb), dim3(256), 0, s, n, pitch, stride, W, J, coef, Y, part);
+                      const double2* coef, double2* Y, double* part, unsigned* ticket,
+                      const GmresState& st, int j, int m, double tol_abs, int final_pass) {
+  const dim3 nb = vec_grid(n);
+#define MGC_MA(JM) hipLaunchKernelGGL((k_multiaxpy<JM>), nb, dim3(256), 0, s, n, pitch, stride, W, J, coef, Y, part, ticket, st, j, m, tol_abs, final_pass)
+  if (J <= 8) MGC_MA(8);
+  else if (J <= 16) MGC_MA(16);
+  else MGC_MA(32);
+#undef MGC_MA
 }
 template <typename TZ>
 void launch_update(hipStream_t s, int n, int pitch, size_t stride, const void* Z, int J,
                    const double2* coef, double2* u) {
-  hipLaunchKernelGGL((k_update<TZ, 32>), dim3(vec_blocks(n)), dim3(256), 0, s, n, pitch, stride,
+  hipLaunchKernelGGL((k_update<TZ, 32>), vec_grid(n), dim3(256), 0, s, n, pitch, stride,
                      (const v2<TZ>*)Z, J, coef, u);
 }
 template void launch_update<double>(hipStream_t, int, int, size_t, const void*, int, const double2*, double2*);
@@ -1093,7 +1487,7 @@ template void launch_update<float>(hipStream_t, int, int, size_t, const void*, i
 template <typename TI, typename TO>
 void launch_scale_copy(hipStream_t s, int n, int pitch_in, int pitch_out, const void* in,
                        const double* sc, void* out) {
-  hipLaunchKernelGGL((k_scale_copy<TI, TO>), dim3(vec_blocks(n)), dim3(256), 0, s, n, pitch_in,
+  hipLaunchKernelGGL((k_scale_copy<TI, TO>), vec_grid(n), dim3(256), 0, s, n, pitch_in,
                      pitch_out, (const v2<TI>*)in, sc, (v2<TO>*)out);
 }
 template void launch_scale_copy<double, double>(hipStream_t, int, int, int, const void*, const double*, void*);
@@ -1103,16 +1497,10 @@ template void launch_scale_copy<float, float>(hipStream_t, int, int, int, const 
 
 void launch_weight(hipStream_t s, int n, int pitch, const double2* w, int divide, const double2* in,
                    double2* out) {
-  hipLaunchKernelGGL(k_weight, dim3(vec_blocks(n)), dim3(256), 0, s, n, pitch, w, divide, in, out);
+  hipLaunchKernelGGL(k_weight, vec_grid(n), dim3(256), 0, s, n, pitch, w, divide, in, out);
 }
 void launch_sum_partials(hipStream_t s, int nb, int nq, const double* part, double* out) {
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, nb, nq, part, out);
-}
-void launch_gmres_coef(hipStream_t s, const GmresState& st, int j, int pass) {
-  hipLaunchKernelGGL(k_gmres_coef, dim3(1), dim3(1), 0, s, st, j, pass);
-}
-void launch_gmres_step(hipStream_t s, const GmresState& st, int j, int m, double tol_abs) {
-  hipLaunchKernelGGL(k_gmres_step, dim3(1), dim3(1), 0, s, st, j, m, tol_abs);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, nb, nq, part, out);
 }
 void launch_gmres_begin(hipStream_t s, const GmresState& st, int m) {
   hipLaunchKernelGGL(k_gmres_begin, dim3(1), dim3(1), 0, s, st, m);
@@ -1131,11 +1519,23 @@ void launch_fill_zero(hipStream_t s, void* p, size_t bytes) {
 }
 void launch_rhs_tp(hipStream_t s, int n, int pitch, int j0, const double2* z, double Z1, double Z2,
                    double lam, double k0, double2* chi) {
-  hipLaunchKernelGGL(k_rhs_tp, dim3(vec_blocks(n)), dim3(256), 0, s, n, pitch, j0, z, Z1, Z2, lam, k0, chi);
+  hipLaunchKernelGGL(k_rhs_tp, vec_grid(n), dim3(256), 0, s, n, pitch, j0, z, Z1, Z2, lam, k0, chi);
+}
+void launch_adj_rhs(hipStream_t s, int n, int pitch, int j0, const double2* tm, const double* f1,
+                    const double* f2, double2* out) {
+  hipLaunchKernelGGL(k_adj_rhs, vec_grid(n), dim3(256), 0, s, n, pitch, j0, tm, f1, f2, out);
+}
+void launch_sens_part(hipStream_t s, int n, int pitch, int j0, const double2* z, const double2* tm,
+                      const double* f1, const double* f2, const double* df1, const double* df2,
+                      const double2* u, const double2* v, const double2* chi, double Z1, double Z2,
+                      double lam, double E, double* part) {
+  TPParams P{Z1, Z2, lam, E, sqrt(2.0 * E + Z1 * Z1)};
+  hipLaunchKernelGGL(k_sens_part, vec_grid(n), dim3(256), 0, s, n, pitch, j0, z, tm, f1, f2, df1, df2,
+                     u, v, chi, P, part);
 }
 void launch_zeta_part(hipStream_t s, int n, int pitch, int j0, const double2* tm, const double* f1,
                       const double* f2, const double2* u, const double2* chi, double* part) {
-  hipLaunchKernelGGL(k_zeta_part, dim3(VEC_BLOCKS), dim3(256), 0, s, n, pitch, j0, tm, f1, f2, u, chi, part);
+  hipLaunchKernelGGL(k_zeta_part, vec_grid(n), dim3(256), 0, s, n, pitch, j0, tm, f1, f2, u, chi, part);
 }
 
 }  // namespace mgc

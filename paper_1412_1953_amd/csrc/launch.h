@@ -7,19 +7,31 @@
 namespace mgc {
 
 // Grid size of the grid-stride vector kernels (dots, axpys, copies).
-constexpr int VEC_BLOCKS = 1024;
+constexpr int VEC_BLOCKS = 512;
+
+// Optional in-kernel completion of a stencil partial-sum reduction: the last
+// block sums the partials into out[0..1] and optionally copies out[0].
+struct Finish {
+  unsigned* ticket = nullptr;
+  double* out = nullptr;
+  double* copy_to = nullptr;
+};
 
 // Scratch of one CCCS application (device pointers, precision-agnostic).
 struct CccsScratch {
-  void* rbuf;    // level-0 field: residual
+  void* partA;   // [tiles][n+1][M]  row-projection partials
+  void* partB;   // [tiles][n+1][L]  column-projection partials
   void* rhoA;    // [n+1][M]
   void* rhoB;    // [n+1][L]
-  void* partB;   // [nchunks][n+1][L]
+  void* partC;   // [tiles][M][L]    coupling-coefficient partials
   void* coef;    // [M][L]
+  unsigned* tickets;   // [3] last-block tickets (reduce, chain A, chain B)
   void* gA;      // [N][M]   local solutions
   void* gB;      // [N][L]
   void* YA;      // [P-1][2M] interface solution
   void* YB;      // [P-1][2L]
+  void* HA;      // [P-1][2][2M] halves of the interface right-hand sides
+  void* HB;      // [P-1][2][2L]
   void* eA;      // [n+1][M] channel corrections
   void* eB;      // [n+1][L]
 };
@@ -48,7 +60,7 @@ int launch_vec_blocks(int n);
 
 template <typename T, typename TU, typename TF, typename TO>
 void launch_stencil(hipStream_t s, const Level<T>& L, const void* u, const void* f, void* out,
-                    int mode, double* part);
+                    int mode, double* part, Finish fin = Finish());
 template <typename T>
 void launch_jacobi(hipStream_t s, const Level<T>& L, const void* u, const void* f, void* out, double omega);
 template <typename T>
@@ -70,10 +82,16 @@ void launch_cccs(hipStream_t s, const Level<T>& L, void* u, const void* f, const
                  const ChanTab<T>& ch, const ChanSys<T>& SA, const ChanSys<T>& SB,
                  const CccsScratch& w);
 
+// multi-dot over W_0..W_{J-1}; the last block finishes the sums into st.dots
+// and updates the Hessenberg column j (CGS pass `pass`).
 void launch_multidot(hipStream_t s, int n, int pitch, size_t stride, const double2* W, int J,
-                     const double2* Y, double* part);
+                     const double2* Y, double* part, unsigned* ticket, const GmresState& st, int j,
+                     int pass);
+// Y -= sum coef_q W_q; with final_pass the last block finishes ||Y||^2 and
+// performs the Givens step of column j.
 void launch_multiaxpy(hipStream_t s, int n, int pitch, size_t stride, const double2* W, int J,
-                      const double2* coef, double2* Y, double* part);
+                      const double2* coef, double2* Y, double* part, unsigned* ticket,
+                      const GmresState& st, int j, int m, double tol_abs, int final_pass);
 template <typename TZ>
 void launch_update(hipStream_t s, int n, int pitch, size_t stride, const void* Z, int J,
                    const double2* coef, double2* u);
@@ -83,8 +101,6 @@ void launch_scale_copy(hipStream_t s, int n, int pitch_in, int pitch_out, const 
 void launch_weight(hipStream_t s, int n, int pitch, const double2* w, int divide, const double2* in,
                    double2* out);
 void launch_sum_partials(hipStream_t s, int nb, int nq, const double* part, double* out);
-void launch_gmres_coef(hipStream_t s, const GmresState& st, int j, int pass);
-void launch_gmres_step(hipStream_t s, const GmresState& st, int j, int m, double tol_abs);
 void launch_gmres_begin(hipStream_t s, const GmresState& st, int m);
 void launch_gmres_solve(hipStream_t s, const GmresState& st, int m, int mm);
 void launch_ir_scale(hipStream_t s, const double* nrm2, double Nn, double* sc);
@@ -92,6 +108,13 @@ void launch_copy_scalar(hipStream_t s, const double* src, double* dst);
 void launch_fill_zero(hipStream_t s, void* p, size_t bytes);   // bytes: multiple of 16
 void launch_rhs_tp(hipStream_t s, int n, int pitch, int j0, const double2* z, double Z1, double Z2,
                    double lam, double k0, double2* chi);
+void launch_adj_rhs(hipStream_t s, int n, int pitch, int j0, const double2* tm, const double* f1,
+                    const double* f2, double2* out);
+// VEC_BLOCKS x 12 partials: explicit and adjoint parts of d zeta / d(Z1, Z2, lambda)
+void launch_sens_part(hipStream_t s, int n, int pitch, int j0, const double2* z, const double2* tm,
+                      const double* f1, const double* f2, const double* df1, const double* df2,
+                      const double2* u, const double2* v, const double2* chi, double Z1, double Z2,
+                      double lam, double E, double* part);
 void launch_zeta_part(hipStream_t s, int n, int pitch, int j0, const double2* tm, const double* f1,
                       const double* f2, const double2* u, const double2* chi, double* part);
 

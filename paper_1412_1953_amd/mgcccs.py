@@ -23,8 +23,8 @@ STATIONARY, IR, FGMRES = 0, 1, 2
 
 EXPORTED = ["mgc_create_grid", "mgc_workspace_bytes", "mgc_bind_workspace", "mgc_field_pitch",
             "mgc_set_potential", "mgc_set_energy", "mgc_build_rhs_tp", "mgc_residual", "mgc_vcycle",
-            "mgc_cccs", "mgc_solve", "mgc_solve_transpose", "mgc_cross_section", "mgc_destroy_grid",
-            "mgc_last_error"]
+            "mgc_cccs", "mgc_solve", "mgc_solve_transpose", "mgc_cross_section",
+            "mgc_cross_section_grad", "mgc_destroy_grid", "mgc_last_error"]
 
 
 class GridDesc(ctypes.Structure):
@@ -73,6 +73,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mgc_solve": [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(Stats)],
         "mgc_solve_transpose": [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(Stats)],
         "mgc_cross_section": [vp, vp, vp, d, d, ctypes.POINTER(d), ctypes.POINTER(d)],
+        "mgc_cross_section_grad": [vp, vp, vp, d, d, ctypes.POINTER(SolveOpts), vp,
+                                   ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(d),
+                                   ctypes.POINTER(Stats)],
         "mgc_destroy_grid": [vp],
     }
     for name, args in sig.items():
@@ -210,6 +213,25 @@ class Grid:
                         inner_cycles=2, tol=1e-10, hist_cap=4096):
         return self._solve(self.lib.mgc_solve_transpose, v, g, outer, inner, restart, max_it,
                            inner_cycles, tol, hist_cap)
+
+    def cross_section_grad(self, u, chi, k1, k2, v, outer=FGMRES, inner=FP64, restart=10,
+                           max_it=5000, tol=1e-13, hist_cap=4096):
+        """(d sigma / d(Z1, Z2, lambda), zeta, sigma, adjoint SolveResult); v holds
+        the adjoint initial guess on entry and the adjoint solution on exit."""
+        opts = SolveOpts(outer, inner, restart, max_it, 2, tol)
+        hist = (ctypes.c_double * hist_cap)()
+        st = Stats(0, 0, 0.0, ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)), hist_cap, 0,
+                   0.0, 0.0)
+        ds = (ctypes.c_double * 3)()
+        z = (ctypes.c_double * 2)()
+        sig = ctypes.c_double()
+        rc = _check(self.lib.mgc_cross_section_grad(self.h, self._ptr(u), self._ptr(chi), k1, k2,
+                                                    ctypes.byref(opts), self._ptr(v), ds, z,
+                                                    ctypes.byref(sig), ctypes.byref(st)),
+                    allow=(MGC_ENOCONV,))
+        res = SolveResult(rc, st.iters, st.vcycles, st.relres,
+                          [hist[i] for i in range(st.hist_len)], st.t_setup_ms, st.t_solve_ms)
+        return [ds[0], ds[1], ds[2]], complex(z[0], z[1]), sig.value, res
 
     def cross_section(self, u, chi, k1, k2):
         z = (ctypes.c_double * 2)()

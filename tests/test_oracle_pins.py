@@ -354,3 +354,16 @@ def test_zeta_is_affine_in_u():
     u1, u2 = rng_field(64, 12), rng_field(64, 13)
     z = lambda u: fn.zeta(g, 1.0, 1.0, u, chi, 0.7, 0.7)
     assert abs(z(u1 + 2 * u2) - (z(u1) + 2 * z(u2) - 2 * z(0 * u1))) < 1e-12 * abs(z(u1))
+
+
+# ---------------------------------------------------------------- P14 (adjoint)
+@pytest.mark.parametrize("p", [(1.0, 1.0, 1.0), (1.1, 0.9, 1.3)])
+def test_adjoint_gradient_matches_central_differences(p):
+    """Holomorphic adjoint (complex symmetry, Sec. 2.5) for d sigma/d(Z1, Z2, lambda)
+    against central differences (step 1e-5) of exact direct solves."""
+    g = Grid1D(64, 20.0, 15.0, math.pi / 6)
+    E = 0.5
+    k = math.sqrt(E)
+    a, _ = fn.grad_adjoint(g, p, E, k, k)
+    c = fn.grad_central(g, p, E, k, k)
+    assert np.all(np.abs(a - c) <= 1e-6 * np.abs(c))
