@@ -511,19 +511,68 @@ mgc_status solve_ir(mgc_grid g, void* u, const void* f, const mgc_solve_opts* o,
 }
 
 // ---- FGMRES -------------------------------------------------------------------
-mgc_status solve_fgmres(mgc_grid g, void* u, const void* f, const mgc_solve_opts* o, mgc_stats* st) {
+// One FGMRES restart cycle of mm <= m steps enqueued on stream st: Arnoldi
+// with the MG-CCCS preconditioner, device-side Givens bookkeeping, the small
+// least-squares solve and the update of u.  No host synchronisation.
+void enqueue_fgmres_cycle(mgc_grid g, void* u, const mgc_solve_opts* o, double tol_abs, int mm,
+                          hipStream_t st) {
   const int n = g->d.n, pitch = g->lv[0].pitch, m = o->restart;
   const bool f32 = o->inner == MGC_FP32;
   const size_t fb = g->field_bytes(0, P64), fbz = g->field_bytes(0, f32 ? P32 : P64);
   const size_t stride64 = fb / 16, stridez = fbz / (f32 ? 8 : 16);
-  hipStream_t s = g->stream;
   GmresState gs = gmres_state(g);
   double2* W = g->at<double2>(g->W);
   char* Z = g->ws + g->Z[f32 ? P32 : P64];
   double* part = g->at<double>(g->part);
   unsigned* ticket = g->at<unsigned>(g->ticket);
   Level<double> EX = exact_level(g);
+  hipStream_t saved = g->stream;
+  g->stream = st;                           // the cycle drivers launch on g->stream
+  launch_gmres_begin(st, gs, m);
+  for (int j = 0; j < mm; ++j) {
+    double2* Wj = W + (size_t)j * stride64;
+    double2* Wn = W + (size_t)(j + 1) * stride64;
+    char* Zj = Z + (size_t)j * fbz;
+    // preconditioner on the normalised basis vector v_j = s_j W_j
+    if (f32) {
+      launch_scale_copy<double, float>(st, n, pitch, pitch, Wj, gs.scale + j, g->ws + g->f32);
+      mgcccs_cycle<float>(g, Zj, g->ws + g->f32, true);
+      launch_stencil<double, float, double, double>(st, EX, Zj, nullptr, Wn, 1, nullptr);
+    } else {
+      mgcccs_cycle<double>(g, Zj, Wj, true, gs.scale + j);
+      launch_stencil<double, double, double, double>(st, EX, Zj, nullptr, Wn, 1, nullptr);
+    }
+    // classical Gram-Schmidt with one re-orthogonalisation; the reductions
+    // and the Hessenberg / Givens updates finish inside the last blocks
+    for (int pass = 0; pass < 2; ++pass) {
+      launch_multidot(st, n, pitch, stride64, W, j + 1, Wn, part, ticket, gs, j, pass);
+      launch_multiaxpy(st, n, pitch, stride64, W, j + 1, gs.axcoef, Wn, part, ticket, gs, j, m, tol_abs,
+                       pass == 1);
+    }
+  }
+  launch_gmres_solve(st, gs, m, mm);
+  if (f32) launch_update<float>(st, n, pitch, stridez, Z, mm, gs.upcoef, (double2*)u);
+  else launch_update<double>(st, n, pitch, stridez, Z, mm, gs.upcoef, (double2*)u);
+  g->stream = saved;
+}
 
+// True residual W_0 = f - A u with ||W_0||^2, ||f||^2 finished in-kernel into
+// scal[0..1] and ||W_0||^2 copied to the Krylov state (next cycle's start).
+void enqueue_true_residual(mgc_grid g, const void* u, const void* f, hipStream_t st) {
+  GmresState gs = gmres_state(g);
+  Finish fin;
+  fin.ticket = g->at<unsigned>(g->ticket);
+  fin.out = g->at<double>(g->scal);
+  fin.copy_to = gs.nrm2;
+  launch_stencil<double, double, double, double>(st, exact_level(g), u, f, g->at<double2>(g->W), 0,
+                                                 g->at<double>(g->part), fin);
+}
+
+mgc_status solve_fgmres(mgc_grid g, void* u, const void* f, const mgc_solve_opts* o, mgc_stats* st) {
+  const int m = o->restart;
+  hipStream_t s = g->stream;
+  GmresState gs = gmres_state(g);
+  double2* W = g->at<double2>(g->W);
   // W_0 = f - A u  (||W_0||^2 lands in gs.nrm2 for the next cycle's start)
   double rr, ff;
   mgc_status rc = exact_residual(g, u, f, W, &rr, &ff, gs.nrm2);
@@ -531,40 +580,10 @@ mgc_status solve_fgmres(mgc_grid g, void* u, const void* f, const mgc_solve_opts
   const double fn = std::sqrt(ff);
   double rel = std::sqrt(rr) / fn;
   record(st, 0, rel);
-  int it = 0, cycles = 0, rs = 0;
+  int it = 0, rs = 0;
   const bool use_graph = std::getenv("MGC_NO_GRAPH") == nullptr;
   while (rel > o->tol && it < o->max_it && std::isfinite(rel)) {
     const int mm = std::min(m, o->max_it - it);
-    auto enqueue_cycle = [&](hipStream_t st) {
-      hipStream_t saved = g->stream;
-      g->stream = st;                       // the cycle drivers launch on g->stream
-      launch_gmres_begin(st, gs, m);
-      for (int j = 0; j < mm; ++j) {
-        double2* Wj = W + (size_t)j * stride64;
-        double2* Wn = W + (size_t)(j + 1) * stride64;
-        char* Zj = Z + (size_t)j * fbz;
-        // preconditioner on the normalised basis vector v_j = s_j W_j
-        if (f32) {
-          launch_scale_copy<double, float>(st, n, pitch, pitch, Wj, gs.scale + j, g->ws + g->f32);
-          mgcccs_cycle<float>(g, Zj, g->ws + g->f32, true);
-          launch_stencil<double, float, double, double>(st, EX, Zj, nullptr, Wn, 1, nullptr);
-        } else {
-          mgcccs_cycle<double>(g, Zj, Wj, true, gs.scale + j);
-          launch_stencil<double, double, double, double>(st, EX, Zj, nullptr, Wn, 1, nullptr);
-        }
-        // classical Gram-Schmidt with one re-orthogonalisation; the reductions
-        // and the Hessenberg / Givens updates finish inside the last blocks
-        for (int pass = 0; pass < 2; ++pass) {
-          launch_multidot(st, n, pitch, stride64, W, j + 1, Wn, part, ticket, gs, j, pass);
-          launch_multiaxpy(st, n, pitch, stride64, W, j + 1, gs.axcoef, Wn, part, ticket, gs, j, m,
-                           o->tol * fn, pass == 1);
-        }
-      }
-      launch_gmres_solve(st, gs, m, mm);
-      if (f32) launch_update<float>(st, n, pitch, stridez, Z, mm, gs.upcoef, (double2*)u);
-      else launch_update<double>(st, n, pitch, stridez, Z, mm, gs.upcoef, (double2*)u);
-      g->stream = saved;
-    };
     if (use_graph) {
       GraphCache& gc = g->graph;
       if (!gc.exec || gc.u != u || gc.f != f || gc.m != m || gc.mm != mm || gc.inner != (int)o->inner ||
@@ -572,7 +591,7 @@ mgc_status solve_fgmres(mgc_grid g, void* u, const void* f, const mgc_solve_opts
         if (gc.exec) { (void)hipGraphExecDestroy(gc.exec); gc.exec = nullptr; }
         hipGraph_t graph;
         HIPCHK(g, hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal));
-        enqueue_cycle(g->cap);
+        enqueue_fgmres_cycle(g, u, o, o->tol * fn, mm, g->cap);
         HIPCHK(g, hipStreamEndCapture(g->cap, &graph));
         hipError_t e = hipGraphInstantiate(&gc.exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
@@ -581,9 +600,8 @@ mgc_status solve_fgmres(mgc_grid g, void* u, const void* f, const mgc_solve_opts
       }
       HIPCHK(g, hipGraphLaunch(gc.exec, s));
     } else {
-      enqueue_cycle(s);
+      enqueue_fgmres_cycle(g, u, o, o->tol * fn, mm, s);
     }
-    ++cycles;
     rc = exact_residual(g, u, f, W, &rr, &ff, gs.nrm2);
     if (rc) return rc;
     int kused = mm;

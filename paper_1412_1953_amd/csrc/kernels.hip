@@ -686,7 +686,6 @@ __device__ __forceinline__ int lane_shift_for(int R) {
   return s;                      // g = 2^s lanes per row, g * r2 <= 64
 }
 
-constexpr int PD = 4;            // prefetch distance of the chains (steps)
 
 // Step 3: channel right-hand sides, chunk-local block LU solves and, in the
 // last chunk of each system, the interface system.  Block = one wave;
@@ -695,7 +694,7 @@ constexpr int PD = 4;            // prefetch distance of the chains (steps)
 // (Remark 4 convention):
 //   r^A_i(k) = rho^A_i(k) - sum_{l > i} c_il varphi_l(k)
 //   r^B_l(j) = rho^B_l(j) - sum_{m >= l} c_ml phi_m(j)
-template <typename T, int NE, int NEI, int MC>
+template <typename T, int NE, int NEI, int MC, int PDL, int PDI>
 __global__ void __launch_bounds__(64) k_cccs_chain(ChanSys<T> SA, ChanSys<T> SB, ChanTab<T> ch,
                                                    int n, const v2<T>* __restrict__ rhoA,
                                                    const v2<T>* __restrict__ rhoB,
@@ -732,9 +731,9 @@ __global__ void __launch_bounds__(64) k_cccs_chain(ChanSys<T> SA, ChanSys<T> SB,
   __syncthreads();                    // single wave: orders the g writes before the reads below
   const int gsh = lane_shift_for(M), row = lane >> gsh, part = lane & ((1 << gsh) - 1);
   const bool owner = (row < M) && part == 0;
-  // (b) forward sweep  Z_t = G_t (r_t - lo_t Z_{t-1})  with a PD-deep prefetch;
+  // (b) forward sweep  Z_t = G_t (r_t - lo_t Z_{t-1})  with a PDL-deep prefetch;
   //     rq holds r_t at the lane's columns
-  v2<T> A[PD][NE], rq[PD][NE], cq[PD];
+  v2<T> A[PDL][NE], rq[PDL][NE], cq[PDL];
   auto load_fwd = [&](int d, int t) {
     load_row<T, NE>(A[d], S.G + (size_t)t * MM, M, gsh);
 #pragma unroll
@@ -745,12 +744,12 @@ __global__ void __launch_bounds__(64) k_cccs_chain(ChanSys<T> SA, ChanSys<T> SB,
     cq[d] = S.lo[t];
   };
 #pragma unroll
-  for (int d = 0; d < PD; ++d)
+  for (int d = 0; d < PDL; ++d)
     if (s + d <= e) load_fwd(d, s + d);
   v2<T> y = mk<T>(0, 0);
-  for (int t0 = s; t0 <= e; t0 += PD) {
+  for (int t0 = s; t0 <= e; t0 += PDL) {
 #pragma unroll
-    for (int d = 0; d < PD; ++d) {
+    for (int d = 0; d < PDL; ++d) {
       const int t = t0 + d;
       if (t > e) break;
       v2<T> x[NE];
@@ -763,32 +762,32 @@ __global__ void __launch_bounds__(64) k_cccs_chain(ChanSys<T> SA, ChanSys<T> SB,
         for (int q = 0; q < NE; ++q) x[q] = rq[d][q];
       }
       y = rowsum<T, NE>(A[d], x, gsh);
-      if (t + PD <= e) load_fwd(d, t + PD);
+      if (t + PDL <= e) load_fwd(d, t + PDL);
       if (owner) g[(size_t)t * M + row] = y;
     }
   }
   __syncthreads();                    // forward results written by other lanes become visible
   // (c) backward sweep  g_t = Z_t - up_t G_t g_{t+1};  zq holds Z_t at the lane's row
-  v2<T> zq[PD];
+  v2<T> zq[PDL];
   auto load_bwd = [&](int d, int t) {
     load_row<T, NE>(A[d], S.G + (size_t)t * MM, M, gsh);
     zq[d] = row < M ? g[(size_t)t * M + row] : mk<T>(0, 0);
     cq[d] = S.up[t];
   };
 #pragma unroll
-  for (int d = 0; d < PD; ++d)
+  for (int d = 0; d < PDL; ++d)
     if (e - 1 - d >= s) load_bwd(d, e - 1 - d);
   const v2<T> gs = y;                 // g at the chunk's last row
-  for (int t0 = e - 1; t0 >= s; t0 -= PD) {
+  for (int t0 = e - 1; t0 >= s; t0 -= PDL) {
 #pragma unroll
-    for (int d = 0; d < PD; ++d) {
+    for (int d = 0; d < PDL; ++d) {
       const int t = t0 - d;
       if (t < s) break;
       v2<T> x[NE];
       gather<T, NE>(x, y, M, gsh, gsh, 0, M);
       const v2<T> acc = rowsum<T, NE>(A[d], x, gsh);
       const v2<T> z = zq[d], cu = cq[d];
-      if (t - PD >= s) load_bwd(d, t - PD);
+      if (t - PDL >= s) load_bwd(d, t - PDL);
       y = csub(z, cmul(cu, acc));
       if (owner) g[(size_t)t * M + row] = y;
     }
@@ -829,26 +828,26 @@ __global__ void __launch_bounds__(64) k_cccs_chain(ChanSys<T> SA, ChanSys<T> SB,
   if (!is_last) return;
   __threadfence();
   // forward: Z_q = H_q - Rlo_q Z_{q-1}
-  v2<T> B[PD][NEI], hq[PD];
+  v2<T> B[PDI][NEI], hq[PDI];
   auto load_ifw = [&](int d, int q) {
     load_row<T, NEI>(B[d], S.Rlo + (size_t)q * RR, R, gsi);
     hq[d] = rowi < R ? cadd(H[((size_t)q * 2) * R + rowi], H[((size_t)q * 2 + 1) * R + rowi]) : mk<T>(0, 0);
   };
 #pragma unroll
-  for (int d = 0; d < PD; ++d)
+  for (int d = 0; d < PDI; ++d)
     if (1 + d < Q) load_ifw(d, 1 + d);
   v2<T> zz = rowi < R ? cadd(H[rowi], H[R + rowi]) : mk<T>(0, 0);
   if (own) Y[rowi] = zz;
-  for (int q0 = 1; q0 < Q; q0 += PD) {
+  for (int q0 = 1; q0 < Q; q0 += PDI) {
 #pragma unroll
-    for (int d = 0; d < PD; ++d) {
+    for (int d = 0; d < PDI; ++d) {
       const int q = q0 + d;
       if (q >= Q) break;
       v2<T> x[NEI];
       gather<T, NEI>(x, zz, R, gsi, gsi, 0, R);
       const v2<T> acc = rowsum<T, NEI>(B[d], x, gsi);
       const v2<T> h = hq[d];
-      if (q + PD < Q) load_ifw(d, q + PD);
+      if (q + PDI < Q) load_ifw(d, q + PDI);
       zz = csub(h, acc);
       if (own) Y[(size_t)q * R + rowi] = zz;
     }
@@ -860,18 +859,18 @@ __global__ void __launch_bounds__(64) k_cccs_chain(ChanSys<T> SA, ChanSys<T> SB,
     hq[d] = rowi < R ? Y[(size_t)q * R + rowi] : mk<T>(0, 0);
   };
 #pragma unroll
-  for (int d = 0; d < PD; ++d)
+  for (int d = 0; d < PDI; ++d)
     if (Q - 2 - d >= 0) load_ibw(d, Q - 2 - d);
-  for (int q0 = Q - 2; q0 >= 0; q0 -= PD) {
+  for (int q0 = Q - 2; q0 >= 0; q0 -= PDI) {
 #pragma unroll
-    for (int d = 0; d < PD; ++d) {
+    for (int d = 0; d < PDI; ++d) {
       const int q = q0 - d;
       if (q < 0) break;
       v2<T> x[NEI];
       gather<T, NEI>(x, zz, R, gsi, gsi, 0, R);
       const v2<T> acc = rowsum<T, NEI>(B[d], x, gsi);
       const v2<T> h = hq[d];
-      if (q - PD >= 0) load_ibw(d, q - PD);
+      if (q - PDI >= 0) load_ibw(d, q - PDI);
       zz = csub(h, acc);
       if (own) Y[(size_t)q * R + rowi] = zz;
     }
@@ -954,59 +953,79 @@ __device__ __forceinline__ int flat_block() { return blockIdx.x + gridDim.x * bl
 
 // ----------------------------------------------------------------------------
 // FGMRES bookkeeping on the device (run by one thread of the last block).
-__device__ void gmres_coef_dev(const GmresState& st, int j, int pass) {
+// Called by every thread of the last block after the reductions finished.
+// Loads go to LDS in parallel; only the short sequential Givens arithmetic
+// runs on one thread.
+__device__ void gmres_coef_blk(const GmresState& st, int j, int pass) {
   // after a multi-dot over W_0..W_j: c_i -> h_i += s_i c_i ; axpy coefficient s_i^2 c_i
-  for (int i = 0; i <= j; ++i) {
-    double s = st.scale[i];
-    double cr = st.dots[2 * i], ci = st.dots[2 * i + 1];
-    if (pass == 0) { st.hcol[2 * i] = 0; st.hcol[2 * i + 1] = 0; }
-    st.hcol[2 * i] += s * cr;
-    st.hcol[2 * i + 1] += s * ci;
+  const int i = threadIdx.x + blockDim.x * threadIdx.y;
+  if (i <= j) {
+    const double s = st.scale[i];
+    const double cr = st.dots[2 * i], ci = st.dots[2 * i + 1];
+    const double hr = pass == 0 ? 0.0 : st.hcol[2 * i], hi = pass == 0 ? 0.0 : st.hcol[2 * i + 1];
+    st.hcol[2 * i] = hr + s * cr;
+    st.hcol[2 * i + 1] = hi + s * ci;
     st.axcoef[i] = make_double2(s * s * cr, s * s * ci);
   }
 }
 
-__device__ void gmres_step_dev(const GmresState& st, int j, int m, double tol_abs) {
-  // after the final norm: nrm = sqrt(st.nrm2[0]); column j of H, Givens, residual estimate
+__device__ void gmres_step_blk(const GmresState& st, int j, int m, double tol_abs) {
+  // after the final norm: column j of H (= projections, then the norm),
+  // earlier rotations, new rotation, residual estimate
+  __shared__ double col[2 * 34], rot[4 * 33], gg[4];
+  const int tid = threadIdx.x + blockDim.x * threadIdx.y;
   const int R = m + 1;
-  double nrm = sqrt(st.nrm2[0]);
-  const double sj = 1.0;   // z_j = P(v_j) with the normalised v_j
-  double* H = st.H;                       // column-major (m+1) x m complex
-  for (int i = 0; i <= j; ++i) {
-    H[2 * (j * R + i)] = sj * st.hcol[2 * i];
-    H[2 * (j * R + i) + 1] = sj * st.hcol[2 * i + 1];
+  if (tid <= j) {
+    col[2 * tid] = st.hcol[2 * tid];
+    col[2 * tid + 1] = st.hcol[2 * tid + 1];
   }
-  H[2 * (j * R + j + 1)] = sj * nrm;
-  H[2 * (j * R + j + 1) + 1] = 0;
-  st.scale[j + 1] = nrm > 0 ? 1.0 / nrm : 0.0;
-  // earlier rotations
-  for (int i = 0; i < j; ++i) {
-    double* x1 = &H[2 * (j * R + i)];
-    double* x2 = &H[2 * (j * R + i + 1)];
-    double cr = st.cs[2 * i], ci = st.cs[2 * i + 1], sr = st.sn[2 * i], si = st.sn[2 * i + 1];
-    double a = x1[0], b = x1[1], c = x2[0], d = x2[1];
-    // t1 = conj(cs) x1 + conj(sn) x2 ; t2 = -sn x1 + cs x2
-    double t1r = cr * a + ci * b + sr * c + si * d;
-    double t1i = cr * b - ci * a + sr * d - si * c;
-    double t2r = -(sr * a - si * b) + (cr * c - ci * d);
-    double t2i = -(sr * b + si * a) + (cr * d + ci * c);
-    x1[0] = t1r; x1[1] = t1i; x2[0] = t2r; x2[1] = t2i;
+  if (tid < j) {
+    rot[4 * tid] = st.cs[2 * tid];
+    rot[4 * tid + 1] = st.cs[2 * tid + 1];
+    rot[4 * tid + 2] = st.sn[2 * tid];
+    rot[4 * tid + 3] = st.sn[2 * tid + 1];
   }
-  double* hj = &H[2 * (j * R + j)];
-  double* hn = &H[2 * (j * R + j + 1)];
-  double den = sqrt(hj[0] * hj[0] + hj[1] * hj[1] + hn[0] * hn[0] + hn[1] * hn[1]);
-  double cr = hj[0] / den, ci = hj[1] / den, sr = hn[0] / den, si = hn[1] / den;
-  st.cs[2 * j] = cr; st.cs[2 * j + 1] = ci; st.sn[2 * j] = sr; st.sn[2 * j + 1] = si;
-  hj[0] = den; hj[1] = 0; hn[0] = 0; hn[1] = 0;
-  double gr = st.g[2 * j], gi = st.g[2 * j + 1];
-  // g_{j+1} = -sn g_j ; g_j = conj(cs) g_j
-  st.g[2 * (j + 1)] = -(sr * gr - si * gi);
-  st.g[2 * (j + 1) + 1] = -(sr * gi + si * gr);
-  st.g[2 * j] = cr * gr + ci * gi;
-  st.g[2 * j + 1] = cr * gi - ci * gr;
-  double est = sqrt(st.g[2 * (j + 1)] * st.g[2 * (j + 1)] + st.g[2 * (j + 1) + 1] * st.g[2 * (j + 1) + 1]);
-  st.est[j] = est;
-  if (st.kstar[0] < 0 && (est <= tol_abs || !(nrm > 0))) st.kstar[0] = j + 1;
+  if (tid == 0) {
+    gg[0] = st.g[2 * j];
+    gg[1] = st.g[2 * j + 1];
+    gg[2] = sqrt(st.nrm2[0]);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const double nrm = gg[2];
+    col[2 * (j + 1)] = nrm;
+    col[2 * (j + 1) + 1] = 0.0;
+    for (int i = 0; i < j; ++i) {
+      const double cr = rot[4 * i], ci = rot[4 * i + 1], sr = rot[4 * i + 2], si = rot[4 * i + 3];
+      const double a = col[2 * i], b = col[2 * i + 1], c = col[2 * i + 2], d = col[2 * i + 3];
+      // t1 = conj(cs) x1 + conj(sn) x2 ; t2 = -sn x1 + cs x2
+      col[2 * i] = cr * a + ci * b + sr * c + si * d;
+      col[2 * i + 1] = cr * b - ci * a + sr * d - si * c;
+      col[2 * i + 2] = -(sr * a - si * b) + (cr * c - ci * d);
+      col[2 * i + 3] = -(sr * b + si * a) + (cr * d + ci * c);
+    }
+    const double hr = col[2 * j], hi = col[2 * j + 1], nr = col[2 * j + 2], ni = col[2 * j + 3];
+    const double den = sqrt(hr * hr + hi * hi + nr * nr + ni * ni);
+    const double cr = hr / den, ci = hi / den, sr = nr / den, si = ni / den;
+    st.cs[2 * j] = cr; st.cs[2 * j + 1] = ci; st.sn[2 * j] = sr; st.sn[2 * j + 1] = si;
+    col[2 * j] = den; col[2 * j + 1] = 0; col[2 * j + 2] = 0; col[2 * j + 3] = 0;
+    const double gr = gg[0], gi = gg[1];
+    // g_{j+1} = -sn g_j ; g_j = conj(cs) g_j
+    const double g1r = -(sr * gr - si * gi), g1i = -(sr * gi + si * gr);
+    st.g[2 * (j + 1)] = g1r;
+    st.g[2 * (j + 1) + 1] = g1i;
+    st.g[2 * j] = cr * gr + ci * gi;
+    st.g[2 * j + 1] = cr * gi - ci * gr;
+    const double est = sqrt(g1r * g1r + g1i * g1i);
+    st.est[j] = est;
+    st.scale[j + 1] = nrm > 0 ? 1.0 / nrm : 0.0;
+    if (st.kstar[0] < 0 && (est <= tol_abs || !(nrm > 0))) st.kstar[0] = j + 1;
+  }
+  __syncthreads();
+  if (tid <= j + 1) {                  // Hessenberg is column-major (m+1) x m complex
+    st.H[2 * (j * R + tid)] = col[2 * tid];
+    st.H[2 * (j * R + tid) + 1] = col[2 * tid + 1];
+  }
 }
 
 // part[b][q] = sum conj(W_q) Y over the block's nodes, q < J (J <= 32).
@@ -1040,7 +1059,7 @@ __global__ void __launch_bounds__(256) k_multidot(int n, int pitch, size_t strid
   }
   if (last_block(ticket)) {
     finish_sum(part, gridDim.x * gridDim.y, 2 * J, st.dots);
-    if (threadIdx.x == 0) gmres_coef_dev(st, jcol, pass);
+    gmres_coef_blk(st, jcol, pass);
   }
 }
 
@@ -1077,7 +1096,7 @@ __global__ void __launch_bounds__(256) k_multiaxpy(int n, int pitch, size_t stri
   if (threadIdx.x == 0) part[flat_block()] = tot[0];
   if (final_pass && last_block(ticket)) {
     finish_sum(part, gridDim.x * gridDim.y, 1, st.nrm2);
-    if (threadIdx.x == 0) gmres_step_dev(st, jcol, mrest, tol_abs);
+    gmres_step_blk(st, jcol, mrest, tol_abs);
   }
 }
 
@@ -1147,29 +1166,39 @@ __global__ void k_gmres_begin(GmresState st, int m) {
   st.beta[0] = beta;
 }
 
-__global__ void k_gmres_solve(GmresState st, int m, int mm) {
+__global__ void __launch_bounds__(256) k_gmres_solve(GmresState st, int m, int mm) {
   // y = H(1:k,1:k)^{-1} g(1:k); k = first step meeting the tolerance, else the
-  // mm <= m steps this cycle performed; update coefficients y_i
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  // mm <= m steps this cycle performed; update coefficients y_i.  H and g are
+  // staged in LDS by all threads, the back substitution runs on one thread.
+  __shared__ double Hs[2 * 33 * 32], gs[2 * 33], ys[2 * 32];
+  const int tid = threadIdx.x;
   const int R = m + 1;
-  int k = (st.kstar[0] > 0 && st.kstar[0] <= mm) ? st.kstar[0] : mm;
-  st.kused[0] = k;
-  double* H = st.H;
-  for (int i = k - 1; i >= 0; --i) {
-    double vr = st.g[2 * i], vi = st.g[2 * i + 1];
-    for (int c = i + 1; c < k; ++c) {
-      double hr = H[2 * (c * R + i)], hi = H[2 * (c * R + i) + 1];
-      double yr = st.y[2 * c], yi = st.y[2 * c + 1];
-      vr -= hr * yr - hi * yi;
-      vi -= hr * yi + hi * yr;
+  for (int q = tid; q < 2 * R * m; q += 256) Hs[q] = st.H[q];
+  for (int q = tid; q < 2 * R; q += 256) gs[q] = st.g[q];
+  __syncthreads();
+  if (tid == 0) {
+    const int k = (st.kstar[0] > 0 && st.kstar[0] <= mm) ? st.kstar[0] : mm;
+    st.kused[0] = k;
+    for (int i = k - 1; i >= 0; --i) {
+      double vr = gs[2 * i], vi = gs[2 * i + 1];
+      for (int c = i + 1; c < k; ++c) {
+        const double hr = Hs[2 * (c * R + i)], hi = Hs[2 * (c * R + i) + 1];
+        vr -= hr * ys[2 * c] - hi * ys[2 * c + 1];
+        vi -= hr * ys[2 * c + 1] + hi * ys[2 * c];
+      }
+      const double dr = Hs[2 * (i * R + i)], di = Hs[2 * (i * R + i) + 1];
+      const double den = dr * dr + di * di;
+      ys[2 * i] = (vr * dr + vi * di) / den;
+      ys[2 * i + 1] = (vi * dr - vr * di) / den;
     }
-    double dr = H[2 * (i * R + i)], di = H[2 * (i * R + i) + 1];
-    double den = dr * dr + di * di;
-    st.y[2 * i] = (vr * dr + vi * di) / den;
-    st.y[2 * i + 1] = (vi * dr - vr * di) / den;
+    for (int i = k; i < m; ++i) { ys[2 * i] = 0; ys[2 * i + 1] = 0; }
   }
-  for (int i = 0; i < m; ++i)
-    st.upcoef[i] = (i < k) ? make_double2(st.y[2 * i], st.y[2 * i + 1]) : make_double2(0, 0);
+  __syncthreads();
+  if (tid < m) {
+    st.y[2 * tid] = ys[2 * tid];
+    st.y[2 * tid + 1] = ys[2 * tid + 1];
+    st.upcoef[tid] = make_double2(ys[2 * tid], ys[2 * tid + 1]);
+  }
 }
 
 // Iterative refinement scale: s = sqrt(N)/||r|| (RMS normalisation); sc[1] = 1/s.
@@ -1419,13 +1448,14 @@ void launch_cccs(hipStream_t s, const Level<T>& L, void* u, const void* f, const
                      (const v2<T>*)partB, rhoA, rhoB, partC, w.tickets, coef);
   const int P = SA.P > SB.P ? SA.P : SB.P;
   // entries per lane: chains over M x M blocks, interface over 2M x 2M blocks
-#define MGC_CHAIN(NE, NEI, MCC)                                                                 \
-  hipLaunchKernelGGL((k_cccs_chain<T, NE, NEI, MCC>), dim3(P, 2), dim3(64), 0, s, SA, SB, ch, n, \
+#define MGC_CHAIN(NE, NEI, MCC, PDL, PDI)                                                       \
+  hipLaunchKernelGGL((k_cccs_chain<T, NE, NEI, MCC, PDL, PDI>), dim3(P, 2), dim3(64), 0, s, SA, SB, ch, n, \
                      (const v2<T>*)rhoA, (const v2<T>*)rhoB, (const v2<T>*)coef, gA, gB, YA, YB,    \
                      (v2<T>*)w.HA, (v2<T>*)w.HB, w.tickets + 1)
-  if (MC <= 4) MGC_CHAIN(1, 2, 4);
-  else if (MC <= 8) MGC_CHAIN(1, 4, 8);
-  else MGC_CHAIN(4, 16, 16);
+  // prefetch depth (chain steps in flight) traded against registers
+  if (MC <= 4) MGC_CHAIN(1, 2, 4, 4, 4);
+  else if (MC <= 8) MGC_CHAIN(1, 4, 8, 4, 4);
+  else MGC_CHAIN(4, 16, 16, 2, 1);
 #undef MGC_CHAIN
   const int NM = (SA.N * SA.M > SB.N * SB.M) ? SA.N * SA.M : SB.N * SB.M;
   hipLaunchKernelGGL((k_cccs_retrieve<T>), dim3((NM + 255) / 256, 2), dim3(256), 0, s, SA, SB,
@@ -1506,7 +1536,7 @@ void launch_gmres_begin(hipStream_t s, const GmresState& st, int m) {
   hipLaunchKernelGGL(k_gmres_begin, dim3(1), dim3(1), 0, s, st, m);
 }
 void launch_gmres_solve(hipStream_t s, const GmresState& st, int m, int mm) {
-  hipLaunchKernelGGL(k_gmres_solve, dim3(1), dim3(1), 0, s, st, m, mm);
+  hipLaunchKernelGGL(k_gmres_solve, dim3(1), dim3(256), 0, s, st, m, mm);
 }
 void launch_ir_scale(hipStream_t s, const double* nrm2, double Nn, double* sc) {
   hipLaunchKernelGGL(k_ir_scale, dim3(1), dim3(1), 0, s, nrm2, Nn, sc);

@@ -70,6 +70,7 @@ template <typename T>
 void launch_prolong_add(hipStream_t s, int n, int pitch, void* u, const void* ec, int pitch_c);
 template <typename T>
 void launch_coarse_solve(hipStream_t s, const double2* Ainv, int nc, int pitch, const void* f, void* u);
+
 // fused zero-guess passes (nu1 = nu2 = 1); fs: optional device scale of f
 template <typename T>
 void launch_s1_zero(hipStream_t s, const Level<T>& L, const void* f, const double* fs, double omega,
