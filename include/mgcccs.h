@@ -57,6 +57,9 @@ typedef enum {
   MGC_ENUMERIC = -6   /* NaN or Inf encountered                                */
 } mgc_status;
 
+/* Largest FGMRES restart length (basis size) the library supports. */
+#define MGC_MAX_RESTART 16
+
 typedef enum { MGC_FP64 = 0, MGC_FP32 = 1 } mgc_precision;
 
 typedef enum {
@@ -85,7 +88,8 @@ typedef struct mgc_grid_s* mgc_grid;   /* opaque, library-owned host object */
  *          x <= R0 (the complex-contour operator of Sec. 3.1/Sec. 6), followed
  *          by the ECS ray.  pc_gamma = 0 makes every level the exact operator.
  *          The CCCS acts on the level-0 operator of the hierarchy.
- * max_restart  FGMRES basis size the workspace must hold (0: no FGMRES).
+ * max_restart  FGMRES basis size the workspace must hold, 0 .. MGC_MAX_RESTART
+ *              (0: no FGMRES).
  * precisions   bit mask (1 << MGC_FP64) | (1 << MGC_FP32) of the cycle
  *          precisions the workspace must hold.                                */
 typedef struct {

@@ -45,7 +45,7 @@ struct SysOff {                            // offsets of one channel system's fa
 struct CcOff {                             // CCCS tables + scratch for one precision
   size_t wphi = 0, phi = 0, wvphi = 0, vphi = 0;
   SysOff A, B;
-  size_t partA = 0, partB = 0, rhoA = 0, rhoB = 0, partC = 0, coef = 0, tickets = 0, gA = 0, gB = 0,
+  size_t partA = 0, partB = 0, rhoA = 0, rhoB = 0, partC = 0, gA = 0, gB = 0,
          YA = 0, YB = 0, HA = 0, HB = 0, eA = 0, eB = 0;
 };
 
@@ -80,7 +80,9 @@ struct mgc_grid_s {
   size_t ws_bytes = 0, need = 0;
   size_t exact_tab = 0, exact_tab32 = 0, exact_w = 0, exact_z = 0, coarse_inv = 0, tt = 0;
   CcOff cc[2];
-  size_t part = 0, scal = 0, ticket = 0;   // reduction partials, small scalars, last-block ticket
+  size_t part = 0, scal = 0;               // reduction partials, small scalars
+  size_t apart = 0;                        // 3 x ARNOLDI_PART partials of the Arnoldi passes
+  bool basis_dirty = false;                // Krylov basis may hold non-finite values
   size_t r64 = 0, f32 = 0, u32 = 0, tw = 0, tz = 0;
   size_t W = 0, Z[2] = {0, 0};
   size_t gm = 0;                           // GmresState arrays
@@ -164,8 +166,6 @@ void layout(mgc_grid g) {
       c.rhoA = take((size_t)(n + 1) * M * e);
       c.rhoB = take((size_t)(n + 1) * Lc * e);
       c.partC = take((size_t)g->nchunksB * M * Lc * e);
-      c.coef = take((size_t)M * Lc * e + e);
-      c.tickets = take(4 * sizeof(unsigned));
       c.gA = take((size_t)N * M * e);
       c.gB = take((size_t)N * Lc * e);
       c.YA = take((size_t)g->PA * 2 * M * e);
@@ -181,7 +181,7 @@ void layout(mgc_grid g) {
   const int nb = std::max(launch_stencil_blocks(n), launch_vec_blocks(n));
   g->part = take((size_t)nb * 64 * sizeof(double));
   g->scal = take(256 * sizeof(double));
-  g->ticket = take(256);
+  g->apart = take((size_t)3 * ARNOLDI_PART * sizeof(double));
   g->r64 = take(g->field_bytes(0, P64));
   g->tw = take(g->field_bytes(0, P64));
   g->tz = take(g->field_bytes(0, P64));
@@ -208,9 +208,7 @@ GmresState gmres_state(mgc_grid g) {
   GmresState s;
   size_t o = 0;
   auto take = [&](size_t cnt) { double* p = b + o; o += cnt; return p; };
-  s.dots = take(2 * (m + 1));
   s.hcol = take(2 * (m + 1));
-  s.axcoef = reinterpret_cast<double2*>(take(2 * (m + 1)));
   s.nrm2 = take(2);
   s.scale = take(m + 2);
   s.H = take(2 * (m + 1) * m);
@@ -299,8 +297,6 @@ CccsScratch scratch_of(mgc_grid g, int p) {
   w.rhoA = g->ws + c.rhoA;
   w.rhoB = g->ws + c.rhoB;
   w.partC = g->ws + c.partC;
-  w.coef = g->ws + c.coef;
-  w.tickets = (unsigned*)(g->ws + c.tickets);
   w.gA = g->ws + c.gA;
   w.gB = g->ws + c.gB;
   w.YA = g->ws + c.YA;
@@ -427,7 +423,6 @@ mgc_status exact_residual(mgc_grid g, const void* u, const void* f, void* r, dou
   double* part = g->at<double>(g->part);
   double* out = g->at<double>(g->scal);
   Finish fin;
-  fin.ticket = g->at<unsigned>(g->ticket);
   fin.out = out;
   fin.copy_to = copy_to;
   launch_stencil<double, double, double, double>(g->stream, exact_level(g), u, f, r, 0, part, fin);
@@ -523,8 +518,9 @@ void enqueue_fgmres_cycle(mgc_grid g, void* u, const mgc_solve_opts* o, double t
   GmresState gs = gmres_state(g);
   double2* W = g->at<double2>(g->W);
   char* Z = g->ws + g->Z[f32 ? P32 : P64];
-  double* part = g->at<double>(g->part);
-  unsigned* ticket = g->at<unsigned>(g->ticket);
+  double* p0 = g->at<double>(g->apart);
+  double* p1 = p0 + ARNOLDI_PART;
+  double* p2 = p1 + ARNOLDI_PART;
   Level<double> EX = exact_level(g);
   hipStream_t saved = g->stream;
   g->stream = st;                           // the cycle drivers launch on g->stream
@@ -537,18 +533,16 @@ void enqueue_fgmres_cycle(mgc_grid g, void* u, const mgc_solve_opts* o, double t
     if (f32) {
       launch_scale_copy<double, float>(st, n, pitch, pitch, Wj, gs.scale + j, g->ws + g->f32);
       mgcccs_cycle<float>(g, Zj, g->ws + g->f32, true);
-      launch_stencil<double, float, double, double>(st, EX, Zj, nullptr, Wn, 1, nullptr);
+      launch_apply_dot<float>(st, EX, Zj, stride64, W, j + 1, Wn, p0);
     } else {
       mgcccs_cycle<double>(g, Zj, Wj, true, gs.scale + j);
-      launch_stencil<double, double, double, double>(st, EX, Zj, nullptr, Wn, 1, nullptr);
+      launch_apply_dot<double>(st, EX, Zj, stride64, W, j + 1, Wn, p0);
     }
-    // classical Gram-Schmidt with one re-orthogonalisation; the reductions
-    // and the Hessenberg / Givens updates finish inside the last blocks
-    for (int pass = 0; pass < 2; ++pass) {
-      launch_multidot(st, n, pitch, stride64, W, j + 1, Wn, part, ticket, gs, j, pass);
-      launch_multiaxpy(st, n, pitch, stride64, W, j + 1, gs.axcoef, Wn, part, ticket, gs, j, m, tol_abs,
-                       pass == 1);
-    }
+    // classical Gram-Schmidt with one re-orthogonalisation, then the
+    // Hessenberg column and its Givens rotation on the device
+    launch_axpy_pass(st, n, pitch, stride64, W, j + 1, Wn, p0, p1, gs, 0);
+    launch_axpy_pass(st, n, pitch, stride64, W, j + 1, Wn, p1, p2, gs, 1);
+    launch_gmres_step(st, n, pitch, p2, gs, j, m, tol_abs);
   }
   launch_gmres_solve(st, gs, m, mm);
   if (f32) launch_update<float>(st, n, pitch, stridez, Z, mm, gs.upcoef, (double2*)u);
@@ -561,7 +555,6 @@ void enqueue_fgmres_cycle(mgc_grid g, void* u, const mgc_solve_opts* o, double t
 void enqueue_true_residual(mgc_grid g, const void* u, const void* f, hipStream_t st) {
   GmresState gs = gmres_state(g);
   Finish fin;
-  fin.ticket = g->at<unsigned>(g->ticket);
   fin.out = g->at<double>(g->scal);
   fin.copy_to = gs.nrm2;
   launch_stencil<double, double, double, double>(st, exact_level(g), u, f, g->at<double2>(g->W), 0,
@@ -573,6 +566,12 @@ mgc_status solve_fgmres(mgc_grid g, void* u, const void* f, const mgc_solve_opts
   hipStream_t s = g->stream;
   GmresState gs = gmres_state(g);
   double2* W = g->at<double2>(g->W);
+  if (g->basis_dirty) {
+    // a failed solve may have left non-finite values outside the interior,
+    // which the padded-array passes would pick up: start from zeros again
+    HIPCHK(g, hipMemsetAsync(W, 0, (size_t)(g->d.max_restart + 1) * g->field_bytes(0, P64), s));
+    g->basis_dirty = false;
+  }
   // W_0 = f - A u  (||W_0||^2 lands in gs.nrm2 for the next cycle's start)
   double rr, ff;
   mgc_status rc = exact_residual(g, u, f, W, &rr, &ff, gs.nrm2);
@@ -612,6 +611,7 @@ mgc_status solve_fgmres(mgc_grid g, void* u, const void* f, const mgc_solve_opts
     record(st, ++rs, rel);
   }
   if (st) { st->iters = it; st->vcycles = it; st->relres = rel; }
+  if (!std::isfinite(rel)) g->basis_dirty = true;
   return finish_status(rel, o->tol);
 }
 
@@ -693,7 +693,8 @@ mgc_status mgc_create_grid(const mgc_grid_desc* d, void* hip_stream, mgc_grid* o
   if (d->nu1 < 0 || d->nu2 < 0 || d->nu1 + d->nu2 < 1 || d->nu1 > 8 || d->nu2 > 8) return fail(MGC_EINVAL, "bad smoothing counts");
   if (!(d->pc_gamma >= 0) || !(d->pc_gamma < M_PI / 4)) return fail(MGC_EINVAL, "pc_gamma must lie in [0, pi/4)");
   if (d->pc_first_level < 0) return fail(MGC_EINVAL, "pc_first_level must be >= 0");
-  if (d->max_restart < 0 || d->max_restart > 32) return fail(MGC_EINVAL, "max_restart must lie in [0, 32]");
+  if (d->max_restart < 0 || d->max_restart > MGC_MAX_RESTART)
+    return fail(MGC_EINVAL, "max_restart must lie in [0, 16]");
   if ((d->precisions & 1) == 0 || (d->precisions & ~3)) return fail(MGC_EINVAL, "precisions must include MGC_FP64");
 
   mgc_grid g = new mgc_grid_s();

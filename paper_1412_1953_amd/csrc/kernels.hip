@@ -138,28 +138,9 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* out) {
   __syncthreads();
 }
 
-// Last-block completion of a two-stage reduction.  Every block has written
-// its partial sums; exactly one block (the last to take a ticket) sees true,
-// after which all partials are visible to it.  That block resets the ticket,
-// so the counter is clean for the next launch or graph replay.  The order of
-// the final summation is fixed (by block index), hence deterministic.
-__device__ __forceinline__ bool last_block(unsigned* ticket) {
-  __shared__ int is_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0 && threadIdx.y == 0) {
-    const unsigned nb = gridDim.x * gridDim.y;
-    const unsigned t = atomicAdd(ticket, 1u);
-    is_last = (t == nb - 1);
-    if (is_last) atomicExch(ticket, 0u);
-  }
-  __syncthreads();
-  if (is_last) __threadfence();
-  return is_last != 0;
-}
-
-// In the last block: out[q] = sum_b part[b*nq + q] (b ascending in slices,
-// slices combined in ascending order).  blockDim = 256 threads, nq <= 256.
+// Second stage of a two-stage reduction, run by one block of 256 threads on
+// partials written by an earlier kernel: out[q] = sum_b part[b*nq + q] (b
+// ascending in slices, slices combined in ascending order), nq <= 256.
 __device__ void finish_sum(const double* part, int nb, int nq, double* out) {
   __shared__ double red[256];
   const int t = threadIdx.x + blockDim.x * threadIdx.y;
@@ -167,8 +148,7 @@ __device__ void finish_sum(const double* part, int nb, int nq, double* out) {
   const int q = t % nq, sl = t / nq;
   double s = 0.0;
   if (sl < ns) {
-    // plain loads: last_block() ended with an agent-scope fence, so the other
-    // blocks' partials are visible; four independent chains keep loads in flight
+    // four independent chains keep loads in flight
     double s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int b = sl;
     for (; b + 3 * ns < nb; b += 4 * ns) {
@@ -200,7 +180,7 @@ template <typename T, typename TU, typename TF, typename TO>
 __global__ void __launch_bounds__(256) k_stencil(Level<T> L, const v2<TU>* __restrict__ u,
                                                  const v2<TF>* __restrict__ f,
                                                  v2<TO>* __restrict__ out, int mode,
-                                                 double* __restrict__ part, Finish fin) {
+                                                 double* __restrict__ part) {
   const int j = 1 + blockIdx.x * SX + threadIdx.x;
   const int k0 = 1 + (blockIdx.y * SY + threadIdx.y) * ROWS;
   const int n = L.n, p = L.pitch;
@@ -230,10 +210,6 @@ __global__ void __launch_bounds__(256) k_stencil(Level<T> L, const v2<TU>* __res
       const int b = blockIdx.x + gridDim.x * blockIdx.y;
       part[2 * b] = tot[0];
       part[2 * b + 1] = tot[1];
-    }
-    if (fin.ticket && last_block(fin.ticket)) {
-      finish_sum(part, gridDim.x * gridDim.y, 2, fin.out);
-      if (fin.copy_to && threadIdx.x == 0 && threadIdx.y == 0) *fin.copy_to = fin.out[0];
     }
   }
 }
@@ -580,16 +556,16 @@ __global__ void __launch_bounds__(256) k_cccs_project(Level<T> L, const v2<T>* _
   }
 }
 
-// Step 2: rho^A, rho^B from the tile partials (fixed order) and the coupling
-// coefficients c[i][l] = sum_k w_k varphi_l(k) rho^A[k][i] (eq. coefficients):
-// per-block sums over 64 rows, finished by the last block.
+// Step 2: rho^A, rho^B from the tile partials (fixed order) and per-block
+// partial sums over 64 rows of the coupling coefficients
+// c[i][l] = sum_k w_k varphi_l(k) rho^A[k][i] (eq. coefficients); the chain
+// kernel adds up the blocks.
 template <typename T>
 __global__ void __launch_bounds__(256) k_cccs_reduce(int n, int ntiles, ChanTab<T> ch,
                                                      const v2<T>* __restrict__ partA,
                                                      const v2<T>* __restrict__ partB,
                                                      v2<T>* __restrict__ rhoA, v2<T>* __restrict__ rhoB,
-                                                     v2<T>* __restrict__ partC, unsigned* ticket,
-                                                     v2<T>* __restrict__ coef) {
+                                                     v2<T>* __restrict__ partC) {
   __shared__ v2<T> ra[PT][16];
   const int M = ch.M, Lc = ch.L, tid = threadIdx.x;
   const int kb = 1 + blockIdx.x * PT;
@@ -623,18 +599,6 @@ __global__ void __launch_bounds__(256) k_cccs_reduce(int n, int ntiles, ChanTab<
       xi += (double)a.x * b.y + (double)a.y * b.x;
     }
     partC[(size_t)blockIdx.x * P + tid] = mk<T>((T)xr, (T)xi);
-  }
-  if (last_block(ticket)) {
-    if (tid < P) {
-      double xr = 0, xi = 0;
-#pragma unroll 8
-      for (int b = 0; b < (int)gridDim.x; ++b) {
-        const v2<T> c = partC[(size_t)b * P + tid];
-        xr += c.x;
-        xi += c.y;
-      }
-      coef[tid] = mk<T>((T)xr, (T)xi);
-    }
   }
 }
 
@@ -687,22 +651,20 @@ __device__ __forceinline__ int lane_shift_for(int R) {
 }
 
 
-// Step 3: channel right-hand sides, chunk-local block LU solves and, in the
-// last chunk of each system, the interface system.  Block = one wave;
+// Step 3: channel right-hand sides, chunk-local block LU solves and the
+// chunks' contributions to the interface right-hand sides.  Block = one wave;
 // blockIdx.x = chunk, blockIdx.y = system (0: A, functions of x2 with the x1
 // channels; 1: B, functions of x1 with the x2 channels).  Right-hand sides
 // (Remark 4 convention):
 //   r^A_i(k) = rho^A_i(k) - sum_{l > i} c_il varphi_l(k)
 //   r^B_l(j) = rho^B_l(j) - sum_{m >= l} c_ml phi_m(j)
-template <typename T, int NE, int NEI, int MC, int PDL, int PDI>
+template <typename T, int NE, int NEI, int MC, int PDL>
 __global__ void __launch_bounds__(64) k_cccs_chain(ChanSys<T> SA, ChanSys<T> SB, ChanTab<T> ch,
                                                    int n, const v2<T>* __restrict__ rhoA,
                                                    const v2<T>* __restrict__ rhoB,
-                                                   const v2<T>* __restrict__ coef,
+                                                   const v2<T>* __restrict__ partC, int ntiles,
                                                    v2<T>* __restrict__ gA, v2<T>* __restrict__ gB,
-                                                   v2<T>* __restrict__ YA, v2<T>* __restrict__ YB,
-                                                   v2<T>* __restrict__ HA, v2<T>* __restrict__ HB,
-                                                   unsigned* tickets) {
+                                                   v2<T>* __restrict__ HA, v2<T>* __restrict__ HB) {
   const bool isA = blockIdx.y == 0;
   const ChanSys<T>& S = isA ? SA : SB;
   const int p = blockIdx.x;
@@ -712,6 +674,20 @@ __global__ void __launch_bounds__(64) k_cccs_chain(ChanSys<T> SA, ChanSys<T> SB,
   const int lane = threadIdx.x;
   v2<T>* g = isA ? gA : gB;
   const v2<T>* rho = isA ? rhoA : rhoB;
+  // coupling coefficients c[i][l]: the reduce kernel's per-block partials,
+  // added in block order
+  __shared__ v2<T> coef[256];
+  const int npair = ch.M * ch.L;
+  for (int idx = lane; idx < npair; idx += 64) {
+    double xr = 0, xi = 0;
+    for (int b = 0; b < ntiles; ++b) {
+      const v2<T> c = partC[(size_t)b * npair + idx];
+      xr += c.x;
+      xi += c.y;
+    }
+    coef[idx] = mk<T>((T)xr, (T)xi);
+  }
+  __syncthreads();
   // (a) right-hand sides of the chunk rows, written into g
   for (int idx = lane; idx < (e - s + 1) * M; idx += 64) {
     const int t = s + idx / M, i = idx % M, node = t + 1;
@@ -798,7 +774,6 @@ __global__ void __launch_bounds__(64) k_cccs_chain(ChanSys<T> SA, ChanSys<T> SB,
   const int R = 2 * M, RR = R * R;
   const int gsi = lane_shift_for(R), rowi = lane >> gsi;
   const bool own = (rowi < R) && (lane & ((1 << gsi) - 1)) == 0;
-  v2<T>* Y = isA ? YA : YB;
   v2<T>* H = isA ? HA : HB;           // [Q][2][R]: halves of Rinv_q [g(e_q); g(s_{q+1})]
   // (d) this chunk's contributions to the interface right-hand sides
   if (p < Q) {                        // interface p, from the last row: x = [gs; 0]
@@ -815,18 +790,26 @@ __global__ void __launch_bounds__(64) k_cccs_chain(ChanSys<T> SA, ChanSys<T> SB,
     const v2<T> acc = rowsum<T, NEI>(a, x, gsi);
     if (own) H[((size_t)(p - 1) * 2 + 1) * R + rowi] = acc;
   }
-  // (e) the last chunk of this system to finish solves the interface system
-  __shared__ int is_last;
-  __threadfence();
-  __syncthreads();
-  if (lane == 0) {
-    const unsigned t = atomicAdd(&tickets[isA ? 0 : 1], 1u);
-    is_last = (t == (unsigned)S.P - 1);
-    if (is_last) atomicExch(&tickets[isA ? 0 : 1], 0u);
-  }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
+}
+
+// Step 3b: the interface system of each system (blockIdx.y), one wave:
+// block-tridiagonal in 2M x 2M blocks, forward and backward block Thomas
+// sweeps with the precomputed Rinv, Rlo = Rinv Sub, Rup = Rinv Sup.
+template <typename T, int NEI, int PDI>
+__global__ void __launch_bounds__(64) k_cccs_interface(ChanSys<T> SA, ChanSys<T> SB,
+                                                       v2<T>* __restrict__ YA, v2<T>* __restrict__ YB,
+                                                       const v2<T>* __restrict__ HA,
+                                                       const v2<T>* __restrict__ HB) {
+  const bool isA = blockIdx.y == 0;
+  const ChanSys<T>& S = isA ? SA : SB;
+  const int Q = S.P - 1;
+  if (Q <= 0) return;
+  const int lane = threadIdx.x;
+  const int M = S.M, R = 2 * M, RR = R * R;
+  const int gsi = lane_shift_for(R), rowi = lane >> gsi;
+  const bool own = (rowi < R) && (lane & ((1 << gsi) - 1)) == 0;
+  v2<T>* Y = isA ? YA : YB;
+  const v2<T>* H = isA ? HA : HB;
   // forward: Z_q = H_q - Rlo_q Z_{q-1}
   v2<T> B[PDI][NEI], hq[PDI];
   auto load_ifw = [&](int d, int q) {
@@ -952,23 +935,9 @@ __global__ void __launch_bounds__(256) k_cccs_expand(int n, int pitch, v2<T>* __
 __device__ __forceinline__ int flat_block() { return blockIdx.x + gridDim.x * blockIdx.y; }
 
 // ----------------------------------------------------------------------------
-// FGMRES bookkeeping on the device (run by one thread of the last block).
-// Called by every thread of the last block after the reductions finished.
-// Loads go to LDS in parallel; only the short sequential Givens arithmetic
-// runs on one thread.
-__device__ void gmres_coef_blk(const GmresState& st, int j, int pass) {
-  // after a multi-dot over W_0..W_j: c_i -> h_i += s_i c_i ; axpy coefficient s_i^2 c_i
-  const int i = threadIdx.x + blockDim.x * threadIdx.y;
-  if (i <= j) {
-    const double s = st.scale[i];
-    const double cr = st.dots[2 * i], ci = st.dots[2 * i + 1];
-    const double hr = pass == 0 ? 0.0 : st.hcol[2 * i], hi = pass == 0 ? 0.0 : st.hcol[2 * i + 1];
-    st.hcol[2 * i] = hr + s * cr;
-    st.hcol[2 * i + 1] = hi + s * ci;
-    st.axcoef[i] = make_double2(s * s * cr, s * s * ci);
-  }
-}
-
+// FGMRES bookkeeping on the device, by one block after the reductions
+// finished.  Loads go to LDS in parallel; only the short sequential Givens
+// arithmetic runs on one thread.
 __device__ void gmres_step_blk(const GmresState& st, int j, int m, double tol_abs) {
   // after the final norm: column j of H (= projections, then the norm),
   // earlier rotations, new rotation, residual estimate
@@ -1028,76 +997,157 @@ __device__ void gmres_step_blk(const GmresState& st, int j, int m, double tol_ab
   }
 }
 
-// part[b][q] = sum conj(W_q) Y over the block's nodes, q < J (J <= 32).
-template <int JMAX>
-__global__ void __launch_bounds__(256) k_multidot(int n, int pitch, size_t stride,
-                                                  const double2* __restrict__ W, int J,
-                                                  const double2* __restrict__ Y,
-                                                  double* __restrict__ part, unsigned* ticket,
-                                                  GmresState st, int jcol, int pass) {
-  double acc[2 * JMAX];
+// ----------------------------------------------------------------------------
+// Fused Arnoldi passes of FGMRES step j (FP64 basis W_0..W_{J-1}, J = j+1,
+// new vector Y = W_{j+1}), classical Gram-Schmidt with one re-orthogonalisation:
+//   k_apply_dot  : Y = A z_j (exact operator)          per-block c_q = W_q^H Y
+//   k_axpy_pass 0: a_q = s_q^2 c_q, Y -= sum a_q W_q,   per-block c_q = W_q^H Y
+//   k_axpy_pass 1: same with the new c_q,               per-block ||Y||^2
+//   k_gmres_step : ||Y||, Hessenberg column j and its Givens rotation
+// Three sweeps of (J + 2) vectors per step.  s_q = 1/||W_q|| (unscaled basis).
+// No pass finishes its own reduction: a per-block fence and ticket would cost
+// far more than the kernel boundary, so each consumer adds up the producer's
+// per-block partials itself (every block in the same fixed order; block 0
+// also records the projections h_q += s_q c_q).
+// The axpy passes run over the whole padded array: every basis vector is zero
+// outside the interior (the workspace starts zeroed, the operator pass writes
+// interior nodes only and the axpys keep zeros zero), so the ring and the
+// padding add nothing to the dots.  J (<= 16) is a template argument, so that
+// all loads of a node are issued together.
+constexpr int AB = 512;          // threads per block of the Arnoldi passes
+constexpr int AD_SY = 8;         // k_apply_dot block: 64 columns x 8 row groups
+constexpr int AX_BLOCKS = 256;   // at most this many blocks per Arnoldi pass
+
+// out[q] = sum_b part[b*nq + q] by a block of NT threads (nq <= NT), fixed
+// summation order; ends with a barrier.
+template <int NT>
+__device__ void finish_sum_nt(const double* part, int nb, int nq, double* out) {
+  __shared__ double red[NT];
+  const int t = threadIdx.x + blockDim.x * threadIdx.y;
+  const int ns = NT / nq;
+  const int q = t % nq, sl = t / nq;
+  double s = 0.0;
+  if (sl < ns) {
+    double s1 = 0.0;
+    int b = sl;
+    for (; b + ns < nb; b += 2 * ns) {
+      s += part[(size_t)b * nq + q];
+      s1 += part[(size_t)(b + ns) * nq + q];
+    }
+    if (b < nb) s += part[(size_t)b * nq + q];
+    s += s1;
+  }
+  red[t] = s;
+  __syncthreads();
+  if (t < nq) {
+    double tot = 0.0;
+    for (int w = 0; w < ns; ++w) tot += red[w * nq + t];
+    out[t] = tot;
+  }
+  __syncthreads();
+}
+
+#define MGC_JFOR(q) _Pragma("unroll") for (int q = 0; q < J; ++q)
+
+// rows: rows per thread (each thread walks `rows` consecutive rows of a column)
+template <typename TZ, int J>
+__global__ void __launch_bounds__(AB) k_apply_dot(Level<double> L, const v2<TZ>* __restrict__ z,
+                                                  const double2* __restrict__ W, size_t stride,
+                                                  double2* __restrict__ Y, double* __restrict__ part,
+                                                  int rows) {
+  const int j = 1 + blockIdx.x * SX + threadIdx.x;
+  const int k0 = 1 + (blockIdx.y * AD_SY + threadIdx.y) * rows;
+  const int n = L.n, p = L.pitch;
+  double acc[2 * J];
 #pragma unroll
-  for (int q = 0; q < 2 * JMAX; ++q) acc[q] = 0;
-  MGC_NODE_LOOP(n, k, j) {
-    const size_t idx = (size_t)k * pitch + j;
-    double2 y = Y[idx];
-#pragma unroll
-    for (int q = 0; q < JMAX; ++q) {
-      if (q < J) {
-        double2 w = W[q * stride + idx];
-        acc[2 * q] += w.x * y.x + w.y * y.y;
-        acc[2 * q + 1] += w.x * y.y - w.y * y.x;
+  for (int q = 0; q < 2 * J; ++q) acc[q] = 0.0;
+  if (j < n) {
+    ColumnStencil<double, v2<TZ>> cs(L, z, j, __builtin_amdgcn_readfirstlane(k0));
+#pragma unroll 2
+    for (int r = 0; r < rows; ++r) {
+      const int k = __builtin_amdgcn_readfirstlane(k0 + r);
+      if (k < n) {
+        const size_t idx = (size_t)k * p + j;
+        double2 w[J];
+        MGC_JFOR(q) w[q] = W[q * stride + idx];
+        const double2 o = cs.step(k);
+        Y[idx] = o;
+        MGC_JFOR(q) {
+          acc[2 * q] += w[q].x * o.x + w[q].y * o.y;
+          acc[2 * q + 1] += w[q].x * o.y - w[q].y * o.x;
+        }
       }
     }
   }
-  double tot[2 * JMAX];
-  block_sum<2 * JMAX>(acc, tot);
-  if (threadIdx.x == 0) {
+  double tot[2 * J];
+  block_sum<2 * J>(acc, tot);
+  if (threadIdx.x == 0 && threadIdx.y == 0) {
 #pragma unroll
-    for (int q = 0; q < 2 * JMAX; ++q)
-      if (q < 2 * J) part[(size_t)flat_block() * 2 * J + q] = tot[q];
-  }
-  if (last_block(ticket)) {
-    finish_sum(part, gridDim.x * gridDim.y, 2 * J, st.dots);
-    gmres_coef_blk(st, jcol, pass);
+    for (int q = 0; q < 2 * J; ++q) part[(size_t)flat_block() * 2 * J + q] = tot[q];
   }
 }
 
-// Y -= sum_q coef_q W_q  (coef on the device, complex), then per-block
-// partial ||Y||^2 into part[b].
-template <int JMAX>
-__global__ void __launch_bounds__(256) k_multiaxpy(int n, int pitch, size_t stride,
-                                                   const double2* __restrict__ W, int J,
-                                                   const double2* __restrict__ coef,
-                                                   double2* __restrict__ Y,
-                                                   double* __restrict__ part, unsigned* ticket,
-                                                   GmresState st, int jcol, int mrest, double tol_abs,
-                                                   int final_pass) {
-  __shared__ double2 cf[JMAX];
-  if (threadIdx.x < J) cf[threadIdx.x] = coef[threadIdx.x];
+// Flat axpy pass over Nf = (n+1) * pitch nodes.  pin: nbin x 2J per-block
+// dots of the previous pass; pass 0 starts the projections h, pass 1 adds.
+template <int J, bool NORM>
+__global__ void __launch_bounds__(AB) k_axpy_pass(size_t Nf, size_t stride, const double2* __restrict__ W,
+                                                  double2* __restrict__ Y, const double* __restrict__ pin,
+                                                  int nbin, double* __restrict__ pout, GmresState st,
+                                                  int pass) {
+  constexpr int NV = NORM ? 1 : 2 * J;
+  __shared__ double dsum[2 * J];
+  __shared__ double2 cf[J];
+  finish_sum_nt<AB>(pin, nbin, 2 * J, dsum);
+  if (threadIdx.x < J) {
+    const int i = threadIdx.x;
+    const double s = st.scale[i], cr = dsum[2 * i], ci = dsum[2 * i + 1];
+    cf[i] = make_double2(s * s * cr, s * s * ci);
+    if (blockIdx.x == 0) {
+      const double hr = pass == 0 ? 0.0 : st.hcol[2 * i], hi = pass == 0 ? 0.0 : st.hcol[2 * i + 1];
+      st.hcol[2 * i] = hr + s * cr;
+      st.hcol[2 * i + 1] = hi + s * ci;
+    }
+  }
   __syncthreads();
-  double acc[1] = {0};
-  MGC_NODE_LOOP(n, k, j) {
-    const size_t idx = (size_t)k * pitch + j;
-    double2 y = Y[idx];
+  double2 c[J];
+  MGC_JFOR(q) c[q] = cf[q];
+  double acc[NV];
 #pragma unroll
-    for (int q = 0; q < JMAX; ++q) {
-      if (q < J) {
-        double2 w = W[q * stride + idx], c = cf[q];
-        y.x -= c.x * w.x - c.y * w.y;
-        y.y -= c.x * w.y + c.y * w.x;
+  for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+  const size_t nt = (size_t)gridDim.x * AB;
+#pragma unroll 2
+  for (size_t i = (size_t)blockIdx.x * AB + threadIdx.x; i < Nf; i += nt) {
+    double2 w[J];
+    MGC_JFOR(q) w[q] = W[q * stride + i];
+    double2 y = Y[i];
+    MGC_JFOR(q) {
+      y.x -= c[q].x * w[q].x - c[q].y * w[q].y;
+      y.y -= c[q].x * w[q].y + c[q].y * w[q].x;
+    }
+    Y[i] = y;
+    if (NORM) {
+      acc[0] += y.x * y.x + y.y * y.y;
+    } else {
+      MGC_JFOR(q) {
+        acc[2 * q] += w[q].x * y.x + w[q].y * y.y;
+        acc[2 * q + 1] += w[q].x * y.y - w[q].y * y.x;
       }
     }
-    Y[idx] = y;
-    acc[0] += y.x * y.x + y.y * y.y;
   }
-  double tot[1];
-  block_sum<1>(acc, tot);
-  if (threadIdx.x == 0) part[flat_block()] = tot[0];
-  if (final_pass && last_block(ticket)) {
-    finish_sum(part, gridDim.x * gridDim.y, 1, st.nrm2);
-    gmres_step_blk(st, jcol, mrest, tol_abs);
+  double tot[NV];
+  block_sum<NV>(acc, tot);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) pout[(size_t)blockIdx.x * NV + q] = tot[q];
   }
+}
+#undef MGC_JFOR
+
+// ||Y||^2 from the final pass's partials, then column j of H and its rotation.
+__global__ void __launch_bounds__(256) k_gmres_step(const double* __restrict__ part, int nb, GmresState st,
+                                                    int j, int m, double tol_abs) {
+  finish_sum(part, nb, 1, st.nrm2);
+  gmres_step_blk(st, j, m, tol_abs);
 }
 
 // u += sum_q coef_q Z_q with Z stored in precision TZ.
@@ -1146,10 +1196,12 @@ __global__ void __launch_bounds__(256) k_weight(int n, int pitch, const double2*
   }
 }
 
-// Sum of per-block partials in fixed order: out[q] = sum_b part[b*nq + q].
+// Sum of per-block partials in fixed order: out[q] = sum_b part[b*nq + q];
+// out[0] also lands in copy_to (nullable).
 __global__ void __launch_bounds__(256) k_sum_partials(int nb, int nq, const double* __restrict__ part,
-                                                      double* __restrict__ out) {
+                                                      double* __restrict__ out, double* copy_to) {
   finish_sum(part, nb, nq, out);
+  if (copy_to && threadIdx.x == 0) *copy_to = out[0];
 }
 
 // ----------------------------------------------------------------------------
@@ -1361,7 +1413,10 @@ template <typename T, typename TU, typename TF, typename TO>
 void launch_stencil(hipStream_t s, const Level<T>& L, const void* u, const void* f, void* out,
                     int mode, double* part, Finish fin) {
   hipLaunchKernelGGL((k_stencil<T, TU, TF, TO>), stencil_grid(L.n), dim3(SX, SY), 0, s, L,
-                     (const v2<TU>*)u, (const v2<TF>*)f, (v2<TO>*)out, mode, part, fin);
+                     (const v2<TU>*)u, (const v2<TF>*)f, (v2<TO>*)out, mode, part);
+  if (part && fin.out)
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, stencil_blocks(L.n), 2, part, fin.out,
+                       fin.copy_to);
 }
 template void launch_stencil<double, double, double, double>(hipStream_t, const Level<double>&, const void*, const void*, void*, int, double*, Finish);
 template void launch_stencil<double, float, double, double>(hipStream_t, const Level<double>&, const void*, const void*, void*, int, double*, Finish);
@@ -1430,7 +1485,6 @@ void launch_cccs(hipStream_t s, const Level<T>& L, void* u, const void* f, const
   v2<T>* rhoA = (v2<T>*)w.rhoA;
   v2<T>* rhoB = (v2<T>*)w.rhoB;
   v2<T>* partC = (v2<T>*)w.partC;
-  v2<T>* coef = (v2<T>*)w.coef;
   v2<T>* gA = (v2<T>*)w.gA;
   v2<T>* gB = (v2<T>*)w.gB;
   v2<T>* YA = (v2<T>*)w.YA;
@@ -1445,17 +1499,23 @@ void launch_cccs(hipStream_t s, const Level<T>& L, void* u, const void* f, const
   MGC_CC_DISPATCH(k_cccs_project, dim3(nt, nt), dim3(64, 4), L, (const v2<T>*)u, (const v2<T>*)f,
                   fs, ch, partA, partB);
   hipLaunchKernelGGL((k_cccs_reduce<T>), dim3(nt), dim3(256), 0, s, n, nt, ch, (const v2<T>*)partA,
-                     (const v2<T>*)partB, rhoA, rhoB, partC, w.tickets, coef);
+                     (const v2<T>*)partB, rhoA, rhoB, partC);
   const int P = SA.P > SB.P ? SA.P : SB.P;
   // entries per lane: chains over M x M blocks, interface over 2M x 2M blocks
-#define MGC_CHAIN(NE, NEI, MCC, PDL, PDI)                                                       \
-  hipLaunchKernelGGL((k_cccs_chain<T, NE, NEI, MCC, PDL, PDI>), dim3(P, 2), dim3(64), 0, s, SA, SB, ch, n, \
-                     (const v2<T>*)rhoA, (const v2<T>*)rhoB, (const v2<T>*)coef, gA, gB, YA, YB,    \
-                     (v2<T>*)w.HA, (v2<T>*)w.HB, w.tickets + 1)
+#define MGC_CHAIN(NE, NEI, MCC, PDL, PDI)                                                          \
+  hipLaunchKernelGGL((k_cccs_chain<T, NE, NEI, MCC, PDL>), dim3(P, 2), dim3(64), 0, s, SA, SB, ch, n,     \
+                     (const v2<T>*)rhoA, (const v2<T>*)rhoB, (const v2<T>*)partC, nt, gA, gB,        \
+                     (v2<T>*)w.HA, (v2<T>*)w.HB);                                                    \
+  hipLaunchKernelGGL((k_cccs_interface<T, NEI, PDI>), dim3(1, 2), dim3(64), 0, s, SA, SB, YA, YB,    \
+                     (const v2<T>*)w.HA, (const v2<T>*)w.HB)
   // prefetch depth (chain steps in flight) traded against registers
-  if (MC <= 4) MGC_CHAIN(1, 2, 4, 4, 4);
-  else if (MC <= 8) MGC_CHAIN(1, 4, 8, 4, 4);
-  else MGC_CHAIN(4, 16, 16, 2, 1);
+  if (MC <= 4) {
+    MGC_CHAIN(1, 2, 4, 4, 4);
+  } else if (MC <= 8) {
+    MGC_CHAIN(1, 4, 8, 4, 4);
+  } else {
+    MGC_CHAIN(4, 16, 16, 2, 1);
+  }
 #undef MGC_CHAIN
   const int NM = (SA.N * SA.M > SB.N * SB.M) ? SA.N * SA.M : SB.N * SB.M;
   hipLaunchKernelGGL((k_cccs_retrieve<T>), dim3((NM + 255) / 256, 2), dim3(256), 0, s, SA, SB,
@@ -1485,25 +1545,75 @@ static inline int vec_blocks(int n) {
 }
 int launch_vec_blocks(int n) { return vec_blocks(n); }
 
-void launch_multidot(hipStream_t s, int n, int pitch, size_t stride, const double2* W, int J,
-                     const double2* Y, double* part, unsigned* ticket, const GmresState& st, int j,
-                     int pass) {
-  const dim3 nb = vec_grid(n);
-#define MGC_MD(JM) hipLaunchKernelGGL((k_multidot<JM>), nb, dim3(256), 0, s, n, pitch, stride, W, J, Y, part, ticket, st, j, pass)
-  if (J <= 8) MGC_MD(8);
-  else if (J <= 16) MGC_MD(16);
-  else MGC_MD(32);
-#undef MGC_MD
+// k_apply_dot grid: 64-column tiles in x, at most AX_BLOCKS blocks in all;
+// every thread walks `rows` consecutive rows.
+struct ApplyGrid { dim3 grid; int rows; };
+static inline ApplyGrid apply_dot_grid(int n) {
+  const int gx = (n - 1 + SX - 1) / SX;
+  int gy = (n - 1 + AD_SY * 8 - 1) / (AD_SY * 8);
+  const int cap = AX_BLOCKS / gx > 1 ? AX_BLOCKS / gx : 1;
+  if (gy > cap) gy = cap;
+  const int rows = (n - 1 + gy * AD_SY - 1) / (gy * AD_SY);
+  return {dim3(gx, gy), rows};
 }
-void launch_multiaxpy(hipStream_t s, int n, int pitch, size_t stride, const double2* W, int J,
-                      const double2* coef, double2* Y, double* part, unsigned* ticket,
-                      const GmresState& st, int j, int m, double tol_abs, int final_pass) {
-  const dim3 nb = vec_grid(n);
-#define MGC_MA(JM) hipLaunchKernelGGL((k_multiaxpy<JM>), nb, dim3(256), 0, s, n, pitch, stride, W, J, coef, Y, part, ticket, st, j, m, tol_abs, final_pass)
-  if (J <= 8) MGC_MA(8);
-  else if (J <= 16) MGC_MA(16);
-  else MGC_MA(32);
-#undef MGC_MA
+static inline int axpy_blocks(int n, int pitch) {
+  const size_t Nf = (size_t)(n + 1) * pitch;
+  size_t b = (Nf + (size_t)AB * 4 - 1) / ((size_t)AB * 4);
+  return (int)(b < 1 ? 1 : (b > AX_BLOCKS ? AX_BLOCKS : b));
+}
+
+// one instantiation per basis size J = 1 .. 16 (the library caps the restart
+// length at 16); other J launch nothing
+#define MGC_JSWITCH(M)                                                                      \
+  switch (J) {                                                                              \
+    case 1: M(1); break;   case 2: M(2); break;   case 3: M(3); break;   case 4: M(4); break; \
+    case 5: M(5); break;   case 6: M(6); break;   case 7: M(7); break;   case 8: M(8); break; \
+    case 9: M(9); break;   case 10: M(10); break; case 11: M(11); break; case 12: M(12); break; \
+    case 13: M(13); break; case 14: M(14); break; case 15: M(15); break; case 16: M(16); break; \
+    default: break;                                                                         \
+  }
+
+template <typename TZ>
+void launch_apply_dot(hipStream_t s, const Level<double>& L, const void* z, size_t stride,
+                      const double2* W, int J, double2* Y, double* part0) {
+  const ApplyGrid ag = apply_dot_grid(L.n);
+#define MGC_AD(JT)                                                                               \
+  hipLaunchKernelGGL((k_apply_dot<TZ, JT>), ag.grid, dim3(SX, AD_SY), 0, s, L, (const v2<TZ>*)z, W, \
+                     stride, Y, part0, ag.rows)
+  MGC_JSWITCH(MGC_AD)
+#undef MGC_AD
+}
+template void launch_apply_dot<double>(hipStream_t, const Level<double>&, const void*, size_t, const double2*,
+                                       int, double2*, double*);
+template void launch_apply_dot<float>(hipStream_t, const Level<double>&, const void*, size_t, const double2*,
+                                      int, double2*, double*);
+
+void launch_axpy_pass(hipStream_t s, int n, int pitch, size_t stride, const double2* W, int J,
+                      double2* Y, const double* part_in, double* part_out, const GmresState& st,
+                      int pass) {
+  const size_t Nf = (size_t)(n + 1) * pitch;
+  const int nb = axpy_blocks(n, pitch);
+  const int nbin = pass == 0 ? (int)(apply_dot_grid(n).grid.x * apply_dot_grid(n).grid.y) : nb;
+#define MGC_AXN(JT)                                                                                \
+  hipLaunchKernelGGL((k_axpy_pass<JT, true>), dim3(nb), dim3(AB), 0, s, Nf, stride, W, Y, part_in,   \
+                     nbin, part_out, st, pass)
+#define MGC_AXD(JT)                                                                                 \
+  hipLaunchKernelGGL((k_axpy_pass<JT, false>), dim3(nb), dim3(AB), 0, s, Nf, stride, W, Y, part_in,   \
+                     nbin, part_out, st, pass)
+  if (pass == 1) {
+    MGC_JSWITCH(MGC_AXN)
+  } else {
+    MGC_JSWITCH(MGC_AXD)
+  }
+#undef MGC_AXN
+#undef MGC_AXD
+}
+#undef MGC_JSWITCH
+
+void launch_gmres_step(hipStream_t s, int n, int pitch, const double* part2, const GmresState& st,
+                       int j, int m, double tol_abs) {
+  hipLaunchKernelGGL(k_gmres_step, dim3(1), dim3(256), 0, s, part2, axpy_blocks(n, pitch), st, j, m,
+                     tol_abs);
 }
 template <typename TZ>
 void launch_update(hipStream_t s, int n, int pitch, size_t stride, const void* Z, int J,
@@ -1530,7 +1640,7 @@ void launch_weight(hipStream_t s, int n, int pitch, const double2* w, int divide
   hipLaunchKernelGGL(k_weight, vec_grid(n), dim3(256), 0, s, n, pitch, w, divide, in, out);
 }
 void launch_sum_partials(hipStream_t s, int nb, int nq, const double* part, double* out) {
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, nb, nq, part, out);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, nb, nq, part, out, (double*)nullptr);
 }
 void launch_gmres_begin(hipStream_t s, const GmresState& st, int m) {
   hipLaunchKernelGGL(k_gmres_begin, dim3(1), dim3(1), 0, s, st, m);

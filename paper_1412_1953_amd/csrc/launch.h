@@ -11,8 +11,9 @@ constexpr int VEC_BLOCKS = 512;
 
 // Optional in-kernel completion of a stencil partial-sum reduction: the last
 // block sums the partials into out[0..1] and optionally copies out[0].
+// Optional second reduction stage after a stencil pass: out[0..1] = the
+// per-block partials added up, out[0] also copied to copy_to (nullable).
 struct Finish {
-  unsigned* ticket = nullptr;
   double* out = nullptr;
   double* copy_to = nullptr;
 };
@@ -24,8 +25,6 @@ struct CccsScratch {
   void* rhoA;    // [n+1][M]
   void* rhoB;    // [n+1][L]
   void* partC;   // [tiles][M][L]    coupling-coefficient partials
-  void* coef;    // [M][L]
-  unsigned* tickets;   // [3] last-block tickets (reduce, chain A, chain B)
   void* gA;      // [N][M]   local solutions
   void* gB;      // [N][L]
   void* YA;      // [P-1][2M] interface solution
@@ -38,9 +37,7 @@ struct CccsScratch {
 
 // Device-resident FGMRES bookkeeping (all pointers into the workspace).
 struct GmresState {
-  double* dots;    // [2*(m+1)]     raw multi-dot results
   double* hcol;    // [2*(m+1)]     accumulated projections of the current column
-  double2* axcoef; // [m+1]         multi-axpy coefficients
   double* nrm2;    // [1]           squared norm
   double* scale;   // [m+2]         1/||W_i|| of the unscaled basis
   double* H;       // [2*(m+1)*m]   Hessenberg, column-major, rotated in place
@@ -83,16 +80,21 @@ void launch_cccs(hipStream_t s, const Level<T>& L, void* u, const void* f, const
                  const ChanTab<T>& ch, const ChanSys<T>& SA, const ChanSys<T>& SB,
                  const CccsScratch& w);
 
-// multi-dot over W_0..W_{J-1}; the last block finishes the sums into st.dots
-// and updates the Hessenberg column j (CGS pass `pass`).
-void launch_multidot(hipStream_t s, int n, int pitch, size_t stride, const double2* W, int J,
-                     const double2* Y, double* part, unsigned* ticket, const GmresState& st, int j,
-                     int pass);
-// Y -= sum coef_q W_q; with final_pass the last block finishes ||Y||^2 and
-// performs the Givens step of column j.
-void launch_multiaxpy(hipStream_t s, int n, int pitch, size_t stride, const double2* W, int J,
-                      const double2* coef, double2* Y, double* part, unsigned* ticket,
-                      const GmresState& st, int j, int m, double tol_abs, int final_pass);
+// Arnoldi step j of FGMRES over the FP64 basis W_0..W_{J-1} (J = j+1 <= 16),
+// new vector Y = W_{j+1}; part0..part2 hold ARNOLDI_PART doubles each.
+//   apply_dot : Y = A z, per-block dots W^H Y                  -> part0
+//   axpy pass0: coefficients from part0, Y -= ..., dots W^H Y  -> part1
+//   axpy pass1: coefficients from part1, Y -= ..., ||Y||^2     -> part2
+//   gmres_step: ||Y|| from part2, Hessenberg column j, Givens rotation
+constexpr int ARNOLDI_PART = 256 * 32;
+template <typename TZ>
+void launch_apply_dot(hipStream_t s, const Level<double>& L, const void* z, size_t stride,
+                      const double2* W, int J, double2* Y, double* part0);
+void launch_axpy_pass(hipStream_t s, int n, int pitch, size_t stride, const double2* W, int J,
+                      double2* Y, const double* part_in, double* part_out, const GmresState& st,
+                      int pass);
+void launch_gmres_step(hipStream_t s, int n, int pitch, const double* part2, const GmresState& st,
+                       int j, int m, double tol_abs);
 template <typename TZ>
 void launch_update(hipStream_t s, int n, int pitch, size_t stride, const void* Z, int J,
                    const double2* coef, double2* u);

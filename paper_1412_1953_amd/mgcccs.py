@@ -115,7 +115,7 @@ class Grid:
     """One MG-CCCS handle with a torch-allocated workspace on a CUDA device."""
 
     def __init__(self, n, L, R0, theta, levels, M, Lch=None, omega=2.0 / 3.0, nu1=1, nu2=1,
-                 pc_gamma=0.0, pc_first_level=0, max_restart=20, fp32=True, device="cuda:0"):
+                 pc_gamma=0.0, pc_first_level=0, max_restart=16, fp32=True, device="cuda:0"):
         import torch
         self.torch = torch
         self.lib = load_library()
