@@ -27,7 +27,12 @@ sys.path.insert(0, ROOT)
 
 PC_GAMMA = math.radians(5.0)
 RESTART = 10
-HBM_PEAK_GBS = 8000.0
+HBM_PEAK_GBS = 8000.0                  # MI355X HBM3E, published
+# kernel classes of the library's event timer, by short name
+KCLASS = {"apply_dot": 1, "axpy": 2, "s1": 3, "s2": 4, "cccs_project": 5, "cccs_chain": 6}
+# the kernel whose roofline the line reports: the largest share of the step's
+# kernel time in the committed rocprofv3 summary
+ROOFLINE_KERNEL = "cccs_chain"
 
 
 def parse():
@@ -41,6 +46,9 @@ def parse():
     p.add_argument("--cpu-iters", type=int, default=6)
     p.add_argument("--energies", type=str, default="0.05,0.5,2.0",
                    help="subset of the workload energies (profiling runs)")
+    p.add_argument("--roofline-kernel", type=str, default=ROOFLINE_KERNEL, choices=sorted(KCLASS))
+    p.add_argument("--copy-probe", action="store_true",
+                   help="also run a plain device copy of known size (counter calibration)")
     return p.parse_args()
 
 
@@ -67,9 +75,13 @@ def run_step(problems, inner, torch, max_it):
     return out
 
 
-def time_steps(problems, inner, torch, steps, warmup, max_it):
+def time_steps(problems, inner, torch, steps, warmup, max_it, kclass=0):
+    """Seconds per step; with kclass, the library's HIP-event timer brackets
+    every launch of that kernel inside the timed steps (on its own stream)."""
     for _ in range(warmup):
         run_step(problems, inner, torch, max_it)
+    for g, *_ in problems:
+        g.set_kernel_timer(kclass)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = []
@@ -77,7 +89,43 @@ def time_steps(problems, inner, torch, steps, warmup, max_it):
         res = run_step(problems, inner, torch, max_it)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
-    return dt, res
+    ms = launches = nbytes = 0
+    for g, *_ in problems:
+        a, b, c = g.read_kernel_timer()
+        ms, launches, nbytes = ms + a, launches + b, nbytes + c
+        g.set_kernel_timer(0)
+    return dt, res, (ms, launches, nbytes)
+
+
+def traffic_from_profile(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when there is none or the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}.txt")
+    src = os.path.join(ROOT, "paper_1412_1953_amd", "csrc", "kernels.hip")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    with open(src, "rb") as fh:
+        sha = hashlib.sha256(fh.read()).hexdigest()
+    if fields.get("kernels.hip sha256") != sha or "traffic bytes per launch" not in fields:
+        return None
+    return float(fields["traffic bytes per launch"])
+
+
+def copy_probe(torch):
+    """A plain 256 MiB device-to-device copy, the reference for the byte
+    counters (read and write sizes known exactly)."""
+    src = torch.empty(1 << 28, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
 
 
 def cpu_baseline(w, iters, gpu_iters):
@@ -123,7 +171,11 @@ def main():
     problems = [make_problem(w, torch) for w in wls]
     unknowns = sum(w.unknowns for w in wls)
 
-    dt64, r64 = time_steps(problems, mgcccs.FP64, torch, a.steps, a.warmup, a.max_it)
+    if a.copy_probe:
+        copy_probe(torch)
+    kclass = KCLASS[a.roofline_kernel]
+    dt64, r64, (kms, kl, kb) = time_steps(problems, mgcccs.FP64, torch, a.steps, a.warmup, a.max_it,
+                                          kclass)
     line = {
         "metric": "solved unknowns/s to 1e-10 rel. residual, mixed vs FP64 MG-CCCS; HBM GB/s",
         "value": unknowns / dt64,
@@ -140,8 +192,16 @@ def main():
                  "status": [r.status for r in r64],
                  "vcycles_per_s": sum(r.vcycles for r in r64) / dt64},
     }
+    if kl > 0:
+        avg_s = kms * 1e-3 / kl
+        achieved = kb / kl / avg_s / 1e9
+        traffic = traffic_from_profile(a.roofline_kernel)
+        line["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                            "kernel": a.roofline_kernel, "launches": kl,
+                            "avg_us": avg_s * 1e6, "bytes_per_launch": kb / kl}
     if not a.no_mixed:
-        dt32, r32 = time_steps(problems, mgcccs.FP32, torch, a.steps, a.warmup, a.max_it)
+        dt32, r32, _ = time_steps(problems, mgcccs.FP32, torch, a.steps, a.warmup, a.max_it)
         line["mixed"] = {"value": unknowns / dt32, "ms_per_step": dt32 * 1e3,
                          "iters": [r.iters for r in r32], "relres": [r.relres for r in r32],
                          "status": [r.status for r in r32],

@@ -209,6 +209,33 @@ mgc_status mgc_cross_section_grad(mgc_grid g, const void* u, const void* chi, do
                                   const mgc_solve_opts* opts, void* v, double dsigma[3],
                                   double zeta[2], double* sigma, mgc_stats* stats);
 
+/* Kernel timing (measurement support; no effect on results).
+ * mgc_set_kernel_timer selects one kernel class.  While it is selected, every
+ * launch of that kernel inside the FGMRES restart cycles of mgc_solve and
+ * mgc_solve_transpose is bracketed by two HIP events recorded on the stream
+ * the kernel runs on (event nodes inside the captured restart graphs).  The
+ * durations, the launch count and the kernel's algorithmic bytes (compulsory
+ * loads and stores of its operands over the interior nodes) accumulate until
+ * mgc_read_kernel_timer, which returns and clears them.  MGC_KT_NONE turns
+ * timing off.  A new selection re-captures the restart graph.
+ * MGC_EINVAL for an unknown class, MGC_EHIP if events cannot be created.     */
+typedef enum {
+  MGC_KT_NONE = 0,
+  MGC_KT_APPLY_DOT = 1,      /* exact operator + basis dots, each Arnoldi step */
+  MGC_KT_AXPY = 2,           /* both orthogonalisation axpy passes            */
+  MGC_KT_S1 = 3,             /* finest level: smoothing, residual, restriction */
+  MGC_KT_S2 = 4,             /* finest level: prolongation, post-smoothing     */
+  MGC_KT_CCCS_PROJECT = 5,   /* CCCS residual + channel projections            */
+  MGC_KT_CCCS_CHAIN = 6      /* CCCS chunk-local channel solves                */
+} mgc_kernel_class;
+typedef struct {
+  double total_ms;           /* summed event durations                         */
+  long long launches;
+  double bytes;              /* summed algorithmic bytes                       */
+} mgc_kernel_timing;
+mgc_status mgc_set_kernel_timer(mgc_grid g, int kernel_class);
+mgc_status mgc_read_kernel_timer(mgc_grid g, mgc_kernel_timing* out);
+
 mgc_status mgc_destroy_grid(mgc_grid g);
 
 /* Thread-local description of the last error (never NULL).                  */

@@ -55,8 +55,22 @@ struct GraphCache {                       // one captured FGMRES restart cycle
   hipGraphExec_t exec = nullptr;
   const void* u = nullptr;
   const void* f = nullptr;
-  int m = 0, mm = 0, inner = -1;
+  int m = 0, mm = 0, inner = -1, kt = 0;
   double tol_abs = 0;
+  int kt_slots = 0;                        // timer slots recorded in the graph
+  std::vector<double> kt_bytes;
+};
+
+// Event timing of one kernel class (mgc_set_kernel_timer).  Slots are event
+// pairs handed out in launch order during one restart cycle's enqueue.
+struct KernelTimer {
+  static constexpr int SLOTS = 2 * MGC_MAX_RESTART + 8;
+  int which = MGC_KT_NONE;
+  hipEvent_t ev[2 * SLOTS] = {};
+  std::vector<double> bytes = std::vector<double>(SLOTS, 0.0);
+  int used = 0;
+  double ms = 0, total_bytes = 0;
+  long long launches = 0;
 };
 
 struct mgc_grid_s {
@@ -64,6 +78,7 @@ struct mgc_grid_s {
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;               // capture stream (default priority)
   GraphCache graph;
+  KernelTimer kt;
   int device = 0;
   bool failed = false;
   Axis exact;                              // level-0 axis of the physical operator
@@ -165,7 +180,7 @@ void layout(mgc_grid g) {
       c.partB = take((size_t)g->nchunksB * (n + 1) * Lc * e);
       c.rhoA = take((size_t)(n + 1) * M * e);
       c.rhoB = take((size_t)(n + 1) * Lc * e);
-      c.partC = take((size_t)g->nchunksB * M * Lc * e);
+      c.partC = take((size_t)launch_cccs_reduce_blocks(n) * M * Lc * e);
       c.gA = take((size_t)N * M * e);
       c.gB = take((size_t)N * Lc * e);
       c.YA = take((size_t)g->PA * 2 * M * e);
@@ -357,6 +372,46 @@ mgc_status check_ready(mgc_grid g, bool need_energy = true) {
 
 // --------------------------------------------------------------------------
 // V-cycle and CCCS drivers
+// Kernel timer hooks.  kt_slot hands out the next event pair for a launch of
+// class `kind` (-1: that class is not being timed); kt_mark records one end.
+int kt_slot(mgc_grid g, int kind, double bytes) {
+  KernelTimer& t = g->kt;
+  if (t.which == MGC_KT_NONE || t.which != kind || t.used >= KernelTimer::SLOTS) return -1;
+  t.bytes[t.used] = bytes;
+  return t.used++;
+}
+// While the stream is being captured the event becomes an explicit event
+// record node appended to the capture's current dependencies.
+void kt_mark(mgc_grid g, hipStream_t s, int slot, int end) {
+  if (slot < 0) return;
+  hipEvent_t ev = g->kt.ev[2 * slot + end];
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (!hip_ok(g, hipStreamIsCapturing(s, &cs), "timer: capture state")) return;
+  if (cs != hipStreamCaptureStatusActive) {
+    (void)hip_ok(g, hipEventRecord(ev, s), "timer: event record");
+    return;
+  }
+  hipGraph_t graph = nullptr;
+  const hipGraphNode_t* deps = nullptr;
+  size_t nd = 0;
+  if (!hip_ok(g, hipStreamGetCaptureInfo_v2(s, &cs, nullptr, &graph, &deps, &nd), "timer: capture info")) return;
+  hipGraphNode_t node;
+  if (!hip_ok(g, hipGraphAddEventRecordNode(&node, graph, deps, nd, ev), "timer: event node")) return;
+  (void)hip_ok(g, hipStreamUpdateCaptureDependencies(s, &node, 1, hipStreamSetCaptureDependencies),
+               "timer: capture dependencies");
+}
+// After the stream has synchronised: add up the first `slots` event pairs.
+void kt_harvest(mgc_grid g, int slots, const std::vector<double>& bytes) {
+  KernelTimer& t = g->kt;
+  for (int i = 0; i < slots; ++i) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, t.ev[2 * i], t.ev[2 * i + 1]) != hipSuccess) continue;
+    t.ms += ms;
+    t.total_bytes += bytes[i];
+    ++t.launches;
+  }
+}
+
 template <typename T>
 void vcycle_level(mgc_grid g, int l, void* u, const void* f, bool zero_guess, const double* fs = nullptr) {
   const int p = sizeof(T) == 8 ? P64 : P32;
@@ -371,9 +426,17 @@ void vcycle_level(mgc_grid g, int l, void* u, const void* f, bool zero_guess, co
   const double om = g->d.omega;
   if (zero_guess && g->d.nu1 == 1 && g->d.nu2 == 1) {
     // fused passes: u' = omega f/d is recomputed, never stored
+    const double Nf = (double)(L.n - 1) * (L.n - 1), Nc = (double)(L.n / 2 - 1) * (L.n / 2 - 1);
+    const double e = (double)sizeof(v2<T>);
+    int ts = l == 0 ? kt_slot(g, MGC_KT_S1, (Nf + Nc) * e) : -1;   // f in, f_c out
+    kt_mark(g, s, ts, 0);
     launch_s1_zero<T>(s, L, f, fs, om, g->ws + LC.ff[p], LC.pitch);
+    kt_mark(g, s, ts, 1);
     vcycle_level<T>(g, l + 1, g->ws + LC.fu[p], g->ws + LC.ff[p], true);
+    ts = l == 0 ? kt_slot(g, MGC_KT_S2, (2 * Nf + Nc) * e) : -1;    // f, e_c in, u out
+    kt_mark(g, s, ts, 0);
     launch_s2_zero<T>(s, L, f, fs, om, g->ws + LC.fu[p], LC.pitch, u);
+    kt_mark(g, s, ts, 1);
     return;
   }
   void* bufs[2] = {u, g->ws + LI.ft[p]};
@@ -398,8 +461,29 @@ void vcycle_level(mgc_grid g, int l, void* u, const void* f, bool zero_guess, co
 template <typename T> void cccs_apply(mgc_grid g, void* u, const void* f, const double* fs = nullptr) {
   if (g->d.M == 0 && g->d.Lch == 0) return;
   const int p = sizeof(T) == 8 ? P64 : P32;
+  // timed kernel: projection (reads u, f; writes rho^A, rho^B) or chunk chains
+  // (per system of Mc channels: G_t read in both sweeps, rho read, g written
+  // and re-read in each sweep)
+  const int n = g->d.n, M = g->d.M, Lc = g->d.Lch;
+  const double e = (double)sizeof(v2<T>), N1 = n - 1;
+  int kind = 0, slot = -1;
+  if (g->kt.which == MGC_KT_CCCS_PROJECT) {
+    kind = 1;
+    slot = kt_slot(g, MGC_KT_CCCS_PROJECT, (2 * N1 * N1 + N1 * (M + Lc)) * e);
+  } else if (g->kt.which == MGC_KT_CCCS_CHAIN) {
+    kind = 2;
+    slot = kt_slot(g, MGC_KT_CCCS_CHAIN, ((2.0 * M * M + 4.0 * M) + (2.0 * Lc * Lc + 4.0 * Lc)) * N1 * e);
+  }
+  struct Ctx { mgc_grid g; int slot; } ctx{g, slot};
+  MarkHook hook;
+  hook.fn = [](void* c, hipStream_t s, int end) {
+    const Ctx* x = static_cast<const Ctx*>(c);
+    kt_mark(x->g, s, x->slot, end);
+  };
+  hook.ctx = &ctx;
+  hook.kind = slot >= 0 ? kind : 0;
   launch_cccs<T>(g->stream, level_of<T>(g, 0), u, f, fs, chan_of<T>(g), sys_of<T>(g, true),
-                 sys_of<T>(g, false), scratch_of(g, p));
+                 sys_of<T>(g, false), scratch_of(g, p), &hook);
 }
 
 // One MG-CCCS cycle.  fs (nullable device scalar) scales f; the fused
@@ -524,24 +608,35 @@ void enqueue_fgmres_cycle(mgc_grid g, void* u, const mgc_solve_opts* o, double t
   Level<double> EX = exact_level(g);
   hipStream_t saved = g->stream;
   g->stream = st;                           // the cycle drivers launch on g->stream
+  g->kt.used = 0;
+  const double Nint = (double)(n - 1) * (n - 1);
   launch_gmres_begin(st, gs, m);
   for (int j = 0; j < mm; ++j) {
     double2* Wj = W + (size_t)j * stride64;
     double2* Wn = W + (size_t)(j + 1) * stride64;
     char* Zj = Z + (size_t)j * fbz;
     // preconditioner on the normalised basis vector v_j = s_j W_j
+    // algorithmic bytes: z (inner precision), J basis vectors, Y written
+    const int ta = kt_slot(g, MGC_KT_APPLY_DOT, Nint * ((f32 ? 8.0 : 16.0) + 16.0 * (j + 1) + 16.0));
     if (f32) {
       launch_scale_copy<double, float>(st, n, pitch, pitch, Wj, gs.scale + j, g->ws + g->f32);
       mgcccs_cycle<float>(g, Zj, g->ws + g->f32, true);
+      kt_mark(g, st, ta, 0);
       launch_apply_dot<float>(st, EX, Zj, stride64, W, j + 1, Wn, p0);
     } else {
       mgcccs_cycle<double>(g, Zj, Wj, true, gs.scale + j);
+      kt_mark(g, st, ta, 0);
       launch_apply_dot<double>(st, EX, Zj, stride64, W, j + 1, Wn, p0);
     }
+    kt_mark(g, st, ta, 1);
     // classical Gram-Schmidt with one re-orthogonalisation, then the
     // Hessenberg column and its Givens rotation on the device
-    launch_axpy_pass(st, n, pitch, stride64, W, j + 1, Wn, p0, p1, gs, 0);
-    launch_axpy_pass(st, n, pitch, stride64, W, j + 1, Wn, p1, p2, gs, 1);
+    for (int pass = 0; pass < 2; ++pass) {
+      const int tx = kt_slot(g, MGC_KT_AXPY, Nint * (16.0 * (j + 1) + 32.0));  // J in, Y in and out
+      kt_mark(g, st, tx, 0);
+      launch_axpy_pass(st, n, pitch, stride64, W, j + 1, Wn, pass ? p1 : p0, pass ? p2 : p1, gs, pass);
+      kt_mark(g, st, tx, 1);
+    }
     launch_gmres_step(st, n, pitch, p2, gs, j, m, tol_abs);
   }
   launch_gmres_solve(st, gs, m, mm);
@@ -586,26 +681,36 @@ mgc_status solve_fgmres(mgc_grid g, void* u, const void* f, const mgc_solve_opts
     if (use_graph) {
       GraphCache& gc = g->graph;
       if (!gc.exec || gc.u != u || gc.f != f || gc.m != m || gc.mm != mm || gc.inner != (int)o->inner ||
-          gc.tol_abs != o->tol * fn) {
+          gc.tol_abs != o->tol * fn || gc.kt != g->kt.which) {
         if (gc.exec) { (void)hipGraphExecDestroy(gc.exec); gc.exec = nullptr; }
         hipGraph_t graph;
         HIPCHK(g, hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal));
         enqueue_fgmres_cycle(g, u, o, o->tol * fn, mm, g->cap);
         HIPCHK(g, hipStreamEndCapture(g->cap, &graph));
+        if (g->failed) {                   // a timer node could not be added
+          (void)hipGraphDestroy(graph);
+          return MGC_EHIP;
+        }
         hipError_t e = hipGraphInstantiate(&gc.exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         HIPCHK(g, e);
         gc.u = u; gc.f = f; gc.m = m; gc.mm = mm; gc.inner = (int)o->inner; gc.tol_abs = o->tol * fn;
+        gc.kt = g->kt.which;
+        gc.kt_slots = g->kt.used;
+        gc.kt_bytes = g->kt.bytes;
       }
       HIPCHK(g, hipGraphLaunch(gc.exec, s));
     } else {
       enqueue_fgmres_cycle(g, u, o, o->tol * fn, mm, s);
+      if (g->failed) return MGC_EHIP;
     }
+    const int kt_slots = use_graph ? g->graph.kt_slots : g->kt.used;
     rc = exact_residual(g, u, f, W, &rr, &ff, gs.nrm2);
     if (rc) return rc;
     int kused = mm;
     HIPCHK(g, hipMemcpyAsync(&kused, gs.kused, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(g, hipStreamSynchronize(s));
+    if (kt_slots > 0) kt_harvest(g, kt_slots, use_graph ? g->graph.kt_bytes : g->kt.bytes);
     it += std::min(kused, mm);
     rel = std::sqrt(rr) / fn;
     record(st, ++rs, rel);
@@ -1141,9 +1246,39 @@ mgc_status mgc_cross_section_grad(mgc_grid g, const void* u, const void* chi, do
   return solve_rc;
 }
 
+mgc_status mgc_set_kernel_timer(mgc_grid g, int kernel_class) {
+  if (!g) return fail(MGC_EINVAL, "null handle");
+  if (kernel_class < MGC_KT_NONE || kernel_class > MGC_KT_CCCS_CHAIN)
+    return fail(MGC_EINVAL, "unknown kernel class");
+  KernelTimer& t = g->kt;
+  if (kernel_class != MGC_KT_NONE && !t.ev[0]) {
+    for (int i = 0; i < 2 * KernelTimer::SLOTS; ++i) HIPCHK(g, hipEventCreate(&t.ev[i]));
+  }
+  t.which = kernel_class;
+  t.used = 0;
+  t.ms = 0;
+  t.total_bytes = 0;
+  t.launches = 0;
+  return MGC_OK;
+}
+
+mgc_status mgc_read_kernel_timer(mgc_grid g, mgc_kernel_timing* out) {
+  if (!g || !out) return fail(MGC_EINVAL, "null argument");
+  KernelTimer& t = g->kt;
+  out->total_ms = t.ms;
+  out->launches = t.launches;
+  out->bytes = t.total_bytes;
+  t.ms = 0;
+  t.total_bytes = 0;
+  t.launches = 0;
+  return MGC_OK;
+}
+
 mgc_status mgc_destroy_grid(mgc_grid g) {
   if (!g) return fail(MGC_EINVAL, "null handle");
   if (g->graph.exec) (void)hipGraphExecDestroy(g->graph.exec);
+  for (hipEvent_t e : g->kt.ev)
+    if (e) (void)hipEventDestroy(e);
   if (g->cap) (void)hipStreamDestroy(g->cap);
   delete g;
   return MGC_OK;

@@ -557,50 +557,67 @@ __global__ void __launch_bounds__(256) k_cccs_project(Level<T> L, const v2<T>* _
 }
 
 // Step 2: rho^A, rho^B from the tile partials (fixed order) and per-block
-// partial sums over 64 rows of the coupling coefficients
+// partial sums over RB rows of the coupling coefficients
 // c[i][l] = sum_k w_k varphi_l(k) rho^A[k][i] (eq. coefficients); the chain
-// kernel adds up the blocks.
+// kernel adds up the blocks.  Each (row, channel) sum is one thread's; the
+// coupling partials use every thread (pairs x row groups, combined in order).
+constexpr int RB = 32;
 template <typename T>
 __global__ void __launch_bounds__(256) k_cccs_reduce(int n, int ntiles, ChanTab<T> ch,
                                                      const v2<T>* __restrict__ partA,
                                                      const v2<T>* __restrict__ partB,
                                                      v2<T>* __restrict__ rhoA, v2<T>* __restrict__ rhoB,
                                                      v2<T>* __restrict__ partC) {
-  __shared__ v2<T> ra[PT][16];
+  __shared__ v2<T> ra[RB][16], wv[RB][16];
+  __shared__ double pcr[256], pci[256];
   const int M = ch.M, Lc = ch.L, tid = threadIdx.x;
-  const int kb = 1 + blockIdx.x * PT;
-  for (int idx = tid; idx < PT * 16; idx += 256) {
-    const int r = idx / 16, i = idx % 16, k = kb + r;
-    v2<T> sa = mk<T>(0, 0), sb = mk<T>(0, 0);
+  const int kb = 1 + blockIdx.x * RB;
+  for (int idx = tid; idx < RB * 16; idx += 256) {
+    const int r = idx >> 4, i = idx & 15, k = kb + r;
+    v2<T> sa = mk<T>(0, 0), sb = mk<T>(0, 0), w = mk<T>(0, 0);
     if (k < n) {
       if (i < M) {
-#pragma unroll 8
+#pragma unroll 16
         for (int t = 0; t < ntiles; ++t) sa = cadd(sa, partA[((size_t)t * (n + 1) + k) * M + i]);
         rhoA[(size_t)k * M + i] = sa;
       }
       if (i < Lc) {
-#pragma unroll 8
+#pragma unroll 16
         for (int t = 0; t < ntiles; ++t) sb = cadd(sb, partB[((size_t)t * (n + 1) + k) * Lc + i]);
         rhoB[(size_t)k * Lc + i] = sb;
+        w = ch.wvphi[(size_t)i * (n + 1) + k];
       }
     }
     ra[r][i] = sa;
+    wv[r][i] = w;
   }
   __syncthreads();
   const int P = M * Lc;                      // <= 256 pairs
-  if (tid < P) {
-    const int i = tid / Lc, l = tid % Lc;
+  const int G = 256 / P;                     // row groups per pair
+  const int pair = tid % P, grp = tid / P;
+  if (grp < G) {
+    const int i = pair / Lc, l = pair % Lc;
+    const int rmax = min(RB, n - kb);
     double xr = 0, xi = 0;
-    const int rmax = min(PT, n - kb);
-#pragma unroll 8
-    for (int r = 0; r < rmax; ++r) {
-      v2<T> a = ch.wvphi[(size_t)l * (n + 1) + kb + r], b = ra[r][i];
+    for (int r = grp; r < rmax; r += G) {
+      const v2<T> a = wv[r][l], b = ra[r][i];
       xr += (double)a.x * b.x - (double)a.y * b.y;
       xi += (double)a.x * b.y + (double)a.y * b.x;
+    }
+    pcr[grp * P + pair] = xr;
+    pci[grp * P + pair] = xi;
+  }
+  __syncthreads();
+  if (tid < P) {
+    double xr = 0, xi = 0;
+    for (int q = 0; q < G; ++q) {
+      xr += pcr[q * P + tid];
+      xi += pci[q * P + tid];
     }
     partC[(size_t)blockIdx.x * P + tid] = mk<T>((T)xr, (T)xi);
   }
 }
+int launch_cccs_reduce_blocks(int n) { return (n - 1 + RB - 1) / RB; }
 
 // Wave-level mat-vec for the chains.  Lane = (row i, part): g = 2^gsh lanes
 // share a row, the lane holds the NE matrix entries A[i][part + g e] and the
@@ -662,7 +679,7 @@ template <typename T, int NE, int NEI, int MC, int PDL>
 __global__ void __launch_bounds__(64) k_cccs_chain(ChanSys<T> SA, ChanSys<T> SB, ChanTab<T> ch,
                                                    int n, const v2<T>* __restrict__ rhoA,
                                                    const v2<T>* __restrict__ rhoB,
-                                                   const v2<T>* __restrict__ partC, int ntiles,
+                                                   const v2<T>* __restrict__ partC, int nparts,
                                                    v2<T>* __restrict__ gA, v2<T>* __restrict__ gB,
                                                    v2<T>* __restrict__ HA, v2<T>* __restrict__ HB) {
   const bool isA = blockIdx.y == 0;
@@ -680,7 +697,8 @@ __global__ void __launch_bounds__(64) k_cccs_chain(ChanSys<T> SA, ChanSys<T> SB,
   const int npair = ch.M * ch.L;
   for (int idx = lane; idx < npair; idx += 64) {
     double xr = 0, xi = 0;
-    for (int b = 0; b < ntiles; ++b) {
+#pragma unroll 8
+    for (int b = 0; b < nparts; ++b) {
       const v2<T> c = partC[(size_t)b * npair + idx];
       xr += c.x;
       xi += c.y;
@@ -1477,7 +1495,10 @@ MGC_INST_LEVEL(float)
 template <typename T>
 void launch_cccs(hipStream_t s, const Level<T>& L, void* u, const void* f, const double* fs,
                  const ChanTab<T>& ch, const ChanSys<T>& SA, const ChanSys<T>& SB,
-                 const CccsScratch& w) {
+                 const CccsScratch& w, const MarkHook* hook) {
+  auto mark = [&](int kind, int end) {
+    if (hook && hook->fn && hook->kind == kind) hook->fn(hook->ctx, s, end);
+  };
   const int n = L.n;
   const int MC = ch.M > ch.L ? ch.M : ch.L;
   v2<T>* partA = (v2<T>*)w.partA;
@@ -1496,16 +1517,21 @@ void launch_cccs(hipStream_t s, const Level<T>& L, void* u, const void* f, const
   if (MC <= 4) hipLaunchKernelGGL((KERNEL<T, 4>), GRID, BLOCK, 0, s, __VA_ARGS__);      \
   else if (MC <= 8) hipLaunchKernelGGL((KERNEL<T, 8>), GRID, BLOCK, 0, s, __VA_ARGS__); \
   else hipLaunchKernelGGL((KERNEL<T, 16>), GRID, BLOCK, 0, s, __VA_ARGS__);
+  mark(1, 0);
   MGC_CC_DISPATCH(k_cccs_project, dim3(nt, nt), dim3(64, 4), L, (const v2<T>*)u, (const v2<T>*)f,
                   fs, ch, partA, partB);
-  hipLaunchKernelGGL((k_cccs_reduce<T>), dim3(nt), dim3(256), 0, s, n, nt, ch, (const v2<T>*)partA,
+  mark(1, 1);
+  const int nrb = launch_cccs_reduce_blocks(n);
+  hipLaunchKernelGGL((k_cccs_reduce<T>), dim3(nrb), dim3(256), 0, s, n, nt, ch, (const v2<T>*)partA,
                      (const v2<T>*)partB, rhoA, rhoB, partC);
   const int P = SA.P > SB.P ? SA.P : SB.P;
   // entries per lane: chains over M x M blocks, interface over 2M x 2M blocks
 #define MGC_CHAIN(NE, NEI, MCC, PDL, PDI)                                                          \
+  mark(2, 0);                                                                                        \
   hipLaunchKernelGGL((k_cccs_chain<T, NE, NEI, MCC, PDL>), dim3(P, 2), dim3(64), 0, s, SA, SB, ch, n,     \
-                     (const v2<T>*)rhoA, (const v2<T>*)rhoB, (const v2<T>*)partC, nt, gA, gB,        \
+                     (const v2<T>*)rhoA, (const v2<T>*)rhoB, (const v2<T>*)partC, nrb, gA, gB,       \
                      (v2<T>*)w.HA, (v2<T>*)w.HB);                                                    \
+  mark(2, 1);                                                                                        \
   hipLaunchKernelGGL((k_cccs_interface<T, NEI, PDI>), dim3(1, 2), dim3(64), 0, s, SA, SB, YA, YB,    \
                      (const v2<T>*)w.HA, (const v2<T>*)w.HB)
   // prefetch depth (chain steps in flight) traded against registers
@@ -1526,10 +1552,10 @@ void launch_cccs(hipStream_t s, const Level<T>& L, void* u, const void* f, const
 }
 template void launch_cccs<double>(hipStream_t, const Level<double>&, void*, const void*, const double*,
                                   const ChanTab<double>&, const ChanSys<double>&, const ChanSys<double>&,
-                                  const CccsScratch&);
+                                  const CccsScratch&, const MarkHook*);
 template void launch_cccs<float>(hipStream_t, const Level<float>&, void*, const void*, const double*,
                                  const ChanTab<float>&, const ChanSys<float>&, const ChanSys<float>&,
-                                 const CccsScratch&);
+                                 const CccsScratch&, const MarkHook*);
 
 static inline dim3 vec_grid(int n) {
   const int gx = (n - 1 + 63) / 64;

@@ -75,10 +75,18 @@ void launch_s1_zero(hipStream_t s, const Level<T>& L, const void* f, const doubl
 template <typename T>
 void launch_s2_zero(hipStream_t s, const Level<T>& L, const void* f, const double* fs, double omega,
                     const void* ec, int pitch_c, void* u);
+int launch_cccs_reduce_blocks(int n);   // blocks of coupling-coefficient partials
+// Timing hook around one kernel of a multi-kernel launcher: fn(ctx, s, 0)
+// before and fn(ctx, s, 1) after the kernel selected by kind.
+struct MarkHook {
+  void (*fn)(void* ctx, hipStream_t s, int end) = nullptr;
+  void* ctx = nullptr;
+  int kind = 0;                    // launch_cccs: 1 projection pass, 2 chunk chains
+};
 template <typename T>
 void launch_cccs(hipStream_t s, const Level<T>& L, void* u, const void* f, const double* fs,
                  const ChanTab<T>& ch, const ChanSys<T>& SA, const ChanSys<T>& SB,
-                 const CccsScratch& w);
+                 const CccsScratch& w, const MarkHook* hook = nullptr);
 
 // Arnoldi step j of FGMRES over the FP64 basis W_0..W_{J-1} (J = j+1 <= 16),
 // new vector Y = W_{j+1}; part0..part2 hold ARNOLDI_PART doubles each.

@@ -24,7 +24,11 @@ STATIONARY, IR, FGMRES = 0, 1, 2
 EXPORTED = ["mgc_create_grid", "mgc_workspace_bytes", "mgc_bind_workspace", "mgc_field_pitch",
             "mgc_set_potential", "mgc_set_energy", "mgc_build_rhs_tp", "mgc_residual", "mgc_vcycle",
             "mgc_cccs", "mgc_solve", "mgc_solve_transpose", "mgc_cross_section",
-            "mgc_cross_section_grad", "mgc_destroy_grid", "mgc_last_error"]
+            "mgc_cross_section_grad", "mgc_set_kernel_timer", "mgc_read_kernel_timer",
+            "mgc_destroy_grid", "mgc_last_error"]
+
+# kernel classes of mgc_set_kernel_timer
+KT_NONE, KT_APPLY_DOT, KT_AXPY, KT_S1, KT_S2, KT_CCCS_PROJECT, KT_CCCS_CHAIN = range(7)
 
 
 class GridDesc(ctypes.Structure):
@@ -38,6 +42,11 @@ class GridDesc(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("outer", ctypes.c_int), ("inner", ctypes.c_int), ("restart", ctypes.c_int),
                 ("max_it", ctypes.c_int), ("inner_cycles", ctypes.c_int), ("tol", ctypes.c_double)]
+
+
+class KernelTiming(ctypes.Structure):
+    _fields_ = [("total_ms", ctypes.c_double), ("launches", ctypes.c_longlong),
+                ("bytes", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -76,6 +85,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mgc_cross_section_grad": [vp, vp, vp, d, d, ctypes.POINTER(SolveOpts), vp,
                                    ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(d),
                                    ctypes.POINTER(Stats)],
+        "mgc_set_kernel_timer": [vp, i],
+        "mgc_read_kernel_timer": [vp, ctypes.POINTER(KernelTiming)],
         "mgc_destroy_grid": [vp],
     }
     for name, args in sig.items():
@@ -232,6 +243,16 @@ class Grid:
         res = SolveResult(rc, st.iters, st.vcycles, st.relres,
                           [hist[i] for i in range(st.hist_len)], st.t_setup_ms, st.t_solve_ms)
         return [ds[0], ds[1], ds[2]], complex(z[0], z[1]), sig.value, res
+
+    def set_kernel_timer(self, kernel_class: int):
+        """Time every launch of one kernel class inside FGMRES solves (KT_*)."""
+        _check(self.lib.mgc_set_kernel_timer(self.h, kernel_class))
+
+    def read_kernel_timer(self):
+        """(total ms, launches, algorithmic bytes) since the last read; clears."""
+        t = KernelTiming()
+        _check(self.lib.mgc_read_kernel_timer(self.h, ctypes.byref(t)))
+        return t.total_ms, t.launches, t.bytes
 
     def cross_section(self, u, chi, k1, k2):
         z = (ctypes.c_double * 2)()

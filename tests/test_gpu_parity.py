@@ -219,3 +219,50 @@ def test_graph_replays_match_eager_launches(monkeypatch):
         g.solve(ut, ft, outer=mgcccs.FGMRES, restart=10, max_it=40, tol=1e-300)
         outs[mode] = to_np(ut)
     assert np.array_equal(outs["eager"], outs["graph"])
+
+
+@pytest.mark.parametrize("graph", [True, False], ids=["graph", "eager"])
+@pytest.mark.parametrize("kclass", [1, 2, 3, 4, 5, 6], ids=["apply", "axpy", "s1", "s2", "project", "chain"])
+def test_kernel_timer_counts_launches_and_leaves_results_unchanged(kclass, graph, monkeypatch):
+    """Event timing of one kernel class: one event pair per launch (FGMRES
+    steps: apply 1, axpy 2, finest S1/S2 1, CCCS projection/chain 1), the
+    algorithmic byte count of each class (FP64 inner cycle), and a
+    bitwise-identical iterate."""
+    from paper_1412_1953_amd import mgcccs
+    if graph:
+        monkeypatch.delenv("MGC_NO_GRAPH", raising=False)
+    else:
+        monkeypatch.setenv("MGC_NO_GRAPH", "1")
+    c = Case(64, 20.0, 0.3, 4, 4, pc_gamma=GAM)
+    g = c.grid()
+    o = c.oracle()
+    chi = tp_rhs(o.g, c.Z1, c.Z2, c.lam, c.E)
+    its = 23                                   # restart cycles of 10, 10, 3 steps
+    u_ref, f = g.from_numpy(c.u0()), g.from_numpy(chi)
+    g.solve(u_ref, f, outer=mgcccs.FGMRES, restart=10, max_it=its, tol=1e-300)
+    g.set_kernel_timer(kclass)
+    u = g.from_numpy(c.u0())
+    r = g.solve(u, f, outer=mgcccs.FGMRES, restart=10, max_it=its, tol=1e-300)
+    ms, launches, nbytes = g.read_kernel_timer()
+    g.set_kernel_timer(mgcccs.KT_NONE)
+    assert r.iters == its
+    assert np.array_equal(to_np(u), to_np(u_ref))
+    per_step = 2 if kclass == mgcccs.KT_AXPY else 1
+    assert launches == per_step * its
+    assert ms > 0
+    n, N = c.n, (c.n - 1) ** 2
+    steps = [j for cyc in (10, 10, 3) for j in range(cyc)]
+    if kclass == mgcccs.KT_APPLY_DOT:
+        want = sum(N * (16 + 16 * (j + 1) + 16) for j in steps)
+    elif kclass == mgcccs.KT_AXPY:
+        want = 2 * sum(N * (16 * (j + 1) + 32) for j in steps)
+    elif kclass == mgcccs.KT_S1:
+        want = its * (N + (n // 2 - 1) ** 2) * 16
+    elif kclass == mgcccs.KT_S2:
+        want = its * (2 * N + (n // 2 - 1) ** 2) * 16
+    elif kclass == mgcccs.KT_CCCS_PROJECT:
+        want = its * (2 * N + (n - 1) * (c.M + c.M)) * 16
+    else:
+        want = its * 2 * (2 * c.M ** 2 + 4 * c.M) * (n - 1) * 16
+    assert nbytes == pytest.approx(want, rel=1e-12)
+    assert g.read_kernel_timer() == (0.0, 0, 0.0)
