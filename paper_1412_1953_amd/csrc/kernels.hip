@@ -619,54 +619,93 @@ __global__ void __launch_bounds__(256) k_cccs_reduce(int n, int ntiles, ChanTab<
 }
 int launch_cccs_reduce_blocks(int n) { return (n - 1 + RB - 1) / RB; }
 
-// Wave-level mat-vec for the chains.  Lane = (row i, part): g = 2^gsh lanes
-// share a row, the lane holds the NE matrix entries A[i][part + g e] and the
-// matching vector entries in registers.  A vector y distributed by rows (every
-// lane of row group m holds y[m]) is gathered with one bpermute per entry; no
-// LDS and no barrier are involved.
-template <typename T, int NE>
-__device__ __forceinline__ void load_row(v2<T> (&a)[NE], const v2<T>* A, int R, int gsh) {
-  const int lane = threadIdx.x & 63, g = 1 << gsh, i = lane >> gsh, part = lane & (g - 1);
+// Block recurrences of the channel solves, one wave per recurrence.  A step
+// is a small mat-vec y = A_q x with A_q an Mr x Mr block (Mr <= MC) and x the
+// previous step's result.  Lane = (group, row), MC lanes per group, NG =
+// 64 / MC groups: the lane of row i holds row i of A_q in registers and reads
+// x from LDS as a broadcast, so a step costs one LDS round trip and no
+// shuffles.  Step q belongs to group q mod NG, and a round is NG consecutive
+// steps.  Each lane keeps NSET register sets, one per round in flight: the
+// steps of round r read set r mod NSET only, and the set is refilled (all
+// lanes, one batch) when its round ends, for round r + NSET.  With NSET = 3 a
+// matrix row is requested two rounds before its step and no set is read
+// while a load into it is still pending (NSET = 1 where three sets of wide
+// rows would not fit in registers).  LDS rows zs[l][0..MC) are zero beyond Mr.
+template <typename T, int MC> struct StepRow {
+  v2<T> a[MC];
+  v2<T> c;
+};
+
+// Row `row` of block idx of A (Mr x Mr, row-major) and the step scalar
+// cv[idx] (HASC).  Addresses are clamped instead of masked, so that no value
+// is selected right after its load (which would force an early wait): rows
+// beyond Mr repeat row Mr-1 (their results are never stored) and columns
+// beyond Mr repeat column Mr-1 (they meet zero vector entries).
+template <typename T, int MC, bool HASC>
+__device__ __forceinline__ void load_step(StepRow<T, MC>& r, const v2<T>* __restrict__ A, int Mr, int row,
+                                          const v2<T>* __restrict__ cv, int idx) {
+  const int rr = row < Mr ? row : Mr - 1;
+  const v2<T>* Ar = A + ((size_t)idx * Mr + rr) * Mr;
 #pragma unroll
-  for (int e = 0; e < NE; ++e) {
-    const int m = part + g * e;
-    a[e] = (i < R && m < R) ? A[i * R + m] : mk<T>(0, 0);
-  }
-}
-// x[e] = y[part + g e] (zero beyond R); y[m] lives in lane m << ysh, offset yo
-template <typename T, int NE>
-__device__ __forceinline__ void gather(v2<T> (&x)[NE], v2<T> y, int R, int gsh, int ysh, int lo_m,
-                                       int hi_m) {
-  const int lane = threadIdx.x & 63, g = 1 << gsh, part = lane & (g - 1);
-#pragma unroll
-  for (int e = 0; e < NE; ++e) {
-    const int m = part + g * e;
-    const bool in = m < R && m >= lo_m && m < hi_m;
-    const int src = (in ? m - lo_m : 0) << ysh;
-    const T xr = __shfl(y.x, src, 64), xi = __shfl(y.y, src, 64);
-    x[e] = in ? mk<T>(xr, xi) : mk<T>(0, 0);
-  }
-}
-template <typename T, int NE>
-__device__ __forceinline__ v2<T> rowsum(const v2<T> (&a)[NE], const v2<T> (&x)[NE], int gsh) {
-  T sr = 0, si = 0;
-#pragma unroll
-  for (int e = 0; e < NE; ++e) {
-    sr += a[e].x * x[e].x - a[e].y * x[e].y;
-    si += a[e].x * x[e].y + a[e].y * x[e].x;
-  }
-  for (int s = 1; s < (1 << gsh); s <<= 1) { sr += shfl_xor_t(sr, s); si += shfl_xor_t(si, s); }
-  return mk<T>(sr, si);
+  for (int m = 0; m < MC; ++m) r.a[m] = Ar[m < Mr ? m : Mr - 1];
+  if (HASC) r.c = cv[idx];
 }
 
-__device__ __forceinline__ int lane_shift_for(int R) {
-  int r2 = 1;
-  while (r2 < R) r2 <<= 1;
-  int s = 0;
-  while ((1 << (s + 1)) * r2 <= 64) ++s;
-  return s;                      // g = 2^s lanes per row, g * r2 <= 64
+template <typename T, int MC>
+__device__ __forceinline__ v2<T> step_dot(const StepRow<T, MC>& r, const v2<T>* x) {
+  v2<T> s0 = mk<T>(0, 0), s1 = mk<T>(0, 0);
+#pragma unroll
+  for (int m = 0; m < MC; m += 2) {
+    s0 = cfma(s0, r.a[m], x[m]);
+    s1 = cfma(s1, r.a[m + 1], x[m + 1]);
+  }
+  return cadd(s0, s1);
 }
 
+// One pipelined sweep over zs[0..len) (LDS, MC entries per row).
+//   FWD:  step q = 0..len-1 on row q, block base+q, previous row q-1:
+//         z_q = b_q - c_q A_q z_{q-1}   (no product at q = 0)
+//   !FWD: step q = 0..len-2 on row l = len-2-q, block base+l, previous row l+1:
+//         z_l = b_l - c_l A_l z_{l+1}
+// b = A_q zs[row] when PROD_B (the row holds a right-hand side still to be
+// multiplied by the step's block), else b = zs[row] itself; c = 1 unless HASC.
+template <typename T, int MC, bool FWD, bool PROD_B, bool HASC, int NSET>
+__device__ __forceinline__ void lds_sweep(v2<T>* zs, int len, const v2<T>* __restrict__ A,
+                                          const v2<T>* __restrict__ cv, int base, int Mr) {
+  constexpr int NG = 64 / MC;
+  const int lane = threadIdx.x, grp = lane / MC, row = lane % MC;
+  const int nsteps = FWD ? len : len - 1;
+  if (nsteps <= 0) return;
+  // block index of step q (steps past the end reload the last block; unused)
+  auto blk = [&](int q) {
+    const int qc = q < nsteps ? q : nsteps - 1;
+    return base + (FWD ? qc : len - 2 - qc);
+  };
+  StepRow<T, MC> R[NSET];
+#pragma unroll
+  for (int h = 0; h < NSET; ++h) load_step<T, MC, HASC>(R[h], A, Mr, row, cv, blk(grp + h * NG));
+  for (int q0 = 0; q0 < nsteps; q0 += NSET * NG) {
+#pragma unroll
+    for (int h = 0; h < NSET; ++h) {
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        const int q = q0 + h * NG + g;
+        if (q < nsteps) {
+          const int l = FWD ? q : len - 2 - q;
+          const v2<T> b = PROD_B ? step_dot<T, MC>(R[h], zs + l * MC) : zs[l * MC + row];
+          v2<T> z = b;
+          if (!FWD || q > 0) {
+            const v2<T> acc = step_dot<T, MC>(R[h], zs + (FWD ? l - 1 : l + 1) * MC);
+            z = csub(b, HASC ? cmul(R[h].c, acc) : acc);
+          }
+          if (grp == g && row < Mr) zs[l * MC + row] = z;
+          __syncthreads();                 // one wave: orders the row write before the next reads
+        }
+      }
+      load_step<T, MC, HASC>(R[h], A, Mr, row, cv, blk(q0 + (h + NSET) * NG + grp));
+    }
+  }
+}
 
 // Step 3: channel right-hand sides, chunk-local block LU solves and the
 // chunks' contributions to the interface right-hand sides.  Block = one wave;
@@ -675,206 +714,161 @@ __device__ __forceinline__ int lane_shift_for(int R) {
 // (Remark 4 convention):
 //   r^A_i(k) = rho^A_i(k) - sum_{l > i} c_il varphi_l(k)
 //   r^B_l(j) = rho^B_l(j) - sum_{m >= l} c_ml phi_m(j)
-template <typename T, int NE, int NEI, int MC, int PDL>
+// Chunk rows s..e with the precomputed block LU (G_t = Schur-complement
+// inverses, scalar couplings lo_t, up_t):
+//   forward   Z_t = G_t (r_t - lo_t Z_{t-1})
+//   backward  g_t = Z_t - up_t G_t g_{t+1},  g_e = Z_e
+// The chunk lives in dynamic LDS (len x MC values).
+template <typename T, int MC>
 __global__ void __launch_bounds__(64) k_cccs_chain(ChanSys<T> SA, ChanSys<T> SB, ChanTab<T> ch,
                                                    int n, const v2<T>* __restrict__ rhoA,
                                                    const v2<T>* __restrict__ rhoB,
                                                    const v2<T>* __restrict__ partC, int nparts,
                                                    v2<T>* __restrict__ gA, v2<T>* __restrict__ gB,
                                                    v2<T>* __restrict__ HA, v2<T>* __restrict__ HB) {
+  extern __shared__ __align__(16) unsigned char chain_lds[];
+  v2<T>* zs = reinterpret_cast<v2<T>*>(chain_lds);
   const bool isA = blockIdx.y == 0;
   const ChanSys<T>& S = isA ? SA : SB;
   const int p = blockIdx.x;
   if (p >= S.P) return;
-  const int M = S.M, MM = M * M, Mo = isA ? ch.L : ch.M;
-  const int s = S.start[p], e = S.start[p + 1] - 1;
+  const int M = S.M, Mo = isA ? ch.L : ch.M;
+  const int s = S.start[p], e = S.start[p + 1] - 1, len = e - s + 1;
   const int lane = threadIdx.x;
   v2<T>* g = isA ? gA : gB;
   const v2<T>* rho = isA ? rhoA : rhoB;
   // coupling coefficients c[i][l]: the reduce kernel's per-block partials,
-  // added in block order
+  // added in a fixed order (16 loads in flight per lane, four partial sums)
   __shared__ v2<T> coef[256];
   const int npair = ch.M * ch.L;
   for (int idx = lane; idx < npair; idx += 64) {
-    double xr = 0, xi = 0;
-#pragma unroll 8
-    for (int b = 0; b < nparts; ++b) {
-      const v2<T> c = partC[(size_t)b * npair + idx];
-      xr += c.x;
-      xi += c.y;
+    double xr[4] = {0, 0, 0, 0}, xi[4] = {0, 0, 0, 0};
+    int b = 0;
+    for (; b + 16 <= nparts; b += 16) {
+      v2<T> c[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) c[u] = partC[(size_t)(b + u) * npair + idx];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        xr[u & 3] += c[u].x;
+        xi[u & 3] += c[u].y;
+      }
     }
-    coef[idx] = mk<T>((T)xr, (T)xi);
+    for (; b < nparts; ++b) {
+      const v2<T> c = partC[(size_t)b * npair + idx];
+      xr[0] += c.x;
+      xi[0] += c.y;
+    }
+    coef[idx] = mk<T>((T)((xr[0] + xr[1]) + (xr[2] + xr[3])), (T)((xi[0] + xi[1]) + (xi[2] + xi[3])));
   }
   __syncthreads();
-  // (a) right-hand sides of the chunk rows, written into g
-  for (int idx = lane; idx < (e - s + 1) * M; idx += 64) {
-    const int t = s + idx / M, i = idx % M, node = t + 1;
-    v2<T> v = rho[(size_t)node * M + i];
-    v2<T> cf[MC], bs[MC];
+  // (a) right-hand sides of the chunk rows into LDS (zero beyond M).  Loads
+  // use clamped indices and unused terms get a zero coefficient, so that all
+  // loads of two elements per lane are in flight together.
+  const v2<T>* basis = isA ? ch.vphi : ch.phi;
+  for (int idx0 = 0; idx0 < len * MC; idx0 += 128) {
+    v2<T> v[2], bs[2][MC];
 #pragma unroll
-    for (int l = 0; l < MC; ++l) {
-      const bool use = isA ? (l > i && l < Mo) : (l >= i && l < Mo);
-      cf[l] = use ? (isA ? coef[i * Mo + l] : coef[l * M + i]) : mk<T>(0, 0);
-      bs[l] = use ? (isA ? ch.vphi[(size_t)l * (n + 1) + node] : ch.phi[(size_t)l * (n + 1) + node])
-                  : mk<T>(0, 0);
+    for (int u = 0; u < 2; ++u) {
+      const int idx = idx0 + u * 64 + lane;
+      const int q = idx < len * MC ? idx / MC : 0, i = idx % MC, node = s + q + 1;
+      v[u] = rho[(size_t)node * M + (i < M ? i : M - 1)];
+#pragma unroll
+      for (int l = 0; l < MC; ++l) bs[u][l] = basis[(size_t)(l < Mo ? l : Mo - 1) * (n + 1) + node];
     }
 #pragma unroll
-    for (int l = 0; l < MC; ++l) v = csub(v, cmul(cf[l], bs[l]));
-    g[(size_t)t * M + i] = v;
-  }
-  __syncthreads();                    // single wave: orders the g writes before the reads below
-  const int gsh = lane_shift_for(M), row = lane >> gsh, part = lane & ((1 << gsh) - 1);
-  const bool owner = (row < M) && part == 0;
-  // (b) forward sweep  Z_t = G_t (r_t - lo_t Z_{t-1})  with a PDL-deep prefetch;
-  //     rq holds r_t at the lane's columns
-  v2<T> A[PDL][NE], rq[PDL][NE], cq[PDL];
-  auto load_fwd = [&](int d, int t) {
-    load_row<T, NE>(A[d], S.G + (size_t)t * MM, M, gsh);
+    for (int u = 0; u < 2; ++u) {
+      const int idx = idx0 + u * 64 + lane;
+      if (idx < len * MC) {
+        const int i = idx % MC;
+        v2<T> r = mk<T>(0, 0);
+        if (i < M) {
+          r = v[u];
 #pragma unroll
-    for (int q = 0; q < NE; ++q) {
-      const int m = part + (1 << gsh) * q;
-      rq[d][q] = m < M ? g[(size_t)t * M + m] : mk<T>(0, 0);
-    }
-    cq[d] = S.lo[t];
-  };
-#pragma unroll
-  for (int d = 0; d < PDL; ++d)
-    if (s + d <= e) load_fwd(d, s + d);
-  v2<T> y = mk<T>(0, 0);
-  for (int t0 = s; t0 <= e; t0 += PDL) {
-#pragma unroll
-    for (int d = 0; d < PDL; ++d) {
-      const int t = t0 + d;
-      if (t > e) break;
-      v2<T> x[NE];
-      if (t > s) {
-        gather<T, NE>(x, y, M, gsh, gsh, 0, M);
-#pragma unroll
-        for (int q = 0; q < NE; ++q) x[q] = csub(rq[d][q], cmul(cq[d], x[q]));
-      } else {
-#pragma unroll
-        for (int q = 0; q < NE; ++q) x[q] = rq[d][q];
+          for (int l = 0; l < MC; ++l) {
+            const bool use = l < Mo && (isA ? (l > i) : (l >= i));
+            const v2<T> cf = use ? (isA ? coef[i * Mo + l] : coef[l * M + i]) : mk<T>(0, 0);
+            r = csub(r, cmul(cf, bs[u][l]));
+          }
+        }
+        zs[idx] = r;
       }
-      y = rowsum<T, NE>(A[d], x, gsh);
-      if (t + PDL <= e) load_fwd(d, t + PDL);
-      if (owner) g[(size_t)t * M + row] = y;
     }
   }
-  __syncthreads();                    // forward results written by other lanes become visible
-  // (c) backward sweep  g_t = Z_t - up_t G_t g_{t+1};  zq holds Z_t at the lane's row
-  v2<T> zq[PDL];
-  auto load_bwd = [&](int d, int t) {
-    load_row<T, NE>(A[d], S.G + (size_t)t * MM, M, gsh);
-    zq[d] = row < M ? g[(size_t)t * M + row] : mk<T>(0, 0);
-    cq[d] = S.up[t];
-  };
-#pragma unroll
-  for (int d = 0; d < PDL; ++d)
-    if (e - 1 - d >= s) load_bwd(d, e - 1 - d);
-  const v2<T> gs = y;                 // g at the chunk's last row
-  for (int t0 = e - 1; t0 >= s; t0 -= PDL) {
-#pragma unroll
-    for (int d = 0; d < PDL; ++d) {
-      const int t = t0 - d;
-      if (t < s) break;
-      v2<T> x[NE];
-      gather<T, NE>(x, y, M, gsh, gsh, 0, M);
-      const v2<T> acc = rowsum<T, NE>(A[d], x, gsh);
-      const v2<T> z = zq[d], cu = cq[d];
-      if (t - PDL >= s) load_bwd(d, t - PDL);
-      y = csub(z, cmul(cu, acc));
-      if (owner) g[(size_t)t * M + row] = y;
-    }
+  __syncthreads();
+  // (b) forward sweep (the right-hand side is multiplied by G_t in the step),
+  // (c) backward sweep
+  lds_sweep<T, MC, true, true, true, 3>(zs, len, S.G, S.lo, s, M);
+  lds_sweep<T, MC, false, false, true, 3>(zs, len, S.G, S.up, s, M);
+  for (int idx = lane; idx < len * M; idx += 64) {
+    const int q = idx / M, i = idx % M;
+    g[(size_t)(s + q) * M + i] = zs[q * MC + i];
   }
-  // y = g at the chunk's first row, gs = g at its last row (row-distributed)
+  // (d) this chunk's contributions to the interface right-hand sides:
+  //     interface p   from the last row:  Rinv_p     [g_e; 0]
+  //     interface p-1 from the first row: Rinv_{p-1} [0; g_s]
   const int Q = S.P - 1;
   if (Q <= 0) return;
-  const int R = 2 * M, RR = R * R;
-  const int gsi = lane_shift_for(R), rowi = lane >> gsi;
-  const bool own = (rowi < R) && (lane & ((1 << gsi) - 1)) == 0;
+  const int R = 2 * M;
   v2<T>* H = isA ? HA : HB;           // [Q][2][R]: halves of Rinv_q [g(e_q); g(s_{q+1})]
-  // (d) this chunk's contributions to the interface right-hand sides
-  if (p < Q) {                        // interface p, from the last row: x = [gs; 0]
-    v2<T> a[NEI], x[NEI];
-    load_row<T, NEI>(a, S.Rinv + (size_t)p * RR, R, gsi);
-    gather<T, NEI>(x, gs, R, gsi, gsh, 0, M);
-    const v2<T> acc = rowsum<T, NEI>(a, x, gsi);
-    if (own) H[((size_t)p * 2) * R + rowi] = acc;
-  }
-  if (p > 0) {                        // interface p-1, from the first row: x = [0; y]
-    v2<T> a[NEI], x[NEI];
-    load_row<T, NEI>(a, S.Rinv + (size_t)(p - 1) * RR, R, gsi);
-    gather<T, NEI>(x, y, R, gsi, gsh, M, 2 * M);
-    const v2<T> acc = rowsum<T, NEI>(a, x, gsi);
-    if (own) H[((size_t)(p - 1) * 2 + 1) * R + rowi] = acc;
+  // (zs entries beyond M are zero, so clamped loads need no masking)
+  if (lane < R) {
+    v2<T> r1[MC], r2[MC];
+    const v2<T>* Ri1 = S.Rinv + (size_t)(p < Q ? p : 0) * R * R + (size_t)lane * R;
+    const v2<T>* Ri2 = S.Rinv + (size_t)(p > 0 ? p - 1 : 0) * R * R + (size_t)lane * R + M;
+#pragma unroll
+    for (int m = 0; m < MC; ++m) {
+      r1[m] = Ri1[m < M ? m : M - 1];
+      r2[m] = Ri2[m < M ? m : M - 1];
+    }
+    if (p < Q) {
+      v2<T> acc = mk<T>(0, 0);
+#pragma unroll
+      for (int m = 0; m < MC; ++m) acc = cfma(acc, r1[m], zs[(len - 1) * MC + m]);
+      H[((size_t)p * 2) * R + lane] = acc;
+    }
+    if (p > 0) {
+      v2<T> acc = mk<T>(0, 0);
+#pragma unroll
+      for (int m = 0; m < MC; ++m) acc = cfma(acc, r2[m], zs[m]);
+      H[((size_t)(p - 1) * 2 + 1) * R + lane] = acc;
+    }
   }
 }
 
 // Step 3b: the interface system of each system (blockIdx.y), one wave:
-// block-tridiagonal in 2M x 2M blocks, forward and backward block Thomas
-// sweeps with the precomputed Rinv, Rlo = Rinv Sub, Rup = Rinv Sup.
-template <typename T, int NEI, int PDI>
+// block tridiagonal in 2M x 2M blocks, block Thomas sweeps with the
+// precomputed Rlo = Rinv Sub, Rup = Rinv Sup:
+//   forward   Z_q = (H_q^0 + H_q^1) - Rlo_q Z_{q-1}
+//   backward  Y_q = Z_q - Rup_q Y_{q+1},  Y_{Q-1} = Z_{Q-1}
+template <typename T, int RC>
 __global__ void __launch_bounds__(64) k_cccs_interface(ChanSys<T> SA, ChanSys<T> SB,
                                                        v2<T>* __restrict__ YA, v2<T>* __restrict__ YB,
                                                        const v2<T>* __restrict__ HA,
                                                        const v2<T>* __restrict__ HB) {
+  extern __shared__ __align__(16) unsigned char iface_lds[];
+  v2<T>* zs = reinterpret_cast<v2<T>*>(iface_lds);
   const bool isA = blockIdx.y == 0;
   const ChanSys<T>& S = isA ? SA : SB;
   const int Q = S.P - 1;
   if (Q <= 0) return;
-  const int lane = threadIdx.x;
-  const int M = S.M, R = 2 * M, RR = R * R;
-  const int gsi = lane_shift_for(R), rowi = lane >> gsi;
-  const bool own = (rowi < R) && (lane & ((1 << gsi) - 1)) == 0;
+  const int lane = threadIdx.x, R = 2 * S.M;
   v2<T>* Y = isA ? YA : YB;
   const v2<T>* H = isA ? HA : HB;
-  // forward: Z_q = H_q - Rlo_q Z_{q-1}
-  v2<T> B[PDI][NEI], hq[PDI];
-  auto load_ifw = [&](int d, int q) {
-    load_row<T, NEI>(B[d], S.Rlo + (size_t)q * RR, R, gsi);
-    hq[d] = rowi < R ? cadd(H[((size_t)q * 2) * R + rowi], H[((size_t)q * 2 + 1) * R + rowi]) : mk<T>(0, 0);
-  };
-#pragma unroll
-  for (int d = 0; d < PDI; ++d)
-    if (1 + d < Q) load_ifw(d, 1 + d);
-  v2<T> zz = rowi < R ? cadd(H[rowi], H[R + rowi]) : mk<T>(0, 0);
-  if (own) Y[rowi] = zz;
-  for (int q0 = 1; q0 < Q; q0 += PDI) {
-#pragma unroll
-    for (int d = 0; d < PDI; ++d) {
-      const int q = q0 + d;
-      if (q >= Q) break;
-      v2<T> x[NEI];
-      gather<T, NEI>(x, zz, R, gsi, gsi, 0, R);
-      const v2<T> acc = rowsum<T, NEI>(B[d], x, gsi);
-      const v2<T> h = hq[d];
-      if (q + PDI < Q) load_ifw(d, q + PDI);
-      zz = csub(h, acc);
-      if (own) Y[(size_t)q * R + rowi] = zz;
-    }
+#pragma unroll 4
+  for (int idx = lane; idx < Q * RC; idx += 64) {
+    const int q = idx / RC, i = idx % RC, ic = i < R ? i : R - 1;
+    const v2<T> h = cadd(H[((size_t)q * 2) * R + ic], H[((size_t)q * 2 + 1) * R + ic]);
+    zs[idx] = i < R ? h : mk<T>(0, 0);
   }
-  __syncthreads();                    // forward interface results visible to every lane
-  // backward: Y_q = Z_q - Rup_q Y_{q+1}
-  auto load_ibw = [&](int d, int q) {
-    load_row<T, NEI>(B[d], S.Rup + (size_t)q * RR, R, gsi);
-    hq[d] = rowi < R ? Y[(size_t)q * R + rowi] : mk<T>(0, 0);
-  };
-#pragma unroll
-  for (int d = 0; d < PDI; ++d)
-    if (Q - 2 - d >= 0) load_ibw(d, Q - 2 - d);
-  for (int q0 = Q - 2; q0 >= 0; q0 -= PDI) {
-#pragma unroll
-    for (int d = 0; d < PDI; ++d) {
-      const int q = q0 - d;
-      if (q < 0) break;
-      v2<T> x[NEI];
-      gather<T, NEI>(x, zz, R, gsi, gsi, 0, R);
-      const v2<T> acc = rowsum<T, NEI>(B[d], x, gsi);
-      const v2<T> h = hq[d];
-      if (q - PDI >= 0) load_ibw(d, q - PDI);
-      zz = csub(h, acc);
-      if (own) Y[(size_t)q * R + rowi] = zz;
-    }
+  __syncthreads();
+  // forward block index q uses Rlo_q (q >= 1); backward row l uses Rup_l
+  constexpr int NS = RC * sizeof(T) >= 256 ? 1 : 3;   // 32 FP64 values per row: one set
+  lds_sweep<T, RC, true, false, false, NS>(zs, Q, S.Rlo, nullptr, 0, R);
+  lds_sweep<T, RC, false, false, false, NS>(zs, Q, S.Rup, nullptr, 0, R);
+  for (int idx = lane; idx < Q * R; idx += 64) {
+    const int q = idx / R, i = idx % R;
+    Y[(size_t)q * R + i] = zs[q * RC + i];
   }
 }
 
@@ -1526,21 +1520,27 @@ void launch_cccs(hipStream_t s, const Level<T>& L, void* u, const void* f, const
                      (const v2<T>*)partB, rhoA, rhoB, partC);
   const int P = SA.P > SB.P ? SA.P : SB.P;
   // entries per lane: chains over M x M blocks, interface over 2M x 2M blocks
-#define MGC_CHAIN(NE, NEI, MCC, PDL, PDI)                                                          \
-  mark(2, 0);                                                                                        \
-  hipLaunchKernelGGL((k_cccs_chain<T, NE, NEI, MCC, PDL>), dim3(P, 2), dim3(64), 0, s, SA, SB, ch, n,     \
-                     (const v2<T>*)rhoA, (const v2<T>*)rhoB, (const v2<T>*)partC, nrb, gA, gB,       \
-                     (v2<T>*)w.HA, (v2<T>*)w.HB);                                                    \
-  mark(2, 1);                                                                                        \
-  hipLaunchKernelGGL((k_cccs_interface<T, NEI, PDI>), dim3(1, 2), dim3(64), 0, s, SA, SB, YA, YB,    \
-                     (const v2<T>*)w.HA, (const v2<T>*)w.HB)
-  // prefetch depth (chain steps in flight) traded against registers
+  // dynamic LDS: one chunk (chains) or all interfaces (interface sweeps)
+  const int NN = SA.N > SB.N ? SA.N : SB.N;
+  const int PP = SA.P < SB.P ? SA.P : SB.P;
+  const int maxlen = (NN + PP - 1) / PP;
+  const int Qmax = P - 1;
+#define MGC_CHAIN(MCC)                                                                                 \
+  mark(2, 0);                                                                                          \
+  hipLaunchKernelGGL((k_cccs_chain<T, MCC>), dim3(P, 2), dim3(64), (size_t)maxlen * MCC * sizeof(v2<T>), \
+                     s, SA, SB, ch, n, (const v2<T>*)rhoA, (const v2<T>*)rhoB, (const v2<T>*)partC, nrb, \
+                     gA, gB, (v2<T>*)w.HA, (v2<T>*)w.HB);                                               \
+  mark(2, 1);                                                                                          \
+  if (Qmax > 0)                                                                                        \
+    hipLaunchKernelGGL((k_cccs_interface<T, 2 * MCC>), dim3(1, 2), dim3(64),                            \
+                       (size_t)Qmax * 2 * MCC * sizeof(v2<T>), s, SA, SB, YA, YB, (const v2<T>*)w.HA,   \
+                       (const v2<T>*)w.HB)
   if (MC <= 4) {
-    MGC_CHAIN(1, 2, 4, 4, 4);
+    MGC_CHAIN(4);
   } else if (MC <= 8) {
-    MGC_CHAIN(1, 4, 8, 4, 4);
+    MGC_CHAIN(8);
   } else {
-    MGC_CHAIN(4, 16, 16, 2, 1);
+    MGC_CHAIN(16);
   }
 #undef MGC_CHAIN
   const int NM = (SA.N * SA.M > SB.N * SB.M) ? SA.N * SA.M : SB.N * SB.M;
