@@ -323,6 +323,50 @@ constexpr int S1CX = 32, S1CY = 8;                       // coarse points per bl
 constexpr int S1W = 2 * S1CX + 3, S1H = 2 * S1CY + 3;    // u' tile (fine nodes)
 constexpr int S1RW = 2 * S1CX + 1, S1RH = 2 * S1CY + 1;  // residual tile
 
+// 1D operator tables of a tile, staged in LDS in the same load round as the
+// field values: by column (px, a, c, tm at the columns' x1 nodes) and by row
+// (py, a, c, tm at the rows' x2 nodes); zero outside the interior.
+template <typename T, int W, int H> struct TileTabs {
+  v2<T> col[4][W];
+  v2<T> row[4][H];
+};
+template <typename T, int W, int H>
+__device__ __forceinline__ void stage_tabs(TileTabs<T, W, H>& tb, const Level<T>& L, int c0, int r0, int tid) {
+  if (tid < W + H) {
+    const bool isc = tid < W;
+    const int ix = isc ? c0 + tid : r0 + (tid - W);
+    const bool ok = ix > 0 && ix < L.n;
+    const int ic = ok ? ix : 1;
+    const v2<T>* pd = isc ? L.px : L.py;
+    v2<T> t0 = pd[ic], t1 = L.a[ic], t2 = L.c[ic], t3 = L.tm[ic];
+    if (!ok) t0 = t1 = t2 = t3 = mk<T>(0, 0);
+    if (isc) {
+      tb.col[0][tid] = t0; tb.col[1][tid] = t1; tb.col[2][tid] = t2; tb.col[3][tid] = t3;
+    } else {
+      const int r = tid - W;
+      tb.row[0][r] = t0; tb.row[1][r] = t1; tb.row[2][r] = t2; tb.row[3][r] = t3;
+    }
+  }
+}
+// diagonal px_j + py_k + tm_max(j,k) - E at tile position (rr, cc), node (k, j)
+template <typename T, int W, int H>
+__device__ __forceinline__ v2<T> tab_diag(const TileTabs<T, W, H>& tb, T E, int rr, int cc, int k, int j) {
+  v2<T> d = cadd(cadd(tb.col[0][cc], tb.row[0][rr]), j > k ? tb.col[3][cc] : tb.row[3][rr]);
+  d.x -= E;
+  return d;
+}
+// (A w)(k, j) from an LDS tile w with a one-node halo
+template <typename T, int W, int H, int TW>
+__device__ __forceinline__ v2<T> tab_apply(const TileTabs<T, W, H>& tb, T E, const v2<T> (*w)[TW], int rr,
+                                           int cc, int k, int j) {
+  v2<T> acc = cmul(tab_diag(tb, E, rr, cc, k, j), w[rr][cc]);
+  acc = cfma(acc, tb.col[1][cc], w[rr][cc - 1]);
+  acc = cfma(acc, tb.col[2][cc], w[rr][cc + 1]);
+  acc = cfma(acc, tb.row[1][rr], w[rr - 1][cc]);
+  acc = cfma(acc, tb.row[2][rr], w[rr + 1][cc]);
+  return acc;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_s1_zero(Level<T> L, const v2<T>* __restrict__ f,
                                                  const double* __restrict__ fs, T omega,
@@ -330,6 +374,7 @@ __global__ void __launch_bounds__(256) k_s1_zero(Level<T> L, const v2<T>* __rest
   __shared__ v2<T> up[S1H][S1W];
   __shared__ v2<T> fl[S1H][S1W];
   __shared__ v2<T> rl[S1RH][S1RW];
+  __shared__ TileTabs<T, S1W, S1H> tb;
   const int n = L.n, p = L.pitch, nc = n / 2;
   const int tid = threadIdx.x + 64 * threadIdx.y;
   const int J0 = 1 + blockIdx.x * S1CX, K0 = 1 + blockIdx.y * S1CY;
@@ -344,6 +389,8 @@ __global__ void __launch_bounds__(256) k_s1_zero(Level<T> L, const v2<T>* __rest
     const int k = r0 + rr, j = c0 + cc;
     fr[q] = (idx < S1H * S1W && j > 0 && j < n && k > 0 && k < n) ? f[(size_t)k * p + j] : mk<T>(0, 0);
   }
+  stage_tabs(tb, L, c0, r0, tid);
+  __syncthreads();
 #pragma unroll
   for (int q = 0; q < NL1; ++q) {
     const int idx = tid + 256 * q;
@@ -353,7 +400,7 @@ __global__ void __launch_bounds__(256) k_s1_zero(Level<T> L, const v2<T>* __rest
     v2<T> fv = mk<T>(0, 0), uv = mk<T>(0, 0);
     if (j > 0 && j < n && k > 0 && k < n) {
       fv = cscale(fr[q], sc);
-      uv = cscale(cdiv(fv, diag_at(L, k, j)), omega);
+      uv = cscale(cdiv(fv, tab_diag(tb, L.E, rr, cc, k, j)), omega);
     }
     up[rr][cc] = uv;
     fl[rr][cc] = fv;
@@ -363,14 +410,7 @@ __global__ void __launch_bounds__(256) k_s1_zero(Level<T> L, const v2<T>* __rest
     const int rr = 1 + idx / S1RW, cc = 1 + idx % S1RW;
     const int k = r0 + rr, j = c0 + cc;
     v2<T> r = mk<T>(0, 0);
-    if (j > 0 && j < n && k > 0 && k < n) {
-      v2<T> acc = cmul(diag_at(L, k, j), up[rr][cc]);
-      acc = cfma(acc, L.a[j], up[rr][cc - 1]);
-      acc = cfma(acc, L.c[j], up[rr][cc + 1]);
-      acc = cfma(acc, L.a[k], up[rr - 1][cc]);
-      acc = cfma(acc, L.c[k], up[rr + 1][cc]);
-      r = csub(fl[rr][cc], acc);
-    }
+    if (j > 0 && j < n && k > 0 && k < n) r = csub(fl[rr][cc], tab_apply(tb, L.E, up, rr, cc, k, j));
     rl[rr - 1][cc - 1] = r;
   }
   __syncthreads();
@@ -392,6 +432,7 @@ __global__ void __launch_bounds__(256) k_s1_zero(Level<T> L, const v2<T>* __rest
 
 constexpr int S2TX = 64, S2TY = 16;
 constexpr int S2W = S2TX + 2, S2H = S2TY + 2;
+constexpr int S2CW = S2W / 2 + 2, S2CH = S2H / 2 + 2;    // coarse correction tile
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_s2_zero(Level<T> L, const v2<T>* __restrict__ f,
@@ -400,27 +441,37 @@ __global__ void __launch_bounds__(256) k_s2_zero(Level<T> L, const v2<T>* __rest
                                                  v2<T>* __restrict__ u) {
   __shared__ v2<T> wl[S2H][S2W];
   __shared__ v2<T> fl[S2H][S2W];
+  __shared__ v2<T> el[S2CH][S2CW];
+  __shared__ TileTabs<T, S2W, S2H> tb;
   const int n = L.n, p = L.pitch, nc = n / 2;
   const int tid = threadIdx.x + 64 * threadIdx.y;
   const int j0 = 1 + blockIdx.x * S2TX - 1, k0 = 1 + blockIdx.y * S2TY - 1;   // tile origin (halo)
+  const int J0 = j0 >> 1, K0 = k0 >> 1;                                       // coarse origin
   const T sc = fs ? (T)*fs : T(1);
   constexpr int NL2 = (S2H * S2W + 255) / 256;
-  v2<T> fr[NL2], er[NL2];
+  constexpr int NLC = (S2CH * S2CW + 255) / 256;
+  v2<T> fr[NL2], er[NLC];
 #pragma unroll
   for (int q = 0; q < NL2; ++q) {          // issue every tile load first
     const int idx = tid + 256 * q;
     const int rr = idx / S2W, cc = idx % S2W;
     const int k = k0 + rr, j = j0 + cc;
-    const bool in = idx < S2H * S2W && j > 0 && j < n && k > 0 && k < n;
-    fr[q] = in ? f[(size_t)k * p + j] : mk<T>(0, 0);
-    if (in) {
-      const int Ja = j >> 1, Jb = (j + 1) >> 1, Ka = k >> 1, Kb = (k + 1) >> 1;
-      er[q] = cadd(cadd(ldf<T>(ec, pitch_c, Ka, Ja, nc), ldf<T>(ec, pitch_c, Ka, Jb, nc)),
-                   cadd(ldf<T>(ec, pitch_c, Kb, Ja, nc), ldf<T>(ec, pitch_c, Kb, Jb, nc)));
-    } else {
-      er[q] = mk<T>(0, 0);
-    }
+    fr[q] = (idx < S2H * S2W && j > 0 && j < n && k > 0 && k < n) ? f[(size_t)k * p + j] : mk<T>(0, 0);
   }
+#pragma unroll
+  for (int q = 0; q < NLC; ++q) {
+    const int idx = tid + 256 * q;
+    const int K = K0 + idx / S2CW, J = J0 + idx % S2CW;
+    er[q] = (idx < S2CH * S2CW && J > 0 && J < nc && K > 0 && K < nc) ? ec[(size_t)K * pitch_c + J]
+                                                                      : mk<T>(0, 0);
+  }
+  stage_tabs(tb, L, j0, k0, tid);
+#pragma unroll
+  for (int q = 0; q < NLC; ++q) {
+    const int idx = tid + 256 * q;
+    if (idx < S2CH * S2CW) el[idx / S2CW][idx % S2CW] = er[q];
+  }
+  __syncthreads();
 #pragma unroll
   for (int q = 0; q < NL2; ++q) {
     const int idx = tid + 256 * q;
@@ -430,7 +481,10 @@ __global__ void __launch_bounds__(256) k_s2_zero(Level<T> L, const v2<T>* __rest
     v2<T> fv = mk<T>(0, 0), wv = mk<T>(0, 0);
     if (j > 0 && j < n && k > 0 && k < n) {
       fv = cscale(fr[q], sc);
-      wv = cadd(cscale(cdiv(fv, diag_at(L, k, j)), omega), cscale(er[q], T(0.25)));
+      // bilinear prolongation: mean of the (up to) four coarse neighbours
+      const int Ja = (j >> 1) - J0, Jb = ((j + 1) >> 1) - J0, Ka = (k >> 1) - K0, Kb = ((k + 1) >> 1) - K0;
+      const v2<T> s = cadd(cadd(el[Ka][Ja], el[Ka][Jb]), cadd(el[Kb][Ja], el[Kb][Jb]));
+      wv = cadd(cscale(cdiv(fv, tab_diag(tb, L.E, rr, cc, k, j)), omega), cscale(s, T(0.25)));
     }
     wl[rr][cc] = wv;
     fl[rr][cc] = fv;
@@ -443,13 +497,8 @@ __global__ void __launch_bounds__(256) k_s2_zero(Level<T> L, const v2<T>* __rest
     const int rr = 1 + threadIdx.y + 4 * q;
     const int k = k0 + rr;
     if (k >= n) break;
-    v2<T> d = diag_at(L, k, j);
-    v2<T> acc = cmul(d, wl[rr][cc]);
-    acc = cfma(acc, L.a[j], wl[rr][cc - 1]);
-    acc = cfma(acc, L.c[j], wl[rr][cc + 1]);
-    acc = cfma(acc, L.a[k], wl[rr - 1][cc]);
-    acc = cfma(acc, L.c[k], wl[rr + 1][cc]);
-    v2<T> res = csub(fl[rr][cc], acc);
+    const v2<T> d = tab_diag(tb, L.E, rr, cc, k, j);
+    const v2<T> res = csub(fl[rr][cc], tab_apply(tb, L.E, wl, rr, cc, k, j));
     u[(size_t)k * p + j] = cadd(wl[rr][cc], cscale(cdiv(res, d), omega));
   }
 }
@@ -459,10 +508,17 @@ __global__ void __launch_bounds__(256) k_s2_zero(Level<T> L, const v2<T>* __rest
 // tiles; r is never stored.
 //   rho^A[k][i] = sum_j w_j phi_i(j) r[k][j]   -> partA[tile_x][k][i]
 //   rho^B[j][l] = sum_k w_k varphi_l(k) r[k][j] -> partB[tile_y][j][l]
-// Thread = one column, 16 rows; the block's 4 waves cover 64 rows.  The row
-// sums use a transposed butterfly: MC values over 64 lanes in
-// (MC - 1) + (6 - log2 MC) shuffle rounds instead of 6 MC.
+// Thread = one column, PT / W rows; the block's W waves cover 64 rows (many
+// waves per CU hide the shuffle latency; W = 8 or 4 where 16 waves would not fit
+// the registers of wide channel sets).  The row sums use a transposed
+// butterfly: MC values over 64 lanes in (MC - 1) + (6 - log2 MC) shuffle
+// rounds instead of 6 MC.
 constexpr int PT = 64;
+template <typename T, int MC> struct ProjCfg {
+  static constexpr int W = MC * sizeof(T) >= 256 ? 4 : (MC * sizeof(T) >= 64 ? 8 : 16);   // waves
+  static constexpr int R = PT / W;                           // rows per wave
+  static constexpr int U = W == 4 ? 4 : 2;                   // rows unrolled
+};
 
 template <int MC> constexpr int log2c() { return MC <= 1 ? 0 : 1 + log2c<MC / 2>(); }
 
@@ -493,19 +549,20 @@ __device__ __forceinline__ void butterfly_sum(v2<T> (&v)[MC]) {
   }
 }
 template <typename T, int MC>
-__global__ void __launch_bounds__(256) k_cccs_project(Level<T> L, const v2<T>* __restrict__ u,
-                                                      const v2<T>* __restrict__ f,
-                                                      const double* __restrict__ fs, ChanTab<T> ch,
-                                                      v2<T>* __restrict__ partA,
-                                                      v2<T>* __restrict__ partB) {
+__global__ void __launch_bounds__((64 * ProjCfg<T, MC>::W)) k_cccs_project(Level<T> L, const v2<T>* __restrict__ u,
+                                                          const v2<T>* __restrict__ f,
+                                                          const double* __restrict__ fs, ChanTab<T> ch,
+                                                          v2<T>* __restrict__ partA,
+                                                          v2<T>* __restrict__ partB) {
+  constexpr int PW = ProjCfg<T, MC>::W, PR = ProjCfg<T, MC>::R;
   __shared__ v2<T> wv[PT][MC];
-  __shared__ v2<T> red[PT][MC];
+  __shared__ v2<T> red[64][MC];
   const int n = L.n, p = L.pitch, M = ch.M, Lc = ch.L;
   const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + 64 * ty;
   const int j = 1 + blockIdx.x * PT + tx;
   const int kb = 1 + blockIdx.y * PT;
   const T sc = fs ? (T)*fs : T(1);
-  for (int idx = tid; idx < PT * MC; idx += 256) {
+  for (int idx = tid; idx < PT * MC; idx += 64 * PW) {
     const int r = idx / MC, l = idx % MC, k = kb + r;
     wv[r][l] = (l < Lc && k < n) ? ch.wvphi[(size_t)l * (n + 1) + k] : mk<T>(0, 0);
   }
@@ -517,10 +574,10 @@ __global__ void __launch_bounds__(256) k_cccs_project(Level<T> L, const v2<T>* _
   }
   __syncthreads();
   constexpr int SH = 6 - log2c<MC>();
-  const int kw = __builtin_amdgcn_readfirstlane(kb + (PT / 4) * ty);
+  const int kw = __builtin_amdgcn_readfirstlane(kb + PR * ty);
   ColumnStencil<T, v2<T>> cs(L, u, j, kw);
-#pragma unroll 4
-  for (int q = 0; q < PT / 4; ++q) {
+#pragma unroll ProjCfg<T, MC>::U
+  for (int q = 0; q < PR; ++q) {
     const int k = kw + q;                               // wave-uniform row
     const int rr = k - kb;
     if (k >= n) break;
@@ -538,21 +595,21 @@ __global__ void __launch_bounds__(256) k_cccs_project(Level<T> L, const v2<T>* _
     if ((tx & ((1 << SH) - 1)) == 0 && idx < M)
       partA[((size_t)blockIdx.x * (n + 1) + k) * M + idx] = pa[0];
   }
-  // rho^B over the block's 64 rows: waves 1..3 hand their sums to wave 0
-  for (int w = 1; w < 4; ++w) {
+  // rho^B over the block's 64 rows: the waves add their sums in order
+  if (ty == 0)
+#pragma unroll
+    for (int l = 0; l < MC; ++l) red[tx][l] = accB[l];
+  __syncthreads();
+  for (int w = 1; w < PW; ++w) {
     if (ty == w)
 #pragma unroll
-      for (int l = 0; l < MC; ++l) red[tx][l] = accB[l];
-    __syncthreads();
-    if (ty == 0)
-#pragma unroll
-      for (int l = 0; l < MC; ++l) accB[l] = cadd(accB[l], red[tx][l]);
+      for (int l = 0; l < MC; ++l) red[tx][l] = cadd(red[tx][l], accB[l]);
     __syncthreads();
   }
   if (ty == 0 && j < n) {
 #pragma unroll
     for (int l = 0; l < MC; ++l)
-      if (l < Lc) partB[((size_t)blockIdx.y * (n + 1) + j) * Lc + l] = accB[l];
+      if (l < Lc) partB[((size_t)blockIdx.y * (n + 1) + j) * Lc + l] = red[tx][l];
   }
 }
 
@@ -563,43 +620,53 @@ __global__ void __launch_bounds__(256) k_cccs_project(Level<T> L, const v2<T>* _
 // coupling partials use every thread (pairs x row groups, combined in order).
 constexpr int RB = 32;
 template <typename T>
-__global__ void __launch_bounds__(256) k_cccs_reduce(int n, int ntiles, ChanTab<T> ch,
+__global__ void __launch_bounds__(512) k_cccs_reduce(int n, int ntiles, ChanTab<T> ch,
                                                      const v2<T>* __restrict__ partA,
                                                      const v2<T>* __restrict__ partB,
                                                      v2<T>* __restrict__ rhoA, v2<T>* __restrict__ rhoB,
                                                      v2<T>* __restrict__ partC) {
   __shared__ v2<T> ra[RB][16], wv[RB][16];
-  __shared__ double pcr[256], pci[256];
+  __shared__ double pcr[512], pci[512];
   const int M = ch.M, Lc = ch.L, tid = threadIdx.x;
   const int kb = 1 + blockIdx.x * RB;
-  for (int idx = tid; idx < RB * 16; idx += 256) {
-    const int r = idx >> 4, i = idx & 15, k = kb + r;
-    v2<T> sa = mk<T>(0, 0), sb = mk<T>(0, 0), w = mk<T>(0, 0);
-    if (k < n) {
-      if (i < M) {
-#pragma unroll 16
-        for (int t = 0; t < ntiles; ++t) sa = cadd(sa, partA[((size_t)t * (n + 1) + k) * M + i]);
-        rhoA[(size_t)k * M + i] = sa;
+  {
+    // item (row r, slot i): loads with clamped indices, 16 tiles at a time
+    const int r = tid >> 4, i = tid & 15, k = kb + r;
+    const int kc = k < n ? k : n - 1, ia = i < M ? i : M - 1, ib = i < Lc ? i : Lc - 1;
+    const v2<T> w = ch.wvphi[(size_t)ib * (n + 1) + kc];
+    v2<T> sa = mk<T>(0, 0), sb = mk<T>(0, 0);
+    int t = 0;
+    for (; t + 16 <= ntiles; t += 16) {
+      v2<T> xa[16], xb[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        xa[u] = partA[((size_t)(t + u) * (n + 1) + kc) * M + ia];
+        xb[u] = partB[((size_t)(t + u) * (n + 1) + kc) * Lc + ib];
       }
-      if (i < Lc) {
-#pragma unroll 16
-        for (int t = 0; t < ntiles; ++t) sb = cadd(sb, partB[((size_t)t * (n + 1) + k) * Lc + i]);
-        rhoB[(size_t)k * Lc + i] = sb;
-        w = ch.wvphi[(size_t)i * (n + 1) + k];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        sa = cadd(sa, xa[u]);
+        sb = cadd(sb, xb[u]);
       }
     }
-    ra[r][i] = sa;
-    wv[r][i] = w;
+    for (; t < ntiles; ++t) {
+      sa = cadd(sa, partA[((size_t)t * (n + 1) + kc) * M + ia]);
+      sb = cadd(sb, partB[((size_t)t * (n + 1) + kc) * Lc + ib]);
+    }
+    const bool row = k < n;
+    if (row && i < M) rhoA[(size_t)k * M + i] = sa;
+    if (row && i < Lc) rhoB[(size_t)k * Lc + i] = sb;
+    ra[r][i] = (row && i < M) ? sa : mk<T>(0, 0);
+    wv[r][i] = (row && i < Lc) ? w : mk<T>(0, 0);
   }
   __syncthreads();
   const int P = M * Lc;                      // <= 256 pairs
-  const int G = 256 / P;                     // row groups per pair
+  const int G = 512 / P;                     // row groups per pair
   const int pair = tid % P, grp = tid / P;
   if (grp < G) {
     const int i = pair / Lc, l = pair % Lc;
-    const int rmax = min(RB, n - kb);
     double xr = 0, xi = 0;
-    for (int r = grp; r < rmax; r += G) {
+    for (int r = grp; r < RB; r += G) {
       const v2<T> a = wv[r][l], b = ra[r][i];
       xr += (double)a.x * b.x - (double)a.y * b.y;
       xi += (double)a.x * b.y + (double)a.y * b.x;
@@ -889,44 +956,60 @@ __global__ void __launch_bounds__(256) k_cccs_retrieve(ChanSys<T> SA, ChanSys<T>
   const v2<T>* g = isA ? gA : gB;
   const v2<T>* Y = isA ? YA : YB;
   v2<T>* e = isA ? eA : eB;
-  int p = 0;
-  while (t >= S.start[p + 1]) ++p;
+  // chunk of row t: start[p] = floor(N p / P), so p = floor(t P / N) or p + 1
+  int p = (int)(((long long)t * S.P) / S.N);
+  if (p + 1 < S.P && t >= S.start[p + 1]) ++p;
   v2<T> v = g[(size_t)t * M + i];
   if (p + 1 < S.P) {
     const v2<T>* Tn = Y + (size_t)p * R + M;
+#pragma unroll 8
     for (int m = 0; m < M; ++m) v = csub(v, cmul(S.Vs[(size_t)t * MM + i * M + m], Tn[m]));
   }
   if (p > 0) {
     const v2<T>* Bp = Y + (size_t)(p - 1) * R;
+#pragma unroll 8
     for (int m = 0; m < M; ++m) v = csub(v, cmul(S.Ws[(size_t)t * MM + i * M + m], Bp[m]));
   }
   e[(size_t)(t + 1) * M + i] = v;   // node index t+1
 }
 
-// Step 5: expansion u += sum_m eA[k][m] phi_m(j) + sum_l eB[j][l] varphi_l(k)
+// Step 5: expansion u += sum_m eA[k][m] phi_m(j) + sum_l eB[j][l] varphi_l(k).
+// The row-dependent factors of the block's SY * ROWS rows are staged in LDS
+// (one load each), the column-dependent ones stay in registers.
 template <typename T, int MC>
 __global__ void __launch_bounds__(256) k_cccs_expand(int n, int pitch, v2<T>* __restrict__ u,
                                                      ChanTab<T> ch, const v2<T>* __restrict__ eA,
                                                      const v2<T>* __restrict__ eB) {
-  const int j = 1 + blockIdx.x * SX + threadIdx.x;
-  const int k0 = 1 + (blockIdx.y * SY + threadIdx.y) * ROWS;
-  if (j >= n) return;
+  constexpr int BR = SY * ROWS;
+  __shared__ v2<T> ea[BR][MC], vp[BR][MC];
+  const int tid = threadIdx.x + SX * threadIdx.y;
+  const int kb = 1 + blockIdx.y * BR;
   const int M = ch.M, Lc = ch.L;
+  for (int idx = tid; idx < BR * MC; idx += SX * SY) {
+    const int r = idx / MC, m = idx % MC, k = kb + r;
+    const bool ok = k < n;
+    ea[r][m] = (ok && m < M) ? eA[(size_t)k * M + m] : mk<T>(0, 0);
+    vp[r][m] = (ok && m < Lc) ? ch.vphi[(size_t)m * (n + 1) + k] : mk<T>(0, 0);
+  }
+  const int j = 1 + blockIdx.x * SX + threadIdx.x;
   v2<T> ph[MC], eb[MC];
 #pragma unroll
   for (int m = 0; m < MC; ++m) {
-    ph[m] = (m < M) ? ch.phi[(size_t)m * (n + 1) + j] : mk<T>(0, 0);
-    eb[m] = (m < Lc) ? eB[(size_t)j * Lc + m] : mk<T>(0, 0);
+    ph[m] = (m < M && j < n) ? ch.phi[(size_t)m * (n + 1) + j] : mk<T>(0, 0);
+    eb[m] = (m < Lc && j < n) ? eB[(size_t)j * Lc + m] : mk<T>(0, 0);
   }
-  for (int r = 0; r < ROWS; ++r) {
-    const int k = __builtin_amdgcn_readfirstlane(k0 + r);   // wave-uniform row
+  __syncthreads();
+  if (j >= n) return;
+#pragma unroll
+  for (int q = 0; q < ROWS; ++q) {
+    const int r = threadIdx.y * ROWS + q, k = kb + r;
     if (k >= n) break;
     const size_t idx = (size_t)k * pitch + j;
     v2<T> v = u[idx];
 #pragma unroll
     for (int m = 0; m < MC; ++m) {
-      if (m < M) v = cfma(v, eA[(size_t)k * M + m], ph[m]);
-      if (m < Lc) v = cfma(v, eb[m], ch.vphi[(size_t)m * (n + 1) + k]);
+      v = cfma(v, ea[r][m], ph[m]);
+      v = cfma(v, eb[m], vp[r][m]);
     }
     u[idx] = v;
   }
@@ -1512,11 +1595,20 @@ void launch_cccs(hipStream_t s, const Level<T>& L, void* u, const void* f, const
   else if (MC <= 8) hipLaunchKernelGGL((KERNEL<T, 8>), GRID, BLOCK, 0, s, __VA_ARGS__); \
   else hipLaunchKernelGGL((KERNEL<T, 16>), GRID, BLOCK, 0, s, __VA_ARGS__);
   mark(1, 0);
-  MGC_CC_DISPATCH(k_cccs_project, dim3(nt, nt), dim3(64, 4), L, (const v2<T>*)u, (const v2<T>*)f,
-                  fs, ch, partA, partB);
+#define MGC_PROJ(MCC)                                                                               \
+  hipLaunchKernelGGL((k_cccs_project<T, MCC>), dim3(nt, nt), dim3(64, ProjCfg<T, MCC>::W), 0, s, L,   \
+                     (const v2<T>*)u, (const v2<T>*)f, fs, ch, partA, partB)
+  if (MC <= 4) {
+    MGC_PROJ(4);
+  } else if (MC <= 8) {
+    MGC_PROJ(8);
+  } else {
+    MGC_PROJ(16);
+  }
+#undef MGC_PROJ
   mark(1, 1);
   const int nrb = launch_cccs_reduce_blocks(n);
-  hipLaunchKernelGGL((k_cccs_reduce<T>), dim3(nrb), dim3(256), 0, s, n, nt, ch, (const v2<T>*)partA,
+  hipLaunchKernelGGL((k_cccs_reduce<T>), dim3(nrb), dim3(512), 0, s, n, nt, ch, (const v2<T>*)partA,
                      (const v2<T>*)partB, rhoA, rhoB, partC);
   const int P = SA.P > SB.P ? SA.P : SB.P;
   // entries per lane: chains over M x M blocks, interface over 2M x 2M blocks
