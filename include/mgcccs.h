@@ -210,21 +210,25 @@ mgc_status mgc_cross_section_grad(mgc_grid g, const void* u, const void* chi, do
                                   double zeta[2], double* sigma, mgc_stats* stats);
 
 /* Kernel timing (measurement support; no effect on results).
- * mgc_set_kernel_timer selects one kernel class.  While it is selected, every
- * launch of that kernel inside the FGMRES restart cycles of mgc_solve and
- * mgc_solve_transpose is bracketed by two HIP events recorded on the stream
- * the kernel runs on (event nodes inside the captured restart graphs).  The
- * durations, the launch count and the kernel's algorithmic bytes (compulsory
- * loads and stores of its operands over the interior nodes) accumulate until
- * mgc_read_kernel_timer, which returns and clears them.  MGC_KT_NONE turns
- * timing off.  A new selection re-captures the restart graph.
- * MGC_EINVAL for an unknown class, MGC_EHIP if events cannot be created.     */
+ * mgc_set_kernel_timer selects one kernel class.  While it is selected, its
+ * launches inside the FGMRES restart cycles of mgc_solve and
+ * mgc_solve_transpose are bracketed by HIP events recorded on the stream the
+ * kernels run on (event nodes inside the captured restart graphs): every
+ * Arnoldi step for the classes that depend on the step (APPLY_DOT, AXPY), the
+ * first step of each restart cycle for the others.  S1 and S2 launches of
+ * all levels follow each other, so one event pair brackets each such run.
+ * The durations, the launch count and the kernels' algorithmic bytes
+ * (compulsory loads and stores of their operands over the interior nodes)
+ * accumulate until mgc_read_kernel_timer, which returns and clears them.
+ * MGC_KT_NONE turns timing off.  A new selection re-captures the restart
+ * graph.  MGC_EINVAL for an unknown class, MGC_EHIP if events cannot be
+ * created.                                                                    */
 typedef enum {
   MGC_KT_NONE = 0,
   MGC_KT_APPLY_DOT = 1,      /* exact operator + basis dots, each Arnoldi step */
   MGC_KT_AXPY = 2,           /* both orthogonalisation axpy passes            */
-  MGC_KT_S1 = 3,             /* finest level: smoothing, residual, restriction */
-  MGC_KT_S2 = 4,             /* finest level: prolongation, post-smoothing     */
+  MGC_KT_S1 = 3,             /* smoothing, residual, restriction (all levels)  */
+  MGC_KT_S2 = 4,             /* prolongation, post-smoothing (all levels)      */
   MGC_KT_CCCS_PROJECT = 5,   /* CCCS residual + channel projections            */
   MGC_KT_CCCS_CHAIN = 6      /* CCCS chunk-local channel solves                */
 } mgc_kernel_class;

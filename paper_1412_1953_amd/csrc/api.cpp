@@ -59,16 +59,24 @@ struct GraphCache {                       // one captured FGMRES restart cycle
   double tol_abs = 0;
   int kt_slots = 0;                        // timer slots recorded in the graph
   std::vector<double> kt_bytes;
+  std::vector<int> kt_count;
 };
 
 // Event timing of one kernel class (mgc_set_kernel_timer).  Slots are event
-// pairs handed out in launch order during one restart cycle's enqueue.
+// pairs handed out in launch order during one restart cycle's enqueue; a slot
+// brackets one launch or a run of consecutive launches of the class (count).
+// Event record nodes cost a few microseconds each inside a graph, so classes
+// whose launches do not depend on the Arnoldi step are timed in the first
+// step of each restart cycle only (`open`).
 struct KernelTimer {
-  static constexpr int SLOTS = 2 * MGC_MAX_RESTART + 8;
+  static constexpr int SLOTS = 4 * MGC_MAX_RESTART;
   int which = MGC_KT_NONE;
   hipEvent_t ev[2 * SLOTS] = {};
   std::vector<double> bytes = std::vector<double>(SLOTS, 0.0);
+  std::vector<int> count = std::vector<int>(SLOTS, 0);
   int used = 0;
+  bool open = true;                        // slots may be handed out in this step
+  int run = -1;                            // slot of the S1 / S2 run in progress
   double ms = 0, total_bytes = 0;
   long long launches = 0;
 };
@@ -376,8 +384,9 @@ mgc_status check_ready(mgc_grid g, bool need_energy = true) {
 // class `kind` (-1: that class is not being timed); kt_mark records one end.
 int kt_slot(mgc_grid g, int kind, double bytes) {
   KernelTimer& t = g->kt;
-  if (t.which == MGC_KT_NONE || t.which != kind || t.used >= KernelTimer::SLOTS) return -1;
+  if (t.which == MGC_KT_NONE || t.which != kind || !t.open || t.used >= KernelTimer::SLOTS) return -1;
   t.bytes[t.used] = bytes;
+  t.count[t.used] = 1;
   return t.used++;
 }
 // While the stream is being captured the event becomes an explicit event
@@ -401,14 +410,14 @@ void kt_mark(mgc_grid g, hipStream_t s, int slot, int end) {
                "timer: capture dependencies");
 }
 // After the stream has synchronised: add up the first `slots` event pairs.
-void kt_harvest(mgc_grid g, int slots, const std::vector<double>& bytes) {
+void kt_harvest(mgc_grid g, int slots, const std::vector<double>& bytes, const std::vector<int>& count) {
   KernelTimer& t = g->kt;
   for (int i = 0; i < slots; ++i) {
     float ms = 0.0f;
     if (hipEventElapsedTime(&ms, t.ev[2 * i], t.ev[2 * i + 1]) != hipSuccess) continue;
     t.ms += ms;
     t.total_bytes += bytes[i];
-    ++t.launches;
+    t.launches += count[i];
   }
 }
 
@@ -428,15 +437,39 @@ void vcycle_level(mgc_grid g, int l, void* u, const void* f, bool zero_guess, co
     // fused passes: u' = omega f/d is recomputed, never stored
     const double Nf = (double)(L.n - 1) * (L.n - 1), Nc = (double)(L.n / 2 - 1) * (L.n / 2 - 1);
     const double e = (double)sizeof(v2<T>);
-    int ts = l == 0 ? kt_slot(g, MGC_KT_S1, (Nf + Nc) * e) : -1;   // f in, f_c out
-    kt_mark(g, s, ts, 0);
+    // timing: the S1 launches of all levels run back to back (one event
+    // pair around them), and so do the S2 launches
+    KernelTimer& kt = g->kt;
+    const bool last = l + 1 == g->coarsest();
+    if (l == 0) {
+      kt.run = kt_slot(g, MGC_KT_S1, 0.0);
+      if (kt.run >= 0) kt.count[kt.run] = 0;
+      kt_mark(g, s, kt.run, 0);
+    }
+    if (kt.run >= 0 && kt.which == MGC_KT_S1) {
+      kt.bytes[kt.run] += (Nf + Nc) * e;                             // f in, f_c out
+      ++kt.count[kt.run];
+    }
     launch_s1_zero<T>(s, L, f, fs, om, g->ws + LC.ff[p], LC.pitch);
-    kt_mark(g, s, ts, 1);
+    if (last && kt.which == MGC_KT_S1) {
+      kt_mark(g, s, kt.run, 1);
+      kt.run = -1;
+    }
     vcycle_level<T>(g, l + 1, g->ws + LC.fu[p], g->ws + LC.ff[p], true);
-    ts = l == 0 ? kt_slot(g, MGC_KT_S2, (2 * Nf + Nc) * e) : -1;    // f, e_c in, u out
-    kt_mark(g, s, ts, 0);
+    if (last) {
+      kt.run = kt_slot(g, MGC_KT_S2, 0.0);
+      if (kt.run >= 0) kt.count[kt.run] = 0;
+      kt_mark(g, s, kt.run, 0);
+    }
+    if (kt.run >= 0 && kt.which == MGC_KT_S2) {
+      kt.bytes[kt.run] += (2 * Nf + Nc) * e;                         // f, e_c in, u out
+      ++kt.count[kt.run];
+    }
     launch_s2_zero<T>(s, L, f, fs, om, g->ws + LC.fu[p], LC.pitch, u);
-    kt_mark(g, s, ts, 1);
+    if (l == 0 && kt.which == MGC_KT_S2) {
+      kt_mark(g, s, kt.run, 1);
+      kt.run = -1;
+    }
     return;
   }
   void* bufs[2] = {u, g->ws + LI.ft[p]};
@@ -609,9 +642,12 @@ void enqueue_fgmres_cycle(mgc_grid g, void* u, const mgc_solve_opts* o, double t
   hipStream_t saved = g->stream;
   g->stream = st;                           // the cycle drivers launch on g->stream
   g->kt.used = 0;
+  g->kt.run = -1;
+  const bool per_step = g->kt.which == MGC_KT_APPLY_DOT || g->kt.which == MGC_KT_AXPY;
   const double Nint = (double)(n - 1) * (n - 1);
   launch_gmres_begin(st, gs, m);
   for (int j = 0; j < mm; ++j) {
+    g->kt.open = per_step || j == 0;
     double2* Wj = W + (size_t)j * stride64;
     double2* Wn = W + (size_t)(j + 1) * stride64;
     char* Zj = Z + (size_t)j * fbz;
@@ -639,6 +675,7 @@ void enqueue_fgmres_cycle(mgc_grid g, void* u, const mgc_solve_opts* o, double t
     }
     launch_gmres_step(st, n, pitch, p2, gs, j, m, tol_abs);
   }
+  g->kt.open = true;
   launch_gmres_solve(st, gs, m, mm);
   if (f32) launch_update<float>(st, n, pitch, stridez, Z, mm, gs.upcoef, (double2*)u);
   else launch_update<double>(st, n, pitch, stridez, Z, mm, gs.upcoef, (double2*)u);
@@ -698,6 +735,7 @@ mgc_status solve_fgmres(mgc_grid g, void* u, const void* f, const mgc_solve_opts
         gc.kt = g->kt.which;
         gc.kt_slots = g->kt.used;
         gc.kt_bytes = g->kt.bytes;
+        gc.kt_count = g->kt.count;
       }
       HIPCHK(g, hipGraphLaunch(gc.exec, s));
     } else {
@@ -710,7 +748,9 @@ mgc_status solve_fgmres(mgc_grid g, void* u, const void* f, const mgc_solve_opts
     int kused = mm;
     HIPCHK(g, hipMemcpyAsync(&kused, gs.kused, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(g, hipStreamSynchronize(s));
-    if (kt_slots > 0) kt_harvest(g, kt_slots, use_graph ? g->graph.kt_bytes : g->kt.bytes);
+    if (kt_slots > 0)
+      kt_harvest(g, kt_slots, use_graph ? g->graph.kt_bytes : g->kt.bytes,
+                 use_graph ? g->graph.kt_count : g->kt.count);
     it += std::min(kused, mm);
     rel = std::sqrt(rr) / fn;
     record(st, ++rs, rel);

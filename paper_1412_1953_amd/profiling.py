@@ -1,0 +1,120 @@
+"""Summaries of rocprofv3 CSV output for the committed profile records.
+
+    python3 -m paper_1412_1953_amd.profiling stats <kernel_stats.csv> <kernel_trace.csv> <out.txt> -- <command>
+    python3 -m paper_1412_1953_amd.profiling traffic <kernel> <fetch.csv> <write.csv> <out.txt> -- <command>
+
+`stats` lists the kernels by total time (rocprofv3 --kernel-trace --stats)
+and, per kernel, the launch shapes (grid sizes) with their average duration.
+`traffic` turns two counter runs (--pmc FETCH_SIZE, then --pmc WRITE_SIZE,
+KiB per dispatch) into HBM bytes per launch of one kernel class, each counter
+scaled by what it reads for a plain device copy of known size (the 256 MiB
+copy that bench.py --copy-probe performs).  The record carries the SHA-256
+of the kernel source it was measured on; bench.py reports the traffic only
+while that source is unchanged.
+"""
+from __future__ import annotations
+
+import collections
+import csv
+import hashlib
+import os
+import re
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+KERNEL_SRC = os.path.join(ROOT, "paper_1412_1953_amd", "csrc", "kernels.hip")
+COPY_BYTES = 1 << 28                       # bench.py --copy-probe
+# kernel classes of the library's timer -> kernel-name pattern
+CLASS_PATTERN = {
+    "apply_dot": r"k_apply_dot<double",
+    "axpy": r"k_axpy_pass<",
+    "s1": r"k_s1_zero<double>",
+    "s2": r"k_s2_zero<double>",
+    "cccs_project": r"k_cccs_project<double",
+    "cccs_chain": r"k_cccs_chain<double",
+}
+
+
+def short(name: str) -> str:
+    return re.sub(r"\(.*", "", name).strip()
+
+
+def source_sha() -> str:
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def stats(stats_csv, trace_csv, out, command):
+    rows = list(csv.DictReader(open(stats_csv)))
+    total = sum(int(r["TotalDurationNs"]) for r in rows)
+    shapes = collections.defaultdict(lambda: [0, 0])
+    for r in csv.DictReader(open(trace_csv)):
+        key = (short(r["Kernel_Name"]), int(r["Grid_Size_X"]), int(r["Grid_Size_Y"]))
+        shapes[key][0] += 1
+        shapes[key][1] += int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    lines = [f"command: {command}", f"kernel time: {total / 1e6:.3f} ms", "",
+             f"{'share':>6} {'total ms':>9} {'calls':>6} {'avg us':>8}  kernel"]
+    for r in sorted(rows, key=lambda r: -int(r["TotalDurationNs"]))[:25]:
+        t = int(r["TotalDurationNs"])
+        lines.append(f"{100 * t / total:5.1f}% {t / 1e6:9.3f} {int(r['Calls']):6d} "
+                     f"{float(r['AverageNs']) / 1e3:8.2f}  {short(r['Name'])}")
+    lines += ["", "launch shapes (grid x, grid y in work-items):",
+              f"{'calls':>6} {'avg us':>8}  kernel [grid]"]
+    for (nm, gx, gy), (c, d) in sorted(shapes.items(), key=lambda x: -x[1][1])[:40]:
+        lines.append(f"{c:6d} {d / c / 1e3:8.2f}  {nm} [{gx} x {gy}]")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
+def counter_rows(path):
+    out = []
+    for r in csv.DictReader(open(path)):
+        out.append((short(r["Kernel_Name"]), float(r["Counter_Value"])))
+    return out
+
+
+def traffic(kclass, fetch_csv, write_csv, out, command):
+    pat = re.compile(CLASS_PATTERN[kclass])
+    res = {}
+    for label, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = counter_rows(path)
+        # the copy probe is the largest single dispatch of a copy kernel
+        copies = [v for nm, v in rows if "copy" in nm.lower()]
+        if not copies:
+            raise SystemExit(f"{path}: no copy dispatch found (run bench.py --copy-probe)")
+        kib_copy = max(copies)
+        scale = COPY_BYTES / (kib_copy * 1024.0)
+        vals = [v for nm, v in rows if pat.search(nm)]
+        if not vals:
+            raise SystemExit(f"{path}: no dispatch of {kclass}")
+        res[label] = (sum(vals) / len(vals), len(vals), kib_copy, scale)
+    fetch = res["FETCH_SIZE"][0] * 1024.0 * res["FETCH_SIZE"][3]
+    write = res["WRITE_SIZE"][0] * 1024.0 * res["WRITE_SIZE"][3]
+    lines = [f"command: {command}",
+             f"kernel class: {kclass} ({CLASS_PATTERN[kclass]})",
+             f"kernels.hip sha256: {source_sha()}"]
+    for label, (avg, cnt, kib_copy, scale) in res.items():
+        lines.append(f"{label}: {avg:.1f} KiB per dispatch over {cnt} dispatches; copy probe of "
+                     f"{COPY_BYTES} B read {kib_copy:.1f} KiB -> scale {scale:.4f}")
+    lines += [f"fetch bytes per launch: {fetch:.0f}",
+              f"write bytes per launch: {write:.0f}",
+              f"traffic bytes per launch: {fetch + write:.0f}"]
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
+def main(argv):
+    if "--" not in argv:
+        raise SystemExit(__doc__)
+    cut = argv.index("--")
+    args, command = argv[:cut], " ".join(argv[cut + 1:])
+    if args[0] == "stats":
+        stats(args[1], args[2], args[3], command)
+    elif args[0] == "traffic":
+        traffic(args[1], args[2], args[3], args[4], command)
+    else:
+        raise SystemExit(__doc__)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])
