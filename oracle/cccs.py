@@ -48,8 +48,9 @@ def select_lowest(evals: np.ndarray, M: int) -> np.ndarray:
 def bound_states(g: Grid1D, V: np.ndarray, M: int, refine_steps: int = 2):
     """Lowest M eigenpairs of H = -1/2 d^2/dz^2 + V on the complex grid.
 
-    Generalised complex-symmetric problem S phi = lambda W phi (S = W H) solved
-    densely; bilinear normalisation phi^T W phi = 1; sign fixed so that the
+    The discrete eigenproblem H phi = lambda phi (eq. 1d_eigenstate; H = W^-1 S
+    with the complex-symmetric S = W H) solved densely in this standard form;
+    bilinear normalisation phi^T W phi = 1; sign fixed so that the
     entry of largest modulus has a positive real part; then ``refine_steps``
     shift-and-invert steps (S - lambda W) psi = W phi (Sec. 5.1) and a
     Rayleigh-quotient update of lambda.
@@ -61,7 +62,7 @@ def bound_states(g: Grid1D, V: np.ndarray, M: int, refine_steps: int = 2):
         raise ValueError("need 1 <= M <= n-1")
     S = g.weighted_hamiltonian_dense(V)
     W = np.diag(g.w[1:n])
-    evals, evecs = sla.eig(S, W)
+    evals, evecs = sla.eig(S / g.w[1:n, None])
     sel = select_lowest(evals, M)
     lam = np.empty(M, np.complex128)
     phi = np.zeros((M, n + 1), np.complex128)
