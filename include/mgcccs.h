@@ -240,6 +240,29 @@ typedef struct {
 mgc_status mgc_set_kernel_timer(mgc_grid g, int kernel_class);
 mgc_status mgc_read_kernel_timer(mgc_grid g, mgc_kernel_timing* out);
 
+/* Batched solves (many energies and grid sizes at once).
+ * A batch groups `count` handles that live on one device, each with its own
+ * workspace, potential and energy already set (the handles stay owned by the
+ * caller and must outlive the batch).  mgc_batch_solve runs FGMRES (opts->outer
+ * must be MGC_FGMRES) on all of them together: each unfinished solve's
+ * restart cycle, its true residual and a three-number report are captured
+ * into one graph per solve; each round launches these graphs over 4
+ * library-owned streams (default priority) so that they run concurrently and
+ * synchronises once, then reads the reports.  Finished solves drop out.  The
+ * initial residuals run on the first handle's stream, which the side streams
+ * wait for.  u[i] (initial guess in, solution out) and f[i] are FP64 level-0
+ * fields of handle i; stats (nullable) receives one entry per solve, with
+ * t_solve_ms the wall time of the whole batch.  Each solve performs the same
+ * arithmetic as mgc_solve on its handle, so it reaches the same iterate.
+ * Returns MGC_OK when every solve converged, otherwise the first failing
+ * status in handle order (per-solve iterations and residuals are in stats
+ * either way).  No device memory is allocated.                               */
+typedef struct mgc_batch_s* mgc_batch;
+mgc_status mgc_batch_create(const mgc_grid* grids, int count, mgc_batch* out);
+mgc_status mgc_batch_solve(mgc_batch b, void* const* u, const void* const* f,
+                           const mgc_solve_opts* opts, mgc_stats* stats);
+mgc_status mgc_batch_destroy(mgc_batch b);
+
 mgc_status mgc_destroy_grid(mgc_grid g);
 
 /* Thread-local description of the last error (never NULL).                  */

@@ -1314,6 +1314,228 @@ mgc_status mgc_read_kernel_timer(mgc_grid g, mgc_kernel_timing* out) {
   return MGC_OK;
 }
 
+}  // extern "C"
+
+// ----------------------------------------------------------------------------
+// Batched FGMRES: every solve's restart cycle is its own captured graph; the
+// graphs of a round are launched over NSTREAMS streams so that they run
+// concurrently, and the host synchronises once per round.
+struct mgc_batch_s {
+  static constexpr int NSTREAMS = 4;
+  std::vector<mgc_grid> g;
+  hipStream_t side[NSTREAMS] = {};         // default priority, non-blocking
+  hipEvent_t start = nullptr;              // side streams wait for the batch stream
+};
+
+namespace {
+constexpr int REPORT = 32;                 // report slot in the handle's scalars
+
+struct BatchSolve {
+  void* u = nullptr;
+  const void* f = nullptr;
+  double fn = 0, rel = 0;
+  int it = 0, rs = 0, mm = 0;
+  bool active = true;
+  mgc_status status = MGC_OK;
+  hipGraphExec_t exec = nullptr;           // restart cycle + true residual + report
+  hipStream_t saved = nullptr;
+};
+
+// Capture solve s's restart cycle of mm steps, the true residual of the new
+// iterate and the report (||r||^2, ||f||^2, steps used) into scal[REPORT..],
+// and instantiate it.
+mgc_status capture_cycle(mgc_grid g, BatchSolve& s, const mgc_solve_opts* o) {
+  if (s.exec) {
+    (void)hipGraphExecDestroy(s.exec);
+    s.exec = nullptr;
+  }
+  GmresState gs = gmres_state(g);
+  double* scal = g->at<double>(g->scal);
+  HIPCHK(g, hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal));
+  enqueue_fgmres_cycle(g, s.u, o, o->tol * s.fn, s.mm, g->cap);
+  enqueue_true_residual(g, s.u, s.f, g->cap);
+  launch_report(g->cap, scal, gs.kused, scal + REPORT);
+  hipGraph_t graph = nullptr;
+  HIPCHK(g, hipStreamEndCapture(g->cap, &graph));
+  if (g->failed) {
+    (void)hipGraphDestroy(graph);
+    return MGC_EHIP;
+  }
+  hipError_t e = hipGraphInstantiate(&s.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) s.exec = nullptr;
+  HIPCHK(g, e);
+  return MGC_OK;
+}
+}  // namespace
+
+extern "C" {
+
+mgc_status mgc_batch_create(const mgc_grid* grids, int count, mgc_batch* out) {
+  if (!grids || !out || count < 1) return fail(MGC_EINVAL, "need grids, count >= 1 and an output handle");
+  *out = nullptr;
+  for (int i = 0; i < count; ++i) {
+    if (!grids[i]) return fail(MGC_EINVAL, "null handle in batch");
+    if (grids[i]->device != grids[0]->device) return fail(MGC_EINVAL, "batch handles must share one device");
+    for (int j = 0; j < i; ++j)
+      if (grids[j] == grids[i]) return fail(MGC_EINVAL, "a handle appears twice in the batch");
+  }
+  mgc_batch b = new mgc_batch_s;
+  b->g.assign(grids, grids + count);
+  for (int k = 0; k < mgc_batch_s::NSTREAMS; ++k)
+    if (hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking) != hipSuccess) {
+      (void)mgc_batch_destroy(b);
+      return fail(MGC_EHIP, "batch streams");
+    }
+  if (hipEventCreateWithFlags(&b->start, hipEventDisableTiming) != hipSuccess) {
+    (void)mgc_batch_destroy(b);
+    return fail(MGC_EHIP, "batch event");
+  }
+  *out = b;
+  return MGC_OK;
+}
+
+mgc_status mgc_batch_solve(mgc_batch b, void* const* u, const void* const* f, const mgc_solve_opts* o,
+                           mgc_stats* stats) {
+  if (!b || !u || !f || !o) return fail(MGC_EINVAL, "null argument");
+  if (o->outer != MGC_FGMRES) return fail(MGC_EINVAL, "batched solves run FGMRES");
+  const int nb = (int)b->g.size();
+  mgc_status rc;
+  for (int i = 0; i < nb; ++i) {
+    if ((rc = check_ready(b->g[i]))) return rc;
+    if ((rc = validate_opts(b->g[i], o))) return rc;
+    if (!u[i] || !f[i] || u[i] == f[i]) return fail(MGC_EINVAL, "bad field pointers in batch");
+  }
+  constexpr int NS = mgc_batch_s::NSTREAMS;
+  mgc_grid g0 = b->g[0];
+  hipStream_t s = g0->stream;
+  std::vector<BatchSolve> v(nb);
+  auto cleanup = [&]() {
+    for (BatchSolve& x : v)
+      if (x.exec) {
+        (void)hipGraphExecDestroy(x.exec);
+        x.exec = nullptr;
+      }
+    for (int i = 0; i < nb; ++i)
+      if (v[i].saved) b->g[i]->stream = v[i].saved;
+  };
+  const auto t0 = std::chrono::steady_clock::now();
+  // every handle works on the batch stream for the duration of the call
+  for (int i = 0; i < nb; ++i) {
+    v[i].saved = b->g[i]->stream;
+    b->g[i]->stream = s;
+    v[i].u = u[i];
+    v[i].f = f[i];
+  }
+  // initial residuals W_0 = f - A u
+  for (int i = 0; i < nb; ++i) {
+    mgc_grid g = b->g[i];
+    if (g->basis_dirty) {
+      if (!hip_ok(g, hipMemsetAsync(g->at<double2>(g->W), 0,
+                                    (size_t)(g->d.max_restart + 1) * g->field_bytes(0, P64), s),
+                  "hipMemsetAsync")) {
+        cleanup();
+        return MGC_EHIP;
+      }
+      g->basis_dirty = false;
+    }
+    double rr = 0, ff = 0;
+    if ((rc = exact_residual(g, u[i], f[i], g->at<double2>(g->W), &rr, &ff, gmres_state(g).nrm2))) {
+      cleanup();
+      return rc;
+    }
+    v[i].fn = std::sqrt(ff);
+    v[i].rel = std::sqrt(rr) / v[i].fn;
+    if (stats) record(&stats[i], 0, v[i].rel);
+    v[i].active = v[i].rel > o->tol && std::isfinite(v[i].rel);
+  }
+  if (!hip_ok(g0, hipEventRecord(b->start, s), "hipEventRecord")) {
+    cleanup();
+    return MGC_EHIP;
+  }
+  for (int k = 0; k < NS; ++k)
+    if (!hip_ok(g0, hipStreamWaitEvent(b->side[k], b->start, 0), "hipStreamWaitEvent")) {
+      cleanup();
+      return MGC_EHIP;
+    }
+  const int m = o->restart;
+  while (true) {
+    int nact = 0;
+    for (int i = 0; i < nb; ++i) {
+      BatchSolve& x = v[i];
+      if (!x.active) continue;
+      const int mm = std::min(m, o->max_it - x.it);
+      if (!x.exec || mm != x.mm) {
+        x.mm = mm;
+        if ((rc = capture_cycle(b->g[i], x, o))) {
+          cleanup();
+          return rc;
+        }
+      }
+      if (!hip_ok(b->g[i], hipGraphLaunch(x.exec, b->side[nact % NS]), "hipGraphLaunch")) {
+        cleanup();
+        return MGC_EHIP;
+      }
+      ++nact;
+    }
+    if (nact == 0) break;
+    for (int k = 0; k < std::min(NS, nact); ++k)
+      if (!hip_ok(g0, hipStreamSynchronize(b->side[k]), "hipStreamSynchronize")) {
+        cleanup();
+        return MGC_EHIP;
+      }
+    for (int i = 0; i < nb; ++i) {
+      BatchSolve& x = v[i];
+      if (!x.active) continue;
+      mgc_grid g = b->g[i];
+      double r[3];
+      if (!hip_ok(g, hipMemcpy(r, g->at<double>(g->scal) + REPORT, sizeof(r), hipMemcpyDeviceToHost),
+                  "hipMemcpy")) {
+        cleanup();
+        return MGC_EHIP;
+      }
+      const int kused = (int)r[2];
+      x.it += std::min(kused, x.mm);
+      x.rel = std::sqrt(r[0]) / x.fn;
+      ++x.rs;
+      if (stats) record(&stats[i], x.rs, x.rel);
+      if (x.rel <= o->tol || x.it >= o->max_it || !std::isfinite(x.rel)) x.active = false;
+    }
+  }
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  cleanup();
+  mgc_status first = MGC_OK;
+  for (int i = 0; i < nb; ++i) {
+    BatchSolve& x = v[i];
+    if (!std::isfinite(x.rel)) {
+      x.status = MGC_ENUMERIC;
+      b->g[i]->basis_dirty = true;
+    } else if (x.rel > o->tol) {
+      x.status = MGC_ENOCONV;
+    }
+    if (stats) {
+      stats[i].iters = x.it;
+      stats[i].vcycles = x.it;
+      stats[i].relres = x.rel;
+      stats[i].t_solve_ms = ms;
+      stats[i].t_setup_ms = b->g[i]->t_setup_ms;
+    }
+    if (first == MGC_OK && x.status != MGC_OK) first = x.status;
+  }
+  if (first == MGC_ENUMERIC) return fail(MGC_ENUMERIC, "non-finite residual in a batched solve");
+  if (first == MGC_ENOCONV) return fail(MGC_ENOCONV, "iteration limit reached in a batched solve");
+  return MGC_OK;
+}
+
+mgc_status mgc_batch_destroy(mgc_batch b) {
+  if (!b) return fail(MGC_EINVAL, "null batch");
+  for (hipStream_t& st : b->side)
+    if (st) (void)hipStreamDestroy(st);
+  if (b->start) (void)hipEventDestroy(b->start);
+  delete b;
+  return MGC_OK;
+}
+
 mgc_status mgc_destroy_grid(mgc_grid g) {
   if (!g) return fail(MGC_EINVAL, "null handle");
   if (g->graph.exec) (void)hipGraphExecDestroy(g->graph.exec);

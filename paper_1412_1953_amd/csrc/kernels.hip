@@ -1769,6 +1769,16 @@ void launch_gmres_solve(hipStream_t s, const GmresState& st, int m, int mm) {
 void launch_ir_scale(hipStream_t s, const double* nrm2, double Nn, double* sc) {
   hipLaunchKernelGGL(k_ir_scale, dim3(1), dim3(1), 0, s, nrm2, Nn, sc);
 }
+__global__ void k_report(const double* __restrict__ scal, const int* __restrict__ kused, double* rep) {
+  if (threadIdx.x == 0) {
+    rep[0] = scal[0];
+    rep[1] = scal[1];
+    rep[2] = (double)kused[0];
+  }
+}
+void launch_report(hipStream_t s, const double* scal, const int* kused, double* rep) {
+  hipLaunchKernelGGL(k_report, dim3(1), dim3(64), 0, s, scal, kused, rep);
+}
 void launch_copy_scalar(hipStream_t s, const double* src, double* dst) {
   hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, s, src, dst);
 }

@@ -25,6 +25,7 @@ EXPORTED = ["mgc_create_grid", "mgc_workspace_bytes", "mgc_bind_workspace", "mgc
             "mgc_set_potential", "mgc_set_energy", "mgc_build_rhs_tp", "mgc_residual", "mgc_vcycle",
             "mgc_cccs", "mgc_solve", "mgc_solve_transpose", "mgc_cross_section",
             "mgc_cross_section_grad", "mgc_set_kernel_timer", "mgc_read_kernel_timer",
+            "mgc_batch_create", "mgc_batch_solve", "mgc_batch_destroy",
             "mgc_destroy_grid", "mgc_last_error"]
 
 # kernel classes of mgc_set_kernel_timer
@@ -87,6 +88,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                    ctypes.POINTER(Stats)],
         "mgc_set_kernel_timer": [vp, i],
         "mgc_read_kernel_timer": [vp, ctypes.POINTER(KernelTiming)],
+        "mgc_batch_create": [ctypes.POINTER(vp), i, ctypes.POINTER(vp)],
+        "mgc_batch_solve": [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(SolveOpts),
+                            ctypes.POINTER(Stats)],
+        "mgc_batch_destroy": [vp],
         "mgc_destroy_grid": [vp],
     }
     for name, args in sig.items():
@@ -265,3 +270,48 @@ class Grid:
 def k0_of(E: float, Z1: float = 1.0) -> float:
     """Incoming momentum sqrt(2(E + Z1^2/2)) of the 1s target."""
     return math.sqrt(2.0 * (E + 0.5 * Z1 * Z1))
+
+
+class Batch:
+    """Handles solved together (mgc_batch_*): one parent graph launch and one
+    synchronisation per restart round for all unfinished solves."""
+
+    def __init__(self, grids):
+        self.lib = load_library()
+        self.grids = list(grids)             # keep the handles alive
+        arr = (ctypes.c_void_p * len(self.grids))(*[g.h.value for g in self.grids])
+        h = ctypes.c_void_p()
+        _check(self.lib.mgc_batch_create(arr, len(self.grids), ctypes.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self.lib.mgc_batch_destroy(h)
+            self.h = None
+
+    def solve(self, us, fs, inner=FP32, restart=10, max_it=20000, tol=1e-10, hist_cap=4096):
+        """Solve grids[i] u_i = f_i for all i; returns one SolveResult each."""
+        nb = len(self.grids)
+        assert len(us) == nb and len(fs) == nb
+        opts = SolveOpts(FGMRES, inner, restart, max_it, 1, tol)
+        hists = [(ctypes.c_double * hist_cap)() for _ in range(nb)]
+        st = (Stats * nb)()
+        for i in range(nb):
+            st[i] = Stats(0, 0, 0.0, ctypes.cast(hists[i], ctypes.POINTER(ctypes.c_double)), hist_cap, 0,
+                          0.0, 0.0)
+        up = (ctypes.c_void_p * nb)(*[x.data_ptr() for x in us])
+        fp = (ctypes.c_void_p * nb)(*[x.data_ptr() for x in fs])
+        _check(self.lib.mgc_batch_solve(self.h, up, fp, ctypes.byref(opts), st),
+               allow=(MGC_ENOCONV, MGC_ENUMERIC))
+        out = []
+        for i in range(nb):
+            s = st[i]
+            status = MGC_OK
+            if not math.isfinite(s.relres):
+                status = MGC_ENUMERIC
+            elif s.relres > tol:
+                status = MGC_ENOCONV
+            out.append(SolveResult(status, s.iters, s.vcycles, s.relres,
+                                   [hists[i][k] for k in range(s.hist_len)], s.t_setup_ms, s.t_solve_ms))
+        return out
