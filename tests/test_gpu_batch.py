@@ -169,3 +169,46 @@ def test_batch_of_64_mixed_size_solves():
     print(f"64 solves, {unknowns} unknowns, {sum(r.iters for r in res)} iterations: setup {t_setup:.1f} s, "
           f"batch {t_batch:.2f} s ({unknowns / t_batch:.3e} solved unknowns/s), one by one "
           f"{t_single:.2f} s ({unknowns / t_single:.3e})")
+
+
+def test_batch_of_mixed_sizes_against_one_by_one():
+    """Twelve solves of the mixed-size workload (four each of 257^2, 513^2,
+    1025^2; FP32 cycle in FP64 FGMRES): every solve to 1e-10 and bit-equal to
+    its individual solve; batch wall time against the same solves one by one."""
+    import torch
+    from paper_1412_1953_amd import mgcccs
+    from paper_1412_1953_amd.workloads import initial_guess
+    wls = batch_workloads()
+    pick = []
+    for n in (256, 512, 1024):
+        pick += [w for w in wls if w.n == n][:4]
+    grids, chis = [], []
+    for w in pick:
+        g = mgcccs.Grid.from_workload(w, pc_gamma=GAM, max_restart=10, fp32=True)
+        g.set_potential(w.Z1, w.Z2, w.lam)
+        g.set_energy(w.E)
+        grids.append(g)
+        chis.append(g.build_rhs_tp(g.field()))
+    us = [g.from_numpy(initial_guess(w.n, w.seed)) for g, w in zip(grids, pick)]
+    batch = mgcccs.Batch(grids)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = batch.solve(us, chis, inner=mgcccs.FP32, restart=10, max_it=20000, tol=1e-10)
+    t_batch = time.perf_counter() - t0
+    for w, r in zip(pick, res):
+        assert r.status == mgcccs.MGC_OK and r.relres <= 1e-10, (w.name, r.iters, r.relres)
+    t0 = time.perf_counter()
+    single = []
+    for g, w, chi in zip(grids, pick, chis):
+        ui = g.from_numpy(initial_guess(w.n, w.seed))
+        single.append((ui, g.solve(ui, chi, outer=mgcccs.FGMRES, inner=mgcccs.FP32, restart=10,
+                                   max_it=20000, tol=1e-10)))
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    for u, r, (ui, ri) in zip(us, res, single):
+        assert r.iters == ri.iters
+        assert np.array_equal(to_np(u), to_np(ui))
+    unknowns = sum(w.unknowns for w in pick)
+    print(f"12 solves, {unknowns} unknowns, iterations {[r.iters for r in res]}: batch {t_batch:.3f} s "
+          f"({unknowns / t_batch:.3e} solved unknowns/s), one by one {t_single:.3f} s "
+          f"({unknowns / t_single:.3e})")
