@@ -687,89 +687,119 @@ __global__ void __launch_bounds__(512) k_cccs_reduce(int n, int ntiles, ChanTab<
 int launch_cccs_reduce_blocks(int n) { return (n - 1 + RB - 1) / RB; }
 
 // Block recurrences of the channel solves, one wave per recurrence.  A step
-// is a small mat-vec y = A_q x with A_q an Mr x Mr block (Mr <= MC) and x the
-// previous step's result.  Lane = (group, row), MC lanes per group, NG =
-// 64 / MC groups: the lane of row i holds row i of A_q in registers and reads
-// x from LDS as a broadcast, so a step costs one LDS round trip and no
-// shuffles.  Step q belongs to group q mod NG, and a round is NG consecutive
-// steps.  Each lane keeps NSET register sets, one per round in flight: the
-// steps of round r read set r mod NSET only, and the set is refilled (all
-// lanes, one batch) when its round ends, for round r + NSET.  With NSET = 3 a
-// matrix row is requested two rounds before its step and no set is read
-// while a load into it is still pending (NSET = 1 where three sets of wide
-// rows would not fit in registers).  LDS rows zs[l][0..MC) are zero beyond Mr.
-template <typename T, int MC> struct StepRow {
-  v2<T> a[MC];
+// is a small mat-vec with an Mr x Mr block A_q (Mr <= MC) and the previous
+// step's vector.  The block is spread over the whole wave: lane = (row, part),
+// PPR lanes per row, each holding EPL entries A_q[row][part + PPR e]; the
+// vector entries come from LDS (one broadcast row), the row sums from DPP
+// lane permutations inside each group of PPR lanes (no LDS round trip, no
+// bpermute), and the part-0 lane of each row stores the result row.  Every
+// lane works on every step, so a prefetch ring of PD steps in registers keeps
+// the block loads PD steps ahead: step q reads ring slot q mod PD and refills
+// it for step q + PD.  LDS rows zs[l][0..MC) are zero beyond Mr.
+template <int MC> struct LaneSplit {
+  static constexpr int PPR = MC <= 8 ? MC : 64 / MC;            // lanes per row
+  static constexpr int EPL = MC / PPR;                            // entries per lane
+  static constexpr int PD = EPL == 1 ? 8 : (EPL <= 4 ? 4 : 2);    // prefetch ring depth
+};
+
+// v of lane l replaced by v of the lane the DPP control selects (within rows
+// of 16 lanes); 64-bit values move as two 32-bit halves
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+// sum over each group of PPR consecutive lanes (PPR = 2, 4 or 8), in every lane
+template <int PPR, typename T>
+__device__ __forceinline__ v2<T> group_sum(v2<T> v) {
+  if (PPR >= 2) v = mk<T>(v.x + dpp_mov<0xB1>(v.x), v.y + dpp_mov<0xB1>(v.y));     // lane ^ 1
+  if (PPR >= 4) v = mk<T>(v.x + dpp_mov<0x4E>(v.x), v.y + dpp_mov<0x4E>(v.y));     // lane ^ 2
+  if (PPR >= 8) v = mk<T>(v.x + dpp_mov<0x141>(v.x), v.y + dpp_mov<0x141>(v.y));   // 7 - lane in 8
+  return v;
+}
+
+template <typename T, int EPL> struct StepEnt {
+  v2<T> a[EPL];
   v2<T> c;
 };
 
-// Row `row` of block idx of A (Mr x Mr, row-major) and the step scalar
-// cv[idx] (HASC).  Addresses are clamped instead of masked, so that no value
-// is selected right after its load (which would force an early wait): rows
-// beyond Mr repeat row Mr-1 (their results are never stored) and columns
-// beyond Mr repeat column Mr-1 (they meet zero vector entries).
+// entries A[idx][row][part + PPR e] and the step scalar cv[idx] (HASC), with
+// clamped indices (rows beyond Mr repeat row Mr-1, columns beyond Mr repeat
+// column Mr-1 and meet zero vector entries), so no loaded value is masked
 template <typename T, int MC, bool HASC>
-__device__ __forceinline__ void load_step(StepRow<T, MC>& r, const v2<T>* __restrict__ A, int Mr, int row,
-                                          const v2<T>* __restrict__ cv, int idx) {
+__device__ __forceinline__ void load_ent(StepEnt<T, LaneSplit<MC>::EPL>& r, const v2<T>* __restrict__ A, int Mr,
+                                         int row, int part, const v2<T>* __restrict__ cv, int idx) {
+  constexpr int PPR = LaneSplit<MC>::PPR, EPL = LaneSplit<MC>::EPL;
   const int rr = row < Mr ? row : Mr - 1;
   const v2<T>* Ar = A + ((size_t)idx * Mr + rr) * Mr;
 #pragma unroll
-  for (int m = 0; m < MC; ++m) r.a[m] = Ar[m < Mr ? m : Mr - 1];
+  for (int e = 0; e < EPL; ++e) {
+    const int m = part + PPR * e;
+    r.a[e] = Ar[m < Mr ? m : Mr - 1];
+  }
   if (HASC) r.c = cv[idx];
 }
 
-template <typename T, int MC>
-__device__ __forceinline__ v2<T> step_dot(const StepRow<T, MC>& r, const v2<T>* x) {
-  v2<T> s0 = mk<T>(0, 0), s1 = mk<T>(0, 0);
-#pragma unroll
-  for (int m = 0; m < MC; m += 2) {
-    s0 = cfma(s0, r.a[m], x[m]);
-    s1 = cfma(s1, r.a[m + 1], x[m + 1]);
-  }
-  return cadd(s0, s1);
-}
-
-// One pipelined sweep over zs[0..len) (LDS, MC entries per row).
-//   FWD:  step q = 0..len-1 on row q, block base+q, previous row q-1:
-//         z_q = b_q - c_q A_q z_{q-1}   (no product at q = 0)
-//   !FWD: step q = 0..len-2 on row l = len-2-q, block base+l, previous row l+1:
-//         z_l = b_l - c_l A_l z_{l+1}
-// b = A_q zs[row] when PROD_B (the row holds a right-hand side still to be
-// multiplied by the step's block), else b = zs[row] itself; c = 1 unless HASC.
-template <typename T, int MC, bool FWD, bool PROD_B, bool HASC, int NSET>
+// One sweep over zs[0..len) (LDS, MC entries per row).
+//   FWD (chain forward, PRE):  step q on row q with block base+q:
+//        z_q = A_q (zs_q - c_q z_{q-1})      (zs_q holds the right-hand side)
+//   FWD (interface forward):   z_q = zs_q - A_q z_{q-1}   (no product at q = 0)
+//   !FWD: step q on row l = len-2-q with block base+l:
+//        z_l = zs_l - c_l A_l z_{l+1}        (c = 1 unless HASC)
+template <typename T, int MC, bool FWD, bool PRE, bool HASC>
 __device__ __forceinline__ void lds_sweep(v2<T>* zs, int len, const v2<T>* __restrict__ A,
                                           const v2<T>* __restrict__ cv, int base, int Mr) {
-  constexpr int NG = 64 / MC;
-  const int lane = threadIdx.x, grp = lane / MC, row = lane % MC;
+  constexpr int PPR = LaneSplit<MC>::PPR, EPL = LaneSplit<MC>::EPL, PD = LaneSplit<MC>::PD;
+  const int lane = threadIdx.x, row = lane / PPR, part = lane % PPR;
+  const bool writer = part == 0 && row < Mr;
   const int nsteps = FWD ? len : len - 1;
   if (nsteps <= 0) return;
-  // block index of step q (steps past the end reload the last block; unused)
   auto blk = [&](int q) {
     const int qc = q < nsteps ? q : nsteps - 1;
     return base + (FWD ? qc : len - 2 - qc);
   };
-  StepRow<T, MC> R[NSET];
+  StepEnt<T, EPL> R[PD];
 #pragma unroll
-  for (int h = 0; h < NSET; ++h) load_step<T, MC, HASC>(R[h], A, Mr, row, cv, blk(grp + h * NG));
-  for (int q0 = 0; q0 < nsteps; q0 += NSET * NG) {
+  for (int d = 0; d < PD; ++d) load_ent<T, MC, HASC>(R[d], A, Mr, row, part, cv, blk(d));
+  for (int q0 = 0; q0 < nsteps; q0 += PD) {
 #pragma unroll
-    for (int h = 0; h < NSET; ++h) {
+    for (int d = 0; d < PD; ++d) {
+      const int q = q0 + d;
+      if (q < nsteps) {
+        const int l = FWD ? q : len - 2 - q;
+        const v2<T>* zl = zs + l * MC;
+        const v2<T>* zp = zs + (FWD ? l - 1 : l + 1) * MC;
+        v2<T> acc = mk<T>(0, 0);
+        if (FWD && PRE) {
+          const v2<T> c = R[d].c;
 #pragma unroll
-      for (int g = 0; g < NG; ++g) {
-        const int q = q0 + h * NG + g;
-        if (q < nsteps) {
-          const int l = FWD ? q : len - 2 - q;
-          const v2<T> b = PROD_B ? step_dot<T, MC>(R[h], zs + l * MC) : zs[l * MC + row];
-          v2<T> z = b;
-          if (!FWD || q > 0) {
-            const v2<T> acc = step_dot<T, MC>(R[h], zs + (FWD ? l - 1 : l + 1) * MC);
-            z = csub(b, HASC ? cmul(R[h].c, acc) : acc);
+          for (int e = 0; e < EPL; ++e) {
+            const int m = part + PPR * e;
+            const v2<T> x = q > 0 ? csub(zl[m], cmul(c, zp[m])) : zl[m];
+            acc = cfma(acc, R[d].a[e], x);
           }
-          if (grp == g && row < Mr) zs[l * MC + row] = z;
-          __syncthreads();                 // one wave: orders the row write before the next reads
+        } else if (!FWD || q > 0) {
+#pragma unroll
+          for (int e = 0; e < EPL; ++e) acc = cfma(acc, R[d].a[e], zp[part + PPR * e]);
         }
+        acc = group_sum<PPR, T>(acc);
+        v2<T> z;
+        if (FWD && PRE) {
+          z = acc;
+        } else {
+          const v2<T> b = zl[row < MC ? row : 0];
+          z = (FWD && q == 0) ? b : csub(b, HASC ? cmul(R[d].c, acc) : acc);
+        }
+        if (writer) zs[l * MC + row] = z;
+        __syncthreads();                   // one wave: orders the row write before the next reads
+        load_ent<T, MC, HASC>(R[d], A, Mr, row, part, cv, blk(q + PD));
       }
-      load_step<T, MC, HASC>(R[h], A, Mr, row, cv, blk(q0 + (h + NSET) * NG + grp));
     }
   }
 }
@@ -863,10 +893,9 @@ __global__ void __launch_bounds__(64) k_cccs_chain(ChanSys<T> SA, ChanSys<T> SB,
     }
   }
   __syncthreads();
-  // (b) forward sweep (the right-hand side is multiplied by G_t in the step),
-  // (c) backward sweep
-  lds_sweep<T, MC, true, true, true, 3>(zs, len, S.G, S.lo, s, M);
-  lds_sweep<T, MC, false, false, true, 3>(zs, len, S.G, S.up, s, M);
+  // (b) forward sweep, (c) backward sweep
+  lds_sweep<T, MC, true, true, true>(zs, len, S.G, S.lo, s, M);
+  lds_sweep<T, MC, false, false, true>(zs, len, S.G, S.up, s, M);
   for (int idx = lane; idx < len * M; idx += 64) {
     const int q = idx / M, i = idx % M;
     g[(size_t)(s + q) * M + i] = zs[q * MC + i];
@@ -930,9 +959,8 @@ __global__ void __launch_bounds__(64) k_cccs_interface(ChanSys<T> SA, ChanSys<T>
   }
   __syncthreads();
   // forward block index q uses Rlo_q (q >= 1); backward row l uses Rup_l
-  constexpr int NS = RC * sizeof(T) >= 256 ? 1 : 3;   // 32 FP64 values per row: one set
-  lds_sweep<T, RC, true, false, false, NS>(zs, Q, S.Rlo, nullptr, 0, R);
-  lds_sweep<T, RC, false, false, false, NS>(zs, Q, S.Rup, nullptr, 0, R);
+  lds_sweep<T, RC, true, false, false>(zs, Q, S.Rlo, nullptr, 0, R);
+  lds_sweep<T, RC, false, false, false>(zs, Q, S.Rup, nullptr, 0, R);
   for (int idx = lane; idx < Q * R; idx += 64) {
     const int q = idx / R, i = idx % R;
     Y[(size_t)q * R + i] = zs[q * RC + i];
