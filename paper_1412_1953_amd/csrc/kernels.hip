@@ -695,11 +695,12 @@ int launch_cccs_reduce_blocks(int n) { return (n - 1 + RB - 1) / RB; }
 // bpermute), and the part-0 lane of each row stores the result row.  Every
 // lane works on every step, so a prefetch ring of PD steps in registers keeps
 // the block loads PD steps ahead: step q reads ring slot q mod PD and refills
-// it for step q + PD.  LDS rows zs[l][0..MC) are zero beyond Mr.
+// it for step q + PD; the steps' scalars are read from LDS, so the ring is
+// the only global load of a step.  LDS rows zs[l][0..MC) are zero beyond Mr.
 template <int MC> struct LaneSplit {
   static constexpr int PPR = MC <= 8 ? MC : 64 / MC;            // lanes per row
   static constexpr int EPL = MC / PPR;                            // entries per lane
-  static constexpr int PD = EPL == 1 ? 8 : (EPL <= 4 ? 4 : 2);    // prefetch ring depth
+  static constexpr int PD = EPL == 1 ? 12 : (EPL <= 4 ? 6 : 2);   // prefetch ring depth
 };
 
 // v of lane l replaced by v of the lane the DPP control selects (within rows
@@ -726,15 +727,14 @@ __device__ __forceinline__ v2<T> group_sum(v2<T> v) {
 
 template <typename T, int EPL> struct StepEnt {
   v2<T> a[EPL];
-  v2<T> c;
 };
 
-// entries A[idx][row][part + PPR e] and the step scalar cv[idx] (HASC), with
-// clamped indices (rows beyond Mr repeat row Mr-1, columns beyond Mr repeat
-// column Mr-1 and meet zero vector entries), so no loaded value is masked
-template <typename T, int MC, bool HASC>
+// entries A[idx][row][part + PPR e] with clamped indices (rows beyond Mr
+// repeat row Mr-1, columns beyond Mr repeat column Mr-1 and meet zero vector
+// entries), so no loaded value is masked
+template <typename T, int MC>
 __device__ __forceinline__ void load_ent(StepEnt<T, LaneSplit<MC>::EPL>& r, const v2<T>* __restrict__ A, int Mr,
-                                         int row, int part, const v2<T>* __restrict__ cv, int idx) {
+                                         int row, int part, int idx) {
   constexpr int PPR = LaneSplit<MC>::PPR, EPL = LaneSplit<MC>::EPL;
   const int rr = row < Mr ? row : Mr - 1;
   const v2<T>* Ar = A + ((size_t)idx * Mr + rr) * Mr;
@@ -743,7 +743,6 @@ __device__ __forceinline__ void load_ent(StepEnt<T, LaneSplit<MC>::EPL>& r, cons
     const int m = part + PPR * e;
     r.a[e] = Ar[m < Mr ? m : Mr - 1];
   }
-  if (HASC) r.c = cv[idx];
 }
 
 // One sweep over zs[0..len) (LDS, MC entries per row).
@@ -752,9 +751,10 @@ __device__ __forceinline__ void load_ent(StepEnt<T, LaneSplit<MC>::EPL>& r, cons
 //   FWD (interface forward):   z_q = zs_q - A_q z_{q-1}   (no product at q = 0)
 //   !FWD: step q on row l = len-2-q with block base+l:
 //        z_l = zs_l - c_l A_l z_{l+1}        (c = 1 unless HASC)
+// cs: the steps' scalars in LDS, indexed by row (HASC).
 template <typename T, int MC, bool FWD, bool PRE, bool HASC>
-__device__ __forceinline__ void lds_sweep(v2<T>* zs, int len, const v2<T>* __restrict__ A,
-                                          const v2<T>* __restrict__ cv, int base, int Mr) {
+__device__ __forceinline__ void lds_sweep(v2<T>* zs, int len, const v2<T>* __restrict__ A, const v2<T>* cs,
+                                          int base, int Mr) {
   constexpr int PPR = LaneSplit<MC>::PPR, EPL = LaneSplit<MC>::EPL, PD = LaneSplit<MC>::PD;
   const int lane = threadIdx.x, row = lane / PPR, part = lane % PPR;
   const bool writer = part == 0 && row < Mr;
@@ -766,7 +766,7 @@ __device__ __forceinline__ void lds_sweep(v2<T>* zs, int len, const v2<T>* __res
   };
   StepEnt<T, EPL> R[PD];
 #pragma unroll
-  for (int d = 0; d < PD; ++d) load_ent<T, MC, HASC>(R[d], A, Mr, row, part, cv, blk(d));
+  for (int d = 0; d < PD; ++d) load_ent<T, MC>(R[d], A, Mr, row, part, blk(d));
   for (int q0 = 0; q0 < nsteps; q0 += PD) {
 #pragma unroll
     for (int d = 0; d < PD; ++d) {
@@ -777,7 +777,7 @@ __device__ __forceinline__ void lds_sweep(v2<T>* zs, int len, const v2<T>* __res
         const v2<T>* zp = zs + (FWD ? l - 1 : l + 1) * MC;
         v2<T> acc = mk<T>(0, 0);
         if (FWD && PRE) {
-          const v2<T> c = R[d].c;
+          const v2<T> c = cs[l];
 #pragma unroll
           for (int e = 0; e < EPL; ++e) {
             const int m = part + PPR * e;
@@ -794,11 +794,11 @@ __device__ __forceinline__ void lds_sweep(v2<T>* zs, int len, const v2<T>* __res
           z = acc;
         } else {
           const v2<T> b = zl[row < MC ? row : 0];
-          z = (FWD && q == 0) ? b : csub(b, HASC ? cmul(R[d].c, acc) : acc);
+          z = (FWD && q == 0) ? b : csub(b, HASC ? cmul(cs[l], acc) : acc);
         }
         if (writer) zs[l * MC + row] = z;
         __syncthreads();                   // one wave: orders the row write before the next reads
-        load_ent<T, MC, HASC>(R[d], A, Mr, row, part, cv, blk(q + PD));
+        load_ent<T, MC>(R[d], A, Mr, row, part, blk(q + PD));
       }
     }
   }
@@ -822,9 +822,11 @@ __global__ void __launch_bounds__(64) k_cccs_chain(ChanSys<T> SA, ChanSys<T> SB,
                                                    const v2<T>* __restrict__ rhoB,
                                                    const v2<T>* __restrict__ partC, int nparts,
                                                    v2<T>* __restrict__ gA, v2<T>* __restrict__ gB,
-                                                   v2<T>* __restrict__ HA, v2<T>* __restrict__ HB) {
+                                                   v2<T>* __restrict__ HA, v2<T>* __restrict__ HB, int maxlen) {
   extern __shared__ __align__(16) unsigned char chain_lds[];
-  v2<T>* zs = reinterpret_cast<v2<T>*>(chain_lds);
+  v2<T>* zs = reinterpret_cast<v2<T>*>(chain_lds);       // [maxlen][MC]
+  v2<T>* slo = zs + (size_t)maxlen * MC;                   // [maxlen] lo_t of the chunk rows
+  v2<T>* sup = slo + maxlen;                               // [maxlen] up_t
   const bool isA = blockIdx.y == 0;
   const ChanSys<T>& S = isA ? SA : SB;
   const int p = blockIdx.x;
@@ -893,9 +895,14 @@ __global__ void __launch_bounds__(64) k_cccs_chain(ChanSys<T> SA, ChanSys<T> SB,
     }
   }
   __syncthreads();
+  for (int q = lane; q < len; q += 64) {
+    slo[q] = S.lo[s + q];
+    sup[q] = S.up[s + q];
+  }
+  __syncthreads();
   // (b) forward sweep, (c) backward sweep
-  lds_sweep<T, MC, true, true, true>(zs, len, S.G, S.lo, s, M);
-  lds_sweep<T, MC, false, false, true>(zs, len, S.G, S.up, s, M);
+  lds_sweep<T, MC, true, true, true>(zs, len, S.G, slo, s, M);
+  lds_sweep<T, MC, false, false, true>(zs, len, S.G, sup, s, M);
   for (int idx = lane; idx < len * M; idx += 64) {
     const int q = idx / M, i = idx % M;
     g[(size_t)(s + q) * M + i] = zs[q * MC + i];
@@ -1647,9 +1654,10 @@ void launch_cccs(hipStream_t s, const Level<T>& L, void* u, const void* f, const
   const int Qmax = P - 1;
 #define MGC_CHAIN(MCC)                                                                                 \
   mark(2, 0);                                                                                          \
-  hipLaunchKernelGGL((k_cccs_chain<T, MCC>), dim3(P, 2), dim3(64), (size_t)maxlen * MCC * sizeof(v2<T>), \
-                     s, SA, SB, ch, n, (const v2<T>*)rhoA, (const v2<T>*)rhoB, (const v2<T>*)partC, nrb, \
-                     gA, gB, (v2<T>*)w.HA, (v2<T>*)w.HB);                                               \
+  hipLaunchKernelGGL((k_cccs_chain<T, MCC>), dim3(P, 2), dim3(64),                                     \
+                     (size_t)maxlen * (MCC + 2) * sizeof(v2<T>), s, SA, SB, ch, n, (const v2<T>*)rhoA,   \
+                     (const v2<T>*)rhoB, (const v2<T>*)partC, nrb, gA, gB, (v2<T>*)w.HA, (v2<T>*)w.HB,   \
+                     maxlen);                                                                           \
   mark(2, 1);                                                                                          \
   if (Qmax > 0)                                                                                        \
     hipLaunchKernelGGL((k_cccs_interface<T, 2 * MCC>), dim3(1, 2), dim3(64),                            \
