@@ -226,7 +226,7 @@ mgc_status mgc_cross_section_grad(mgc_grid g, const void* u, const void* chi, do
 typedef enum {
   MGC_KT_NONE = 0,
   MGC_KT_APPLY_DOT = 1,      /* exact operator + basis dots, each Arnoldi step */
-  MGC_KT_AXPY = 2,           /* both orthogonalisation axpy passes            */
+  MGC_KT_AXPY = 2,           /* first orthogonalisation axpy pass             */
   MGC_KT_S1 = 3,             /* smoothing, residual, restriction (all levels)  */
   MGC_KT_S2 = 4,             /* prolongation, post-smoothing (all levels)      */
   MGC_KT_CCCS_PROJECT = 5,   /* CCCS residual + channel projections            */

@@ -665,12 +665,13 @@ void enqueue_fgmres_cycle(mgc_grid g, void* u, const mgc_solve_opts* o, double t
       launch_apply_dot<double>(st, EX, Zj, stride64, W, j + 1, Wn, p0);
     }
     kt_mark(g, st, ta, 1);
-    // classical Gram-Schmidt with one re-orthogonalisation, then the
+    // classical Gram-Schmidt with a selective second pass, then the
     // Hessenberg column and its Givens rotation on the device
     for (int pass = 0; pass < 2; ++pass) {
-      const int tx = kt_slot(g, MGC_KT_AXPY, Nint * (16.0 * (j + 1) + 32.0));  // J in, Y in and out
+      // timed: the first pass (the second one runs only when needed)
+      const int tx = pass == 0 ? kt_slot(g, MGC_KT_AXPY, Nint * (16.0 * (j + 1) + 32.0)) : -1;  // J in, Y in/out
       kt_mark(g, st, tx, 0);
-      launch_axpy_pass(st, n, pitch, stride64, W, j + 1, Wn, pass ? p1 : p0, pass ? p2 : p1, gs, pass);
+      launch_axpy_pass(st, n, pitch, stride64, W, j + 1, Wn, pass ? p1 : p0, pass ? p2 : p1, gs, pass, p0);
       kt_mark(g, st, tx, 1);
     }
     launch_gmres_step(st, n, pitch, p2, gs, j, m, tol_abs);

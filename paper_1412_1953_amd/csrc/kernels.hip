@@ -1133,6 +1133,10 @@ __device__ void gmres_step_blk(const GmresState& st, int j, int m, double tol_ab
 //   k_apply_dot  : Y = A z_j (exact operator)          per-block c_q = W_q^H Y
 //   k_axpy_pass 0: a_q = s_q^2 c_q, Y -= sum a_q W_q,   per-block c_q = W_q^H Y
 //   k_axpy_pass 1: same with the new c_q,               per-block ||Y||^2
+// The re-orthogonalisation is selective: the operator pass and pass 0 also
+// accumulate ||Y||^2, and pass 1 skips its sweep (forwarding pass 0's norm)
+// when pass 0 kept more than REORTH_ETA of the norm, since one classical pass
+// then loses orthogonality only at the level of rounding / REORTH_ETA.
 //   k_gmres_step : ||Y||, Hessenberg column j and its Givens rotation
 // Three sweeps of (J + 2) vectors per step.  s_q = 1/||W_q|| (unscaled basis).
 // No pass finishes its own reduction: a per-block fence and ticket would cost
@@ -1147,11 +1151,13 @@ __device__ void gmres_step_blk(const GmresState& st, int j, int m, double tol_ab
 constexpr int AB = 512;          // threads per block of the Arnoldi passes
 constexpr int AD_SY = 8;         // k_apply_dot block: 64 columns x 8 row groups
 constexpr int AX_BLOCKS = 256;   // at most this many blocks per Arnoldi pass
+constexpr double REORTH_ETA = 0.05;
 
 // out[q] = sum_b part[b*nq + q] by a block of NT threads (nq <= NT), fixed
 // summation order; ends with a barrier.
 template <int NT>
-__device__ void finish_sum_nt(const double* part, int nb, int nq, double* out) {
+__device__ void finish_sum_nt(const double* part, int nb, int nq, double* out, int stride = 0) {
+  if (stride == 0) stride = nq;
   __shared__ double red[NT];
   const int t = threadIdx.x + blockDim.x * threadIdx.y;
   const int ns = NT / nq;
@@ -1161,10 +1167,10 @@ __device__ void finish_sum_nt(const double* part, int nb, int nq, double* out) {
     double s1 = 0.0;
     int b = sl;
     for (; b + ns < nb; b += 2 * ns) {
-      s += part[(size_t)b * nq + q];
-      s1 += part[(size_t)(b + ns) * nq + q];
+      s += part[(size_t)b * stride + q];
+      s1 += part[(size_t)(b + ns) * stride + q];
     }
-    if (b < nb) s += part[(size_t)b * nq + q];
+    if (b < nb) s += part[(size_t)b * stride + q];
     s += s1;
   }
   red[t] = s;
@@ -1188,9 +1194,9 @@ __global__ void __launch_bounds__(AB) k_apply_dot(Level<double> L, const v2<TZ>*
   const int j = 1 + blockIdx.x * SX + threadIdx.x;
   const int k0 = 1 + (blockIdx.y * AD_SY + threadIdx.y) * rows;
   const int n = L.n, p = L.pitch;
-  double acc[2 * J];
+  double acc[2 * J + 1];
 #pragma unroll
-  for (int q = 0; q < 2 * J; ++q) acc[q] = 0.0;
+  for (int q = 0; q <= 2 * J; ++q) acc[q] = 0.0;
   if (j < n) {
     ColumnStencil<double, v2<TZ>> cs(L, z, j, __builtin_amdgcn_readfirstlane(k0));
 #pragma unroll 2
@@ -1206,28 +1212,40 @@ __global__ void __launch_bounds__(AB) k_apply_dot(Level<double> L, const v2<TZ>*
           acc[2 * q] += w[q].x * o.x + w[q].y * o.y;
           acc[2 * q + 1] += w[q].x * o.y - w[q].y * o.x;
         }
+        acc[2 * J] += o.x * o.x + o.y * o.y;
       }
     }
   }
-  double tot[2 * J];
-  block_sum<2 * J>(acc, tot);
+  double tot[2 * J + 1];
+  block_sum<2 * J + 1>(acc, tot);
   if (threadIdx.x == 0 && threadIdx.y == 0) {
 #pragma unroll
-    for (int q = 0; q < 2 * J; ++q) part[(size_t)flat_block() * 2 * J + q] = tot[q];
+    for (int q = 0; q <= 2 * J; ++q) part[(size_t)flat_block() * (2 * J + 1) + q] = tot[q];
   }
 }
 
-// Flat axpy pass over Nf = (n+1) * pitch nodes.  pin: nbin x 2J per-block
-// dots of the previous pass; pass 0 starts the projections h, pass 1 adds.
+// Flat axpy pass over Nf = (n+1) * pitch nodes.  pin: nbin x (2J + 1)
+// per-block dots and ||Y||^2 of the previous pass; pass 0 starts the
+// projections h, pass 1 adds.  Pass 1 (NORM) also reads the operator pass's
+// partials (p0, nb0 blocks) to decide whether it is needed at all.
 template <int J, bool NORM>
 __global__ void __launch_bounds__(AB) k_axpy_pass(size_t Nf, size_t stride, const double2* __restrict__ W,
                                                   double2* __restrict__ Y, const double* __restrict__ pin,
                                                   int nbin, double* __restrict__ pout, GmresState st,
-                                                  int pass) {
-  constexpr int NV = NORM ? 1 : 2 * J;
-  __shared__ double dsum[2 * J];
+                                                  int pass, const double* __restrict__ p0, int nb0) {
+  constexpr int NV = NORM ? 1 : 2 * J + 1;
+  __shared__ double dsum[2 * J + 1];
+  __shared__ double n0[1];
   __shared__ double2 cf[J];
-  finish_sum_nt<AB>(pin, nbin, 2 * J, dsum);
+  finish_sum_nt<AB>(pin, nbin, 2 * J + 1, dsum);
+  if (NORM) {
+    finish_sum_nt<AB>(p0 + 2 * J, nb0, 1, n0, 2 * J + 1);
+    if (dsum[2 * J] >= REORTH_ETA * REORTH_ETA * n0[0]) {
+      // pass 0 kept enough of the norm: its ||Y||^2 partials are the result
+      if (threadIdx.x == 0) pout[blockIdx.x] = pin[(size_t)blockIdx.x * (2 * J + 1) + 2 * J];
+      return;
+    }
+  }
   if (threadIdx.x < J) {
     const int i = threadIdx.x;
     const double s = st.scale[i], cr = dsum[2 * i], ci = dsum[2 * i + 1];
@@ -1262,6 +1280,7 @@ __global__ void __launch_bounds__(AB) k_axpy_pass(size_t Nf, size_t stride, cons
         acc[2 * q] += w[q].x * y.x + w[q].y * y.y;
         acc[2 * q + 1] += w[q].x * y.y - w[q].y * y.x;
       }
+      acc[2 * J] += y.x * y.x + y.y * y.y;
     }
   }
   double tot[NV];
@@ -1744,16 +1763,17 @@ template void launch_apply_dot<float>(hipStream_t, const Level<double>&, const v
 
 void launch_axpy_pass(hipStream_t s, int n, int pitch, size_t stride, const double2* W, int J,
                       double2* Y, const double* part_in, double* part_out, const GmresState& st,
-                      int pass) {
+                      int pass, const double* part0) {
   const size_t Nf = (size_t)(n + 1) * pitch;
   const int nb = axpy_blocks(n, pitch);
-  const int nbin = pass == 0 ? (int)(apply_dot_grid(n).grid.x * apply_dot_grid(n).grid.y) : nb;
+  const int nb0 = (int)(apply_dot_grid(n).grid.x * apply_dot_grid(n).grid.y);
+  const int nbin = pass == 0 ? nb0 : nb;
 #define MGC_AXN(JT)                                                                                \
   hipLaunchKernelGGL((k_axpy_pass<JT, true>), dim3(nb), dim3(AB), 0, s, Nf, stride, W, Y, part_in,   \
-                     nbin, part_out, st, pass)
+                     nbin, part_out, st, pass, part0, nb0)
 #define MGC_AXD(JT)                                                                                 \
   hipLaunchKernelGGL((k_axpy_pass<JT, false>), dim3(nb), dim3(AB), 0, s, Nf, stride, W, Y, part_in,   \
-                     nbin, part_out, st, pass)
+                     nbin, part_out, st, pass, part0, nb0)
   if (pass == 1) {
     MGC_JSWITCH(MGC_AXN)
   } else {

@@ -90,17 +90,18 @@ void launch_cccs(hipStream_t s, const Level<T>& L, void* u, const void* f, const
 
 // Arnoldi step j of FGMRES over the FP64 basis W_0..W_{J-1} (J = j+1 <= 16),
 // new vector Y = W_{j+1}; part0..part2 hold ARNOLDI_PART doubles each.
-//   apply_dot : Y = A z, per-block dots W^H Y                  -> part0
-//   axpy pass0: coefficients from part0, Y -= ..., dots W^H Y  -> part1
-//   axpy pass1: coefficients from part1, Y -= ..., ||Y||^2     -> part2
+//   apply_dot : Y = A z, per-block dots W^H Y and ||Y||^2                 -> part0
+//   axpy pass0: coefficients from part0, Y -= ..., dots W^H Y, ||Y||^2    -> part1
+//   axpy pass1: if needed (selective re-orthogonalisation) coefficients
+//               from part1, Y -= ..., ||Y||^2; else pass 0's ||Y||^2     -> part2
 //   gmres_step: ||Y|| from part2, Hessenberg column j, Givens rotation
-constexpr int ARNOLDI_PART = 256 * 32;
+constexpr int ARNOLDI_PART = 256 * 33;
 template <typename TZ>
 void launch_apply_dot(hipStream_t s, const Level<double>& L, const void* z, size_t stride,
                       const double2* W, int J, double2* Y, double* part0);
 void launch_axpy_pass(hipStream_t s, int n, int pitch, size_t stride, const double2* W, int J,
                       double2* Y, const double* part_in, double* part_out, const GmresState& st,
-                      int pass);
+                      int pass, const double* part0);
 void launch_gmres_step(hipStream_t s, int n, int pitch, const double* part2, const GmresState& st,
                        int j, int m, double tol_abs);
 template <typename TZ>
