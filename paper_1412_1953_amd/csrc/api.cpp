@@ -446,6 +446,54 @@ void vcycle_level(mgc_grid g, int l, void* u, const void* f, bool zero_guess, co
       if (kt.run >= 0) kt.count[kt.run] = 0;
       kt_mark(g, s, kt.run, 0);
     }
+    const int nl = g->coarsest() - l;
+    if (L.n <= TAIL_MAX_N && nl <= TMAXL) {
+      // coarse tail: every remaining level in two launches
+      TailArgs<T> A{};
+      double b1 = 0.0, b2 = 0.0;
+      for (int i = 0; i <= nl; ++i) {
+        const LevelInfo& Li = g->lv[l + i];
+        if (i < nl) {
+          A.L[i] = level_of<T>(g, l + i);
+          const double nf = (double)(Li.n - 1) * (Li.n - 1), nc = (double)(Li.n / 2 - 1) * (Li.n / 2 - 1);
+          b1 += (nf + nc) * e;                                       // f in, f_c out
+          b2 += (2 * nf + nc) * e;                                   // f, e_c in, u out
+        }
+        A.f[i] = (v2<T>*)(i == 0 ? (void*)f : (void*)(g->ws + Li.ff[p]));
+        A.u[i] = (v2<T>*)(i == 0 ? u : (void*)(g->ws + Li.fu[p]));
+        A.pitch[i] = Li.pitch;
+      }
+      const int ncs = g->lv[g->coarsest()].n;
+      const double Ncs = (double)(ncs - 1) * (ncs - 1);
+      b1 += Ncs * Ncs * 16.0 + Ncs * e;                              // Ainv in, u_c out
+      A.nl = nl;
+      A.nc = ncs;
+      A.Ainv = g->at<const double2>(g->coarse_inv);
+      A.fs = fs;
+      A.omega = (T)om;
+      if (kt.run >= 0 && kt.which == MGC_KT_S1) {
+        kt.bytes[kt.run] += b1;
+        ++kt.count[kt.run];
+      }
+      launch_tail<T>(s, A, true);
+      if (kt.which == MGC_KT_S1) {
+        kt_mark(g, s, kt.run, 1);
+        kt.run = -1;
+      }
+      kt.run = kt_slot(g, MGC_KT_S2, 0.0);
+      if (kt.run >= 0) kt.count[kt.run] = 0;
+      kt_mark(g, s, kt.run, 0);
+      if (kt.run >= 0 && kt.which == MGC_KT_S2) {
+        kt.bytes[kt.run] += b2;
+        ++kt.count[kt.run];
+      }
+      launch_tail<T>(s, A, false);
+      if (l == 0 && kt.which == MGC_KT_S2) {
+        kt_mark(g, s, kt.run, 1);
+        kt.run = -1;
+      }
+      return;
+    }
     if (kt.run >= 0 && kt.which == MGC_KT_S1) {
       kt.bytes[kt.run] += (Nf + Nc) * e;                             // f in, f_c out
       ++kt.count[kt.run];

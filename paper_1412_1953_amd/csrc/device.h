@@ -27,6 +27,21 @@ template <typename T> struct Level {
   T E;
 };
 
+// Coarse tail of the zero-guess V-cycle: smoothing levels lt .. lt+nl-1 (each
+// with n <= 64) and the coarsest level lt+nl, indexed from 0 here.
+constexpr int TMAXL = 4;
+template <typename T> struct TailArgs {
+  Level<T> L[TMAXL];          // smoothing levels
+  v2<T>* f[TMAXL + 1];        // f[0]: input; f[1..nl]: restricted residuals
+  v2<T>* u[TMAXL + 1];        // u[0]: output; u[nl]: coarsest solution
+  int pitch[TMAXL + 1];
+  int nl;                     // number of smoothing levels, 1..TMAXL
+  int nc;                     // n of the coarsest level
+  const double2* Ainv;        // dense inverse on the coarsest level
+  const double* fs;           // optional device scale of f[0]
+  T omega;
+};
+
 // CCCS tables of one precision on level 0.
 template <typename T> struct ChanTab {
   const v2<T>* wphi;   // [M][n+1]  w_j phi_i(z_j)       (x1 channels)

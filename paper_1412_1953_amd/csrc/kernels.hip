@@ -138,33 +138,58 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* out) {
   __syncthreads();
 }
 
-// Second stage of a two-stage reduction, run by one block of 256 threads on
-// partials written by an earlier kernel: out[q] = sum_b part[b*nq + q] (b
-// ascending in slices, slices combined in ascending order), nq <= 256.
-__device__ void finish_sum(const double* part, int nb, int nq, double* out) {
-  __shared__ double red[256];
-  const int t = threadIdx.x + blockDim.x * threadIdx.y;
-  const int ns = 256 / nq;
-  const int q = t % nq, sl = t / nq;
+// Second stage of a two-stage reduction on partials written by an earlier
+// kernel, run by one block of NT threads: out[q] = sum_b part[b*stride + q]
+// (stride defaults to nq; nq <= NT).  Thread slice sl sums b = sl, sl + ns, ...
+// in groups of eight loads issued together (pairwise within a group, groups in
+// ascending order); the slices are then combined in ascending order.  The
+// order depends only on (nb, nq, NT).  Ends with a barrier.
+template <int NT>
+__device__ __forceinline__ double slice_sum(const double* part, int nb, int stride, int q, int sl, int ns) {
   double s = 0.0;
-  if (sl < ns) {
-    // four independent chains keep loads in flight
-    double s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int b = sl;
-    for (; b + 3 * ns < nb; b += 4 * ns) {
-      s += part[(size_t)b * nq + q];
-      s1 += part[(size_t)(b + ns) * nq + q];
-      s2 += part[(size_t)(b + 2 * ns) * nq + q];
-      s3 += part[(size_t)(b + 3 * ns) * nq + q];
+  for (int b0 = sl; b0 < nb; b0 += 8 * ns) {
+    double v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int b = b0 + i * ns;
+      v[i] = b < nb ? part[(size_t)b * stride + q] : 0.0;
     }
-    for (; b < nb; b += ns) s += part[(size_t)b * nq + q];
-    s = (s + s1) + (s2 + s3);
+    s += ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
   }
-  red[t] = s;
+  return s;
+}
+template <int NT>
+__device__ void finish_sum_nt(const double* part, int nb, int nq, double* out, int stride = 0) {
+  if (stride == 0) stride = nq;
+  __shared__ double red[NT];
+  const int t = threadIdx.x + blockDim.x * threadIdx.y;
+  const int ns = NT / nq;
+  const int q = t % nq, sl = t / nq;
+  red[t] = sl < ns ? slice_sum<NT>(part, nb, stride, q, sl, ns) : 0.0;
   __syncthreads();
   if (t < nq) {
     double tot = 0.0;
     for (int w = 0; w < ns; ++w) tot += red[w * nq + t];
+    out[t] = tot;
+  }
+  __syncthreads();
+}
+__device__ void finish_sum(const double* part, int nb, int nq, double* out) {
+  finish_sum_nt<256>(part, nb, nq, out);
+}
+// Two single sums in one pass (half of the block each):
+// out[0] = sum_b a[b*sa], out[1] = sum_b c[b*sc].  Ends with a barrier.
+template <int NT>
+__device__ void finish_sum_pair(const double* a, int na, int sa, const double* c, int nc, int sc,
+                                double* out) {
+  __shared__ double red[NT];
+  const int t = threadIdx.x + blockDim.x * threadIdx.y;
+  constexpr int H = NT / 2;
+  red[t] = t < H ? slice_sum<NT>(a, na, sa, 0, t, H) : slice_sum<NT>(c, nc, sc, 0, t - H, H);
+  __syncthreads();
+  if (t < 2) {
+    double tot = 0.0;
+    for (int w = 0; w < H; ++w) tot += red[t * H + w];
     out[t] = tot;
   }
   __syncthreads();
@@ -367,63 +392,104 @@ __device__ __forceinline__ v2<T> tab_apply(const TileTabs<T, W, H>& tb, T E, con
   return acc;
 }
 
+// S1 tile loads: every thread first takes its points of the residual region
+// (kept in registers for the residual), then at most one halo point, so that
+// only u' needs an LDS tile.
+constexpr int S1NR = (S1RH * S1RW + 255) / 256;                 // residual points per thread
+constexpr int S1NH = (S1H * S1W - S1RH * S1RW + 255) / 256;    // halo points per thread
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_s1_zero(Level<T> L, const v2<T>* __restrict__ f,
                                                  const double* __restrict__ fs, T omega,
                                                  v2<T>* __restrict__ fc, int pitch_c) {
-  __shared__ v2<T> up[S1H][S1W];
-  __shared__ v2<T> fl[S1H][S1W];
-  __shared__ v2<T> rl[S1RH][S1RW];
+  __shared__ v2<T> up[S1H][S1W];          // u', then the residual on the same nodes
   __shared__ TileTabs<T, S1W, S1H> tb;
   const int n = L.n, p = L.pitch, nc = n / 2;
   const int tid = threadIdx.x + 64 * threadIdx.y;
   const int J0 = 1 + blockIdx.x * S1CX, K0 = 1 + blockIdx.y * S1CY;
   const int c0 = 2 * J0 - 2, r0 = 2 * K0 - 2;             // fine origin of the u' tile
   const T sc = fs ? (T)*fs : T(1);
-  constexpr int NL1 = (S1H * S1W + 255) / 256;
-  v2<T> fr[NL1];
-#pragma unroll
-  for (int q = 0; q < NL1; ++q) {          // issue every tile load first
+  // tile position of the thread's q-th residual-region point / halo point
+  auto rpos = [&](int q, int& rr, int& cc) {
     const int idx = tid + 256 * q;
-    const int rr = idx / S1W, cc = idx % S1W;
+    rr = 1 + idx / S1RW;
+    cc = 1 + idx % S1RW;
+    return idx < S1RH * S1RW;
+  };
+  auto hpos = [&](int q, int& rr, int& cc) {
+    const int h = tid + 256 * q;                 // halo: rows 0 and S1H-1, columns 0 and S1W-1
+    if (h < S1W) { rr = 0; cc = h; return true; }
+    if (h < 2 * S1W) { rr = S1H - 1; cc = h - S1W; return true; }
+    const int v = h - 2 * S1W;
+    if (v < 2 * (S1H - 2)) { rr = 1 + (v >> 1); cc = (v & 1) ? S1W - 1 : 0; return true; }
+    return false;
+  };
+  v2<T> fr[S1NR], fh[S1NH];
+#pragma unroll
+  for (int q = 0; q < S1NR; ++q) {         // issue every tile load first
+    int rr, cc;
+    const bool in = rpos(q, rr, cc);
     const int k = r0 + rr, j = c0 + cc;
-    fr[q] = (idx < S1H * S1W && j > 0 && j < n && k > 0 && k < n) ? f[(size_t)k * p + j] : mk<T>(0, 0);
+    fr[q] = (in && j > 0 && j < n && k > 0 && k < n) ? f[(size_t)k * p + j] : mk<T>(0, 0);
+  }
+#pragma unroll
+  for (int q = 0; q < S1NH; ++q) {
+    int rr, cc;
+    const bool in = hpos(q, rr, cc);
+    const int k = r0 + rr, j = c0 + cc;
+    fh[q] = (in && j > 0 && j < n && k > 0 && k < n) ? f[(size_t)k * p + j] : mk<T>(0, 0);
   }
   stage_tabs(tb, L, c0, r0, tid);
   __syncthreads();
-#pragma unroll
-  for (int q = 0; q < NL1; ++q) {
-    const int idx = tid + 256 * q;
-    if (idx >= S1H * S1W) break;
-    const int rr = idx / S1W, cc = idx % S1W;
+  // u' = omega f / d on the whole tile
+  auto put_u = [&](int rr, int cc, v2<T>& fv) {
     const int k = r0 + rr, j = c0 + cc;
-    v2<T> fv = mk<T>(0, 0), uv = mk<T>(0, 0);
+    v2<T> uv = mk<T>(0, 0);
     if (j > 0 && j < n && k > 0 && k < n) {
-      fv = cscale(fr[q], sc);
+      fv = cscale(fv, sc);
       uv = cscale(cdiv(fv, tab_diag(tb, L.E, rr, cc, k, j)), omega);
     }
     up[rr][cc] = uv;
-    fl[rr][cc] = fv;
+  };
+#pragma unroll
+  for (int q = 0; q < S1NR; ++q) {
+    int rr, cc;
+    if (rpos(q, rr, cc)) put_u(rr, cc, fr[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < S1NH; ++q) {
+    int rr, cc;
+    if (hpos(q, rr, cc)) put_u(rr, cc, fh[q]);
   }
   __syncthreads();
-  for (int idx = tid; idx < S1RH * S1RW; idx += 256) {
-    const int rr = 1 + idx / S1RW, cc = 1 + idx % S1RW;
+  // residual r = f - A u' on the residual region (f from registers); it
+  // replaces u' in the tile once every thread has read its neighbours
+#pragma unroll
+  for (int q = 0; q < S1NR; ++q) {
+    int rr, cc;
+    const bool in = rpos(q, rr, cc);
     const int k = r0 + rr, j = c0 + cc;
     v2<T> r = mk<T>(0, 0);
-    if (j > 0 && j < n && k > 0 && k < n) r = csub(fl[rr][cc], tab_apply(tb, L.E, up, rr, cc, k, j));
-    rl[rr - 1][cc - 1] = r;
+    if (in && j > 0 && j < n && k > 0 && k < n) r = csub(fr[q], tab_apply(tb, L.E, up, rr, cc, k, j));
+    fr[q] = r;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < S1NR; ++q) {
+    int rr, cc;
+    if (rpos(q, rr, cc)) up[rr][cc] = fr[q];
   }
   __syncthreads();
   const int J = J0 + threadIdx.x % S1CX, K = K0 + (tid / S1CX);
   if (tid < S1CX * S1CY && J < nc && K < nc) {
-    const int cr = 2 * (K - K0) + 1, ccn = 2 * (J - J0) + 1;   // centre in rl
+    const int cr = 2 * (K - K0) + 2, ccn = 2 * (J - J0) + 2;   // centre in the tile
     v2<T> acc = mk<T>(0, 0);
 #pragma unroll
     for (int a = -1; a <= 1; ++a)
 #pragma unroll
       for (int b = -1; b <= 1; ++b) {
         const T w = T((a == 0 ? 2 : 1) * (b == 0 ? 2 : 1));
-        v2<T> r = rl[cr + a][ccn + b];
+        v2<T> r = up[cr + a][ccn + b];
         acc = mk<T>(acc.x + w * r.x, acc.y + w * r.y);
       }
     fc[(size_t)K * pitch_c + J] = cscale(acc, T(1.0 / 16.0));
@@ -433,14 +499,16 @@ __global__ void __launch_bounds__(256) k_s1_zero(Level<T> L, const v2<T>* __rest
 constexpr int S2TX = 64, S2TY = 16;
 constexpr int S2W = S2TX + 2, S2H = S2TY + 2;
 constexpr int S2CW = S2W / 2 + 2, S2CH = S2H / 2 + 2;    // coarse correction tile
+constexpr int S2NH = (S2H * S2W - S2TX * S2TY + 255) / 256;  // halo points per thread
 
+// S2: the thread's four output points (column 1 + tx, rows 1 + ty + 4q) keep
+// f in registers; only w = u' + P e_c needs an LDS tile.
 template <typename T>
 __global__ void __launch_bounds__(256) k_s2_zero(Level<T> L, const v2<T>* __restrict__ f,
                                                  const double* __restrict__ fs, T omega,
                                                  const v2<T>* __restrict__ ec, int pitch_c,
                                                  v2<T>* __restrict__ u) {
   __shared__ v2<T> wl[S2H][S2W];
-  __shared__ v2<T> fl[S2H][S2W];
   __shared__ v2<T> el[S2CH][S2CW];
   __shared__ TileTabs<T, S2W, S2H> tb;
   const int n = L.n, p = L.pitch, nc = n / 2;
@@ -448,15 +516,29 @@ __global__ void __launch_bounds__(256) k_s2_zero(Level<T> L, const v2<T>* __rest
   const int j0 = 1 + blockIdx.x * S2TX - 1, k0 = 1 + blockIdx.y * S2TY - 1;   // tile origin (halo)
   const int J0 = j0 >> 1, K0 = k0 >> 1;                                       // coarse origin
   const T sc = fs ? (T)*fs : T(1);
-  constexpr int NL2 = (S2H * S2W + 255) / 256;
   constexpr int NLC = (S2CH * S2CW + 255) / 256;
-  v2<T> fr[NL2], er[NLC];
+  constexpr int NO = S2TY / 4;                                                // output rows per thread
+  auto hpos = [&](int q, int& rr, int& cc) {
+    const int h = tid + 256 * q;                 // halo: rows 0 and S2H-1, columns 0 and S2W-1
+    if (h < S2W) { rr = 0; cc = h; return true; }
+    if (h < 2 * S2W) { rr = S2H - 1; cc = h - S2W; return true; }
+    const int v = h - 2 * S2W;
+    if (v < 2 * (S2H - 2)) { rr = 1 + (v >> 1); cc = (v & 1) ? S2W - 1 : 0; return true; }
+    return false;
+  };
+  const int occ = 1 + threadIdx.x;
+  v2<T> fo[NO], fh[S2NH], er[NLC];
 #pragma unroll
-  for (int q = 0; q < NL2; ++q) {          // issue every tile load first
-    const int idx = tid + 256 * q;
-    const int rr = idx / S2W, cc = idx % S2W;
+  for (int q = 0; q < NO; ++q) {           // issue every tile load first
+    const int k = k0 + 1 + threadIdx.y + 4 * q, j = j0 + occ;
+    fo[q] = (j > 0 && j < n && k > 0 && k < n) ? f[(size_t)k * p + j] : mk<T>(0, 0);
+  }
+#pragma unroll
+  for (int q = 0; q < S2NH; ++q) {
+    int rr, cc;
+    const bool in = hpos(q, rr, cc);
     const int k = k0 + rr, j = j0 + cc;
-    fr[q] = (idx < S2H * S2W && j > 0 && j < n && k > 0 && k < n) ? f[(size_t)k * p + j] : mk<T>(0, 0);
+    fh[q] = (in && j > 0 && j < n && k > 0 && k < n) ? f[(size_t)k * p + j] : mk<T>(0, 0);
   }
 #pragma unroll
   for (int q = 0; q < NLC; ++q) {
@@ -472,35 +554,328 @@ __global__ void __launch_bounds__(256) k_s2_zero(Level<T> L, const v2<T>* __rest
     if (idx < S2CH * S2CW) el[idx / S2CW][idx % S2CW] = er[q];
   }
   __syncthreads();
-#pragma unroll
-  for (int q = 0; q < NL2; ++q) {
-    const int idx = tid + 256 * q;
-    if (idx >= S2H * S2W) break;
-    const int rr = idx / S2W, cc = idx % S2W;
+  // w = omega f / d + P e_c (bilinear: mean of the up to four coarse neighbours)
+  auto put_w = [&](int rr, int cc, v2<T>& fv) {
     const int k = k0 + rr, j = j0 + cc;
-    v2<T> fv = mk<T>(0, 0), wv = mk<T>(0, 0);
+    v2<T> wv = mk<T>(0, 0);
     if (j > 0 && j < n && k > 0 && k < n) {
-      fv = cscale(fr[q], sc);
-      // bilinear prolongation: mean of the (up to) four coarse neighbours
+      fv = cscale(fv, sc);
       const int Ja = (j >> 1) - J0, Jb = ((j + 1) >> 1) - J0, Ka = (k >> 1) - K0, Kb = ((k + 1) >> 1) - K0;
       const v2<T> s = cadd(cadd(el[Ka][Ja], el[Ka][Jb]), cadd(el[Kb][Ja], el[Kb][Jb]));
       wv = cadd(cscale(cdiv(fv, tab_diag(tb, L.E, rr, cc, k, j)), omega), cscale(s, T(0.25)));
     }
     wl[rr][cc] = wv;
-    fl[rr][cc] = fv;
+  };
+#pragma unroll
+  for (int q = 0; q < NO; ++q) put_w(1 + threadIdx.y + 4 * q, occ, fo[q]);
+#pragma unroll
+  for (int q = 0; q < S2NH; ++q) {
+    int rr, cc;
+    if (hpos(q, rr, cc)) put_w(rr, cc, fh[q]);
   }
   __syncthreads();
-  const int cc = 1 + threadIdx.x;
-  const int j = j0 + cc;
+  const int j = j0 + occ;
   if (j >= n) return;
-  for (int q = 0; q < S2TY / 4; ++q) {
+#pragma unroll
+  for (int q = 0; q < NO; ++q) {
     const int rr = 1 + threadIdx.y + 4 * q;
     const int k = k0 + rr;
     if (k >= n) break;
-    const v2<T> d = tab_diag(tb, L.E, rr, cc, k, j);
-    const v2<T> res = csub(fl[rr][cc], tab_apply(tb, L.E, wl, rr, cc, k, j));
-    u[(size_t)k * p + j] = cadd(wl[rr][cc], cscale(cdiv(res, d), omega));
+    const v2<T> d = tab_diag(tb, L.E, rr, occ, k, j);
+    const v2<T> res = csub(fo[q], tab_apply(tb, L.E, wl, rr, occ, k, j));
+    u[(size_t)k * p + j] = cadd(wl[rr][occ], cscale(cdiv(res, d), omega));
   }
+}
+
+// ----------------------------------------------------------------------------
+// Coarse tail of the zero-guess V-cycle: the levels with n <= TN are held
+// whole in LDS (one node row of halo on each side is the zero boundary).
+//   k_tail_down: the S1 passes of every tail level, then u_c = Ainv f_c on the
+//     coarsest level.  Each block repeats the (small) S1 passes and takes 16
+//     rows of Ainv, so the coarsest solve needs no second launch; block 0
+//     stores the restricted right-hand sides the up pass needs.
+//   k_tail_up: the S2 passes from the coarsest level up; each block repeats
+//     the passes below the top tail level and takes 16 rows of the top one.
+// The arithmetic per node is that of k_s1_zero / k_s2_zero / k_coarse_solve.
+constexpr int TN = 64, TBW = TN + 1, TSW = TN / 2 + 1;
+constexpr int TT = 1024;                       // threads per tail block
+constexpr int TROWS = TT / 64;                 // Ainv rows per tail-down block
+template <int LV> constexpr int tail_np() {    // nodes per thread on tail level LV
+  return (((TN >> LV) + 1) * ((TN >> LV) + 1) + TT - 1) / TT;
+}
+
+// nodes (k, j) of a level of size n (0..n both ways) owned by thread t
+__device__ __forceinline__ bool tail_node(int t, int q, int n, int& k, int& j) {
+  const int i = t + TT * q, w = n + 1;
+  k = i / w;
+  j = i - k * w;
+  return i < w * w;
+}
+
+template <typename T, int LV, int NP>
+__device__ __forceinline__ void tail_load(v2<T> (&fr)[NP], const TailArgs<T>& A, int t) {
+  const int n = A.L[LV].n, p = A.pitch[LV];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    int k, j;
+    const bool in = tail_node(t, q, n, k, j);
+    fr[q] = (in && j > 0 && j < n && k > 0 && k < n) ? A.f[LV][(size_t)k * p + j] : mk<T>(0, 0);
+  }
+}
+
+// Tables of every tail level, staged once at kernel start (130 threads per
+// level); the caller's barrier publishes them.
+template <typename T>
+__device__ __forceinline__ void tail_tabs(TileTabs<T, TBW, TBW> (&tb)[TMAXL], const TailArgs<T>& A, int t) {
+  const int lv = t / (2 * TBW);
+  if (lv < TMAXL && lv < A.nl) stage_tabs(tb[lv], A.L[lv], 0, 0, t - lv * 2 * TBW);
+}
+
+// one S1 pass on tail level LV: f (registers, scaled by sc) -> f of LV + 1 in
+// sml (and in global memory when store).  Entered after a barrier.
+template <typename T, int LV, int NP>
+__device__ __forceinline__ void tail_s1(const TailArgs<T>& A, v2<T> (&fr)[NP], T sc, v2<T> (*big)[TBW],
+                                        v2<T> (*sml)[TSW], const TileTabs<T, TBW, TBW>& tb, int t,
+                                        bool store) {
+  const Level<T>& L = A.L[LV];
+  const int n = L.n, nc = n / 2;
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    int k, j;
+    if (!tail_node(t, q, n, k, j)) break;
+    v2<T> uv = mk<T>(0, 0);
+    if (j > 0 && j < n && k > 0 && k < n) {
+      fr[q] = cscale(fr[q], sc);
+      uv = cscale(cdiv(fr[q], tab_diag(tb, L.E, k, j, k, j)), A.omega);
+    }
+    big[k][j] = uv;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    int k, j;
+    const bool in = tail_node(t, q, n, k, j);
+    v2<T> r = mk<T>(0, 0);
+    if (in && j > 0 && j < n && k > 0 && k < n) r = csub(fr[q], tab_apply(tb, L.E, big, k, j, k, j));
+    fr[q] = r;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    int k, j;
+    if (tail_node(t, q, n, k, j)) big[k][j] = fr[q];
+  }
+  __syncthreads();
+  const int pc = A.pitch[LV + 1];
+  for (int i = t; i < (nc + 1) * (nc + 1); i += TT) {
+    const int K = i / (nc + 1), J = i - K * (nc + 1);
+    v2<T> acc = mk<T>(0, 0);
+    if (J > 0 && J < nc && K > 0 && K < nc) {
+#pragma unroll
+      for (int a = -1; a <= 1; ++a)
+#pragma unroll
+        for (int b = -1; b <= 1; ++b) {
+          const T w = T((a == 0 ? 2 : 1) * (b == 0 ? 2 : 1));
+          const v2<T> r = big[2 * K + a][2 * J + b];
+          acc = mk<T>(acc.x + w * r.x, acc.y + w * r.y);
+        }
+      acc = cscale(acc, T(1.0 / 16.0));
+      if (store) A.f[LV + 1][(size_t)K * pc + J] = acc;
+    }
+    sml[K][J] = acc;
+  }
+  __syncthreads();
+}
+
+// S1 passes of levels LV .. nl-1 (f of level LV already in registers)
+template <typename T, int LV>
+__device__ __forceinline__ void tail_down_from(const TailArgs<T>& A, v2<T> (&fr)[tail_np<LV>()], T sc,
+                                               v2<T> (*big)[TBW], v2<T> (*sml)[TSW],
+                                               const TileTabs<T, TBW, TBW> (&tb)[TMAXL], int t, bool store) {
+  tail_s1<T, LV>(A, fr, sc, big, sml, tb[LV], t, store);
+  if constexpr (LV + 1 < TMAXL) {
+    if (LV + 1 < A.nl) {
+      constexpr int NQ = tail_np<LV + 1>();
+      v2<T> fn[NQ];
+      const int n = A.L[LV + 1].n;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        int k, j;
+        fn[q] = tail_node(t, q, n, k, j) ? sml[k][j] : mk<T>(0, 0);
+      }
+      tail_down_from<T, LV + 1>(A, fn, T(1), big, sml, tb, t, store);
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TT) k_tail_down(TailArgs<T> A) {
+  __shared__ v2<T> big[TBW][TBW];
+  __shared__ v2<T> sml[TSW][TSW];
+  __shared__ TileTabs<T, TBW, TBW> tb[TMAXL];
+  const int t = threadIdx.x;
+  const int m = A.nc - 1, N = m * m;
+  const int row = blockIdx.x * TROWS + (t >> 6), lane = t & 63;
+  // this wave's row of Ainv (first 256 columns) is fetched while the S1 passes run
+  constexpr int NA = 4;
+  double2 ar[NA];
+#pragma unroll
+  for (int i = 0; i < NA; ++i) {
+    const int c = lane + 64 * i;
+    ar[i] = (row < N && c < N) ? A.Ainv[(size_t)row * N + c] : make_double2(0, 0);
+  }
+  v2<T> fr[tail_np<0>()];
+  tail_load<T, 0>(fr, A, t);
+  tail_tabs(tb, A, t);
+  const T sc = A.fs ? (T)*A.fs : T(1);
+  __syncthreads();
+  tail_down_from<T, 0>(A, fr, sc, big, sml, tb, t, blockIdx.x == 0);
+  if (row >= N) return;
+  double sr = 0, si = 0;
+#pragma unroll
+  for (int i = 0; i < NA; ++i) {
+    const int c = lane + 64 * i;
+    if (c < N) {
+      const v2<double> fv = cvt<double>(sml[c / m + 1][c % m + 1]);
+      sr += ar[i].x * fv.x - ar[i].y * fv.y;
+      si += ar[i].x * fv.y + ar[i].y * fv.x;
+    }
+  }
+  for (int c = lane + 64 * NA; c < N; c += 64) {
+    const double2 av = A.Ainv[(size_t)row * N + c];
+    const v2<double> fv = cvt<double>(sml[c / m + 1][c % m + 1]);
+    sr += av.x * fv.x - av.y * fv.y;
+    si += av.x * fv.y + av.y * fv.x;
+  }
+  sr = wave_sum(sr);
+  si = wave_sum(si);
+  if (lane == 0) {
+    const int k = row / m + 1, j = row % m + 1;
+    A.u[A.nl][(size_t)k * A.pitch[A.nl] + j] = mk<T>((T)sr, (T)si);
+  }
+}
+
+// one S2 pass on tail level LV >= 1: e of level LV + 1 in sml -> e of level
+// LV in sml.  Entered after a barrier.
+template <typename T, int LV, int NP>
+__device__ __forceinline__ void tail_s2(const TailArgs<T>& A, v2<T> (&fr)[NP], T sc, v2<T> (*big)[TBW],
+                                        v2<T> (*sml)[TSW], const TileTabs<T, TBW, TBW>& tb, int t) {
+  const Level<T>& L = A.L[LV];
+  const int n = L.n;
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    int k, j;
+    if (!tail_node(t, q, n, k, j)) break;
+    v2<T> wv = mk<T>(0, 0);
+    if (j > 0 && j < n && k > 0 && k < n) {
+      fr[q] = cscale(fr[q], sc);
+      const int Ja = j >> 1, Jb = (j + 1) >> 1, Ka = k >> 1, Kb = (k + 1) >> 1;
+      const v2<T> s = cadd(cadd(sml[Ka][Ja], sml[Ka][Jb]), cadd(sml[Kb][Ja], sml[Kb][Jb]));
+      wv = cadd(cscale(cdiv(fr[q], tab_diag(tb, L.E, k, j, k, j)), A.omega), cscale(s, T(0.25)));
+    }
+    big[k][j] = wv;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    int k, j;
+    const bool in = tail_node(t, q, n, k, j);
+    v2<T> o = mk<T>(0, 0);
+    if (in && j > 0 && j < n && k > 0 && k < n) {
+      const v2<T> d = tab_diag(tb, L.E, k, j, k, j);
+      const v2<T> res = csub(fr[q], tab_apply(tb, L.E, big, k, j, k, j));
+      o = cadd(big[k][j], cscale(cdiv(res, d), A.omega));
+    }
+    fr[q] = o;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    int k, j;
+    if (tail_node(t, q, n, k, j)) sml[k][j] = fr[q];
+  }
+  __syncthreads();
+}
+
+// The top tail level's S2 pass on output rows [ka, kb) only (w on rows
+// ka-1 .. kb); nodes row-major from row ka-1.
+constexpr int TUPR = 16;                                        // output rows per up block
+constexpr int TNP_TOP = ((TUPR + 2) * TBW + TT - 1) / TT;
+__device__ __forceinline__ bool tail_row_node(int t, int q, int n, int ka, int kb, int& k, int& j) {
+  const int i = t + TT * q, w = n + 1;
+  const int r = i / w;
+  k = ka - 1 + r;
+  j = i - r * w;
+  return k <= kb;
+}
+template <typename T>
+__device__ __forceinline__ void tail_s2_rows(const TailArgs<T>& A, v2<T> (&fr)[TNP_TOP], T sc,
+                                             v2<T> (*big)[TBW], v2<T> (*sml)[TSW],
+                                             const TileTabs<T, TBW, TBW>& tb, int t, int ka, int kb) {
+  const Level<T>& L = A.L[0];
+  const int n = L.n;
+#pragma unroll
+  for (int q = 0; q < TNP_TOP; ++q) {
+    int k, j;
+    if (!tail_row_node(t, q, n, ka, kb, k, j)) break;
+    v2<T> wv = mk<T>(0, 0);
+    if (j > 0 && j < n && k > 0 && k < n) {
+      fr[q] = cscale(fr[q], sc);
+      const int Ja = j >> 1, Jb = (j + 1) >> 1, Ka = k >> 1, Kb = (k + 1) >> 1;
+      const v2<T> s = cadd(cadd(sml[Ka][Ja], sml[Ka][Jb]), cadd(sml[Kb][Ja], sml[Kb][Jb]));
+      wv = cadd(cscale(cdiv(fr[q], tab_diag(tb, L.E, k, j, k, j)), A.omega), cscale(s, T(0.25)));
+    }
+    big[k][j] = wv;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < TNP_TOP; ++q) {
+    int k, j;
+    if (!tail_row_node(t, q, n, ka, kb, k, j)) break;
+    if (k >= ka && k < kb && j > 0 && j < n) {
+      const v2<T> d = tab_diag(tb, L.E, k, j, k, j);
+      const v2<T> res = csub(fr[q], tab_apply(tb, L.E, big, k, j, k, j));
+      A.u[0][(size_t)k * A.pitch[0] + j] = cadd(big[k][j], cscale(cdiv(res, d), A.omega));
+    }
+  }
+}
+
+// Up pass: block b repeats the S2 passes below the top tail level and takes
+// rows [1 + 16 b, 17 + 16 b) of the top level.
+template <typename T>
+__global__ void __launch_bounds__(TT) k_tail_up(TailArgs<T> A) {
+  static_assert(TMAXL == 4, "the up pass is written out for four tail levels");
+  __shared__ v2<T> big[TBW][TBW];
+  __shared__ v2<T> sml[TSW][TSW];
+  __shared__ TileTabs<T, TBW, TBW> tb[TMAXL];
+  const int t = threadIdx.x;
+  const int n0 = A.L[0].n;
+  const int ka = 1 + blockIdx.x * TUPR, kb = min(n0, ka + TUPR);
+  // every load up front: e on the coarsest level, f of each tail level, tables
+  {
+    const int nc = A.nc, p = A.pitch[A.nl];
+    for (int i = t; i < (nc + 1) * (nc + 1); i += TT) {
+      const int K = i / (nc + 1), J = i - K * (nc + 1);
+      sml[K][J] = (J > 0 && J < nc && K > 0 && K < nc) ? A.u[A.nl][(size_t)K * p + J] : mk<T>(0, 0);
+    }
+  }
+  v2<T> f0[TNP_TOP], f1[tail_np<1>()], f2[tail_np<2>()], f3[tail_np<3>()];
+#pragma unroll
+  for (int q = 0; q < TNP_TOP; ++q) {
+    int k, j;
+    const bool in = tail_row_node(t, q, n0, ka, kb, k, j);
+    f0[q] = (in && j > 0 && j < n0 && k > 0 && k < n0) ? A.f[0][(size_t)k * A.pitch[0] + j] : mk<T>(0, 0);
+  }
+  if (A.nl > 1) tail_load<T, 1>(f1, A, t);
+  if (A.nl > 2) tail_load<T, 2>(f2, A, t);
+  if (A.nl > 3) tail_load<T, 3>(f3, A, t);
+  tail_tabs(tb, A, t);
+  const T sc = A.fs ? (T)*A.fs : T(1);
+  __syncthreads();
+  if (A.nl > 3) tail_s2<T, 3>(A, f3, T(1), big, sml, tb[3], t);
+  if (A.nl > 2) tail_s2<T, 2>(A, f2, T(1), big, sml, tb[2], t);
+  if (A.nl > 1) tail_s2<T, 1>(A, f1, T(1), big, sml, tb[1], t);
+  tail_s2_rows<T>(A, f0, sc, big, sml, tb[0], t, ka, kb);
 }
 
 // ----------------------------------------------------------------------------
@@ -618,15 +993,16 @@ __global__ void __launch_bounds__((64 * ProjCfg<T, MC>::W)) k_cccs_project(Level
 // c[i][l] = sum_k w_k varphi_l(k) rho^A[k][i] (eq. coefficients); the chain
 // kernel adds up the blocks.  Each (row, channel) sum is one thread's; the
 // coupling partials use every thread (pairs x row groups, combined in order).
-constexpr int RB = 32;
+constexpr int RB = 32;                   // rows per reduce block
+constexpr int RT = RB * 16;              // threads per reduce block (>= 256 pairs)
 template <typename T>
-__global__ void __launch_bounds__(512) k_cccs_reduce(int n, int ntiles, ChanTab<T> ch,
+__global__ void __launch_bounds__(RT) k_cccs_reduce(int n, int ntiles, ChanTab<T> ch,
                                                      const v2<T>* __restrict__ partA,
                                                      const v2<T>* __restrict__ partB,
                                                      v2<T>* __restrict__ rhoA, v2<T>* __restrict__ rhoB,
                                                      v2<T>* __restrict__ partC) {
   __shared__ v2<T> ra[RB][16], wv[RB][16];
-  __shared__ double pcr[512], pci[512];
+  __shared__ double pcr[RT], pci[RT];
   const int M = ch.M, Lc = ch.L, tid = threadIdx.x;
   const int kb = 1 + blockIdx.x * RB;
   {
@@ -661,7 +1037,7 @@ __global__ void __launch_bounds__(512) k_cccs_reduce(int n, int ntiles, ChanTab<
   }
   __syncthreads();
   const int P = M * Lc;                      // <= 256 pairs
-  const int G = 512 / P;                     // row groups per pair
+  const int G = RT / P;                      // row groups per pair
   const int pair = tid % P, grp = tid / P;
   if (grp < G) {
     const int i = pair / Lc, l = pair % Lc;
@@ -1153,36 +1529,6 @@ constexpr int AD_SY = 8;         // k_apply_dot block: 64 columns x 8 row groups
 constexpr int AX_BLOCKS = 256;   // at most this many blocks per Arnoldi pass
 constexpr double REORTH_ETA = 0.05;
 
-// out[q] = sum_b part[b*nq + q] by a block of NT threads (nq <= NT), fixed
-// summation order; ends with a barrier.
-template <int NT>
-__device__ void finish_sum_nt(const double* part, int nb, int nq, double* out, int stride = 0) {
-  if (stride == 0) stride = nq;
-  __shared__ double red[NT];
-  const int t = threadIdx.x + blockDim.x * threadIdx.y;
-  const int ns = NT / nq;
-  const int q = t % nq, sl = t / nq;
-  double s = 0.0;
-  if (sl < ns) {
-    double s1 = 0.0;
-    int b = sl;
-    for (; b + ns < nb; b += 2 * ns) {
-      s += part[(size_t)b * stride + q];
-      s1 += part[(size_t)(b + ns) * stride + q];
-    }
-    if (b < nb) s += part[(size_t)b * stride + q];
-    s += s1;
-  }
-  red[t] = s;
-  __syncthreads();
-  if (t < nq) {
-    double tot = 0.0;
-    for (int w = 0; w < ns; ++w) tot += red[w * nq + t];
-    out[t] = tot;
-  }
-  __syncthreads();
-}
-
 #define MGC_JFOR(q) _Pragma("unroll") for (int q = 0; q < J; ++q)
 
 // rows: rows per thread (each thread walks `rows` consecutive rows of a column)
@@ -1235,17 +1581,18 @@ __global__ void __launch_bounds__(AB) k_axpy_pass(size_t Nf, size_t stride, cons
                                                   int pass, const double* __restrict__ p0, int nb0) {
   constexpr int NV = NORM ? 1 : 2 * J + 1;
   __shared__ double dsum[2 * J + 1];
-  __shared__ double n0[1];
+  __shared__ double nn[2];
   __shared__ double2 cf[J];
-  finish_sum_nt<AB>(pin, nbin, 2 * J + 1, dsum);
   if (NORM) {
-    finish_sum_nt<AB>(p0 + 2 * J, nb0, 1, n0, 2 * J + 1);
-    if (dsum[2 * J] >= REORTH_ETA * REORTH_ETA * n0[0]) {
+    // ||Y||^2 after pass 0 and before it decide whether pass 1 runs
+    finish_sum_pair<AB>(pin + 2 * J, nbin, 2 * J + 1, p0 + 2 * J, nb0, 2 * J + 1, nn);
+    if (nn[0] >= REORTH_ETA * REORTH_ETA * nn[1]) {
       // pass 0 kept enough of the norm: its ||Y||^2 partials are the result
       if (threadIdx.x == 0) pout[blockIdx.x] = pin[(size_t)blockIdx.x * (2 * J + 1) + 2 * J];
       return;
     }
   }
+  finish_sum_nt<AB>(pin, nbin, 2 * J + 1, dsum);
   if (threadIdx.x < J) {
     const int i = threadIdx.x;
     const double s = st.scale[i], cr = dsum[2 * i], ci = dsum[2 * i + 1];
@@ -1613,13 +1960,24 @@ void launch_s2_zero(hipStream_t s, const Level<T>& L, const void* f, const doubl
                      (const v2<T>*)ec, pitch_c, (v2<T>*)u);
 }
 
+template <typename T>
+void launch_tail(hipStream_t s, const TailArgs<T>& A, bool down) {
+  if (down) {
+    const int N = (A.nc - 1) * (A.nc - 1);
+    hipLaunchKernelGGL((k_tail_down<T>), dim3((N + TROWS - 1) / TROWS), dim3(TT), 0, s, A);
+  } else {
+    hipLaunchKernelGGL((k_tail_up<T>), dim3((A.L[0].n - 1 + TUPR - 1) / TUPR), dim3(TT), 0, s, A);
+  }
+}
+
 #define MGC_INST_LEVEL(T)                                                                      \
   template void launch_jacobi<T>(hipStream_t, const Level<T>&, const void*, const void*, void*, double); \
   template void launch_resid_restrict<T>(hipStream_t, const Level<T>&, const void*, const void*, void*, int); \
   template void launch_prolong_add<T>(hipStream_t, int, int, void*, const void*, int);        \
   template void launch_coarse_solve<T>(hipStream_t, const double2*, int, int, const void*, void*); \
   template void launch_s1_zero<T>(hipStream_t, const Level<T>&, const void*, const double*, double, void*, int); \
-  template void launch_s2_zero<T>(hipStream_t, const Level<T>&, const void*, const double*, double, const void*, int, void*);
+  template void launch_s2_zero<T>(hipStream_t, const Level<T>&, const void*, const double*, double, const void*, int, void*); \
+  template void launch_tail<T>(hipStream_t, const TailArgs<T>&, bool);
 MGC_INST_LEVEL(double)
 MGC_INST_LEVEL(float)
 
@@ -1662,7 +2020,7 @@ void launch_cccs(hipStream_t s, const Level<T>& L, void* u, const void* f, const
 #undef MGC_PROJ
   mark(1, 1);
   const int nrb = launch_cccs_reduce_blocks(n);
-  hipLaunchKernelGGL((k_cccs_reduce<T>), dim3(nrb), dim3(512), 0, s, n, nt, ch, (const v2<T>*)partA,
+  hipLaunchKernelGGL((k_cccs_reduce<T>), dim3(nrb), dim3(RT), 0, s, n, nt, ch, (const v2<T>*)partA,
                      (const v2<T>*)partB, rhoA, rhoB, partC);
   const int P = SA.P > SB.P ? SA.P : SB.P;
   // entries per lane: chains over M x M blocks, interface over 2M x 2M blocks
