@@ -883,16 +883,16 @@ __global__ void __launch_bounds__(TT) k_tail_up(TailArgs<T> A) {
 // tiles; r is never stored.
 //   rho^A[k][i] = sum_j w_j phi_i(j) r[k][j]   -> partA[tile_x][k][i]
 //   rho^B[j][l] = sum_k w_k varphi_l(k) r[k][j] -> partB[tile_y][j][l]
-// Thread = one column, PT / W rows; the block's W waves cover 64 rows (many
-// waves per CU hide the shuffle latency; W = 8 or 4 where 16 waves would not fit
-// the registers of wide channel sets).  The row sums use a transposed
-// butterfly: MC values over 64 lanes in (MC - 1) + (6 - log2 MC) shuffle
-// rounds instead of 6 MC.
+// Thread = one column, PT / W rows; the block's W waves cover 64 rows (W = 8
+// or 4 where 16 waves would not fit the registers of wide channel sets).  All
+// loads are issued together at the start: u on the tile and its halo into
+// LDS, f, the column and row tables; the rows then run from LDS and
+// registers.  The row sums use a transposed butterfly: MC values over 64
+// lanes in (MC - 1) + (6 - log2 MC) shuffle rounds instead of 6 MC.
 constexpr int PT = 64;
 template <typename T, int MC> struct ProjCfg {
   static constexpr int W = MC * sizeof(T) >= 256 ? 4 : (MC * sizeof(T) >= 64 ? 8 : 16);   // waves
   static constexpr int R = PT / W;                           // rows per wave
-  static constexpr int U = W == 4 ? 4 : 2;                   // rows unrolled
 };
 
 template <int MC> constexpr int log2c() { return MC <= 1 ? 0 : 1 + log2c<MC / 2>(); }
@@ -929,46 +929,107 @@ __global__ void __launch_bounds__((64 * ProjCfg<T, MC>::W)) k_cccs_project(Level
                                                           const double* __restrict__ fs, ChanTab<T> ch,
                                                           v2<T>* __restrict__ partA,
                                                           v2<T>* __restrict__ partB) {
-  constexpr int PW = ProjCfg<T, MC>::W, PR = ProjCfg<T, MC>::R;
+  constexpr int PW = ProjCfg<T, MC>::W, PR = ProjCfg<T, MC>::R, NT = 64 * PW;
+  constexpr int UW = PT + 2;                     // u tile with its one-node halo
+  constexpr int NU = (UW * UW + NT - 1) / NT;    // u tile loads per thread
+  constexpr int FR = PR < 8 ? PR : 8;            // rows of f per register batch
+  __shared__ v2<T> ut[UW][UW];
+  __shared__ v2<T> rt[4][PT];                    // per tile row: py, a, c, tm
   __shared__ v2<T> wv[PT][MC];
   __shared__ v2<T> red[64][MC];
   const int n = L.n, p = L.pitch, M = ch.M, Lc = ch.L;
   const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + 64 * ty;
-  const int j = 1 + blockIdx.x * PT + tx;
+  const int j0 = 1 + blockIdx.x * PT, j = j0 + tx;
   const int kb = 1 + blockIdx.y * PT;
+  const bool jok = j < n;
+  const int jc = jok ? j : n - 1;
+  const int kw = __builtin_amdgcn_readfirstlane(kb + PR * ty);   // the wave's first row
+  auto clampi = [&](int x) { return x < 1 ? 1 : (x > n - 1 ? n - 1 : x); };
+  // phase 1: every load at once (clamped addresses; zeros selected at the
+  // LDS writes)
+  v2<T> ul[NU];
+#pragma unroll
+  for (int q = 0; q < NU; ++q) {
+    const int idx = tid + NT * q, rr = idx / UW, cc = idx - rr * UW;
+    ul[q] = u[(size_t)clampi(kb - 1 + rr) * p + clampi(j0 - 1 + cc)];
+  }
+  v2<T> fv[FR];
+#pragma unroll
+  for (int q = 0; q < FR; ++q) fv[q] = f[(size_t)clampi(kw + q) * p + jc];
+  const v2<T> aj = L.a[jc], cj = L.c[jc], pxj = L.px[jc], tmj = L.tm[jc];
+  v2<T> wp[MC];
+#pragma unroll
+  for (int i = 0; i < MC; ++i) wp[i] = ch.wphi[(size_t)(i < M ? i : M - 1) * (n + 1) + jc];
+  v2<T> tv = mk<T>(0, 0);
+  if (tid < 4 * PT) {
+    const int t4 = tid / PT, kc = clampi(kb + tid % PT);
+    const v2<T>* tab = t4 == 0 ? L.py : (t4 == 1 ? L.a : (t4 == 2 ? L.c : L.tm));
+    tv = tab[kc];
+  }
+  constexpr int NW = (PT * MC + NT - 1) / NT;
+  v2<T> wl[NW];
+#pragma unroll
+  for (int q = 0; q < NW; ++q) {
+    const int idx = tid + NT * q, l = idx % MC;
+    wl[q] = ch.wvphi[(size_t)(l < Lc ? l : Lc - 1) * (n + 1) + clampi(kb + idx / MC)];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int q = 0; q < NU; ++q) {
+    const int idx = tid + NT * q, rr = idx / UW, cc = idx - rr * UW;
+    const int k = kb - 1 + rr, jj = j0 - 1 + cc;
+    if (idx < UW * UW) ut[rr][cc] = (k > 0 && k < n && jj > 0 && jj < n) ? ul[q] : mk<T>(0, 0);
+  }
+  if (tid < 4 * PT) rt[tid / PT][tid % PT] = tv;
+#pragma unroll
+  for (int q = 0; q < NW; ++q) {
+    const int idx = tid + NT * q, r = idx / MC, l = idx % MC;
+    if (idx < PT * MC) wv[r][l] = (l < Lc && kb + r < n) ? wl[q] : mk<T>(0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < MC; ++i)
+    if (i >= M || !jok) wp[i] = mk<T>(0, 0);
   const T sc = fs ? (T)*fs : T(1);
-  for (int idx = tid; idx < PT * MC; idx += 64 * PW) {
-    const int r = idx / MC, l = idx % MC, k = kb + r;
-    wv[r][l] = (l < Lc && k < n) ? ch.wvphi[(size_t)l * (n + 1) + k] : mk<T>(0, 0);
-  }
-  v2<T> wp[MC], accB[MC];
-#pragma unroll
-  for (int i = 0; i < MC; ++i) {
-    wp[i] = (i < M && j < n) ? ch.wphi[(size_t)i * (n + 1) + j] : mk<T>(0, 0);
-    accB[i] = mk<T>(0, 0);
-  }
   __syncthreads();
-  constexpr int SH = 6 - log2c<MC>();
-  const int kw = __builtin_amdgcn_readfirstlane(kb + PR * ty);
-  ColumnStencil<T, v2<T>> cs(L, u, j, kw);
-#pragma unroll ProjCfg<T, MC>::U
-  for (int q = 0; q < PR; ++q) {
-    const int k = kw + q;                               // wave-uniform row
-    const int rr = k - kb;
-    if (k >= n) break;
-    v2<T> r = mk<T>(0, 0);
-    const v2<T> Au = cs.step(k);
-    if (j < n) r = csub(cscale(f[(size_t)k * p + j], sc), Au);
-    v2<T> pa[MC];
+  // phase 2: the wave's rows from LDS and registers
+  v2<T> accB[MC];
 #pragma unroll
-    for (int i = 0; i < MC; ++i) {
-      accB[i] = cfma(accB[i], wv[rr][i], r);
-      pa[i] = cmul(wp[i], r);
+  for (int i = 0; i < MC; ++i) accB[i] = mk<T>(0, 0);
+  constexpr int SH = 6 - log2c<MC>();
+  const int uc = tx + 1;
+#pragma unroll
+  for (int q0 = 0; q0 < PR; q0 += FR) {
+    if (q0 > 0) {
+#pragma unroll
+      for (int q = 0; q < FR; ++q) fv[q] = f[(size_t)clampi(kw + q0 + q) * p + jc];
     }
-    butterfly_sum<T, MC>(pa);
-    const int idx = tx >> SH;
-    if ((tx & ((1 << SH) - 1)) == 0 && idx < M)
-      partA[((size_t)blockIdx.x * (n + 1) + k) * M + idx] = pa[0];
+#pragma unroll
+    for (int q = 0; q < FR; ++q) {
+      const int k = kw + q0 + q;                        // wave-uniform row
+      if (k >= n) break;
+      const int rr = k - kb, ur = rr + 1;
+      v2<T> r = mk<T>(0, 0);
+      if (jok) {
+        v2<T> d = cadd(cadd(pxj, rt[0][rr]), j > k ? tmj : rt[3][rr]);
+        d.x -= L.E;
+        v2<T> acc = cmul(d, ut[ur][uc]);
+        acc = cfma(acc, aj, ut[ur][uc - 1]);
+        acc = cfma(acc, cj, ut[ur][uc + 1]);
+        acc = cfma(acc, rt[1][rr], ut[ur - 1][uc]);
+        acc = cfma(acc, rt[2][rr], ut[ur + 1][uc]);
+        r = csub(cscale(fv[q], sc), acc);
+      }
+      v2<T> pa[MC];
+#pragma unroll
+      for (int i = 0; i < MC; ++i) {
+        accB[i] = cfma(accB[i], wv[rr][i], r);
+        pa[i] = cmul(wp[i], r);
+      }
+      butterfly_sum<T, MC>(pa);
+      const int idx = tx >> SH;
+      if ((tx & ((1 << SH) - 1)) == 0 && idx < M)
+        partA[((size_t)blockIdx.x * (n + 1) + k) * M + idx] = pa[0];
+    }
   }
   // rho^B over the block's 64 rows: the waves add their sums in order
   if (ty == 0)
@@ -981,7 +1042,7 @@ __global__ void __launch_bounds__((64 * ProjCfg<T, MC>::W)) k_cccs_project(Level
       for (int l = 0; l < MC; ++l) red[tx][l] = cadd(red[tx][l], accB[l]);
     __syncthreads();
   }
-  if (ty == 0 && j < n) {
+  if (ty == 0 && jok) {
 #pragma unroll
     for (int l = 0; l < MC; ++l)
       if (l < Lc) partB[((size_t)blockIdx.y * (n + 1) + j) * Lc + l] = red[tx][l];
@@ -1019,6 +1080,9 @@ __global__ void __launch_bounds__(RT) k_cccs_reduce(int n, int ntiles, ChanTab<T
         xa[u] = partA[((size_t)(t + u) * (n + 1) + kc) * M + ia];
         xb[u] = partB[((size_t)(t + u) * (n + 1) + kc) * Lc + ib];
       }
+      // keep all 32 loads ahead of the sums (the scheduler would otherwise
+      // wait for each load before issuing the next)
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         sa = cadd(sa, xa[u]);
@@ -1368,8 +1432,9 @@ __global__ void __launch_bounds__(256) k_cccs_retrieve(ChanSys<T> SA, ChanSys<T>
   const v2<T>* Y = isA ? YA : YB;
   v2<T>* e = isA ? eA : eB;
   // chunk of row t: start[p] = floor(N p / P), so p = floor(t P / N) or p + 1
+  // (the boundary is recomputed rather than loaded: no load ahead of the rest)
   int p = (int)(((long long)t * S.P) / S.N);
-  if (p + 1 < S.P && t >= S.start[p + 1]) ++p;
+  if (p + 1 < S.P && t >= (int)(((long long)S.N * (p + 1)) / S.P)) ++p;
   v2<T> v = g[(size_t)t * M + i];
   if (p + 1 < S.P) {
     const v2<T>* Tn = Y + (size_t)p * R + M;
@@ -1392,37 +1457,57 @@ __global__ void __launch_bounds__(256) k_cccs_expand(int n, int pitch, v2<T>* __
                                                      ChanTab<T> ch, const v2<T>* __restrict__ eA,
                                                      const v2<T>* __restrict__ eB) {
   constexpr int BR = SY * ROWS;
+  static_assert(BR * MC <= SX * SY, "one staged factor per thread");
   __shared__ v2<T> ea[BR][MC], vp[BR][MC];
   const int tid = threadIdx.x + SX * threadIdx.y;
   const int kb = 1 + blockIdx.y * BR;
   const int M = ch.M, Lc = ch.L;
-  for (int idx = tid; idx < BR * MC; idx += SX * SY) {
-    const int r = idx / MC, m = idx % MC, k = kb + r;
-    const bool ok = k < n;
-    ea[r][m] = (ok && m < M) ? eA[(size_t)k * M + m] : mk<T>(0, 0);
-    vp[r][m] = (ok && m < Lc) ? ch.vphi[(size_t)m * (n + 1) + k] : mk<T>(0, 0);
-  }
   const int j = 1 + blockIdx.x * SX + threadIdx.x;
+  const bool jok = j < n;
+  const int jc = jok ? j : n - 1;
+  // every load first (clamped indices, selects afterwards): the thread's rows
+  // of u, its column factors, one staged row factor
+  v2<T> uv[ROWS];
+#pragma unroll
+  for (int q = 0; q < ROWS; ++q) {
+    const int k = kb + threadIdx.y * ROWS + q;
+    uv[q] = u[(size_t)(k < n ? k : n - 1) * pitch + jc];
+  }
   v2<T> ph[MC], eb[MC];
 #pragma unroll
   for (int m = 0; m < MC; ++m) {
-    ph[m] = (m < M && j < n) ? ch.phi[(size_t)m * (n + 1) + j] : mk<T>(0, 0);
-    eb[m] = (m < Lc && j < n) ? eB[(size_t)j * Lc + m] : mk<T>(0, 0);
+    ph[m] = ch.phi[(size_t)(m < M ? m : M - 1) * (n + 1) + jc];
+    eb[m] = eB[(size_t)jc * Lc + (m < Lc ? m : Lc - 1)];
+  }
+  const int sr = tid / MC, sm = tid % MC, sk = kb + sr, skc = sk < n ? sk : n - 1;
+  v2<T> sa = mk<T>(0, 0), sv = mk<T>(0, 0);
+  if (tid < BR * MC) {
+    sa = eA[(size_t)skc * M + (sm < M ? sm : M - 1)];
+    sv = ch.vphi[(size_t)(sm < Lc ? sm : Lc - 1) * (n + 1) + skc];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  if (tid < BR * MC) {
+    ea[sr][sm] = (sk < n && sm < M) ? sa : mk<T>(0, 0);
+    vp[sr][sm] = (sk < n && sm < Lc) ? sv : mk<T>(0, 0);
+  }
+#pragma unroll
+  for (int m = 0; m < MC; ++m) {
+    if (m >= M) ph[m] = mk<T>(0, 0);
+    if (m >= Lc) eb[m] = mk<T>(0, 0);
   }
   __syncthreads();
-  if (j >= n) return;
+  if (!jok) return;
 #pragma unroll
   for (int q = 0; q < ROWS; ++q) {
     const int r = threadIdx.y * ROWS + q, k = kb + r;
     if (k >= n) break;
-    const size_t idx = (size_t)k * pitch + j;
-    v2<T> v = u[idx];
+    v2<T> v = uv[q];
 #pragma unroll
     for (int m = 0; m < MC; ++m) {
       v = cfma(v, ea[r][m], ph[m]);
       v = cfma(v, eb[m], vp[r][m]);
     }
-    u[idx] = v;
+    u[(size_t)k * pitch + j] = v;
   }
 }
 
