@@ -886,9 +886,10 @@ __global__ void __launch_bounds__(TT) k_tail_up(TailArgs<T> A) {
 // Thread = one column, PT / W rows; the block's W waves cover 64 rows (W = 8
 // or 4 where 16 waves would not fit the registers of wide channel sets).  All
 // loads are issued together at the start: u on the tile and its halo into
-// LDS, f, the column and row tables; the rows then run from LDS and
-// registers.  The row sums use a transposed butterfly: MC values over 64
-// lanes in (MC - 1) + (6 - log2 MC) shuffle rounds instead of 6 MC.
+// LDS, f, the column and row tables.  The column sums (rho^B) accumulate in
+// registers over the wave's rows; the residual tile then goes to LDS, where
+// the row sums (rho^A) run with lane = row over a slice of columns per wave.
+// Both are combined over the waves in a fixed order (no shuffles).
 constexpr int PT = 64;
 template <typename T, int MC> struct ProjCfg {
   static constexpr int W = MC * sizeof(T) >= 256 ? 4 : (MC * sizeof(T) >= 64 ? 8 : 16);   // waves
@@ -933,10 +934,15 @@ __global__ void __launch_bounds__((64 * ProjCfg<T, MC>::W)) k_cccs_project(Level
   constexpr int UW = PT + 2;                     // u tile with its one-node halo
   constexpr int NU = (UW * UW + NT - 1) / NT;    // u tile loads per thread
   constexpr int FR = PR < 8 ? PR : 8;            // rows of f per register batch
+  constexpr int RP = PT + 1;                     // row pitch of the residual tile (odd: no bank conflicts)
+  constexpr int CPW = PT / PW;                   // columns per wave in the row sums
+  static_assert(PT * RP <= UW * UW, "the residual tile reuses the u tile");
   __shared__ v2<T> ut[UW][UW];
   __shared__ v2<T> rt[4][PT];                    // per tile row: py, a, c, tm
-  __shared__ v2<T> wv[PT][MC];
-  __shared__ v2<T> red[64][MC];
+  __shared__ v2<T> wv[PT][MC];                   // w_k varphi_l(k) of the tile rows
+  __shared__ v2<T> wpl[MC][PT];                  // w_j phi_i(j) of the tile columns
+  __shared__ v2<T> red[64][MC], redA[64][MC];
+  v2<T>* rtile = &ut[0][0];                      // [PT][RP] residual, after the stencil
   const int n = L.n, p = L.pitch, M = ch.M, Lc = ch.L;
   const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + 64 * ty;
   const int j0 = 1 + blockIdx.x * PT, j = j0 + tx;
@@ -957,9 +963,6 @@ __global__ void __launch_bounds__((64 * ProjCfg<T, MC>::W)) k_cccs_project(Level
 #pragma unroll
   for (int q = 0; q < FR; ++q) fv[q] = f[(size_t)clampi(kw + q) * p + jc];
   const v2<T> aj = L.a[jc], cj = L.c[jc], pxj = L.px[jc], tmj = L.tm[jc];
-  v2<T> wp[MC];
-#pragma unroll
-  for (int i = 0; i < MC; ++i) wp[i] = ch.wphi[(size_t)(i < M ? i : M - 1) * (n + 1) + jc];
   v2<T> tv = mk<T>(0, 0);
   if (tid < 4 * PT) {
     const int t4 = tid / PT, kc = clampi(kb + tid % PT);
@@ -967,11 +970,14 @@ __global__ void __launch_bounds__((64 * ProjCfg<T, MC>::W)) k_cccs_project(Level
     tv = tab[kc];
   }
   constexpr int NW = (PT * MC + NT - 1) / NT;
-  v2<T> wl[NW];
+  v2<T> wl[NW], wq[NW];
 #pragma unroll
   for (int q = 0; q < NW; ++q) {
-    const int idx = tid + NT * q, l = idx % MC;
-    wl[q] = ch.wvphi[(size_t)(l < Lc ? l : Lc - 1) * (n + 1) + clampi(kb + idx / MC)];
+    const int idx = tid + NT * q, l = idx % MC, c = idx / MC;
+    wl[q] = ch.wvphi[(size_t)(l < Lc ? l : Lc - 1) * (n + 1) + clampi(kb + c)];
+    // w_j phi_i(j): idx = i * PT + column (coalesced)
+    const int i = idx / PT, cc = idx % PT;
+    wq[q] = ch.wphi[(size_t)(i < M ? i : M - 1) * (n + 1) + clampi(j0 + cc)];
   }
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -983,19 +989,22 @@ __global__ void __launch_bounds__((64 * ProjCfg<T, MC>::W)) k_cccs_project(Level
   if (tid < 4 * PT) rt[tid / PT][tid % PT] = tv;
 #pragma unroll
   for (int q = 0; q < NW; ++q) {
-    const int idx = tid + NT * q, r = idx / MC, l = idx % MC;
-    if (idx < PT * MC) wv[r][l] = (l < Lc && kb + r < n) ? wl[q] : mk<T>(0, 0);
+    const int idx = tid + NT * q;
+    if (idx < PT * MC) {
+      const int r = idx / MC, l = idx % MC;
+      wv[r][l] = (l < Lc && kb + r < n) ? wl[q] : mk<T>(0, 0);
+      const int i = idx / PT, cc = idx % PT;
+      wpl[i][cc] = (i < M && j0 + cc < n) ? wq[q] : mk<T>(0, 0);
+    }
   }
-#pragma unroll
-  for (int i = 0; i < MC; ++i)
-    if (i >= M || !jok) wp[i] = mk<T>(0, 0);
   const T sc = fs ? (T)*fs : T(1);
   __syncthreads();
-  // phase 2: the wave's rows from LDS and registers
-  v2<T> accB[MC];
+  // phase 2: the wave's residual rows (registers) and its rho^B partials
+  v2<T> accB[MC], rr_[PR];
 #pragma unroll
   for (int i = 0; i < MC; ++i) accB[i] = mk<T>(0, 0);
-  constexpr int SH = 6 - log2c<MC>();
+#pragma unroll
+  for (int q = 0; q < PR; ++q) rr_[q] = mk<T>(0, 0);
   const int uc = tx + 1;
 #pragma unroll
   for (int q0 = 0; q0 < PR; q0 += FR) {
@@ -1019,28 +1028,48 @@ __global__ void __launch_bounds__((64 * ProjCfg<T, MC>::W)) k_cccs_project(Level
         acc = cfma(acc, rt[2][rr], ut[ur + 1][uc]);
         r = csub(cscale(fv[q], sc), acc);
       }
-      v2<T> pa[MC];
+      rr_[q0 + q] = r;
 #pragma unroll
-      for (int i = 0; i < MC; ++i) {
-        accB[i] = cfma(accB[i], wv[rr][i], r);
-        pa[i] = cmul(wp[i], r);
-      }
-      butterfly_sum<T, MC>(pa);
-      const int idx = tx >> SH;
-      if ((tx & ((1 << SH) - 1)) == 0 && idx < M)
-        partA[((size_t)blockIdx.x * (n + 1) + k) * M + idx] = pa[0];
+      for (int i = 0; i < MC; ++i) accB[i] = cfma(accB[i], wv[rr][i], r);
     }
   }
-  // rho^B over the block's 64 rows: the waves add their sums in order
+  __syncthreads();                               // every stencil read of u is done
+#pragma unroll
+  for (int q = 0; q < PR; ++q) rtile[(PR * ty + q) * RP + tx] = rr_[q];
+  __syncthreads();
+  // phase 3: rho^A row sums, lane = tile row, wave = a slice of CPW columns
+  v2<T> accA[MC];
+#pragma unroll
+  for (int i = 0; i < MC; ++i) accA[i] = mk<T>(0, 0);
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const int cc = CPW * ty + c;
+    const v2<T> rv = rtile[tx * RP + cc];
+#pragma unroll
+    for (int i = 0; i < MC; ++i) accA[i] = cfma(accA[i], wpl[i][cc], rv);
+  }
+  // the waves add their sums in order (rho^B by column, rho^A by row)
   if (ty == 0)
 #pragma unroll
-    for (int l = 0; l < MC; ++l) red[tx][l] = accB[l];
+    for (int l = 0; l < MC; ++l) {
+      red[tx][l] = accB[l];
+      redA[tx][l] = accA[l];
+    }
   __syncthreads();
   for (int w = 1; w < PW; ++w) {
     if (ty == w)
 #pragma unroll
-      for (int l = 0; l < MC; ++l) red[tx][l] = cadd(red[tx][l], accB[l]);
+      for (int l = 0; l < MC; ++l) {
+        red[tx][l] = cadd(red[tx][l], accB[l]);
+        redA[tx][l] = cadd(redA[tx][l], accA[l]);
+      }
     __syncthreads();
+  }
+  // partA rows kb .. kb+63 of this column tile are contiguous
+  const size_t baseA = ((size_t)blockIdx.x * (n + 1) + kb) * M;
+  for (int idx = tid; idx < PT * M; idx += NT) {
+    const int r = idx / M, i = idx % M;
+    if (kb + r < n) partA[baseA + idx] = redA[r][i];
   }
   if (ty == 0 && jok) {
 #pragma unroll
@@ -1459,6 +1488,7 @@ __global__ void __launch_bounds__(256) k_cccs_expand(int n, int pitch, v2<T>* __
   constexpr int BR = SY * ROWS;
   static_assert(BR * MC <= SX * SY, "one staged factor per thread");
   __shared__ v2<T> ea[BR][MC], vp[BR][MC];
+  __shared__ v2<T> ebt[MC][SX];                  // eB of the block's columns, transposed
   const int tid = threadIdx.x + SX * threadIdx.y;
   const int kb = 1 + blockIdx.y * BR;
   const int M = ch.M, Lc = ch.L;
@@ -1473,11 +1503,18 @@ __global__ void __launch_bounds__(256) k_cccs_expand(int n, int pitch, v2<T>* __
     const int k = kb + threadIdx.y * ROWS + q;
     uv[q] = u[(size_t)(k < n ? k : n - 1) * pitch + jc];
   }
-  v2<T> ph[MC], eb[MC];
+  v2<T> ph[MC];
 #pragma unroll
-  for (int m = 0; m < MC; ++m) {
-    ph[m] = ch.phi[(size_t)(m < M ? m : M - 1) * (n + 1) + jc];
-    eb[m] = eB[(size_t)jc * Lc + (m < Lc ? m : Lc - 1)];
+  for (int m = 0; m < MC; ++m) ph[m] = ch.phi[(size_t)(m < M ? m : M - 1) * (n + 1) + jc];
+  // eB[j][l] of the block's SX columns is contiguous: coalesced loads, then
+  // transposed through LDS (a per-column load would touch one line per lane)
+  constexpr int NEB = (SX * MC + SX * SY - 1) / (SX * SY);
+  const int jb = 1 + blockIdx.x * SX;
+  v2<T> ebl[NEB];
+#pragma unroll
+  for (int q = 0; q < NEB; ++q) {
+    const int idx = tid + SX * SY * q, cj = jb + idx / Lc;
+    ebl[q] = eB[(size_t)(cj < n ? cj : n - 1) * Lc + idx % Lc];
   }
   const int sr = tid / MC, sm = tid % MC, sk = kb + sr, skc = sk < n ? sk : n - 1;
   v2<T> sa = mk<T>(0, 0), sv = mk<T>(0, 0);
@@ -1491,12 +1528,20 @@ __global__ void __launch_bounds__(256) k_cccs_expand(int n, int pitch, v2<T>* __
     vp[sr][sm] = (sk < n && sm < Lc) ? sv : mk<T>(0, 0);
   }
 #pragma unroll
-  for (int m = 0; m < MC; ++m) {
-    if (m >= M) ph[m] = mk<T>(0, 0);
-    if (m >= Lc) eb[m] = mk<T>(0, 0);
+  for (int q = 0; q < NEB; ++q) {
+    const int idx = tid + SX * SY * q;
+    if (idx < SX * Lc) ebt[idx % Lc][idx / Lc] = ebl[q];
   }
+  for (int idx = tid; idx < SX * (MC - Lc); idx += SX * SY)                // unused channels
+    ebt[Lc + idx / SX][idx % SX] = mk<T>(0, 0);
+#pragma unroll
+  for (int m = 0; m < MC; ++m)
+    if (m >= M) ph[m] = mk<T>(0, 0);
   __syncthreads();
   if (!jok) return;
+  v2<T> eb[MC];
+#pragma unroll
+  for (int m = 0; m < MC; ++m) eb[m] = ebt[m][threadIdx.x];
 #pragma unroll
   for (int q = 0; q < ROWS; ++q) {
     const int r = threadIdx.y * ROWS + q, k = kb + r;
