@@ -217,6 +217,11 @@ mgc_status mgc_cross_section_grad(mgc_grid g, const void* u, const void* chi, do
  * Arnoldi step for the classes that depend on the step (APPLY_DOT, AXPY), the
  * first step of each restart cycle for the others.  S1 and S2 launches of
  * all levels follow each other, so one event pair brackets each such run.
+ * Right before each bracket a second event pair brackets one empty kernel
+ * launch: its duration (floor_ms) is what the event nodes and a launch add
+ * to a bracket, so that total_ms - floor_ms estimates the kernels' own time
+ * (short by the empty kernel's own run time).  The empty launch is one more
+ * kernel in the timed restart cycles.
  * The durations, the launch count and the kernels' algorithmic bytes
  * (compulsory loads and stores of their operands over the interior nodes)
  * accumulate until mgc_read_kernel_timer, which returns and clears them.
@@ -236,6 +241,7 @@ typedef struct {
   double total_ms;           /* summed event durations                         */
   long long launches;
   double bytes;              /* summed algorithmic bytes                       */
+  double floor_ms;           /* summed durations of the empty event pairs      */
 } mgc_kernel_timing;
 mgc_status mgc_set_kernel_timer(mgc_grid g, int kernel_class);
 mgc_status mgc_read_kernel_timer(mgc_grid g, mgc_kernel_timing* out);

@@ -67,17 +67,20 @@ struct GraphCache {                       // one captured FGMRES restart cycle
 // brackets one launch or a run of consecutive launches of the class (count).
 // Event record nodes cost a few microseconds each inside a graph, so classes
 // whose launches do not depend on the Arnoldi step are timed in the first
-// step of each restart cycle only (`open`).
+// step of each restart cycle only (`open`).  Right before each bracket a
+// second pair (fev) brackets one empty launch: what the event nodes and a
+// launch add to a bracket, subtracted from the bracketed time.
 struct KernelTimer {
   static constexpr int SLOTS = 4 * MGC_MAX_RESTART;
   int which = MGC_KT_NONE;
   hipEvent_t ev[2 * SLOTS] = {};
+  hipEvent_t fev[2 * SLOTS] = {};
   std::vector<double> bytes = std::vector<double>(SLOTS, 0.0);
   std::vector<int> count = std::vector<int>(SLOTS, 0);
   int used = 0;
   bool open = true;                        // slots may be handed out in this step
   int run = -1;                            // slot of the S1 / S2 run in progress
-  double ms = 0, total_bytes = 0;
+  double ms = 0, floor_ms = 0, total_bytes = 0;
   long long launches = 0;
 };
 
@@ -391,9 +394,17 @@ int kt_slot(mgc_grid g, int kind, double bytes) {
 }
 // While the stream is being captured the event becomes an explicit event
 // record node appended to the capture's current dependencies.
+void kt_record(mgc_grid g, hipStream_t s, hipEvent_t ev);
 void kt_mark(mgc_grid g, hipStream_t s, int slot, int end) {
   if (slot < 0) return;
-  hipEvent_t ev = g->kt.ev[2 * slot + end];
+  if (!end) {
+    kt_record(g, s, g->kt.fev[2 * slot]);
+    launch_nop(s);
+    kt_record(g, s, g->kt.fev[2 * slot + 1]);
+  }
+  kt_record(g, s, g->kt.ev[2 * slot + end]);
+}
+void kt_record(mgc_grid g, hipStream_t s, hipEvent_t ev) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (!hip_ok(g, hipStreamIsCapturing(s, &cs), "timer: capture state")) return;
   if (cs != hipStreamCaptureStatusActive) {
@@ -413,9 +424,11 @@ void kt_mark(mgc_grid g, hipStream_t s, int slot, int end) {
 void kt_harvest(mgc_grid g, int slots, const std::vector<double>& bytes, const std::vector<int>& count) {
   KernelTimer& t = g->kt;
   for (int i = 0; i < slots; ++i) {
-    float ms = 0.0f;
+    float ms = 0.0f, fl = 0.0f;
     if (hipEventElapsedTime(&ms, t.ev[2 * i], t.ev[2 * i + 1]) != hipSuccess) continue;
+    if (hipEventElapsedTime(&fl, t.fev[2 * i], t.fev[2 * i + 1]) != hipSuccess) continue;
     t.ms += ms;
+    t.floor_ms += fl;
     t.total_bytes += bytes[i];
     t.launches += count[i];
   }
@@ -1341,11 +1354,15 @@ mgc_status mgc_set_kernel_timer(mgc_grid g, int kernel_class) {
     return fail(MGC_EINVAL, "unknown kernel class");
   KernelTimer& t = g->kt;
   if (kernel_class != MGC_KT_NONE && !t.ev[0]) {
-    for (int i = 0; i < 2 * KernelTimer::SLOTS; ++i) HIPCHK(g, hipEventCreate(&t.ev[i]));
+    for (int i = 0; i < 2 * KernelTimer::SLOTS; ++i) {
+      HIPCHK(g, hipEventCreate(&t.ev[i]));
+      HIPCHK(g, hipEventCreate(&t.fev[i]));
+    }
   }
   t.which = kernel_class;
   t.used = 0;
   t.ms = 0;
+  t.floor_ms = 0;
   t.total_bytes = 0;
   t.launches = 0;
   return MGC_OK;
@@ -1357,7 +1374,9 @@ mgc_status mgc_read_kernel_timer(mgc_grid g, mgc_kernel_timing* out) {
   out->total_ms = t.ms;
   out->launches = t.launches;
   out->bytes = t.total_bytes;
+  out->floor_ms = t.floor_ms;
   t.ms = 0;
+  t.floor_ms = 0;
   t.total_bytes = 0;
   t.launches = 0;
   return MGC_OK;
@@ -1589,6 +1608,8 @@ mgc_status mgc_destroy_grid(mgc_grid g) {
   if (!g) return fail(MGC_EINVAL, "null handle");
   if (g->graph.exec) (void)hipGraphExecDestroy(g->graph.exec);
   for (hipEvent_t e : g->kt.ev)
+    if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : g->kt.fev)
     if (e) (void)hipEventDestroy(e);
   if (g->cap) (void)hipStreamDestroy(g->cap);
   delete g;

@@ -43,8 +43,6 @@ __device__ __forceinline__ v2<T> ldf(const V* p, int pitch, int k, int j, int n)
   return cvt<T>(p[(size_t)k * pitch + j]);
 }
 
-template <typename T> __device__ __forceinline__ T shfl_xor_t(T v, int m) { return __shfl_xor(v, m, 64); }
-
 __device__ __forceinline__ double wave_sum(double v) {
   for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
   return v;
@@ -896,34 +894,6 @@ template <typename T, int MC> struct ProjCfg {
   static constexpr int R = PT / W;                           // rows per wave
 };
 
-template <int MC> constexpr int log2c() { return MC <= 1 ? 0 : 1 + log2c<MC / 2>(); }
-
-template <typename T, int MC>
-__device__ __forceinline__ void butterfly_sum(v2<T> (&v)[MC]) {
-  const int lane = threadIdx.x & 63;
-  constexpr int LV = log2c<MC>();
-#pragma unroll
-  for (int lev = 0; lev < LV; ++lev) {
-    const int half = MC >> (lev + 1);
-    const int o = 32 >> lev;
-    const bool up = (lane & o) != 0;
-#pragma unroll
-    for (int i = 0; i < MC / 2; ++i) {
-      if (i < half) {
-        const v2<T> lo = v[i], hi = v[i + half];
-        const T sx = up ? lo.x : hi.x, sy = up ? lo.y : hi.y;
-        const T kx = up ? hi.x : lo.x, ky = up ? hi.y : lo.y;
-        v[i] = mk<T>(kx + shfl_xor_t(sx, o), ky + shfl_xor_t(sy, o));
-      }
-    }
-  }
-#pragma unroll
-  for (int lev = LV; lev < 6; ++lev) {
-    const int o = 32 >> lev;
-    v[0].x += shfl_xor_t(v[0].x, o);
-    v[0].y += shfl_xor_t(v[0].y, o);
-  }
-}
 template <typename T, int MC>
 __global__ void __launch_bounds__((64 * ProjCfg<T, MC>::W)) k_cccs_project(Level<T> L, const v2<T>* __restrict__ u,
                                                           const v2<T>* __restrict__ f,
@@ -2320,6 +2290,11 @@ __global__ void k_report(const double* __restrict__ scal, const int* __restrict_
     rep[2] = (double)kused[0];
   }
 }
+// An empty launch: the timer brackets it to measure what the event nodes and
+// one launch add around a bracketed run.
+__global__ void __launch_bounds__(64) k_nop() {}
+void launch_nop(hipStream_t s) { hipLaunchKernelGGL(k_nop, dim3(1), dim3(64), 0, s); }
+
 void launch_report(hipStream_t s, const double* scal, const int* kused, double* rep) {
   hipLaunchKernelGGL(k_report, dim3(1), dim3(64), 0, s, scal, kused, rep);
 }

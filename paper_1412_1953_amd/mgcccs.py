@@ -47,7 +47,7 @@ class SolveOpts(ctypes.Structure):
 
 class KernelTiming(ctypes.Structure):
     _fields_ = [("total_ms", ctypes.c_double), ("launches", ctypes.c_longlong),
-                ("bytes", ctypes.c_double)]
+                ("bytes", ctypes.c_double), ("floor_ms", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -254,10 +254,11 @@ class Grid:
         _check(self.lib.mgc_set_kernel_timer(self.h, kernel_class))
 
     def read_kernel_timer(self):
-        """(total ms, launches, algorithmic bytes) since the last read; clears."""
+        """(total ms, launches, algorithmic bytes, empty-pair ms) since the last
+        read; clears."""
         t = KernelTiming()
         _check(self.lib.mgc_read_kernel_timer(self.h, ctypes.byref(t)))
-        return t.total_ms, t.launches, t.bytes
+        return t.total_ms, t.launches, t.bytes, t.floor_ms
 
     def cross_section(self, u, chi, k1, k2):
         z = (ctypes.c_double * 2)()

@@ -27,7 +27,7 @@ COPY_BYTES = 1 << 28                       # bench.py --copy-probe
 # kernel classes of the library's timer -> kernel-name pattern
 CLASS_PATTERN = {
     "apply_dot": r"k_apply_dot<double",
-    "axpy": r"k_axpy_pass<",
+    "axpy": r"k_axpy_pass<\d+, false>",
     "s1": r"k_s1_zero<double>|k_tail_down<double>",
     "s2": r"k_s2_zero<double>|k_tail_up<double>",
     "cccs_project": r"k_cccs_project<double",
@@ -58,6 +58,29 @@ def stats(stats_csv, trace_csv, out, command):
         t = int(r["TotalDurationNs"])
         lines.append(f"{100 * t / total:5.1f}% {t / 1e6:9.3f} {int(r['Calls']):6d} "
                      f"{float(r['AverageNs']) / 1e3:8.2f}  {short(r['Name'])}")
+    # per timer class: mean kernel duration per launch, and the mean span of
+    # its runs of consecutive launches per launch (what one event pair around
+    # such a run covers, inter-kernel gaps included)
+    trace = sorted(csv.DictReader(open(trace_csv)), key=lambda r: int(r["Start_Timestamp"]))
+    lines += ["", "timer classes (mean per launch):",
+              f"{'class':>13} {'launches':>8} {'kernel us':>10} {'run span us':>12}  kernels"]
+    for kc, pat in CLASS_PATTERN.items():
+        rx = re.compile(pat)
+        n = busy = span = 0
+        run = None
+        for r in trace:
+            if rx.search(r["Kernel_Name"]):
+                s, e = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+                n += 1
+                busy += e - s
+                run = [s, e] if run is None else [run[0], e]
+            elif run is not None:
+                span += run[1] - run[0]
+                run = None
+        if run is not None:
+            span += run[1] - run[0]
+        if n:
+            lines.append(f"{kc:>13} {n:8d} {busy / n / 1e3:10.2f} {span / n / 1e3:12.2f}  {pat}")
     lines += ["", "launch shapes (grid x, grid y in work-items):",
               f"{'calls':>6} {'avg us':>8}  kernel [grid]"]
     for (nm, gx, gy), (c, d) in sorted(shapes.items(), key=lambda x: -x[1][1])[:40]:
