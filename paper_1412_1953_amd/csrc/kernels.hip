@@ -176,18 +176,23 @@ __device__ void finish_sum(const double* part, int nb, int nq, double* out) {
   finish_sum_nt<256>(part, nb, nq, out);
 }
 // Two single sums in one pass (half of the block each):
-// out[0] = sum_b a[b*sa], out[1] = sum_b c[b*sc].  Ends with a barrier.
+// out[0] = sum_b a[b*sa], out[1] = sum_b c[b*sc].  Each thread sums its slice,
+// the waves reduce by shuffles, the per-wave sums are added in wave order.
+// Ends with a barrier.
 template <int NT>
 __device__ void finish_sum_pair(const double* a, int na, int sa, const double* c, int nc, int sc,
                                 double* out) {
-  __shared__ double red[NT];
+  static_assert(NT % 128 == 0, "whole waves per half");
+  constexpr int H = NT / 2, HW = H / 64;
+  __shared__ double red[NT / 64];
   const int t = threadIdx.x + blockDim.x * threadIdx.y;
-  constexpr int H = NT / 2;
-  red[t] = t < H ? slice_sum<NT>(a, na, sa, 0, t, H) : slice_sum<NT>(c, nc, sc, 0, t - H, H);
+  double s = t < H ? slice_sum<NT>(a, na, sa, 0, t, H) : slice_sum<NT>(c, nc, sc, 0, t - H, H);
+  s = wave_sum(s);
+  if ((t & 63) == 0) red[t >> 6] = s;
   __syncthreads();
   if (t < 2) {
     double tot = 0.0;
-    for (int w = 0; w < H; ++w) tot += red[t * H + w];
+    for (int w = 0; w < HW; ++w) tot += red[t * HW + w];
     out[t] = tot;
   }
   __syncthreads();
@@ -342,9 +347,17 @@ __global__ void __launch_bounds__(256) k_coarse_solve(const double2* __restrict_
 //   S1: r = f - A u' on the fine tile, then full weighting -> f_c
 //   S2: w = u' + P e_c, then one omega-Jacobi sweep -> u
 // fs (nullable, device scalar) scales f on the fly.
-constexpr int S1CX = 32, S1CY = 8;                       // coarse points per block
-constexpr int S1W = 2 * S1CX + 3, S1H = 2 * S1CY + 3;    // u' tile (fine nodes)
-constexpr int S1RW = 2 * S1CX + 1, S1RH = 2 * S1CY + 1;  // residual tile
+// S1 tile: CX x CY coarse points per block (32 x 8 on the finest levels,
+// 16 x 4 where the large tiles would give fewer than two blocks per CU)
+template <int CX_, int CY_> struct S1Tile {
+  static constexpr int CX = CX_, CY = CY_;
+  static constexpr int W = 2 * CX + 3, H = 2 * CY + 3;     // u' tile (fine nodes)
+  static constexpr int RW = 2 * CX + 1, RH = 2 * CY + 1;   // residual region
+  static constexpr int NR = (RH * RW + 255) / 256;         // residual points per thread
+  static constexpr int NH = (H * W - RH * RW + 255) / 256; // halo points per thread
+};
+using S1Big = S1Tile<32, 8>;
+using S1Small = S1Tile<16, 4>;
 
 // 1D operator tables of a tile, staged in LDS in the same load round as the
 // field values: by column (px, a, c, tm at the columns' x1 nodes) and by row
@@ -393,13 +406,12 @@ __device__ __forceinline__ v2<T> tab_apply(const TileTabs<T, W, H>& tb, T E, con
 // S1 tile loads: every thread first takes its points of the residual region
 // (kept in registers for the residual), then at most one halo point, so that
 // only u' needs an LDS tile.
-constexpr int S1NR = (S1RH * S1RW + 255) / 256;                 // residual points per thread
-constexpr int S1NH = (S1H * S1W - S1RH * S1RW + 255) / 256;    // halo points per thread
-
-template <typename T>
+template <typename T, typename TL>
 __global__ void __launch_bounds__(256) k_s1_zero(Level<T> L, const v2<T>* __restrict__ f,
                                                  const double* __restrict__ fs, T omega,
                                                  v2<T>* __restrict__ fc, int pitch_c) {
+  constexpr int S1CX = TL::CX, S1CY = TL::CY, S1W = TL::W, S1H = TL::H, S1RW = TL::RW, S1RH = TL::RH;
+  constexpr int S1NR = TL::NR, S1NH = TL::NH;
   __shared__ v2<T> up[S1H][S1W];          // u', then the residual on the same nodes
   __shared__ TileTabs<T, S1W, S1H> tb;
   const int n = L.n, p = L.pitch, nc = n / 2;
@@ -494,18 +506,26 @@ __global__ void __launch_bounds__(256) k_s1_zero(Level<T> L, const v2<T>* __rest
   }
 }
 
-constexpr int S2TX = 64, S2TY = 16;
-constexpr int S2W = S2TX + 2, S2H = S2TY + 2;
-constexpr int S2CW = S2W / 2 + 2, S2CH = S2H / 2 + 2;    // coarse correction tile
-constexpr int S2NH = (S2H * S2W - S2TX * S2TY + 255) / 256;  // halo points per thread
+// S2 tile: 64 x TY fine nodes per block (TY = 16 on the finest levels, 4
+// where the large tiles would give fewer than two blocks per CU)
+template <int TY_> struct S2Tile {
+  static constexpr int TX = 64, TY = TY_;
+  static constexpr int W = TX + 2, H = TY + 2;
+  static constexpr int CW = W / 2 + 2, CH = H / 2 + 2;            // coarse correction tile
+  static constexpr int NH = (H * W - TX * TY + 255) / 256;       // halo points per thread
+};
+using S2Big = S2Tile<16>;
+using S2Small = S2Tile<4>;
 
-// S2: the thread's four output points (column 1 + tx, rows 1 + ty + 4q) keep
-// f in registers; only w = u' + P e_c needs an LDS tile.
-template <typename T>
+// S2: the thread's output points (column 1 + tx, rows 1 + ty + 4q) keep f in
+// registers; only w = u' + P e_c needs an LDS tile.
+template <typename T, typename TL>
 __global__ void __launch_bounds__(256) k_s2_zero(Level<T> L, const v2<T>* __restrict__ f,
                                                  const double* __restrict__ fs, T omega,
                                                  const v2<T>* __restrict__ ec, int pitch_c,
                                                  v2<T>* __restrict__ u) {
+  constexpr int S2TX = TL::TX, S2TY = TL::TY, S2W = TL::W, S2H = TL::H, S2CW = TL::CW, S2CH = TL::CH;
+  constexpr int S2NH = TL::NH;
   __shared__ v2<T> wl[S2H][S2W];
   __shared__ v2<T> el[S2CH][S2CW];
   __shared__ TileTabs<T, S2W, S2H> tb;
@@ -1544,29 +1564,51 @@ __device__ __forceinline__ int flat_block() { return blockIdx.x + gridDim.x * bl
 // FGMRES bookkeeping on the device, by one block after the reductions
 // finished.  Loads go to LDS in parallel; only the short sequential Givens
 // arithmetic runs on one thread.
-__device__ void gmres_step_blk(const GmresState& st, int j, int m, double tol_abs) {
+__device__ void gmres_step_blk(const GmresState& st, int j, int m, double tol_abs, const double* __restrict__ part,
+                               int nb) {
   // after the final norm: column j of H (= projections, then the norm),
-  // earlier rotations, new rotation, residual estimate
-  __shared__ double col[2 * 34], rot[4 * 33], gg[4];
+  // earlier rotations, new rotation, residual estimate.  The state loads are
+  // issued together with the norm's partial loads.
+  __shared__ double col[2 * 34], rot[4 * 33], gg[4], red[4];
   const int tid = threadIdx.x + blockDim.x * threadIdx.y;
   const int R = m + 1;
+  double h0 = 0, h1 = 0, r0 = 0, r1 = 0, r2 = 0, r3 = 0, g0 = 0, g1 = 0;
   if (tid <= j) {
-    col[2 * tid] = st.hcol[2 * tid];
-    col[2 * tid + 1] = st.hcol[2 * tid + 1];
+    h0 = st.hcol[2 * tid];
+    h1 = st.hcol[2 * tid + 1];
   }
   if (tid < j) {
-    rot[4 * tid] = st.cs[2 * tid];
-    rot[4 * tid + 1] = st.cs[2 * tid + 1];
-    rot[4 * tid + 2] = st.sn[2 * tid];
-    rot[4 * tid + 3] = st.sn[2 * tid + 1];
+    r0 = st.cs[2 * tid];
+    r1 = st.cs[2 * tid + 1];
+    r2 = st.sn[2 * tid];
+    r3 = st.sn[2 * tid + 1];
   }
   if (tid == 0) {
-    gg[0] = st.g[2 * j];
-    gg[1] = st.g[2 * j + 1];
-    gg[2] = sqrt(st.nrm2[0]);
+    g0 = st.g[2 * j];
+    g1 = st.g[2 * j + 1];
+  }
+  // ||Y||^2: one partial per thread, wave sums added in wave order
+  double s = 0.0;
+  for (int b = tid; b < nb; b += 256) s += part[b];
+  s = wave_sum(s);
+  if ((tid & 63) == 0) red[tid >> 6] = s;
+  if (tid <= j) {
+    col[2 * tid] = h0;
+    col[2 * tid + 1] = h1;
+  }
+  if (tid < j) {
+    rot[4 * tid] = r0;
+    rot[4 * tid + 1] = r1;
+    rot[4 * tid + 2] = r2;
+    rot[4 * tid + 3] = r3;
   }
   __syncthreads();
   if (tid == 0) {
+    const double nrm2 = (red[0] + red[1]) + (red[2] + red[3]);
+    st.nrm2[0] = nrm2;
+    gg[0] = g0;
+    gg[1] = g1;
+    gg[2] = sqrt(nrm2);
     const double nrm = gg[2];
     col[2 * (j + 1)] = nrm;
     col[2 * (j + 1) + 1] = 0.0;
@@ -1739,11 +1781,11 @@ __global__ void __launch_bounds__(AB) k_axpy_pass(size_t Nf, size_t stride, cons
 }
 #undef MGC_JFOR
 
-// ||Y||^2 from the final pass's partials, then column j of H and its rotation.
+// ||Y||^2 from the final pass's partials (one per thread, wave sums added in
+// wave order), then column j of H and its rotation.
 __global__ void __launch_bounds__(256) k_gmres_step(const double* __restrict__ part, int nb, GmresState st,
                                                     int j, int m, double tol_abs) {
-  finish_sum(part, nb, 1, st.nrm2);
-  gmres_step_blk(st, j, m, tol_abs);
+  gmres_step_blk(st, j, m, tol_abs, part, nb);
 }
 
 // u += sum_q coef_q Z_q with Z stored in precision TZ.
@@ -2048,16 +2090,28 @@ template <typename T>
 void launch_s1_zero(hipStream_t s, const Level<T>& L, const void* f, const double* fs, double omega,
                     void* fc, int pitch_c) {
   const int nc = L.n / 2;
-  dim3 grid((nc - 1 + S1CX - 1) / S1CX, (nc - 1 + S1CY - 1) / S1CY);
-  hipLaunchKernelGGL((k_s1_zero<T>), grid, dim3(64, 4), 0, s, L, (const v2<T>*)f, fs, (T)omega,
-                     (v2<T>*)fc, pitch_c);
+  const dim3 big((nc - 1 + S1Big::CX - 1) / S1Big::CX, (nc - 1 + S1Big::CY - 1) / S1Big::CY);
+  if (big.x * big.y >= 512) {
+    hipLaunchKernelGGL((k_s1_zero<T, S1Big>), big, dim3(64, 4), 0, s, L, (const v2<T>*)f, fs, (T)omega,
+                       (v2<T>*)fc, pitch_c);
+  } else {
+    const dim3 sm((nc - 1 + S1Small::CX - 1) / S1Small::CX, (nc - 1 + S1Small::CY - 1) / S1Small::CY);
+    hipLaunchKernelGGL((k_s1_zero<T, S1Small>), sm, dim3(64, 4), 0, s, L, (const v2<T>*)f, fs, (T)omega,
+                       (v2<T>*)fc, pitch_c);
+  }
 }
 template <typename T>
 void launch_s2_zero(hipStream_t s, const Level<T>& L, const void* f, const double* fs, double omega,
                     const void* ec, int pitch_c, void* u) {
-  dim3 grid((L.n - 1 + S2TX - 1) / S2TX, (L.n - 1 + S2TY - 1) / S2TY);
-  hipLaunchKernelGGL((k_s2_zero<T>), grid, dim3(64, 4), 0, s, L, (const v2<T>*)f, fs, (T)omega,
-                     (const v2<T>*)ec, pitch_c, (v2<T>*)u);
+  const dim3 big((L.n - 1 + S2Big::TX - 1) / S2Big::TX, (L.n - 1 + S2Big::TY - 1) / S2Big::TY);
+  if (big.x * big.y >= 512) {
+    hipLaunchKernelGGL((k_s2_zero<T, S2Big>), big, dim3(64, 4), 0, s, L, (const v2<T>*)f, fs, (T)omega,
+                       (const v2<T>*)ec, pitch_c, (v2<T>*)u);
+  } else {
+    const dim3 sm((L.n - 1 + S2Small::TX - 1) / S2Small::TX, (L.n - 1 + S2Small::TY - 1) / S2Small::TY);
+    hipLaunchKernelGGL((k_s2_zero<T, S2Small>), sm, dim3(64, 4), 0, s, L, (const v2<T>*)f, fs, (T)omega,
+                       (const v2<T>*)ec, pitch_c, (v2<T>*)u);
+  }
 }
 
 template <typename T>
