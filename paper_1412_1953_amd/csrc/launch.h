@@ -75,11 +75,11 @@ void launch_s1_zero(hipStream_t s, const Level<T>& L, const void* f, const doubl
 template <typename T>
 void launch_s2_zero(hipStream_t s, const Level<T>& L, const void* f, const double* fs, double omega,
                     const void* ec, int pitch_c, void* u);
-// coarse tail (levels with n <= 64 whole in LDS): down = S1 passes + coarsest
-// solve, up = S2 passes
+// coarse tail (levels with n <= TAIL_MAX_N whole in LDS; the kernels take up
+// to n = 64): down = S1 passes + coarsest solve, up = S2 passes
 template <typename T>
 void launch_tail(hipStream_t s, const TailArgs<T>& A, bool down);
-constexpr int TAIL_MAX_N = 64;
+constexpr int TAIL_MAX_N = 32;
 int launch_cccs_reduce_blocks(int n);   // blocks of coupling-coefficient partials
 // Timing hook around one kernel of a multi-kernel launcher: fn(ctx, s, 0)
 // before and fn(ctx, s, 1) after the kernel selected by kind.
