@@ -434,6 +434,24 @@ void kt_harvest(mgc_grid g, int slots, const std::vector<double>& bytes, const s
   }
 }
 
+// Fused zero-guess cycle: does level l take the small tiles (fewer than two
+// large tiles per CU), is it in the coarse tail, and is it the finer level of
+// a pair whose S2 passes share one launch (pairs counted from the first
+// small-tile level, both members above the tail)?
+bool small_tiles(mgc_grid g, int l) {
+  const int n = g->lv[l].n;
+  return (long long)((n - 1 + 63) / 64) * ((n - 1 + 15) / 16) < 512;
+}
+bool in_tail(mgc_grid g, int l) {
+  return g->lv[l].n <= TAIL_MAX_N && g->coarsest() - l <= TMAXL;
+}
+bool pair_level(mgc_grid g, int l) {
+  if (l + 1 >= g->coarsest() || in_tail(g, l) || in_tail(g, l + 1) || !small_tiles(g, l)) return false;
+  int s0 = l;
+  while (s0 > 0 && small_tiles(g, s0 - 1)) --s0;
+  return (l - s0) % 2 == 0;
+}
+
 template <typename T>
 void vcycle_level(mgc_grid g, int l, void* u, const void* f, bool zero_guess, const double* fs = nullptr) {
   const int p = sizeof(T) == 8 ? P64 : P32;
@@ -453,7 +471,6 @@ void vcycle_level(mgc_grid g, int l, void* u, const void* f, bool zero_guess, co
     // timing: the S1 launches of all levels run back to back (one event
     // pair around them), and so do the S2 launches
     KernelTimer& kt = g->kt;
-    const bool last = l + 1 == g->coarsest();
     if (l == 0) {
       kt.run = kt_slot(g, MGC_KT_S1, 0.0);
       if (kt.run >= 0) kt.count[kt.run] = 0;
@@ -507,26 +524,43 @@ void vcycle_level(mgc_grid g, int l, void* u, const void* f, bool zero_guess, co
       }
       return;
     }
+    // levels l and l+1 in one S2 launch (small tiles, both above the tail)
+    const bool pair = pair_level(g, l);
+    const int lnext = pair ? l + 2 : l + 1;
+    const LevelInfo& LN = g->lv[lnext];
+    const double N1 = (double)(LC.n - 1) * (LC.n - 1), N2 = (double)(LC.n / 2 - 1) * (LC.n / 2 - 1);
     if (kt.run >= 0 && kt.which == MGC_KT_S1) {
       kt.bytes[kt.run] += (Nf + Nc) * e;                             // f in, f_c out
       ++kt.count[kt.run];
     }
     launch_s1_zero<T>(s, L, f, fs, om, g->ws + LC.ff[p], LC.pitch);
+    if (pair) {
+      if (kt.run >= 0 && kt.which == MGC_KT_S1) {
+        kt.bytes[kt.run] += (N1 + N2) * e;
+        ++kt.count[kt.run];
+      }
+      launch_s1_zero<T>(s, level_of<T>(g, l + 1), g->ws + LC.ff[p], nullptr, om, g->ws + LN.ff[p], LN.pitch);
+    }
+    const bool last = lnext == g->coarsest();
     if (last && kt.which == MGC_KT_S1) {
       kt_mark(g, s, kt.run, 1);
       kt.run = -1;
     }
-    vcycle_level<T>(g, l + 1, g->ws + LC.fu[p], g->ws + LC.ff[p], true);
+    vcycle_level<T>(g, lnext, g->ws + LN.fu[p], g->ws + LN.ff[p], true);
     if (last) {
       kt.run = kt_slot(g, MGC_KT_S2, 0.0);
       if (kt.run >= 0) kt.count[kt.run] = 0;
       kt_mark(g, s, kt.run, 0);
     }
     if (kt.run >= 0 && kt.which == MGC_KT_S2) {
-      kt.bytes[kt.run] += (2 * Nf + Nc) * e;                         // f, e_c in, u out
+      kt.bytes[kt.run] += (2 * Nf + Nc) * e + (pair ? (2 * N1 + N2) * e : 0.0);   // f, e_c in, u out
       ++kt.count[kt.run];
     }
-    launch_s2_zero<T>(s, L, f, fs, om, g->ws + LC.fu[p], LC.pitch, u);
+    if (pair)
+      launch_s2_pair<T>(s, L, level_of<T>(g, l + 1), f, fs, om, g->ws + LC.ff[p], g->ws + LN.fu[p], LN.pitch,
+                        u);
+    else
+      launch_s2_zero<T>(s, L, f, fs, om, g->ws + LC.fu[p], LC.pitch, u);
     if (l == 0 && kt.which == MGC_KT_S2) {
       kt_mark(g, s, kt.run, 1);
       kt.run = -1;

@@ -605,6 +605,127 @@ __global__ void __launch_bounds__(256) k_s2_zero(Level<T> L, const v2<T>* __rest
   }
 }
 
+// S2 on two consecutive levels in one launch: level l+1 on the region that
+// the prolongation of a 64 x 4 tile of level l reads (5 x 35 nodes, from w on
+// 7 x 37 nodes), then level l on the tile.  Blocks overlap on level l+1 and
+// compute the same values there; u of level l+1 stays on chip.
+//   ff, fs: f of level l (fs: optional device scale);  fc: f of level l+1;
+//   ecc: e of level l+2 (pitch_cc);  u: output of level l.
+template <typename T>
+__global__ void __launch_bounds__(256) k_s2_pair(Level<T> Lf, Level<T> Lc, const v2<T>* __restrict__ ff,
+                                                 const double* __restrict__ fs, const v2<T>* __restrict__ fc,
+                                                 const v2<T>* __restrict__ ecc, int pitch_cc, T omega,
+                                                 v2<T>* __restrict__ u) {
+  using TL = S2Small;
+  constexpr int FW = TL::W, FH = TL::H;                 // fine w tile (66 x 6)
+  constexpr int EW = TL::CW, EH = TL::CH;               // e of level l+1 (35 x 5)
+  constexpr int CW = EW + 2, CH = EH + 2;               // w of level l+1 (37 x 7)
+  constexpr int QW = 20, QH = 5;                        // e of level l+2 under it
+  constexpr int NCW = (CW * CH + 255) / 256;
+  static_assert(TL::TY == 4 && TL::NH == 1 && QW * QH <= 256, "tile layout");
+  __shared__ v2<T> wf[FH][FW];
+  __shared__ v2<T> e1[EH][EW];
+  __shared__ v2<T> w1[CH][CW];
+  __shared__ v2<T> e2[QH][QW];
+  __shared__ TileTabs<T, FW, FH> tbf;
+  __shared__ TileTabs<T, CW, CH> tbc;
+  const int n = Lf.n, p = Lf.pitch, nc = Lc.n, pc = Lc.pitch, ncc = nc / 2;
+  const int tid = threadIdx.x + 64 * threadIdx.y;
+  const int j0 = blockIdx.x * TL::TX, k0 = blockIdx.y * TL::TY;    // fine tile origin (halo)
+  const int J0 = j0 >> 1, K0 = k0 >> 1;                            // e1 origin
+  const int Q0 = (J0 >> 1) - 1, R0 = (K0 >> 1) - 1;                // e2 origin (J0, K0 even)
+  auto hpos = [&](int& rr, int& cc) {
+    const int h = tid;                            // fine halo: rows 0 and FH-1, columns 0 and FW-1
+    if (h < FW) { rr = 0; cc = h; return true; }
+    if (h < 2 * FW) { rr = FH - 1; cc = h - FW; return true; }
+    const int v = h - 2 * FW;
+    if (v < 2 * (FH - 2)) { rr = 1 + (v >> 1); cc = (v & 1) ? FW - 1 : 0; return true; }
+    return false;
+  };
+  // every load first: f of level l (output node + one halo node), f of level
+  // l+1 on the w1 region, e of level l+2, the tables of both levels
+  const int orr = 1 + threadIdx.y, occ = 1 + threadIdx.x;
+  v2<T> fo, fh, fcv[NCW], eq = mk<T>(0, 0);
+  {
+    const int k = k0 + orr, j = j0 + occ;
+    fo = (j > 0 && j < n && k > 0 && k < n) ? ff[(size_t)k * p + j] : mk<T>(0, 0);
+    int rr, cc;
+    const bool in = hpos(rr, cc);
+    const int kh = k0 + rr, jh = j0 + cc;
+    fh = (in && jh > 0 && jh < n && kh > 0 && kh < n) ? ff[(size_t)kh * p + jh] : mk<T>(0, 0);
+  }
+#pragma unroll
+  for (int q = 0; q < NCW; ++q) {
+    const int idx = tid + 256 * q, K = K0 - 1 + idx / CW, J = J0 - 1 + idx % CW;
+    fcv[q] = (idx < CW * CH && J > 0 && J < nc && K > 0 && K < nc) ? fc[(size_t)K * pc + J] : mk<T>(0, 0);
+  }
+  if (tid < QW * QH) {
+    const int K = R0 + tid / QW, J = Q0 + tid % QW;
+    if (J > 0 && J < ncc && K > 0 && K < ncc) eq = ecc[(size_t)K * pitch_cc + J];
+  }
+  if (tid < CW + CH) stage_tabs(tbc, Lc, J0 - 1, K0 - 1, tid);
+  if (tid >= 64 && tid < 64 + FW + FH) stage_tabs(tbf, Lf, j0, k0, tid - 64);
+  if (tid < QW * QH) e2[tid / QW][tid % QW] = eq;
+  __syncthreads();
+  // level l+1: w = omega f / d + P e2 on 7 x 37 nodes
+#pragma unroll
+  for (int q = 0; q < NCW; ++q) {
+    const int idx = tid + 256 * q;
+    if (idx < CW * CH) {
+      const int rr = idx / CW, cc = idx % CW, K = K0 - 1 + rr, J = J0 - 1 + cc;
+      v2<T> wv = mk<T>(0, 0);
+      if (J > 0 && J < nc && K > 0 && K < nc) {
+        const int Ja = (J >> 1) - Q0, Jb = ((J + 1) >> 1) - Q0, Ka = (K >> 1) - R0, Kb = ((K + 1) >> 1) - R0;
+        const v2<T> s = cadd(cadd(e2[Ka][Ja], e2[Ka][Jb]), cadd(e2[Kb][Ja], e2[Kb][Jb]));
+        wv = cadd(cscale(cdiv(fcv[q], tab_diag(tbc, Lc.E, rr, cc, K, J)), omega), cscale(s, T(0.25)));
+      }
+      w1[rr][cc] = wv;
+    }
+  }
+  __syncthreads();
+  // level l+1: u = w + omega (f - A w) / d on the inner 5 x 35 nodes
+#pragma unroll
+  for (int q = 0; q < NCW; ++q) {
+    const int idx = tid + 256 * q;
+    const int rr = idx / CW, cc = idx % CW;
+    if (idx < CW * CH && rr >= 1 && rr <= EH && cc >= 1 && cc <= EW) {
+      const int K = K0 - 1 + rr, J = J0 - 1 + cc;
+      v2<T> o = mk<T>(0, 0);
+      if (J > 0 && J < nc && K > 0 && K < nc) {
+        const v2<T> d = tab_diag(tbc, Lc.E, rr, cc, K, J);
+        const v2<T> res = csub(fcv[q], tab_apply(tbc, Lc.E, w1, rr, cc, K, J));
+        o = cadd(w1[rr][cc], cscale(cdiv(res, d), omega));
+      }
+      e1[rr - 1][cc - 1] = o;
+    }
+  }
+  __syncthreads();
+  // level l: w = omega f / d + P e1 on the 6 x 66 tile
+  const T sc = fs ? (T)*fs : T(1);
+  auto put_w = [&](int rr, int cc, v2<T>& fv) {
+    const int k = k0 + rr, j = j0 + cc;
+    v2<T> wv = mk<T>(0, 0);
+    if (j > 0 && j < n && k > 0 && k < n) {
+      fv = cscale(fv, sc);
+      const int Ja = (j >> 1) - J0, Jb = ((j + 1) >> 1) - J0, Ka = (k >> 1) - K0, Kb = ((k + 1) >> 1) - K0;
+      const v2<T> s = cadd(cadd(e1[Ka][Ja], e1[Ka][Jb]), cadd(e1[Kb][Ja], e1[Kb][Jb]));
+      wv = cadd(cscale(cdiv(fv, tab_diag(tbf, Lf.E, rr, cc, k, j)), omega), cscale(s, T(0.25)));
+    }
+    wf[rr][cc] = wv;
+  };
+  put_w(orr, occ, fo);
+  {
+    int rr, cc;
+    if (hpos(rr, cc)) put_w(rr, cc, fh);
+  }
+  __syncthreads();
+  const int k = k0 + orr, j = j0 + occ;
+  if (j >= n || k >= n) return;
+  const v2<T> d = tab_diag(tbf, Lf.E, orr, occ, k, j);
+  const v2<T> res = csub(fo, tab_apply(tbf, Lf.E, wf, orr, occ, k, j));
+  u[(size_t)k * p + j] = cadd(wf[orr][occ], cscale(cdiv(res, d), omega));
+}
+
 // ----------------------------------------------------------------------------
 // Coarse tail of the zero-guess V-cycle: the levels with n <= TN are held
 // whole in LDS (one node row of halo on each side is the zero boundary).
@@ -2124,6 +2245,14 @@ void launch_tail(hipStream_t s, const TailArgs<T>& A, bool down) {
   }
 }
 
+template <typename T>
+void launch_s2_pair(hipStream_t s, const Level<T>& Lf, const Level<T>& Lc, const void* f, const double* fs,
+                    double omega, const void* fc, const void* ecc, int pitch_cc, void* u) {
+  const dim3 grid((Lf.n - 1 + S2Small::TX - 1) / S2Small::TX, (Lf.n - 1 + S2Small::TY - 1) / S2Small::TY);
+  hipLaunchKernelGGL((k_s2_pair<T>), grid, dim3(64, 4), 0, s, Lf, Lc, (const v2<T>*)f, fs,
+                     (const v2<T>*)fc, (const v2<T>*)ecc, pitch_cc, (T)omega, (v2<T>*)u);
+}
+
 #define MGC_INST_LEVEL(T)                                                                      \
   template void launch_jacobi<T>(hipStream_t, const Level<T>&, const void*, const void*, void*, double); \
   template void launch_resid_restrict<T>(hipStream_t, const Level<T>&, const void*, const void*, void*, int); \
@@ -2131,7 +2260,9 @@ void launch_tail(hipStream_t s, const TailArgs<T>& A, bool down) {
   template void launch_coarse_solve<T>(hipStream_t, const double2*, int, int, const void*, void*); \
   template void launch_s1_zero<T>(hipStream_t, const Level<T>&, const void*, const double*, double, void*, int); \
   template void launch_s2_zero<T>(hipStream_t, const Level<T>&, const void*, const double*, double, const void*, int, void*); \
-  template void launch_tail<T>(hipStream_t, const TailArgs<T>&, bool);
+  template void launch_tail<T>(hipStream_t, const TailArgs<T>&, bool);                        \
+  template void launch_s2_pair<T>(hipStream_t, const Level<T>&, const Level<T>&, const void*, const double*, \
+                                  double, const void*, const void*, int, void*);
 MGC_INST_LEVEL(double)
 MGC_INST_LEVEL(float)
 

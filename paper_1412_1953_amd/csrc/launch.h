@@ -75,6 +75,11 @@ void launch_s1_zero(hipStream_t s, const Level<T>& L, const void* f, const doubl
 template <typename T>
 void launch_s2_zero(hipStream_t s, const Level<T>& L, const void* f, const double* fs, double omega,
                     const void* ec, int pitch_c, void* u);
+// S2 of levels l+1 and l in one launch (small tiles): f, fs of level l; fc of
+// level l+1; ecc = e of level l+2; u = output of level l
+template <typename T>
+void launch_s2_pair(hipStream_t s, const Level<T>& Lf, const Level<T>& Lc, const void* f, const double* fs,
+                    double omega, const void* fc, const void* ecc, int pitch_cc, void* u);
 // coarse tail (levels with n <= TAIL_MAX_N whole in LDS; the kernels take up
 // to n = 64): down = S1 passes + coarsest solve, up = S2 passes
 template <typename T>
