@@ -524,23 +524,21 @@ void vcycle_level(mgc_grid g, int l, void* u, const void* f, bool zero_guess, co
       }
       return;
     }
-    // levels l and l+1 in one S2 launch (small tiles, both above the tail)
+    // levels l and l+1 in one S1 and one S2 launch (small tiles, both above
+    // the tail)
     const bool pair = pair_level(g, l);
     const int lnext = pair ? l + 2 : l + 1;
     const LevelInfo& LN = g->lv[lnext];
-    const double N1 = (double)(LC.n - 1) * (LC.n - 1), N2 = (double)(LC.n / 2 - 1) * (LC.n / 2 - 1);
+    const double N2 = (double)(LC.n / 2 - 1) * (LC.n / 2 - 1);
     if (kt.run >= 0 && kt.which == MGC_KT_S1) {
-      kt.bytes[kt.run] += (Nf + Nc) * e;                             // f in, f_c out
+      kt.bytes[kt.run] += (Nf + Nc) * e + (pair ? N2 * e : 0.0);    // f in, f_c (and f_cc) out
       ++kt.count[kt.run];
     }
-    launch_s1_zero<T>(s, L, f, fs, om, g->ws + LC.ff[p], LC.pitch);
-    if (pair) {
-      if (kt.run >= 0 && kt.which == MGC_KT_S1) {
-        kt.bytes[kt.run] += (N1 + N2) * e;
-        ++kt.count[kt.run];
-      }
-      launch_s1_zero<T>(s, level_of<T>(g, l + 1), g->ws + LC.ff[p], nullptr, om, g->ws + LN.ff[p], LN.pitch);
-    }
+    if (pair)
+      launch_s1_pair<T>(s, L, level_of<T>(g, l + 1), f, fs, om, g->ws + LC.ff[p], LC.pitch, g->ws + LN.ff[p],
+                        LN.pitch);
+    else
+      launch_s1_zero<T>(s, L, f, fs, om, g->ws + LC.ff[p], LC.pitch);
     const bool last = lnext == g->coarsest();
     if (last && kt.which == MGC_KT_S1) {
       kt_mark(g, s, kt.run, 1);
@@ -553,7 +551,7 @@ void vcycle_level(mgc_grid g, int l, void* u, const void* f, bool zero_guess, co
       kt_mark(g, s, kt.run, 0);
     }
     if (kt.run >= 0 && kt.which == MGC_KT_S2) {
-      kt.bytes[kt.run] += (2 * Nf + Nc) * e + (pair ? (2 * N1 + N2) * e : 0.0);   // f, e_c in, u out
+      kt.bytes[kt.run] += (2 * Nf + Nc) * e + (pair ? N2 * e : 0.0);  // f, e_c (or f_c, e_cc) in, u out
       ++kt.count[kt.run];
     }
     if (pair)

@@ -605,6 +605,177 @@ __global__ void __launch_bounds__(256) k_s2_zero(Level<T> L, const v2<T>* __rest
   }
 }
 
+// S1 on two consecutive levels in one launch: level l on the 25 x 73 nodes
+// whose residual restricts to the 11 x 35 tile of level l+1 that the second
+// pass needs, then level l+1 on that tile, restricted to 4 x 16 points of
+// level l+2.  Blocks overlap on level l and compute the same values there.
+// Each block stores its own 8 x 32 part of f on level l+1 (read later by the
+// post-smoothing) and its 4 x 16 points of f on level l+2.
+template <typename T>
+__global__ void __launch_bounds__(512) k_s1_pair(Level<T> Lf, Level<T> Lc, const v2<T>* __restrict__ f,
+                                                 const double* __restrict__ fs, T omega,
+                                                 v2<T>* __restrict__ f1, int pitch1, v2<T>* __restrict__ f2,
+                                                 int pitch2) {
+  using TC = S1Small;                                   // level l+1 tile: 11 x 35, outputs 4 x 16
+  constexpr int CW = TC::W, CH = TC::H, CRW = TC::RW, CRH = TC::RH;
+  constexpr int FW = 2 * CW + 3, FH = 2 * CH + 3;       // level l tile: 25 x 73
+  constexpr int RW = FW - 2, RH = FH - 2;               // its residual region: 23 x 71
+  constexpr int NT = 512;                               // threads (64 x 8)
+  constexpr int NR = (RH * RW + NT - 1) / NT, NH = (FH * FW - RH * RW + NT - 1) / NT;
+  constexpr int NC = (CH * CW + NT - 1) / NT, NCR = (CRH * CRW + NT - 1) / NT;
+  static_assert(NH == 1 && TC::NH == 1, "one halo node per thread");
+  __shared__ v2<T> up0[FH][FW];                         // u', then r on level l
+  __shared__ v2<T> ft1[CH][CW];                         // f on level l+1
+  __shared__ v2<T> up1[CH][CW];                         // u', then r on level l+1
+  __shared__ TileTabs<T, FW, FH> tb0;
+  __shared__ TileTabs<T, CW, CH> tb1;
+  const int n = Lf.n, p = Lf.pitch, n1 = Lc.n, n2 = n1 / 2;
+  const int tid = threadIdx.x + 64 * threadIdx.y;
+  const int J2 = 1 + blockIdx.x * TC::CX, K2 = 1 + blockIdx.y * TC::CY;   // level l+2 origin
+  const int c1 = 2 * J2 - 2, r1 = 2 * K2 - 2;                             // level l+1 tile origin
+  const int c0 = 2 * c1 - 2, r0 = 2 * r1 - 2;                             // level l tile origin
+  auto rpos = [&](int q, int& rr, int& cc) {
+    const int idx = tid + NT * q;
+    rr = 1 + idx / RW;
+    cc = 1 + idx % RW;
+    return idx < RH * RW;
+  };
+  auto hpos = [&](int& rr, int& cc) {
+    const int h = tid;
+    if (h < FW) { rr = 0; cc = h; return true; }
+    if (h < 2 * FW) { rr = FH - 1; cc = h - FW; return true; }
+    const int v = h - 2 * FW;
+    if (v < 2 * (FH - 2)) { rr = 1 + (v >> 1); cc = (v & 1) ? FW - 1 : 0; return true; }
+    return false;
+  };
+  auto interior = [](int k, int j, int m) { return j > 0 && j < m && k > 0 && k < m; };
+  // every load first
+  v2<T> fr[NR], fh;
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    int rr, cc;
+    const bool in = rpos(q, rr, cc);
+    const int k = r0 + rr, j = c0 + cc;
+    fr[q] = (in && interior(k, j, n)) ? f[(size_t)k * p + j] : mk<T>(0, 0);
+  }
+  {
+    int rr, cc;
+    const bool in = hpos(rr, cc);
+    const int k = r0 + rr, j = c0 + cc;
+    fh = (in && interior(k, j, n)) ? f[(size_t)k * p + j] : mk<T>(0, 0);
+  }
+  if (tid < FW + FH) stage_tabs(tb0, Lf, c0, r0, tid);
+  if (tid >= 128 && tid < 128 + CW + CH) stage_tabs(tb1, Lc, c1, r1, tid - 128);
+  const T sc = fs ? (T)*fs : T(1);
+  __syncthreads();
+  // level l: u' = omega f / d on the tile
+  auto put_u = [&](int rr, int cc, v2<T>& fv) {
+    const int k = r0 + rr, j = c0 + cc;
+    v2<T> uv = mk<T>(0, 0);
+    if (interior(k, j, n)) {
+      fv = cscale(fv, sc);
+      uv = cscale(cdiv(fv, tab_diag(tb0, Lf.E, rr, cc, k, j)), omega);
+    }
+    up0[rr][cc] = uv;
+  };
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    int rr, cc;
+    if (rpos(q, rr, cc)) put_u(rr, cc, fr[q]);
+  }
+  {
+    int rr, cc;
+    if (hpos(rr, cc)) put_u(rr, cc, fh);
+  }
+  __syncthreads();
+  // level l: r = f - A u' on the residual region, then in place of u'
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    int rr, cc;
+    const bool in = rpos(q, rr, cc);
+    const int k = r0 + rr, j = c0 + cc;
+    v2<T> r = mk<T>(0, 0);
+    if (in && interior(k, j, n)) r = csub(fr[q], tab_apply(tb0, Lf.E, up0, rr, cc, k, j));
+    fr[q] = r;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    int rr, cc;
+    if (rpos(q, rr, cc)) up0[rr][cc] = fr[q];
+  }
+  __syncthreads();
+  // level l+1: f by full weighting on the 11 x 35 tile (zero off the interior);
+  // the block's own 8 x 32 part goes to memory
+  auto fw = [&](v2<T> (*w)[FW], int cr, int cn) {
+    v2<T> acc = mk<T>(0, 0);
+#pragma unroll
+    for (int a = -1; a <= 1; ++a)
+#pragma unroll
+      for (int b = -1; b <= 1; ++b) {
+        const T wt = T((a == 0 ? 2 : 1) * (b == 0 ? 2 : 1));
+        const v2<T> r = w[cr + a][cn + b];
+        acc = mk<T>(acc.x + wt * r.x, acc.y + wt * r.y);
+      }
+    return cscale(acc, T(1.0 / 16.0));
+  };
+  v2<T> f1r[NC];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    const int idx = tid + NT * q, rr = idx / CW, cc = idx % CW, K = r1 + rr, J = c1 + cc;
+    v2<T> v = mk<T>(0, 0);
+    if (idx < CH * CW && interior(K, J, n1)) {
+      v = fw(up0, 2 * rr + 2, 2 * cc + 2);           // level-l node 2K, 2J at tile position 2rr+2, 2cc+2
+      // own part: rows 1..8, columns 1..32 of the tile (the last block row /
+      // column also takes the rest of the interior)
+      const bool own_r = rr >= 1 && (rr <= 2 * TC::CY || blockIdx.y + 1 == gridDim.y);
+      const bool own_c = cc >= 1 && (cc <= 2 * TC::CX || blockIdx.x + 1 == gridDim.x);
+      if (own_r && own_c) f1[(size_t)K * pitch1 + J] = v;
+    }
+    f1r[q] = v;
+    if (idx < CH * CW) ft1[rr][cc] = v;
+  }
+  __syncthreads();
+  // level l+1: u' on the tile, r on its residual region, full weighting
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    const int idx = tid + NT * q, rr = idx / CW, cc = idx % CW, K = r1 + rr, J = c1 + cc;
+    if (idx < CH * CW)
+      up1[rr][cc] = interior(K, J, n1) ? cscale(cdiv(f1r[q], tab_diag(tb1, Lc.E, rr, cc, K, J)), omega)
+                                       : mk<T>(0, 0);
+  }
+  __syncthreads();
+  v2<T> r1v[NCR];
+#pragma unroll
+  for (int q = 0; q < NCR; ++q) {
+    const int idx = tid + NT * q, rr = 1 + idx / CRW, cc = 1 + idx % CRW, K = r1 + rr, J = c1 + cc;
+    v2<T> r = mk<T>(0, 0);
+    if (idx < CRH * CRW && interior(K, J, n1)) r = csub(ft1[rr][cc], tab_apply(tb1, Lc.E, up1, rr, cc, K, J));
+    r1v[q] = r;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NCR; ++q) {
+    const int idx = tid + NT * q;
+    if (idx < CRH * CRW) up1[1 + idx / CRW][1 + idx % CRW] = r1v[q];
+  }
+  __syncthreads();
+  const int J = J2 + tid % TC::CX, K = K2 + tid / TC::CX;
+  if (tid < TC::CX * TC::CY && J < n2 && K < n2) {
+    const int cr = 2 * (K - K2) + 2, cn = 2 * (J - J2) + 2;
+    v2<T> acc = mk<T>(0, 0);
+#pragma unroll
+    for (int a = -1; a <= 1; ++a)
+#pragma unroll
+      for (int b = -1; b <= 1; ++b) {
+        const T wt = T((a == 0 ? 2 : 1) * (b == 0 ? 2 : 1));
+        const v2<T> r = up1[cr + a][cn + b];
+        acc = mk<T>(acc.x + wt * r.x, acc.y + wt * r.y);
+      }
+    f2[(size_t)K * pitch2 + J] = cscale(acc, T(1.0 / 16.0));
+  }
+}
+
 // S2 on two consecutive levels in one launch: level l+1 on the region that
 // the prolongation of a 64 x 4 tile of level l reads (5 x 35 nodes, from w on
 // 7 x 37 nodes), then level l on the tile.  Blocks overlap on level l+1 and
@@ -2246,6 +2417,14 @@ void launch_tail(hipStream_t s, const TailArgs<T>& A, bool down) {
 }
 
 template <typename T>
+void launch_s1_pair(hipStream_t s, const Level<T>& Lf, const Level<T>& Lc, const void* f, const double* fs,
+                    double omega, void* f1, int pitch1, void* f2, int pitch2) {
+  const int n2 = Lc.n / 2;
+  const dim3 grid((n2 - 1 + S1Small::CX - 1) / S1Small::CX, (n2 - 1 + S1Small::CY - 1) / S1Small::CY);
+  hipLaunchKernelGGL((k_s1_pair<T>), grid, dim3(64, 8), 0, s, Lf, Lc, (const v2<T>*)f, fs, (T)omega,
+                     (v2<T>*)f1, pitch1, (v2<T>*)f2, pitch2);
+}
+template <typename T>
 void launch_s2_pair(hipStream_t s, const Level<T>& Lf, const Level<T>& Lc, const void* f, const double* fs,
                     double omega, const void* fc, const void* ecc, int pitch_cc, void* u) {
   const dim3 grid((Lf.n - 1 + S2Small::TX - 1) / S2Small::TX, (Lf.n - 1 + S2Small::TY - 1) / S2Small::TY);
@@ -2262,7 +2441,9 @@ void launch_s2_pair(hipStream_t s, const Level<T>& Lf, const Level<T>& Lc, const
   template void launch_s2_zero<T>(hipStream_t, const Level<T>&, const void*, const double*, double, const void*, int, void*); \
   template void launch_tail<T>(hipStream_t, const TailArgs<T>&, bool);                        \
   template void launch_s2_pair<T>(hipStream_t, const Level<T>&, const Level<T>&, const void*, const double*, \
-                                  double, const void*, const void*, int, void*);
+                                  double, const void*, const void*, int, void*);                 \
+  template void launch_s1_pair<T>(hipStream_t, const Level<T>&, const Level<T>&, const void*, const double*, \
+                                  double, void*, int, void*, int);
 MGC_INST_LEVEL(double)
 MGC_INST_LEVEL(float)
 

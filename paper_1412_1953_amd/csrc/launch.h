@@ -75,6 +75,11 @@ void launch_s1_zero(hipStream_t s, const Level<T>& L, const void* f, const doubl
 template <typename T>
 void launch_s2_zero(hipStream_t s, const Level<T>& L, const void* f, const double* fs, double omega,
                     const void* ec, int pitch_c, void* u);
+// S1 of levels l and l+1 in one launch (small tiles): f, fs of level l; f1 =
+// f of level l+1 (written), f2 = f of level l+2 (written)
+template <typename T>
+void launch_s1_pair(hipStream_t s, const Level<T>& Lf, const Level<T>& Lc, const void* f, const double* fs,
+                    double omega, void* f1, int pitch1, void* f2, int pitch2);
 // S2 of levels l+1 and l in one launch (small tiles): f, fs of level l; fc of
 // level l+1; ecc = e of level l+2; u = output of level l
 template <typename T>
