@@ -28,8 +28,8 @@ COPY_BYTES = 1 << 28                       # bench.py --copy-probe
 CLASS_PATTERN = {
     "apply_dot": r"k_apply_dot<double",
     "axpy": r"k_axpy_pass<\d+, false>",
-    "s1": r"k_s1_zero<double\b|k_tail_down<double>",
-    "s2": r"k_s2_zero<double\b|k_tail_up<double>",
+    "s1": r"k_s1_zero<double\b|k_s1_pair<double>|k_tail_down<double>",
+    "s2": r"k_s2_zero<double\b|k_s2_pair<double>|k_tail_up<double>",
     "cccs_project": r"k_cccs_project<double",
     "cccs_chain": r"k_cccs_chain<double",
 }
