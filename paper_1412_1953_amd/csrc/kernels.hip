@@ -1690,39 +1690,46 @@ __global__ void __launch_bounds__(64) k_cccs_chain(ChanSys<T> SA, ChanSys<T> SB,
   }
 }
 
-// Step 3b: the interface system of each system (blockIdx.y), one wave:
-// block tridiagonal in 2M x 2M blocks, block Thomas sweeps with the
-// precomputed Rlo = Rinv Sub, Rup = Rinv Sup:
-//   forward   Z_q = (H_q^0 + H_q^1) - Rlo_q Z_{q-1}
-//   backward  Y_q = Z_q - Rup_q Y_{q+1},  Y_{Q-1} = Z_{Q-1}
-template <typename T, int RC>
-__global__ void __launch_bounds__(64) k_cccs_interface(ChanSys<T> SA, ChanSys<T> SB,
-                                                       v2<T>* __restrict__ YA, v2<T>* __restrict__ YB,
-                                                       const v2<T>* __restrict__ HA,
+// Step 3b: the interface system of each system (block tridiagonal in 2M x 2M
+// blocks).  Its block Thomas sweeps (Rlo = Rinv Sub, Rup = Rinv Sup) are
+// linear in the right-hand side, so the host applies them to unit vectors
+// once per energy; here they act as one matrix, Y = Tif h with
+// h_q = H_q^0 + H_q^1.  One wave per row of each system (blockIdx.y), lanes
+// over the columns, the row sum by shuffles.
+template <typename T>
+__global__ void __launch_bounds__(256) k_cccs_iface_mv(ChanSys<T> SA, ChanSys<T> SB, v2<T>* __restrict__ YA,
+                                                       v2<T>* __restrict__ YB, const v2<T>* __restrict__ HA,
                                                        const v2<T>* __restrict__ HB) {
-  extern __shared__ __align__(16) unsigned char iface_lds[];
-  v2<T>* zs = reinterpret_cast<v2<T>*>(iface_lds);
   const bool isA = blockIdx.y == 0;
   const ChanSys<T>& S = isA ? SA : SB;
-  const int Q = S.P - 1;
-  if (Q <= 0) return;
-  const int lane = threadIdx.x, R = 2 * S.M;
-  v2<T>* Y = isA ? YA : YB;
+  const int R = 2 * S.M, QR = (S.P - 1) * R;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= QR) return;
   const v2<T>* H = isA ? HA : HB;
-#pragma unroll 4
-  for (int idx = lane; idx < Q * RC; idx += 64) {
-    const int q = idx / RC, i = idx % RC, ic = i < R ? i : R - 1;
-    const v2<T> h = cadd(H[((size_t)q * 2) * R + ic], H[((size_t)q * 2 + 1) * R + ic]);
-    zs[idx] = i < R ? h : mk<T>(0, 0);
+  const v2<T>* Tr = S.Tif + (size_t)row * QR;
+  constexpr int U = 8;                           // columns per lane in flight
+  double sr = 0, si = 0;
+  for (int c0 = lane; c0 < QR; c0 += 64 * U) {
+    v2<T> t[U], h0[U], h1[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int c = c0 + 64 * u, cc = c < QR ? c : QR - 1, q = cc / R, i = cc - q * R;
+      t[u] = Tr[cc];
+      h0[u] = H[((size_t)q * 2) * R + i];
+      h1[u] = H[((size_t)q * 2 + 1) * R + i];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (c0 + 64 * u < QR) {
+        const double hx = (double)h0[u].x + (double)h1[u].x, hy = (double)h0[u].y + (double)h1[u].y;
+        sr += (double)t[u].x * hx - (double)t[u].y * hy;
+        si += (double)t[u].x * hy + (double)t[u].y * hx;
+      }
+    }
   }
-  __syncthreads();
-  // forward block index q uses Rlo_q (q >= 1); backward row l uses Rup_l
-  lds_sweep<T, RC, true, false, false>(zs, Q, S.Rlo, nullptr, 0, R);
-  lds_sweep<T, RC, false, false, false>(zs, Q, S.Rup, nullptr, 0, R);
-  for (int idx = lane; idx < Q * R; idx += 64) {
-    const int q = idx / R, i = idx % R;
-    Y[(size_t)q * R + i] = zs[q * RC + i];
-  }
+  sr = wave_sum(sr);
+  si = wave_sum(si);
+  if (lane == 0) (isA ? YA : YB)[row] = mk<T>((T)sr, (T)si);
 }
 
 // Step 4: retrieval e_t = g_t - V_t T_{p+1} - W_t B_{p-1}; thread per (t, i).
@@ -2503,9 +2510,8 @@ void launch_cccs(hipStream_t s, const Level<T>& L, void* u, const void* f, const
                      maxlen);                                                                           \
   mark(2, 1);                                                                                          \
   if (Qmax > 0)                                                                                        \
-    hipLaunchKernelGGL((k_cccs_interface<T, 2 * MCC>), dim3(1, 2), dim3(64),                            \
-                       (size_t)Qmax * 2 * MCC * sizeof(v2<T>), s, SA, SB, YA, YB, (const v2<T>*)w.HA,   \
-                       (const v2<T>*)w.HB)
+    hipLaunchKernelGGL((k_cccs_iface_mv<T>), dim3((Qmax * 2 * MC + 3) / 4, 2), dim3(256), 0, s, SA, SB,  \
+                       YA, YB, (const v2<T>*)w.HA, (const v2<T>*)w.HB)
   if (MC <= 4) {
     MGC_CHAIN(4);
   } else if (MC <= 8) {

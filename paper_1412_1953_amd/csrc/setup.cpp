@@ -387,6 +387,24 @@ bool factor_channels(int N, int M, int P, const std::vector<cd>& lo,
     matmul(R, inv.data(), Sup.data(), &f.Rup[q * RR]);
     std::copy(f.Rup.begin() + q * RR, f.Rup.begin() + (q + 1) * RR, prevRinvSup.begin());
   }
+  // the two sweeps (forward Z_q = h_q - Rlo_q Z_{q-1}, backward Y_q = Z_q -
+  // Rup_q Y_{q+1}) are linear in h: apply them to every unit vector
+  const size_t QR = (size_t)std::max(Q, 0) * R;
+  f.Tif.assign(QR * QR, 0.0);
+  std::vector<cd> Y(QR), t(R);
+  for (size_t c = 0; c < QR; ++c) {
+    std::fill(Y.begin(), Y.end(), 0.0);
+    Y[c] = 1.0;
+    for (int q = 1; q < Q; ++q) {
+      matvec(R, &f.Rlo[q * RR], &Y[(q - 1) * R], t.data());
+      for (int i = 0; i < R; ++i) Y[q * R + i] -= t[i];
+    }
+    for (int q = Q - 2; q >= 0; --q) {
+      matvec(R, &f.Rup[q * RR], &Y[(q + 1) * R], t.data());
+      for (int i = 0; i < R; ++i) Y[q * R + i] -= t[i];
+    }
+    for (size_t r = 0; r < QR; ++r) f.Tif[r * QR + c] = Y[r];
+  }
   return true;
 }
 

@@ -63,6 +63,9 @@ struct ChannelFactors {
   // interface system, block Thomas factors for q = 0..P-2:
   std::vector<cd> Rinv;            // [P-1][2M][2M]  inverse Schur blocks
   std::vector<cd> Rlo, Rup;        // [P-1][2M][2M]  sub / super blocks
+  // the interface solve as one matrix: Y = Tif h for h_q = Rinv_q rhs_q
+  // (both sweeps applied to unit vectors), [(P-1)2M][(P-1)2M] row-major
+  std::vector<cd> Tif;
 };
 bool factor_channels(int N, int M, int P, const std::vector<cd>& lo,
                      const std::vector<cd>& up, const std::vector<cd>& D,
