@@ -612,7 +612,7 @@ __global__ void __launch_bounds__(256) k_s2_zero(Level<T> L, const v2<T>* __rest
 // Each block stores its own 8 x 32 part of f on level l+1 (read later by the
 // post-smoothing) and its 4 x 16 points of f on level l+2.
 template <typename T>
-__global__ void __launch_bounds__(512) k_s1_pair(Level<T> Lf, Level<T> Lc, const v2<T>* __restrict__ f,
+__global__ void __launch_bounds__(1024) k_s1_pair(Level<T> Lf, Level<T> Lc, const v2<T>* __restrict__ f,
                                                  const double* __restrict__ fs, T omega,
                                                  v2<T>* __restrict__ f1, int pitch1, v2<T>* __restrict__ f2,
                                                  int pitch2) {
@@ -620,7 +620,7 @@ __global__ void __launch_bounds__(512) k_s1_pair(Level<T> Lf, Level<T> Lc, const
   constexpr int CW = TC::W, CH = TC::H, CRW = TC::RW, CRH = TC::RH;
   constexpr int FW = 2 * CW + 3, FH = 2 * CH + 3;       // level l tile: 25 x 73
   constexpr int RW = FW - 2, RH = FH - 2;               // its residual region: 23 x 71
-  constexpr int NT = 512;                               // threads (64 x 8)
+  constexpr int NT = 1024;                              // threads (64 x 16)
   constexpr int NR = (RH * RW + NT - 1) / NT, NH = (FH * FW - RH * RW + NT - 1) / NT;
   constexpr int NC = (CH * CW + NT - 1) / NT, NCR = (CRH * CRW + NT - 1) / NT;
   static_assert(NH == 1 && TC::NH == 1, "one halo node per thread");
@@ -2428,7 +2428,7 @@ void launch_s1_pair(hipStream_t s, const Level<T>& Lf, const Level<T>& Lc, const
                     double omega, void* f1, int pitch1, void* f2, int pitch2) {
   const int n2 = Lc.n / 2;
   const dim3 grid((n2 - 1 + S1Small::CX - 1) / S1Small::CX, (n2 - 1 + S1Small::CY - 1) / S1Small::CY);
-  hipLaunchKernelGGL((k_s1_pair<T>), grid, dim3(64, 8), 0, s, Lf, Lc, (const v2<T>*)f, fs, (T)omega,
+  hipLaunchKernelGGL((k_s1_pair<T>), grid, dim3(64, 16), 0, s, Lf, Lc, (const v2<T>*)f, fs, (T)omega,
                      (v2<T>*)f1, pitch1, (v2<T>*)f2, pitch2);
 }
 template <typename T>
