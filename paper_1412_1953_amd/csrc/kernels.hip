@@ -30,6 +30,10 @@ template <typename T> __device__ __forceinline__ v2<T> mk(T x, T y) { v2<T> r; r
   __device__ __forceinline__ V cdiv(V a, V b) {                                             \
     T inv = T(1) / (b.x * b.x + b.y * b.y);                                                 \
     return mk<T>((a.x * b.x + a.y * b.y) * inv, (a.y * b.x - a.x * b.y) * inv);             \
+  }                                                                                         \
+  /* a / b with inv = 1 / |b|^2 given (the same arithmetic as cdiv) */                      \
+  __device__ __forceinline__ V cdiv_inv(V a, V b, T inv) {                                  \
+    return mk<T>((a.x * b.x + a.y * b.y) * inv, (a.y * b.x - a.x * b.y) * inv);             \
   }
 MGC_CPLX_OPS(double2, double)
 MGC_CPLX_OPS(float2, float)
@@ -391,7 +395,18 @@ __device__ __forceinline__ v2<T> tab_diag(const TileTabs<T, W, H>& tb, T E, int 
   d.x -= E;
   return d;
 }
-// (A w)(k, j) from an LDS tile w with a one-node halo
+// (A w)(k, j) from an LDS tile w with a one-node halo; tab_apply_d takes the
+// diagonal d at (k, j) already formed
+template <typename T, int W, int H, int TW>
+__device__ __forceinline__ v2<T> tab_apply_d(const TileTabs<T, W, H>& tb, v2<T> d, const v2<T> (*w)[TW], int rr,
+                                             int cc) {
+  v2<T> acc = cmul(d, w[rr][cc]);
+  acc = cfma(acc, tb.col[1][cc], w[rr][cc - 1]);
+  acc = cfma(acc, tb.col[2][cc], w[rr][cc + 1]);
+  acc = cfma(acc, tb.row[1][rr], w[rr - 1][cc]);
+  acc = cfma(acc, tb.row[2][rr], w[rr + 1][cc]);
+  return acc;
+}
 template <typename T, int W, int H, int TW>
 __device__ __forceinline__ v2<T> tab_apply(const TileTabs<T, W, H>& tb, T E, const v2<T> (*w)[TW], int rr,
                                            int cc, int k, int j) {
@@ -572,24 +587,33 @@ __global__ void __launch_bounds__(256) k_s2_zero(Level<T> L, const v2<T>* __rest
     if (idx < S2CH * S2CW) el[idx / S2CW][idx % S2CW] = er[q];
   }
   __syncthreads();
-  // w = omega f / d + P e_c (bilinear: mean of the up to four coarse neighbours)
-  auto put_w = [&](int rr, int cc, v2<T>& fv) {
+  // w = omega f / d + P e_c (bilinear: mean of the up to four coarse
+  // neighbours); d and 1/|d|^2 of the output nodes are kept for the sweep
+  auto put_w = [&](int rr, int cc, v2<T>& fv, v2<T>& d, T& inv) {
     const int k = k0 + rr, j = j0 + cc;
     v2<T> wv = mk<T>(0, 0);
+    d = mk<T>(1, 0);
+    inv = T(1);
     if (j > 0 && j < n && k > 0 && k < n) {
       fv = cscale(fv, sc);
       const int Ja = (j >> 1) - J0, Jb = ((j + 1) >> 1) - J0, Ka = (k >> 1) - K0, Kb = ((k + 1) >> 1) - K0;
       const v2<T> s = cadd(cadd(el[Ka][Ja], el[Ka][Jb]), cadd(el[Kb][Ja], el[Kb][Jb]));
-      wv = cadd(cscale(cdiv(fv, tab_diag(tb, L.E, rr, cc, k, j)), omega), cscale(s, T(0.25)));
+      d = tab_diag(tb, L.E, rr, cc, k, j);
+      inv = T(1) / (d.x * d.x + d.y * d.y);
+      wv = cadd(cscale(cdiv_inv(fv, d, inv), omega), cscale(s, T(0.25)));
     }
     wl[rr][cc] = wv;
   };
+  v2<T> dq[NO];
+  T iq[NO];
 #pragma unroll
-  for (int q = 0; q < NO; ++q) put_w(1 + threadIdx.y + 4 * q, occ, fo[q]);
+  for (int q = 0; q < NO; ++q) put_w(1 + threadIdx.y + 4 * q, occ, fo[q], dq[q], iq[q]);
 #pragma unroll
   for (int q = 0; q < S2NH; ++q) {
     int rr, cc;
-    if (hpos(q, rr, cc)) put_w(rr, cc, fh[q]);
+    v2<T> dh;
+    T ih;
+    if (hpos(q, rr, cc)) put_w(rr, cc, fh[q], dh, ih);
   }
   __syncthreads();
   const int j = j0 + occ;
@@ -599,9 +623,8 @@ __global__ void __launch_bounds__(256) k_s2_zero(Level<T> L, const v2<T>* __rest
     const int rr = 1 + threadIdx.y + 4 * q;
     const int k = k0 + rr;
     if (k >= n) break;
-    const v2<T> d = tab_diag(tb, L.E, rr, occ, k, j);
-    const v2<T> res = csub(fo[q], tab_apply(tb, L.E, wl, rr, occ, k, j));
-    u[(size_t)k * p + j] = cadd(wl[rr][occ], cscale(cdiv(res, d), omega));
+    const v2<T> res = csub(fo[q], tab_apply_d(tb, dq[q], wl, rr, occ));
+    u[(size_t)k * p + j] = cadd(wl[rr][occ], cscale(cdiv_inv(res, dq[q], iq[q]), omega));
   }
 }
 
@@ -838,17 +861,23 @@ __global__ void __launch_bounds__(256) k_s2_pair(Level<T> Lf, Level<T> Lc, const
   if (tid >= 64 && tid < 64 + FW + FH) stage_tabs(tbf, Lf, j0, k0, tid - 64);
   if (tid < QW * QH) e2[tid / QW][tid % QW] = eq;
   __syncthreads();
-  // level l+1: w = omega f / d + P e2 on 7 x 37 nodes
+  // level l+1: w = omega f / d + P e2 on 7 x 37 nodes (d, 1/|d|^2 kept)
+  v2<T> dc[NCW];
+  T ic[NCW];
 #pragma unroll
   for (int q = 0; q < NCW; ++q) {
     const int idx = tid + 256 * q;
+    dc[q] = mk<T>(1, 0);
+    ic[q] = T(1);
     if (idx < CW * CH) {
       const int rr = idx / CW, cc = idx % CW, K = K0 - 1 + rr, J = J0 - 1 + cc;
       v2<T> wv = mk<T>(0, 0);
       if (J > 0 && J < nc && K > 0 && K < nc) {
         const int Ja = (J >> 1) - Q0, Jb = ((J + 1) >> 1) - Q0, Ka = (K >> 1) - R0, Kb = ((K + 1) >> 1) - R0;
         const v2<T> s = cadd(cadd(e2[Ka][Ja], e2[Ka][Jb]), cadd(e2[Kb][Ja], e2[Kb][Jb]));
-        wv = cadd(cscale(cdiv(fcv[q], tab_diag(tbc, Lc.E, rr, cc, K, J)), omega), cscale(s, T(0.25)));
+        dc[q] = tab_diag(tbc, Lc.E, rr, cc, K, J);
+        ic[q] = T(1) / (dc[q].x * dc[q].x + dc[q].y * dc[q].y);
+        wv = cadd(cscale(cdiv_inv(fcv[q], dc[q], ic[q]), omega), cscale(s, T(0.25)));
       }
       w1[rr][cc] = wv;
     }
@@ -863,9 +892,8 @@ __global__ void __launch_bounds__(256) k_s2_pair(Level<T> Lf, Level<T> Lc, const
       const int K = K0 - 1 + rr, J = J0 - 1 + cc;
       v2<T> o = mk<T>(0, 0);
       if (J > 0 && J < nc && K > 0 && K < nc) {
-        const v2<T> d = tab_diag(tbc, Lc.E, rr, cc, K, J);
-        const v2<T> res = csub(fcv[q], tab_apply(tbc, Lc.E, w1, rr, cc, K, J));
-        o = cadd(w1[rr][cc], cscale(cdiv(res, d), omega));
+        const v2<T> res = csub(fcv[q], tab_apply_d(tbc, dc[q], w1, rr, cc));
+        o = cadd(w1[rr][cc], cscale(cdiv_inv(res, dc[q], ic[q]), omega));
       }
       e1[rr - 1][cc - 1] = o;
     }
@@ -873,28 +901,35 @@ __global__ void __launch_bounds__(256) k_s2_pair(Level<T> Lf, Level<T> Lc, const
   __syncthreads();
   // level l: w = omega f / d + P e1 on the 6 x 66 tile
   const T sc = fs ? (T)*fs : T(1);
-  auto put_w = [&](int rr, int cc, v2<T>& fv) {
+  auto put_w = [&](int rr, int cc, v2<T>& fv, v2<T>& d, T& inv) {
     const int k = k0 + rr, j = j0 + cc;
     v2<T> wv = mk<T>(0, 0);
+    d = mk<T>(1, 0);
+    inv = T(1);
     if (j > 0 && j < n && k > 0 && k < n) {
       fv = cscale(fv, sc);
       const int Ja = (j >> 1) - J0, Jb = ((j + 1) >> 1) - J0, Ka = (k >> 1) - K0, Kb = ((k + 1) >> 1) - K0;
       const v2<T> s = cadd(cadd(e1[Ka][Ja], e1[Ka][Jb]), cadd(e1[Kb][Ja], e1[Kb][Jb]));
-      wv = cadd(cscale(cdiv(fv, tab_diag(tbf, Lf.E, rr, cc, k, j)), omega), cscale(s, T(0.25)));
+      d = tab_diag(tbf, Lf.E, rr, cc, k, j);
+      inv = T(1) / (d.x * d.x + d.y * d.y);
+      wv = cadd(cscale(cdiv_inv(fv, d, inv), omega), cscale(s, T(0.25)));
     }
     wf[rr][cc] = wv;
   };
-  put_w(orr, occ, fo);
+  v2<T> dq;
+  T iq;
+  put_w(orr, occ, fo, dq, iq);
   {
     int rr, cc;
-    if (hpos(rr, cc)) put_w(rr, cc, fh);
+    v2<T> dh;
+    T ih;
+    if (hpos(rr, cc)) put_w(rr, cc, fh, dh, ih);
   }
   __syncthreads();
   const int k = k0 + orr, j = j0 + occ;
   if (j >= n || k >= n) return;
-  const v2<T> d = tab_diag(tbf, Lf.E, orr, occ, k, j);
-  const v2<T> res = csub(fo, tab_apply(tbf, Lf.E, wf, orr, occ, k, j));
-  u[(size_t)k * p + j] = cadd(wf[orr][occ], cscale(cdiv(res, d), omega));
+  const v2<T> res = csub(fo, tab_apply_d(tbf, dq, wf, orr, occ));
+  u[(size_t)k * p + j] = cadd(wf[orr][occ], cscale(cdiv_inv(res, dq, iq), omega));
 }
 
 // ----------------------------------------------------------------------------
