@@ -466,25 +466,30 @@ __global__ void __launch_bounds__(256) k_s1_zero(Level<T> L, const v2<T>* __rest
   }
   stage_tabs(tb, L, c0, r0, tid);
   __syncthreads();
-  // u' = omega f / d on the whole tile
-  auto put_u = [&](int rr, int cc, v2<T>& fv) {
+  // u' = omega f / d on the whole tile (d of the residual region kept)
+  auto put_u = [&](int rr, int cc, v2<T>& fv, v2<T>& d) {
     const int k = r0 + rr, j = c0 + cc;
     v2<T> uv = mk<T>(0, 0);
+    d = mk<T>(1, 0);
     if (j > 0 && j < n && k > 0 && k < n) {
       fv = cscale(fv, sc);
-      uv = cscale(cdiv(fv, tab_diag(tb, L.E, rr, cc, k, j)), omega);
+      d = tab_diag(tb, L.E, rr, cc, k, j);
+      uv = cscale(cdiv(fv, d), omega);
     }
     up[rr][cc] = uv;
   };
+  v2<T> dr[S1NR];
 #pragma unroll
   for (int q = 0; q < S1NR; ++q) {
     int rr, cc;
-    if (rpos(q, rr, cc)) put_u(rr, cc, fr[q]);
+    dr[q] = mk<T>(1, 0);
+    if (rpos(q, rr, cc)) put_u(rr, cc, fr[q], dr[q]);
   }
 #pragma unroll
   for (int q = 0; q < S1NH; ++q) {
     int rr, cc;
-    if (hpos(q, rr, cc)) put_u(rr, cc, fh[q]);
+    v2<T> dh;
+    if (hpos(q, rr, cc)) put_u(rr, cc, fh[q], dh);
   }
   __syncthreads();
   // residual r = f - A u' on the residual region (f from registers); it
@@ -495,7 +500,7 @@ __global__ void __launch_bounds__(256) k_s1_zero(Level<T> L, const v2<T>* __rest
     const bool in = rpos(q, rr, cc);
     const int k = r0 + rr, j = c0 + cc;
     v2<T> r = mk<T>(0, 0);
-    if (in && j > 0 && j < n && k > 0 && k < n) r = csub(fr[q], tab_apply(tb, L.E, up, rr, cc, k, j));
+    if (in && j > 0 && j < n && k > 0 && k < n) r = csub(fr[q], tab_apply_d(tb, dr[q], up, rr, cc));
     fr[q] = r;
   }
   __syncthreads();
