@@ -448,7 +448,12 @@ bool small_tiles(mgc_grid g, int l) {
 bool in_tail(mgc_grid g, int l) {
   return g->lv[l].n <= TAIL_MAX_N && g->coarsest() - l <= TMAXL;
 }
+// MGC_LEVEL_PASSES set in the environment (read when the cycle is enqueued):
+// every level by its own S1 / S2 launch, no pairs and no coarse tail.  The
+// results are the same bit for bit; the tests compare the two.
+bool level_passes() { return std::getenv("MGC_LEVEL_PASSES") != nullptr; }
 bool pair_level(mgc_grid g, int l) {
+  if (level_passes()) return false;
   if (l + 1 >= g->coarsest() || in_tail(g, l) || in_tail(g, l + 1) || !small_tiles(g, l)) return false;
   int s0 = l;
   while (s0 > 0 && small_tiles(g, s0 - 1)) --s0;
@@ -480,7 +485,7 @@ void vcycle_level(mgc_grid g, int l, void* u, const void* f, bool zero_guess, co
       kt_mark(g, s, kt.run, 0);
     }
     const int nl = g->coarsest() - l;
-    if (L.n <= TAIL_MAX_N && nl <= TMAXL) {
+    if (L.n <= TAIL_MAX_N && nl <= TMAXL && !level_passes()) {
       // coarse tail: every remaining level in two launches
       TailArgs<T> A{};
       double b1 = 0.0, b2 = 0.0;

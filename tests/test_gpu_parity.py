@@ -221,6 +221,34 @@ def test_graph_replays_match_eager_launches(monkeypatch):
     assert np.array_equal(outs["eager"], outs["graph"])
 
 
+@pytest.mark.parametrize("c", [Case(128, 40.0, 0.3, 5, 4, pc_gamma=GAM),       # pair 128/64, tail 32
+                               Case(512, 40.0, 0.2, 7, 8, pc_gamma=GAM),       # pairs 512/256, 128/64
+                               Case(256, 20.0, 1.1, 4, 6, pc_gamma=GAM)],      # pair 256/128, tail 32
+                         ids=["n128", "n512", "n256"])
+@pytest.mark.parametrize("fp32", [False, True], ids=["fp64", "fp32"])
+def test_fused_level_passes_match_per_level_launches(c, fp32, monkeypatch):
+    """The paired-level launches and the coarse tail compute, node by node,
+    the arithmetic of one S1 / S2 launch per level and the coarsest solve:
+    twelve FGMRES steps give the same iterate bit for bit either way."""
+    from paper_1412_1953_amd import mgcccs
+    from oracle.grid import Grid1D
+    chi = tp_rhs(Grid1D(c.n, c.L, c.R0, c.theta), c.Z1, c.Z2, c.lam, c.E)
+    inner = mgcccs.FP32 if fp32 else mgcccs.FP64
+    outs = []
+    for per_level in (False, True):
+        if per_level:
+            monkeypatch.setenv("MGC_LEVEL_PASSES", "1")
+        else:
+            monkeypatch.delenv("MGC_LEVEL_PASSES", raising=False)
+        g = c.grid()                                   # a fresh handle: its own captured graph
+        ut, ft = g.from_numpy(c.u0()), g.from_numpy(chi)
+        r = g.solve(ut, ft, outer=mgcccs.FGMRES, inner=inner, restart=10, max_it=12, tol=1e-300)
+        outs.append((to_np(ut), r.history))
+    monkeypatch.delenv("MGC_LEVEL_PASSES", raising=False)
+    assert outs[0][1] == outs[1][1]
+    assert np.array_equal(outs[0][0], outs[1][0])
+
+
 @pytest.mark.parametrize("graph", [True, False], ids=["graph", "eager"])
 @pytest.mark.parametrize("kclass", [1, 2, 3, 4, 5, 6], ids=["apply", "axpy", "s1", "s2", "project", "chain"])
 def test_kernel_timer_counts_launches_and_leaves_results_unchanged(kclass, graph, monkeypatch):
