@@ -1263,7 +1263,7 @@ __global__ void __launch_bounds__((64 * ProjCfg<T, MC>::W)) k_cccs_project(Level
   __shared__ v2<T> rt[4][PT];                    // per tile row: py, a, c, tm
   __shared__ v2<T> wv[PT][MC];                   // w_k varphi_l(k) of the tile rows
   __shared__ v2<T> wpl[MC][PT];                  // w_j phi_i(j) of the tile columns
-  __shared__ v2<T> red[64][MC], redA[64][MC];
+  __shared__ v2<T> red[64][MC + 1], redA[64][MC + 1];   // odd row pitch: lane = row without bank conflicts
   v2<T>* rtile = &ut[0][0];                      // [PT][RP] residual, after the stencil
   const int n = L.n, p = L.pitch, M = ch.M, Lc = ch.L;
   const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + 64 * ty;
