@@ -1817,7 +1817,8 @@ __global__ void __launch_bounds__(256) k_cccs_expand(int n, int pitch, v2<T>* __
   constexpr int BR = SY * ROWS;
   static_assert(BR * MC <= SX * SY, "one staged factor per thread");
   __shared__ v2<T> ea[BR][MC], vp[BR][MC];
-  __shared__ v2<T> ebt[MC][SX];                  // eB of the block's columns, transposed
+  __shared__ v2<T> ebt[MC][SX + 1];              // eB of the block's columns, transposed (odd pitch: the
+                                                 // transposing writes avoid bank conflicts)
   const int tid = threadIdx.x + SX * threadIdx.y;
   const int kb = 1 + blockIdx.y * BR;
   const int M = ch.M, Lc = ch.L;
