@@ -39,7 +39,7 @@ struct LevelInfo {
 };
 
 struct SysOff {                            // offsets of one channel system's factors
-  size_t G = 0, Vs = 0, Ws = 0, lo = 0, up = 0, Rinv = 0, Rlo = 0, Rup = 0, Tif = 0, start = 0;
+  size_t G = 0, Vs = 0, Ws = 0, lo = 0, up = 0, Rinv = 0, Tif = 0, start = 0;
 };
 
 struct CcOff {                             // CCCS tables + scratch for one precision
@@ -181,8 +181,6 @@ void layout(mgc_grid g) {
         s.up = take((size_t)N * e);
         const size_t RR = (size_t)4 * m * m;
         s.Rinv = take((size_t)(P > 1 ? P - 1 : 1) * RR * e);
-        s.Rlo = take((size_t)(P > 1 ? P - 1 : 1) * RR * e);
-        s.Rup = take((size_t)(P > 1 ? P - 1 : 1) * RR * e);
         const size_t QR = (size_t)(P > 1 ? P - 1 : 1) * 2 * m;
         s.Tif = take(QR * QR * e);
         s.start = take((size_t)(P + 1) * sizeof(int));
@@ -308,8 +306,6 @@ template <typename T> ChanSys<T> sys_of(mgc_grid g, bool A) {
   o.lo = g->at<const v2<T>>(s.lo);
   o.up = g->at<const v2<T>>(s.up);
   o.Rinv = g->at<const v2<T>>(s.Rinv);
-  o.Rlo = g->at<const v2<T>>(s.Rlo);
-  o.Rup = g->at<const v2<T>>(s.Rup);
   o.Tif = g->at<const v2<T>>(s.Tif);
   o.start = g->at<const int>(s.start);
   o.N = g->d.n - 1;
@@ -1093,8 +1089,7 @@ mgc_status upload_factors(mgc_grid g, int p, const SysOff& so, const ChannelFact
       (rc = up(so.up, f.up)))
     return rc;
   if (f.P > 1) {
-    if ((rc = up(so.Rinv, f.Rinv)) || (rc = up(so.Rlo, f.Rlo)) || (rc = up(so.Rup, f.Rup)) ||
-        (rc = up(so.Tif, f.Tif)))
+    if ((rc = up(so.Rinv, f.Rinv)) || (rc = up(so.Tif, f.Tif)))
       return rc;
   }
   (void)p;

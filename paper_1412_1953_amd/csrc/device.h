@@ -59,8 +59,6 @@ template <typename T> struct ChanSys {
   const v2<T>* lo;     // [N]
   const v2<T>* up;     // [N]
   const v2<T>* Rinv;   // [P-1][2M][2M]
-  const v2<T>* Rlo;    // [P-1][2M][2M]
-  const v2<T>* Rup;    // [P-1][2M][2M]
   const v2<T>* Tif;    // [(P-1)2M][(P-1)2M] interface solve as one matrix
   const int* start;    // [P+1]
   int N, M, P;
