@@ -962,7 +962,8 @@ mgc_status mgc_create_grid(const mgc_grid_desc* d, void* hip_stream, mgc_grid* o
   const int N = n - 1;
   // SPIKE chunks: the chunk chains are sequential in the rows of a chunk,
   // the interface system is one precomputed matrix applied in parallel, so
-  // the chunks are kept short (about sqrt(2N) of them)
+  // the chunks are kept short (about sqrt(2N) of them); at most 64, the bound
+  // the interface mat-vec stages in LDS ((P-1) 2M <= 63 x 32 entries)
   auto chunks = [&](int) {
     int P = (int)std::lround(std::sqrt(2.0 * N));
     return std::max(1, std::min(64, P));

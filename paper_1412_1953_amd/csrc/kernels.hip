@@ -1735,41 +1735,73 @@ __global__ void __launch_bounds__(64) k_cccs_chain(ChanSys<T> SA, ChanSys<T> SB,
 // linear in the right-hand side, so the host applies them to unit vectors
 // once per energy; here they act as one matrix, Y = Tif h with
 // h_q = H_q^0 + H_q^1.  One wave per row of each system (blockIdx.y), lanes
-// over the columns, the row sum by shuffles.
+// over the columns, the row sum by shuffles.  The block first issues its
+// rows' Tif loads (up to 64 U columns per row in one round), then stages h
+// (formed in FP64) in LDS from the small H vector, so that HBM sees only Tif.
+constexpr int IF_MAXQR = 63 * 32;   // (P - 1) 2M for P <= 64 chunks and M <= 16
 template <typename T>
 __global__ void __launch_bounds__(256) k_cccs_iface_mv(ChanSys<T> SA, ChanSys<T> SB, v2<T>* __restrict__ YA,
                                                        v2<T>* __restrict__ YB, const v2<T>* __restrict__ HA,
                                                        const v2<T>* __restrict__ HB) {
+  __shared__ v2<double> hs[IF_MAXQR];
   const bool isA = blockIdx.y == 0;
   const ChanSys<T>& S = isA ? SA : SB;
   const int R = 2 * S.M, QR = (S.P - 1) * R;
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (row >= QR) return;
+  const int row0 = blockIdx.x * 4;
+  if (row0 >= QR) return;                        // the whole block: no barrier is left waiting
+  const int row = row0 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const bool rok = row < QR;
   const v2<T>* H = isA ? HA : HB;
-  const v2<T>* Tr = S.Tif + (size_t)row * QR;
-  constexpr int U = 8;                           // columns per lane in flight
+  const v2<T>* Tr = S.Tif + (size_t)(rok ? row : QR - 1) * QR;
+  constexpr int U = 12;                          // columns per lane in flight
+  constexpr int NS = (IF_MAXQR + 255) / 256;     // staged entries per thread at most
+  v2<T> t[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int c = lane + 64 * u;
+    t[u] = Tr[c < QR ? c : QR - 1];
+  }
+  v2<T> h0[NS], h1[NS];
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    const int c = threadIdx.x + 256 * q, cc = c < QR ? c : QR - 1, b = cc / R, i = cc - b * R;
+    h0[q] = H[((size_t)b * 2) * R + i];
+    h1[q] = H[((size_t)b * 2 + 1) * R + i];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    const int c = threadIdx.x + 256 * q;
+    if (c < QR) {
+      v2<double> h;
+      h.x = (double)h0[q].x + (double)h1[q].x;
+      h.y = (double)h0[q].y + (double)h1[q].y;
+      hs[c] = h;
+    }
+  }
+  __syncthreads();
   double sr = 0, si = 0;
   for (int c0 = lane; c0 < QR; c0 += 64 * U) {
-    v2<T> t[U], h0[U], h1[U];
+    if (c0 != lane) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int c = c0 + 64 * u, cc = c < QR ? c : QR - 1, q = cc / R, i = cc - q * R;
-      t[u] = Tr[cc];
-      h0[u] = H[((size_t)q * 2) * R + i];
-      h1[u] = H[((size_t)q * 2 + 1) * R + i];
+      for (int u = 0; u < U; ++u) {
+        const int c = c0 + 64 * u;
+        t[u] = Tr[c < QR ? c : QR - 1];
+      }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (c0 + 64 * u < QR) {
-        const double hx = (double)h0[u].x + (double)h1[u].x, hy = (double)h0[u].y + (double)h1[u].y;
-        sr += (double)t[u].x * hx - (double)t[u].y * hy;
-        si += (double)t[u].x * hy + (double)t[u].y * hx;
+      const int c = c0 + 64 * u;
+      if (c < QR) {
+        const v2<double> h = hs[c];
+        sr += (double)t[u].x * h.x - (double)t[u].y * h.y;
+        si += (double)t[u].x * h.y + (double)t[u].y * h.x;
       }
     }
   }
   sr = wave_sum(sr);
   si = wave_sum(si);
-  if (lane == 0) (isA ? YA : YB)[row] = mk<T>((T)sr, (T)si);
+  if (rok && lane == 0) (isA ? YA : YB)[row] = mk<T>((T)sr, (T)si);
 }
 
 // Step 4: retrieval e_t = g_t - V_t T_{p+1} - W_t B_{p-1}; thread per (t, i).

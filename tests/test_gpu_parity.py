@@ -81,6 +81,22 @@ def test_cccs(c, fp32):
     assert rel_err(corr, ref - u) < (1e-4 if fp32 else 1e-10)
 
 
+def test_cccs_long_interface():
+    """513^2 with 16 channels: 32 chunks per channel system, so each interface
+    row holds 992 entries and a lane loads its row in more than one round.
+    FP64 only: the indexing is shared by both precisions, and the FP32 cycle's
+    accuracy at full size is checked through the converged mixed solves."""
+    c = Case(512, 40.0, 0.2, 6, 16)
+    g = c.grid()
+    o = c.oracle()
+    chi = tp_rhs(o.g, c.Z1, c.Z2, c.lam, c.E)
+    u = c.u0()
+    ut, ft = g.from_numpy(u, False), g.from_numpy(chi, False)
+    g.cccs(ut, ft)
+    ref = o.cc.step(u, chi)
+    assert rel_err(to_np(ut) - u, ref - u) < 1e-10
+
+
 @pytest.mark.parametrize("c", [Case(64, 20.0, -0.4, 4, 4), Case(128, 40.0, 0.1, 5, 4)],
                          ids=lambda c: f"n{c.n}_E{c.E}")
 def test_stationary_trajectory(c):
