@@ -1805,13 +1805,19 @@ __global__ void __launch_bounds__(256) k_cccs_iface_mv(ChanSys<T> SA, ChanSys<T>
 }
 
 // Step 4: retrieval e_t = g_t - V_t T_{p+1} - W_t B_{p-1}; thread per (t, i).
-template <typename T>
-__global__ void __launch_bounds__(256) k_cccs_retrieve(ChanSys<T> SA, ChanSys<T> SB,
-                                                       const v2<T>* __restrict__ gA,
-                                                       const v2<T>* __restrict__ gB,
-                                                       const v2<T>* __restrict__ YA,
-                                                       const v2<T>* __restrict__ YB,
-                                                       v2<T>* __restrict__ eA, v2<T>* __restrict__ eB) {
+// MC bounds the channel count at compile time, so that every load of a group
+// of G channels (spike entries and interface values of both terms) is issued
+// before the first use (clamped indices; unused terms are skipped at the
+// arithmetic: a group's T terms, then its B terms, one group for M <= 8).
+// One-wave blocks spread the few rows over every CU.
+template <typename T, int MC>
+__global__ void __launch_bounds__(64) k_cccs_retrieve(ChanSys<T> SA, ChanSys<T> SB,
+                                                      const v2<T>* __restrict__ gA,
+                                                      const v2<T>* __restrict__ gB,
+                                                      const v2<T>* __restrict__ YA,
+                                                      const v2<T>* __restrict__ YB,
+                                                      v2<T>* __restrict__ eA, v2<T>* __restrict__ eB) {
+  constexpr int G = MC < 8 ? MC : 8;
   const bool isA = blockIdx.y == 0;
   const ChanSys<T>& S = isA ? SA : SB;
   const int M = S.M, MM = M * M, R = 2 * M;
@@ -1825,16 +1831,31 @@ __global__ void __launch_bounds__(256) k_cccs_retrieve(ChanSys<T> SA, ChanSys<T>
   // (the boundary is recomputed rather than loaded: no load ahead of the rest)
   int p = (int)(((long long)t * S.P) / S.N);
   if (p + 1 < S.P && t >= (int)(((long long)S.N * (p + 1)) / S.P)) ++p;
+  const bool hasT = p + 1 < S.P, hasB = p > 0;
+  const size_t base = (size_t)t * MM + (size_t)i * M;
+  // Y holds P 2M-blocks, so both clamped interface rows stay inside it
+  const v2<T>* Tn = Y + (size_t)p * R + M;
+  const v2<T>* Bp = Y + (size_t)(hasB ? p - 1 : 0) * R;
+  const v2<T>* Sr[2] = {S.Vs + base, S.Ws + base};
+  const v2<T>* Xr[2] = {Tn, Bp};
+  const bool on[2] = {hasT, hasB};
   v2<T> v = g[(size_t)t * M + i];
-  if (p + 1 < S.P) {
-    const v2<T>* Tn = Y + (size_t)p * R + M;
-#pragma unroll 8
-    for (int m = 0; m < M; ++m) v = csub(v, cmul(S.Vs[(size_t)t * MM + i * M + m], Tn[m]));
-  }
-  if (p > 0) {
-    const v2<T>* Bp = Y + (size_t)(p - 1) * R;
-#pragma unroll 8
-    for (int m = 0; m < M; ++m) v = csub(v, cmul(S.Ws[(size_t)t * MM + i * M + m], Bp[m]));
+#pragma unroll
+  for (int m0 = 0; m0 < MC; m0 += G) {
+    v2<T> sv[2][G], xv[2][G];                    // [0]: V_t, T_{p+1}; [1]: W_t, B_{p-1}
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        const int mc = m0 + u < M ? m0 + u : M - 1;
+        sv[h][u] = Sr[h][mc];
+        xv[h][u] = Xr[h][mc];
+      }
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int u = 0; u < G; ++u)
+        if (on[h] && m0 + u < M) v = csub(v, cmul(sv[h][u], xv[h][u]));
   }
   e[(size_t)(t + 1) * M + i] = v;   // node index t+1
 }
@@ -2594,8 +2615,17 @@ void launch_cccs(hipStream_t s, const Level<T>& L, void* u, const void* f, const
   }
 #undef MGC_CHAIN
   const int NM = (SA.N * SA.M > SB.N * SB.M) ? SA.N * SA.M : SB.N * SB.M;
-  hipLaunchKernelGGL((k_cccs_retrieve<T>), dim3((NM + 255) / 256, 2), dim3(256), 0, s, SA, SB,
-                     (const v2<T>*)gA, (const v2<T>*)gB, (const v2<T>*)YA, (const v2<T>*)YB, eA, eB);
+#define MGC_RETRIEVE(MCC)                                                                              \
+  hipLaunchKernelGGL((k_cccs_retrieve<T, MCC>), dim3((NM + 63) / 64, 2), dim3(64), 0, s, SA, SB,        \
+                     (const v2<T>*)gA, (const v2<T>*)gB, (const v2<T>*)YA, (const v2<T>*)YB, eA, eB)
+  if (MC <= 4) {
+    MGC_RETRIEVE(4);
+  } else if (MC <= 8) {
+    MGC_RETRIEVE(8);
+  } else {
+    MGC_RETRIEVE(16);
+  }
+#undef MGC_RETRIEVE
   MGC_CC_DISPATCH(k_cccs_expand, stencil_grid(n), dim3(SX, SY), n, L.pitch, (v2<T>*)u, ch,
                   (const v2<T>*)eA, (const v2<T>*)eB);
 #undef MGC_CC_DISPATCH
