@@ -9,7 +9,8 @@ initial guess and workspace are resident in HBM when it starts.
 
 value = solved unknowns per second = 3 * 1023^2 / (seconds per step).
 The same step with the complex-FP32 preconditioner inside the FP64 FGMRES is
-reported as "mixed".  "roofline" covers the dominant kernel, timed with HIP
+reported as "mixed", and the same FP64 solves run together through the batch
+entry point as "batched".  "roofline" covers the dominant kernel, timed with HIP
 events on the library's stream inside the timed steps; "cpu_baseline" is the
 FP64 CPU oracle on a bounded sample of the same workload.
 """
@@ -43,6 +44,7 @@ def parse():
     p.add_argument("--max-it", type=int, default=20000)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-mixed", action="store_true")
+    p.add_argument("--no-batch", action="store_true", help="skip the batched leg")
     p.add_argument("--energies", type=str, default="0.05,0.5,2.0",
                    help="subset of the workload energies (profiling runs)")
     p.add_argument("--roofline-kernel", type=str, default=ROOFLINE_KERNEL, choices=sorted(KCLASS))
@@ -98,6 +100,31 @@ def time_steps(problems, inner, torch, steps, warmup, max_it, kclass=0):
         ms, launches, nbytes, floor = ms + a, launches + b, nbytes + c, floor + d
         g.set_kernel_timer(0)
     return dt, res, (ms, launches, nbytes, floor)
+
+
+def time_batch(problems, inner, torch, steps, warmup, max_it):
+    """Seconds per step with the step's solves run together through the batch
+    entry point (one graph per unfinished solve and restart round, launched
+    over the batch's streams, one synchronisation per round)."""
+    from paper_1412_1953_amd import mgcccs
+    batch = mgcccs.Batch([g for g, *_ in problems])
+    us = [p[3] for p in problems]
+    fs = [p[1] for p in problems]
+
+    def one():
+        for _, _, u0, u in problems:
+            u.copy_(u0)
+        return batch.solve(us, fs, inner=inner, restart=RESTART, max_it=max_it, tol=1e-10)
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = []
+    for _ in range(steps):
+        res = one()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, res
 
 
 def traffic_from_profile(kernel):
@@ -209,6 +236,12 @@ def main():
                          "iters": [r.iters for r in r32], "relres": [r.relres for r in r32],
                          "status": [r.status for r in r32],
                          "speedup_vs_fp64": dt64 / dt32}
+    if not a.no_batch:
+        dtb, rb = time_batch(problems, mgcccs.FP64, torch, a.steps, a.warmup, a.max_it)
+        line["batched"] = {"value": unknowns / dtb, "ms_per_step": dtb * 1e3,
+                           "iters": [r.iters for r in rb], "relres": [r.relres for r in rb],
+                           "status": [r.status for r in rb],
+                           "speedup_vs_fp64": dt64 / dtb}
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(wls[0])
     print(json.dumps(line), flush=True)

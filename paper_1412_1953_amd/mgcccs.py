@@ -274,8 +274,9 @@ def k0_of(E: float, Z1: float = 1.0) -> float:
 
 
 class Batch:
-    """Handles solved together (mgc_batch_*): one parent graph launch and one
-    synchronisation per restart round for all unfinished solves."""
+    """Handles solved together (mgc_batch_*): per restart round, one graph per
+    unfinished solve, launched over the batch's streams, and one
+    synchronisation for all of them."""
 
     def __init__(self, grids):
         self.lib = load_library()
