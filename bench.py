@@ -45,6 +45,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-mixed", action="store_true")
     p.add_argument("--no-batch", action="store_true", help="skip the batched leg")
+    p.add_argument("--no-sweep", action="store_true", help="skip the cross-section sweep leg")
     p.add_argument("--energies", type=str, default="0.05,0.5,2.0",
                    help="subset of the workload energies (profiling runs)")
     p.add_argument("--roofline-kernel", type=str, default=ROOFLINE_KERNEL, choices=sorted(KCLASS))
@@ -125,6 +126,25 @@ def time_batch(problems, inner, torch, steps, warmup, max_it):
         res = one()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps, res
+
+
+def time_sweep(problem, E, torch, calls=20, npairs=256):
+    """Wall-clock milliseconds per energy-sharing sweep of the ionisation
+    amplitude at excess energy E (npairs momentum pairs in one
+    mgc_cross_section_sweep call, host test functions and the synchronising
+    read-back included) on the step's converged solution."""
+    from paper_1412_1953_amd import mgcccs
+    g, chi, _, u = problem
+    alphas = [0.01 + (math.pi / 2 - 0.02) * a / (npairs - 1) for a in range(npairs)]
+    k1s, k2s = mgcccs.sharing_momenta(E, alphas)
+    g.cross_section_sweep(u, chi, k1s, k2s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        zs, _ = g.cross_section_sweep(u, chi, k1s, k2s)
+    dt = (time.perf_counter() - t0) / calls
+    return {"pairs": npairs, "excess_energy": E, "ms_per_call": dt * 1e3,
+            "zeta_max": max(abs(z) for z in zs)}
 
 
 def traffic_from_profile(kernel):
@@ -236,6 +256,8 @@ def main():
                          "iters": [r.iters for r in r32], "relres": [r.relres for r in r32],
                          "status": [r.status for r in r32],
                          "speedup_vs_fp64": dt64 / dt32}
+    if not a.no_sweep:
+        line["sweep"] = time_sweep(problems[0], wls[0].E, torch)
     if not a.no_batch:
         dtb, rb = time_batch(problems, mgcccs.FP64, torch, a.steps, a.warmup, a.max_it)
         line["batched"] = {"value": unknowns / dtb, "ms_per_step": dtb * 1e3,

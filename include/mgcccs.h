@@ -60,6 +60,9 @@ typedef enum {
 /* Largest FGMRES restart length (basis size) the library supports. */
 #define MGC_MAX_RESTART 16
 
+/* Most momentum pairs one mgc_cross_section_sweep call evaluates. */
+#define MGC_SWEEP_MAX 256
+
 typedef enum { MGC_FP64 = 0, MGC_FP32 = 1 } mgc_precision;
 
 typedef enum {
@@ -191,6 +194,18 @@ mgc_status mgc_solve_transpose(mgc_grid g, void* v, const void* gvec,
  * sigma = 8 pi^2 / k0^2 * |zeta|^2 / (k1 k2).  Synchronising.                 */
 mgc_status mgc_cross_section(mgc_grid g, const void* u, const void* chi,
                              double k1, double k2, double zeta[2], double* sigma);
+
+/* The amplitude and cross section of mgc_cross_section for many momentum
+ * pairs in one pass over the field (Sec. 3.3: the singly differential cross
+ * section of an energy sharing is sigma along k1 = K cos a, k2 = K sin a,
+ * K^2 / 2 the excess energy, a in [0, pi/2]):
+ *   zeta[2a], zeta[2a+1] = Re, Im zeta(k1[a], k2[a]),  sigma[a] = sigma(k1[a], k2[a]).
+ * k1, k2: host arrays of npairs momenta > 0; zeta: host array of 2 npairs
+ * doubles; sigma: host array of npairs doubles, or NULL.  u, chi: FP64 level-0
+ * fields.  1 <= npairs <= MGC_SWEEP_MAX, else MGC_EINVAL (also for a null
+ * pointer or a momentum that is not positive).  Synchronising.                */
+mgc_status mgc_cross_section_sweep(mgc_grid g, const void* u, const void* chi, int npairs,
+                                   const double* k1, const double* k2, double* zeta, double* sigma);
 
 /* Gradient of sigma(k1, k2) with respect to (Z1, Z2, lambda) for u = A^{-1} chi,
  * chi the Temkin-Poet right-hand side of mgc_build_rhs_tp (call order:

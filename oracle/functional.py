@@ -12,8 +12,9 @@ phi_k comes from the 3-point recurrence of eq. testfunction on the real nodes
 and is scaled so that its local amplitude at R0,
     a^2 = phi(R0)^2 + (phi'(R0)/p)^2,   p = sqrt(k^2 - 2 V1(R0)),
 equals 1/sqrt(p).  Physical cross-section values are parity unpinned (the
-paper prints none for this model); the pins are the Z1 = 0 closed form and
-linearity in u.
+paper prints none for this model); the pins are the Z1 = 0 closed form,
+linearity in u, the factorisation for a separable source and the exchange
+symmetry of the two coordinates.
 """
 from __future__ import annotations
 
@@ -70,6 +71,13 @@ def zeta(g: Grid1D, Z1: float, lam: float, u: np.ndarray, chi: np.ndarray,
     V12 = lam / zr[m]
     src = chi - V12 * u
     return complex(f2 @ src @ f1)              # sum_k f2[k] sum_j src[k, j] f1[j]
+
+
+def zeta_sweep(g: Grid1D, Z1: float, lam: float, u: np.ndarray, chi: np.ndarray, k1s, k2s) -> list:
+    """zeta for each momentum pair (k1s[a], k2s[a]), pair by pair.  An energy
+    sharing sweep (Sec. 3.3) takes k1 = K cos a, k2 = K sin a, K^2/2 the excess
+    energy, for a in [0, pi/2]."""
+    return [zeta(g, Z1, lam, u, chi, k1, k2) for k1, k2 in zip(k1s, k2s)]
 
 
 def sigma(z: complex, E: float, Z1: float, k1: float, k2: float) -> float:

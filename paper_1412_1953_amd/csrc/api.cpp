@@ -113,6 +113,7 @@ struct mgc_grid_s {
   size_t W = 0, Z[2] = {0, 0};
   size_t gm = 0;                           // GmresState arrays
   size_t zeta_f = 0, adj = 0;
+  size_t sweep_f = 0, sweep_part = 0, sweep_out = 0;   // mgc_cross_section_sweep
   int nchunksB = 1;
   bool prec_on[2] = {true, false};
 
@@ -225,6 +226,9 @@ void layout(mgc_grid g) {
   g->gm = take((size_t)(16 * (m + 2) + 2 * (m + 1) * (m + 1) + 64) * sizeof(double));
   g->zeta_f = take(4 * (n + 1) * sizeof(double));
   g->adj = take(g->field_bytes(0, P64));
+  g->sweep_f = take((size_t)2 * (n + 1) * MGC_SWEEP_MAX * sizeof(double));
+  g->sweep_part = take((size_t)zeta_sweep_blocks(n) * 2 * MGC_SWEEP_MAX * sizeof(double));
+  g->sweep_out = take((size_t)2 * MGC_SWEEP_MAX * sizeof(double));
   g->need = off;
 }
 
@@ -1327,6 +1331,44 @@ mgc_status mgc_cross_section(mgc_grid g, const void* u, const void* chi, double 
   zeta[1] = hz[1];
   const double k0sq = 2.0 * (g->E + 0.5 * g->Z1 * g->Z1);
   if (sigma) *sigma = 8.0 * M_PI * M_PI / k0sq * (hz[0] * hz[0] + hz[1] * hz[1]) / (k1 * k2);
+  return MGC_OK;
+}
+
+mgc_status mgc_cross_section_sweep(mgc_grid g, const void* u, const void* chi, int npairs, const double* k1,
+                                   const double* k2, double* zeta, double* sigma) {
+  mgc_status rc = check_ready(g);
+  if (rc) return rc;
+  if (!u || !chi || !k1 || !k2 || !zeta) return fail(MGC_EINVAL, "null argument");
+  if (npairs < 1 || npairs > MGC_SWEEP_MAX) return fail(MGC_EINVAL, "npairs must lie in [1, MGC_SWEEP_MAX]");
+  for (int a = 0; a < npairs; ++a)
+    if (!(k1[a] > 0) || !(k2[a] > 0) || !std::isfinite(k1[a]) || !std::isfinite(k2[a]))
+      return fail(MGC_EINVAL, "momenta must be finite and positive");
+  const Axis& ax = g->exact;
+  const int n = ax.n, top = std::min(ax.j0, n - 1);
+  const int pp = (npairs + 63) / 64 * 64;
+  // weighted test functions as [node][pair], zero for the padding pairs
+  std::vector<double> F((size_t)2 * (n + 1) * pp, 0.0), f, d;
+  for (int a = 0; a < npairs; ++a) {
+    test_function(ax, g->Z1, k1[a], f, d);
+    for (int j = 0; j <= n; ++j) F[(size_t)j * pp + a] = f[j];
+    test_function(ax, g->Z1, k2[a], f, d);
+    for (int j = 0; j <= n; ++j) F[(size_t)(n + 1 + j) * pp + a] = f[j];
+  }
+  if ((rc = upload(g, g->sweep_f, F.data(), F.size() * sizeof(double)))) return rc;
+  const double* F1T = g->at<const double>(g->sweep_f);
+  double* out = g->at<double>(g->sweep_out);
+  launch_zeta_sweep(g->stream, n, g->lv[0].pitch, top, pp, exact_level(g).tm, F1T, F1T + (size_t)(n + 1) * pp,
+                    (const double2*)u, (const double2*)chi, g->at<double>(g->sweep_part), out);
+  std::vector<double> hz((size_t)2 * pp);
+  HIPCHK(g, hipMemcpyAsync(hz.data(), out, hz.size() * sizeof(double), hipMemcpyDeviceToHost, g->stream));
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  const double k0sq = 2.0 * (g->E + 0.5 * g->Z1 * g->Z1);
+  for (int a = 0; a < npairs; ++a) {
+    zeta[2 * a] = hz[2 * a];
+    zeta[2 * a + 1] = hz[2 * a + 1];
+    if (sigma)
+      sigma[a] = 8.0 * M_PI * M_PI / k0sq * (hz[2 * a] * hz[2 * a] + hz[2 * a + 1] * hz[2 * a + 1]) / (k1[a] * k2[a]);
+  }
   return MGC_OK;
 }
 

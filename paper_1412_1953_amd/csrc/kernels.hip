@@ -2340,6 +2340,80 @@ __global__ void __launch_bounds__(256) k_zeta_part(int n, int pitch, int j0, con
 }
 
 
+// Many momentum pairs at once (eq. double-ionization for each pair a):
+//   zeta_a = sum_k f2_a[k] sum_j s[k][j] f1_a[j],   s = chi - V12 u,
+// over the real region, rows and columns 1 .. top.  Block = SWR rows k and one
+// of SWJ column ranges, thread = pair a (blockDim.x = pp).  s of the block's
+// rows is staged in LDS SWC columns at a time (one value per thread and
+// round), the test functions are read as [node][pair] rows, coalesced over the
+// pairs, a round's SWC of them issued together.  One (re, im) partial per
+// block and pair; k_zeta_sweep_sum adds the blocks in a fixed order.
+constexpr int SWR = 8, SWJ = 4, SWC = 32;
+__global__ void __launch_bounds__(256) k_zeta_sweep_part(int n, int pitch, int top, int pp,
+                                                         const double2* __restrict__ tm,
+                                                         const double* __restrict__ F1T,
+                                                         const double* __restrict__ F2T,
+                                                         const double2* __restrict__ u,
+                                                         const double2* __restrict__ chi,
+                                                         double* __restrict__ part) {
+  __shared__ v2<double> st[SWR][SWC];
+  const int a = threadIdx.x;
+  const int k0 = 1 + blockIdx.x * SWR;
+  const int jn = (top + SWJ - 1) / SWJ;
+  const int jb = 1 + blockIdx.y * jn, je = jb + jn < top + 1 ? jb + jn : top + 1;   // j in [jb, je)
+  double ar[SWR], ai[SWR];
+#pragma unroll
+  for (int r = 0; r < SWR; ++r) ar[r] = ai[r] = 0.0;
+  for (int c0 = jb; c0 < je; c0 += SWC) {
+    double f[SWC];
+#pragma unroll
+    for (int c = 0; c < SWC; ++c) {
+      const int j = c0 + c;
+      f[c] = F1T[(size_t)(j < n ? j : n) * pp + a];
+    }
+    for (int q = a; q < SWR * SWC; q += pp) {
+      const int r = q / SWC, c = q - r * SWC, k = k0 + r, j = c0 + c;
+      v2<double> v = mk<double>(0, 0);
+      if (k <= top && j < je) {
+        const size_t idx = (size_t)k * pitch + j;
+        v = csub(chi[idx], cmul(tm[j > k ? j : k], u[idx]));
+      }
+      st[r][c] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < SWC; ++c)
+#pragma unroll
+      for (int r = 0; r < SWR; ++r) {
+        const v2<double> sv = st[r][c];      // zero beyond the column range
+        ar[r] += sv.x * f[c];
+        ai[r] += sv.y * f[c];
+      }
+    __syncthreads();
+  }
+  double zr = 0.0, zi = 0.0;
+#pragma unroll
+  for (int r = 0; r < SWR; ++r) {
+    const int k = k0 + r;
+    if (k <= top) {
+      const double w = F2T[(size_t)k * pp + a];
+      zr += w * ar[r];
+      zi += w * ai[r];
+    }
+  }
+  const size_t blk = blockIdx.x + (size_t)gridDim.x * blockIdx.y;
+  part[blk * 2 * pp + 2 * a] = zr;
+  part[blk * 2 * pp + 2 * a + 1] = zi;
+}
+
+// out[q] = sum_b part[b * 2pp + q], 256 quantities per block
+__global__ void __launch_bounds__(256) k_zeta_sweep_sum(int nb, int nq, const double* __restrict__ part,
+                                                        double* __restrict__ out) {
+  const int q0 = 256 * blockIdx.x;
+  const int nqb = nq - q0 < 256 ? nq - q0 : 256;
+  finish_sum_nt<256>(part + q0, nb, nqb, out + q0, nq);
+}
+
 // ----------------------------------------------------------------------------
 // Sensitivities of the ionisation amplitude zeta (eq. double-ionization) with
 // respect to p = (Z1, Z2, lambda).  With F = f2[k] f1[j] (trapezoid-weighted
@@ -2798,6 +2872,14 @@ void launch_sens_part(hipStream_t s, int n, int pitch, int j0, const double2* z,
 void launch_zeta_part(hipStream_t s, int n, int pitch, int j0, const double2* tm, const double* f1,
                       const double* f2, const double2* u, const double2* chi, double* part) {
   hipLaunchKernelGGL(k_zeta_part, vec_grid(n), dim3(256), 0, s, n, pitch, j0, tm, f1, f2, u, chi, part);
+}
+int zeta_sweep_blocks(int top) { return ((top + SWR - 1) / SWR) * SWJ; }
+void launch_zeta_sweep(hipStream_t s, int n, int pitch, int top, int pp, const double2* tm, const double* F1T,
+                       const double* F2T, const double2* u, const double2* chi, double* part, double* out) {
+  hipLaunchKernelGGL(k_zeta_sweep_part, dim3((top + SWR - 1) / SWR, SWJ), dim3(pp), 0, s, n, pitch, top, pp, tm,
+                     F1T, F2T, u, chi, part);
+  hipLaunchKernelGGL(k_zeta_sweep_sum, dim3((2 * pp + 255) / 256), dim3(256), 0, s, zeta_sweep_blocks(top),
+                     2 * pp, (const double*)part, out);
 }
 
 }  // namespace mgc

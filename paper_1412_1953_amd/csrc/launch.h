@@ -147,5 +147,12 @@ void launch_sens_part(hipStream_t s, int n, int pitch, int j0, const double2* z,
                       double lam, double E, double* part);
 void launch_zeta_part(hipStream_t s, int n, int pitch, int j0, const double2* tm, const double* f1,
                       const double* f2, const double2* u, const double2* chi, double* part);
+// zeta for pp momentum pairs (pp a multiple of 64, <= 256): F1T, F2T are the
+// weighted test functions as [n+1][pp] (row = node, column = pair), rows
+// 1 .. top of the real region are summed.  part: zeta_sweep_blocks(top) x 2pp
+// doubles; out: 2pp doubles (re, im per pair).
+int zeta_sweep_blocks(int top);
+void launch_zeta_sweep(hipStream_t s, int n, int pitch, int top, int pp, const double2* tm, const double* F1T,
+                       const double* F2T, const double2* u, const double2* chi, double* part, double* out);
 
 }  // namespace mgc

@@ -19,12 +19,13 @@ MGC_OK, MGC_EINVAL, MGC_ENOMEM, MGC_EHIP, MGC_ENOCONV, MGC_ESTATE, MGC_ENUMERIC 
 STATUS_NAMES = {0: "MGC_OK", -1: "MGC_EINVAL", -2: "MGC_ENOMEM", -3: "MGC_EHIP", -4: "MGC_ENOCONV",
                 -5: "MGC_ESTATE", -6: "MGC_ENUMERIC"}
 FP64, FP32 = 0, 1
+SWEEP_MAX = 256                      # MGC_SWEEP_MAX
 STATIONARY, IR, FGMRES = 0, 1, 2
 
 EXPORTED = ["mgc_create_grid", "mgc_workspace_bytes", "mgc_bind_workspace", "mgc_field_pitch",
             "mgc_set_potential", "mgc_set_energy", "mgc_build_rhs_tp", "mgc_residual", "mgc_vcycle",
             "mgc_cccs", "mgc_solve", "mgc_solve_transpose", "mgc_cross_section",
-            "mgc_cross_section_grad", "mgc_set_kernel_timer", "mgc_read_kernel_timer",
+            "mgc_cross_section_sweep", "mgc_cross_section_grad", "mgc_set_kernel_timer", "mgc_read_kernel_timer",
             "mgc_batch_create", "mgc_batch_solve", "mgc_batch_destroy",
             "mgc_destroy_grid", "mgc_last_error"]
 
@@ -83,6 +84,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mgc_solve": [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(Stats)],
         "mgc_solve_transpose": [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(Stats)],
         "mgc_cross_section": [vp, vp, vp, d, d, ctypes.POINTER(d), ctypes.POINTER(d)],
+        "mgc_cross_section_sweep": [vp, vp, vp, i, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(d),
+                                    ctypes.POINTER(d)],
         "mgc_cross_section_grad": [vp, vp, vp, d, d, ctypes.POINTER(SolveOpts), vp,
                                    ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(d),
                                    ctypes.POINTER(Stats)],
@@ -266,6 +269,26 @@ class Grid:
         _check(self.lib.mgc_cross_section(self.h, self._ptr(u), self._ptr(chi), k1, k2, z,
                                           ctypes.byref(sig)))
         return complex(z[0], z[1]), sig.value
+
+
+    def cross_section_sweep(self, u, chi, k1s, k2s):
+        """zeta and sigma for every pair (k1s[a], k2s[a]) in one pass (at most
+        SWEEP_MAX pairs); returns (list of complex zeta, list of sigma)."""
+        npairs = len(k1s)
+        assert len(k2s) == npairs
+        a1 = (ctypes.c_double * npairs)(*[float(k) for k in k1s])
+        a2 = (ctypes.c_double * npairs)(*[float(k) for k in k2s])
+        z = (ctypes.c_double * (2 * npairs))()
+        sig = (ctypes.c_double * npairs)()
+        _check(self.lib.mgc_cross_section_sweep(self.h, self._ptr(u), self._ptr(chi), npairs, a1, a2, z, sig))
+        return [complex(z[2 * a], z[2 * a + 1]) for a in range(npairs)], [sig[a] for a in range(npairs)]
+
+
+def sharing_momenta(E_excess: float, alphas):
+    """Momentum pairs k1 = K cos a, k2 = K sin a of an energy-sharing sweep,
+    K^2 / 2 = E_excess (Sec. 3.3)."""
+    K = math.sqrt(2.0 * E_excess)
+    return [K * math.cos(a) for a in alphas], [K * math.sin(a) for a in alphas]
 
 
 def k0_of(E: float, Z1: float = 1.0) -> float:

@@ -356,6 +356,45 @@ def test_zeta_is_affine_in_u():
     assert abs(z(u1 + 2 * u2) - (z(u1) + 2 * z(u2) - 2 * z(0 * u1))) < 1e-12 * abs(z(u1))
 
 
+def test_zeta_factorises_for_a_separable_source():
+    """u = 0 and chi[k][j] = a_k b_j (row k <-> x2): the double integral of
+    eq. double-ionization splits into two 1D trapezoid sums,
+    zeta(k1, k2) = (sum_k t_k phi_k2(x_k) a_k) (sum_j t_j phi_k1(x_j) b_j),
+    for every pair of a sweep (k1 != k2, so a swap of the two roles fails)."""
+    g = Grid1D(64, 20.0, 15.0, math.pi / 6)
+    rng = np.random.default_rng(5)
+    a = rng.standard_normal(65) + 1j * rng.standard_normal(65)
+    b = rng.standard_normal(65) + 1j * rng.standard_normal(65)
+    chi = np.outer(a, b)
+    u = np.zeros_like(chi)
+    alphas = np.linspace(0.05, 1.5, 7)
+    K = 1.1
+    k1s, k2s = K * np.cos(alphas), K * np.sin(alphas)
+    zs = fn.zeta_sweep(g, 1.0, 1.0, u, chi, k1s, k2s)
+    t = fn.trapezoid_weights(g)
+    for z, k1, k2 in zip(zs, k1s, k2s):
+        p1 = np.zeros(65)
+        p2 = np.zeros(65)
+        q1, q2 = fn.test_function(g, 1.0, k1), fn.test_function(g, 1.0, k2)
+        p1[:len(q1)] = q1
+        p2[:len(q2)] = q2
+        ref = np.sum(t * p2 * a) * np.sum(t * p1 * b)
+        assert abs(z - ref) < 1e-12 * abs(ref)
+
+
+def test_zeta_exchange_symmetry():
+    """V12 = lambda / z_max(j,k) is symmetric under x1 <-> x2, so exchanging the
+    two coordinates of u and chi exchanges the momenta:
+    zeta(k1, k2; u, chi) = zeta(k2, k1; u^T, chi^T)."""
+    g = Grid1D(64, 20.0, 15.0, math.pi / 6)
+    chi = rng_field(64, 21)
+    u = rng_field(64, 22)
+    za = fn.zeta_sweep(g, 1.0, 1.3, u, chi, [0.4, 0.9], [1.2, 0.5])
+    zb = fn.zeta_sweep(g, 1.0, 1.3, u.T.copy(), chi.T.copy(), [1.2, 0.5], [0.4, 0.9])
+    for x, y in zip(za, zb):
+        assert abs(x - y) < 1e-12 * abs(x)
+
+
 # ---------------------------------------------------------------- P14 (adjoint)
 @pytest.mark.parametrize("p", [(1.0, 1.0, 1.0), (1.1, 0.9, 1.3)])
 def test_adjoint_gradient_matches_central_differences(p):
