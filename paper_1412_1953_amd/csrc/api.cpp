@@ -5,12 +5,15 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "launch.h"
@@ -1347,13 +1350,34 @@ mgc_status mgc_cross_section_sweep(mgc_grid g, const void* u, const void* chi, i
   const int n = ax.n, top = std::min(ax.j0, n - 1);
   const int pp = (npairs + 63) / 64 * 64;
   // weighted test functions as [node][pair], zero for the padding pairs
-  std::vector<double> F((size_t)2 * (n + 1) * pp, 0.0), f, d;
-  for (int a = 0; a < npairs; ++a) {
-    test_function(ax, g->Z1, k1[a], f, d);
-    for (int j = 0; j <= n; ++j) F[(size_t)j * pp + a] = f[j];
-    test_function(ax, g->Z1, k2[a], f, d);
-    for (int j = 0; j <= n; ++j) F[(size_t)(n + 1 + j) * pp + a] = f[j];
+  // The pairs' recurrences are independent: host threads take blocks of 8
+  // pairs (one 64-byte line of a table row, so no line has two writers) from
+  // a shared counter.  A thread that cannot be started leaves its share to the
+  // others; every pair's arithmetic is the same as in a sequential loop.
+  std::vector<double> F((size_t)2 * (n + 1) * pp, 0.0);
+  const int nblk = (npairs + 7) / 8;
+  std::atomic<int> next{0};
+  auto work = [&]() {
+    std::vector<double> f, d;
+    for (int b; (b = next.fetch_add(1)) < nblk;)
+      for (int a = 8 * b; a < std::min(npairs, 8 * b + 8); ++a) {
+        test_function(ax, g->Z1, k1[a], f, d);
+        for (int j = 0; j <= n; ++j) F[(size_t)j * pp + a] = f[j];
+        test_function(ax, g->Z1, k2[a], f, d);
+        for (int j = 0; j <= n; ++j) F[(size_t)(n + 1 + j) * pp + a] = f[j];
+      }
+  };
+  const int nt = std::min(nblk, (int)std::min(std::max(1u, std::thread::hardware_concurrency()), 16u));
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nt; ++t) {
+    try {
+      pool.emplace_back(work);
+    } catch (...) {
+      break;
+    }
   }
+  work();
+  for (auto& th : pool) th.join();
   if ((rc = upload(g, g->sweep_f, F.data(), F.size() * sizeof(double)))) return rc;
   const double* F1T = g->at<const double>(g->sweep_f);
   double* out = g->at<double>(g->sweep_out);
