@@ -2348,7 +2348,7 @@ __global__ void __launch_bounds__(256) k_zeta_part(int n, int pitch, int j0, con
 // round), the test functions are read as [node][pair] rows, coalesced over the
 // pairs, a round's SWC of them issued together.  One (re, im) partial per
 // block and pair; k_zeta_sweep_sum adds the blocks in a fixed order.
-constexpr int SWR = 8, SWJ = 4, SWC = 32;
+constexpr int SWR = 8, SWJ = 8, SWC = 32;
 __global__ void __launch_bounds__(256) k_zeta_sweep_part(int n, int pitch, int top, int pp,
                                                          const double2* __restrict__ tm,
                                                          const double* __restrict__ F1T,
@@ -2406,11 +2406,14 @@ __global__ void __launch_bounds__(256) k_zeta_sweep_part(int n, int pitch, int t
   part[blk * 2 * pp + 2 * a + 1] = zi;
 }
 
-// out[q] = sum_b part[b * 2pp + q], 256 quantities per block
+// out[q] = sum_b part[b * 2pp + q]: SWQ quantities per block, each summed in
+// 256 / SWQ slices of the blocks (enough blocks and loads in flight for the
+// few hundred partials per quantity)
+constexpr int SWQ = 32;
 __global__ void __launch_bounds__(256) k_zeta_sweep_sum(int nb, int nq, const double* __restrict__ part,
                                                         double* __restrict__ out) {
-  const int q0 = 256 * blockIdx.x;
-  const int nqb = nq - q0 < 256 ? nq - q0 : 256;
+  const int q0 = SWQ * blockIdx.x;
+  const int nqb = nq - q0 < SWQ ? nq - q0 : SWQ;
   finish_sum_nt<256>(part + q0, nb, nqb, out + q0, nq);
 }
 
@@ -2878,7 +2881,7 @@ void launch_zeta_sweep(hipStream_t s, int n, int pitch, int top, int pp, const d
                        const double* F2T, const double2* u, const double2* chi, double* part, double* out) {
   hipLaunchKernelGGL(k_zeta_sweep_part, dim3((top + SWR - 1) / SWR, SWJ), dim3(pp), 0, s, n, pitch, top, pp, tm,
                      F1T, F2T, u, chi, part);
-  hipLaunchKernelGGL(k_zeta_sweep_sum, dim3((2 * pp + 255) / 256), dim3(256), 0, s, zeta_sweep_blocks(top),
+  hipLaunchKernelGGL(k_zeta_sweep_sum, dim3((2 * pp + SWQ - 1) / SWQ), dim3(256), 0, s, zeta_sweep_blocks(top),
                      2 * pp, (const double*)part, out);
 }
 
