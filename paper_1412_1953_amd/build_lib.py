@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "api.cpp", "setup.cpp")]
 OUT = os.path.join(HERE, "libmgcccs.so")
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-pthread",
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # packed FP32 instructions are disabled on purpose: the compiler must
          # not emit v_pk_* FP32 arithmetic for any kernel in this library
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -5,15 +5,12 @@
 
 #include <hip/hip_runtime.h>
 
-#include <algorithm>
-#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <string>
-#include <thread>
 #include <vector>
 
 #include "launch.h"
@@ -116,7 +113,7 @@ struct mgc_grid_s {
   size_t W = 0, Z[2] = {0, 0};
   size_t gm = 0;                           // GmresState arrays
   size_t zeta_f = 0, adj = 0;
-  size_t sweep_f = 0, sweep_part = 0, sweep_out = 0;   // mgc_cross_section_sweep
+  size_t sweep_f = 0, sweep_k = 0, sweep_part = 0, sweep_out = 0;   // mgc_cross_section_sweep
   int nchunksB = 1;
   bool prec_on[2] = {true, false};
 
@@ -232,6 +229,7 @@ void layout(mgc_grid g) {
   g->sweep_f = take((size_t)2 * (n + 1) * MGC_SWEEP_MAX * sizeof(double));
   g->sweep_part = take((size_t)zeta_sweep_blocks(n) * 2 * MGC_SWEEP_MAX * sizeof(double));
   g->sweep_out = take((size_t)2 * MGC_SWEEP_MAX * sizeof(double));
+  g->sweep_k = take((size_t)2 * MGC_SWEEP_MAX * sizeof(double));
   g->need = off;
 }
 
@@ -1349,37 +1347,14 @@ mgc_status mgc_cross_section_sweep(mgc_grid g, const void* u, const void* chi, i
   const Axis& ax = g->exact;
   const int n = ax.n, top = std::min(ax.j0, n - 1);
   const int pp = (npairs + 63) / 64 * 64;
-  // weighted test functions as [node][pair], zero for the padding pairs
-  // The pairs' recurrences are independent: host threads take blocks of 8
-  // pairs (one 64-byte line of a table row, so no line has two writers) from
-  // a shared counter.  A thread that cannot be started leaves its share to the
-  // others; every pair's arithmetic is the same as in a sequential loop.
-  std::vector<double> F((size_t)2 * (n + 1) * pp, 0.0);
-  const int nblk = (npairs + 7) / 8;
-  std::atomic<int> next{0};
-  auto work = [&]() {
-    std::vector<double> f, d;
-    for (int b; (b = next.fetch_add(1)) < nblk;)
-      for (int a = 8 * b; a < std::min(npairs, 8 * b + 8); ++a) {
-        test_function(ax, g->Z1, k1[a], f, d);
-        for (int j = 0; j <= n; ++j) F[(size_t)j * pp + a] = f[j];
-        test_function(ax, g->Z1, k2[a], f, d);
-        for (int j = 0; j <= n; ++j) F[(size_t)(n + 1 + j) * pp + a] = f[j];
-      }
-  };
-  const int nt = std::min(nblk, (int)std::min(std::max(1u, std::thread::hardware_concurrency()), 16u));
-  std::vector<std::thread> pool;
-  for (int t = 1; t < nt; ++t) {
-    try {
-      pool.emplace_back(work);
-    } catch (...) {
-      break;
-    }
-  }
-  work();
-  for (auto& th : pool) th.join();
-  if ((rc = upload(g, g->sweep_f, F.data(), F.size() * sizeof(double)))) return rc;
-  const double* F1T = g->at<const double>(g->sweep_f);
+  // weighted test functions as [node][pair], zero for the padding pairs,
+  // computed on the device from the momenta
+  std::vector<double> kk(k1, k1 + npairs);
+  kk.insert(kk.end(), k2, k2 + npairs);
+  if ((rc = upload(g, g->sweep_k, kk.data(), kk.size() * sizeof(double)))) return rc;
+  double* F = g->at<double>(g->sweep_f);
+  launch_sweep_testfn(g->stream, n, ax.j0, ax.h, g->Z1, npairs, pp, g->at<const double>(g->sweep_k), F);
+  const double* F1T = F;
   double* out = g->at<double>(g->sweep_out);
   launch_zeta_sweep(g->stream, n, g->lv[0].pitch, top, pp, exact_level(g).tm, F1T, F1T + (size_t)(n + 1) * pp,
                     (const double2*)u, (const double2*)chi, g->at<double>(g->sweep_part), out);

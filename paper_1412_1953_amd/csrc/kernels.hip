@@ -2406,6 +2406,67 @@ __global__ void __launch_bounds__(256) k_zeta_sweep_part(int n, int pitch, int t
   part[blk * 2 * pp + 2 * a + 1] = zi;
 }
 
+// Weighted test functions of the sweep (eq. testfunction), one thread per
+// function: column c < pp of F takes momentum kk[c] (the x1 side), column
+// pp + c momentum kk[npairs + c] (the x2 side); the table is [side][node][pair],
+// F[(side (n+1) + j) pp + c].  The three-point finite-difference recurrence of
+// the real-axis radial equation starts from phi(0) = 0, phi(h) = h; the
+// amplitude is fixed by the WKB-type matching at node jr = min(j0, top - 1)
+// (unit asymptotic amplitude 1 / sqrt(p)), and the trapezoid weight (h, half
+// at j0) is folded in.  Nodes outside 1 .. min(j0, n - 1) and padding pairs
+// are zero.  Contraction is off so every value is the correctly rounded
+// sequence of operations of the host's single-pair test function.
+__global__ void __launch_bounds__(64) k_sweep_testfn(int n, int j0, double h, double Z1, int npairs, int pp,
+                                                     const double* __restrict__ kk, double* __restrict__ F) {
+#pragma clang fp contract(off)
+  constexpr int CH = 1024;                         // potential values staged per round
+  __shared__ double V[CH];
+  const int t = blockIdx.x * 64 + threadIdx.x;     // the grid is exactly 2 pp threads
+  const int side = t / pp, c = t - side * pp;
+  const bool live = c < npairs;                    // padding pairs run along and store zeros
+  double* col = F + (size_t)side * (n + 1) * pp + c;
+  const double k = live ? kk[side * npairs + c] : 1.0;
+  const int top = j0 + 1 < n ? j0 + 1 : n;
+  const double g2 = 2.0 * h * h, kh = 0.5 * k * k;
+  double pm = 0.0, p0 = h;                         // phi[j-1], phi[j]
+  col[0] = 0.0;
+  col[(size_t)pp] = h;
+  // the potential term depends on the node only: the block computes it once
+  // per round, so no division sits on the recurrence's dependency chain
+  for (int jc = 1; jc < top; jc += CH) {
+    const int cnt = top - jc < CH ? top - jc : CH;
+    __syncthreads();
+    for (int i = threadIdx.x; i < cnt; i += 64) V[i] = 0.0 - Z1 / ((double)(jc + i) * h);
+    __syncthreads();
+    for (int i = 0; i < cnt; ++i) {
+      const double pn = (2.0 * p0 - pm) + (g2 * (V[i] - kh)) * p0;
+      col[(size_t)(jc + i + 1) * pp] = pn;
+      pm = p0;
+      p0 = pn;
+    }
+  }
+  const int jr = j0 < top - 1 ? j0 : top - 1;
+  const double pr = sqrt(k * k - 2.0 * (0.0 - Z1 / ((double)jr * h)));
+  const double dphi = (col[(size_t)(jr + 1) * pp] - col[(size_t)(jr - 1) * pp]) / (2.0 * h);
+  const double q = dphi / pr, f = col[(size_t)jr * pp];
+  const double amp = sqrt(f * f + q * q);
+  const double sc = 1.0 / (amp * sqrt(pr));
+  const int last = live ? (j0 < n - 1 ? j0 : n - 1) : 0;
+  // scaling pass: 16 loads in flight per group (one memory latency per group,
+  // not per node), then the group's stores
+  col[0] = 0.0;
+  for (int jb = 1; jb <= n; jb += 16) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = jb + u <= last ? col[(size_t)(jb + u) * pp] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int j = jb + u;
+      if (j <= n) col[(size_t)j * pp] = j <= last ? (j == j0 ? 0.5 * h : h) * (v[u] * sc) : 0.0;
+    }
+  }
+}
+
 // out[q] = sum_b part[b * 2pp + q]: SWQ quantities per block, each summed in
 // 256 / SWQ slices of the blocks (enough blocks and loads in flight for the
 // few hundred partials per quantity)
@@ -2877,6 +2938,10 @@ void launch_zeta_part(hipStream_t s, int n, int pitch, int j0, const double2* tm
   hipLaunchKernelGGL(k_zeta_part, vec_grid(n), dim3(256), 0, s, n, pitch, j0, tm, f1, f2, u, chi, part);
 }
 int zeta_sweep_blocks(int top) { return ((top + SWR - 1) / SWR) * SWJ; }
+void launch_sweep_testfn(hipStream_t s, int n, int j0, double h, double Z1, int npairs, int pp, const double* kk,
+                         double* F) {
+  hipLaunchKernelGGL(k_sweep_testfn, dim3((2 * pp + 63) / 64), dim3(64), 0, s, n, j0, h, Z1, npairs, pp, kk, F);
+}
 void launch_zeta_sweep(hipStream_t s, int n, int pitch, int top, int pp, const double2* tm, const double* F1T,
                        const double* F2T, const double2* u, const double2* chi, double* part, double* out) {
   hipLaunchKernelGGL(k_zeta_sweep_part, dim3((top + SWR - 1) / SWR, SWJ), dim3(pp), 0, s, n, pitch, top, pp, tm,

@@ -152,6 +152,11 @@ void launch_zeta_part(hipStream_t s, int n, int pitch, int j0, const double2* tm
 // 1 .. top of the real region are summed.  part: zeta_sweep_blocks(top) x 2pp
 // doubles; out: 2pp doubles (re, im per pair).
 int zeta_sweep_blocks(int top);
+// The sweep's weighted test functions on the device: F is [2][n+1][pp]
+// (x1 side with momenta kk[0 .. npairs), x2 side with kk[npairs .. 2 npairs)),
+// zero for the padding pairs npairs .. pp - 1.  Needs 1 <= j0 and n >= 2.
+void launch_sweep_testfn(hipStream_t s, int n, int j0, double h, double Z1, int npairs, int pp, const double* kk,
+                         double* F);
 void launch_zeta_sweep(hipStream_t s, int n, int pitch, int top, int pp, const double2* tm, const double* F1T,
                        const double* F2T, const double2* u, const double2* chi, double* part, double* out);
 
