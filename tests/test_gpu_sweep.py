@@ -96,3 +96,23 @@ def test_sweep_rejects_bad_arguments():
     with pytest.raises(mgcccs.MGCError) as e:
         g.cross_section_sweep(ut, ct, [0.5, -0.1], [0.5, 0.5])
     assert e.value.status == mgcccs.MGC_EINVAL
+
+
+def test_sweep_device_test_functions_span_several_rounds():
+    """2049^2 (1537 real-region nodes): the device test functions stage the
+    potential term in more than one round; the sweep must agree with
+    single-pair calls, whose test functions the host computes in the same
+    operation order."""
+    c = Case(2048, 160.0, 0.1, 8, 8)
+    g = c.grid(fp32=False)
+    from paper_1412_1953_amd import mgcccs
+    u = c.u0()
+    chi = c.rand()
+    ut, ct = g.from_numpy(u), g.from_numpy(chi)
+    alphas = np.linspace(0.05, math.pi / 2 - 0.05, 65)
+    k1s, k2s = mgcccs.sharing_momenta(c.E, alphas)
+    zs, sig = g.cross_section_sweep(ut, ct, k1s, k2s)
+    for a in (0, 31, 64):
+        z1, s1 = g.cross_section(ut, ct, k1s[a], k2s[a])
+        assert abs(zs[a] - z1) < 1e-13 * abs(z1)
+        assert abs(sig[a] - s1) < 1e-12 * s1
