@@ -3,7 +3,8 @@
 Sec. 3.3: the double-ionisation amplitude (eq. double-ionization)
     zeta(k1,k2) = int phi_{k1}(x) phi_{k2}(y) (f - V12 u) dx dy
 with phi_k the regular solution of (-1/2 d^2/dx^2 + V1 - k^2/2) phi_k = 0
-(eq. testfunction) "normalised by 1/sqrt(k)", and
+(eq. testfunction), normalised as in eq. testfunction (Sec. 3.3) to
+asymptotic amplitude 1/sqrt(k), and
     sigma(k1,k2) = 8 pi^2 / k0^2 * |zeta|^2 / (k1 k2).
 
 Readings (the paper leaves them open for an ECS grid): the integral runs over
@@ -12,9 +13,10 @@ phi_k comes from the 3-point recurrence of eq. testfunction on the real nodes
 and is scaled so that its local amplitude at R0,
     a^2 = phi(R0)^2 + (phi'(R0)/p)^2,   p = sqrt(k^2 - 2 V1(R0)),
 equals 1/sqrt(p).  Physical cross-section values are parity unpinned (the
-paper prints none for this model); the pins are the Z1 = 0 closed form,
-linearity in u, the factorisation for a separable source and the exchange
-symmetry of the two coordinates.
+paper prints none for this model); the pins are the Z1 = 0 closed form, the
+Z1 > 0 shape against the regular Coulomb function F_0(-Z1/k, kx) (second
+order in h, amplitude 1/sqrt(k)), linearity in u, the factorisation for a
+separable source and the exchange symmetry of the two coordinates.
 """
 from __future__ import annotations
 

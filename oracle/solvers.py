@@ -1,13 +1,15 @@
 """Outer iterations around one MG-CCCS cycle (TEST INFRASTRUCTURE ONLY).
 
 * Stationary MG-CCCS: repeat {V-cycle; CCCS} (Sec. 6.1).
-* FGMRES(m) right-preconditioned by one MG-CCCS cycle started from zero
-  (Sec. 6, "only one MG-CCCS V-cycle is used to approximately solve the
-  preconditioning system"; Table 1), classical Gram-Schmidt with one
-  re-orthogonalisation, Givens rotations, true residual at every restart.
+* FGMRES(m) right-preconditioned by one MG-CCCS cycle from a zero guess per
+  preconditioner application (Sec. 6; Table 1), classical Gram-Schmidt with
+  one re-orthogonalisation, Givens rotations, true residual at every restart.
 * Iterative refinement: r = f - A u, s = sqrt(N)/||r||_2 (RMS scaling),
   e = k cycles on A e = s r from zero, u += e/s.  (Reading; the paper has no
-  mixed-precision loop.)
+  mixed-precision loop.)  Every cycle is affine with a fixed linear part, so
+  one refinement step with k inner cycles equals k stationary cycles from u,
+  whatever s is; the pins check that and the fixed point against a dense
+  direct solve.
 
 Preconditioning hierarchy.  The cycle may act on the complex-contour operator
 of Sec. 3.1 (interior rotated by ``pc_gamma``) on levels >= ``pc_first_level``

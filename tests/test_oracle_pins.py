@@ -217,6 +217,47 @@ def test_fgmres_fixed_point_on_the_129_grid_matches_sparse_lu():
     assert np.linalg.norm(r.u[1:n, 1:n].ravel() - x) / np.linalg.norm(x) < 1e-8
 
 
+# ---------------------------------------------------------------- IR -------
+IR_CASES = [(32, 10.0, -0.3, 3), (32, 10.0, 0.3, 3), (16, 8.0, 0.3, 2)]
+
+
+@pytest.mark.parametrize("n,L,E,M", IR_CASES)
+def test_iterative_refinement_converges_to_the_dense_direct_solution(n, L, E, M):
+    """Mixed-precision outer loop (reading; FP64 here): on grids where the
+    stationary MG-CCCS cycle contracts, refinement with two inner cycles per
+    step reaches the brute-force dense solution of A u = f."""
+    s = MGCCCS(n, L, 0.75 * L, math.pi / 6, 1.0, 1.0, 1.0, E, 3, M)
+    f = s.rhs()
+    x = np.linalg.solve(s.op.sparse().toarray(), f[1:n, 1:n].ravel())
+    r = s.solve_ir(initial_guess(n, 1), f, 1e-12, inner_cycles=2, max_it=80)
+    assert r.relres <= 1e-12 and r.vcycles == 2 * r.iters
+    assert np.linalg.norm(r.u[1:n, 1:n].ravel() - x) / np.linalg.norm(x) < 1e-11
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_refinement_step_equals_stationary_cycles(k):
+    """The cycle u -> u + B (f - A u) is affine with a fixed linear B, so one
+    refinement step (correction of k cycles on A e = s r from zero, added as
+    e / s) equals k stationary cycles from u for any scale s.  A planted
+    mistake, the correction added as e * s, does not."""
+    n, L, E, M = IR_CASES[1]
+    s = MGCCCS(n, L, 0.75 * L, math.pi / 6, 1.0, 1.0, 1.0, E, 3, M)
+    f = s.rhs()
+    u0 = initial_guess(n, 2)
+    ref = u0
+    for _ in range(k):
+        ref = s.cycle(ref, f)
+    got = s.solve_ir(u0, f, 0.0, inner_cycles=k, max_it=1).u
+    assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max()
+    r = s.op.residual(u0, f)
+    sc = (n - 1) / np.linalg.norm(r)
+    e = np.zeros_like(r)
+    for _ in range(k):
+        e = s.cycle(e, sc * r)
+    bad = u0 + e * sc
+    assert np.abs(bad - ref).max() > 1e-2 * np.abs(ref).max()
+
+
 # ---------------------------------------------------------------- P7 -------
 def test_separable_case_matches_fast_diagonalisation():
     """lambda = 0: A = H1 (x) I + I (x) H2 - E is separable, solved exactly by
@@ -305,6 +346,74 @@ def test_channel_potential_prefix_sum_identity():
     assert np.abs(V - cc.VA).max() < 1e-13 * np.abs(cc.VA).max()
 
 
+def _channel_identity_case():
+    """lambda != 0 and Z1 != Z2: the channel bases differ, the two-body
+    coupling V^A / V^B is present and not diagonal."""
+    g = Grid1D(64, 20.0, 15.0, math.pi / 6)
+    op = tp_operator(g, 1.0, 0.7, 1.3, 0.3)
+    cc = CCCS(op, 4, 3)
+    n = g.n
+    rng = np.random.default_rng(13)
+    rA = np.zeros((n + 1, 4), complex)
+    rB = np.zeros((n + 1, 3), complex)
+    rA[1:n] = rng.standard_normal((n - 1, 4)) + 1j * rng.standard_normal((n - 1, 4))
+    rB[1:n] = rng.standard_normal((n - 1, 3)) + 1j * rng.standard_normal((n - 1, 3))
+    return g, op, cc, rA, rB
+
+
+def _project_applied(g, op, cc, eA=None, eB=None):
+    """sum_j w_j phi_i(j) [A (sum_m eA_m phi_m)](k, j)  and
+    sum_k w_k varphi_l(k) [A (sum_p eB_p varphi_p)](k, j): the channel
+    equations of Sec. 4.2 follow from projecting the 2D operator applied to a
+    single-sided channel expansion onto the (bilinearly orthonormal) bound
+    states, since H1 phi_m = lambda_m phi_m."""
+    w = g.w
+    out = []
+    if eA is not None:
+        out.append(op.apply(eA @ cc.phi) @ (w[:, None] * cc.phi.T))
+    if eB is not None:
+        out.append(op.apply((eB @ cc.vphi).T).T @ (w[:, None] * cc.vphi.T))
+    return out
+
+
+def test_channel_systems_are_the_projected_2d_operator_with_coupling():
+    """Sec. 4.2 eqs. channel1/channel2 at lambda != 0, Z1 != Z2: the solution
+    e^A of the A system satisfies, for every channel i and node k,
+        sum_j w_j phi_i(x_j) [A (sum_m e^A_m phi_m)](y_k, x_j) = r^A_i(y_k),
+    and the mirrored identity holds for B with the x2 channels.  This ties the
+    block-tridiagonal systems (1D operator, eigenvalue shift, channel
+    potentials on and off the block diagonal) to the 2D operator they come
+    from, independently of how the systems are assembled."""
+    g, op, cc, rA, rB = _channel_identity_case()
+    n = g.n
+    eA = cc.sysA.solve(rA)
+    eB = cc.sysB.solve(rB)
+    pA, pB = _project_applied(g, op, cc, eA, eB)
+    assert np.abs(pA[1:n] - rA[1:n]).max() < 1e-11 * np.abs(rA).max()
+    assert np.abs(pB[1:n] - rB[1:n]).max() < 1e-11 * np.abs(rB).max()
+
+
+@pytest.mark.parametrize("mistake", ["drop_diagonal_coupling", "swap_one_body_potential",
+                                     "drop_off_diagonal_coupling"])
+def test_planted_channel_system_mistakes_break_the_projected_identity(mistake):
+    """Planted mistakes in a copy of the A system's ingredients (the oracle
+    itself is untouched): each must fail the identity above."""
+    from oracle.cccs import ChannelSystem
+    g, op, cc, rA, _ = _channel_identity_case()
+    n = g.n
+    VA, Vone = cc.VA.copy(), op.V2
+    if mistake == "drop_diagonal_coupling":
+        for i in range(VA.shape[1]):
+            VA[:, i, i] = 0
+    elif mistake == "drop_off_diagonal_coupling":
+        VA = np.einsum("kii->ki", VA)[:, :, None] * np.eye(VA.shape[1])[None]
+    else:
+        Vone = op.V1                   # the x1 potential in the x2 equation
+    bad = ChannelSystem(g, Vone, cc.lamA, VA, op.E)
+    (pA,) = _project_applied(g, op, cc, eA=bad.solve(rA))
+    assert np.abs(pA[1:n] - rA[1:n]).max() > 1e-3 * np.abs(rA).max()
+
+
 # ---------------------------------------------------------------- P9 / P15 -
 def test_symmetric_problem_has_a_symmetric_solution():
     n = 32
@@ -332,6 +441,41 @@ def test_rhs_structure():
     assert np.abs(np.diag(chi2)).max() > 0
 
 
+def _incoming_wave_profiles(n, E):
+    """With Z1 = Z2 = lambda = 1 the upper triangle k < j <= j0 of
+    sqrt(2) chi equals (1/z_j - 1/z_k) phi_1s(z_j) sin(k0 z_k): divided by the
+    potential factor it is the rank-one incoming wave.  Returns its x1 profile
+    (row k = 3), its x2 profile (column j = j0) and the grid."""
+    g = Grid1D(n, 40.0, 30.0, math.pi / 6)
+    chi = tp_rhs(g, 1.0, 1.0, 1.0, E) * math.sqrt(2)
+    z, j0 = g.z.real, g.j0
+    row = np.array([chi[3, j] / (1 / z[j] - 1 / z[3]) for j in range(4, j0 + 1)])
+    col = np.array([chi[k, j0] / (1 / z[j0] - 1 / z[k]) for k in range(1, j0)])
+    return g, row, col
+
+
+def test_incoming_wave_is_the_target_ground_state_times_a_free_wave():
+    """Sec. 3.1 Remark 3 / Sec. 5.1: the source is (V2 + V12) acting on the
+    incoming wave phi_1s(x1) sin(k0 x2).  Pinned against independent pieces:
+    its x1 profile is the lowest discrete eigenvector of H1 (the oracle's
+    eigensolver) and its x2 profile has discrete kinetic energy k0^2/2 =
+    E - (-Z1^2/2), the energy balance with the closed-form 1s energy; both at
+    second order in h."""
+    errs, kins = [], []
+    E = 0.4
+    for n in (256, 512, 1024):
+        g, row, col = _incoming_wave_profiles(n, E)
+        _, phi = bound_states(g, tp_one_body(g, 1.0), 1)
+        p = phi[0, 4:g.j0 + 1]
+        c = np.dot(row, p) / np.dot(p, p)
+        errs.append(np.abs(row - c * p).max() / np.abs(row).max())
+        q = -0.5 * (col[2:] - 2 * col[1:-1] + col[:-2]) / g.h ** 2
+        big = np.abs(col[1:-1]) > 0.3 * np.abs(col).max()
+        kins.append(np.median((q[big] / col[1:-1][big]).real) - (E + 0.5))
+    assert errs[2] < 5e-4 and 3.5 < errs[0] / errs[1] < 4.6 and 3.5 < errs[1] / errs[2] < 4.6, errs
+    assert abs(kins[2]) < 5e-4 and 3.5 < kins[0] / kins[1] < 4.6, kins
+
+
 # ---------------------------------------------------------------- P14 ------
 def test_free_test_function_is_a_normalised_discrete_sine():
     """Z1 = 0: phi_j = h sin(kappa j h)/sin(kappa h) with cos(kappa h) = 1 - (kh)^2/2,
@@ -346,6 +490,42 @@ def test_free_test_function_is_a_normalised_discrete_sine():
     amp2 = (h * math.sin(kap * R0) / math.sin(kap * h)) ** 2 + (math.cos(kap * R0) / k) ** 2
     ref = raw / math.sqrt(amp2 * k)
     assert np.abs(ph - ref).max() < 1e-12
+
+
+def _coulomb_shape_error(n, Z1, k):
+    """max |phi - c F_0| / max |F_0| at x = 1.25 .. 30 (nodes of every grid),
+    c the least-squares amplitude; F_0(eta, rho) is the regular Coulomb wave
+    function with eta = -Z1/k, rho = k x, the regular solution of
+    -1/2 u'' - Z1/x u - k^2/2 u = 0 with unit asymptotic amplitude."""
+    import mpmath
+    g = Grid1D(n, 40.0, 30.0, math.pi / 6)
+    ph = fn.test_function(g, Z1, k)
+    xs = 1.25 * np.arange(1, 25)
+    idx = np.rint(xs / g.h).astype(int)
+    F = np.array([float(mpmath.coulombf(0, -abs(Z1) / k, k * x)) for x in xs])
+    p = ph[idx]
+    c = float(np.dot(p, F) / np.dot(F, F))
+    return float(np.abs(p - c * F).max() / np.abs(F).max()), c
+
+
+@pytest.mark.parametrize("Z1,k", [(1.0, 0.5), (1.0, 1.0), (2.0, 0.7)])
+def test_coulomb_test_function_is_the_regular_coulomb_function(Z1, k):
+    """Sec. 3.3 eq. testfunction with the Coulomb term: the recurrence's
+    phi_k converges to F_0(-Z1/k, k x) at second order in h (error ratio 4 per
+    halving), and its amplitude tends to 1/sqrt(k) (the WKB normalisation at
+    R0 differs from the asymptotic one by O(Z1/(k^2 R0^2)))."""
+    e = [_coulomb_shape_error(n, Z1, k) for n in (256, 512, 1024)]
+    r1, r2 = e[0][0] / e[1][0], e[1][0] / e[2][0]
+    assert 3.8 < r1 < 4.2 and 3.8 < r2 < 4.2, (r1, r2)
+    assert e[2][0] < 3e-3
+    assert abs(e[2][1] * math.sqrt(k) - 1) < 3e-3, e[2][1]
+
+
+def test_planted_coulomb_sign_mistake_fails_the_shape_pin():
+    """Planted mistake: the potential term with the wrong sign (a repulsive
+    Coulomb field, obtained by passing -Z1) is far from F_0(-Z1/k, kx)."""
+    err, _ = _coulomb_shape_error(512, -1.0, 0.7)
+    assert err > 0.1
 
 
 def test_zeta_is_affine_in_u():
