@@ -699,6 +699,8 @@ mgc_status solve_ir(mgc_grid g, void* u, const void* f, const mgc_solve_opts* o,
   double rel = std::sqrt(rr) / fn;
   record(st, 0, rel);
   int it = 0, cyc = 0;
+  // sc[0] = s, (sc[2], sc[3]) = (1/s, 0): the complex coefficient at a
+  // 16-byte boundary (scal is 256-byte aligned) for k_update's double2 load
   double* sc = g->at<double>(g->scal) + 8;
   double* nr = g->at<double>(g->scal);
   const double Nn = (double)(n - 1) * (n - 1);
@@ -707,11 +709,11 @@ mgc_status solve_ir(mgc_grid g, void* u, const void* f, const mgc_solve_opts* o,
     if (o->inner == MGC_FP32) {
       launch_scale_copy<double, float>(g->stream, n, pitch, pitch, r, sc, g->ws + g->f32);
       for (int c = 0; c < o->inner_cycles; ++c) mgcccs_cycle<float>(g, g->ws + g->u32, g->ws + g->f32, c == 0);
-      launch_update<float>(g->stream, n, pitch, 0, g->ws + g->u32, 1, (const double2*)(sc + 1), (double2*)u);
+      launch_update<float>(g->stream, n, pitch, 0, g->ws + g->u32, 1, (const double2*)(sc + 2), (double2*)u);
     } else {
       launch_scale_copy<double, double>(g->stream, n, pitch, pitch, r, sc, g->ws + g->tw);
       for (int c = 0; c < o->inner_cycles; ++c) mgcccs_cycle<double>(g, g->ws + g->tz, g->ws + g->tw, c == 0);
-      launch_update<double>(g->stream, n, pitch, 0, g->ws + g->tz, 1, (const double2*)(sc + 1), (double2*)u);
+      launch_update<double>(g->stream, n, pitch, 0, g->ws + g->tz, 1, (const double2*)(sc + 2), (double2*)u);
     }
     cyc += o->inner_cycles;
     ++it;
@@ -1325,6 +1327,7 @@ mgc_status mgc_cross_section(mgc_grid g, const void* u, const void* chi, double 
   launch_zeta_part(g->stream, n, g->lv[0].pitch, j0, exact_level(g).tm, d1, d1 + (n + 1), (const double2*)u,
                    (const double2*)chi, part);
   launch_sum_partials(g->stream, launch_vec_blocks(n), 2, part, out);
+  HIPCHK(g, hipGetLastError());
   double hz[2];
   HIPCHK(g, hipMemcpyAsync(hz, out, sizeof(hz), hipMemcpyDeviceToHost, g->stream));
   HIPCHK(g, hipStreamSynchronize(g->stream));
@@ -1358,6 +1361,7 @@ mgc_status mgc_cross_section_sweep(mgc_grid g, const void* u, const void* chi, i
   double* out = g->at<double>(g->sweep_out);
   launch_zeta_sweep(g->stream, n, g->lv[0].pitch, top, pp, exact_level(g).tm, F1T, F1T + (size_t)(n + 1) * pp,
                     (const double2*)u, (const double2*)chi, g->at<double>(g->sweep_part), out);
+  HIPCHK(g, hipGetLastError());
   std::vector<double> hz((size_t)2 * pp);
   HIPCHK(g, hipMemcpyAsync(hz.data(), out, hz.size() * sizeof(double), hipMemcpyDeviceToHost, g->stream));
   HIPCHK(g, hipStreamSynchronize(g->stream));
@@ -1400,6 +1404,7 @@ mgc_status mgc_cross_section_grad(mgc_grid g, const void* u, const void* chi, do
   // zeta
   launch_zeta_part(g->stream, n, pitch, j0, tm, F, F + (n + 1), (const double2*)u, (const double2*)chi, part);
   launch_sum_partials(g->stream, launch_vec_blocks(n), 2, part, out);
+  HIPCHK(g, hipGetLastError());
   double hz[2];
   HIPCHK(g, hipMemcpyAsync(hz, out, sizeof(hz), hipMemcpyDeviceToHost, g->stream));
   // adjoint: A^T v = d zeta / du

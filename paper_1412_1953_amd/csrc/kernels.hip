@@ -2284,13 +2284,14 @@ __global__ void __launch_bounds__(256) k_gmres_solve(GmresState st, int m, int m
   }
 }
 
-// Iterative refinement scale: s = sqrt(N)/||r|| (RMS normalisation); sc[1] = 1/s.
+// Iterative refinement scale: s = sqrt(N)/||r|| (RMS normalisation) in sc[0];
+// the complex coefficient (1/s, 0) in sc[2..3], 16-byte aligned for double2 loads.
 __global__ void k_ir_scale(const double* nrm2, double Nn, double* sc) {
   double r = sqrt(nrm2[0]);
   double s = r > 0 ? sqrt(Nn) / r : 1.0;
   sc[0] = s;
-  sc[1] = 1.0 / s;
-  sc[2] = 0.0;
+  sc[2] = 1.0 / s;
+  sc[3] = 0.0;
 }
 __global__ void k_copy_scalar(const double* src, double* dst) { dst[0] = src[0]; }
 __global__ void k_fill_zero(size_t n16, double2* p) {

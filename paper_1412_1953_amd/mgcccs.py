@@ -183,12 +183,40 @@ class Grid:
         out.copy_(self.torch.from_numpy(a).to(out.dtype))
         return out
 
-    @staticmethod
-    def _ptr(x):
+    def _ptr(self, x, prec=FP64):
+        """Device pointer of a level-0 field after checking that the kernels'
+        indexing (element (k, j) at k * pitch + j, k, j <= n) stays inside it:
+        a tensor on this handle's device, complex128 (FP64) or complex64
+        (FP32), shape (n+1, n+1), strides (pitch, 1) and storage for
+        (n+1) * pitch elements from its first element.  MGCError(MGC_EINVAL)
+        otherwise; nothing reaches the library."""
+        t = self.torch
+        want = t.complex128 if prec == FP64 else t.complex64
+        bad = None
+        if not isinstance(x, t.Tensor):
+            bad = f"expected a torch tensor, got {type(x).__name__}"
+        elif x.device != self.device:
+            bad = f"field on {x.device}, handle on {self.device}"
+        elif x.dtype != want:
+            bad = f"field dtype {x.dtype}, this call needs {want}"
+        elif tuple(x.shape) != (self.n + 1, self.n + 1):
+            bad = f"field shape {tuple(x.shape)}, expected {(self.n + 1, self.n + 1)}"
+        elif tuple(x.stride()) != (self.pitch, 1):
+            bad = f"field strides {tuple(x.stride())}, expected {(self.pitch, 1)} (use Grid.field())"
+        else:
+            avail = x.untyped_storage().nbytes() - x.storage_offset() * x.element_size()
+            if avail < (self.n + 1) * self.pitch * x.element_size():
+                bad = f"field storage holds {avail} bytes, needs {(self.n + 1) * self.pitch * x.element_size()}"
+        if bad is not None:
+            raise MGCError(MGC_EINVAL, bad)
         return ctypes.c_void_p(x.data_ptr())
 
     def _prec(self, x):
-        return FP32 if x.dtype == self.torch.complex64 else FP64
+        """Precision of the call from the first field's dtype (the other
+        fields must match it: _ptr checks them against it)."""
+        if getattr(x, "dtype", None) == self.torch.complex64:
+            return FP32
+        return FP64
 
     # ---- entry points (same names as the C ABI) -------------------------------
     def set_potential(self, Z1, Z2, lam):
@@ -203,15 +231,18 @@ class Grid:
 
     def residual(self, u, f, r, want_relres=True):
         rel = ctypes.c_double()
-        _check(self.lib.mgc_residual(self.h, self._ptr(u), self._ptr(f), self._ptr(r),
-                                     ctypes.byref(rel) if want_relres else None, self._prec(u)))
+        p = self._prec(u)
+        _check(self.lib.mgc_residual(self.h, self._ptr(u, p), self._ptr(f, p), self._ptr(r, p),
+                                     ctypes.byref(rel) if want_relres else None, p))
         return rel.value if want_relres else None
 
     def vcycle(self, u, f):
-        _check(self.lib.mgc_vcycle(self.h, self._ptr(u), self._ptr(f), self._prec(u)))
+        p = self._prec(u)
+        _check(self.lib.mgc_vcycle(self.h, self._ptr(u, p), self._ptr(f, p), p))
 
     def cccs(self, u, f):
-        _check(self.lib.mgc_cccs(self.h, self._ptr(u), self._ptr(f), self._prec(u)))
+        p = self._prec(u)
+        _check(self.lib.mgc_cccs(self.h, self._ptr(u, p), self._ptr(f, p), p))
 
     def _solve(self, fn, u, f, outer, inner, restart, max_it, inner_cycles, tol, hist_cap):
         opts = SolveOpts(outer, inner, restart, max_it, inner_cycles, tol)
@@ -325,8 +356,8 @@ class Batch:
         for i in range(nb):
             st[i] = Stats(0, 0, 0.0, ctypes.cast(hists[i], ctypes.POINTER(ctypes.c_double)), hist_cap, 0,
                           0.0, 0.0)
-        up = (ctypes.c_void_p * nb)(*[x.data_ptr() for x in us])
-        fp = (ctypes.c_void_p * nb)(*[x.data_ptr() for x in fs])
+        up = (ctypes.c_void_p * nb)(*[g._ptr(x).value for g, x in zip(self.grids, us)])
+        fp = (ctypes.c_void_p * nb)(*[g._ptr(x).value for g, x in zip(self.grids, fs)])
         _check(self.lib.mgc_batch_solve(self.h, up, fp, ctypes.byref(opts), st),
                allow=(MGC_ENOCONV, MGC_ENUMERIC))
         out = []

@@ -110,9 +110,9 @@ def test_mixed_precision_2049_against_fp64():
     print(f"2049^2 E={w.E}: FP64 {out[mgcccs.FP64][1]} it (relres {out[mgcccs.FP64][2]:.3e}), "
           f"mixed {out[mgcccs.FP32][1]} it (relres {out[mgcccs.FP32][2]:.3e}), "
           f"relative 2-norm difference of the solutions {diff:.3e}")
-    # both meet the residual tolerance; their difference is bounded by the
-    # conditioning of the ECS operator times the tolerance
-    assert diff < 1e-6
+    # both meet the residual tolerance; their difference (4.1e-11 measured)
+    # stays within a few times the tolerance
+    assert diff < 5e-10
 
 
 # FGMRES(10) in FP64 levels off near a relative residual of 1e-12 on this

@@ -36,6 +36,30 @@ def test_gradient_matches_oracle_adjoint(p):
     assert np.linalg.norm(to_np(v) - vo) / np.linalg.norm(vo) < 1e-9
 
 
+def test_gradient_513_matches_oracle_adjoint():
+    """The differentiation workload's spacing (h = 0.078125, ECS beyond
+    0.75 L at pi/6, 8 channels, E = 0.5, Z1 = Z2 = lambda = 1) on [0,40]^2:
+    the library's adjoint gradient against the oracle's adjoint with sparse
+    direct solves, to 1e-6 relative per component."""
+    from paper_1412_1953_amd import mgcccs
+    c = Case(512, 40.0, 0.5, 6, 8, pc_gamma=GAM)
+    g = c.grid()
+    chi = g.build_rhs_tp(g.field())
+    u = g.from_numpy(c.u0())
+    res = g.solve(u, chi, outer=mgcccs.FGMRES, restart=10, max_it=20000, tol=1e-12)
+    assert res.status == mgcccs.MGC_OK, (res.iters, res.relres)
+    k = math.sqrt(c.E)
+    v = g.field()
+    ds, zeta, sig, ares = g.cross_section_grad(u, chi, k, k, v, tol=1e-12, max_it=20000)
+    assert ares.status == mgcccs.MGC_OK, (ares.iters, ares.relres)
+    go = Grid1D(c.n, c.L, c.R0, c.theta)
+    ref, info = fn.grad_adjoint(go, (c.Z1, c.Z2, c.lam), c.E, k, k)
+    print(f"513^2: forward {res.iters} it, adjoint {ares.iters} it; sigma {sig:.9e} vs {info['J']:.9e}; "
+          f"gradient {np.array(ds)} vs {ref}")
+    assert abs(sig - info["J"]) < 1e-8 * info["J"]
+    assert np.all(np.abs(np.array(ds) - ref) <= 1e-6 * np.abs(ref)), (ds, ref)
+
+
 def test_autograd_function_matches_central_differences():
     import torch
     from paper_1412_1953_amd import autograd

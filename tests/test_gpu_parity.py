@@ -163,6 +163,79 @@ def test_fgmres_solution_matches_direct_solve(c, fp32):
     assert rel_residual(o.op, to_np(ut), chi) < 2e-12
 
 
+# Iterative refinement (MGC_IR): grids on which the stationary cycle contracts
+IR_CASES = [Case(32, 10.0, 0.3, 3, 3), Case(64, 16.0, -0.2, 4, 4)]
+
+
+@pytest.mark.parametrize("c", IR_CASES, ids=lambda c: f"n{c.n}")
+@pytest.mark.parametrize("fp32", [False, True], ids=["fp64", "fp32"])
+def test_ir_trajectory(c, fp32):
+    """Four refinement steps of two MG-CCCS cycles each from the same seed:
+    the oracle's refinement iterate (FP64 inner cycles) to 1e-10 in FP64; with
+    complex-FP32 inner cycles the corrections carry FP32 rounding, stated
+    against the FP64 oracle (1e-5)."""
+    from paper_1412_1953_amd import mgcccs
+    g = c.grid()
+    o = c.oracle()
+    chi = tp_rhs(o.g, c.Z1, c.Z2, c.lam, c.E)
+    u = c.u0()
+    ut, ft = g.from_numpy(u), g.from_numpy(chi)
+    res = g.solve(ut, ft, outer=mgcccs.IR, inner=mgcccs.FP32 if fp32 else mgcccs.FP64,
+                  max_it=4, inner_cycles=2, tol=1e-300)
+    assert res.status == mgcccs.MGC_ENOCONV and res.iters == 4 and res.vcycles == 8
+    ref = o.solve_ir(u, chi, 0.0, inner_cycles=2, max_it=4)
+    err = rel2(to_np(ut), ref.u)
+    assert err < (1e-5 if fp32 else 1e-10), err
+    hist = np.array(res.history)
+    assert np.all(np.abs(hist - np.array(ref.history)) <= (1e-3 if fp32 else 1e-8) * np.array(ref.history))
+
+
+@pytest.mark.parametrize("c", IR_CASES, ids=lambda c: f"n{c.n}")
+@pytest.mark.parametrize("fp32", [False, True], ids=["fp64", "fp32"])
+def test_ir_solution_matches_direct_solve(c, fp32):
+    """Refinement to 1e-12 with FP64 or complex-FP32 inner cycles reaches the
+    sparse direct solution (the FP64 outer residual removes the FP32 error)."""
+    from paper_1412_1953_amd import mgcccs
+    g = c.grid()
+    o = c.oracle()
+    n = c.n
+    chi = tp_rhs(o.g, c.Z1, c.Z2, c.lam, c.E)
+    ut, ft = g.from_numpy(c.u0()), g.from_numpy(chi)
+    res = g.solve(ut, ft, outer=mgcccs.IR, inner=mgcccs.FP32 if fp32 else mgcccs.FP64,
+                  max_it=200, inner_cycles=2, tol=1e-12)
+    assert res.status == mgcccs.MGC_OK and res.relres <= 1e-12, res
+    x = spla.spsolve(o.op.sparse(), chi[1:n, 1:n].ravel()).reshape(n - 1, n - 1)
+    assert rel2(to_np(ut)[1:n, 1:n], x) < 1e-10
+    assert rel_residual(o.op, to_np(ut), chi) < 2e-12
+
+
+def test_small_workload_129_as_specified():
+    """The 129^2 workload exactly as specified (domain [0,40]^2, ECS beyond 30
+    at pi/6, E = 0.1, 5 levels, 4 channels, seed 0, tol 1e-8), FGMRES(10) with
+    the FP64 MG-CCCS cycle: the oracle's FGMRES reaches the tolerance after the
+    same number of iterations, the two iterates agree to 1e-10, and both are
+    the sparse direct solution to within the conditioning times 1e-8."""
+    from paper_1412_1953_amd import mgcccs
+    from paper_1412_1953_amd.workloads import SMALL_129 as w
+    c = Case(w.n, w.L, w.E, w.levels, w.M, pc_gamma=GAM, seed=w.seed)
+    g = c.grid()
+    o = c.oracle()
+    n = c.n
+    chi = tp_rhs(o.g, c.Z1, c.Z2, c.lam, c.E)
+    u = c.u0()
+    ut, ft = g.from_numpy(u), g.from_numpy(chi)
+    res = g.solve(ut, ft, outer=mgcccs.FGMRES, restart=10, max_it=2000, tol=w.tol)
+    assert res.status == mgcccs.MGC_OK and res.relres <= w.tol, res
+    ref = o.solve_fgmres(u, chi, w.tol, restart=10, max_it=2000)
+    assert ref.relres <= w.tol and ref.iters == res.iters, (ref.iters, res.iters)
+    err = rel2(to_np(ut), ref.u)
+    assert err < 1e-10, err
+    x = spla.splu(o.op.sparse()).solve(chi[1:n, 1:n].ravel()).reshape(n - 1, n - 1)
+    print(f"129^2 workload: {res.iters} iterations, relres {res.relres:.3e}, GPU vs oracle {err:.2e}, "
+          f"GPU vs direct {rel2(to_np(ut)[1:n, 1:n], x):.2e}")
+    assert rel2(to_np(ut)[1:n, 1:n], x) < 1e-5
+
+
 def test_coarsest_only_grid_is_a_direct_solve():
     c = Case(8, 4.0, 0.2, 1, 1)
     g = c.grid()
@@ -213,6 +286,38 @@ def test_error_paths():
     g.set_energy(0.3)
     with pytest.raises(mgcccs.MGCError) as e:
         g.solve(u, f, outer=mgcccs.STATIONARY, max_it=3, tol=1e-8, inner=mgcccs.FP32)
+    assert e.value.status == mgcccs.MGC_EINVAL
+
+
+def test_binding_rejects_fields_the_kernels_would_overrun():
+    """Every field is checked before the call: a contiguous (n+1, n+1) tensor
+    (the kernels use a row pitch of round16(n+1)), the wrong dtype for the
+    call's precision, a mismatched second field, another shape, a view that
+    does not reach the end of the buffer."""
+    import torch
+    from paper_1412_1953_amd import mgcccs
+    c = Case(32, 10.0, 0.3, 3, 2)
+    g = c.grid()
+    n = c.n
+    good = g.field()
+    chi = g.build_rhs_tp(g.field())
+    bad = [torch.zeros((n + 1, n + 1), dtype=torch.complex128, device=g.device),
+           g.field(fp32=True),
+           g.field()[:n, :n],
+           torch.zeros(((n + 1) * g.pitch,), dtype=torch.complex128, device=g.device)[1:].as_strided(
+               (n + 1, n + 1), (g.pitch, 1))]
+    for b in bad:
+        for call in (lambda: g.vcycle(good, b) if b.dtype == good.dtype else g.cross_section(b, chi, 0.5, 0.5),
+                     lambda: g.solve(b, chi, max_it=1),
+                     lambda: g.cross_section(good, b, 0.5, 0.5)):
+            with pytest.raises(mgcccs.MGCError) as e:
+                call()
+            assert e.value.status == mgcccs.MGC_EINVAL
+    with pytest.raises(mgcccs.MGCError) as e:                   # FP32 u with an FP64 f
+        g.residual(g.field(fp32=True), chi, g.field(fp32=True))
+    assert e.value.status == mgcccs.MGC_EINVAL
+    with pytest.raises(mgcccs.MGCError) as e:
+        g.vcycle(good, chi.cpu())
     assert e.value.status == mgcccs.MGC_EINVAL
 
 
