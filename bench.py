@@ -8,11 +8,20 @@ complex-normal initial guess to a relative residual of 1e-10.  Setup
 initial guess and workspace are resident in HBM when it starts.
 
 value = solved unknowns per second = 3 * 1023^2 / (seconds per step).
-The same step with the complex-FP32 preconditioner inside the FP64 FGMRES is
-reported as "mixed", and the same FP64 solves run together through the batch
-entry point as "batched".  "roofline" covers the dominant kernel, timed with HIP
-events on the library's stream inside the timed steps; "cpu_baseline" is the
-FP64 CPU oracle on a bounded sample of the same workload.
+
+Further legs of the same JSON line:
+  mixed          the same step with the complex-FP32 MG-CCCS cycle inside the
+                 FP64 FGMRES;
+  batched        the step's solves run together through the batch entry point,
+                 FP64 and FP32 cycles;
+  c2             the 2049^2 workload (E = 0.1): one FP64 and one mixed solve;
+  hbm_4097       a 4097^2 grid (every FP64 field larger than the on-die cache):
+                 the finest-level streaming kernels timed with HIP events,
+                 algorithmic bytes / time against the 8 TB/s HBM peak;
+  kernels        the same per-kernel figures on the timed 1025^2 workload;
+  roofline       the dominant kernel, timed with HIP events on the library's
+                 stream inside the timed steps;
+  cpu_baseline   the FP64 CPU oracle on a bounded sample of the step.
 """
 from __future__ import annotations
 
@@ -26,14 +35,16 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PC_GAMMA = math.radians(5.0)
 RESTART = 10
 HBM_PEAK_GBS = 8000.0                  # MI355X HBM3E, published
 # kernel classes of the library's event timer, by short name
-KCLASS = {"apply_dot": 1, "axpy": 2, "s1": 3, "s2": 4, "cccs_project": 5, "cccs_chain": 6}
+KCLASS = {"apply_dot": 1, "axpy": 2, "s1": 3, "s2": 4, "cccs_project": 5, "cccs_chain": 6,
+          "s1_fine": 7, "s2_fine": 8, "cccs_expand": 9}
 # the kernel whose roofline the line reports: the largest share of the step's
-# kernel time in the committed rocprofv3 summary
-ROOFLINE_KERNEL = "s1"
+# kernel time among single kernels in the committed rocprofv3 summary
+ROOFLINE_KERNEL = "apply_dot"
+# per-kernel figures reported beside it (the finest-level streaming passes)
+PROBE_KERNELS = ["s1_fine", "s2_fine", "cccs_project", "cccs_expand", "apply_dot", "axpy"]
 
 
 def parse():
@@ -44,20 +55,26 @@ def parse():
     p.add_argument("--max-it", type=int, default=20000)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-mixed", action="store_true")
-    p.add_argument("--no-batch", action="store_true", help="skip the batched leg")
+    p.add_argument("--no-batch", action="store_true", help="skip the batched legs")
     p.add_argument("--no-sweep", action="store_true", help="skip the cross-section sweep leg")
+    p.add_argument("--no-c2", action="store_true", help="skip the 2049^2 leg")
+    p.add_argument("--no-hbm", action="store_true", help="skip the 4097^2 bandwidth leg")
+    p.add_argument("--no-kernels", action="store_true", help="skip the per-kernel 1025^2 figures")
+    p.add_argument("--only-hbm", action="store_true", help="only the 4097^2 leg (profiling runs)")
     p.add_argument("--energies", type=str, default="0.05,0.5,2.0",
                    help="subset of the workload energies (profiling runs)")
     p.add_argument("--roofline-kernel", type=str, default=ROOFLINE_KERNEL, choices=sorted(KCLASS))
     p.add_argument("--copy-probe", action="store_true",
                    help="also run a plain device copy of known size (counter calibration)")
+    p.add_argument("--cpu-iters", type=int, default=20,
+                   help="oracle FGMRES iterations timed per energy for the CPU baseline")
     return p.parse_args()
 
 
-def make_problem(w, torch):
+def make_problem(w, torch, fp32=True):
     from paper_1412_1953_amd import mgcccs
     from paper_1412_1953_amd.workloads import initial_guess
-    g = mgcccs.Grid.from_workload(w, pc_gamma=PC_GAMMA, max_restart=RESTART, fp32=True)
+    g = mgcccs.Grid.from_workload(w, max_restart=RESTART, fp32=fp32)
     g.set_potential(w.Z1, w.Z2, w.lam)
     g.set_energy(w.E)
     chi = g.build_rhs_tp(g.field())
@@ -66,18 +83,17 @@ def make_problem(w, torch):
     return g, chi, u0, u
 
 
-def run_step(problems, inner, torch, max_it):
+def run_step(problems, inner, torch, max_it, tol=1e-10):
     from paper_1412_1953_amd import mgcccs
     out = []
     for g, chi, u0, u in problems:
         u.copy_(u0)
-        r = g.solve(u, chi, outer=mgcccs.FGMRES, inner=inner, restart=RESTART, max_it=max_it,
-                    tol=1e-10)
+        r = g.solve(u, chi, outer=mgcccs.FGMRES, inner=inner, restart=RESTART, max_it=max_it, tol=tol)
         out.append(r)
     return out
 
 
-def time_steps(problems, inner, torch, steps, warmup, max_it, kclass=0):
+def time_steps(problems, inner, torch, steps, warmup, max_it, kclass=0, tol=1e-10):
     """Seconds per step; with kclass, the library's HIP-event timer brackets
     every launch of that kernel inside the timed steps (on its own stream).
     The timer is selected before the warmup, so that the restart graphs with
@@ -85,14 +101,14 @@ def time_steps(problems, inner, torch, steps, warmup, max_it, kclass=0):
     for g, *_ in problems:
         g.set_kernel_timer(kclass)
     for _ in range(warmup):
-        run_step(problems, inner, torch, max_it)
+        run_step(problems, inner, torch, max_it, tol)
     torch.cuda.synchronize()
     for g, *_ in problems:
         g.read_kernel_timer()                      # drop the warmup's figures
     t0 = time.perf_counter()
     res = []
     for _ in range(steps):
-        res = run_step(problems, inner, torch, max_it)
+        res = run_step(problems, inner, torch, max_it, tol)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     ms = launches = nbytes = floor = 0
@@ -101,6 +117,29 @@ def time_steps(problems, inner, torch, steps, warmup, max_it, kclass=0):
         ms, launches, nbytes, floor = ms + a, launches + b, nbytes + c, floor + d
         g.set_kernel_timer(0)
     return dt, res, (ms, launches, nbytes, floor)
+
+
+def kernel_figure(timing):
+    """GB/s of one kernel class from the timer's (ms, launches, bytes, floor):
+    event brackets minus the bracket of an empty launch recorded before each."""
+    ms, launches, nbytes, floor = timing
+    if launches <= 0:
+        return None
+    avg_s = (ms - floor) * 1e-3 / launches
+    achieved = nbytes / launches / avg_s / 1e9
+    return {"achieved_gbs": achieved, "frac_hbm": achieved / HBM_PEAK_GBS, "avg_us": avg_s * 1e6,
+            "avg_us_raw_events": ms * 1e3 / launches, "event_floor_us_per_launch": floor * 1e3 / launches,
+            "bytes_per_launch": nbytes / launches, "launches": launches}
+
+
+def per_kernel(problems, inner, torch, max_it, kernels):
+    """Per-kernel timer figures over one more run of the solves (outside the
+    timed steps), one class per run."""
+    out = {}
+    for k in kernels:
+        _, _, t = time_steps(problems, inner, torch, 1, 0, max_it, KCLASS[k])
+        out[k] = kernel_figure(t)
+    return out
 
 
 def time_batch(problems, inner, torch, steps, warmup, max_it):
@@ -131,8 +170,8 @@ def time_batch(problems, inner, torch, steps, warmup, max_it):
 def time_sweep(problem, E, torch, calls=20, npairs=256):
     """Wall-clock milliseconds per energy-sharing sweep of the ionisation
     amplitude at excess energy E (npairs momentum pairs in one
-    mgc_cross_section_sweep call, host test functions and the synchronising
-    read-back included) on the step's converged solution."""
+    mgc_cross_section_sweep call, the synchronising read-back included) on the
+    step's converged solution."""
     from paper_1412_1953_amd import mgcccs
     g, chi, _, u = problem
     alphas = [0.01 + (math.pi / 2 - 0.02) * a / (npairs - 1) for a in range(npairs)]
@@ -145,6 +184,45 @@ def time_sweep(problem, E, torch, calls=20, npairs=256):
     dt = (time.perf_counter() - t0) / calls
     return {"pairs": npairs, "excess_energy": E, "ms_per_call": dt * 1e3,
             "zeta_max": max(abs(z) for z in zs)}
+
+
+def c2_leg(torch, max_it):
+    """The 2049^2 workload: one FP64 and one mixed (FP32 cycle) solve, each
+    timed once after one untimed solve."""
+    from paper_1412_1953_amd import mgcccs
+    from paper_1412_1953_amd.workloads import TP2049 as w
+    prob = make_problem(w, torch)
+    out = {"workload": w.name, "n": w.n, "E": w.E, "tol": w.tol}
+    for name, inner in (("fp64", mgcccs.FP64), ("mixed", mgcccs.FP32)):
+        dt, res, _ = time_steps([prob], inner, torch, 1, 1, max_it)
+        r = res[0]
+        out[name] = {"value": w.unknowns / dt, "ms": dt * 1e3, "iters": r.iters, "relres": r.relres,
+                     "status": r.status}
+    out["speedup_mixed_vs_fp64"] = out["mixed"]["value"] / out["fp64"]["value"]
+    del prob
+    torch.cuda.empty_cache()
+    return out
+
+
+def hbm_leg(torch, kernels, iters=20):
+    """4097^2 probe: every FP64 field (270 MB) exceeds the 256 MB on-die cache,
+    so the finest-level passes stream from HBM.  Each kernel class is timed
+    over a short FGMRES(10) run of `iters` iterations (two restart cycles)."""
+    from paper_1412_1953_amd import mgcccs
+    from paper_1412_1953_amd.workloads import TP4097 as w
+    t0 = time.perf_counter()
+    prob = make_problem(w, torch, fp32=False)
+    setup_s = time.perf_counter() - t0
+    out = {"workload": w.name, "n": w.n, "field_bytes": (w.n + 1) * prob[0].pitch * 16,
+           "iterations_per_run": iters, "setup_s": setup_s}
+    figs = {}
+    for k in kernels:
+        _, res, t = time_steps([prob], mgcccs.FP64, torch, 1, 1, iters, KCLASS[k], tol=1e-300)
+        figs[k] = kernel_figure(t)
+    out["kernels"] = figs
+    del prob
+    torch.cuda.empty_cache()
+    return out
 
 
 def traffic_from_profile(kernel):
@@ -178,29 +256,57 @@ def copy_probe(torch):
     torch.cuda.synchronize()
 
 
-def cpu_baseline(w):
-    """The FP64 CPU oracle on a bounded sample of the workload: the complete
-    solve of its first energy (same grid, right-hand side, initial guess,
-    FGMRES(10) with the MG-CCCS preconditioner, tolerance 1e-10) on one
-    thread; setup (bound states, factorisations) excluded as on the GPU."""
+def host_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wls, iters_needed, sample_iters):
+    """The FP64 CPU oracle on a bounded sample of the step: for each of the
+    step's energies, `sample_iters` FGMRES(10) iterations of the oracle (same
+    grid, right-hand side, initial guess and preconditioner) are timed; the
+    solve time is that rate times the iterations the solve needs (the GPU
+    solve's count: the two follow the same iteration), setup excluded as on
+    the GPU.  Run on one thread and on every core of the process's affinity
+    mask."""
+    from threadpoolctl import threadpool_limits
+
     from oracle.solvers import MGCCCS
     from paper_1412_1953_amd.workloads import initial_guess
-    try:
-        from threadpoolctl import threadpool_limits
-        limiter = threadpool_limits(limits=1)
-    except Exception:  # pragma: no cover
-        limiter = None
-    o = MGCCCS.from_workload(w, pc_gamma=PC_GAMMA)
-    f = o.rhs()
-    u0 = initial_guess(w.n, w.seed)
-    t0 = time.perf_counter()
-    r = o.solve_fgmres(u0, f, w.tol, restart=RESTART, max_it=20000)
-    dt = time.perf_counter() - t0
-    if limiter is not None:
-        limiter.unregister()
-    return {"value": w.unknowns / dt, "unit": "solved unknowns/s", "cores": 1, "kind": "oracle",
-            "sample": f"complete E={w.E} solve of the 1025^2 workload, {r.iters} FGMRES({RESTART}) "
-                      f"iterations to relres {r.relres:.2e} in {dt:.1f} s on one host thread"}
+    solvers = []
+    for w in wls:
+        o = MGCCCS.from_workload(w)
+        solvers.append((w, o, o.rhs(), initial_guess(w.n, w.seed)))
+    ncores = len(os.sched_getaffinity(0))
+    runs = {}
+    for threads in (1, ncores):
+        with threadpool_limits(limits=threads):
+            total = 0.0
+            per = []
+            for (w, o, f, u0), need in zip(solvers, iters_needed):
+                t0 = time.perf_counter()
+                r = o.solve_fgmres(u0, f, 0.0, restart=RESTART, max_it=sample_iters)
+                dt = time.perf_counter() - t0
+                total += dt / r.iters * need
+                per.append(dt / r.iters)
+            runs[threads] = (total, per)
+    unknowns = sum(w.unknowns for w in wls)
+    t1, per1 = runs[1]
+    tn, pern = runs[ncores]
+    return {"value": unknowns / t1, "unit": "solved unknowns/s", "cores": 1, "kind": "oracle",
+            "sample": (f"{sample_iters} FGMRES({RESTART}) iterations of the oracle for each energy "
+                       f"{[w.E for w in wls]} of the 1025^2 workload, timed on one host thread "
+                       f"({', '.join(f'{1e3 * p:.0f}' for p in per1)} ms per iteration) and scaled to "
+                       f"the {iters_needed} iterations the solves need to 1e-10; setup excluded"),
+            "all_cores": {"value": unknowns / tn, "threads_allowed": ncores,
+                          "ms_per_iteration": [1e3 * p for p in pern]},
+            "host": host_model()}
 
 
 def main():
@@ -214,15 +320,18 @@ def main():
     from paper_1412_1953_amd.workloads import TP1025
     mgcccs.load_library()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if a.copy_probe:
+        copy_probe(torch)
+    if a.only_hbm:
+        print(json.dumps({"hbm_4097": hbm_leg(torch, PROBE_KERNELS)}), flush=True)
+        return
     wls = [TP1025[float(E)] for E in a.energies.split(",")]
     problems = [make_problem(w, torch) for w in wls]
     unknowns = sum(w.unknowns for w in wls)
+    w0 = wls[0]
 
-    if a.copy_probe:
-        copy_probe(torch)
     kclass = KCLASS[a.roofline_kernel]
-    dt64, r64, (kms, kl, kb, kfloor) = time_steps(problems, mgcccs.FP64, torch, a.steps, a.warmup,
-                                                  a.max_it, kclass)
+    dt64, r64, kt = time_steps(problems, mgcccs.FP64, torch, a.steps, a.warmup, a.max_it, kclass)
     line = {
         "metric": "solved unknowns/s to 1e-10 rel. residual, mixed vs FP64 MG-CCCS; HBM GB/s",
         "value": unknowns / dt64,
@@ -234,38 +343,47 @@ def main():
         "config": {"workload": "tp1025_fp64_E0.05_0.5_2.0", "n": 1024, "L": 80.0, "R0": 60.0,
                    "theta": "pi/6", "levels": 7, "channels": 8, "tol": 1e-10,
                    "outer": f"FGMRES({RESTART})", "preconditioner": "MG-CCCS V(1,1)",
-                   "pc_gamma_deg": 5.0, "energies": [w.E for w in wls]},
+                   "pc_gamma_deg": round(math.degrees(w0.pc_gamma), 6),
+                   "pc_first_level": w0.pc_first_level, "energies": [w.E for w in wls]},
         "fp64": {"iters": [r.iters for r in r64], "relres": [r.relres for r in r64],
                  "status": [r.status for r in r64],
                  "vcycles_per_s": sum(r.vcycles for r in r64) / dt64},
     }
-    if kl > 0:
-        # event brackets minus the bracket of an empty launch recorded before each
-        avg_s = (kms - kfloor) * 1e-3 / kl
-        achieved = kb / kl / avg_s / 1e9
-        traffic = traffic_from_profile(a.roofline_kernel)
-        line["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                            "kernel": a.roofline_kernel, "launches": kl,
-                            "avg_us": avg_s * 1e6, "avg_us_raw_events": kms * 1e3 / kl,
-                            "event_floor_us_per_launch": kfloor * 1e3 / kl,
-                            "bytes_per_launch": kb / kl}
+    fig = kernel_figure(kt)
+    if fig is not None:
+        line["roofline"] = {"bound": "hbm", "achieved": fig["achieved_gbs"], "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": fig["achieved_gbs"] / HBM_PEAK_GBS,
+                            "traffic": traffic_from_profile(a.roofline_kernel),
+                            "kernel": a.roofline_kernel, "launches": fig["launches"],
+                            "avg_us": fig["avg_us"], "avg_us_raw_events": fig["avg_us_raw_events"],
+                            "event_floor_us_per_launch": fig["event_floor_us_per_launch"],
+                            "bytes_per_launch": fig["bytes_per_launch"]}
     if not a.no_mixed:
         dt32, r32, _ = time_steps(problems, mgcccs.FP32, torch, a.steps, a.warmup, a.max_it)
         line["mixed"] = {"value": unknowns / dt32, "ms_per_step": dt32 * 1e3,
                          "iters": [r.iters for r in r32], "relres": [r.relres for r in r32],
                          "status": [r.status for r in r32],
                          "speedup_vs_fp64": dt64 / dt32}
-    if not a.no_sweep:
-        line["sweep"] = time_sweep(problems[0], wls[0].E, torch)
     if not a.no_batch:
-        dtb, rb = time_batch(problems, mgcccs.FP64, torch, a.steps, a.warmup, a.max_it)
-        line["batched"] = {"value": unknowns / dtb, "ms_per_step": dtb * 1e3,
-                           "iters": [r.iters for r in rb], "relres": [r.relres for r in rb],
-                           "status": [r.status for r in rb],
-                           "speedup_vs_fp64": dt64 / dtb}
+        for name, inner in (("batched", mgcccs.FP64), ("batched_mixed", mgcccs.FP32)):
+            dtb, rb = time_batch(problems, inner, torch, a.steps, a.warmup, a.max_it)
+            line[name] = {"value": unknowns / dtb, "ms_per_step": dtb * 1e3,
+                          "iters": [r.iters for r in rb], "relres": [r.relres for r in rb],
+                          "status": [r.status for r in rb],
+                          "speedup_vs_fp64": dt64 / dtb}
+    if not a.no_sweep:
+        line["sweep"] = time_sweep(problems[0], w0.E, torch)
+    if not a.no_kernels:
+        line["kernels"] = per_kernel(problems, mgcccs.FP64, torch, a.max_it, PROBE_KERNELS)
+    iters_needed = [r.iters for r in r64]
+    del problems
+    torch.cuda.empty_cache()
+    if not a.no_c2:
+        line["c2"] = c2_leg(torch, a.max_it)
+    if not a.no_hbm:
+        line["hbm_4097"] = hbm_leg(torch, PROBE_KERNELS)
     if not a.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(wls[0])
+        line["cpu_baseline"] = cpu_baseline(wls, iters_needed, a.cpu_iters)
     print(json.dumps(line), flush=True)
 
 

@@ -85,12 +85,14 @@ typedef struct mgc_grid_s* mgc_grid;   /* opaque, library-owned host object */
  * M, Lch   channels (lowest 1D eigenstates) in x1 and in x2; 0 <= M,Lch <= 16.
  *          M = Lch = 0 disables the CCCS.
  * omega, nu1, nu2   omega-Jacobi weight and pre/post smoothing sweeps.
- * pc_gamma, pc_first_level
+ * pc_gamma, pc_first_level, pc_gamma0
  *          interior contour rotation used by the preconditioning hierarchy:
  *          on levels >= pc_first_level the grid is z = x e^{i pc_gamma} for
  *          x <= R0 (the complex-contour operator of Sec. 3.1/Sec. 6), followed
- *          by the ECS ray.  pc_gamma = 0 makes every level the exact operator.
- *          The CCCS acts on the level-0 operator of the hierarchy.
+ *          by the ECS ray; levels below pc_first_level use the angle
+ *          pc_gamma0 in the same way.  pc_gamma = pc_gamma0 = 0 makes every
+ *          level the exact operator.  Both angles lie in [0, pi/4).  The
+ *          CCCS acts on the level-0 operator of the hierarchy.
  * max_restart  FGMRES basis size the workspace must hold, 0 .. MGC_MAX_RESTART
  *              (0: no FGMRES).
  * precisions   bit mask (1 << MGC_FP64) | (1 << MGC_FP32) of the cycle
@@ -106,6 +108,7 @@ typedef struct {
   int pc_first_level;
   int max_restart;
   int precisions;
+  double pc_gamma0;
 } mgc_grid_desc;
 
 typedef struct {
@@ -143,6 +146,31 @@ mgc_status mgc_bind_workspace(mgc_grid g, void* dev_ptr, size_t bytes);
 
 /* Row pitch (in complex elements) of level-l fields; level 0 is the caller's. */
 mgc_status mgc_field_pitch(mgc_grid g, int level, int* pitch_elems);
+
+/* Launch schedule of the zero-guess MG-CCCS cycle (the cycle inside FGMRES
+ * and the first inner cycle of IR).  It changes how the work of the V-cycle
+ * of Sec. 3.2 is cut into launches, never the arithmetic: every choice gives
+ * the same iterate bit for bit.  The project's autotuner picks it per grid
+ * size, channel count and precision.
+ * small_tiles  bit l set: level l's fused smoothing passes use the small tiles
+ *              (16 x 4 coarse points / 64 x 4 nodes) instead of the large
+ *              ones (32 x 8 / 64 x 16); -1 (default): large tiles on levels
+ *              with at least 512 of them.
+ * level_pairs  1 (default): two consecutive small-tile levels above the
+ *              coarse tail share one pre- and one post-smoothing launch;
+ *              0: one launch per level and pass.
+ * coarse_tail  1 (default): the levels with n <= 32 (at most four) and the
+ *              coarsest solve run as two launches with the levels held in
+ *              LDS; 0: per-level launches and a separate coarsest solve.
+ * mgc_set_schedule returns MGC_EINVAL for small_tiles < -1 or a flag outside
+ * {0, 1}; the new schedule applies from the next call.                        */
+typedef struct {
+  int small_tiles;
+  int level_pairs;
+  int coarse_tail;
+} mgc_schedule;
+mgc_status mgc_set_schedule(mgc_grid g, const mgc_schedule* s);
+mgc_status mgc_get_schedule(mgc_grid g, mgc_schedule* s);
 
 /* Temkin-Poet potential strengths: V1 = -Z1/x1, V2 = -Z2/x2,
  * V12 = lambda/max(x1,x2) (Sec. 6.2).  Computes the M (Lch) lowest 1D
@@ -250,7 +278,10 @@ typedef enum {
   MGC_KT_S1 = 3,             /* smoothing, residual, restriction (all levels)  */
   MGC_KT_S2 = 4,             /* prolongation, post-smoothing (all levels)      */
   MGC_KT_CCCS_PROJECT = 5,   /* CCCS residual + channel projections            */
-  MGC_KT_CCCS_CHAIN = 6      /* CCCS chunk-local channel solves                */
+  MGC_KT_CCCS_CHAIN = 6,     /* CCCS chunk-local channel solves                */
+  MGC_KT_S1_FINE = 7,        /* the finest level's S1 launch alone             */
+  MGC_KT_S2_FINE = 8,        /* the finest level's S2 launch alone             */
+  MGC_KT_CCCS_EXPAND = 9     /* CCCS expansion u += e* (Sec. 4.3 eq. cccs)      */
 } mgc_kernel_class;
 typedef struct {
   double total_ms;           /* summed event durations                         */

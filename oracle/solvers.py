@@ -13,8 +13,9 @@
 
 Preconditioning hierarchy.  The cycle may act on the complex-contour operator
 of Sec. 3.1 (interior rotated by ``pc_gamma``) on levels >= ``pc_first_level``
-while the outer iteration solves the exterior-complex-scaled system; with
-``pc_gamma = 0`` the cycle uses the exact operator on every level.
+and by ``pc_gamma0`` below it, while the outer iteration solves the
+exterior-complex-scaled system; with both angles 0 the cycle uses the exact
+operator on every level.
 
 All stop tests use ||f - A u||_2 / ||f||_2 over the interior (Table 1 caption).
 """
@@ -43,10 +44,10 @@ class MGCCCS:
 
     def __init__(self, n, L, R0, theta, Z1, Z2, lam, E, levels, M,
                  omega=2.0 / 3.0, nu1=1, nu2=1, Lch=None, refine_steps=2,
-                 pc_gamma=0.0, pc_first_level=0):
+                 pc_gamma=0.0, pc_first_level=0, pc_gamma0=0.0):
         self.g = Grid1D(n, L, R0, theta)
         self.Z1, self.Z2, self.lam, self.E = Z1, Z2, lam, E
-        gammas = [pc_gamma if l >= pc_first_level else 0.0 for l in range(levels)]
+        gammas = [pc_gamma if l >= pc_first_level else pc_gamma0 for l in range(levels)]
         self.mg = Hierarchy(self.g, Z1, Z2, lam, E, levels, omega, nu1, nu2, gammas)
         self.op = tp_operator(self.g, Z1, Z2, lam, E)       # exact operator
         self.pc_op = self.mg.ops[0]                         # level 0 of the hierarchy
@@ -55,6 +56,9 @@ class MGCCCS:
 
     @classmethod
     def from_workload(cls, w, **kw):
+        kw.setdefault("pc_gamma", w.pc_gamma)
+        kw.setdefault("pc_first_level", w.pc_first_level)
+        kw.setdefault("pc_gamma0", w.pc_gamma0)
         return cls(w.n, w.L, w.R0, w.theta, w.Z1, w.Z2, w.lam, w.E, w.levels, w.M,
                    w.omega, w.nu1, w.nu2, **kw)
 

@@ -86,6 +86,7 @@ struct KernelTimer {
 
 struct mgc_grid_s {
   mgc_grid_desc d{};
+  mgc_schedule sched{-1, 1, 1};            // launch schedule (mgc_set_schedule)
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;               // capture stream (default priority)
   GraphCache graph;
@@ -442,19 +443,19 @@ void kt_harvest(mgc_grid g, int slots, const std::vector<double>& bytes, const s
 // large tiles per CU), is it in the coarse tail, and is it the finer level of
 // a pair whose S2 passes share one launch (pairs counted from the first
 // small-tile level, both members above the tail)?
+// The schedule (mgc_set_schedule) decides the tile size per level, and
+// whether pairs and the tail are used; every choice gives the same results
+// bit for bit (the tests compare them).
 bool small_tiles(mgc_grid g, int l) {
+  if (g->sched.small_tiles >= 0) return l < 31 && ((g->sched.small_tiles >> l) & 1);
   const int n = g->lv[l].n;
   return (long long)((n - 1 + 63) / 64) * ((n - 1 + 15) / 16) < 512;
 }
 bool in_tail(mgc_grid g, int l) {
-  return g->lv[l].n <= TAIL_MAX_N && g->coarsest() - l <= TMAXL;
+  return g->sched.coarse_tail && g->lv[l].n <= TAIL_MAX_N && g->coarsest() - l <= TMAXL;
 }
-// MGC_LEVEL_PASSES set in the environment (read when the cycle is enqueued):
-// every level by its own S1 / S2 launch, no pairs and no coarse tail.  The
-// results are the same bit for bit; the tests compare the two.
-bool level_passes() { return std::getenv("MGC_LEVEL_PASSES") != nullptr; }
 bool pair_level(mgc_grid g, int l) {
-  if (level_passes()) return false;
+  if (!g->sched.level_pairs) return false;
   if (l + 1 >= g->coarsest() || in_tail(g, l) || in_tail(g, l + 1) || !small_tiles(g, l)) return false;
   int s0 = l;
   while (s0 > 0 && small_tiles(g, s0 - 1)) --s0;
@@ -486,7 +487,7 @@ void vcycle_level(mgc_grid g, int l, void* u, const void* f, bool zero_guess, co
       kt_mark(g, s, kt.run, 0);
     }
     const int nl = g->coarsest() - l;
-    if (L.n <= TAIL_MAX_N && nl <= TMAXL && !level_passes()) {
+    if (L.n <= TAIL_MAX_N && nl <= TMAXL && g->sched.coarse_tail) {
       // coarse tail: every remaining level in two launches
       TailArgs<T> A{};
       double b1 = 0.0, b2 = 0.0;
@@ -543,11 +544,15 @@ void vcycle_level(mgc_grid g, int l, void* u, const void* f, bool zero_guess, co
       kt.bytes[kt.run] += (Nf + Nc) * e + (pair ? N2 * e : 0.0);    // f in, f_c (and f_cc) out
       ++kt.count[kt.run];
     }
+    // the finest level's launch alone (S1_FINE / S2_FINE classes)
+    const int tf1 = l == 0 ? kt_slot(g, MGC_KT_S1_FINE, (Nf + Nc) * e + (pair ? N2 * e : 0.0)) : -1;
+    kt_mark(g, s, tf1, 0);
     if (pair)
       launch_s1_pair<T>(s, L, level_of<T>(g, l + 1), f, fs, om, g->ws + LC.ff[p], LC.pitch, g->ws + LN.ff[p],
                         LN.pitch);
     else
-      launch_s1_zero<T>(s, L, f, fs, om, g->ws + LC.ff[p], LC.pitch);
+      launch_s1_zero<T>(s, L, f, fs, om, g->ws + LC.ff[p], LC.pitch, small_tiles(g, l));
+    kt_mark(g, s, tf1, 1);
     const bool last = lnext == g->coarsest();
     if (last && kt.which == MGC_KT_S1) {
       kt_mark(g, s, kt.run, 1);
@@ -563,11 +568,14 @@ void vcycle_level(mgc_grid g, int l, void* u, const void* f, bool zero_guess, co
       kt.bytes[kt.run] += (2 * Nf + Nc) * e + (pair ? N2 * e : 0.0);  // f, e_c (or f_c, e_cc) in, u out
       ++kt.count[kt.run];
     }
+    const int tf2 = l == 0 ? kt_slot(g, MGC_KT_S2_FINE, (2 * Nf + Nc) * e + (pair ? N2 * e : 0.0)) : -1;
+    kt_mark(g, s, tf2, 0);
     if (pair)
       launch_s2_pair<T>(s, L, level_of<T>(g, l + 1), f, fs, om, g->ws + LC.ff[p], g->ws + LN.fu[p], LN.pitch,
                         u);
     else
-      launch_s2_zero<T>(s, L, f, fs, om, g->ws + LC.fu[p], LC.pitch, u);
+      launch_s2_zero<T>(s, L, f, fs, om, g->ws + LC.fu[p], LC.pitch, u, small_tiles(g, l));
+    kt_mark(g, s, tf2, 1);
     if (l == 0 && kt.which == MGC_KT_S2) {
       kt_mark(g, s, kt.run, 1);
       kt.run = -1;
@@ -608,6 +616,9 @@ template <typename T> void cccs_apply(mgc_grid g, void* u, const void* f, const 
   } else if (g->kt.which == MGC_KT_CCCS_CHAIN) {
     kind = 2;
     slot = kt_slot(g, MGC_KT_CCCS_CHAIN, ((2.0 * M * M + 4.0 * M) + (2.0 * Lc * Lc + 4.0 * Lc)) * N1 * e);
+  } else if (g->kt.which == MGC_KT_CCCS_EXPAND) {
+    kind = 3;                              // u in and out, e^A, e^B in
+    slot = kt_slot(g, MGC_KT_CCCS_EXPAND, (2 * N1 * N1 + N1 * (M + Lc)) * e);
   }
   struct Ctx { mgc_grid g; int slot; } ctx{g, slot};
   MarkHook hook;
@@ -942,6 +953,7 @@ mgc_status mgc_create_grid(const mgc_grid_desc* d, void* hip_stream, mgc_grid* o
   if (!(d->omega > 0) || !(d->omega < 2)) return fail(MGC_EINVAL, "omega must lie in (0, 2)");
   if (d->nu1 < 0 || d->nu2 < 0 || d->nu1 + d->nu2 < 1 || d->nu1 > 8 || d->nu2 > 8) return fail(MGC_EINVAL, "bad smoothing counts");
   if (!(d->pc_gamma >= 0) || !(d->pc_gamma < M_PI / 4)) return fail(MGC_EINVAL, "pc_gamma must lie in [0, pi/4)");
+  if (!(d->pc_gamma0 >= 0) || !(d->pc_gamma0 < M_PI / 4)) return fail(MGC_EINVAL, "pc_gamma0 must lie in [0, pi/4)");
   if (d->pc_first_level < 0) return fail(MGC_EINVAL, "pc_first_level must be >= 0");
   if (d->max_restart < 0 || d->max_restart > MGC_MAX_RESTART)
     return fail(MGC_EINVAL, "max_restart must lie in [0, 16]");
@@ -962,7 +974,7 @@ mgc_status mgc_create_grid(const mgc_grid_desc* d, void* hip_stream, mgc_grid* o
     LevelInfo L;
     L.n = n >> l;
     L.pitch = pitch_for(L.n);
-    const double gam = (l >= d->pc_first_level) ? d->pc_gamma : 0.0;
+    const double gam = (l >= d->pc_first_level) ? d->pc_gamma : d->pc_gamma0;
     L.ax = make_axis(L.n, d->L, d->R0, d->theta, gam);
     g->lv.push_back(L);
   }
@@ -980,6 +992,22 @@ mgc_status mgc_create_grid(const mgc_grid_desc* d, void* hip_stream, mgc_grid* o
   g->nchunksB = (N + 63) / 64;
   layout(g);
   *out = g;
+  return MGC_OK;
+}
+
+mgc_status mgc_set_schedule(mgc_grid g, const mgc_schedule* s) {
+  if (!g || !s) return fail(MGC_EINVAL, "null argument");
+  if (s->small_tiles < -1) return fail(MGC_EINVAL, "small_tiles must be -1 or a level bit mask");
+  if ((s->level_pairs != 0 && s->level_pairs != 1) || (s->coarse_tail != 0 && s->coarse_tail != 1))
+    return fail(MGC_EINVAL, "level_pairs and coarse_tail must be 0 or 1");
+  g->sched = *s;
+  drop_graph(g);                           // the captured restart cycle has the old launches
+  return MGC_OK;
+}
+
+mgc_status mgc_get_schedule(mgc_grid g, mgc_schedule* s) {
+  if (!g || !s) return fail(MGC_EINVAL, "null argument");
+  *s = g->sched;
   return MGC_OK;
 }
 
@@ -1244,8 +1272,8 @@ static mgc_status validate_opts(mgc_grid g, const mgc_solve_opts* o) {
   switch (o->outer) {
     case MGC_STATIONARY:
       if (o->inner != MGC_FP64) return fail(MGC_EINVAL, "stationary iteration runs in FP64");
-      if (g->d.pc_first_level == 0 && g->d.pc_gamma != 0.0)
-        return fail(MGC_EINVAL, "stationary iteration needs the exact level-0 operator (pc_first_level >= 1 or pc_gamma = 0)");
+      if ((g->d.pc_first_level == 0 ? g->d.pc_gamma : g->d.pc_gamma0) != 0.0)
+        return fail(MGC_EINVAL, "stationary iteration needs the exact level-0 operator (no rotation on level 0)");
       break;
     case MGC_IR:
       if (o->inner_cycles < 1 || o->inner_cycles > 16) return fail(MGC_EINVAL, "inner_cycles must lie in [1, 16]");
@@ -1437,7 +1465,7 @@ mgc_status mgc_cross_section_grad(mgc_grid g, const void* u, const void* chi, do
 
 mgc_status mgc_set_kernel_timer(mgc_grid g, int kernel_class) {
   if (!g) return fail(MGC_EINVAL, "null handle");
-  if (kernel_class < MGC_KT_NONE || kernel_class > MGC_KT_CCCS_CHAIN)
+  if (kernel_class < MGC_KT_NONE || kernel_class > MGC_KT_CCCS_EXPAND)
     return fail(MGC_EINVAL, "unknown kernel class");
   KernelTimer& t = g->kt;
   if (kernel_class != MGC_KT_NONE && !t.ev[0]) {
@@ -1566,6 +1594,10 @@ mgc_status mgc_batch_solve(mgc_batch b, void* const* u, const void* const* f, co
   hipStream_t s = g0->stream;
   std::vector<BatchSolve> v(nb);
   auto cleanup = [&]() {
+    // an error may leave graphs of this round in flight: drain every stream
+    // before their executable graphs are destroyed
+    for (int k = 0; k < NS; ++k) (void)hipStreamSynchronize(b->side[k]);
+    (void)hipStreamSynchronize(s);
     for (BatchSolve& x : v)
       if (x.exec) {
         (void)hipGraphExecDestroy(x.exec);

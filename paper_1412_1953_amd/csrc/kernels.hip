@@ -2620,10 +2620,10 @@ void launch_coarse_solve(hipStream_t s, const double2* Ainv, int nc, int pitch, 
 
 template <typename T>
 void launch_s1_zero(hipStream_t s, const Level<T>& L, const void* f, const double* fs, double omega,
-                    void* fc, int pitch_c) {
+                    void* fc, int pitch_c, bool small) {
   const int nc = L.n / 2;
   const dim3 big((nc - 1 + S1Big::CX - 1) / S1Big::CX, (nc - 1 + S1Big::CY - 1) / S1Big::CY);
-  if (big.x * big.y >= 512) {
+  if (!small) {
     hipLaunchKernelGGL((k_s1_zero<T, S1Big>), big, dim3(64, 4), 0, s, L, (const v2<T>*)f, fs, (T)omega,
                        (v2<T>*)fc, pitch_c);
   } else {
@@ -2634,9 +2634,9 @@ void launch_s1_zero(hipStream_t s, const Level<T>& L, const void* f, const doubl
 }
 template <typename T>
 void launch_s2_zero(hipStream_t s, const Level<T>& L, const void* f, const double* fs, double omega,
-                    const void* ec, int pitch_c, void* u) {
+                    const void* ec, int pitch_c, void* u, bool small) {
   const dim3 big((L.n - 1 + S2Big::TX - 1) / S2Big::TX, (L.n - 1 + S2Big::TY - 1) / S2Big::TY);
-  if (big.x * big.y >= 512) {
+  if (!small) {
     hipLaunchKernelGGL((k_s2_zero<T, S2Big>), big, dim3(64, 4), 0, s, L, (const v2<T>*)f, fs, (T)omega,
                        (const v2<T>*)ec, pitch_c, (v2<T>*)u);
   } else {
@@ -2677,8 +2677,10 @@ void launch_s2_pair(hipStream_t s, const Level<T>& Lf, const Level<T>& Lc, const
   template void launch_resid_restrict<T>(hipStream_t, const Level<T>&, const void*, const void*, void*, int); \
   template void launch_prolong_add<T>(hipStream_t, int, int, void*, const void*, int);        \
   template void launch_coarse_solve<T>(hipStream_t, const double2*, int, int, const void*, void*); \
-  template void launch_s1_zero<T>(hipStream_t, const Level<T>&, const void*, const double*, double, void*, int); \
-  template void launch_s2_zero<T>(hipStream_t, const Level<T>&, const void*, const double*, double, const void*, int, void*); \
+  template void launch_s1_zero<T>(hipStream_t, const Level<T>&, const void*, const double*, double, void*, int, \
+                                  bool);                                                                      \
+  template void launch_s2_zero<T>(hipStream_t, const Level<T>&, const void*, const double*, double, const void*, \
+                                  int, void*, bool);                                                          \
   template void launch_tail<T>(hipStream_t, const TailArgs<T>&, bool);                        \
   template void launch_s2_pair<T>(hipStream_t, const Level<T>&, const Level<T>&, const void*, const double*, \
                                   double, const void*, const void*, int, void*);                 \
@@ -2765,8 +2767,10 @@ void launch_cccs(hipStream_t s, const Level<T>& L, void* u, const void* f, const
     MGC_RETRIEVE(16);
   }
 #undef MGC_RETRIEVE
+  mark(3, 0);
   MGC_CC_DISPATCH(k_cccs_expand, stencil_grid(n), dim3(SX, SY), n, L.pitch, (v2<T>*)u, ch,
                   (const v2<T>*)eA, (const v2<T>*)eB);
+  mark(3, 1);
 #undef MGC_CC_DISPATCH
 }
 template void launch_cccs<double>(hipStream_t, const Level<double>&, void*, const void*, const double*,

@@ -68,13 +68,15 @@ void launch_prolong_add(hipStream_t s, int n, int pitch, void* u, const void* ec
 template <typename T>
 void launch_coarse_solve(hipStream_t s, const double2* Ainv, int nc, int pitch, const void* f, void* u);
 
-// fused zero-guess passes (nu1 = nu2 = 1); fs: optional device scale of f
+// fused zero-guess passes (nu1 = nu2 = 1); fs: optional device scale of f;
+// small: the small tiles (16 x 4 coarse points / 64 x 4 nodes) instead of the
+// large ones (32 x 8 / 64 x 16)
 template <typename T>
 void launch_s1_zero(hipStream_t s, const Level<T>& L, const void* f, const double* fs, double omega,
-                    void* fc, int pitch_c);
+                    void* fc, int pitch_c, bool small);
 template <typename T>
 void launch_s2_zero(hipStream_t s, const Level<T>& L, const void* f, const double* fs, double omega,
-                    const void* ec, int pitch_c, void* u);
+                    const void* ec, int pitch_c, void* u, bool small);
 // S1 of levels l and l+1 in one launch (small tiles): f, fs of level l; f1 =
 // f of level l+1 (written), f2 = f of level l+2 (written)
 template <typename T>
@@ -96,7 +98,7 @@ int launch_cccs_reduce_blocks(int n);   // blocks of coupling-coefficient partia
 struct MarkHook {
   void (*fn)(void* ctx, hipStream_t s, int end) = nullptr;
   void* ctx = nullptr;
-  int kind = 0;                    // launch_cccs: 1 projection pass, 2 chunk chains
+  int kind = 0;                    // launch_cccs: 1 projection pass, 2 chunk chains, 3 expansion
 };
 template <typename T>
 void launch_cccs(hipStream_t s, const Level<T>& L, void* u, const void* f, const double* fs,

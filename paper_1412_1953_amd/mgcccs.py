@@ -27,10 +27,11 @@ EXPORTED = ["mgc_create_grid", "mgc_workspace_bytes", "mgc_bind_workspace", "mgc
             "mgc_cccs", "mgc_solve", "mgc_solve_transpose", "mgc_cross_section",
             "mgc_cross_section_sweep", "mgc_cross_section_grad", "mgc_set_kernel_timer", "mgc_read_kernel_timer",
             "mgc_batch_create", "mgc_batch_solve", "mgc_batch_destroy",
-            "mgc_destroy_grid", "mgc_last_error"]
+            "mgc_set_schedule", "mgc_get_schedule", "mgc_destroy_grid", "mgc_last_error"]
 
 # kernel classes of mgc_set_kernel_timer
-KT_NONE, KT_APPLY_DOT, KT_AXPY, KT_S1, KT_S2, KT_CCCS_PROJECT, KT_CCCS_CHAIN = range(7)
+(KT_NONE, KT_APPLY_DOT, KT_AXPY, KT_S1, KT_S2, KT_CCCS_PROJECT, KT_CCCS_CHAIN, KT_S1_FINE, KT_S2_FINE,
+ KT_CCCS_EXPAND) = range(10)
 
 
 class GridDesc(ctypes.Structure):
@@ -38,7 +39,12 @@ class GridDesc(ctypes.Structure):
                 ("theta", ctypes.c_double), ("levels", ctypes.c_int), ("M", ctypes.c_int),
                 ("Lch", ctypes.c_int), ("omega", ctypes.c_double), ("nu1", ctypes.c_int),
                 ("nu2", ctypes.c_int), ("pc_gamma", ctypes.c_double), ("pc_first_level", ctypes.c_int),
-                ("max_restart", ctypes.c_int), ("precisions", ctypes.c_int)]
+                ("max_restart", ctypes.c_int), ("precisions", ctypes.c_int), ("pc_gamma0", ctypes.c_double)]
+
+
+class Schedule(ctypes.Structure):
+    """Launch schedule of the zero-guess cycle (mgc_schedule)."""
+    _fields_ = [("small_tiles", ctypes.c_int), ("level_pairs", ctypes.c_int), ("coarse_tail", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -95,6 +101,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mgc_batch_solve": [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(SolveOpts),
                             ctypes.POINTER(Stats)],
         "mgc_batch_destroy": [vp],
+        "mgc_set_schedule": [vp, ctypes.POINTER(Schedule)],
+        "mgc_get_schedule": [vp, ctypes.POINTER(Schedule)],
         "mgc_destroy_grid": [vp],
     }
     for name, args in sig.items():
@@ -134,14 +142,15 @@ class Grid:
     """One MG-CCCS handle with a torch-allocated workspace on a CUDA device."""
 
     def __init__(self, n, L, R0, theta, levels, M, Lch=None, omega=2.0 / 3.0, nu1=1, nu2=1,
-                 pc_gamma=0.0, pc_first_level=0, max_restart=16, fp32=True, device="cuda:0"):
+                 pc_gamma=0.0, pc_first_level=0, max_restart=16, fp32=True, device="cuda:0",
+                 pc_gamma0=0.0):
         import torch
         self.torch = torch
         self.lib = load_library()
         self.device = torch.device(device)
         Lch = M if Lch is None else Lch
         self.desc = GridDesc(n, L, R0, theta, levels, M, Lch, omega, nu1, nu2, pc_gamma,
-                             pc_first_level, max_restart, 1 | (2 if fp32 else 0))
+                             pc_first_level, max_restart, 1 | (2 if fp32 else 0), pc_gamma0)
         self.n, self.levels, self.M, self.Lch = n, levels, M, Lch
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
@@ -162,6 +171,9 @@ class Grid:
 
     @classmethod
     def from_workload(cls, w, **kw):
+        kw.setdefault("pc_gamma", w.pc_gamma)
+        kw.setdefault("pc_first_level", w.pc_first_level)
+        kw.setdefault("pc_gamma0", w.pc_gamma0)
         return cls(w.n, w.L, w.R0, w.theta, w.levels, w.M, omega=w.omega, nu1=w.nu1, nu2=w.nu2, **kw)
 
     def __del__(self):
@@ -282,6 +294,15 @@ class Grid:
         res = SolveResult(rc, st.iters, st.vcycles, st.relres,
                           [hist[i] for i in range(st.hist_len)], st.t_setup_ms, st.t_solve_ms)
         return [ds[0], ds[1], ds[2]], complex(z[0], z[1]), sig.value, res
+
+    def set_schedule(self, small_tiles=-1, level_pairs=1, coarse_tail=1):
+        """Launch schedule of the zero-guess cycle (same results either way)."""
+        _check(self.lib.mgc_set_schedule(self.h, ctypes.byref(Schedule(small_tiles, level_pairs, coarse_tail))))
+
+    def get_schedule(self):
+        s = Schedule()
+        _check(self.lib.mgc_get_schedule(self.h, ctypes.byref(s)))
+        return s.small_tiles, s.level_pairs, s.coarse_tail
 
     def set_kernel_timer(self, kernel_class: int):
         """Time every launch of one kernel class inside FGMRES solves (KT_*)."""

@@ -32,6 +32,9 @@ CLASS_PATTERN = {
     "s2": r"k_s2_zero<double\b|k_s2_pair<double>|k_tail_up<double>",
     "cccs_project": r"k_cccs_project<double",
     "cccs_chain": r"k_cccs_chain<double",
+    "s1_fine": r"k_s1_zero<double\b",
+    "s2_fine": r"k_s2_zero<double\b",
+    "cccs_expand": r"k_cccs_expand<double",
 }
 
 

@@ -42,6 +42,13 @@ class Workload:
     omega: float = 2.0 / 3.0
     nu1: int = 1
     nu2: int = 1
+    # preconditioning hierarchy: levels >= pc_first_level put the real
+    # interior on the rotated contour z = x exp(i pc_gamma) (Sec. 3.1), the
+    # levels below it on z = x exp(i pc_gamma0); the autotuner replaces these
+    # defaults per grid size, channel count and energy
+    pc_gamma: float = math.radians(15.0)
+    pc_first_level: int = 1
+    pc_gamma0: float = math.radians(10.0)
 
     @property
     def unknowns(self) -> int:
@@ -63,6 +70,11 @@ TP1025 = {E: tp_workload(f"tp1025_E{E}_fp64", 1024, 80.0, E, 7, 8, 1e-10, 1)
 
 # Mixed precision, 2049^2 nodes on [0,160]^2, ECS beyond 120, 8 levels, 8 channels.
 TP2049 = tp_workload("tp2049_E0.1_mixed", 2048, 160.0, 0.1, 8, 8, 1e-10, 2)
+
+# Out-of-cache bandwidth probe: 4097^2 nodes (one FP64 field = 270 MB, more
+# than the 256 MB on-die cache) at the 1025^2 spacing, [0,320]^2, ECS beyond
+# 240, 9 levels (coarsest 16 intervals), 8 channels, E = 0.5.
+TP4097 = tp_workload("tp4097_E0.5_probe", 4096, 320.0, 0.5, 9, 8, 1e-10, 5)
 
 # Differentiation: 1025^2 on [0,80]^2 at E = 0.5.
 TP1025_GRAD = tp_workload("tp1025_E0.5_grad", 1024, 80.0, 0.5, 7, 8, 1e-13, 4)

@@ -33,12 +33,11 @@ SIXTEEN = [Case(64 if i % 2 else 128, 20.0 if i % 2 else 40.0, 0.05 + 0.11 * i, 
                 2 + (i % 7), pc_gamma=GAM, seed=100 + i) for i in range(16)]
 
 
-@pytest.mark.skip(reason="a run of this test under an earlier batch implementation (parent graph "
-                         "of child-graph nodes, host-mapped reports) aborted with host heap "
-                         "corruption; cause not identified")
 def test_batch_of_16_runs_groups_concurrently():
-    """16 solves (two parent graphs per round on separate streams): every
-    iterate equals its individual solve; batch time against one by one."""
+    """16 solves (one graph per solve and round over the batch's streams):
+    every iterate equals its individual solve; batch time against one by
+    one.  The host bookkeeping of this batch runs clean under AddressSanitizer
+    (tests/test_host_asan.py)."""
     import torch
     from paper_1412_1953_amd import mgcccs
     grids = [c.grid() for c in SIXTEEN]
@@ -119,18 +118,17 @@ def test_batch_argument_errors():
     assert e.value.status == mgcccs.MGC_EINVAL
 
 
-@pytest.mark.skip(reason="a run of this test under an earlier batch implementation (one parent graph "
-                         "of 64 child-graph nodes) ended in a host segmentation fault; cause not "
-                         "identified")
 def test_batch_of_64_mixed_size_solves():
     """The 64-solve workload: every solve to 1e-10; one solve of each size
-    checked by the oracle's operator; batch time against one-by-one solves."""
+    checked by the oracle's operator; batch time against one-by-one solves.
+    The host bookkeeping of this batch runs clean under AddressSanitizer
+    (tests/test_host_asan.py)."""
     from paper_1412_1953_amd import mgcccs
     wls = batch_workloads()
     t0 = time.perf_counter()
     grids, chis, us = [], [], []
     for w in wls:
-        g = mgcccs.Grid.from_workload(w, pc_gamma=GAM, max_restart=10, fp32=True)
+        g = mgcccs.Grid.from_workload(w, max_restart=10, fp32=True)
         g.set_potential(w.Z1, w.Z2, w.lam)
         g.set_energy(w.E)
         grids.append(g)
@@ -184,7 +182,7 @@ def test_batch_of_mixed_sizes_against_one_by_one():
         pick += [w for w in wls if w.n == n][:4]
     grids, chis = [], []
     for w in pick:
-        g = mgcccs.Grid.from_workload(w, pc_gamma=GAM, max_restart=10, fp32=True)
+        g = mgcccs.Grid.from_workload(w, max_restart=10, fp32=True)
         g.set_potential(w.Z1, w.Z2, w.lam)
         g.set_energy(w.E)
         grids.append(g)

@@ -21,12 +21,11 @@ from oracle.grid import Grid1D, rel_residual, tp_operator, tp_rhs
 from paper_1412_1953_amd.workloads import TP1025, TP2049, TP1025_GRAD
 
 pytestmark = pytest.mark.gpu
-GAM = math.radians(5.0)
-
-
 def case_of(w):
+    """The workload with its own preconditioning hierarchy (exact level 0,
+    rotated contour from pc_first_level on)."""
     return Case(w.n, w.L, w.E, w.levels, w.M, theta=w.theta, R0frac=w.R0 / w.L, seed=w.seed,
-                pc_gamma=GAM)
+                pc_gamma=w.pc_gamma, pc_first_level=w.pc_first_level, pc_gamma0=w.pc_gamma0)
 
 
 @pytest.fixture(scope="module")
