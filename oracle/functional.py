@@ -168,3 +168,64 @@ def grad_adjoint(g: Grid1D, p, E, k1, k2, fd_step=1e-6):
         dJ[q] = 2 * C * np.real(np.conj(zt) * dz)
     dJ[0] += -J * 2 * Z1 / k0sq
     return dJ, dict(J=J, v=v, zeta=zt)
+
+
+# ---------------------------------------------------------------------------
+# Single ionisation and the total double-ionisation cross section (Sec. 3.3).
+def source_term(g: Grid1D, lam: float, u: np.ndarray, chi: np.ndarray) -> np.ndarray:
+    """f - V12 u on every node (V12 = lambda / z_max(j,k); the ring is never
+    weighted)."""
+    n = g.n
+    idx = np.arange(n + 1)
+    m = np.maximum(idx[:, None], idx[None, :])
+    zr = g.z.copy()
+    zr[0] = 1.0
+    return chi - (lam / zr[m]) * u
+
+
+def single_ionization(g: Grid1D, Z1: float, Z2: float, lam: float, E: float,
+                      u: np.ndarray, chi: np.ndarray, nstates: int):
+    """Single-ionisation amplitudes s_n(E), n = 1 .. nstates (eq. single-ionization):
+        s_n = sum_{j,k <= j0} t_j t_k phi_{k_n}(x1_j) phi_n(x2_k) (f - V12 u)_{kj},
+    phi_n the n-th lowest bound state of the x2 one-body Hamiltonian
+    -1/2 d^2/dz^2 - Z2/z on the exterior-complex-scaled grid (eq. 1d_eigenstate,
+    bilinear normalisation), k_n = sqrt(2 (E - lambda_n)) and phi_{k_n} the
+    test function of eq. testfunction in x1.  Readings: the real region with
+    trapezoid weights as for zeta; k_n from the real part of the discrete
+    eigenvalue (its imaginary part is round-off for a true bound state).
+    Returns (lambda_n, k_n, s_n) as arrays."""
+    from .cccs import bound_states
+    from .grid import tp_one_body
+    n, top = g.n, min(g.j0, g.n - 1)
+    lamB, vphi = bound_states(g, tp_one_body(g, Z2), nstates)
+    t = trapezoid_weights(g)
+    src = source_term(g, lam, u, chi)
+    ks, out = [], []
+    for q in range(nstates):
+        kq = math.sqrt(2.0 * (E - lamB[q].real))
+        p1 = test_function(g, Z1, kq)
+        f1 = np.zeros(n + 1)
+        f1[1:top + 1] = t[1:top + 1] * p1[1:top + 1]
+        f2 = np.zeros(n + 1, np.complex128)
+        f2[1:top + 1] = t[1:top + 1] * vphi[q, 1:top + 1]
+        ks.append(kq)
+        out.append(complex(f2 @ src @ f1))
+    return lamB, np.array(ks), np.array(out)
+
+
+def sigma_total(g: Grid1D, Z1: float, lam: float, E: float, u: np.ndarray, chi: np.ndarray,
+                nodes: int = 32) -> float:
+    """Total double-ionisation cross section (eq. total-double-ionization),
+        sigma_tot(E) = int_0^E sigma(sqrt(2 eps), sqrt(2 (E - eps))) d eps,
+    with eps = E sin^2 a (k1 = sqrt(2E) sin a, k2 = sqrt(2E) cos a, the
+    sharing angle of the sweeps): the Jacobian 2 E sin a cos a cancels the
+    1/(k1 k2) of sigma, so
+        sigma_tot = 8 pi^2 / k0^2 int_0^{pi/2} |zeta(k1(a), k2(a))|^2 da,
+    a smooth integrand, taken by Gauss-Legendre quadrature with `nodes` points."""
+    x, w = np.polynomial.legendre.leggauss(nodes)
+    a = (x + 1.0) * math.pi / 4.0
+    wa = w * math.pi / 4.0
+    K = math.sqrt(2.0 * E)
+    zs = zeta_sweep(g, Z1, lam, u, chi, K * np.sin(a), K * np.cos(a))
+    k0sq = 2.0 * (E + 0.5 * Z1 * Z1)
+    return float(8.0 * math.pi ** 2 / k0sq * np.sum(wa * np.abs(np.array(zs)) ** 2))

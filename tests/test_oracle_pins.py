@@ -575,6 +575,70 @@ def test_zeta_exchange_symmetry():
         assert abs(x - y) < 1e-12 * abs(x)
 
 
+# ---------------------------------------------------------------- N1 -------
+def test_total_cross_section_quadrature_matches_the_energy_integral():
+    """Sec. 3.3 eq. total-double-ionization: the Gauss-Legendre rule in the
+    sharing angle (eps = E sin^2 a) against the definition integrated in the
+    energy eps by adaptive quadrature (scipy's QUADPACK, which copes with the
+    1/sqrt endpoint behaviour of sigma).  A planted mistake -- integrating
+    sigma itself over the angle, i.e. dropping the Jacobian 2 E sin a cos a --
+    is far off."""
+    import scipy.integrate as si
+    g = Grid1D(64, 20.0, 15.0, math.pi / 6)
+    E = 0.6
+    chi = tp_rhs(g, 1.0, 1.0, 1.0, E)
+    u = rng_field(64, 3) * 0.1
+    got = fn.sigma_total(g, 1.0, 1.0, E, u, chi, nodes=32)
+
+    def sigma_eps(eps):
+        k1, k2 = math.sqrt(2 * eps), math.sqrt(2 * (E - eps))
+        return fn.sigma(fn.zeta(g, 1.0, 1.0, u, chi, k1, k2), E, 1.0, k1, k2)
+
+    ref, err = si.quad(sigma_eps, 0.0, E, limit=200, epsabs=0, epsrel=1e-11)
+    assert abs(got - ref) < 1e-10 * ref, (got, ref, err)
+    x, w = np.polynomial.legendre.leggauss(32)
+    a = (x + 1) * math.pi / 4
+    K = math.sqrt(2 * E)
+    bad = sum(wq * math.pi / 4 * fn.sigma(fn.zeta(g, 1.0, 1.0, u, chi, K * math.sin(aq), K * math.cos(aq)), E, 1.0,
+                                          K * math.sin(aq), K * math.cos(aq)) for aq, wq in zip(a, w))
+    assert abs(bad - ref) > 0.1 * ref
+
+
+def test_single_ionization_factorises_for_a_separable_source():
+    """Sec. 3.3 eq. single-ionization with u = 0 and chi[k][j] = a_k b_j (row
+    k <-> x2): s_n = (sum_k t_k phi_n(x2_k) a_k)(sum_j t_j phi_{k_n}(x1_j) b_j),
+    phi_n the bound state of the x2 Hamiltonian (Z2), phi_{k_n} the x1 test
+    function (Z1) at k_n = sqrt(2 (E - lambda_n)).  With Z1 != Z2 and a != b a
+    mistake in which coordinate carries which function fails."""
+    from oracle.cccs import bound_states
+    g = Grid1D(128, 30.0, 22.5, math.pi / 6)
+    rng = np.random.default_rng(7)
+    a = rng.standard_normal(129) + 1j * rng.standard_normal(129)
+    b = rng.standard_normal(129) + 1j * rng.standard_normal(129)
+    chi = np.outer(a, b)
+    u = np.zeros_like(chi)
+    E, Z1, Z2 = 0.4, 1.0, 1.4
+    lamB, ks, s = fn.single_ionization(g, Z1, Z2, 0.7, E, u, chi, 3)
+    t = fn.trapezoid_weights(g)
+    lam2, phi2 = bound_states(g, tp_one_body(g, Z2), 3)
+    lam1, phi1 = bound_states(g, tp_one_body(g, Z1), 3)
+    assert np.allclose(lamB, lam2, rtol=0, atol=1e-13)
+    assert abs(lam2[0].real + Z2 ** 2 / 2) < 0.05           # the hydrogenic ground state of Z2 (h = 0.23)
+    for q in range(3):
+        kq = math.sqrt(2 * (E - lam2[q].real))
+        pk = np.zeros(129)
+        tf = fn.test_function(g, Z1, kq)
+        pk[:len(tf)] = tf
+        ref = np.sum(t * phi2[q] * a) * np.sum(t * pk * b)
+        assert abs(s[q] - ref) < 1e-12 * abs(ref)
+        # planted: the bound state on x1 and the test function on x2
+        swapped = np.sum(t * pk * a) * np.sum(t * phi2[q] * b)
+        assert abs(swapped - ref) > 1e-3 * abs(ref)
+        # planted: the bound state of the x1 Hamiltonian (Z1)
+        wrong = np.sum(t * phi1[q] * a) * np.sum(t * pk * b)
+        assert abs(wrong - ref) > 1e-3 * abs(ref)
+
+
 # ---------------------------------------------------------------- P14 (adjoint)
 @pytest.mark.parametrize("p", [(1.0, 1.0, 1.0), (1.1, 0.9, 1.3)])
 def test_adjoint_gradient_matches_central_differences(p):
