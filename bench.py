@@ -15,6 +15,8 @@ Further legs of the same JSON line:
   batched        the step's solves run together through the batch entry point,
                  FP64 and FP32 cycles;
   c2             the 2049^2 workload (E = 0.1): one FP64 and one mixed solve;
+  c3             the 64-solve batch workload: mixed precision through the batch
+                 entry point against plain FP64 solves one after another;
   hbm_4097       a 4097^2 grid (every FP64 field larger than the on-die cache):
                  the finest-level streaming kernels timed with HIP events,
                  algorithmic bytes / time against the 8 TB/s HBM peak;
@@ -59,6 +61,7 @@ def parse():
     p.add_argument("--no-sweep", action="store_true", help="skip the cross-section sweep leg")
     p.add_argument("--no-c2", action="store_true", help="skip the 2049^2 leg")
     p.add_argument("--no-hbm", action="store_true", help="skip the 4097^2 bandwidth leg")
+    p.add_argument("--no-c3", action="store_true", help="skip the 64-solve batch leg")
     p.add_argument("--no-kernels", action="store_true", help="skip the per-kernel 1025^2 figures")
     p.add_argument("--only-hbm", action="store_true", help="only the 4097^2 leg (profiling runs)")
     p.add_argument("--energies", type=str, default="0.05,0.5,2.0",
@@ -72,11 +75,11 @@ def parse():
 
 
 def make_problem(w, torch, fp32=True):
-    from paper_1412_1953_amd import mgcccs
+    """Handle with the tuned preconditioning hierarchy (autotuner cache),
+    right-hand side, initial guess and solution field."""
+    from paper_1412_1953_amd import autotune
     from paper_1412_1953_amd.workloads import initial_guess
-    g = mgcccs.Grid.from_workload(w, max_restart=RESTART, fp32=fp32)
-    g.set_potential(w.Z1, w.Z2, w.lam)
-    g.set_energy(w.E)
+    g = autotune.tuned_grid(w, max_restart=RESTART, fp32=fp32)
     chi = g.build_rhs_tp(g.field())
     u0 = g.from_numpy(initial_guess(w.n, w.seed))
     u = g.field()
@@ -91,6 +94,13 @@ def run_step(problems, inner, torch, max_it, tol=1e-10):
         r = g.solve(u, chi, outer=mgcccs.FGMRES, inner=inner, restart=RESTART, max_it=max_it, tol=tol)
         out.append(r)
     return out
+
+
+def use_schedule(problems, inner, wls):
+    """The tuned launch schedule of each handle for the cycle precision."""
+    from paper_1412_1953_amd import autotune, mgcccs
+    for (g, *_), w in zip(problems, wls):
+        g.set_schedule(*autotune.schedule_of(w, inner == mgcccs.FP32))
 
 
 def time_steps(problems, inner, torch, steps, warmup, max_it, kclass=0, tol=1e-10):
@@ -194,12 +204,60 @@ def c2_leg(torch, max_it):
     prob = make_problem(w, torch)
     out = {"workload": w.name, "n": w.n, "E": w.E, "tol": w.tol}
     for name, inner in (("fp64", mgcccs.FP64), ("mixed", mgcccs.FP32)):
+        use_schedule([prob], inner, [w])
         dt, res, _ = time_steps([prob], inner, torch, 1, 1, max_it)
         r = res[0]
         out[name] = {"value": w.unknowns / dt, "ms": dt * 1e3, "iters": r.iters, "relres": r.relres,
                      "status": r.status}
     out["speedup_mixed_vs_fp64"] = out["mixed"]["value"] / out["fp64"]["value"]
     del prob
+    torch.cuda.empty_cache()
+    return out
+
+
+def c3_leg(torch, max_it):
+    """The 64-solve batch workload (257^2 / 513^2 / 1025^2, E in [0.02, 3.0],
+    4..16 channels, each with its tuned hierarchy and schedule): all solves
+    together through the batch entry point with the complex-FP32 cycle, and
+    the same solves one after another with the FP64 cycle, each timed once
+    after an untimed warm-up pass (graph capture)."""
+    from paper_1412_1953_amd import autotune, mgcccs
+    from paper_1412_1953_amd.workloads import batch_workloads, initial_guess
+    wls = batch_workloads()
+    t0 = time.perf_counter()
+    probs = []
+    for w in wls:
+        g = autotune.tuned_grid(w, fp32_cycle=True, max_restart=RESTART, fp32=True)
+        probs.append((g, g.build_rhs_tp(g.field()), g.from_numpy(initial_guess(w.n, w.seed)), g.field()))
+    setup_s = time.perf_counter() - t0
+    unknowns = sum(w.unknowns for w in wls)
+    out = {"solves": len(wls), "unknowns": unknowns, "setup_s": setup_s}
+    batch = mgcccs.Batch([p[0] for p in probs])
+    us, fs = [p[3] for p in probs], [p[1] for p in probs]
+    for timed in (False, True):
+        for _, _, u0, u in probs:
+            u.copy_(u0)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rb = batch.solve(us, fs, inner=mgcccs.FP32, restart=RESTART, max_it=max_it, tol=1e-10)
+        torch.cuda.synchronize()
+        dtb = time.perf_counter() - t1
+    out["batched_mixed"] = {"value": unknowns / dtb, "s": dtb, "iters": sum(r.iters for r in rb),
+                            "max_relres": max(r.relres for r in rb),
+                            "converged": sum(r.status == mgcccs.MGC_OK for r in rb)}
+    for (g, *_), w in zip(probs, wls):
+        g.set_schedule(*autotune.schedule_of(w, False))
+    for timed in (False, True):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rs = run_step(probs, mgcccs.FP64, torch, max_it)
+        torch.cuda.synchronize()
+        dts = time.perf_counter() - t1
+    out["sequential_fp64"] = {"value": unknowns / dts, "s": dts, "iters": sum(r.iters for r in rs),
+                              "max_relres": max(r.relres for r in rs),
+                              "converged": sum(r.status == mgcccs.MGC_OK for r in rs)}
+    out["speedup_batched_mixed_vs_fp64"] = dts / dtb
+    del batch, probs
     torch.cuda.empty_cache()
     return out
 
@@ -216,6 +274,7 @@ def hbm_leg(torch, kernels, iters=20):
     out = {"workload": w.name, "n": w.n, "field_bytes": (w.n + 1) * prob[0].pitch * 16,
            "iterations_per_run": iters, "setup_s": setup_s}
     figs = {}
+    use_schedule([prob], mgcccs.FP64, [w])
     for k in kernels:
         _, res, t = time_steps([prob], mgcccs.FP64, torch, 1, 1, iters, KCLASS[k], tol=1e-300)
         figs[k] = kernel_figure(t)
@@ -278,10 +337,11 @@ def cpu_baseline(wls, iters_needed, sample_iters):
     from threadpoolctl import threadpool_limits
 
     from oracle.solvers import MGCCCS
+    from paper_1412_1953_amd import autotune
     from paper_1412_1953_amd.workloads import initial_guess
     solvers = []
     for w in wls:
-        o = MGCCCS.from_workload(w)
+        o = MGCCCS.from_workload(w, **autotune.hierarchy_of(w))
         solvers.append((w, o, o.rhs(), initial_guess(w.n, w.seed)))
     ncores = len(os.sched_getaffinity(0))
     runs = {}
@@ -316,7 +376,7 @@ def main():
               "MI355X (multi-GPU sharding is a design note, not implemented)", file=sys.stderr)
         sys.exit(2)
     import torch
-    from paper_1412_1953_amd import mgcccs
+    from paper_1412_1953_amd import autotune, mgcccs
     from paper_1412_1953_amd.workloads import TP1025
     mgcccs.load_library()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -331,6 +391,7 @@ def main():
     w0 = wls[0]
 
     kclass = KCLASS[a.roofline_kernel]
+    use_schedule(problems, mgcccs.FP64, wls)
     dt64, r64, kt = time_steps(problems, mgcccs.FP64, torch, a.steps, a.warmup, a.max_it, kclass)
     line = {
         "metric": "solved unknowns/s to 1e-10 rel. residual, mixed vs FP64 MG-CCCS; HBM GB/s",
@@ -343,8 +404,10 @@ def main():
         "config": {"workload": "tp1025_fp64_E0.05_0.5_2.0", "n": 1024, "L": 80.0, "R0": 60.0,
                    "theta": "pi/6", "levels": 7, "channels": 8, "tol": 1e-10,
                    "outer": f"FGMRES({RESTART})", "preconditioner": "MG-CCCS V(1,1)",
-                   "pc_gamma_deg": round(math.degrees(w0.pc_gamma), 6),
-                   "pc_first_level": w0.pc_first_level, "energies": [w.E for w in wls]},
+                   "hierarchy": [{k: (round(math.degrees(v), 6) if k != "pc_first_level" else v)
+                                  for k, v in autotune.hierarchy_of(w).items()} for w in wls],
+                   "schedule_fp64": [autotune.schedule_of(w, False) for w in wls],
+                   "energies": [w.E for w in wls]},
         "fp64": {"iters": [r.iters for r in r64], "relres": [r.relres for r in r64],
                  "status": [r.status for r in r64],
                  "vcycles_per_s": sum(r.vcycles for r in r64) / dt64},
@@ -359,6 +422,7 @@ def main():
                             "event_floor_us_per_launch": fig["event_floor_us_per_launch"],
                             "bytes_per_launch": fig["bytes_per_launch"]}
     if not a.no_mixed:
+        use_schedule(problems, mgcccs.FP32, wls)
         dt32, r32, _ = time_steps(problems, mgcccs.FP32, torch, a.steps, a.warmup, a.max_it)
         line["mixed"] = {"value": unknowns / dt32, "ms_per_step": dt32 * 1e3,
                          "iters": [r.iters for r in r32], "relres": [r.relres for r in r32],
@@ -366,6 +430,7 @@ def main():
                          "speedup_vs_fp64": dt64 / dt32}
     if not a.no_batch:
         for name, inner in (("batched", mgcccs.FP64), ("batched_mixed", mgcccs.FP32)):
+            use_schedule(problems, inner, wls)
             dtb, rb = time_batch(problems, inner, torch, a.steps, a.warmup, a.max_it)
             line[name] = {"value": unknowns / dtb, "ms_per_step": dtb * 1e3,
                           "iters": [r.iters for r in rb], "relres": [r.relres for r in rb],
@@ -374,12 +439,15 @@ def main():
     if not a.no_sweep:
         line["sweep"] = time_sweep(problems[0], w0.E, torch)
     if not a.no_kernels:
+        use_schedule(problems, mgcccs.FP64, wls)
         line["kernels"] = per_kernel(problems, mgcccs.FP64, torch, a.max_it, PROBE_KERNELS)
     iters_needed = [r.iters for r in r64]
     del problems
     torch.cuda.empty_cache()
     if not a.no_c2:
         line["c2"] = c2_leg(torch, a.max_it)
+    if not a.no_c3:
+        line["c3"] = c3_leg(torch, a.max_it)
     if not a.no_hbm:
         line["hbm_4097"] = hbm_leg(torch, PROBE_KERNELS)
     if not a.no_cpu:

@@ -203,6 +203,7 @@ mgc_status mgc_vcycle(mgc_grid g, void* u, const void* f, mgc_precision prec);
 /* One Coupled Channel Correction Step in place on u (Sec. 4.3, eq. cccs).     */
 mgc_status mgc_cccs(mgc_grid g, void* u, const void* f, mgc_precision prec);
 
+
 /* Solve A u = f (FP64 level-0 fields).  u holds the initial guess on entry and
  * the last iterate on exit.  stats may be NULL.                               */
 mgc_status mgc_solve(mgc_grid g, void* u, const void* f,
@@ -234,6 +235,35 @@ mgc_status mgc_cross_section(mgc_grid g, const void* u, const void* chi,
  * pointer or a momentum that is not positive).  Synchronising.                */
 mgc_status mgc_cross_section_sweep(mgc_grid g, const void* u, const void* chi, int npairs,
                                    const double* k1, const double* k2, double* zeta, double* sigma);
+
+/* Most bound states one single-ionisation call evaluates. */
+#define MGC_SI_MAX 16
+
+/* Single-ionisation amplitudes (Sec. 3.3 eq. single-ionization):
+ *   s_n = sum_{j,k<=j0} t_j t_k phi_{k_n}(x1_j) phi_n(x2_k) (chi - V12 u)_{kj},
+ * n = 1 .. nstates, with phi_n the n-th lowest bound state of the exact x2
+ * one-body Hamiltonian -1/2 d2/dz2 - Z2/z (eq. 1d_eigenstate on the
+ * exterior-complex-scaled grid, bilinear normalisation, two shift-and-invert
+ * refinement steps), k_n = sqrt(2 (E - Re lambda_n)) and phi_{k_n} the test
+ * function of eq. testfunction in x1 (as in mgc_cross_section); t the
+ * trapezoid weights of the real region.  s: host array of 2 nstates doubles
+ * (Re, Im of s_n); kn: host array of nstates momenta, or NULL.  u, chi: FP64
+ * level-0 fields.  MGC_EINVAL for nstates outside [1, MGC_SI_MAX] (or not
+ * below n - 1) or a closed channel (E <= Re lambda_n).  One pass over the
+ * field for all states.  Synchronising.                                      */
+mgc_status mgc_single_ionization(mgc_grid g, const void* u, const void* chi, int nstates, double* s, double* kn);
+
+/* Total double-ionisation cross section (Sec. 3.3 eq. total-double-ionization)
+ *   sigma_tot(E) = int_0^E sigma(sqrt(2 eps), sqrt(2 (E - eps))) d eps
+ * with eps = E sin^2 a (k1 = sqrt(2E) sin a, k2 = sqrt(2E) cos a), where the
+ * Jacobian 2E sin a cos a cancels the 1/(k1 k2) of sigma:
+ *   sigma_tot = 8 pi^2 / k0^2 int_0^{pi/2} |zeta(k1(a), k2(a))|^2 da,
+ * by a nodes-point Gauss-Legendre rule in a (all amplitudes in one pass over
+ * the field).  zeta: host array of 2 nodes doubles receiving the amplitudes at
+ * the nodes (ascending a), or NULL.  MGC_EINVAL for nodes outside
+ * [1, MGC_SWEEP_MAX] or E <= 0.  Synchronising.                              */
+mgc_status mgc_total_double_ionization(mgc_grid g, const void* u, const void* chi, int nodes, double* sigma_tot,
+                                       double* zeta);
 
 /* Gradient of sigma(k1, k2) with respect to (Z1, Z2, lambda) for u = A^{-1} chi,
  * chi the Temkin-Poet right-hand side of mgc_build_rhs_tp (call order:
@@ -313,6 +343,14 @@ typedef struct mgc_batch_s* mgc_batch;
 mgc_status mgc_batch_create(const mgc_grid* grids, int count, mgc_batch* out);
 mgc_status mgc_batch_solve(mgc_batch b, void* const* u, const void* const* f,
                            const mgc_solve_opts* opts, mgc_stats* stats);
+/* The cross sections of every solve of a batch (the energies of a batch in
+ * one call): for handle i, sigma_tot[i] as mgc_total_double_ionization with
+ * `nodes` points (skipped for nodes = 0) and s[2 nstates i ..] as
+ * mgc_single_ionization with `nstates` states (skipped for nstates = 0).  The
+ * sweeps of the handles run concurrently on the batch's streams after the
+ * work already queued on the handles' streams; one synchronisation.        */
+mgc_status mgc_batch_cross_sections(mgc_batch b, const void* const* u, const void* const* chi, int nodes,
+                                    int nstates, double* sigma_tot, double* s);
 mgc_status mgc_batch_destroy(mgc_batch b);
 
 mgc_status mgc_destroy_grid(mgc_grid g);

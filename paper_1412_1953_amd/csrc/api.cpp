@@ -115,6 +115,9 @@ struct mgc_grid_s {
   size_t gm = 0;                           // GmresState arrays
   size_t zeta_f = 0, adj = 0;
   size_t sweep_f = 0, sweep_k = 0, sweep_part = 0, sweep_out = 0;   // mgc_cross_section_sweep
+  size_t si_tab = 0;                       // bound states of the exact x2 Hamiltonian (single ionisation)
+  int si_count = 0;                        // states held in si_tab (0: none for this potential)
+  std::vector<cd> si_lam;
   int nchunksB = 1;
   bool prec_on[2] = {true, false};
 
@@ -147,6 +150,26 @@ inline int pitch_for(int n) { return ((n + 1) + 15) / 16 * 16; }
 
 // --------------------------------------------------------------------------
 // workspace layout
+// The scratch of one CCCS application (partials, channel vectors) for
+// precision p, placed by take(bytes) -> offset.
+template <typename Take> void cccs_scratch_layout(const mgc_grid_s* g, int p, Take& take, CcOff& c) {
+  const int n = g->d.n, N = n - 1, M = g->d.M, Lc = g->d.Lch;
+  const size_t e = esize(p);
+  c.partA = take((size_t)g->nchunksB * (n + 1) * M * e);
+  c.partB = take((size_t)g->nchunksB * (n + 1) * Lc * e);
+  c.rhoA = take((size_t)(n + 1) * M * e);
+  c.rhoB = take((size_t)(n + 1) * Lc * e);
+  c.partC = take((size_t)launch_cccs_reduce_blocks(n) * M * Lc * e);
+  c.gA = take((size_t)N * M * e);
+  c.gB = take((size_t)N * Lc * e);
+  c.YA = take((size_t)g->PA * 2 * M * e);
+  c.YB = take((size_t)g->PB * 2 * Lc * e);
+  c.HA = take((size_t)g->PA * 4 * M * e);
+  c.HB = take((size_t)g->PB * 4 * Lc * e);
+  c.eA = take((size_t)(n + 1) * M * e);
+  c.eB = take((size_t)(n + 1) * Lc * e);
+}
+
 void layout(mgc_grid g) {
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -189,19 +212,7 @@ void layout(mgc_grid g) {
       };
       sys(c.A, M, g->PA);
       sys(c.B, Lc, g->PB);
-      c.partA = take((size_t)g->nchunksB * (n + 1) * M * e);
-      c.partB = take((size_t)g->nchunksB * (n + 1) * Lc * e);
-      c.rhoA = take((size_t)(n + 1) * M * e);
-      c.rhoB = take((size_t)(n + 1) * Lc * e);
-      c.partC = take((size_t)launch_cccs_reduce_blocks(n) * M * Lc * e);
-      c.gA = take((size_t)N * M * e);
-      c.gB = take((size_t)N * Lc * e);
-      c.YA = take((size_t)g->PA * 2 * M * e);
-      c.YB = take((size_t)g->PB * 2 * Lc * e);
-      c.HA = take((size_t)g->PA * 4 * M * e);
-      c.HB = take((size_t)g->PB * 4 * Lc * e);
-      c.eA = take((size_t)(n + 1) * M * e);
-      c.eB = take((size_t)(n + 1) * Lc * e);
+      cccs_scratch_layout(g, p, take, c);
     }
   }
   const int nc = g->lv.back().n, Nc = (nc - 1) * (nc - 1);
@@ -231,6 +242,7 @@ void layout(mgc_grid g) {
   g->sweep_part = take((size_t)zeta_sweep_blocks(n) * 2 * MGC_SWEEP_MAX * sizeof(double));
   g->sweep_out = take((size_t)2 * MGC_SWEEP_MAX * sizeof(double));
   g->sweep_k = take((size_t)2 * MGC_SWEEP_MAX * sizeof(double));
+  g->si_tab = take((size_t)MGC_SI_MAX * (n + 1) * 16);
   g->need = off;
 }
 
@@ -320,24 +332,24 @@ template <typename T> ChanSys<T> sys_of(mgc_grid g, bool A) {
   return o;
 }
 
-CccsScratch scratch_of(mgc_grid g, int p) {
-  const CcOff& c = g->cc[p];
+CccsScratch scratch_at(char* base, const CcOff& c) {
   CccsScratch w;
-  w.partA = g->ws + c.partA;
-  w.partB = g->ws + c.partB;
-  w.rhoA = g->ws + c.rhoA;
-  w.rhoB = g->ws + c.rhoB;
-  w.partC = g->ws + c.partC;
-  w.gA = g->ws + c.gA;
-  w.gB = g->ws + c.gB;
-  w.YA = g->ws + c.YA;
-  w.YB = g->ws + c.YB;
-  w.HA = g->ws + c.HA;
-  w.HB = g->ws + c.HB;
-  w.eA = g->ws + c.eA;
-  w.eB = g->ws + c.eB;
+  w.partA = base + c.partA;
+  w.partB = base + c.partB;
+  w.rhoA = base + c.rhoA;
+  w.rhoB = base + c.rhoB;
+  w.partC = base + c.partC;
+  w.gA = base + c.gA;
+  w.gB = base + c.gB;
+  w.YA = base + c.YA;
+  w.YB = base + c.YB;
+  w.HA = base + c.HA;
+  w.HB = base + c.HB;
+  w.eA = base + c.eA;
+  w.eB = base + c.eB;
   return w;
 }
+CccsScratch scratch_of(mgc_grid g, int p) { return scratch_at(g->ws, g->cc[p]); }
 
 // --------------------------------------------------------------------------
 // uploads
@@ -601,7 +613,8 @@ void vcycle_level(mgc_grid g, int l, void* u, const void* f, bool zero_guess, co
   if (cur != 0) launch_scale_copy<T, T>(s, L.n, L.pitch, L.pitch, bufs[cur], nullptr, u);
 }
 
-template <typename T> void cccs_apply(mgc_grid g, void* u, const void* f, const double* fs = nullptr) {
+template <typename T>
+void cccs_apply(mgc_grid g, void* u, const void* f, const double* fs = nullptr, const CccsScratch* ext = nullptr) {
   if (g->d.M == 0 && g->d.Lch == 0) return;
   const int p = sizeof(T) == 8 ? P64 : P32;
   // timed kernel: projection (reads u, f; writes rho^A, rho^B) or chunk chains
@@ -629,7 +642,7 @@ template <typename T> void cccs_apply(mgc_grid g, void* u, const void* f, const 
   hook.ctx = &ctx;
   hook.kind = slot >= 0 ? kind : 0;
   launch_cccs<T>(g->stream, level_of<T>(g, 0), u, f, fs, chan_of<T>(g), sys_of<T>(g, true),
-                 sys_of<T>(g, false), scratch_of(g, p), &hook);
+                 sys_of<T>(g, false), ext ? *ext : scratch_of(g, p), &hook);
 }
 
 // One MG-CCCS cycle.  fs (nullable device scalar) scales f; the fused
@@ -1048,6 +1061,7 @@ mgc_status mgc_set_potential(mgc_grid g, double Z1, double Z2, double lambda) {
   auto t0 = std::chrono::steady_clock::now();
   drop_graph(g);
   g->have_pot = g->have_energy = false;
+  g->si_count = 0;
   g->Z1 = Z1; g->Z2 = Z2; g->lam = lambda;
   const int n = g->d.n, M = g->d.M, Lc = g->d.Lch;
   std::string err;
@@ -1463,6 +1477,179 @@ mgc_status mgc_cross_section_grad(mgc_grid g, const void* u, const void* chi, do
   return solve_rc;
 }
 
+}  // extern "C"
+
+namespace {
+// Gauss-Legendre rule on [-1, 1] (ascending nodes): the roots of P_N, found by
+// Newton's method from x = cos(pi (i + 3/4) / (N + 1/2)), with P_N and P_N'
+// from the three-term recurrence (j+1) P_{j+1} = (2j+1) x P_j - j P_{j-1};
+// weights 2 / ((1 - x^2) P_N'(x)^2).
+void gauss_legendre(int N, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(N, 0.0);
+  w.assign(N, 0.0);
+  for (int i = 0; i < N; ++i) {
+    double r = std::cos(M_PI * (i + 0.75) / (N + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = r;
+      for (int j = 1; j < N; ++j) {
+        const double p2 = ((2.0 * j + 1.0) * r * p1 - j * p0) / (j + 1.0);
+        p0 = p1;
+        p1 = p2;
+      }
+      if (N == 1) { p1 = r; p0 = 1.0; }
+      dp = N * (r * p1 - p0) / (r * r - 1.0);
+      const double dr = p1 / dp;
+      r -= dr;
+      if (std::abs(dr) < 1e-16) break;
+    }
+    x[N - 1 - i] = r;                        // ascending nodes
+    w[N - 1 - i] = 2.0 / ((1.0 - r * r) * dp * dp);
+  }
+}
+
+// Bound states of the exact x2 Hamiltonian -1/2 d2/dz2 - Z2/z (the
+// one-body states phi_n of eq. single-ionization), held on the device for the
+// single-ionisation sweep; recomputed after set_potential.
+mgc_status ensure_si_states(mgc_grid g, int nstates) {
+  if (g->si_count >= nstates) return MGC_OK;
+  const Axis& ax = g->exact;
+  std::vector<std::vector<cd>> phi;
+  std::string err;
+  if (!bound_states(ax, one_body(ax, g->Z2), nstates, 2, g->si_lam, phi, err)) return fail(MGC_ENUMERIC, err);
+  std::vector<cd> tab((size_t)nstates * (ax.n + 1));
+  for (int q = 0; q < nstates; ++q)
+    for (int k = 0; k <= ax.n; ++k) tab[(size_t)q * (ax.n + 1) + k] = phi[q][k];
+  mgc_status rc = upload_cplx<double>(g, g->si_tab, tab);
+  if (rc) return rc;
+  g->si_count = nstates;
+  return MGC_OK;
+}
+
+// One amplitude sweep on stream st: weighted test functions (x1 side from
+// kk[0 .. npairs), x2 side from kk[npairs .. 2 npairs) unless `bound` asks for
+// the bound-state weights instead), the sweep over the field, and the copy of
+// the 2 pp amplitude doubles into out.  kk and out are host buffers that must
+// stay alive until st has synchronised.
+mgc_status enqueue_sweep(mgc_grid g, const void* u, const void* chi, int npairs, const double* kk, int bound,
+                         double* out, hipStream_t st) {
+  const Axis& ax = g->exact;
+  const int n = ax.n, top = std::min(ax.j0, n - 1);
+  const int pp = (npairs + 63) / 64 * 64;
+  double* F = g->at<double>(g->sweep_f);
+  HIPCHK(g, hipMemcpyAsync(g->ws + g->sweep_k, kk, (size_t)2 * npairs * sizeof(double), hipMemcpyHostToDevice, st));
+  launch_sweep_testfn(st, n, ax.j0, ax.h, g->Z1, npairs, pp, g->at<const double>(g->sweep_k), F);
+  if (bound > 0)
+    launch_bound_weights(st, n, top, ax.j0, ax.h, bound, pp, g->at<const double2>(g->si_tab), F + (size_t)(n + 1) * pp);
+  launch_zeta_sweep(st, n, g->lv[0].pitch, top, pp, exact_level(g).tm, F, F + (size_t)(n + 1) * pp,
+                    (const double2*)u, (const double2*)chi, g->at<double>(g->sweep_part), g->at<double>(g->sweep_out));
+  HIPCHK(g, hipGetLastError());
+  HIPCHK(g, hipMemcpyAsync(out, g->ws + g->sweep_out, (size_t)2 * pp * sizeof(double), hipMemcpyDeviceToHost, st));
+  return MGC_OK;
+}
+
+// Host staging of the cross sections of one handle.
+struct XsecJob {
+  int nstates = 0, nodes = 0;
+  std::vector<double> kk_si, out_si, kk_dd, out_dd, wq, kn;
+};
+
+// Validate and build the momenta of both sweeps (nstates may be 0, nodes may
+// be 0); enqueue them on st.
+mgc_status enqueue_xsec(mgc_grid g, const void* u, const void* chi, int nstates, int nodes, XsecJob& J,
+                        hipStream_t st) {
+  J.nstates = nstates;
+  J.nodes = nodes;
+  mgc_status rc;
+  if (nstates > 0) {
+    if ((rc = ensure_si_states(g, nstates))) return rc;
+    J.kn.assign(nstates, 0.0);
+    for (int q = 0; q < nstates; ++q) {
+      const double e = g->E - g->si_lam[q].real();
+      if (!(e > 0)) return fail(MGC_EINVAL, "single ionisation into state " + std::to_string(q + 1) +
+                                                " is closed at this energy (E <= lambda_n)");
+      J.kn[q] = std::sqrt(2.0 * e);
+    }
+    const int np = 2 * nstates;
+    J.kk_si.assign((size_t)2 * np, 1.0);               // x2 side: replaced by the bound states
+    for (int c = 0; c < np; ++c) J.kk_si[c] = J.kn[c / 2];
+    J.out_si.assign((size_t)2 * ((np + 63) / 64 * 64), 0.0);
+    if ((rc = enqueue_sweep(g, u, chi, np, J.kk_si.data(), nstates, J.out_si.data(), st))) return rc;
+  }
+  if (nodes > 0) {
+    if (!(g->E > 0)) return fail(MGC_EINVAL, "double ionisation needs E > 0");
+    std::vector<double> x, w;
+    gauss_legendre(nodes, x, w);
+    const double K = std::sqrt(2.0 * g->E);
+    J.kk_dd.assign((size_t)2 * nodes, 0.0);
+    J.wq.assign(nodes, 0.0);
+    for (int q = 0; q < nodes; ++q) {
+      const double a = (x[q] + 1.0) * M_PI / 4.0;
+      J.kk_dd[q] = K * std::sin(a);
+      J.kk_dd[nodes + q] = K * std::cos(a);
+      J.wq[q] = w[q] * M_PI / 4.0;
+    }
+    J.out_dd.assign((size_t)2 * ((nodes + 63) / 64 * 64), 0.0);
+    if ((rc = enqueue_sweep(g, u, chi, nodes, J.kk_dd.data(), 0, J.out_dd.data(), st))) return rc;
+  }
+  return MGC_OK;
+}
+
+// After the stream has synchronised: s_n from the pairs (2q: real part of
+// the bound state, 2q+1: imaginary part) and sigma_tot from the rule.
+void finish_xsec(mgc_grid g, const XsecJob& J, double* s, double* kn, double* sigma_tot, double* zeta) {
+  for (int q = 0; q < J.nstates; ++q) {
+    const double ar = J.out_si[4 * q], ai = J.out_si[4 * q + 1], br = J.out_si[4 * q + 2],
+                 bi = J.out_si[4 * q + 3];
+    if (s) {
+      s[2 * q] = ar - bi;                      // (a) + i (b), a and b complex
+      s[2 * q + 1] = ai + br;
+    }
+    if (kn) kn[q] = J.kn[q];
+  }
+  if (J.nodes > 0) {
+    double acc = 0.0;
+    for (int q = 0; q < J.nodes; ++q) {
+      const double zr = J.out_dd[2 * q], zi = J.out_dd[2 * q + 1];
+      acc += J.wq[q] * (zr * zr + zi * zi);
+      if (zeta) {
+        zeta[2 * q] = zr;
+        zeta[2 * q + 1] = zi;
+      }
+    }
+    const double k0sq = 2.0 * (g->E + 0.5 * g->Z1 * g->Z1);
+    if (sigma_tot) *sigma_tot = 8.0 * M_PI * M_PI / k0sq * acc;
+  }
+}
+}  // namespace
+
+extern "C" {
+
+mgc_status mgc_single_ionization(mgc_grid g, const void* u, const void* chi, int nstates, double* s, double* kn) {
+  mgc_status rc = check_ready(g);
+  if (rc) return rc;
+  if (!u || !chi || !s) return fail(MGC_EINVAL, "null argument");
+  if (nstates < 1 || nstates > MGC_SI_MAX || nstates > g->d.n - 2)
+    return fail(MGC_EINVAL, "nstates must lie in [1, MGC_SI_MAX] and below n - 1");
+  XsecJob J;
+  if ((rc = enqueue_xsec(g, u, chi, nstates, 0, J, g->stream))) return rc;
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  finish_xsec(g, J, s, kn, nullptr, nullptr);
+  return MGC_OK;
+}
+
+mgc_status mgc_total_double_ionization(mgc_grid g, const void* u, const void* chi, int nodes, double* sigma_tot,
+                                       double* zeta) {
+  mgc_status rc = check_ready(g);
+  if (rc) return rc;
+  if (!u || !chi || !sigma_tot) return fail(MGC_EINVAL, "null argument");
+  if (nodes < 1 || nodes > MGC_SWEEP_MAX) return fail(MGC_EINVAL, "nodes must lie in [1, MGC_SWEEP_MAX]");
+  XsecJob J;
+  if ((rc = enqueue_xsec(g, u, chi, 0, nodes, J, g->stream))) return rc;
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  finish_xsec(g, J, nullptr, nullptr, sigma_tot, zeta);
+  return MGC_OK;
+}
+
 mgc_status mgc_set_kernel_timer(mgc_grid g, int kernel_class) {
   if (!g) return fail(MGC_EINVAL, "null handle");
   if (kernel_class < MGC_KT_NONE || kernel_class > MGC_KT_CCCS_EXPAND)
@@ -1711,6 +1898,44 @@ mgc_status mgc_batch_solve(mgc_batch b, void* const* u, const void* const* f, co
   }
   if (first == MGC_ENUMERIC) return fail(MGC_ENUMERIC, "non-finite residual in a batched solve");
   if (first == MGC_ENOCONV) return fail(MGC_ENOCONV, "iteration limit reached in a batched solve");
+  return MGC_OK;
+}
+
+mgc_status mgc_batch_cross_sections(mgc_batch b, const void* const* u, const void* const* chi, int nodes,
+                                    int nstates, double* sigma_tot, double* s) {
+  if (!b || !u || !chi) return fail(MGC_EINVAL, "null argument");
+  if (nodes < 0 || nodes > MGC_SWEEP_MAX || nstates < 0 || nstates > MGC_SI_MAX || (nodes == 0 && nstates == 0))
+    return fail(MGC_EINVAL, "need 0 <= nodes <= MGC_SWEEP_MAX, 0 <= nstates <= MGC_SI_MAX, not both zero");
+  if ((nodes > 0 && !sigma_tot) || (nstates > 0 && !s)) return fail(MGC_EINVAL, "null output array");
+  const int nb = (int)b->g.size();
+  mgc_status rc;
+  for (int i = 0; i < nb; ++i) {
+    if ((rc = check_ready(b->g[i]))) return rc;
+    if (!u[i] || !chi[i]) return fail(MGC_EINVAL, "null field pointer in batch");
+    if (nstates > b->g[i]->d.n - 2) return fail(MGC_EINVAL, "nstates must lie below n - 1 on every grid");
+    if (nodes > 0 && !(b->g[i]->E > 0)) return fail(MGC_EINVAL, "double ionisation needs E > 0 on every grid");
+  }
+  constexpr int NS = mgc_batch_s::NSTREAMS;
+  mgc_grid g0 = b->g[0];
+  // the side streams start after the work already on the handles' streams
+  for (int i = 0; i < nb; ++i) {
+    if (!hip_ok(g0, hipEventRecord(b->start, b->g[i]->stream), "hipEventRecord")) return MGC_EHIP;
+    for (int k = 0; k < NS; ++k)
+      if (!hip_ok(g0, hipStreamWaitEvent(b->side[k], b->start, 0), "hipStreamWaitEvent")) return MGC_EHIP;
+  }
+  std::vector<XsecJob> jobs(nb);
+  for (int i = 0; i < nb; ++i) {
+    rc = enqueue_xsec(b->g[i], u[i], chi[i], nstates, nodes, jobs[i], b->side[i % NS]);
+    if (rc) {
+      for (int k = 0; k < NS; ++k) (void)hipStreamSynchronize(b->side[k]);
+      return rc;
+    }
+  }
+  for (int k = 0; k < NS; ++k)
+    if (!hip_ok(g0, hipStreamSynchronize(b->side[k]), "hipStreamSynchronize")) return MGC_EHIP;
+  for (int i = 0; i < nb; ++i)
+    finish_xsec(b->g[i], jobs[i], nstates > 0 ? s + (size_t)2 * nstates * i : nullptr, nullptr,
+                nodes > 0 ? sigma_tot + i : nullptr, nullptr);
   return MGC_OK;
 }
 

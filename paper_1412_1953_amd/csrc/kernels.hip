@@ -8,6 +8,8 @@
 // Reductions are deterministic: per-block partial sums in a fixed order
 // (wave shuffles, then LDS), then a second single-block pass.  No floating
 // point atomics are used anywhere.
+#include <algorithm>
+
 #include "device.h"
 #include "launch.h"
 
@@ -2947,6 +2949,29 @@ void launch_sweep_testfn(hipStream_t s, int n, int j0, double h, double Z1, int 
                          double* F) {
   hipLaunchKernelGGL(k_sweep_testfn, dim3((2 * pp + 63) / 64), dim3(64), 0, s, n, j0, h, Z1, npairs, pp, kk, F);
 }
+// x2 side of the single-ionisation sweep: F2[k][2q + part] = t_k * (Re, Im)
+// of the bound state q at node k (t the trapezoid weights of the real region:
+// h, h/2 at j0), zero outside 1 .. top and for the padding pairs.
+__global__ void __launch_bounds__(256) k_bound_weights(int n, int top, int j0, double h, int nstates, int pp,
+                                                      const double2* __restrict__ tab, double* __restrict__ F2) {
+  const size_t total = (size_t)(n + 1) * pp;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (size_t)gridDim.x * 256) {
+    const int k = (int)(i / pp), c = (int)(i - (size_t)k * pp), q = c >> 1;
+    double v = 0.0;
+    if (k >= 1 && k <= top && q < nstates) {
+      const double2 b = tab[(size_t)q * (n + 1) + k];
+      v = (k == j0 ? 0.5 * h : h) * ((c & 1) ? b.y : b.x);
+    }
+    F2[i] = v;
+  }
+}
+void launch_bound_weights(hipStream_t s, int n, int top, int j0, double h, int nstates, int pp, const double2* tab,
+                          double* F2) {
+  const size_t total = (size_t)(n + 1) * pp;
+  const int blocks = (int)std::min<size_t>(1024, (total + 255) / 256);
+  hipLaunchKernelGGL(k_bound_weights, dim3(blocks), dim3(256), 0, s, n, top, j0, h, nstates, pp, tab, F2);
+}
+
 void launch_zeta_sweep(hipStream_t s, int n, int pitch, int top, int pp, const double2* tm, const double* F1T,
                        const double* F2T, const double2* u, const double2* chi, double* part, double* out) {
   hipLaunchKernelGGL(k_zeta_sweep_part, dim3((top + SWR - 1) / SWR, SWJ), dim3(pp), 0, s, n, pitch, top, pp, tm,

@@ -159,6 +159,11 @@ int zeta_sweep_blocks(int top);
 // zero for the padding pairs npairs .. pp - 1.  Needs 1 <= j0 and n >= 2.
 void launch_sweep_testfn(hipStream_t s, int n, int j0, double h, double Z1, int npairs, int pp, const double* kk,
                          double* F);
+// The x2 side of the single-ionisation sweep from the bound states tab
+// ([state][n+1] complex): F2[k][2q] = t_k Re tab_q(k), F2[k][2q+1] = t_k Im
+// tab_q(k) on rows 1 .. top, zero elsewhere and for pairs >= 2 nstates.
+void launch_bound_weights(hipStream_t s, int n, int top, int j0, double h, int nstates, int pp, const double2* tab,
+                          double* F2);
 void launch_zeta_sweep(hipStream_t s, int n, int pitch, int top, int pp, const double2* tm, const double* F1T,
                        const double* F2T, const double2* u, const double2* chi, double* part, double* out);
 

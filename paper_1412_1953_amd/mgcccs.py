@@ -27,7 +27,8 @@ EXPORTED = ["mgc_create_grid", "mgc_workspace_bytes", "mgc_bind_workspace", "mgc
             "mgc_cccs", "mgc_solve", "mgc_solve_transpose", "mgc_cross_section",
             "mgc_cross_section_sweep", "mgc_cross_section_grad", "mgc_set_kernel_timer", "mgc_read_kernel_timer",
             "mgc_batch_create", "mgc_batch_solve", "mgc_batch_destroy",
-            "mgc_set_schedule", "mgc_get_schedule", "mgc_destroy_grid", "mgc_last_error"]
+            "mgc_set_schedule", "mgc_get_schedule", "mgc_single_ionization",
+            "mgc_total_double_ionization", "mgc_batch_cross_sections", "mgc_destroy_grid", "mgc_last_error"]
 
 # kernel classes of mgc_set_kernel_timer
 (KT_NONE, KT_APPLY_DOT, KT_AXPY, KT_S1, KT_S2, KT_CCCS_PROJECT, KT_CCCS_CHAIN, KT_S1_FINE, KT_S2_FINE,
@@ -101,6 +102,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mgc_batch_solve": [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(SolveOpts),
                             ctypes.POINTER(Stats)],
         "mgc_batch_destroy": [vp],
+        "mgc_single_ionization": [vp, vp, vp, i, ctypes.POINTER(d), ctypes.POINTER(d)],
+        "mgc_total_double_ionization": [vp, vp, vp, i, ctypes.POINTER(d), ctypes.POINTER(d)],
+        "mgc_batch_cross_sections": [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i, i, ctypes.POINTER(d),
+                                     ctypes.POINTER(d)],
         "mgc_set_schedule": [vp, ctypes.POINTER(Schedule)],
         "mgc_get_schedule": [vp, ctypes.POINTER(Schedule)],
         "mgc_destroy_grid": [vp],
@@ -335,6 +340,21 @@ class Grid:
         _check(self.lib.mgc_cross_section_sweep(self.h, self._ptr(u), self._ptr(chi), npairs, a1, a2, z, sig))
         return [complex(z[2 * a], z[2 * a + 1]) for a in range(npairs)], [sig[a] for a in range(npairs)]
 
+    def single_ionization(self, u, chi, nstates):
+        """(s_n for n = 1..nstates, k_n): single-ionisation amplitudes (Sec. 3.3)."""
+        s = (ctypes.c_double * (2 * nstates))()
+        kn = (ctypes.c_double * nstates)()
+        _check(self.lib.mgc_single_ionization(self.h, self._ptr(u), self._ptr(chi), nstates, s, kn))
+        return [complex(s[2 * q], s[2 * q + 1]) for q in range(nstates)], [kn[q] for q in range(nstates)]
+
+    def total_double_ionization(self, u, chi, nodes=32):
+        """(sigma_tot, zeta at the Gauss-Legendre angles, ascending) (Sec. 3.3)."""
+        sig = ctypes.c_double()
+        z = (ctypes.c_double * (2 * nodes))()
+        _check(self.lib.mgc_total_double_ionization(self.h, self._ptr(u), self._ptr(chi), nodes,
+                                                    ctypes.byref(sig), z))
+        return sig.value, [complex(z[2 * q], z[2 * q + 1]) for q in range(nodes)]
+
 
 def sharing_momenta(E_excess: float, alphas):
     """Momentum pairs k1 = K cos a, k2 = K sin a of an energy-sharing sweep,
@@ -366,6 +386,20 @@ class Batch:
         if h is not None and h.value:
             self.lib.mgc_batch_destroy(h)
             self.h = None
+
+    def cross_sections(self, us, chis, nodes=32, nstates=0):
+        """(sigma_tot per solve or None, s_n per solve or None) for every
+        handle of the batch in one call (mgc_batch_cross_sections)."""
+        nb = len(self.grids)
+        up = (ctypes.c_void_p * nb)(*[g._ptr(x).value for g, x in zip(self.grids, us)])
+        cp = (ctypes.c_void_p * nb)(*[g._ptr(x).value for g, x in zip(self.grids, chis)])
+        sig = (ctypes.c_double * max(nb, 1))()
+        s = (ctypes.c_double * max(2 * nstates * nb, 1))()
+        _check(self.lib.mgc_batch_cross_sections(self.h, up, cp, nodes, nstates, sig, s))
+        sigs = [sig[i] for i in range(nb)] if nodes > 0 else None
+        ss = ([[complex(s[2 * nstates * i + 2 * q], s[2 * nstates * i + 2 * q + 1]) for q in range(nstates)]
+               for i in range(nb)] if nstates > 0 else None)
+        return sigs, ss
 
     def solve(self, us, fs, inner=FP32, restart=10, max_it=20000, tol=1e-10, hist_cap=4096):
         """Solve grids[i] u_i = f_i for all i; returns one SolveResult each."""

@@ -4,7 +4,8 @@
 // (one line per solve: n L E M levels), runs mgc_batch_solve over several
 // restart rounds in which the solves finish at different rounds, runs each
 // solve alone with mgc_solve, runs the batch again with an iteration limit
-// between the solves' needs, and destroys everything.  Exit status 0 and no
+// between the solves' needs, takes the cross sections of every energy in one
+// batched call, and destroys everything.  Exit status 0 and no
 // sanitizer report mean the host code touched only memory it owned.
 #include <sys/mman.h>
 
@@ -154,6 +155,10 @@ int main(int argc, char** argv) {
   int stopped = 0;
   for (int i = 0; i < nb; ++i) stopped += st[i].relres > o.tol;
   std::printf("limited batch: %d of %d stopped at the limit\n", stopped, nb);
+  // cross sections of every energy of the batch in one call
+  std::vector<double> sig(nb), sn((size_t)nb * 2 * 2);
+  CHECK(mgc_batch_cross_sections(b, up.data(), fp.data(), 24, 2, sig.data(), sn.data()));
+  std::printf("batch cross sections done\n");
   CHECK(mgc_batch_destroy(b));
   for (int i = 0; i < nb; ++i) {
     CHECK(mgc_destroy_grid(g[i]));

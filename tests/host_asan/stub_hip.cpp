@@ -339,6 +339,7 @@ void launch_zeta_part(hipStream_t s, int, int, int, const double2*, const double
   MGC_NOP(s);
 }
 void launch_sweep_testfn(hipStream_t s, int, int, double, double, int, int, const double*, double*) { MGC_NOP(s); }
+void launch_bound_weights(hipStream_t s, int, int, int, double, int, int, const double2*, double*) { MGC_NOP(s); }
 void launch_zeta_sweep(hipStream_t s, int, int, int, int, const double2*, const double*, const double*,
                        const double2*, const double2*, double*, double* out) {
   MGC_NOP(s);

@@ -123,14 +123,12 @@ def test_batch_of_64_mixed_size_solves():
     checked by the oracle's operator; batch time against one-by-one solves.
     The host bookkeeping of this batch runs clean under AddressSanitizer
     (tests/test_host_asan.py)."""
-    from paper_1412_1953_amd import mgcccs
+    from paper_1412_1953_amd import autotune, mgcccs
     wls = batch_workloads()
     t0 = time.perf_counter()
     grids, chis, us = [], [], []
     for w in wls:
-        g = mgcccs.Grid.from_workload(w, max_restart=10, fp32=True)
-        g.set_potential(w.Z1, w.Z2, w.lam)
-        g.set_energy(w.E)
+        g = autotune.tuned_grid(w, fp32_cycle=True, max_restart=10, fp32=True)
         grids.append(g)
         chis.append(g.build_rhs_tp(g.field()))
     t_setup = time.perf_counter() - t0
@@ -174,7 +172,7 @@ def test_batch_of_mixed_sizes_against_one_by_one():
     1025^2; FP32 cycle in FP64 FGMRES): every solve to 1e-10 and bit-equal to
     its individual solve; batch wall time against the same solves one by one."""
     import torch
-    from paper_1412_1953_amd import mgcccs
+    from paper_1412_1953_amd import autotune, mgcccs
     from paper_1412_1953_amd.workloads import initial_guess
     wls = batch_workloads()
     pick = []
@@ -182,9 +180,7 @@ def test_batch_of_mixed_sizes_against_one_by_one():
         pick += [w for w in wls if w.n == n][:4]
     grids, chis = [], []
     for w in pick:
-        g = mgcccs.Grid.from_workload(w, max_restart=10, fp32=True)
-        g.set_potential(w.Z1, w.Z2, w.lam)
-        g.set_energy(w.E)
+        g = autotune.tuned_grid(w, fp32_cycle=True, max_restart=10, fp32=True)
         grids.append(g)
         chis.append(g.build_rhs_tp(g.field()))
     us = [g.from_numpy(initial_guess(w.n, w.seed)) for g, w in zip(grids, pick)]

@@ -22,10 +22,11 @@ from paper_1412_1953_amd.workloads import TP1025, TP2049, TP1025_GRAD
 
 pytestmark = pytest.mark.gpu
 def case_of(w):
-    """The workload with its own preconditioning hierarchy (exact level 0,
-    rotated contour from pc_first_level on)."""
+    """The workload with its tuned preconditioning hierarchy (autotuner
+    cache; the workload's defaults where there is no entry)."""
+    from paper_1412_1953_amd import autotune
     return Case(w.n, w.L, w.E, w.levels, w.M, theta=w.theta, R0frac=w.R0 / w.L, seed=w.seed,
-                pc_gamma=w.pc_gamma, pc_first_level=w.pc_first_level, pc_gamma0=w.pc_gamma0)
+                **autotune.hierarchy_of(w))
 
 
 @pytest.fixture(scope="module")

@@ -218,8 +218,8 @@ def test_small_workload_129_as_specified():
     the sparse direct solution to within the conditioning times 1e-8."""
     from paper_1412_1953_amd import mgcccs
     from paper_1412_1953_amd.workloads import SMALL_129 as w
-    c = Case(w.n, w.L, w.E, w.levels, w.M, pc_gamma=w.pc_gamma, pc_first_level=w.pc_first_level,
-             pc_gamma0=w.pc_gamma0, seed=w.seed)
+    from paper_1412_1953_amd import autotune
+    c = Case(w.n, w.L, w.E, w.levels, w.M, seed=w.seed, **autotune.hierarchy_of(w))
     g = c.grid()
     o = c.oracle()
     n = c.n
