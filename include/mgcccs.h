@@ -203,6 +203,22 @@ mgc_status mgc_vcycle(mgc_grid g, void* u, const void* f, mgc_precision prec);
 /* One Coupled Channel Correction Step in place on u (Sec. 4.3, eq. cccs).     */
 mgc_status mgc_cccs(mgc_grid g, void* u, const void* f, mgc_precision prec);
 
+/* mgc_cccs for callers that cannot allocate device memory -- code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  It
+ * allocates nothing, neither itself nor through a library: the CCCS scratch
+ * (projection partials, channel right-hand sides and solutions, about
+ * (2 ceil((n-1)/64) + 7) (n+1) M complex values for M = Lch) lives in a
+ * static device array of MGC_NOALLOC_SCRATCH_BYTES that each GPU the library
+ * runs on holds until the process ends.  The handle's bound workspace still
+ * provides the setup data (bound states, channel factors).  The region a call
+ * uses is cleared by a fill kernel on the handle's stream before use, so the
+ * array's previous contents never matter; calls that overlap on one GPU (two
+ * streams, two threads) share the array and race.  Same arguments, results
+ * and errors as mgc_cccs, plus MGC_EINVAL when the scratch of this grid and
+ * precision exceeds MGC_NOALLOC_SCRATCH_BYTES (n = 1024 with 16 channels in
+ * FP64 fits) and MGC_EHIP when the array's device address cannot be taken.   */
+#define MGC_NOALLOC_SCRATCH_BYTES (16u << 20)
+mgc_status mgc_cccs_noalloc(mgc_grid g, void* u, const void* f, mgc_precision prec);
 
 /* Solve A u = f (FP64 level-0 fields).  u holds the initial guess on entry and
  * the last iterate on exit.  stats may be NULL.                               */

@@ -5,7 +5,7 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "api.cpp", "setup.cpp")]
+SRC = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "noalloc.hip", "api.cpp", "setup.cpp")]
 OUT = os.path.join(HERE, "libmgcccs.so")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # packed FP32 instructions are disabled on purpose: the compiler must

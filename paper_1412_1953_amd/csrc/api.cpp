@@ -13,6 +13,7 @@
 #include <string>
 #include <vector>
 
+#include "internal.h"
 #include "launch.h"
 #include "setup.h"
 
@@ -1277,6 +1278,44 @@ mgc_status mgc_cccs(mgc_grid g, void* u, const void* f, mgc_precision prec) {
   HIPCHK(g, hipGetLastError());
   return MGC_OK;
 }
+
+}  // extern "C"
+
+namespace mgc {
+// mgc_cccs with its scratch (partials, channel vectors) at `scratch`, a
+// device buffer of `bytes` bytes (the no-allocation entry point passes the
+// library's static array); the region used is cleared first by a fill
+// kernel.  MGC_EINVAL if it does not fit.
+mgc_status cccs_with_scratch(mgc_grid g, void* u, const void* f, mgc_precision prec, void* scratch, size_t bytes) {
+  mgc_status rc = check_ready(g);
+  if (rc) return rc;
+  if (!u || !f || u == f) return fail(MGC_EINVAL, "bad field pointers");
+  if (prec != MGC_FP64 && !g->prec_on[P32]) return fail(MGC_EINVAL, "FP32 not enabled in the descriptor");
+  if (g->d.M == 0 && g->d.Lch == 0) return MGC_OK;
+  const int p = prec == MGC_FP64 ? P64 : P32;
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    size_t o = off;
+    off = align256(off + b);
+    return o;
+  };
+  CcOff c;
+  cccs_scratch_layout(g, p, take, c);
+  if (off > bytes)
+    return fail(MGC_EINVAL, "CCCS scratch of this grid (" + std::to_string(off) + " bytes) exceeds the " +
+                                std::to_string(bytes) + "-byte static scratch");
+  launch_fill_zero(g->stream, scratch, off);
+  const CccsScratch w = scratch_at(static_cast<char*>(scratch), c);
+  if (p == P64) cccs_apply<double>(g, u, f, nullptr, &w);
+  else cccs_apply<float>(g, u, f, nullptr, &w);
+  HIPCHK(g, hipGetLastError());
+  return MGC_OK;
+}
+int handle_device(mgc_grid g) { return g->device; }
+mgc_status set_error(mgc_status s, const char* msg) { return fail(s, msg); }
+}  // namespace mgc
+
+extern "C" {
 
 static mgc_status validate_opts(mgc_grid g, const mgc_solve_opts* o) {
   if (!o) return fail(MGC_EINVAL, "null options");

@@ -27,7 +27,7 @@ EXPORTED = ["mgc_create_grid", "mgc_workspace_bytes", "mgc_bind_workspace", "mgc
             "mgc_cccs", "mgc_solve", "mgc_solve_transpose", "mgc_cross_section",
             "mgc_cross_section_sweep", "mgc_cross_section_grad", "mgc_set_kernel_timer", "mgc_read_kernel_timer",
             "mgc_batch_create", "mgc_batch_solve", "mgc_batch_destroy",
-            "mgc_set_schedule", "mgc_get_schedule", "mgc_single_ionization",
+            "mgc_set_schedule", "mgc_get_schedule", "mgc_cccs_noalloc", "mgc_single_ionization",
             "mgc_total_double_ionization", "mgc_batch_cross_sections", "mgc_destroy_grid", "mgc_last_error"]
 
 # kernel classes of mgc_set_kernel_timer
@@ -88,6 +88,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mgc_residual": [vp, vp, vp, vp, ctypes.POINTER(d), i],
         "mgc_vcycle": [vp, vp, vp, i],
         "mgc_cccs": [vp, vp, vp, i],
+        "mgc_cccs_noalloc": [vp, vp, vp, i],
         "mgc_solve": [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(Stats)],
         "mgc_solve_transpose": [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(Stats)],
         "mgc_cross_section": [vp, vp, vp, d, d, ctypes.POINTER(d), ctypes.POINTER(d)],
@@ -260,6 +261,11 @@ class Grid:
     def cccs(self, u, f):
         p = self._prec(u)
         _check(self.lib.mgc_cccs(self.h, self._ptr(u, p), self._ptr(f, p), p))
+
+    def cccs_noalloc(self, u, f):
+        """mgc_cccs with its scratch in the library's static device array."""
+        p = self._prec(u)
+        _check(self.lib.mgc_cccs_noalloc(self.h, self._ptr(u, p), self._ptr(f, p), p))
 
     def _solve(self, fn, u, f, outer, inner, restart, max_it, inner_cycles, tol, hist_cap):
         opts = SolveOpts(outer, inner, restart, max_it, inner_cycles, tol)
