@@ -1,6 +1,8 @@
 """Outer iterations around one MG-CCCS cycle (TEST INFRASTRUCTURE ONLY).
 
 * Stationary MG-CCCS: repeat {V-cycle; CCCS} (Sec. 6.1).
+* BiCGSTAB right-preconditioned by one MG-CCCS cycle from zero (Sec. 6.1,
+  Fig. convrate2D).
 * FGMRES(m) right-preconditioned by one MG-CCCS cycle from a zero guess per
   preconditioner application (Sec. 6; Table 1), classical Gram-Schmidt with
   one re-orthogonalisation, Givens rotations, true residual at every restart.
@@ -44,8 +46,10 @@ class MGCCCS:
 
     def __init__(self, n, L, R0, theta, Z1, Z2, lam, E, levels, M,
                  omega=2.0 / 3.0, nu1=1, nu2=1, Lch=None, refine_steps=2,
-                 pc_gamma=0.0, pc_first_level=0, pc_gamma0=0.0):
-        self.g = Grid1D(n, L, R0, theta)
+                 pc_gamma=0.0, pc_first_level=0, pc_gamma0=0.0, gamma=0.0):
+        # gamma: contour angle of the system itself (Sec. 3.1; 0 = the
+        # exterior-complex-scaled grid with a real interior)
+        self.g = Grid1D(n, L, R0, theta, gamma)
         self.Z1, self.Z2, self.lam, self.E = Z1, Z2, lam, E
         gammas = [pc_gamma if l >= pc_first_level else pc_gamma0 for l in range(levels)]
         self.mg = Hierarchy(self.g, Z1, Z2, lam, E, levels, omega, nu1, nu2, gammas)
@@ -79,7 +83,7 @@ class MGCCCS:
     # ------------------------------------------------------------------ #
     def solve_stationary(self, u, f, tol, max_it=200) -> SolveResult:
         """Repeat the cycle on the exact system (needs an exact level 0)."""
-        if self.pc_op.g.gamma != 0.0:
+        if self.pc_op.g.gamma != self.g.gamma:
             raise ValueError("stationary iteration needs the exact level-0 operator")
         hist = [rel_residual(self.op, u, f)]
         it = 0
@@ -144,6 +148,58 @@ class MGCCCS:
             if not np.isfinite(hist[-1]):
                 break
         return SolveResult(u, hist[-1], it, it, hist)
+
+    def solve_bicgstab(self, u, f, tol, max_it=500) -> SolveResult:
+        """BiCGSTAB (van der Vorst's stabilised bi-conjugate gradients) on the
+        system, right-preconditioned by one MG-CCCS cycle from zero per
+        application (Sec. 6.1, Fig. convrate2D), with the shadow vector equal
+        to the initial residual and conjugated inner products.  One iteration
+        applies the operator and the preconditioner twice:
+            rho = (r~, r);  beta = (rho / rho_old)(alpha / omega)
+            p = r + beta (p - omega v);  p^ = B p;  v = A p^
+            alpha = rho / (r~, v);  s = r - alpha v
+            s^ = B s;  t = A s^;  omega = (t, s) / (t, t)
+            u += alpha p^ + omega s^;  r = s - omega t
+        history: ||r||/||f|| of the recurred residual at the start and after
+        every iteration; the final relres is recomputed from u."""
+        op = self.op
+        fn = np.linalg.norm(f)
+        r = op.residual(u, f)
+        rt = r.copy()
+        hist = [np.linalg.norm(r) / fn]
+        p = np.zeros_like(r)
+        v = np.zeros_like(r)
+        rho_old = alpha = omega = 1.0
+        it = 0
+
+        def apply(x):
+            y = op.apply(x)
+            y[0, :] = y[-1, :] = y[:, 0] = y[:, -1] = 0
+            return y
+
+        while hist[-1] > tol and it < max_it:
+            rho = np.vdot(rt, r)
+            beta = (rho / rho_old) * (alpha / omega)
+            p = r + beta * (p - omega * v)
+            ph = self.precondition(p)
+            v = apply(ph)
+            alpha = rho / np.vdot(rt, v)
+            s = r - alpha * v
+            it += 1
+            if np.linalg.norm(s) / fn <= tol:
+                u = u + alpha * ph
+                hist.append(np.linalg.norm(s) / fn)
+                break
+            sh = self.precondition(s)
+            t = apply(sh)
+            omega = np.vdot(t, s) / np.vdot(t, t)
+            u = u + alpha * ph + omega * sh
+            r = s - omega * t
+            rho_old = rho
+            hist.append(np.linalg.norm(r) / fn)
+            if not np.isfinite(hist[-1]):
+                break
+        return SolveResult(u, rel_residual(op, u, f), it, 2 * it, hist)
 
     def solve_ir(self, u, f, tol, inner_cycles=2, max_it=200) -> SolveResult:
         op = self.op

@@ -258,6 +258,68 @@ def test_refinement_step_equals_stationary_cycles(k):
     assert np.abs(bad - ref).max() > 1e-2 * np.abs(ref).max()
 
 
+# ---------------------------------------------------------------- BiCGSTAB --
+def _bicg_case():
+    n = 32
+    s = MGCCCS(n, 10.0, 7.5, math.pi / 6, 1.0, 1.0, 1.0, 0.4, 3, 3, pc_gamma=math.radians(10))
+    return n, s, s.rhs(), initial_guess(n, 1)
+
+
+def test_bicgstab_iterates_equal_scipys_right_preconditioned_bicgstab():
+    """Sec. 6.1 / Fig. convrate2D: MG-CCCS-preconditioned BiCGSTAB.  scipy's
+    bicgstab applies its preconditioner M on the right (p^ = M p, v = A p^),
+    with conjugated inner products and the initial residual as shadow vector:
+    given the MG-CCCS cycle as M, its iterates are the oracle's to round-off.
+    A planted mistake (unconjugated inner products) is not."""
+    import scipy.sparse.linalg as spla
+    n, s, f, u0 = _bicg_case()
+    N = (n - 1) ** 2
+
+    def prec(x):
+        X = np.zeros((n + 1, n + 1), complex)
+        X[1:n, 1:n] = x.reshape(n - 1, n - 1)
+        return s.precondition(X)[1:n, 1:n].ravel()
+
+    M = spla.LinearOperator((N, N), matvec=prec, dtype=complex)
+    its = []
+    spla.bicgstab(s.op.sparse(), f[1:n, 1:n].ravel(), x0=u0[1:n, 1:n].ravel(), M=M, maxiter=6, rtol=1e-300,
+                  atol=0, callback=lambda x: its.append(x.copy()))
+    r = s.solve_bicgstab(u0, f, 1e-300, max_it=6)
+    assert len(its) == 6 and r.iters == 6
+    ref = its[-1]
+    assert np.linalg.norm(r.u[1:n, 1:n].ravel() - ref) < 1e-12 * np.linalg.norm(ref)
+    import oracle.solvers as so
+    real_vdot = so.np.vdot
+    try:
+        so.np.vdot = lambda a, b: np.sum(np.ravel(a) * np.ravel(b))      # planted: no conjugation
+        bad = s.solve_bicgstab(u0, f, 1e-300, max_it=6)
+    finally:
+        so.np.vdot = real_vdot
+    assert np.linalg.norm(bad.u[1:n, 1:n].ravel() - ref) > 1e-6 * np.linalg.norm(ref)
+
+
+def test_bicgstab_converges_to_the_dense_direct_solution():
+    n, s, f, u0 = _bicg_case()
+    x = np.linalg.solve(s.op.sparse().toarray(), f[1:n, 1:n].ravel())
+    r = s.solve_bicgstab(u0, f, 1e-12, max_it=200)
+    assert r.relres <= 1e-11 and r.vcycles == 2 * r.iters
+    assert np.linalg.norm(r.u[1:n, 1:n].ravel() - x) / np.linalg.norm(x) < 1e-10
+
+
+def test_full_contour_hydrogen_levels_are_real_at_second_order():
+    """Sec. 3.1: on a fully rotated contour z = x e^{i gamma} (no real part
+    left, R0 = L) the bound states of -1/2 d2/dz2 - 1/z stay the real levels
+    -1/(2 n^2): the discrete eigenvalues converge to them at O(h^2), their
+    imaginary parts included."""
+    errs = []
+    for n in (256, 512, 1024):
+        g = Grid1D(n, 40.0, 40.0, math.pi / 6, math.radians(10.0))
+        lam, _ = bound_states(g, tp_one_body(g, 1.0), 2)
+        errs.append(abs(lam[0] + 0.5))
+        assert abs(lam[1] + 0.125) < 0.02
+    assert 3.6 < errs[0] / errs[1] < 4.4 and 3.6 < errs[1] / errs[2] < 4.4, errs
+
+
 # ---------------------------------------------------------------- P7 -------
 def test_separable_case_matches_fast_diagonalisation():
     """lambda = 0: A = H1 (x) I + I (x) H2 - E is separable, solved exactly by
