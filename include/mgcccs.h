@@ -68,8 +68,13 @@ typedef enum { MGC_FP64 = 0, MGC_FP32 = 1 } mgc_precision;
 typedef enum {
   MGC_STATIONARY = 0, /* repeat {V-cycle; CCCS} on A u = f (Sec. 6.1)          */
   MGC_IR = 1,         /* FP64 iterative refinement around inner MG-CCCS cycles */
-  MGC_FGMRES = 2      /* FP64 FGMRES(restart), right-preconditioned by one
+  MGC_FGMRES = 2,     /* FP64 FGMRES(restart), right-preconditioned by one
                          MG-CCCS cycle started from zero (Sec. 6, Table 1)      */
+  MGC_BICGSTAB = 3    /* FP64 BiCGSTAB right-preconditioned by one MG-CCCS cycle
+                         from zero (Sec. 6.1, Fig. convrate2D): shadow vector =
+                         initial residual, conjugated inner products; two
+                         cycles per iteration.  Needs desc.max_restart >= 5
+                         (its six vectors live in the Krylov basis).            */
 } mgc_outer;
 
 typedef struct mgc_grid_s* mgc_grid;   /* opaque, library-owned host object */
@@ -94,7 +99,12 @@ typedef struct mgc_grid_s* mgc_grid;   /* opaque, library-owned host object */
  *          level the exact operator.  Both angles lie in [0, pi/4).  The
  *          CCCS acts on the level-0 operator of the hierarchy.
  * max_restart  FGMRES basis size the workspace must hold, 0 .. MGC_MAX_RESTART
- *              (0: no FGMRES).
+ *              (0: no FGMRES; BiCGSTAB needs at least 5).
+ * gamma    contour angle of the system itself, [0, pi/4): the operator A is
+ *          discretised on z = x e^{i gamma} for x <= R0 followed by the ECS ray
+ *          (0: the exterior-complex-scaled grid with a real interior; R0 = L
+ *          with gamma > 0: the full complex contour of Sec. 3.1 / Sec. 6).
+ *          The amplitude and cross-section calls need gamma = 0.
  * precisions   bit mask (1 << MGC_FP64) | (1 << MGC_FP32) of the cycle
  *          precisions the workspace must hold.                                */
 typedef struct {
@@ -109,6 +119,7 @@ typedef struct {
   int max_restart;
   int precisions;
   double pc_gamma0;
+  double gamma;
 } mgc_grid_desc;
 
 typedef struct {

@@ -91,6 +91,7 @@ struct mgc_grid_s {
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;               // capture stream (default priority)
   GraphCache graph;
+  GraphCache bicg_graph;                   // one captured BiCGSTAB iteration
   KernelTimer kt;
   int device = 0;
   bool failed = false;
@@ -145,6 +146,8 @@ bool hip_ok(mgc_grid g, hipError_t e, const char* what) {
 void drop_graph(mgc_grid g) {
   if (g->graph.exec) (void)hipGraphExecDestroy(g->graph.exec);
   g->graph = GraphCache();
+  if (g->bicg_graph.exec) (void)hipGraphExecDestroy(g->bicg_graph.exec);
+  g->bicg_graph = GraphCache();
 }
 
 inline int pitch_for(int n) { return ((n + 1) + 15) / 16 * 16; }
@@ -890,6 +893,111 @@ mgc_status solve_fgmres(mgc_grid g, void* u, const void* f, const mgc_solve_opts
   return finish_status(rel, o->tol);
 }
 
+// ---- BiCGSTAB ---------------------------------------------------------------
+// Vectors in the Krylov basis W: r, r~, p, v, s, t (FP64); p^, s^ in Z (the
+// inner precision).  Scalars in scal[BICG ..], the per-iteration report
+// (||r||^2, ||s||^2, converged) in scal[BICG + 16 ..].
+constexpr int BICG = 64;
+void enqueue_bicg_iteration(mgc_grid g, void* u, const mgc_solve_opts* o, double tol2, hipStream_t st) {
+  const int n = g->d.n, pitch = g->lv[0].pitch;
+  const bool f32 = o->inner == MGC_FP32;
+  const size_t s64 = g->field_bytes(0, P64) / 16;
+  double2* W = g->at<double2>(g->W);
+  double2 *r = W, *rt = W + s64, *p = W + 2 * s64, *v = W + 3 * s64, *sv = W + 4 * s64, *t = W + 5 * s64;
+  char* Z = g->ws + g->Z[f32 ? P32 : P64];
+  const size_t fbz = g->field_bytes(0, f32 ? P32 : P64);
+  void* ph = Z;
+  void* sh = Z + fbz;
+  double* bs = g->at<double>(g->scal) + BICG;
+  double* rep = bs + 16;
+  double* p0 = g->at<double>(g->apart);
+  double* p1 = p0 + ARNOLDI_PART;
+  double* p2 = p1 + ARNOLDI_PART;
+  Level<double> EX = exact_level(g);
+  hipStream_t saved = g->stream;
+  g->stream = st;
+  auto precondition = [&](const double2* in, void* out) {
+    if (f32) {
+      launch_scale_copy<double, float>(st, n, pitch, pitch, in, nullptr, g->ws + g->f32);
+      mgcccs_cycle<float>(g, out, g->ws + g->f32, true);
+    } else {
+      mgcccs_cycle<double>(g, out, in, true);
+    }
+  };
+  launch_bicg_p(st, n, pitch, r, v, p, bs);
+  precondition(p, ph);
+  if (f32) launch_apply_dot<float>(st, EX, ph, s64, rt, 1, v, p0);
+  else launch_apply_dot<double>(st, EX, ph, s64, rt, 1, v, p0);
+  launch_bicg_s(st, n, pitch, p0, bs, r, v, sv, p1);
+  precondition(sv, sh);
+  if (f32) launch_apply_dot<float>(st, EX, sh, s64, sv, 1, t, p2);
+  else launch_apply_dot<double>(st, EX, sh, s64, sv, 1, t, p2);
+  if (f32) launch_bicg_x<float>(st, n, pitch, p2, p1, tol2, bs, ph, sh, sv, t, rt, r, (double2*)u, p0);
+  else launch_bicg_x<double>(st, n, pitch, p2, p1, tol2, bs, ph, sh, sv, t, rt, r, (double2*)u, p0);
+  launch_bicg_rho(st, n, p0, bs, rep);
+  g->stream = saved;
+}
+
+mgc_status solve_bicgstab(mgc_grid g, void* u, const void* f, const mgc_solve_opts* o, mgc_stats* st) {
+  if (g->d.max_restart < 5) return fail(MGC_EINVAL, "BiCGSTAB needs desc.max_restart >= 5");
+  hipStream_t s = g->stream;
+  const size_t fb = g->field_bytes(0, P64);
+  double2* W = g->at<double2>(g->W);
+  if (g->basis_dirty) {
+    HIPCHK(g, hipMemsetAsync(W, 0, (size_t)(g->d.max_restart + 1) * fb, s));
+    g->basis_dirty = false;
+  }
+  double* bs = g->at<double>(g->scal) + BICG;
+  double rr, ff;
+  mgc_status rc = exact_residual(g, u, f, W, &rr, &ff);        // r = f - A u
+  if (rc) return rc;
+  const double fn = std::sqrt(ff);
+  double rel = std::sqrt(rr) / fn;
+  record(st, 0, rel);
+  // r~ = r, p = v = 0, scalars from ||r||^2
+  HIPCHK(g, hipMemcpyAsync(W + fb / 16, W, fb, hipMemcpyDeviceToDevice, s));
+  launch_fill_zero(s, W + 2 * (fb / 16), 2 * fb);
+  launch_bicg_init(s, bs, g->at<double>(g->scal));
+  HIPCHK(g, hipGetLastError());
+  const double tol2 = (o->tol * fn) * (o->tol * fn);
+  const bool use_graph = std::getenv("MGC_NO_GRAPH") == nullptr;
+  int it = 0;
+  bool conv = false;
+  while (rel > o->tol && !conv && it < o->max_it && std::isfinite(rel)) {
+    if (use_graph) {
+      GraphCache& gc = g->bicg_graph;
+      if (!gc.exec || gc.u != u || gc.f != f || gc.inner != (int)o->inner || gc.tol_abs != tol2) {
+        if (gc.exec) { (void)hipGraphExecDestroy(gc.exec); gc.exec = nullptr; }
+        hipGraph_t graph;
+        HIPCHK(g, hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal));
+        enqueue_bicg_iteration(g, u, o, tol2, g->cap);
+        HIPCHK(g, hipStreamEndCapture(g->cap, &graph));
+        hipError_t e = hipGraphInstantiate(&gc.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIPCHK(g, e);
+        gc.u = u; gc.f = f; gc.inner = (int)o->inner; gc.tol_abs = tol2;
+      }
+      HIPCHK(g, hipGraphLaunch(gc.exec, s));
+    } else {
+      enqueue_bicg_iteration(g, u, o, tol2, s);
+      HIPCHK(g, hipGetLastError());
+    }
+    double rep[3];
+    HIPCHK(g, hipMemcpyAsync(rep, bs + 16, sizeof(rep), hipMemcpyDeviceToHost, s));
+    HIPCHK(g, hipStreamSynchronize(s));
+    ++it;
+    conv = rep[2] != 0.0;
+    rel = std::sqrt(conv ? rep[1] : rep[0]) / fn;
+    record(st, it, rel);
+  }
+  rc = exact_residual(g, u, f, g->ws + g->r64, &rr, &ff);
+  if (rc) return rc;
+  rel = std::sqrt(rr) / fn;
+  if (st) { st->iters = it; st->vcycles = 2 * it; st->relres = rel; }
+  if (!std::isfinite(rel)) g->basis_dirty = true;
+  return finish_status(rel, o->tol);
+}
+
 }  // namespace
 
 namespace {
@@ -968,6 +1076,7 @@ mgc_status mgc_create_grid(const mgc_grid_desc* d, void* hip_stream, mgc_grid* o
   if (d->nu1 < 0 || d->nu2 < 0 || d->nu1 + d->nu2 < 1 || d->nu1 > 8 || d->nu2 > 8) return fail(MGC_EINVAL, "bad smoothing counts");
   if (!(d->pc_gamma >= 0) || !(d->pc_gamma < M_PI / 4)) return fail(MGC_EINVAL, "pc_gamma must lie in [0, pi/4)");
   if (!(d->pc_gamma0 >= 0) || !(d->pc_gamma0 < M_PI / 4)) return fail(MGC_EINVAL, "pc_gamma0 must lie in [0, pi/4)");
+  if (!(d->gamma >= 0) || !(d->gamma < M_PI / 4)) return fail(MGC_EINVAL, "gamma must lie in [0, pi/4)");
   if (d->pc_first_level < 0) return fail(MGC_EINVAL, "pc_first_level must be >= 0");
   if (d->max_restart < 0 || d->max_restart > MGC_MAX_RESTART)
     return fail(MGC_EINVAL, "max_restart must lie in [0, 16]");
@@ -983,7 +1092,7 @@ mgc_status mgc_create_grid(const mgc_grid_desc* d, void* hip_stream, mgc_grid* o
   }
   g->prec_on[P64] = true;
   g->prec_on[P32] = (d->precisions & 2) != 0;
-  g->exact = make_axis(n, d->L, d->R0, d->theta, 0.0);
+  g->exact = make_axis(n, d->L, d->R0, d->theta, d->gamma);
   for (int l = 0; l < d->levels; ++l) {
     LevelInfo L;
     L.n = n >> l;
@@ -1325,14 +1434,17 @@ static mgc_status validate_opts(mgc_grid g, const mgc_solve_opts* o) {
   switch (o->outer) {
     case MGC_STATIONARY:
       if (o->inner != MGC_FP64) return fail(MGC_EINVAL, "stationary iteration runs in FP64");
-      if ((g->d.pc_first_level == 0 ? g->d.pc_gamma : g->d.pc_gamma0) != 0.0)
-        return fail(MGC_EINVAL, "stationary iteration needs the exact level-0 operator (no rotation on level 0)");
+      if ((g->d.pc_first_level == 0 ? g->d.pc_gamma : g->d.pc_gamma0) != g->d.gamma)
+        return fail(MGC_EINVAL, "stationary iteration needs the exact level-0 operator (level 0 on the system's contour)");
       break;
     case MGC_IR:
       if (o->inner_cycles < 1 || o->inner_cycles > 16) return fail(MGC_EINVAL, "inner_cycles must lie in [1, 16]");
       break;
     case MGC_FGMRES:
       if (o->restart < 1 || o->restart > g->d.max_restart) return fail(MGC_EINVAL, "restart must lie in [1, max_restart]");
+      break;
+    case MGC_BICGSTAB:
+      if (g->d.max_restart < 5) return fail(MGC_EINVAL, "BiCGSTAB needs desc.max_restart >= 5");
       break;
     default:
       return fail(MGC_EINVAL, "bad outer method");
@@ -1352,6 +1464,7 @@ mgc_status mgc_solve(mgc_grid g, void* u, const void* f, const mgc_solve_opts* o
   switch (o->outer) {
     case MGC_STATIONARY: rc = solve_stationary(g, u, f, o, st); break;
     case MGC_IR: rc = solve_ir(g, u, f, o, st); break;
+    case MGC_BICGSTAB: rc = solve_bicgstab(g, u, f, o, st); break;
     default: rc = solve_fgmres(g, u, f, o, st); break;
   }
   if (rc == MGC_EHIP) return rc;
@@ -1393,6 +1506,7 @@ mgc_status mgc_cross_section(mgc_grid g, const void* u, const void* chi, double 
                              double zeta[2], double* sigma) {
   mgc_status rc = check_ready(g);
   if (rc) return rc;
+  if (g->d.gamma != 0.0) return fail(MGC_EINVAL, "the amplitudes are defined on a real interior (gamma = 0)");
   if (!u || !chi || !zeta || !(k1 > 0) || !(k2 > 0)) return fail(MGC_EINVAL, "bad arguments");
   const Axis& ax = g->exact;
   const int n = ax.n, j0 = ax.j0;
@@ -1423,6 +1537,7 @@ mgc_status mgc_cross_section_sweep(mgc_grid g, const void* u, const void* chi, i
                                    const double* k2, double* zeta, double* sigma) {
   mgc_status rc = check_ready(g);
   if (rc) return rc;
+  if (g->d.gamma != 0.0) return fail(MGC_EINVAL, "the amplitudes are defined on a real interior (gamma = 0)");
   if (!u || !chi || !k1 || !k2 || !zeta) return fail(MGC_EINVAL, "null argument");
   if (npairs < 1 || npairs > MGC_SWEEP_MAX) return fail(MGC_EINVAL, "npairs must lie in [1, MGC_SWEEP_MAX]");
   for (int a = 0; a < npairs; ++a)
@@ -1461,6 +1576,7 @@ mgc_status mgc_cross_section_grad(mgc_grid g, const void* u, const void* chi, do
                                   double* sigma, mgc_stats* st) {
   mgc_status rc = check_ready(g);
   if (rc) return rc;
+  if (g->d.gamma != 0.0) return fail(MGC_EINVAL, "the amplitudes are defined on a real interior (gamma = 0)");
   if (!u || !chi || !v || !dsigma || !(k1 > 0) || !(k2 > 0) || v == u || v == chi)
     return fail(MGC_EINVAL, "bad arguments");
   if (!(g->Z1 > 0)) return fail(MGC_EINVAL, "gradient needs Z1 > 0");
@@ -1596,6 +1712,7 @@ struct XsecJob {
 // be 0); enqueue them on st.
 mgc_status enqueue_xsec(mgc_grid g, const void* u, const void* chi, int nstates, int nodes, XsecJob& J,
                         hipStream_t st) {
+  if (g->d.gamma != 0.0) return fail(MGC_EINVAL, "the amplitudes are defined on a real interior (gamma = 0)");
   J.nstates = nstates;
   J.nodes = nodes;
   mgc_status rc;
@@ -1990,6 +2107,7 @@ mgc_status mgc_batch_destroy(mgc_batch b) {
 mgc_status mgc_destroy_grid(mgc_grid g) {
   if (!g) return fail(MGC_EINVAL, "null handle");
   if (g->graph.exec) (void)hipGraphExecDestroy(g->graph.exec);
+  if (g->bicg_graph.exec) (void)hipGraphExecDestroy(g->bicg_graph.exec);
   for (hipEvent_t e : g->kt.ev)
     if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : g->kt.fev)

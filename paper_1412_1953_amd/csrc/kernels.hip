@@ -2949,6 +2949,139 @@ void launch_sweep_testfn(hipStream_t s, int n, int j0, double h, double Z1, int 
                          double* F) {
   hipLaunchKernelGGL(k_sweep_testfn, dim3((2 * pp + 63) / 64), dim3(64), 0, s, n, j0, h, Z1, npairs, pp, kk, F);
 }
+// ----------------------------------------------------------------------------
+// BiCGSTAB outer loop (MGC_BICGSTAB), one iteration:
+//   p = r + beta (p - omega v)                              k_bicg_p
+//   p^ = B p  (one MG-CCCS cycle);  v = A p^, r~^H v        k_apply_dot (J = 1)
+//   alpha = rho / r~^H v;  s = r - alpha v, ||s||^2         k_bicg_s
+//   s^ = B s;  t = A s^, s^H t, ||t||^2                     k_apply_dot (J = 1)
+//   omega = conj(s^H t) / ||t||^2;  u += alpha p^ + omega s^;  r = s - omega t;
+//   r~^H r, ||r||^2 (if ||s|| already meets the tolerance: u += alpha p^, r = s)
+//                                                           k_bicg_x
+//   rho' = r~^H r;  beta = (rho'/rho)(alpha/omega);  rho = rho'   k_bicg_rho
+// Scalars live on the device (BS_* slots below); every block that needs a
+// scalar sums the producer's per-block partials itself in the same fixed
+// order, so all blocks agree bit for bit.  The vectors are zero outside the
+// interior, so the flat passes sweep the padded array.
+enum { BS_RHO = 0, BS_ALPHA = 2, BS_OMEGA = 4, BS_BETA = 6, BS_RR = 8, BS_SS = 9, BS_CONV = 10 };
+__global__ void k_bicg_init(double* bs, const double* nrm2) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  bs[BS_RHO] = nrm2[0];                        // r~ = r: rho = ||r||^2
+  bs[BS_RHO + 1] = 0.0;
+  bs[BS_ALPHA] = bs[BS_OMEGA] = 1.0;
+  bs[BS_ALPHA + 1] = bs[BS_OMEGA + 1] = 0.0;
+  bs[BS_BETA] = bs[BS_BETA + 1] = 0.0;         // p = v = 0 at the start
+  bs[BS_RR] = nrm2[0];
+  bs[BS_SS] = 0.0;
+  bs[BS_CONV] = 0.0;
+}
+__global__ void __launch_bounds__(AB) k_bicg_p(size_t Nf, const double2* __restrict__ r,
+                                               const double2* __restrict__ v, double2* __restrict__ p,
+                                               const double* __restrict__ bs) {
+  const double2 beta = make_double2(bs[BS_BETA], bs[BS_BETA + 1]);
+  const double2 om = make_double2(bs[BS_OMEGA], bs[BS_OMEGA + 1]);
+  for (size_t i = (size_t)blockIdx.x * AB + threadIdx.x; i < Nf; i += (size_t)gridDim.x * AB) {
+    const double2 pv = p[i], vv = v[i], rv = r[i];
+    const double2 d = make_double2(pv.x - (om.x * vv.x - om.y * vv.y), pv.y - (om.x * vv.y + om.y * vv.x));
+    p[i] = make_double2(rv.x + (beta.x * d.x - beta.y * d.y), rv.y + (beta.x * d.y + beta.y * d.x));
+  }
+}
+__global__ void __launch_bounds__(AB) k_bicg_s(size_t Nf, const double* __restrict__ pin, int nbin,
+                                               double* __restrict__ bs, const double2* __restrict__ r,
+                                               const double2* __restrict__ v, double2* __restrict__ sv,
+                                               double* __restrict__ pout) {
+  __shared__ double dsum[3];
+  finish_sum_nt<AB>(pin, nbin, 3, dsum);       // r~^H v, ||v||^2
+  const double2 rho = make_double2(bs[BS_RHO], bs[BS_RHO + 1]);
+  const double2 alpha = cdiv(rho, make_double2(dsum[0], dsum[1]));
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    bs[BS_ALPHA] = alpha.x;
+    bs[BS_ALPHA + 1] = alpha.y;
+  }
+  double acc[1] = {0.0};
+  for (size_t i = (size_t)blockIdx.x * AB + threadIdx.x; i < Nf; i += (size_t)gridDim.x * AB) {
+    const double2 rv = r[i], vv = v[i];
+    const double2 sx = make_double2(rv.x - (alpha.x * vv.x - alpha.y * vv.y), rv.y - (alpha.x * vv.y + alpha.y * vv.x));
+    sv[i] = sx;
+    acc[0] += sx.x * sx.x + sx.y * sx.y;
+  }
+  double tot[1];
+  block_sum<1>(acc, tot);
+  if (threadIdx.x == 0) pout[blockIdx.x] = tot[0];
+}
+template <typename TZ>
+__global__ void __launch_bounds__(256) k_bicg_x(int n, int pitch, const double* __restrict__ pin, int nbin,
+                                                const double* __restrict__ ps, int nbs, double tol2,
+                                                double* __restrict__ bs, const v2<TZ>* __restrict__ ph,
+                                                const v2<TZ>* __restrict__ sh, const double2* __restrict__ sv,
+                                                const double2* __restrict__ t, const double2* __restrict__ rt,
+                                                double2* __restrict__ r, double2* __restrict__ x,
+                                                double* __restrict__ pout) {
+  __shared__ double dsum[3], ssum[1];
+  finish_sum_nt<256>(pin, nbin, 3, dsum);      // s^H t, ||t||^2
+  finish_sum_nt<256>(ps, nbs, 1, ssum);        // ||s||^2
+  const bool conv = ssum[0] <= tol2;
+  const double2 alpha = make_double2(bs[BS_ALPHA], bs[BS_ALPHA + 1]);
+  // t^H s = conj(s^H t)
+  const double2 omega = conv ? make_double2(0.0, 0.0) : make_double2(dsum[0] / dsum[2], -dsum[1] / dsum[2]);
+  if (flat_block() == 0 && threadIdx.x == 0) {
+    bs[BS_OMEGA] = omega.x;
+    bs[BS_OMEGA + 1] = omega.y;
+    bs[BS_SS] = ssum[0];
+    bs[BS_CONV] = conv ? 1.0 : 0.0;
+  }
+  double acc[3] = {0.0, 0.0, 0.0};
+  MGC_NODE_LOOP(n, k, j) {
+    const size_t idx = (size_t)k * pitch + j;
+    const v2<double> a = cvt<double>(ph[idx]);
+    double2 xv = x[idx];
+    const double2 sx = sv[idx];
+    double2 rn;
+    if (conv) {
+      xv = make_double2(xv.x + (alpha.x * a.x - alpha.y * a.y), xv.y + (alpha.x * a.y + alpha.y * a.x));
+      rn = sx;
+    } else {
+      const v2<double> b = cvt<double>(sh[idx]);
+      const double2 tv = t[idx];
+      xv = make_double2(xv.x + (alpha.x * a.x - alpha.y * a.y) + (omega.x * b.x - omega.y * b.y),
+                        xv.y + (alpha.x * a.y + alpha.y * a.x) + (omega.x * b.y + omega.y * b.x));
+      rn = make_double2(sx.x - (omega.x * tv.x - omega.y * tv.y), sx.y - (omega.x * tv.y + omega.y * tv.x));
+    }
+    x[idx] = xv;
+    r[idx] = rn;
+    const double2 w = rt[idx];
+    acc[0] += w.x * rn.x + w.y * rn.y;         // r~^H r
+    acc[1] += w.x * rn.y - w.y * rn.x;
+    acc[2] += rn.x * rn.x + rn.y * rn.y;
+  }
+  double tot[3];
+  block_sum<3>(acc, tot);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) pout[(size_t)flat_block() * 3 + q] = tot[q];
+  }
+}
+__global__ void __launch_bounds__(256) k_bicg_rho(const double* __restrict__ pin, int nbin, double* __restrict__ bs,
+                                                  double* __restrict__ rep) {
+  __shared__ double dsum[3];
+  finish_sum_nt<256>(pin, nbin, 3, dsum);
+  if (threadIdx.x == 0) {
+    const double2 rn = make_double2(dsum[0], dsum[1]);
+    const double2 rho = make_double2(bs[BS_RHO], bs[BS_RHO + 1]);
+    const double2 alpha = make_double2(bs[BS_ALPHA], bs[BS_ALPHA + 1]);
+    const double2 omega = make_double2(bs[BS_OMEGA], bs[BS_OMEGA + 1]);
+    const double2 beta = bs[BS_CONV] != 0.0 ? make_double2(0.0, 0.0) : cmul(cdiv(rn, rho), cdiv(alpha, omega));
+    bs[BS_BETA] = beta.x;
+    bs[BS_BETA + 1] = beta.y;
+    bs[BS_RHO] = rn.x;
+    bs[BS_RHO + 1] = rn.y;
+    bs[BS_RR] = dsum[2];
+    rep[0] = dsum[2];
+    rep[1] = bs[BS_SS];
+    rep[2] = bs[BS_CONV];
+  }
+}
+
 // x2 side of the single-ionisation sweep: F2[k][2q + part] = t_k * (Re, Im)
 // of the bound state q at node k (t the trapezoid weights of the real region:
 // h, h/2 at j0), zero outside 1 .. top and for the padding pairs.
@@ -2970,6 +3103,38 @@ void launch_bound_weights(hipStream_t s, int n, int top, int j0, double h, int n
   const size_t total = (size_t)(n + 1) * pp;
   const int blocks = (int)std::min<size_t>(1024, (total + 255) / 256);
   hipLaunchKernelGGL(k_bound_weights, dim3(blocks), dim3(256), 0, s, n, top, j0, h, nstates, pp, tab, F2);
+}
+
+void launch_bicg_init(hipStream_t s, double* bs, const double* nrm2) {
+  hipLaunchKernelGGL(k_bicg_init, dim3(1), dim3(1), 0, s, bs, nrm2);
+}
+void launch_bicg_p(hipStream_t s, int n, int pitch, const double2* r, const double2* v, double2* p,
+                   const double* bs) {
+  hipLaunchKernelGGL(k_bicg_p, dim3(axpy_blocks(n, pitch)), dim3(AB), 0, s, (size_t)(n + 1) * pitch, r, v, p, bs);
+}
+void launch_bicg_s(hipStream_t s, int n, int pitch, const double* part_ad, double* bs, const double2* r,
+                   const double2* v, double2* sv, double* part_s) {
+  const ApplyGrid ag = apply_dot_grid(n);
+  hipLaunchKernelGGL(k_bicg_s, dim3(axpy_blocks(n, pitch)), dim3(AB), 0, s, (size_t)(n + 1) * pitch, part_ad,
+                     (int)(ag.grid.x * ag.grid.y), bs, r, v, sv, part_s);
+}
+template <typename TZ>
+void launch_bicg_x(hipStream_t s, int n, int pitch, const double* part_ad, const double* part_s, double tol2,
+                   double* bs, const void* ph, const void* sh, const double2* sv, const double2* t, const double2* rt,
+                   double2* r, double2* x, double* part_x) {
+  const ApplyGrid ag = apply_dot_grid(n);
+  hipLaunchKernelGGL((k_bicg_x<TZ>), vec_grid(n), dim3(256), 0, s, n, pitch, part_ad, (int)(ag.grid.x * ag.grid.y),
+                     part_s, axpy_blocks(n, pitch), tol2, bs, (const v2<TZ>*)ph, (const v2<TZ>*)sh, sv, t, rt, r, x,
+                     part_x);
+}
+template void launch_bicg_x<double>(hipStream_t, int, int, const double*, const double*, double, double*, const void*,
+                                    const void*, const double2*, const double2*, const double2*, double2*, double2*,
+                                    double*);
+template void launch_bicg_x<float>(hipStream_t, int, int, const double*, const double*, double, double*, const void*,
+                                   const void*, const double2*, const double2*, const double2*, double2*, double2*,
+                                   double*);
+void launch_bicg_rho(hipStream_t s, int n, const double* part_x, double* bs, double* rep) {
+  hipLaunchKernelGGL(k_bicg_rho, dim3(1), dim3(256), 0, s, part_x, vec_blocks(n), bs, rep);
 }
 
 void launch_zeta_sweep(hipStream_t s, int n, int pitch, int top, int pp, const double2* tm, const double* F1T,

@@ -159,6 +159,18 @@ int zeta_sweep_blocks(int top);
 // zero for the padding pairs npairs .. pp - 1.  Needs 1 <= j0 and n >= 2.
 void launch_sweep_testfn(hipStream_t s, int n, int j0, double h, double Z1, int npairs, int pp, const double* kk,
                          double* F);
+// BiCGSTAB (see kernels.hip): bs = device scalar state (11 doubles); the
+// partial buffers hold at most 3 x 512 doubles.
+void launch_bicg_init(hipStream_t s, double* bs, const double* nrm2);
+void launch_bicg_p(hipStream_t s, int n, int pitch, const double2* r, const double2* v, double2* p,
+                   const double* bs);
+void launch_bicg_s(hipStream_t s, int n, int pitch, const double* part_ad, double* bs, const double2* r,
+                   const double2* v, double2* sv, double* part_s);
+template <typename TZ>
+void launch_bicg_x(hipStream_t s, int n, int pitch, const double* part_ad, const double* part_s, double tol2,
+                   double* bs, const void* ph, const void* sh, const double2* sv, const double2* t, const double2* rt,
+                   double2* r, double2* x, double* part_x);
+void launch_bicg_rho(hipStream_t s, int n, const double* part_x, double* bs, double* rep);
 // The x2 side of the single-ionisation sweep from the bound states tab
 // ([state][n+1] complex): F2[k][2q] = t_k Re tab_q(k), F2[k][2q+1] = t_k Im
 // tab_q(k) on rows 1 .. top, zero elsewhere and for pairs >= 2 nstates.

@@ -1,7 +1,7 @@
 """Summaries of rocprofv3 CSV output for the committed profile records.
 
     python3 -m paper_1412_1953_amd.profiling stats <kernel_stats.csv> <kernel_trace.csv> <out.txt> -- <command>
-    python3 -m paper_1412_1953_amd.profiling traffic <kernel> <fetch.csv> <write.csv> <out.txt> -- <command>
+    python3 -m paper_1412_1953_amd.profiling traffic <kernel> <fetch.csv> <write.csv> <out.txt> [--largest] -- <command>
 
 `stats` lists the kernels by total time (rocprofv3 --kernel-trace --stats)
 and, per kernel, the launch shapes (grid sizes) with their average duration.
@@ -65,8 +65,13 @@ def stats(stats_csv, trace_csv, out, command):
     # its runs of consecutive launches per launch (what one event pair around
     # such a run covers, inter-kernel gaps included)
     trace = sorted(csv.DictReader(open(trace_csv)), key=lambda r: int(r["Start_Timestamp"]))
-    lines += ["", "timer classes (mean per launch):",
-              f"{'class':>13} {'launches':>8} {'kernel us':>10} {'run span us':>12}  kernels"]
+    # the profiler's own per-dispatch floor: the empty kernel that the event
+    # timer launches before each bracket (k_nop), when the run has one
+    nops = [r for r in rows if short(r["Name"]).endswith("k_nop")]
+    floor_us = float(nops[0]["AverageNs"]) / 1e3 if nops else 0.0
+    lines += ["", f"empty-kernel floor (k_nop mean duration): {floor_us:.2f} us",
+              "timer classes (mean per launch; 'net' = kernel us minus the empty-kernel floor):",
+              f"{'class':>13} {'launches':>8} {'kernel us':>10} {'net us':>8} {'run span us':>12}  kernels"]
     for kc, pat in CLASS_PATTERN.items():
         rx = re.compile(pat)
         n = busy = span = 0
@@ -83,7 +88,8 @@ def stats(stats_csv, trace_csv, out, command):
         if run is not None:
             span += run[1] - run[0]
         if n:
-            lines.append(f"{kc:>13} {n:8d} {busy / n / 1e3:10.2f} {span / n / 1e3:12.2f}  {pat}")
+            lines.append(f"{kc:>13} {n:8d} {busy / n / 1e3:10.2f} {busy / n / 1e3 - floor_us:8.2f} "
+                         f"{span / n / 1e3:12.2f}  {pat}")
     lines += ["", "launch shapes (grid x, grid y in work-items):",
               f"{'calls':>6} {'avg us':>8}  kernel [grid]"]
     for (nm, gx, gy), (c, d) in sorted(shapes.items(), key=lambda x: -x[1][1])[:40]:
@@ -99,11 +105,24 @@ def counter_rows(path):
     return out
 
 
-def traffic(kclass, fetch_csv, write_csv, out, command):
+def counter_rows_sized(path):
+    out = []
+    for r in csv.DictReader(open(path)):
+        out.append((short(r["Kernel_Name"]), float(r["Counter_Value"]), int(r["Grid_Size"])))
+    return out
+
+
+def traffic(kclass, fetch_csv, write_csv, out, command, largest=False, name=None):
+    """largest: only the dispatches of the class with the largest grid (the
+    finest level of a multigrid kernel that also runs on coarser levels)."""
     pat = re.compile(CLASS_PATTERN[kclass])
     res = {}
     for label, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
-        rows = counter_rows(path)
+        sized = counter_rows_sized(path)
+        if largest:
+            gmax = max((gs for nm, v, gs in sized if pat.search(nm)), default=None)
+            sized = [(nm, v, gs) for nm, v, gs in sized if not pat.search(nm) or gs == gmax]
+        rows = [(nm, v) for nm, v, gs in sized]
         # the copy probe is the largest single dispatch of a copy kernel
         copies = [v for nm, v in rows if "copy" in nm.lower()]
         if not copies:
@@ -117,7 +136,7 @@ def traffic(kclass, fetch_csv, write_csv, out, command):
     fetch = res["FETCH_SIZE"][0] * 1024.0 * res["FETCH_SIZE"][3]
     write = res["WRITE_SIZE"][0] * 1024.0 * res["WRITE_SIZE"][3]
     lines = [f"command: {command}",
-             f"kernel class: {kclass} ({CLASS_PATTERN[kclass]})",
+             f"kernel class: {kclass} ({CLASS_PATTERN[kclass]})" + (", largest grid only" if largest else ""),
              f"kernels.hip sha256: {source_sha()}"]
     for label, (avg, cnt, kib_copy, scale) in res.items():
         lines.append(f"{label}: {avg:.1f} KiB per dispatch over {cnt} dispatches; copy probe of "
@@ -137,7 +156,7 @@ def main(argv):
     if args[0] == "stats":
         stats(args[1], args[2], args[3], command)
     elif args[0] == "traffic":
-        traffic(args[1], args[2], args[3], args[4], command)
+        traffic(args[1], args[2], args[3], args[4], command, largest="--largest" in args)
     else:
         raise SystemExit(__doc__)
 

@@ -340,6 +340,23 @@ void launch_zeta_part(hipStream_t s, int, int, int, const double2*, const double
 }
 void launch_sweep_testfn(hipStream_t s, int, int, double, double, int, int, const double*, double*) { MGC_NOP(s); }
 void launch_bound_weights(hipStream_t s, int, int, int, double, int, int, const double2*, double*) { MGC_NOP(s); }
+void launch_bicg_init(hipStream_t s, double*, const double*) { MGC_NOP(s); }
+void launch_bicg_p(hipStream_t s, int, int, const double2*, const double2*, double2*, const double*) { MGC_NOP(s); }
+void launch_bicg_s(hipStream_t s, int, int, const double*, double*, const double2*, const double2*, double2*, double*) {
+  MGC_NOP(s);
+}
+template <typename TZ>
+void launch_bicg_x(hipStream_t s, int, int, const double*, const double*, double, double*, const void*, const void*,
+                   const double2*, const double2*, const double2*, double2*, double2*, double*) {
+  MGC_NOP(s);
+}
+template void launch_bicg_x<double>(hipStream_t, int, int, const double*, const double*, double, double*, const void*,
+                                    const void*, const double2*, const double2*, const double2*, double2*, double2*,
+                                    double*);
+template void launch_bicg_x<float>(hipStream_t, int, int, const double*, const double*, double, double*, const void*,
+                                   const void*, const double2*, const double2*, const double2*, double2*, double2*,
+                                   double*);
+void launch_bicg_rho(hipStream_t s, int, const double*, double*, double*) { MGC_NOP(s); }
 void launch_zeta_sweep(hipStream_t s, int, int, int, int, const double2*, const double*, const double*,
                        const double2*, const double2*, double*, double* out) {
   MGC_NOP(s);
