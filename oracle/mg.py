@@ -1,8 +1,8 @@
 """Geometric multigrid V-cycle (TEST INFRASTRUCTURE ONLY; see ``oracle/__init__``).
 
 Components named in Sec. 1 and Sec. 3.2 (proof of concept): a V(1,1)-cycle
-with an omega-Jacobi smoother, full-weighting restriction and bilinear
-interpolation.  Readings where the paper is silent: coarse operators are
+with an omega-Jacobi smoother (or the GMRES(3) smoothing substitute of
+Sec. 6.1), full-weighting restriction and bilinear interpolation.  Readings where the paper is silent: coarse operators are
 rediscretised at 2h; the coarsest level is solved exactly by a dense LU
 factorisation (partial pivoting, FP64); the transfer stencils use the
 standard index-space weights, also inside the complex-scaled layer.
@@ -21,6 +21,41 @@ def jacobi(op: Operator, u: np.ndarray, f: np.ndarray, omega: float) -> np.ndarr
     r = op.residual(u, f)
     out = u.copy()
     out[1:n, 1:n] += omega * r[1:n, 1:n] / op.diag[1:n, 1:n]
+    return out
+
+
+def gmres_smooth(op: Operator, u: np.ndarray, f: np.ndarray, m: int = 3) -> np.ndarray:
+    """One GMRES(m) cycle used as a smoother (Sec. 6.1: the GMRES(3) pre- and
+    post-smoothing substitute of the V(1,1)-cycle): u + V y with y minimising
+    ||f - A (u + V y)||_2 over the Krylov space K_m(A, r0), r0 = f - A u.
+    Arnoldi with classical Gram-Schmidt (one pass), the small least-squares
+    problem min ||beta e1 - H y|| by LAPACK's least squares; an exact
+    breakdown ends the space early (new array)."""
+    r = op.residual(u, f)
+    beta = np.linalg.norm(r)
+    if beta == 0:
+        return u.copy()
+    V = [r / beta]
+    H = np.zeros((m + 1, m), np.complex128)
+    k = m
+    for i in range(m):
+        w = op.apply(V[i])
+        w[0, :] = w[-1, :] = w[:, 0] = w[:, -1] = 0
+        h = np.array([np.vdot(v, w) for v in V])
+        for q, v in enumerate(V):
+            w = w - h[q] * v
+        H[:i + 1, i] = h
+        H[i + 1, i] = np.linalg.norm(w)
+        if H[i + 1, i] == 0:
+            k = i + 1
+            break
+        V.append(w / H[i + 1, i])
+    e1 = np.zeros(k + 1, np.complex128)
+    e1[0] = beta
+    y = np.linalg.lstsq(H[:k + 1, :k], e1, rcond=None)[0]
+    out = u.copy()
+    for q in range(k):
+        out = out + y[q] * V[q]
     return out
 
 
@@ -72,7 +107,7 @@ class Hierarchy:
 
     def __init__(self, g: Grid1D, Z1: float, Z2: float, lam: float, E: float,
                  levels: int, omega: float = 2.0 / 3.0, nu1: int = 1, nu2: int = 1,
-                 gammas=None):
+                 gammas=None, smoother: str = "jacobi"):
         if levels < 1:
             raise ValueError("levels >= 1")
         gammas = [g.gamma] * levels if gammas is None else list(gammas)
@@ -82,6 +117,15 @@ class Hierarchy:
         self.ops = [tp_operator(gl, Z1, Z2, lam, E) for gl in grids]
         self.coarsest = CoarsestSolver(self.ops[-1])
         self.omega, self.nu1, self.nu2 = omega, nu1, nu2
+        if smoother not in ("jacobi", "gmres3"):
+            raise ValueError("smoother: 'jacobi' or 'gmres3'")
+        self.smoother = smoother
+
+    def smooth(self, op: Operator, u: np.ndarray, f: np.ndarray) -> np.ndarray:
+        """One smoothing step: omega-Jacobi, or one GMRES(3) cycle."""
+        if self.smoother == "gmres3":
+            return gmres_smooth(op, u, f, 3)
+        return jacobi(op, u, f, self.omega)
 
     @property
     def levels(self) -> int:
@@ -93,10 +137,10 @@ class Hierarchy:
         if level == self.levels - 1:
             return self.coarsest.solve(f)
         for _ in range(self.nu1):
-            u = jacobi(op, u, f, self.omega)
+            u = self.smooth(op, u, f)
         fc = restrict_fw(op.residual(u, f))
         ec = self.vcycle(np.zeros_like(fc), fc, level + 1)
         u = u + prolong_bilinear(ec)
         for _ in range(self.nu2):
-            u = jacobi(op, u, f, self.omega)
+            u = self.smooth(op, u, f)
         return u

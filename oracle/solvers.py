@@ -46,13 +46,13 @@ class MGCCCS:
 
     def __init__(self, n, L, R0, theta, Z1, Z2, lam, E, levels, M,
                  omega=2.0 / 3.0, nu1=1, nu2=1, Lch=None, refine_steps=2,
-                 pc_gamma=0.0, pc_first_level=0, pc_gamma0=0.0, gamma=0.0):
+                 pc_gamma=0.0, pc_first_level=0, pc_gamma0=0.0, gamma=0.0, smoother="jacobi"):
         # gamma: contour angle of the system itself (Sec. 3.1; 0 = the
         # exterior-complex-scaled grid with a real interior)
         self.g = Grid1D(n, L, R0, theta, gamma)
         self.Z1, self.Z2, self.lam, self.E = Z1, Z2, lam, E
         gammas = [pc_gamma if l >= pc_first_level else pc_gamma0 for l in range(levels)]
-        self.mg = Hierarchy(self.g, Z1, Z2, lam, E, levels, omega, nu1, nu2, gammas)
+        self.mg = Hierarchy(self.g, Z1, Z2, lam, E, levels, omega, nu1, nu2, gammas, smoother)
         self.op = tp_operator(self.g, Z1, Z2, lam, E)       # exact operator
         self.pc_op = self.mg.ops[0]                         # level 0 of the hierarchy
         self.M = M

@@ -153,6 +153,58 @@ def test_vcycle_contraction_on_the_positive_definite_case_is_mesh_independent():
     assert max(rates) - min(rates) < 0.05, rates
 
 
+# ---------------------------------------------------------------- GMRES(3) smoother
+def _gs_case():
+    g = Grid1D(32, 10.0, 7.5, math.pi / 6, math.radians(5.0))
+    return g, tp_operator(g, 1.0, 1.0, 1.0, 0.6), rng_field(32, 14), rng_field(32, 15)
+
+
+def _krylov_min_residual(op, u, f, m):
+    """min over c of ||r0 - A K c||, K = [r0, A r0, ..., A^{m-1} r0]: the
+    least-squares problem on the explicit Krylov basis (no Arnoldi)."""
+    n = op.n
+    r0 = op.residual(u, f)
+    cols, v = [], r0
+    for _ in range(m):
+        cols.append(v[1:n, 1:n].ravel())
+        v = op.apply(v)
+        v[0, :] = v[-1, :] = v[:, 0] = v[:, -1] = 0
+    K = np.array(cols).T
+    AK = np.array([op.apply(np.pad(c.reshape(n - 1, n - 1), 1))[1:n, 1:n].ravel() for c in K.T]).T
+    c, *_ = np.linalg.lstsq(AK, r0[1:n, 1:n].ravel(), rcond=None)
+    return np.linalg.norm(r0[1:n, 1:n].ravel() - AK @ c)
+
+
+def test_gmres3_smoother_minimises_the_residual_over_the_krylov_space():
+    """Sec. 6.1 GMRES(3) smoothing substitute: the smoothed iterate's residual
+    is the least-squares minimum over K_3(A, r0), computed on the explicit
+    Krylov basis; a planted mistake (unconjugated Gram-Schmidt products) is
+    not minimal."""
+    from oracle import mg as mgmod
+    g, op, u, f = _gs_case()
+    target = _krylov_min_residual(op, u, f, 3)
+    got = np.linalg.norm(op.residual(mgmod.gmres_smooth(op, u, f, 3), f))
+    assert abs(got - target) < 1e-12 * target
+    assert got < np.linalg.norm(op.residual(u, f))
+    real_vdot = mgmod.np.vdot
+    try:
+        mgmod.np.vdot = lambda a, b: np.sum(np.ravel(a) * np.ravel(b))
+        bad = np.linalg.norm(op.residual(mgmod.gmres_smooth(op, u, f, 3), f))
+    finally:
+        mgmod.np.vdot = real_vdot
+    assert bad > target * (1 + 1e-6)
+
+
+def test_gmres3_smoothed_cycle_preconditions_fgmres_to_the_direct_solution():
+    n = 32
+    s = MGCCCS(n, 10.0, 7.5, math.pi / 6, 1.0, 1.0, 1.0, 0.6, 3, 2, pc_gamma=math.radians(10), smoother="gmres3")
+    f = s.rhs()
+    x = np.linalg.solve(s.op.sparse().toarray(), f[1:n, 1:n].ravel())
+    r = s.solve_fgmres(initial_guess(n, 3), f, 1e-12, restart=10, max_it=300)
+    assert r.relres <= 1e-12
+    assert np.linalg.norm(r.u[1:n, 1:n].ravel() - x) / np.linalg.norm(x) < 1e-10
+
+
 # ---------------------------------------------------------------- transfers
 def test_full_weighting_is_quarter_transpose_of_bilinear_interpolation():
     n = 32
