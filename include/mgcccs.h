@@ -105,8 +105,15 @@ typedef struct mgc_grid_s* mgc_grid;   /* opaque, library-owned host object */
  *          (0: the exterior-complex-scaled grid with a real interior; R0 = L
  *          with gamma > 0: the full complex contour of Sec. 3.1 / Sec. 6).
  *          The amplitude and cross-section calls need gamma = 0.
+ * smoother MGC_SMOOTH_JACOBI (0): omega-Jacobi; MGC_SMOOTH_GMRES3 (1): one
+ *          GMRES(3) cycle per smoothing step instead (the substitute of
+ *          Sec. 6.1; u += V y minimising the level's residual over the
+ *          3-dimensional Krylov space of its residual), which takes four more
+ *          fields per level and runs the cycle's general (per-level) path.
  * precisions   bit mask (1 << MGC_FP64) | (1 << MGC_FP32) of the cycle
  *          precisions the workspace must hold.                                */
+#define MGC_SMOOTH_JACOBI 0
+#define MGC_SMOOTH_GMRES3 1
 typedef struct {
   int n;
   double L, R0, theta;
@@ -120,6 +127,7 @@ typedef struct {
   int precisions;
   double pc_gamma0;
   double gamma;
+  int smoother;
 } mgc_grid_desc;
 
 typedef struct {

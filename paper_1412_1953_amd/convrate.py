@@ -14,7 +14,9 @@ initial guess to a relative residual of 1e-6 (Table 1) or an iteration cap.
 rate = (||r_k|| / ||r_0||)^(1 / k) over the k iterations performed (one
 iteration = one cycle for the stationary solvers, one Krylov step otherwise).
 
-    python -m paper_1412_1953_amd.convrate OUT.json [n L gamma_deg M E0 E1 dE]
+    python -m paper_1412_1953_amd.convrate OUT.json [n L gamma_deg M E0 E1 dE [smoother]]
+
+(smoother: 0 = omega-Jacobi, 1 = the GMRES(3) smoothing substitute).
 """
 from __future__ import annotations
 
@@ -33,18 +35,19 @@ def contour_source(g, n, L, gamma, s=3.0):
     return g.from_numpy(f.numpy())
 
 
-def rates(n=1024, L=100.0, gamma_deg=10.0, M=2, energies=None, levels=None, tol=1e-6, cap=200, log=print):
+def rates(n=1024, L=100.0, gamma_deg=10.0, M=2, energies=None, levels=None, tol=1e-6, cap=200, smoother=0,
+          log=print):
     from . import mgcccs
     gamma = math.radians(gamma_deg)
     levels = levels or int(math.log2(n)) - 3           # coarsest 16 intervals
     energies = energies if energies is not None else [-2.0 + 0.25 * i for i in range(21)]
     out = []
     for E in energies:
-        row = {"E": E}
+        row = {"E": E, "smoother": "gmres3" if smoother else "jacobi"}
         for name, m, outer, restart in (("mg", 0, mgcccs.STATIONARY, 1), ("mg-cccs", M, mgcccs.STATIONARY, 1),
                                         ("bicgstab", M, mgcccs.BICGSTAB, 1), ("fgmres", M, mgcccs.FGMRES, 5)):
             g = mgcccs.Grid(n, L, L, math.pi / 6, levels, m, pc_gamma=gamma, pc_gamma0=gamma, pc_first_level=0,
-                            gamma=gamma, max_restart=10, fp32=False)
+                            gamma=gamma, max_restart=10, fp32=False, smoother=smoother)
             g.set_potential(1.0, 1.0, 1.0)
             g.set_energy(E)
             f = contour_source(g, n, L, gamma)
@@ -67,9 +70,11 @@ if __name__ == "__main__":
     args = sys.argv[2:]
     kw = {}
     if args:
-        n, L, gd, M, e0, e1, de = args
+        n, L, gd, M, e0, e1, de = args[:7]
+        if len(args) > 7:
+            kw["smoother"] = int(args[7])
         ne = int(round((float(e1) - float(e0)) / float(de))) + 1
-        kw = dict(n=int(n), L=float(L), gamma_deg=float(gd), M=int(M),
+        kw.update(n=int(n), L=float(L), gamma_deg=float(gd), M=int(M),
                   energies=[float(e0) + float(de) * i for i in range(ne)])
     res = rates(log=lambda m: print(m, flush=True), **kw)
     with open(sys.argv[1], "w") as fh:

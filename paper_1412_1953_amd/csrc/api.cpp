@@ -37,6 +37,7 @@ struct LevelInfo {
   Axis ax;                                 // axis of this hierarchy level
   size_t tab[2] = {0, 0};                  // 5 tables a, c, px, py, tm (per precision)
   size_t fu[2] = {0, 0}, ff[2] = {0, 0}, ft[2] = {0, 0};  // fields
+  size_t gsV[2] = {0, 0}, gsst[2] = {0, 0};               // GMRES(3) smoother: 4 fields, state
 };
 
 struct SysOff {                            // offsets of one channel system's factors
@@ -110,6 +111,7 @@ struct mgc_grid_s {
   size_t exact_tab = 0, exact_tab32 = 0, exact_w = 0, exact_z = 0, coarse_inv = 0, tt = 0;
   CcOff cc[2];
   size_t part = 0, scal = 0;               // reduction partials, small scalars
+  size_t gspart = 0;                       // partials of the GMRES(3) smoother
   size_t apart = 0;                        // 3 x ARNOLDI_PART partials of the Arnoldi passes
   bool basis_dirty = false;                // Krylov basis may hold non-finite values
   size_t r64 = 0, f32 = 0, u32 = 0, tw = 0, tz = 0;
@@ -194,6 +196,10 @@ void layout(mgc_grid g) {
       const size_t fb = g->field_bytes((int)l, p);
       if (l > 0) { L.fu[p] = take(fb); L.ff[p] = take(fb); }
       L.ft[p] = take(fb);
+      if (g->d.smoother == MGC_SMOOTH_GMRES3 && (int)l + 1 < (int)g->lv.size()) {
+        L.gsV[p] = take(4 * fb);
+        L.gsst[p] = take(32 * sizeof(double));
+      }
     }
     CcOff& c = g->cc[p];
     const size_t e = esize(p);
@@ -223,6 +229,7 @@ void layout(mgc_grid g) {
   g->coarse_inv = take((size_t)Nc * Nc * 16);
   const int nb = std::max(launch_stencil_blocks(n), launch_vec_blocks(n));
   g->part = take((size_t)nb * 64 * sizeof(double));
+  if (g->d.smoother == MGC_SMOOTH_GMRES3) g->gspart = take((size_t)gmres3_part_doubles(n) * sizeof(double));
   g->scal = take(256 * sizeof(double));
   g->apart = take((size_t)3 * ARNOLDI_PART * sizeof(double));
   g->r64 = take(g->field_bytes(0, P64));
@@ -490,6 +497,20 @@ void vcycle_level(mgc_grid g, int l, void* u, const void* f, bool zero_guess, co
   const LevelInfo& LI = g->lv[l];
   const LevelInfo& LC = g->lv[l + 1];
   const double om = g->d.omega;
+  if (g->d.smoother == MGC_SMOOTH_GMRES3) {
+    // GMRES(3) smoothing substitute: in place on u, per level
+    void* V = g->ws + LI.gsV[p];
+    const size_t stride = g->field_bytes(l, p) / sizeof(v2<T>);
+    double* st = g->at<double>(LI.gsst[p]);
+    double* part = g->at<double>(g->gspart);
+    if (zero_guess) launch_fill_zero(s, u, g->field_bytes(l, p));
+    for (int it = 0; it < g->d.nu1; ++it) launch_gmres3_smooth<T>(s, L, u, f, V, stride, st, part);
+    launch_resid_restrict<T>(s, L, u, f, g->ws + LC.ff[p], LC.pitch);
+    vcycle_level<T>(g, l + 1, g->ws + LC.fu[p], g->ws + LC.ff[p], true);
+    launch_prolong_add<T>(s, L.n, L.pitch, u, g->ws + LC.fu[p], LC.pitch);
+    for (int it = 0; it < g->d.nu2; ++it) launch_gmres3_smooth<T>(s, L, u, f, V, stride, st, part);
+    return;
+  }
   if (zero_guess && g->d.nu1 == 1 && g->d.nu2 == 1) {
     // fused passes: u' = omega f/d is recomputed, never stored
     const double Nf = (double)(L.n - 1) * (L.n - 1), Nc = (double)(L.n / 2 - 1) * (L.n / 2 - 1);
@@ -653,7 +674,7 @@ void cccs_apply(mgc_grid g, void* u, const void* f, const double* fs = nullptr, 
 // zero-guess path applies it on the fly, otherwise f is scaled into scratch.
 template <typename T>
 void mgcccs_cycle(mgc_grid g, void* u, const void* f, bool zero_guess, const double* fs = nullptr) {
-  if (fs && !(zero_guess && g->d.nu1 == 1 && g->d.nu2 == 1)) {
+  if (fs && !(zero_guess && g->d.nu1 == 1 && g->d.nu2 == 1 && g->d.smoother == MGC_SMOOTH_JACOBI)) {
     const int p = sizeof(T) == 8 ? P64 : P32;
     void* tmp = p == P64 ? (void*)(g->ws + g->tw) : (void*)(g->ws + g->f32);
     launch_scale_copy<T, T>(g->stream, g->d.n, g->lv[0].pitch, g->lv[0].pitch, f, fs, tmp);
@@ -1078,6 +1099,8 @@ mgc_status mgc_create_grid(const mgc_grid_desc* d, void* hip_stream, mgc_grid* o
   if (!(d->pc_gamma0 >= 0) || !(d->pc_gamma0 < M_PI / 4)) return fail(MGC_EINVAL, "pc_gamma0 must lie in [0, pi/4)");
   if (!(d->gamma >= 0) || !(d->gamma < M_PI / 4)) return fail(MGC_EINVAL, "gamma must lie in [0, pi/4)");
   if (d->pc_first_level < 0) return fail(MGC_EINVAL, "pc_first_level must be >= 0");
+  if (d->smoother != MGC_SMOOTH_JACOBI && d->smoother != MGC_SMOOTH_GMRES3)
+    return fail(MGC_EINVAL, "smoother must be MGC_SMOOTH_JACOBI or MGC_SMOOTH_GMRES3");
   if (d->max_restart < 0 || d->max_restart > MGC_MAX_RESTART)
     return fail(MGC_EINVAL, "max_restart must lie in [0, 16]");
   if ((d->precisions & 1) == 0 || (d->precisions & ~3)) return fail(MGC_EINVAL, "precisions must include MGC_FP64");

@@ -2950,6 +2950,140 @@ void launch_sweep_testfn(hipStream_t s, int n, int j0, double h, double Z1, int 
   hipLaunchKernelGGL(k_sweep_testfn, dim3((2 * pp + 63) / 64), dim3(64), 0, s, n, j0, h, Z1, npairs, pp, kk, F);
 }
 // ----------------------------------------------------------------------------
+// GMRES(3) smoothing substitute of the V-cycle (Sec. 6.1), on one level:
+// u += V y with y minimising ||f - A(u + V y)|| over K_3(A, r0):
+//   V0 = f - A u (k_stencil, ||V0||^2 partials);  V0 /= beta   k_gs_normalize
+//   for i = 0, 1, 2:  V_{i+1} = A V_i, V_q^H V_{i+1}         k_gs_arnoldi
+//                     H[q][i] = V_q^H V_{i+1}, V_{i+1} -= sum H[q][i] V_q,
+//                     ||V_{i+1}||^2                           k_gs_orth
+//                     H[i+1][i] = ||V_{i+1}||, V_{i+1} /= it  k_gs_normalize
+//   y = argmin ||beta e1 - H y|| by Givens rotations         k_gs_solve
+//   u += sum y_i V_i                                         k_gs_update
+// Classical Gram-Schmidt in one pass; an exact breakdown (a zero norm) ends
+// the space there.  State st (doubles): H (4 x 3 complex, column-major) at 0,
+// beta at GS_BETA, y (3 complex) at GS_Y.
+constexpr int GS_M = 3, GS_BETA = 24, GS_Y = 26;
+__device__ __forceinline__ int gs_h(int row, int col) { return 2 * (col * (GS_M + 1) + row); }
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_gs_normalize(int n, int pitch, v2<T>* __restrict__ V,
+                                                      const double* __restrict__ part, int nb, int pstride,
+                                                      double* __restrict__ st, int slot) {
+  __shared__ double nn[1];
+  finish_sum_nt<256>(part, nb, 1, nn, pstride);
+  const double nrm = sqrt(nn[0]);
+  if (flat_block() == 0 && threadIdx.x == 0) {
+    st[slot] = nrm;
+    if (slot != GS_BETA) st[slot + 1] = 0.0;
+  }
+  const T sc = nrm > 0.0 ? (T)(1.0 / nrm) : T(0);
+  MGC_NODE_LOOP(n, k, j) {
+    const size_t idx = (size_t)k * pitch + j;
+    V[idx] = cscale(V[idx], sc);
+  }
+}
+template <typename T, int J>
+__global__ void __launch_bounds__(256) k_gs_arnoldi(Level<T> L, v2<T>* __restrict__ V, size_t stride,
+                                                    double* __restrict__ part) {
+  double acc[2 * J];
+#pragma unroll
+  for (int q = 0; q < 2 * J; ++q) acc[q] = 0.0;
+  const int n = L.n, p = L.pitch;
+  MGC_NODE_LOOP(n, k, j) {
+    const size_t idx = (size_t)k * p + j;
+    const v2<T> w = apply_at<T>(L, V + (size_t)(J - 1) * stride, k, j);
+    V[(size_t)J * stride + idx] = w;
+#pragma unroll
+    for (int q = 0; q < J; ++q) {
+      const v2<T> v = V[(size_t)q * stride + idx];
+      acc[2 * q] += (double)v.x * w.x + (double)v.y * w.y;
+      acc[2 * q + 1] += (double)v.x * w.y - (double)v.y * w.x;
+    }
+  }
+  double tot[2 * J];
+  block_sum<2 * J>(acc, tot);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < 2 * J; ++q) part[(size_t)flat_block() * (2 * J) + q] = tot[q];
+  }
+}
+template <typename T, int J>
+__global__ void __launch_bounds__(256) k_gs_orth(int n, int pitch, v2<T>* __restrict__ V, size_t stride,
+                                                 const double* __restrict__ pin, int nbin, double* __restrict__ st,
+                                                 double* __restrict__ pout) {
+  __shared__ double h[2 * J];
+  finish_sum_nt<256>(pin, nbin, 2 * J, h);
+  if (flat_block() == 0 && threadIdx.x < 2 * J) st[gs_h(threadIdx.x / 2, J - 1) + (threadIdx.x & 1)] = h[threadIdx.x];
+  v2<T> c[J];
+#pragma unroll
+  for (int q = 0; q < J; ++q) c[q] = mk<T>((T)h[2 * q], (T)h[2 * q + 1]);
+  double acc[1] = {0.0};
+  MGC_NODE_LOOP(n, k, j) {
+    const size_t idx = (size_t)k * pitch + j;
+    v2<T> w = V[(size_t)J * stride + idx];
+#pragma unroll
+    for (int q = 0; q < J; ++q) w = csub(w, cmul(c[q], V[(size_t)q * stride + idx]));
+    V[(size_t)J * stride + idx] = w;
+    acc[0] += (double)w.x * w.x + (double)w.y * w.y;
+  }
+  double tot[1];
+  block_sum<1>(acc, tot);
+  if (threadIdx.x == 0) pout[flat_block()] = tot[0];
+}
+__global__ void k_gs_solve(double* st) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double2 H[GS_M + 1][GS_M], g[GS_M + 1];
+  for (int c = 0; c < GS_M; ++c)
+    for (int r = 0; r <= GS_M; ++r) H[r][c] = make_double2(st[gs_h(r, c)], st[gs_h(r, c) + 1]);
+  for (int r = 0; r <= GS_M; ++r) g[r] = make_double2(0.0, 0.0);
+  g[0] = make_double2(st[GS_BETA], 0.0);
+  int kd = GS_M;
+  for (int i = 0; i < GS_M; ++i)
+    if (H[i + 1][i].x == 0.0 && H[i + 1][i].y == 0.0) { kd = i + 1; break; }
+  double2 y[GS_M];
+  for (int i = 0; i < GS_M; ++i) y[i] = make_double2(0.0, 0.0);
+  if (st[GS_BETA] > 0.0) {
+    // Givens rotations G_i = [conj(c) conj(s); -s c] zero H[i+1][i]
+    for (int i = 0; i < kd; ++i) {
+      const double2 a = H[i][i], b = H[i + 1][i];
+      const double den = sqrt(a.x * a.x + a.y * a.y + b.x * b.x + b.y * b.y);
+      const double2 c = make_double2(a.x / den, a.y / den), sn = make_double2(b.x / den, b.y / den);
+      for (int col = i; col < kd; ++col) {
+        const double2 x1 = H[i][col], x2 = H[i + 1][col];
+        H[i][col] = cadd(cmul(make_double2(c.x, -c.y), x1), cmul(make_double2(sn.x, -sn.y), x2));
+        H[i + 1][col] = csub(cmul(c, x2), cmul(sn, x1));
+      }
+      const double2 g1 = g[i], g2 = g[i + 1];
+      g[i] = cadd(cmul(make_double2(c.x, -c.y), g1), cmul(make_double2(sn.x, -sn.y), g2));
+      g[i + 1] = csub(cmul(c, g2), cmul(sn, g1));
+    }
+    for (int i = kd - 1; i >= 0; --i) {
+      double2 acc = g[i];
+      for (int c = i + 1; c < kd; ++c) acc = csub(acc, cmul(H[i][c], y[c]));
+      y[i] = cdiv(acc, H[i][i]);
+    }
+  }
+  for (int i = 0; i < GS_M; ++i) {
+    st[GS_Y + 2 * i] = y[i].x;
+    st[GS_Y + 2 * i + 1] = y[i].y;
+  }
+}
+template <typename T>
+__global__ void __launch_bounds__(256) k_gs_update(int n, int pitch, const v2<T>* __restrict__ V, size_t stride,
+                                                   const double* __restrict__ st, v2<T>* __restrict__ u) {
+  v2<T> y[GS_M];
+#pragma unroll
+  for (int q = 0; q < GS_M; ++q) y[q] = mk<T>((T)st[GS_Y + 2 * q], (T)st[GS_Y + 2 * q + 1]);
+  MGC_NODE_LOOP(n, k, j) {
+    const size_t idx = (size_t)k * pitch + j;
+    v2<T> v = u[idx];
+#pragma unroll
+    for (int q = 0; q < GS_M; ++q) v = cadd(v, cmul(y[q], V[(size_t)q * stride + idx]));
+    u[idx] = v;
+  }
+}
+
+// ----------------------------------------------------------------------------
 // BiCGSTAB outer loop (MGC_BICGSTAB), one iteration:
 //   p = r + beta (p - omega v)                              k_bicg_p
 //   p^ = B p  (one MG-CCCS cycle);  v = A p^, r~^H v        k_apply_dot (J = 1)
@@ -3104,6 +3238,37 @@ void launch_bound_weights(hipStream_t s, int n, int top, int j0, double h, int n
   const int blocks = (int)std::min<size_t>(1024, (total + 255) / 256);
   hipLaunchKernelGGL(k_bound_weights, dim3(blocks), dim3(256), 0, s, n, top, j0, h, nstates, pp, tab, F2);
 }
+
+template <typename T>
+void launch_gmres3_smooth(hipStream_t s, const Level<T>& L, void* u, const void* f, void* V, size_t stride, double* st,
+                          double* part) {
+  const int n = L.n, p = L.pitch;
+  const dim3 vg = vec_grid(n);
+  const int nbv = vec_blocks(n), nbs = stencil_blocks(n);
+  double* pa = part;                       // dots of the Arnoldi step: nbv x 6
+  double* pb = part + (size_t)nbv * 2 * GS_M;   // squared norms: max(nbv, 2 nbs)
+  v2<T>* Vt = (v2<T>*)V;
+  hipLaunchKernelGGL((k_stencil<T, T, T, T>), stencil_grid(n), dim3(SX, SY), 0, s, L, (const v2<T>*)u,
+                     (const v2<T>*)f, Vt, 0, pb);
+  hipLaunchKernelGGL((k_gs_normalize<T>), vg, dim3(256), 0, s, n, p, Vt, (const double*)pb, nbs, 2, st, GS_BETA);
+#define MGC_GS_STEP(JJ)                                                                                       \
+  hipLaunchKernelGGL((k_gs_arnoldi<T, JJ>), vg, dim3(256), 0, s, L, Vt, stride, pa);                          \
+  hipLaunchKernelGGL((k_gs_orth<T, JJ>), vg, dim3(256), 0, s, n, p, Vt, stride, (const double*)pa, nbv, st, pb); \
+  hipLaunchKernelGGL((k_gs_normalize<T>), vg, dim3(256), 0, s, n, p, Vt + (size_t)JJ * stride, (const double*)pb, \
+                     nbv, 1, st, 2 * ((JJ - 1) * (GS_M + 1) + JJ));
+  MGC_GS_STEP(1)
+  MGC_GS_STEP(2)
+  MGC_GS_STEP(3)
+#undef MGC_GS_STEP
+  hipLaunchKernelGGL(k_gs_solve, dim3(1), dim3(1), 0, s, st);
+  hipLaunchKernelGGL((k_gs_update<T>), vg, dim3(256), 0, s, n, p, (const v2<T>*)Vt, stride, (const double*)st,
+                     (v2<T>*)u);
+}
+template void launch_gmres3_smooth<double>(hipStream_t, const Level<double>&, void*, const void*, void*, size_t,
+                                           double*, double*);
+template void launch_gmres3_smooth<float>(hipStream_t, const Level<float>&, void*, const void*, void*, size_t,
+                                          double*, double*);
+int gmres3_part_doubles(int n) { return vec_blocks(n) * 2 * GS_M + std::max(vec_blocks(n), 2 * stencil_blocks(n)); }
 
 void launch_bicg_init(hipStream_t s, double* bs, const double* nrm2) {
   hipLaunchKernelGGL(k_bicg_init, dim3(1), dim3(1), 0, s, bs, nrm2);

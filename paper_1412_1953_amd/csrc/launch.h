@@ -159,6 +159,13 @@ int zeta_sweep_blocks(int top);
 // zero for the padding pairs npairs .. pp - 1.  Needs 1 <= j0 and n >= 2.
 void launch_sweep_testfn(hipStream_t s, int n, int j0, double h, double Z1, int npairs, int pp, const double* kk,
                          double* F);
+// One GMRES(3) smoothing step on a level (Sec. 6.1): u += V y minimising
+// ||f - A(u + V y)|| over K_3(A, f - A u).  V: 4 level fields `stride`
+// elements apart; st: 32 doubles of state; part: gmres3_part_doubles(n).
+template <typename T>
+void launch_gmres3_smooth(hipStream_t s, const Level<T>& L, void* u, const void* f, void* V, size_t stride, double* st,
+                          double* part);
+int gmres3_part_doubles(int n);
 // BiCGSTAB (see kernels.hip): bs = device scalar state (11 doubles); the
 // partial buffers hold at most 3 x 512 doubles.
 void launch_bicg_init(hipStream_t s, double* bs, const double* nrm2);

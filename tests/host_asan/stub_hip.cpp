@@ -341,6 +341,15 @@ void launch_zeta_part(hipStream_t s, int, int, int, const double2*, const double
 void launch_sweep_testfn(hipStream_t s, int, int, double, double, int, int, const double*, double*) { MGC_NOP(s); }
 void launch_bound_weights(hipStream_t s, int, int, int, double, int, int, const double2*, double*) { MGC_NOP(s); }
 void launch_bicg_init(hipStream_t s, double*, const double*) { MGC_NOP(s); }
+template <typename T>
+void launch_gmres3_smooth(hipStream_t s, const Level<T>&, void*, const void*, void*, size_t, double*, double*) {
+  MGC_NOP(s);
+}
+template void launch_gmres3_smooth<double>(hipStream_t, const Level<double>&, void*, const void*, void*, size_t,
+                                           double*, double*);
+template void launch_gmres3_smooth<float>(hipStream_t, const Level<float>&, void*, const void*, void*, size_t, double*,
+                                          double*);
+int gmres3_part_doubles(int n) { return 8 * n; }
 void launch_bicg_p(hipStream_t s, int, int, const double2*, const double2*, double2*, const double*) { MGC_NOP(s); }
 void launch_bicg_s(hipStream_t s, int, int, const double*, double*, const double2*, const double2*, double2*, double*) {
   MGC_NOP(s);

@@ -98,3 +98,43 @@ def test_full_contour_system(fp32):
     with pytest.raises(mgcccs.MGCError) as e:                  # amplitudes need a real interior
         g.cross_section(ut, ft, 0.5, 0.5)
     assert e.value.status == mgcccs.MGC_EINVAL
+
+
+GS = [Case(64, 20.0, 0.6, 4, 3, pc_gamma=GAM, smoother=1), Case(128, 20.0, 1.2, 5, 2, R0frac=1.0, gamma=GAM,
+                                                              pc_gamma=GAM, pc_gamma0=GAM, smoother=1)]
+
+
+@pytest.mark.parametrize("c", GS, ids=["n64_ecs", "n128_contour"])
+@pytest.mark.parametrize("fp32", [False, True], ids=["fp64", "fp32"])
+def test_gmres3_smoothed_vcycle(c, fp32):
+    """The V-cycle with the GMRES(3) smoothing substitute (Sec. 6.1) against
+    the oracle's hierarchy with the same smoother: from a random guess (one
+    smoothing step per level and pass, the Krylov space of each residual)."""
+    g = c.grid()
+    o = c.oracle()
+    f = c.rand(2)
+    u = c.u0()
+    ut, ft = g.from_numpy(u, fp32), g.from_numpy(f, fp32)
+    g.vcycle(ut, ft)
+    ref = o.mg.vcycle(u, f)
+    err = np.abs(to_np(ut) - ref).max() / np.abs(ref).max()
+    assert err < (2e-4 if fp32 else 1e-11), err
+
+
+@pytest.mark.parametrize("c", GS, ids=["n64_ecs", "n128_contour"])
+@pytest.mark.parametrize("fp32", [False, True], ids=["fp64", "fp32"])
+def test_gmres3_smoothed_fgmres_matches_direct_solve(c, fp32):
+    from paper_1412_1953_amd import mgcccs
+    g = c.grid()
+    o = c.oracle()
+    n = c.n
+    f = c.rand(2)
+    ut, ft = g.from_numpy(c.u0()), g.from_numpy(f)
+    r = g.solve(ut, ft, outer=mgcccs.FGMRES, inner=mgcccs.FP32 if fp32 else mgcccs.FP64, restart=10, max_it=400,
+                tol=1e-11)
+    assert r.status == mgcccs.MGC_OK, r
+    ref = o.solve_fgmres(c.u0(), f, 1e-11, restart=10, max_it=400)
+    if not fp32:
+        assert abs(r.iters - ref.iters) <= 1, (r.iters, ref.iters)
+    x = spla.spsolve(o.op.sparse(), f[1:n, 1:n].ravel()).reshape(n - 1, n - 1)
+    assert rel2(to_np(ut)[1:n, 1:n], x) < 1e-9
