@@ -46,7 +46,8 @@ class MGCCCS:
 
     def __init__(self, n, L, R0, theta, Z1, Z2, lam, E, levels, M,
                  omega=2.0 / 3.0, nu1=1, nu2=1, Lch=None, refine_steps=2,
-                 pc_gamma=0.0, pc_first_level=0, pc_gamma0=0.0, gamma=0.0, smoother="jacobi"):
+                 pc_gamma=0.0, pc_first_level=0, pc_gamma0=0.0, gamma=0.0, smoother="jacobi",
+                 pc_order="mg-cccs"):
         # gamma: contour angle of the system itself (Sec. 3.1; 0 = the
         # exterior-complex-scaled grid with a real interior)
         self.g = Grid1D(n, L, R0, theta, gamma)
@@ -57,6 +58,9 @@ class MGCCCS:
         self.pc_op = self.mg.ops[0]                         # level 0 of the hierarchy
         self.M = M
         self.cc = CCCS(self.pc_op, M, Lch, refine_steps) if M > 0 else None
+        if pc_order not in ("mg-cccs", "deflation"):
+            raise ValueError("pc_order: 'mg-cccs' or 'deflation'")
+        self.pc_order = pc_order
 
     @classmethod
     def from_workload(cls, w, **kw):
@@ -77,7 +81,19 @@ class MGCCCS:
         return u
 
     def precondition(self, v: np.ndarray) -> np.ndarray:
-        """z = one MG-CCCS cycle on A z = v from z = 0 (a fixed linear map)."""
+        """z = one MG-CCCS cycle on A z = v from z = 0 (a fixed linear map).
+
+        pc_order = 'deflation' embeds the channel correction as a deflation
+        step instead (Sec. 7, the alternative the paper names; the additive
+        coarse-space form of deflated Krylov preconditioners): the channel
+        correction of v first, z1 = e*(v), then the V-cycle on the deflated
+        residual, z = z1 + V(v - A z1).  On residuals that lie in the channel
+        space and without two-body coupling the correction is exact and the
+        V-cycle then sees a zero residual."""
+        if self.pc_order == "deflation" and self.cc is not None:
+            z1 = self.cc.correction(v)
+            r1 = self.pc_op.residual(z1, v)
+            return z1 + self.mg.vcycle(np.zeros_like(v), r1)
         return self.cycle(np.zeros_like(v), v)
 
     # ------------------------------------------------------------------ #

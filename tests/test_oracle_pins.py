@@ -528,6 +528,41 @@ def test_planted_channel_system_mistakes_break_the_projected_identity(mistake):
     assert np.abs(pA[1:n] - rA[1:n]).max() > 1e-3 * np.abs(rA).max()
 
 
+# ---------------------------------------------------------------- N4 -------
+def test_deflation_ordering_is_exact_on_the_channel_space():
+    """Sec. 7 (the channel correction as a deflation step): at lambda = 0 a
+    residual in the channel space is solved exactly by the correction, so the
+    deflation-ordered preconditioner returns A^{-1} v (the V-cycle then sees a
+    zero residual), while the paper's V-cycle-first cycle does not."""
+    n = 64
+    kw = dict(n=n, L=20.0, R0=15.0, theta=math.pi / 6, Z1=1.0, Z2=0.9, lam=0.0, E=0.3, levels=4, M=4, Lch=3,
+              pc_gamma=math.radians(15.0), pc_first_level=1)
+    sd = MGCCCS(pc_order="deflation", **kw)
+    sm = MGCCCS(**kw)
+    rng = np.random.default_rng(17)
+    rA = np.zeros((n + 1, 4), complex)
+    rB = np.zeros((n + 1, 3), complex)
+    rA[1:n] = rng.standard_normal((n - 1, 4)) + 1j * rng.standard_normal((n - 1, 4))
+    rB[1:n] = rng.standard_normal((n - 1, 3)) + 1j * rng.standard_normal((n - 1, 3))
+    v = sd.cc.expand(rA, rB)
+    x = spla.spsolve(sd.op.sparse(), v[1:n, 1:n].ravel())
+    zd = sd.precondition(v)[1:n, 1:n].ravel()
+    zm = sm.precondition(v)[1:n, 1:n].ravel()
+    assert np.linalg.norm(zd - x) < 1e-9 * np.linalg.norm(x)
+    assert np.linalg.norm(zm - x) > 1e-4 * np.linalg.norm(x)
+
+
+@pytest.mark.parametrize("lam", [0.0, 1.0])
+def test_deflated_fgmres_converges_to_the_dense_direct_solution(lam):
+    n = 32
+    s = MGCCCS(n, 10.0, 7.5, math.pi / 6, 1.0, 1.0, lam, 0.4, 3, 3, pc_gamma=math.radians(10), pc_order="deflation")
+    f = s.rhs() if lam else rng_field(n, 19)
+    x = np.linalg.solve(s.op.sparse().toarray(), f[1:n, 1:n].ravel())
+    r = s.solve_fgmres(initial_guess(n, 1), f, 1e-12, restart=10, max_it=300)
+    assert r.relres <= 1e-12
+    assert np.linalg.norm(r.u[1:n, 1:n].ravel() - x) / np.linalg.norm(x) < 1e-10
+
+
 # ---------------------------------------------------------------- P9 / P15 -
 def test_symmetric_problem_has_a_symmetric_solution():
     n = 32
