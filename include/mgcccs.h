@@ -110,10 +110,19 @@ typedef struct mgc_grid_s* mgc_grid;   /* opaque, library-owned host object */
  *          Sec. 6.1; u += V y minimising the level's residual over the
  *          3-dimensional Krylov space of its residual), which takes four more
  *          fields per level and runs the cycle's general (per-level) path.
+ * pc_order MGC_PC_MG_CCCS (0): the Krylov preconditioner is the MG-CCCS
+ *          cycle of Sec. 4.3 (V-cycle, then the channel correction of its
+ *          residual); MGC_PC_DEFLATION (1): the channel correction embedded as
+ *          a deflation step (the alternative named in Sec. 7): z1 = e*(v)
+ *          first, then z = z1 + V(v - A z1) with one V-cycle from zero on the
+ *          deflated residual.  Applies to the FGMRES and BiCGSTAB
+ *          preconditioner; takes one more level-0 field per precision.
  * precisions   bit mask (1 << MGC_FP64) | (1 << MGC_FP32) of the cycle
  *          precisions the workspace must hold.                                */
 #define MGC_SMOOTH_JACOBI 0
 #define MGC_SMOOTH_GMRES3 1
+#define MGC_PC_MG_CCCS 0
+#define MGC_PC_DEFLATION 1
 typedef struct {
   int n;
   double L, R0, theta;
@@ -128,6 +137,7 @@ typedef struct {
   double pc_gamma0;
   double gamma;
   int smoother;
+  int pc_order;
 } mgc_grid_desc;
 
 typedef struct {

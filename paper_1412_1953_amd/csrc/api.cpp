@@ -112,6 +112,7 @@ struct mgc_grid_s {
   CcOff cc[2];
   size_t part = 0, scal = 0;               // reduction partials, small scalars
   size_t gspart = 0;                       // partials of the GMRES(3) smoother
+  size_t dfl[2] = {0, 0};                  // deflation-ordered preconditioner: residual, V-cycle correction
   size_t apart = 0;                        // 3 x ARNOLDI_PART partials of the Arnoldi passes
   bool basis_dirty = false;                // Krylov basis may hold non-finite values
   size_t r64 = 0, f32 = 0, u32 = 0, tw = 0, tz = 0;
@@ -230,6 +231,9 @@ void layout(mgc_grid g) {
   const int nb = std::max(launch_stencil_blocks(n), launch_vec_blocks(n));
   g->part = take((size_t)nb * 64 * sizeof(double));
   if (g->d.smoother == MGC_SMOOTH_GMRES3) g->gspart = take((size_t)gmres3_part_doubles(n) * sizeof(double));
+  if (g->d.pc_order == MGC_PC_DEFLATION)
+    for (int p = 0; p < 2; ++p)
+      if (g->prec_on[p]) g->dfl[p] = take(2 * g->field_bytes(0, p));
   g->scal = take(256 * sizeof(double));
   g->apart = take((size_t)3 * ARNOLDI_PART * sizeof(double));
   g->r64 = take(g->field_bytes(0, P64));
@@ -685,6 +689,33 @@ void mgcccs_cycle(mgc_grid g, void* u, const void* f, bool zero_guess, const dou
   cccs_apply<T>(g, u, f, fs);
 }
 
+// The Krylov preconditioner z = B v from zero: the MG-CCCS cycle, or with
+// pc_order = MGC_PC_DEFLATION the channel correction first and one V-cycle
+// from zero on the deflated residual, z = e*(v) + V(v - A e*(v)).
+template <typename T>
+void precondition(mgc_grid g, void* z, const void* v, const double* fs = nullptr) {
+  if (g->d.pc_order != MGC_PC_DEFLATION || (g->d.M == 0 && g->d.Lch == 0)) {
+    mgcccs_cycle<T>(g, z, v, true, fs);
+    return;
+  }
+  const int p = sizeof(T) == 8 ? P64 : P32;
+  const int n = g->d.n, pitch = g->lv[0].pitch;
+  hipStream_t s = g->stream;
+  if (fs) {
+    void* tmp = p == P64 ? (void*)(g->ws + g->tw) : (void*)(g->ws + g->f32);
+    launch_scale_copy<T, T>(s, n, pitch, pitch, v, fs, tmp);
+    v = tmp;
+  }
+  launch_fill_zero(s, z, g->field_bytes(0, p));
+  cccs_apply<T>(g, z, v);                                     // z1 = e*(v)
+  // own buffers: the level-0 smoothing passes ping-pong through lv[0].ft
+  void* r1 = g->ws + g->dfl[p];
+  void* e = g->ws + g->dfl[p] + g->field_bytes(0, p);
+  launch_stencil<T, T, T, T>(s, level_of<T>(g, 0), z, v, r1, 0, nullptr);   // v - A z1
+  vcycle_level<T>(g, 0, e, r1, true);
+  launch_add<T>(s, n, pitch, e, z);
+}
+
 // relres of (u, f) with the exact operator; r written to r64.  Synchronises.
 mgc_status exact_residual(mgc_grid g, const void* u, const void* f, void* r, double* rr2, double* ff2,
                           double* copy_to = nullptr) {
@@ -809,11 +840,11 @@ void enqueue_fgmres_cycle(mgc_grid g, void* u, const mgc_solve_opts* o, double t
     const int ta = kt_slot(g, MGC_KT_APPLY_DOT, Nint * ((f32 ? 8.0 : 16.0) + 16.0 * (j + 1) + 16.0));
     if (f32) {
       launch_scale_copy<double, float>(st, n, pitch, pitch, Wj, gs.scale + j, g->ws + g->f32);
-      mgcccs_cycle<float>(g, Zj, g->ws + g->f32, true);
+      precondition<float>(g, Zj, g->ws + g->f32);
       kt_mark(g, st, ta, 0);
       launch_apply_dot<float>(st, EX, Zj, stride64, W, j + 1, Wn, p0);
     } else {
-      mgcccs_cycle<double>(g, Zj, Wj, true, gs.scale + j);
+      precondition<double>(g, Zj, Wj, gs.scale + j);
       kt_mark(g, st, ta, 0);
       launch_apply_dot<double>(st, EX, Zj, stride64, W, j + 1, Wn, p0);
     }
@@ -937,20 +968,20 @@ void enqueue_bicg_iteration(mgc_grid g, void* u, const mgc_solve_opts* o, double
   Level<double> EX = exact_level(g);
   hipStream_t saved = g->stream;
   g->stream = st;
-  auto precondition = [&](const double2* in, void* out) {
+  auto apply_pc = [&](const double2* in, void* out) {
     if (f32) {
       launch_scale_copy<double, float>(st, n, pitch, pitch, in, nullptr, g->ws + g->f32);
-      mgcccs_cycle<float>(g, out, g->ws + g->f32, true);
+      precondition<float>(g, out, g->ws + g->f32);
     } else {
-      mgcccs_cycle<double>(g, out, in, true);
+      precondition<double>(g, out, in);
     }
   };
   launch_bicg_p(st, n, pitch, r, v, p, bs);
-  precondition(p, ph);
+  apply_pc(p, ph);
   if (f32) launch_apply_dot<float>(st, EX, ph, s64, rt, 1, v, p0);
   else launch_apply_dot<double>(st, EX, ph, s64, rt, 1, v, p0);
   launch_bicg_s(st, n, pitch, p0, bs, r, v, sv, p1);
-  precondition(sv, sh);
+  apply_pc(sv, sh);
   if (f32) launch_apply_dot<float>(st, EX, sh, s64, sv, 1, t, p2);
   else launch_apply_dot<double>(st, EX, sh, s64, sv, 1, t, p2);
   if (f32) launch_bicg_x<float>(st, n, pitch, p2, p1, tol2, bs, ph, sh, sv, t, rt, r, (double2*)u, p0);
@@ -1101,6 +1132,8 @@ mgc_status mgc_create_grid(const mgc_grid_desc* d, void* hip_stream, mgc_grid* o
   if (d->pc_first_level < 0) return fail(MGC_EINVAL, "pc_first_level must be >= 0");
   if (d->smoother != MGC_SMOOTH_JACOBI && d->smoother != MGC_SMOOTH_GMRES3)
     return fail(MGC_EINVAL, "smoother must be MGC_SMOOTH_JACOBI or MGC_SMOOTH_GMRES3");
+  if (d->pc_order != MGC_PC_MG_CCCS && d->pc_order != MGC_PC_DEFLATION)
+    return fail(MGC_EINVAL, "pc_order must be MGC_PC_MG_CCCS or MGC_PC_DEFLATION");
   if (d->max_restart < 0 || d->max_restart > MGC_MAX_RESTART)
     return fail(MGC_EINVAL, "max_restart must lie in [0, 16]");
   if ((d->precisions & 1) == 0 || (d->precisions & ~3)) return fail(MGC_EINVAL, "precisions must include MGC_FP64");

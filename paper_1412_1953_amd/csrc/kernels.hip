@@ -3240,6 +3240,20 @@ void launch_bound_weights(hipStream_t s, int n, int top, int j0, double h, int n
 }
 
 template <typename T>
+__global__ void __launch_bounds__(256) k_add(int n, int pitch, const v2<T>* __restrict__ e, v2<T>* __restrict__ u) {
+  MGC_NODE_LOOP(n, k, j) {
+    const size_t idx = (size_t)k * pitch + j;
+    u[idx] = cadd(u[idx], e[idx]);
+  }
+}
+template <typename T>
+void launch_add(hipStream_t s, int n, int pitch, const void* e, void* u) {
+  hipLaunchKernelGGL((k_add<T>), vec_grid(n), dim3(256), 0, s, n, pitch, (const v2<T>*)e, (v2<T>*)u);
+}
+template void launch_add<double>(hipStream_t, int, int, const void*, void*);
+template void launch_add<float>(hipStream_t, int, int, const void*, void*);
+
+template <typename T>
 void launch_gmres3_smooth(hipStream_t s, const Level<T>& L, void* u, const void* f, void* V, size_t stride, double* st,
                           double* part) {
   const int n = L.n, p = L.pitch;

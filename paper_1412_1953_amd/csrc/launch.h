@@ -166,6 +166,9 @@ template <typename T>
 void launch_gmres3_smooth(hipStream_t s, const Level<T>& L, void* u, const void* f, void* V, size_t stride, double* st,
                           double* part);
 int gmres3_part_doubles(int n);
+// u += e on the interior of a level-0 field
+template <typename T>
+void launch_add(hipStream_t s, int n, int pitch, const void* e, void* u);
 // BiCGSTAB (see kernels.hip): bs = device scalar state (11 doubles); the
 // partial buffers hold at most 3 x 512 doubles.
 void launch_bicg_init(hipStream_t s, double* bs, const double* nrm2);

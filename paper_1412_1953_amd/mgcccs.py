@@ -22,6 +22,7 @@ FP64, FP32 = 0, 1
 SWEEP_MAX = 256                      # MGC_SWEEP_MAX
 STATIONARY, IR, FGMRES, BICGSTAB = 0, 1, 2, 3
 SMOOTH_JACOBI, SMOOTH_GMRES3 = 0, 1
+PC_MG_CCCS, PC_DEFLATION = 0, 1
 
 EXPORTED = ["mgc_create_grid", "mgc_workspace_bytes", "mgc_bind_workspace", "mgc_field_pitch",
             "mgc_set_potential", "mgc_set_energy", "mgc_build_rhs_tp", "mgc_residual", "mgc_vcycle",
@@ -42,7 +43,7 @@ class GridDesc(ctypes.Structure):
                 ("Lch", ctypes.c_int), ("omega", ctypes.c_double), ("nu1", ctypes.c_int),
                 ("nu2", ctypes.c_int), ("pc_gamma", ctypes.c_double), ("pc_first_level", ctypes.c_int),
                 ("max_restart", ctypes.c_int), ("precisions", ctypes.c_int), ("pc_gamma0", ctypes.c_double),
-                ("gamma", ctypes.c_double), ("smoother", ctypes.c_int)]
+                ("gamma", ctypes.c_double), ("smoother", ctypes.c_int), ("pc_order", ctypes.c_int)]
 
 
 class Schedule(ctypes.Structure):
@@ -151,14 +152,15 @@ class Grid:
 
     def __init__(self, n, L, R0, theta, levels, M, Lch=None, omega=2.0 / 3.0, nu1=1, nu2=1,
                  pc_gamma=0.0, pc_first_level=0, max_restart=16, fp32=True, device="cuda:0",
-                 pc_gamma0=0.0, gamma=0.0, smoother=0):
+                 pc_gamma0=0.0, gamma=0.0, smoother=0, pc_order=0):
         import torch
         self.torch = torch
         self.lib = load_library()
         self.device = torch.device(device)
         Lch = M if Lch is None else Lch
         self.desc = GridDesc(n, L, R0, theta, levels, M, Lch, omega, nu1, nu2, pc_gamma,
-                             pc_first_level, max_restart, 1 | (2 if fp32 else 0), pc_gamma0, gamma, smoother)
+                             pc_first_level, max_restart, 1 | (2 if fp32 else 0), pc_gamma0, gamma, smoother,
+                             pc_order)
         self.n, self.levels, self.M, self.Lch = n, levels, M, Lch
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)

@@ -30,6 +30,7 @@ class Case:
     pc_gamma0: float = 0.0
     gamma: float = 0.0
     smoother: int = 0
+    pc_order: int = 0
     pc_first_level: int = 0
     seed: int = 11
 
@@ -41,13 +42,14 @@ class Case:
         return MGCCCS(self.n, self.L, self.R0, self.theta, self.Z1, self.Z2, self.lam, self.E,
                       self.levels, self.M, pc_gamma=self.pc_gamma, pc_gamma0=self.pc_gamma0, gamma=self.gamma,
                       smoother=("gmres3" if self.smoother else "jacobi"),
+                      pc_order=("deflation" if self.pc_order else "mg-cccs"),
                       pc_first_level=self.pc_first_level, **kw)
 
     def grid(self, max_restart=10, fp32=True):
         from paper_1412_1953_amd import mgcccs
         g = mgcccs.Grid(self.n, self.L, self.R0, self.theta, self.levels, self.M,
                         pc_gamma=self.pc_gamma, pc_first_level=self.pc_first_level, pc_gamma0=self.pc_gamma0,
-                        gamma=self.gamma, smoother=self.smoother,
+                        gamma=self.gamma, smoother=self.smoother, pc_order=self.pc_order,
                         max_restart=max_restart, fp32=fp32)
         g.set_potential(self.Z1, self.Z2, self.lam)
         g.set_energy(self.E)

@@ -350,6 +350,10 @@ template void launch_gmres3_smooth<double>(hipStream_t, const Level<double>&, vo
 template void launch_gmres3_smooth<float>(hipStream_t, const Level<float>&, void*, const void*, void*, size_t, double*,
                                           double*);
 int gmres3_part_doubles(int n) { return 8 * n; }
+template <typename T>
+void launch_add(hipStream_t s, int, int, const void*, void*) { MGC_NOP(s); }
+template void launch_add<double>(hipStream_t, int, int, const void*, void*);
+template void launch_add<float>(hipStream_t, int, int, const void*, void*);
 void launch_bicg_p(hipStream_t s, int, int, const double2*, const double2*, double2*, const double*) { MGC_NOP(s); }
 void launch_bicg_s(hipStream_t s, int, int, const double*, double*, const double2*, const double2*, double2*, double*) {
   MGC_NOP(s);
