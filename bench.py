@@ -105,7 +105,8 @@ def use_schedule(problems, inner, wls):
 
 def time_steps(problems, inner, torch, steps, warmup, max_it, kclass=0, tol=1e-10):
     """Seconds per step; with kclass, the library's HIP-event timer brackets
-    every launch of that kernel inside the timed steps (on its own stream).
+    the launches of that kernel inside the timed steps (on the stream they
+    run on), in every fourth restart cycle of each solve.
     The timer is selected before the warmup, so that the restart graphs with
     the event nodes are captured outside the timed region."""
     for g, *_ in problems:
@@ -262,10 +263,11 @@ def c3_leg(torch, max_it):
     return out
 
 
-def hbm_leg(torch, kernels, iters=20):
+def hbm_leg(torch, kernels, iters=50):
     """4097^2 probe: every FP64 field (270 MB) exceeds the 256 MB on-die cache,
     so the finest-level passes stream from HBM.  Each kernel class is timed
-    over a short FGMRES(10) run of `iters` iterations (two restart cycles)."""
+    over a short FGMRES(10) run of `iters` iterations (five restart cycles, of
+    which the library's timer samples the first and the fifth)."""
     from paper_1412_1953_amd import mgcccs
     from paper_1412_1953_amd.workloads import TP4097 as w
     t0 = time.perf_counter()

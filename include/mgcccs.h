@@ -331,9 +331,12 @@ mgc_status mgc_cross_section_grad(mgc_grid g, const void* u, const void* chi, do
  * mgc_set_kernel_timer selects one kernel class.  While it is selected, its
  * launches inside the FGMRES restart cycles of mgc_solve and
  * mgc_solve_transpose are bracketed by HIP events recorded on the stream the
- * kernels run on (event nodes inside the captured restart graphs): every
- * Arnoldi step for the classes that depend on the step (APPLY_DOT, AXPY), the
- * first step of each restart cycle for the others.  S1 and S2 launches of
+ * kernels run on (event nodes inside the captured restart graphs), in every
+ * fourth restart cycle of a solve (the first included; the other cycles
+ * replay a graph without timer nodes, so that the nodes' own cost stays out
+ * of three quarters of the run): every Arnoldi step for the classes that
+ * depend on the step (APPLY_DOT, AXPY), the first step of the cycle for the
+ * others.  S1 and S2 launches of
  * all levels follow each other, so one event pair brackets each such run.
  * Right before each bracket a second event pair brackets one empty kernel
  * launch: its duration (floor_ms) is what the event nodes and a launch add

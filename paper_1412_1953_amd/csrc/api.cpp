@@ -72,6 +72,7 @@ struct GraphCache {                       // one captured FGMRES restart cycle
 // step of each restart cycle only (`open`).  Right before each bracket a
 // second pair (fev) brackets one empty launch: what the event nodes and a
 // launch add to a bracket, subtracted from the bracketed time.
+constexpr int KT_SAMPLE = 4;               // restart cycles per timed one
 struct KernelTimer {
   static constexpr int SLOTS = 4 * MGC_MAX_RESTART;
   int which = MGC_KT_NONE;
@@ -91,7 +92,8 @@ struct mgc_grid_s {
   mgc_schedule sched{-1, 1, 1};            // launch schedule (mgc_set_schedule)
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;               // capture stream (default priority)
-  GraphCache graph;
+  GraphCache graph;                        // restart cycle (with the timer's nodes when one is selected)
+  GraphCache plain;                        // the same cycle without timer nodes (unsampled cycles)
   GraphCache bicg_graph;                   // one captured BiCGSTAB iteration
   KernelTimer kt;
   int device = 0;
@@ -149,6 +151,8 @@ bool hip_ok(mgc_grid g, hipError_t e, const char* what) {
 void drop_graph(mgc_grid g) {
   if (g->graph.exec) (void)hipGraphExecDestroy(g->graph.exec);
   g->graph = GraphCache();
+  if (g->plain.exec) (void)hipGraphExecDestroy(g->plain.exec);
+  g->plain = GraphCache();
   if (g->bicg_graph.exec) (void)hipGraphExecDestroy(g->bicg_graph.exec);
   g->bicg_graph = GraphCache();
 }
@@ -900,34 +904,49 @@ mgc_status solve_fgmres(mgc_grid g, void* u, const void* f, const mgc_solve_opts
   const bool use_graph = std::getenv("MGC_NO_GRAPH") == nullptr;
   while (rel > o->tol && it < o->max_it && std::isfinite(rel)) {
     const int mm = std::min(m, o->max_it - it);
+    // with a timer class selected, every KT_SAMPLE-th restart cycle (the
+    // first included) runs with the timer's event nodes, the others without
+    const bool timed = g->kt.which != MGC_KT_NONE && rs % KT_SAMPLE == 0;
+    int kt_slots = 0;
     if (use_graph) {
-      GraphCache& gc = g->graph;
+      GraphCache& gc = timed || g->kt.which == MGC_KT_NONE ? g->graph : g->plain;
+      const int want = timed ? g->kt.which : MGC_KT_NONE;
       if (!gc.exec || gc.u != u || gc.f != f || gc.m != m || gc.mm != mm || gc.inner != (int)o->inner ||
-          gc.tol_abs != o->tol * fn || gc.kt != g->kt.which) {
+          gc.tol_abs != o->tol * fn || gc.kt != want) {
         if (gc.exec) { (void)hipGraphExecDestroy(gc.exec); gc.exec = nullptr; }
+        const int sel = g->kt.which;
+        g->kt.which = want;                // capture the untimed cycle without timer nodes
         hipGraph_t graph;
-        HIPCHK(g, hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal));
-        enqueue_fgmres_cycle(g, u, o, o->tol * fn, mm, g->cap);
-        HIPCHK(g, hipStreamEndCapture(g->cap, &graph));
+        hipError_t e = hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+          enqueue_fgmres_cycle(g, u, o, o->tol * fn, mm, g->cap);
+          e = hipStreamEndCapture(g->cap, &graph);
+        }
+        g->kt.which = sel;
+        HIPCHK(g, e);
         if (g->failed) {                   // a timer node could not be added
           (void)hipGraphDestroy(graph);
           return MGC_EHIP;
         }
-        hipError_t e = hipGraphInstantiate(&gc.exec, graph, nullptr, nullptr, 0);
+        e = hipGraphInstantiate(&gc.exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         HIPCHK(g, e);
         gc.u = u; gc.f = f; gc.m = m; gc.mm = mm; gc.inner = (int)o->inner; gc.tol_abs = o->tol * fn;
-        gc.kt = g->kt.which;
-        gc.kt_slots = g->kt.used;
+        gc.kt = want;
+        gc.kt_slots = timed ? g->kt.used : 0;
         gc.kt_bytes = g->kt.bytes;
         gc.kt_count = g->kt.count;
       }
       HIPCHK(g, hipGraphLaunch(gc.exec, s));
+      kt_slots = gc.kt_slots;
     } else {
+      const int sel = g->kt.which;
+      if (!timed) g->kt.which = MGC_KT_NONE;
       enqueue_fgmres_cycle(g, u, o, o->tol * fn, mm, s);
+      g->kt.which = sel;
       if (g->failed) return MGC_EHIP;
+      kt_slots = timed ? g->kt.used : 0;
     }
-    const int kt_slots = use_graph ? g->graph.kt_slots : g->kt.used;
     rc = exact_residual(g, u, f, W, &rr, &ff, gs.nrm2);
     if (rc) return rc;
     int kused = mm;
@@ -2163,6 +2182,7 @@ mgc_status mgc_batch_destroy(mgc_batch b) {
 mgc_status mgc_destroy_grid(mgc_grid g) {
   if (!g) return fail(MGC_EINVAL, "null handle");
   if (g->graph.exec) (void)hipGraphExecDestroy(g->graph.exec);
+  if (g->plain.exec) (void)hipGraphExecDestroy(g->plain.exec);
   if (g->bicg_graph.exec) (void)hipGraphExecDestroy(g->bicg_graph.exec);
   for (hipEvent_t e : g->kt.ev)
     if (e) (void)hipEventDestroy(e);

@@ -404,9 +404,10 @@ def test_level0_contour_angle(fp32):
 @pytest.mark.parametrize("kclass", [1, 2, 3, 4, 5, 6, 7, 8, 9],
                          ids=["apply", "axpy", "s1", "s2", "project", "chain", "s1fine", "s2fine", "expand"])
 def test_kernel_timer_counts_launches_and_leaves_results_unchanged(kclass, graph, monkeypatch):
-    """Event timing of one kernel class: launches counted per Arnoldi step
-    (operator pass, first axpy pass) or per restart cycle (S1/S2: one per level
-    above the coarse tail plus the tail launch; CCCS projection/chain 1), the
+    """Event timing of one kernel class in every fourth restart cycle (the
+    first included): launches counted per Arnoldi step (operator pass, first
+    axpy pass) or per timed restart cycle (S1/S2: one per level above the
+    coarse tail plus the tail launch; CCCS projection/chain 1), the
     algorithmic byte count of each class (FP64 inner cycle), and a
     bitwise-identical iterate."""
     from paper_1412_1953_amd import mgcccs
@@ -418,7 +419,7 @@ def test_kernel_timer_counts_launches_and_leaves_results_unchanged(kclass, graph
     g = c.grid()
     o = c.oracle()
     chi = tp_rhs(o.g, c.Z1, c.Z2, c.lam, c.E)
-    its = 23                                   # restart cycles of 10, 10, 3 steps
+    its = 43                                   # restart cycles of 10, 10, 10, 10, 3 steps
     u_ref, f = g.from_numpy(c.u0()), g.from_numpy(chi)
     g.solve(u_ref, f, outer=mgcccs.FGMRES, restart=10, max_it=its, tol=1e-300)
     g.set_kernel_timer(kclass)
@@ -428,17 +429,18 @@ def test_kernel_timer_counts_launches_and_leaves_results_unchanged(kclass, graph
     g.set_kernel_timer(mgcccs.KT_NONE)
     assert r.iters == its
     assert np.array_equal(to_np(u), to_np(u_ref))
-    # classes that do not depend on the Arnoldi step are timed in the first
-    # step of each restart cycle (3 cycles: 10, 10, 3 steps)
-    cycles = 3
+    # cycles 0 and 4 are timed (10 and 3 steps); classes that do not depend
+    # on the Arnoldi step are timed in the first step of a timed cycle
+    timed = [10, 3]
+    cycles = len(timed)
     # n = 64: level 64 by the fused passes, levels 32 and 16 in the coarse
     # tail (one launch down, one up)
-    want_launches = {mgcccs.KT_APPLY_DOT: its, mgcccs.KT_AXPY: its,
+    want_launches = {mgcccs.KT_APPLY_DOT: sum(timed), mgcccs.KT_AXPY: sum(timed),
                      mgcccs.KT_S1: 2 * cycles, mgcccs.KT_S2: 2 * cycles}.get(kclass, cycles)
     assert launches == want_launches
     assert ms > 0 and floor > 0
     n, N = c.n, (c.n - 1) ** 2
-    steps = [j for cyc in (10, 10, 3) for j in range(cyc)]
+    steps = [j for cyc in timed for j in range(cyc)]
     if kclass == mgcccs.KT_APPLY_DOT:
         want = sum(N * (16 + 16 * (j + 1) + 16) for j in steps)
     elif kclass == mgcccs.KT_AXPY:
