@@ -7,7 +7,9 @@ discretised with the 3-point finite-difference Laplacian (Sec. 2.5,
 eq. discrete_schrodinger) on a uniform real grid whose coordinates are
 rotated into the complex plane beyond R0 (exterior complex scaling, Sec. 2.5
 and Sec. 3.3).  Temkin-Poet potentials V1 = -Z1/x, V2 = -Z2/y,
-V12 = lambda/max(x,y) (Sec. 5.2 and Sec. 6.2).
+V12 = lambda/max(x,y) (Sec. 5.2 and Sec. 6.2), or the exponential model
+V1 = -a1 exp(-b1 x^2), V2 = -a2 exp(-b2 y^2), V12 = c12 exp(-d12 (x+y)^2)
+(Sec. 6.1; Sec. 3.3 Fig. 4).
 
 Arrays are full ``(n+1, n+1)`` complex arrays indexed ``[k, j]`` with ``k``
 along x2 (= y) and ``j`` along x1 (= x); row/column 0 and n are the Dirichlet
@@ -108,6 +110,48 @@ def tp_two_body(g: Grid1D, lam: float) -> np.ndarray:
     return V
 
 
+def exp_one_body(g: Grid1D, a: float, b: float) -> np.ndarray:
+    """-a exp(-b z_j^2) on the interior nodes, zero on the ring (the
+    exponential model of Sec. 6.1 and Sec. 3.3 Fig. 4)."""
+    V = np.zeros(g.n + 1, np.complex128)
+    z = g.z[1:g.n]
+    V[1:g.n] = -a * np.exp(-b * z * z)
+    return V
+
+
+def exp_two_body(g: Grid1D, c: float, d: float) -> np.ndarray:
+    """V12[k, j] = c exp(-d (z_j + z_k)^2) on interior nodes (Sec. 6.1:
+    c = 2, d = 0.1; Sec. 3.3 Fig. 4: c = 2, d = 1)."""
+    n = g.n
+    V = np.zeros((n + 1, n + 1), np.complex128)
+    s = g.z[1:n, None] + g.z[None, 1:n]
+    V[1:n, 1:n] = c * np.exp(-d * s * s)
+    return V
+
+
+class TPModel:
+    """Temkin-Poet potentials -Z1/x1, -Z2/x2, lambda/max(x1, x2)."""
+
+    def __init__(self, Z1: float, Z2: float, lam: float):
+        self.Z1, self.Z2, self.lam = Z1, Z2, lam
+
+    def potentials(self, g: Grid1D):
+        return tp_one_body(g, self.Z1), tp_one_body(g, self.Z2), tp_two_body(g, self.lam)
+
+
+class ExpModel:
+    """Exponential potentials V1 = -a1 exp(-b1 x1^2), V2 = -a2 exp(-b2 x2^2),
+    V12 = c12 exp(-d12 (x1 + x2)^2), continued analytically onto the complex
+    nodes (Sec. 6.1; the defaults are its values)."""
+
+    def __init__(self, a1=4.5, b1=1.0, a2=4.5, b2=1.0, c12=2.0, d12=0.1):
+        self.a1, self.b1, self.a2, self.b2, self.c12, self.d12 = a1, b1, a2, b2, c12, d12
+
+    def potentials(self, g: Grid1D):
+        return (exp_one_body(g, self.a1, self.b1), exp_one_body(g, self.a2, self.b2),
+                exp_two_body(g, self.c12, self.d12))
+
+
 class Operator:
     """A = H1 (x) I + I (x) H2 + V12 - E  (Sec. 3.4, eq. hamiltonian2d),
     applied as the 5-point stencil
@@ -159,6 +203,11 @@ class Operator:
 
 def tp_operator(g: Grid1D, Z1: float, Z2: float, lam: float, E: float) -> Operator:
     return Operator(g, tp_one_body(g, Z1), tp_one_body(g, Z2), tp_two_body(g, lam), E)
+
+
+def model_operator(g: Grid1D, model, E: float) -> Operator:
+    """The operator of a potential model (TPModel or ExpModel) on grid g."""
+    return Operator(g, *model.potentials(g), E)
 
 
 def tp_rhs(g: Grid1D, Z1: float, Z2: float, lam: float, E: float) -> np.ndarray:

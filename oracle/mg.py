@@ -12,7 +12,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg as sla
 
-from .grid import Grid1D, Operator, tp_operator
+from .grid import Grid1D, Operator, TPModel, model_operator
 
 
 def jacobi(op: Operator, u: np.ndarray, f: np.ndarray, omega: float) -> np.ndarray:
@@ -103,18 +103,20 @@ class Hierarchy:
     """Operators on every level: level 0 finest, level ``levels-1`` coarsest.
 
     ``gammas[l]`` is the interior contour rotation of level l (all zero: every
-    level is the exterior-complex-scaled operator)."""
+    level is the exterior-complex-scaled operator).  ``model`` (TPModel or
+    ExpModel) replaces the Temkin-Poet strengths Z1, Z2, lam when given."""
 
     def __init__(self, g: Grid1D, Z1: float, Z2: float, lam: float, E: float,
                  levels: int, omega: float = 2.0 / 3.0, nu1: int = 1, nu2: int = 1,
-                 gammas=None, smoother: str = "jacobi"):
+                 gammas=None, smoother: str = "jacobi", model=None):
         if levels < 1:
             raise ValueError("levels >= 1")
         gammas = [g.gamma] * levels if gammas is None else list(gammas)
         grids = [Grid1D(g.n, g.L, g.R0, g.theta, gammas[0])]
         for l in range(1, levels):
             grids.append(grids[-1].coarsen(gammas[l]))
-        self.ops = [tp_operator(gl, Z1, Z2, lam, E) for gl in grids]
+        model = TPModel(Z1, Z2, lam) if model is None else model
+        self.ops = [model_operator(gl, model, E) for gl in grids]
         self.coarsest = CoarsestSolver(self.ops[-1])
         self.omega, self.nu1, self.nu2 = omega, nu1, nu2
         if smoother not in ("jacobi", "gmres3"):

@@ -28,7 +28,7 @@ import dataclasses
 import numpy as np
 
 from .cccs import CCCS
-from .grid import Grid1D, rel_residual, tp_operator, tp_rhs
+from .grid import Grid1D, TPModel, model_operator, rel_residual, tp_rhs
 from .mg import Hierarchy
 
 
@@ -47,14 +47,16 @@ class MGCCCS:
     def __init__(self, n, L, R0, theta, Z1, Z2, lam, E, levels, M,
                  omega=2.0 / 3.0, nu1=1, nu2=1, Lch=None, refine_steps=2,
                  pc_gamma=0.0, pc_first_level=0, pc_gamma0=0.0, gamma=0.0, smoother="jacobi",
-                 pc_order="mg-cccs"):
+                 pc_order="mg-cccs", model=None):
         # gamma: contour angle of the system itself (Sec. 3.1; 0 = the
-        # exterior-complex-scaled grid with a real interior)
+        # exterior-complex-scaled grid with a real interior); model: the
+        # potentials (default: Temkin-Poet with Z1, Z2, lam)
         self.g = Grid1D(n, L, R0, theta, gamma)
         self.Z1, self.Z2, self.lam, self.E = Z1, Z2, lam, E
+        self.model = TPModel(Z1, Z2, lam) if model is None else model
         gammas = [pc_gamma if l >= pc_first_level else pc_gamma0 for l in range(levels)]
-        self.mg = Hierarchy(self.g, Z1, Z2, lam, E, levels, omega, nu1, nu2, gammas, smoother)
-        self.op = tp_operator(self.g, Z1, Z2, lam, E)       # exact operator
+        self.mg = Hierarchy(self.g, Z1, Z2, lam, E, levels, omega, nu1, nu2, gammas, smoother, self.model)
+        self.op = model_operator(self.g, self.model, E)     # exact operator
         self.pc_op = self.mg.ops[0]                         # level 0 of the hierarchy
         self.M = M
         self.cc = CCCS(self.pc_op, M, Lch, refine_steps) if M > 0 else None
@@ -71,6 +73,9 @@ class MGCCCS:
                    w.omega, w.nu1, w.nu2, **kw)
 
     def rhs(self) -> np.ndarray:
+        """The Temkin-Poet impact right-hand side (Temkin-Poet model only)."""
+        if not isinstance(self.model, TPModel):
+            raise ValueError("the impact right-hand side is defined for the Temkin-Poet model")
         return tp_rhs(self.g, self.Z1, self.Z2, self.lam, self.E)
 
     def cycle(self, u: np.ndarray, f: np.ndarray) -> np.ndarray:
