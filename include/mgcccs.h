@@ -117,6 +117,10 @@ typedef struct mgc_grid_s* mgc_grid;   /* opaque, library-owned host object */
  *          first, then z = z1 + V(v - A z1) with one V-cycle from zero on the
  *          deflated residual.  Applies to the FGMRES and BiCGSTAB
  *          preconditioner; takes one more level-0 field per precision.
+ * pot_tables 0: the two-body potential is the Temkin-Poet lambda/max(x1,x2),
+ *          applied from 1D tables; 1: the workspace also holds one general
+ *          two-body table per level and precision (a field of V12 at the
+ *          level's nodes), which mgc_set_potential_exp requires.
  * precisions   bit mask (1 << MGC_FP64) | (1 << MGC_FP32) of the cycle
  *          precisions the workspace must hold.                                */
 #define MGC_SMOOTH_JACOBI 0
@@ -138,6 +142,7 @@ typedef struct {
   double gamma;
   int smoother;
   int pc_order;
+  int pot_tables;
 } mgc_grid_desc;
 
 typedef struct {
@@ -207,6 +212,28 @@ mgc_status mgc_get_schedule(mgc_grid g, mgc_schedule* s);
  * (Sec. 3.1 Remark 3), refined by two shift-and-invert steps (Sec. 5.1), and
  * the channel potentials (Sec. 4.2).  Invalidates the energy setup.           */
 mgc_status mgc_set_potential(mgc_grid g, double Z1, double Z2, double lambda);
+
+/* Exponential potentials (the model of Sec. 6.1 and Sec. 3.3 Fig. 4):
+ *   V1 = -a1 exp(-b1 x1^2),  V2 = -a2 exp(-b2 x2^2),
+ *   V12 = c12 exp(-d12 (x1 + x2)^2),
+ * each evaluated at the complex nodes of every level's contour (analytic
+ * continuation).  Sec. 6.1 uses a1 = a2 = 4.5, b1 = b2 = 1, c12 = 2,
+ * d12 = 0.1, with the source exp(-3 (x1 + x2)^2) supplied by the caller as
+ * a field.  Same setup as mgc_set_potential (bound states, channel potentials
+ * summed directly over the nodes).  Needs a handle created with
+ * pot_tables = 1 (MGC_EINVAL otherwise) and finite parameters with
+ * b1, b2, d12 >= 0.  The right-hand side builder and the cross-section entry
+ * points are defined for the Temkin-Poet model only and return MGC_EINVAL
+ * under this model.  Invalidates the energy setup.                            */
+mgc_status mgc_set_potential_exp(mgc_grid g, double a1, double b1, double a2, double b2, double c12,
+                                 double d12);
+
+/* Eigenvalues of the channel bound states the CCCS uses (Sec. 2.4
+ * eq. 1d_eigenstate, on the hierarchy's level-0 axis): lamA[2 i], lamA[2 i + 1]
+ * = real and imaginary part of lambda_i of H1 for i < M, lamB likewise for the
+ * Lch states of H2 (either pointer may be null).  Host arrays.  MGC_ESTATE
+ * before a set_potential call.                                                */
+mgc_status mgc_channel_energies(mgc_grid g, double* lamA, double* lamB);
 
 /* Total energy E.  Factorises the coupled channel systems (Sec. 4.3) and the
  * coarsest-level operators, uploads all tables.  Requires a bound workspace

@@ -38,6 +38,27 @@ struct LevelInfo {
   size_t tab[2] = {0, 0};                  // 5 tables a, c, px, py, tm (per precision)
   size_t fu[2] = {0, 0}, ff[2] = {0, 0}, ft[2] = {0, 0};  // fields
   size_t gsV[2] = {0, 0}, gsst[2] = {0, 0};               // GMRES(3) smoother: 4 fields, state
+  size_t v12[2] = {0, 0};                  // general two-body table (pot_tables)
+};
+
+// Potential model of a handle: Temkin-Poet (-Z1/x1, -Z2/x2, lambda/max) or the
+// exponential model (-a1 exp(-b1 x1^2), -a2 exp(-b2 x2^2),
+// c12 exp(-d12 (x1 + x2)^2)), both continued onto the complex nodes.
+constexpr int POT_TP = 0, POT_EXP = 1;
+struct PotModel {
+  int kind = POT_TP;
+  double Z1 = 1, Z2 = 1, lam = 1;
+  double a1 = 0, b1 = 0, a2 = 0, b2 = 0, c12 = 0, d12 = 0;
+  cd v1(cd z) const { return kind == POT_EXP ? -a1 * std::exp(-b1 * z * z) : -Z1 / z; }
+  cd v2(cd z) const { return kind == POT_EXP ? -a2 * std::exp(-b2 * z * z) : -Z2 / z; }
+  // two-body value at nodes j (x1) and k (x2) of an axis
+  cd v12(const Axis& ax, int j, int k) const {
+    if (kind == POT_EXP) {
+      const cd s = ax.z[j] + ax.z[k];
+      return c12 * std::exp(-d12 * s * s);
+    }
+    return lam / ax.z[std::max(j, k)];
+  }
 };
 
 struct SysOff {                            // offsets of one channel system's factors
@@ -104,6 +125,7 @@ struct mgc_grid_s {
   // setup state
   bool have_pot = false, have_energy = false;
   double Z1 = 1, Z2 = 1, lam = 1, E = 0;
+  PotModel pot;                            // the model set by mgc_set_potential / mgc_set_potential_exp
   std::vector<cd> lamA, lamB;
   std::vector<std::vector<cd>> phi, vphi;
   double t_setup_ms = 0;
@@ -111,6 +133,7 @@ struct mgc_grid_s {
   char* ws = nullptr;
   size_t ws_bytes = 0, need = 0;
   size_t exact_tab = 0, exact_tab32 = 0, exact_w = 0, exact_z = 0, coarse_inv = 0, tt = 0;
+  size_t exact_v12[2] = {0, 0};            // two-body table of the physical operator (pot_tables)
   CcOff cc[2];
   size_t part = 0, scal = 0;               // reduction partials, small scalars
   size_t gspart = 0;                       // partials of the GMRES(3) smoother
@@ -195,9 +218,11 @@ void layout(mgc_grid g) {
   g->exact_z = take((n + 1) * 16);
   for (int p = 0; p < 2; ++p) {
     if (!g->prec_on[p]) continue;
+    if (g->d.pot_tables) g->exact_v12[p] = take(g->field_bytes(0, p));
     for (size_t l = 0; l < g->lv.size(); ++l) {
       LevelInfo& L = g->lv[l];
       L.tab[p] = take(5 * (L.n + 1) * esize(p));
+      if (g->d.pot_tables) L.v12[p] = take(g->field_bytes((int)l, p));
       const size_t fb = g->field_bytes((int)l, p);
       if (l > 0) { L.fu[p] = take(fb); L.ff[p] = take(fb); }
       L.ft[p] = take(fb);
@@ -298,6 +323,7 @@ template <typename T> Level<T> level_of(mgc_grid g, int l) {
   out.px = (const v2<T>*)(base + 2 * sz);
   out.py = (const v2<T>*)(base + 3 * sz);
   out.tm = (const v2<T>*)(base + 4 * sz);
+  out.v12 = g->pot.kind == POT_EXP ? (const v2<T>*)(g->ws + L.v12[p]) : nullptr;
   out.n = L.n;
   out.pitch = L.pitch;
   out.E = (T)g->E;
@@ -314,6 +340,7 @@ template <typename T = double> Level<T> exact_level(mgc_grid g) {
   out.px = (const v2<T>*)(base + 2 * sz);
   out.py = (const v2<T>*)(base + 3 * sz);
   out.tm = (const v2<T>*)(base + 4 * sz);
+  out.v12 = g->pot.kind == POT_EXP ? (const v2<T>*)(g->ws + g->exact_v12[sizeof(T) == 8 ? P64 : P32]) : nullptr;
   out.n = n;
   out.pitch = g->lv[0].pitch;
   out.E = (T)g->E;
@@ -394,18 +421,33 @@ std::vector<cd> one_body(const Axis& ax, double Z) {
   for (int j = 1; j < ax.n; ++j) V[j] = -Z / ax.z[j];
   return V;
 }
+// V1 (coord 1) or V2 (coord 2) of the model on the interior nodes of an axis
+std::vector<cd> one_body(const Axis& ax, const PotModel& m, int coord) {
+  std::vector<cd> V(ax.n + 1, 0.0);
+  for (int j = 1; j < ax.n; ++j) V[j] = coord == 1 ? m.v1(ax.z[j]) : m.v2(ax.z[j]);
+  return V;
+}
 
-// a, c, px, py, tm for an axis (concatenated)
-std::vector<cd> level_tables(const Axis& ax, double Z1, double Z2, double lam) {
+// a, c, px, py, tm for an axis (concatenated); tm is zero for a model whose
+// two-body part lives in the general table
+std::vector<cd> level_tables(const Axis& ax, const PotModel& m) {
   const int n = ax.n;
   std::vector<cd> t(5 * (n + 1), 0.0);
   for (int j = 1; j < n; ++j) {
     t[j] = ax.a[j];
     t[(n + 1) + j] = ax.c[j];
-    t[2 * (n + 1) + j] = ax.b[j] - Z1 / ax.z[j];
-    t[3 * (n + 1) + j] = ax.b[j] - Z2 / ax.z[j];
-    t[4 * (n + 1) + j] = lam / ax.z[j];
+    t[2 * (n + 1) + j] = ax.b[j] + m.v1(ax.z[j]);
+    t[3 * (n + 1) + j] = ax.b[j] + m.v2(ax.z[j]);
+    t[4 * (n + 1) + j] = m.kind == POT_TP ? m.lam / ax.z[j] : cd(0.0);
   }
+  return t;
+}
+// general two-body table V12(z_j, z_k) at [k][j] (pitch columns), zero on the ring
+std::vector<cd> two_body_table(const Axis& ax, const PotModel& m, int pitch) {
+  const int n = ax.n;
+  std::vector<cd> t((size_t)(n + 1) * pitch, 0.0);
+  for (int k = 1; k < n; ++k)
+    for (int j = 1; j < n; ++j) t[(size_t)k * pitch + j] = m.v12(ax, j, k);
   return t;
 }
 
@@ -1238,34 +1280,46 @@ mgc_status mgc_field_pitch(mgc_grid g, int level, int* pitch) {
   return MGC_OK;
 }
 
-mgc_status mgc_set_potential(mgc_grid g, double Z1, double Z2, double lambda) {
-  mgc_status rc = check_ready(g, false);
-  if (rc) return rc;
-  if (!std::isfinite(Z1) || !std::isfinite(Z2) || !std::isfinite(lambda) || Z1 < 0)
-    return fail(MGC_EINVAL, "potential strengths must be finite, Z1 >= 0");
+}  // extern "C"
+
+namespace {
+// Tables and bound states of the model in g->pot (shared by both set_potential
+// entry points).
+mgc_status apply_potential(mgc_grid g) {
   auto t0 = std::chrono::steady_clock::now();
   drop_graph(g);
   g->have_pot = g->have_energy = false;
   g->si_count = 0;
-  g->Z1 = Z1; g->Z2 = Z2; g->lam = lambda;
+  const PotModel& pm = g->pot;
   const int n = g->d.n, M = g->d.M, Lc = g->d.Lch;
+  mgc_status rc;
   std::string err;
   // level tables of the exact operator and of the hierarchy
   {
-    auto t = level_tables(g->exact, Z1, Z2, lambda);
+    auto t = level_tables(g->exact, pm);
     if ((rc = upload_cplx<double>(g, g->exact_tab, t))) return rc;
     if (g->prec_on[P32] && (rc = upload_cplx<float>(g, g->exact_tab32, t))) return rc;
+    if (pm.kind == POT_EXP) {
+      auto v = two_body_table(g->exact, pm, g->lv[0].pitch);
+      if ((rc = upload_cplx<double>(g, g->exact_v12[P64], v))) return rc;
+      if (g->prec_on[P32] && (rc = upload_cplx<float>(g, g->exact_v12[P32], v))) return rc;
+    }
   }
   for (size_t l = 0; l < g->lv.size(); ++l) {
-    auto t = level_tables(g->lv[l].ax, Z1, Z2, lambda);
+    auto t = level_tables(g->lv[l].ax, pm);
     if ((rc = upload_cplx<double>(g, g->lv[l].tab[P64], t))) return rc;
     if (g->prec_on[P32] && (rc = upload_cplx<float>(g, g->lv[l].tab[P32], t))) return rc;
+    if (pm.kind == POT_EXP) {
+      auto v = two_body_table(g->lv[l].ax, pm, g->lv[l].pitch);
+      if ((rc = upload_cplx<double>(g, g->lv[l].v12[P64], v))) return rc;
+      if (g->prec_on[P32] && (rc = upload_cplx<float>(g, g->lv[l].v12[P32], v))) return rc;
+    }
   }
   // bound states of the hierarchy's level-0 one-body Hamiltonians
   const Axis& ax = g->lv[0].ax;
   if (M > 0) {
-    if (!bound_states(ax, one_body(ax, Z1), M, 2, g->lamA, g->phi, err)) return fail(MGC_ENUMERIC, err);
-    if (!bound_states(ax, one_body(ax, Z2), Lc, 2, g->lamB, g->vphi, err)) return fail(MGC_ENUMERIC, err);
+    if (!bound_states(ax, one_body(ax, pm, 1), M, 2, g->lamA, g->phi, err)) return fail(MGC_ENUMERIC, err);
+    if (!bound_states(ax, one_body(ax, pm, 2), Lc, 2, g->lamB, g->vphi, err)) return fail(MGC_ENUMERIC, err);
     std::vector<cd> wphi((size_t)M * (n + 1)), phi((size_t)M * (n + 1)),
         wvphi((size_t)Lc * (n + 1)), vphi((size_t)Lc * (n + 1));
     for (int i = 0; i < M; ++i)
@@ -1293,8 +1347,47 @@ mgc_status mgc_set_potential(mgc_grid g, double Z1, double Z2, double lambda) {
   g->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return MGC_OK;
 }
+}  // namespace
+
+extern "C" {
+
+mgc_status mgc_set_potential(mgc_grid g, double Z1, double Z2, double lambda) {
+  mgc_status rc = check_ready(g, false);
+  if (rc) return rc;
+  if (!std::isfinite(Z1) || !std::isfinite(Z2) || !std::isfinite(lambda) || Z1 < 0)
+    return fail(MGC_EINVAL, "potential strengths must be finite, Z1 >= 0");
+  g->Z1 = Z1; g->Z2 = Z2; g->lam = lambda;
+  g->pot = PotModel();
+  g->pot.Z1 = Z1; g->pot.Z2 = Z2; g->pot.lam = lambda;
+  return apply_potential(g);
+}
+
+mgc_status mgc_set_potential_exp(mgc_grid g, double a1, double b1, double a2, double b2, double c12, double d12) {
+  mgc_status rc = check_ready(g, false);
+  if (rc) return rc;
+  for (double v : {a1, b1, a2, b2, c12, d12})
+    if (!std::isfinite(v)) return fail(MGC_EINVAL, "exponential model parameters must be finite");
+  if (b1 < 0 || b2 < 0 || d12 < 0) return fail(MGC_EINVAL, "exponential model decay rates must be >= 0");
+  if (!g->d.pot_tables)
+    return fail(MGC_EINVAL, "the exponential model needs a handle created with pot_tables = 1");
+  g->pot = PotModel();
+  g->pot.kind = POT_EXP;
+  g->pot.a1 = a1; g->pot.b1 = b1; g->pot.a2 = a2; g->pot.b2 = b2; g->pot.c12 = c12; g->pot.d12 = d12;
+  g->Z1 = g->Z2 = g->lam = 0;
+  return apply_potential(g);
+}
+
+mgc_status mgc_channel_energies(mgc_grid g, double* lamA, double* lamB) {
+  mgc_status rc = check_ready(g, false);
+  if (rc) return rc;
+  if (!g->have_pot) return fail(MGC_ESTATE, "set_potential required");
+  for (int i = 0; i < g->d.M && lamA; ++i) { lamA[2 * i] = g->lamA[i].real(); lamA[2 * i + 1] = g->lamA[i].imag(); }
+  for (int l = 0; l < g->d.Lch && lamB; ++l) { lamB[2 * l] = g->lamB[l].real(); lamB[2 * l + 1] = g->lamB[l].imag(); }
+  return MGC_OK;
+}
 
 }  // extern "C"
+
 
 namespace {
 // Channel potential V[node][i][m] = sum_j w_j (lam / z_max(j,node)) f_i(j) f_m(j)
@@ -1312,6 +1405,25 @@ std::vector<cd> channel_potential(const Axis& ax, double lam, const std::vector<
       for (int m = 0; m < M; ++m) pre[i * M + m] += ax.w[k] * f[i][k] * f[m][k];
     for (int q = 0; q < MM; ++q)
       V[(size_t)k * MM + q] = (lam / ax.z[k]) * pre[q] + suf[(size_t)(k + 1) * MM + q];
+  }
+  return V;
+}
+
+// Channel potential of a general (symmetric) two-body model, summed directly:
+// V[node][i][m] = sum_j w_j V12(z_j, z_node) f_i(j) f_m(j).
+std::vector<cd> channel_potential(const Axis& ax, const PotModel& pm, const std::vector<std::vector<cd>>& f) {
+  const int n = ax.n, M = (int)f.size(), MM = M * M;
+  std::vector<cd> V((size_t)(n + 1) * MM, 0.0), G((size_t)(n + 1) * MM, 0.0);
+  for (int j = 1; j < n; ++j)
+    for (int i = 0; i < M; ++i)
+      for (int m = 0; m < M; ++m) G[(size_t)j * MM + i * M + m] = ax.w[j] * f[i][j] * f[m][j];
+  for (int k = 1; k < n; ++k) {
+    cd* out = &V[(size_t)k * MM];
+    for (int j = 1; j < n; ++j) {
+      const cd v = pm.v12(ax, j, k);
+      const cd* gj = &G[(size_t)j * MM];
+      for (int q = 0; q < MM; ++q) out[q] += v * gj[q];
+    }
   }
   return V;
 }
@@ -1353,15 +1465,17 @@ mgc_status mgc_set_energy(mgc_grid g, double E) {
       const int m = isA ? M : Lc;
       const auto& basis = isA ? g->phi : g->vphi;
       const auto& lamv = isA ? g->lamA : g->lamB;
-      const double Zo = isA ? g->Z2 : g->Z1;      // one-body potential of the free coordinate
-      std::vector<cd> V = channel_potential(ax, g->lam, basis);
+      // one-body potential of the free coordinate (x2 for the A system)
+      const std::vector<cd> Vo = one_body(ax, g->pot, isA ? 2 : 1);
+      std::vector<cd> V = g->pot.kind == POT_TP ? channel_potential(ax, g->lam, basis)
+                                                : channel_potential(ax, g->pot, basis);
       std::vector<cd> lo(N), upv(N), D((size_t)N * m * m, 0.0);
       for (int t = 0; t < N; ++t) {
         const int node = t + 1;
         lo[t] = ax.a[node];
         upv[t] = ax.c[node];
         for (int q = 0; q < m * m; ++q) D[(size_t)t * m * m + q] = V[(size_t)node * m * m + q];
-        const cd dd = ax.b[node] - Zo / ax.z[node] - E;
+        const cd dd = ax.b[node] + Vo[node] - E;
         for (int i = 0; i < m; ++i) D[(size_t)t * m * m + i * m + i] += dd + lamv[i];
       }
       ChannelFactors f;
@@ -1380,7 +1494,7 @@ mgc_status mgc_set_energy(mgc_grid g, double E) {
     for (int k = 1; k < nc; ++k)
       for (int j = 1; j < nc; ++j) {
         const int r = (k - 1) * m + (j - 1);
-        const cd d = ax.b[j] - g->Z1 / ax.z[j] + ax.b[k] - g->Z2 / ax.z[k] + g->lam / ax.z[std::max(j, k)] - E;
+        const cd d = ax.b[j] + g->pot.v1(ax.z[j]) + ax.b[k] + g->pot.v2(ax.z[k]) + g->pot.v12(ax, j, k) - E;
         A[(size_t)r * Nc + r] = d;
         if (j > 1) A[(size_t)r * Nc + r - 1] = ax.a[j];
         if (j < m) A[(size_t)r * Nc + r + 1] = ax.c[j];
@@ -1399,6 +1513,7 @@ mgc_status mgc_set_energy(mgc_grid g, double E) {
 mgc_status mgc_build_rhs_tp(mgc_grid g, void* chi, mgc_precision prec) {
   mgc_status rc = check_ready(g, false);
   if (rc) return rc;
+  if (g->pot.kind != POT_TP) return fail(MGC_EINVAL, "defined for the Temkin-Poet model only");
   if (!g->have_pot) return fail(MGC_ESTATE, "set_potential required");
   if (!chi) return fail(MGC_EINVAL, "null field");
   if (prec != MGC_FP64) return fail(MGC_EINVAL, "right-hand side is built in FP64");
@@ -1581,6 +1696,7 @@ mgc_status mgc_cross_section(mgc_grid g, const void* u, const void* chi, double 
                              double zeta[2], double* sigma) {
   mgc_status rc = check_ready(g);
   if (rc) return rc;
+  if (g->pot.kind != POT_TP) return fail(MGC_EINVAL, "defined for the Temkin-Poet model only");
   if (g->d.gamma != 0.0) return fail(MGC_EINVAL, "the amplitudes are defined on a real interior (gamma = 0)");
   if (!u || !chi || !zeta || !(k1 > 0) || !(k2 > 0)) return fail(MGC_EINVAL, "bad arguments");
   const Axis& ax = g->exact;
@@ -1612,6 +1728,7 @@ mgc_status mgc_cross_section_sweep(mgc_grid g, const void* u, const void* chi, i
                                    const double* k2, double* zeta, double* sigma) {
   mgc_status rc = check_ready(g);
   if (rc) return rc;
+  if (g->pot.kind != POT_TP) return fail(MGC_EINVAL, "defined for the Temkin-Poet model only");
   if (g->d.gamma != 0.0) return fail(MGC_EINVAL, "the amplitudes are defined on a real interior (gamma = 0)");
   if (!u || !chi || !k1 || !k2 || !zeta) return fail(MGC_EINVAL, "null argument");
   if (npairs < 1 || npairs > MGC_SWEEP_MAX) return fail(MGC_EINVAL, "npairs must lie in [1, MGC_SWEEP_MAX]");
@@ -1651,6 +1768,7 @@ mgc_status mgc_cross_section_grad(mgc_grid g, const void* u, const void* chi, do
                                   double* sigma, mgc_stats* st) {
   mgc_status rc = check_ready(g);
   if (rc) return rc;
+  if (g->pot.kind != POT_TP) return fail(MGC_EINVAL, "defined for the Temkin-Poet model only");
   if (g->d.gamma != 0.0) return fail(MGC_EINVAL, "the amplitudes are defined on a real interior (gamma = 0)");
   if (!u || !chi || !v || !dsigma || !(k1 > 0) || !(k2 > 0) || v == u || v == chi)
     return fail(MGC_EINVAL, "bad arguments");
@@ -1788,6 +1906,7 @@ struct XsecJob {
 mgc_status enqueue_xsec(mgc_grid g, const void* u, const void* chi, int nstates, int nodes, XsecJob& J,
                         hipStream_t st) {
   if (g->d.gamma != 0.0) return fail(MGC_EINVAL, "the amplitudes are defined on a real interior (gamma = 0)");
+  if (g->pot.kind != POT_TP) return fail(MGC_EINVAL, "defined for the Temkin-Poet model only");
   J.nstates = nstates;
   J.nodes = nodes;
   mgc_status rc;
@@ -1858,6 +1977,7 @@ extern "C" {
 mgc_status mgc_single_ionization(mgc_grid g, const void* u, const void* chi, int nstates, double* s, double* kn) {
   mgc_status rc = check_ready(g);
   if (rc) return rc;
+  if (g->pot.kind != POT_TP) return fail(MGC_EINVAL, "defined for the Temkin-Poet model only");
   if (!u || !chi || !s) return fail(MGC_EINVAL, "null argument");
   if (nstates < 1 || nstates > MGC_SI_MAX || nstates > g->d.n - 2)
     return fail(MGC_EINVAL, "nstates must lie in [1, MGC_SI_MAX] and below n - 1");
@@ -1872,6 +1992,7 @@ mgc_status mgc_total_double_ionization(mgc_grid g, const void* u, const void* ch
                                        double* zeta) {
   mgc_status rc = check_ready(g);
   if (rc) return rc;
+  if (g->pot.kind != POT_TP) return fail(MGC_EINVAL, "defined for the Temkin-Poet model only");
   if (!u || !chi || !sigma_tot) return fail(MGC_EINVAL, "null argument");
   if (nodes < 1 || nodes > MGC_SWEEP_MAX) return fail(MGC_EINVAL, "nodes must lie in [1, MGC_SWEEP_MAX]");
   XsecJob J;

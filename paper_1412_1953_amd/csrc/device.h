@@ -15,13 +15,16 @@ template <typename T> using v2 = typename vec2<T>::type;
 //   px   : b_j + V1_j   (x1 diagonal part)
 //   py   : b_k + V2_k   (x2 diagonal part)
 //   tm   : lambda / z_m (two-body part, evaluated at m = max(j,k))
-// Diagonal of the operator: px[j] + py[k] + tm[max(j,k)] - E.
+//   v12  : null, or a general two-body potential V12(z_j, z_k) as a field
+//          ((n+1) rows x pitch, same layout as the unknowns)
+// Diagonal of the operator: px[j] + py[k] + tm[max(j,k)] (+ v12[k][j]) - E.
 template <typename T> struct Level {
   const v2<T>* a;
   const v2<T>* c;
   const v2<T>* px;
   const v2<T>* py;
   const v2<T>* tm;
+  const v2<T>* v12;
   int n;
   int pitch;
   T E;

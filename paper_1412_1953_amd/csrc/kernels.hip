@@ -54,10 +54,19 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Operator diagonal at (k, j): px_j + py_k + tm_max(j,k) - E
+// General two-body table at node (k, j), the indices clamped onto the grid
+// (nodes outside it only occur in halos whose values are never used)
+template <typename T>
+__device__ __forceinline__ v2<T> v12_at(const Level<T>& L, int k, int j) {
+  const int kk = k < 0 ? 0 : (k > L.n ? L.n : k), jj = j < 0 ? 0 : (j > L.n ? L.n : j);
+  return L.v12[(size_t)kk * L.pitch + jj];
+}
+
+// Operator diagonal at (k, j): px_j + py_k + tm_max(j,k) (+ v12_kj) - E
 template <typename T>
 __device__ __forceinline__ v2<T> diag_at(const Level<T>& L, int k, int j) {
   v2<T> d = cadd(cadd(L.px[j], L.py[k]), L.tm[j > k ? j : k]);
+  if (L.v12) d = cadd(d, v12_at(L, k, j));
   d.x -= L.E;
   return d;
 }
@@ -105,6 +114,7 @@ struct ColumnStencil {
     }
     const v2<T> uw = ldf<T>(u, p, k, j - 1, n), ue = ldf<T>(u, p, k, j + 1, n);
     v2<T> d = cadd(cadd(pxj, L.py[k]), L.tm[j > k ? j : k]);
+    if (L.v12) d = cadd(d, v12_at(L, k, j));
     d.x -= L.E;
     v2<T> acc = cmul(d, uc);
     acc = cfma(acc, aj, uw);
@@ -390,11 +400,14 @@ __device__ __forceinline__ void stage_tabs(TileTabs<T, W, H>& tb, const Level<T>
     }
   }
 }
-// diagonal px_j + py_k + tm_max(j,k) - E at tile position (rr, cc), node (k, j)
+// diagonal px_j + py_k + tm_max(j,k) (+ v12_kj) - E at tile position (rr, cc),
+// node (k, j) of level L
 template <typename T, int W, int H>
-__device__ __forceinline__ v2<T> tab_diag(const TileTabs<T, W, H>& tb, T E, int rr, int cc, int k, int j) {
+__device__ __forceinline__ v2<T> tab_diag(const TileTabs<T, W, H>& tb, const Level<T>& L, int rr, int cc, int k,
+                                          int j) {
   v2<T> d = cadd(cadd(tb.col[0][cc], tb.row[0][rr]), j > k ? tb.col[3][cc] : tb.row[3][rr]);
-  d.x -= E;
+  if (L.v12) d = cadd(d, v12_at(L, k, j));
+  d.x -= L.E;
   return d;
 }
 // (A w)(k, j) from an LDS tile w with a one-node halo; tab_apply_d takes the
@@ -410,9 +423,9 @@ __device__ __forceinline__ v2<T> tab_apply_d(const TileTabs<T, W, H>& tb, v2<T> 
   return acc;
 }
 template <typename T, int W, int H, int TW>
-__device__ __forceinline__ v2<T> tab_apply(const TileTabs<T, W, H>& tb, T E, const v2<T> (*w)[TW], int rr,
-                                           int cc, int k, int j) {
-  v2<T> acc = cmul(tab_diag(tb, E, rr, cc, k, j), w[rr][cc]);
+__device__ __forceinline__ v2<T> tab_apply(const TileTabs<T, W, H>& tb, const Level<T>& L, const v2<T> (*w)[TW],
+                                           int rr, int cc, int k, int j) {
+  v2<T> acc = cmul(tab_diag(tb, L, rr, cc, k, j), w[rr][cc]);
   acc = cfma(acc, tb.col[1][cc], w[rr][cc - 1]);
   acc = cfma(acc, tb.col[2][cc], w[rr][cc + 1]);
   acc = cfma(acc, tb.row[1][rr], w[rr - 1][cc]);
@@ -475,7 +488,7 @@ __global__ void __launch_bounds__(256) k_s1_zero(Level<T> L, const v2<T>* __rest
     d = mk<T>(1, 0);
     if (j > 0 && j < n && k > 0 && k < n) {
       fv = cscale(fv, sc);
-      d = tab_diag(tb, L.E, rr, cc, k, j);
+      d = tab_diag(tb, L, rr, cc, k, j);
       uv = cscale(cdiv(fv, d), omega);
     }
     up[rr][cc] = uv;
@@ -605,7 +618,7 @@ __global__ void __launch_bounds__(256) k_s2_zero(Level<T> L, const v2<T>* __rest
       fv = cscale(fv, sc);
       const int Ja = (j >> 1) - J0, Jb = ((j + 1) >> 1) - J0, Ka = (k >> 1) - K0, Kb = ((k + 1) >> 1) - K0;
       const v2<T> s = cadd(cadd(el[Ka][Ja], el[Ka][Jb]), cadd(el[Kb][Ja], el[Kb][Jb]));
-      d = tab_diag(tb, L.E, rr, cc, k, j);
+      d = tab_diag(tb, L, rr, cc, k, j);
       inv = T(1) / (d.x * d.x + d.y * d.y);
       wv = cadd(cscale(cdiv_inv(fv, d, inv), omega), cscale(s, T(0.25)));
     }
@@ -704,7 +717,7 @@ __global__ void __launch_bounds__(1024) k_s1_pair(Level<T> Lf, Level<T> Lc, cons
     v2<T> uv = mk<T>(0, 0);
     if (interior(k, j, n)) {
       fv = cscale(fv, sc);
-      uv = cscale(cdiv(fv, tab_diag(tb0, Lf.E, rr, cc, k, j)), omega);
+      uv = cscale(cdiv(fv, tab_diag(tb0, Lf, rr, cc, k, j)), omega);
     }
     up0[rr][cc] = uv;
   };
@@ -725,7 +738,7 @@ __global__ void __launch_bounds__(1024) k_s1_pair(Level<T> Lf, Level<T> Lc, cons
     const bool in = rpos(q, rr, cc);
     const int k = r0 + rr, j = c0 + cc;
     v2<T> r = mk<T>(0, 0);
-    if (in && interior(k, j, n)) r = csub(fr[q], tab_apply(tb0, Lf.E, up0, rr, cc, k, j));
+    if (in && interior(k, j, n)) r = csub(fr[q], tab_apply(tb0, Lf, up0, rr, cc, k, j));
     fr[q] = r;
   }
   __syncthreads();
@@ -771,7 +784,7 @@ __global__ void __launch_bounds__(1024) k_s1_pair(Level<T> Lf, Level<T> Lc, cons
   for (int q = 0; q < NC; ++q) {
     const int idx = tid + NT * q, rr = idx / CW, cc = idx % CW, K = r1 + rr, J = c1 + cc;
     if (idx < CH * CW)
-      up1[rr][cc] = interior(K, J, n1) ? cscale(cdiv(f1r[q], tab_diag(tb1, Lc.E, rr, cc, K, J)), omega)
+      up1[rr][cc] = interior(K, J, n1) ? cscale(cdiv(f1r[q], tab_diag(tb1, Lc, rr, cc, K, J)), omega)
                                        : mk<T>(0, 0);
   }
   __syncthreads();
@@ -780,7 +793,7 @@ __global__ void __launch_bounds__(1024) k_s1_pair(Level<T> Lf, Level<T> Lc, cons
   for (int q = 0; q < NCR; ++q) {
     const int idx = tid + NT * q, rr = 1 + idx / CRW, cc = 1 + idx % CRW, K = r1 + rr, J = c1 + cc;
     v2<T> r = mk<T>(0, 0);
-    if (idx < CRH * CRW && interior(K, J, n1)) r = csub(ft1[rr][cc], tab_apply(tb1, Lc.E, up1, rr, cc, K, J));
+    if (idx < CRH * CRW && interior(K, J, n1)) r = csub(ft1[rr][cc], tab_apply(tb1, Lc, up1, rr, cc, K, J));
     r1v[q] = r;
   }
   __syncthreads();
@@ -882,7 +895,7 @@ __global__ void __launch_bounds__(256) k_s2_pair(Level<T> Lf, Level<T> Lc, const
       if (J > 0 && J < nc && K > 0 && K < nc) {
         const int Ja = (J >> 1) - Q0, Jb = ((J + 1) >> 1) - Q0, Ka = (K >> 1) - R0, Kb = ((K + 1) >> 1) - R0;
         const v2<T> s = cadd(cadd(e2[Ka][Ja], e2[Ka][Jb]), cadd(e2[Kb][Ja], e2[Kb][Jb]));
-        dc[q] = tab_diag(tbc, Lc.E, rr, cc, K, J);
+        dc[q] = tab_diag(tbc, Lc, rr, cc, K, J);
         ic[q] = T(1) / (dc[q].x * dc[q].x + dc[q].y * dc[q].y);
         wv = cadd(cscale(cdiv_inv(fcv[q], dc[q], ic[q]), omega), cscale(s, T(0.25)));
       }
@@ -917,7 +930,7 @@ __global__ void __launch_bounds__(256) k_s2_pair(Level<T> Lf, Level<T> Lc, const
       fv = cscale(fv, sc);
       const int Ja = (j >> 1) - J0, Jb = ((j + 1) >> 1) - J0, Ka = (k >> 1) - K0, Kb = ((k + 1) >> 1) - K0;
       const v2<T> s = cadd(cadd(e1[Ka][Ja], e1[Ka][Jb]), cadd(e1[Kb][Ja], e1[Kb][Jb]));
-      d = tab_diag(tbf, Lf.E, rr, cc, k, j);
+      d = tab_diag(tbf, Lf, rr, cc, k, j);
       inv = T(1) / (d.x * d.x + d.y * d.y);
       wv = cadd(cscale(cdiv_inv(fv, d, inv), omega), cscale(s, T(0.25)));
     }
@@ -998,7 +1011,7 @@ __device__ __forceinline__ void tail_s1(const TailArgs<T>& A, v2<T> (&fr)[NP], T
     v2<T> uv = mk<T>(0, 0);
     if (j > 0 && j < n && k > 0 && k < n) {
       fr[q] = cscale(fr[q], sc);
-      uv = cscale(cdiv(fr[q], tab_diag(tb, L.E, k, j, k, j)), A.omega);
+      uv = cscale(cdiv(fr[q], tab_diag(tb, L, k, j, k, j)), A.omega);
     }
     big[k][j] = uv;
   }
@@ -1008,7 +1021,7 @@ __device__ __forceinline__ void tail_s1(const TailArgs<T>& A, v2<T> (&fr)[NP], T
     int k, j;
     const bool in = tail_node(t, q, n, k, j);
     v2<T> r = mk<T>(0, 0);
-    if (in && j > 0 && j < n && k > 0 && k < n) r = csub(fr[q], tab_apply(tb, L.E, big, k, j, k, j));
+    if (in && j > 0 && j < n && k > 0 && k < n) r = csub(fr[q], tab_apply(tb, L, big, k, j, k, j));
     fr[q] = r;
   }
   __syncthreads();
@@ -1123,7 +1136,7 @@ __device__ __forceinline__ void tail_s2(const TailArgs<T>& A, v2<T> (&fr)[NP], T
       fr[q] = cscale(fr[q], sc);
       const int Ja = j >> 1, Jb = (j + 1) >> 1, Ka = k >> 1, Kb = (k + 1) >> 1;
       const v2<T> s = cadd(cadd(sml[Ka][Ja], sml[Ka][Jb]), cadd(sml[Kb][Ja], sml[Kb][Jb]));
-      wv = cadd(cscale(cdiv(fr[q], tab_diag(tb, L.E, k, j, k, j)), A.omega), cscale(s, T(0.25)));
+      wv = cadd(cscale(cdiv(fr[q], tab_diag(tb, L, k, j, k, j)), A.omega), cscale(s, T(0.25)));
     }
     big[k][j] = wv;
   }
@@ -1134,8 +1147,8 @@ __device__ __forceinline__ void tail_s2(const TailArgs<T>& A, v2<T> (&fr)[NP], T
     const bool in = tail_node(t, q, n, k, j);
     v2<T> o = mk<T>(0, 0);
     if (in && j > 0 && j < n && k > 0 && k < n) {
-      const v2<T> d = tab_diag(tb, L.E, k, j, k, j);
-      const v2<T> res = csub(fr[q], tab_apply(tb, L.E, big, k, j, k, j));
+      const v2<T> d = tab_diag(tb, L, k, j, k, j);
+      const v2<T> res = csub(fr[q], tab_apply(tb, L, big, k, j, k, j));
       o = cadd(big[k][j], cscale(cdiv(res, d), A.omega));
     }
     fr[q] = o;
@@ -1175,7 +1188,7 @@ __device__ __forceinline__ void tail_s2_rows(const TailArgs<T>& A, v2<T> (&fr)[T
       fr[q] = cscale(fr[q], sc);
       const int Ja = j >> 1, Jb = (j + 1) >> 1, Ka = k >> 1, Kb = (k + 1) >> 1;
       const v2<T> s = cadd(cadd(sml[Ka][Ja], sml[Ka][Jb]), cadd(sml[Kb][Ja], sml[Kb][Jb]));
-      wv = cadd(cscale(cdiv(fr[q], tab_diag(tb, L.E, k, j, k, j)), A.omega), cscale(s, T(0.25)));
+      wv = cadd(cscale(cdiv(fr[q], tab_diag(tb, L, k, j, k, j)), A.omega), cscale(s, T(0.25)));
     }
     big[k][j] = wv;
   }
@@ -1185,8 +1198,8 @@ __device__ __forceinline__ void tail_s2_rows(const TailArgs<T>& A, v2<T> (&fr)[T
     int k, j;
     if (!tail_row_node(t, q, n, ka, kb, k, j)) break;
     if (k >= ka && k < kb && j > 0 && j < n) {
-      const v2<T> d = tab_diag(tb, L.E, k, j, k, j);
-      const v2<T> res = csub(fr[q], tab_apply(tb, L.E, big, k, j, k, j));
+      const v2<T> d = tab_diag(tb, L, k, j, k, j);
+      const v2<T> res = csub(fr[q], tab_apply(tb, L, big, k, j, k, j));
       A.u[0][(size_t)k * A.pitch[0] + j] = cadd(big[k][j], cscale(cdiv(res, d), A.omega));
     }
   }
@@ -1344,6 +1357,7 @@ __global__ void __launch_bounds__((64 * ProjCfg<T, MC>::W)) k_cccs_project(Level
       v2<T> r = mk<T>(0, 0);
       if (jok) {
         v2<T> d = cadd(cadd(pxj, rt[0][rr]), j > k ? tmj : rt[3][rr]);
+        if (L.v12) d = cadd(d, v12_at(L, k, j));
         d.x -= L.E;
         v2<T> acc = cmul(d, ut[ur][uc]);
         acc = cfma(acc, aj, ut[ur][uc - 1]);

@@ -30,7 +30,8 @@ EXPORTED = ["mgc_create_grid", "mgc_workspace_bytes", "mgc_bind_workspace", "mgc
             "mgc_cross_section_sweep", "mgc_cross_section_grad", "mgc_set_kernel_timer", "mgc_read_kernel_timer",
             "mgc_batch_create", "mgc_batch_solve", "mgc_batch_destroy",
             "mgc_set_schedule", "mgc_get_schedule", "mgc_cccs_noalloc", "mgc_single_ionization",
-            "mgc_total_double_ionization", "mgc_batch_cross_sections", "mgc_destroy_grid", "mgc_last_error"]
+            "mgc_total_double_ionization", "mgc_batch_cross_sections", "mgc_set_potential_exp",
+            "mgc_channel_energies", "mgc_destroy_grid", "mgc_last_error"]
 
 # kernel classes of mgc_set_kernel_timer
 (KT_NONE, KT_APPLY_DOT, KT_AXPY, KT_S1, KT_S2, KT_CCCS_PROJECT, KT_CCCS_CHAIN, KT_S1_FINE, KT_S2_FINE,
@@ -43,7 +44,8 @@ class GridDesc(ctypes.Structure):
                 ("Lch", ctypes.c_int), ("omega", ctypes.c_double), ("nu1", ctypes.c_int),
                 ("nu2", ctypes.c_int), ("pc_gamma", ctypes.c_double), ("pc_first_level", ctypes.c_int),
                 ("max_restart", ctypes.c_int), ("precisions", ctypes.c_int), ("pc_gamma0", ctypes.c_double),
-                ("gamma", ctypes.c_double), ("smoother", ctypes.c_int), ("pc_order", ctypes.c_int)]
+                ("gamma", ctypes.c_double), ("smoother", ctypes.c_int), ("pc_order", ctypes.c_int),
+                ("pot_tables", ctypes.c_int)]
 
 
 class Schedule(ctypes.Structure):
@@ -86,6 +88,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mgc_bind_workspace": [vp, vp, ctypes.c_size_t],
         "mgc_field_pitch": [vp, i, ctypes.POINTER(i)],
         "mgc_set_potential": [vp, d, d, d],
+        "mgc_set_potential_exp": [vp, d, d, d, d, d, d],
+        "mgc_channel_energies": [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
         "mgc_set_energy": [vp, d],
         "mgc_build_rhs_tp": [vp, vp, i],
         "mgc_residual": [vp, vp, vp, vp, ctypes.POINTER(d), i],
@@ -152,7 +156,7 @@ class Grid:
 
     def __init__(self, n, L, R0, theta, levels, M, Lch=None, omega=2.0 / 3.0, nu1=1, nu2=1,
                  pc_gamma=0.0, pc_first_level=0, max_restart=16, fp32=True, device="cuda:0",
-                 pc_gamma0=0.0, gamma=0.0, smoother=0, pc_order=0):
+                 pc_gamma0=0.0, gamma=0.0, smoother=0, pc_order=0, pot_tables=0):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -160,7 +164,7 @@ class Grid:
         Lch = M if Lch is None else Lch
         self.desc = GridDesc(n, L, R0, theta, levels, M, Lch, omega, nu1, nu2, pc_gamma,
                              pc_first_level, max_restart, 1 | (2 if fp32 else 0), pc_gamma0, gamma, smoother,
-                             pc_order)
+                             pc_order, pot_tables)
         self.n, self.levels, self.M, self.Lch = n, levels, M, Lch
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
@@ -243,6 +247,21 @@ class Grid:
     # ---- entry points (same names as the C ABI) -------------------------------
     def set_potential(self, Z1, Z2, lam):
         _check(self.lib.mgc_set_potential(self.h, Z1, Z2, lam))
+
+    def set_potential_exp(self, a1=4.5, b1=1.0, a2=4.5, b2=1.0, c12=2.0, d12=0.1):
+        """Exponential model; defaults are the values of Sec. 6.1 (needs
+        pot_tables=1 at construction)."""
+        _check(self.lib.mgc_set_potential_exp(self.h, a1, b1, a2, b2, c12, d12))
+
+    def channel_energies(self):
+        """(lambda_i of H1 for i < M, lambda_l of H2 for l < Lch) as complex arrays."""
+        import numpy as np
+        a = (ctypes.c_double * (2 * max(self.M, 1)))()
+        b = (ctypes.c_double * (2 * max(self.Lch, 1)))()
+        _check(self.lib.mgc_channel_energies(self.h, a, b))
+        la = np.array(a[:2 * self.M]).view(complex) if self.M else np.zeros(0, complex)
+        lb = np.array(b[:2 * self.Lch]).view(complex) if self.Lch else np.zeros(0, complex)
+        return la, lb
 
     def set_energy(self, E):
         _check(self.lib.mgc_set_energy(self.h, E))

@@ -8,6 +8,7 @@ import warnings
 
 import numpy as np
 
+from oracle.grid import ExpModel
 from oracle.solvers import MGCCCS
 from paper_1412_1953_amd.workloads import initial_guess, random_field
 
@@ -33,6 +34,9 @@ class Case:
     pc_order: int = 0
     pc_first_level: int = 0
     seed: int = 11
+    Lch: int | None = None
+    # exponential model (a1, b1, a2, b2, c12, d12) instead of Temkin-Poet
+    exp: tuple | None = None
 
     @property
     def R0(self):
@@ -43,15 +47,19 @@ class Case:
                       self.levels, self.M, pc_gamma=self.pc_gamma, pc_gamma0=self.pc_gamma0, gamma=self.gamma,
                       smoother=("gmres3" if self.smoother else "jacobi"),
                       pc_order=("deflation" if self.pc_order else "mg-cccs"),
-                      pc_first_level=self.pc_first_level, **kw)
+                      pc_first_level=self.pc_first_level, Lch=self.Lch,
+                      model=ExpModel(*self.exp) if self.exp else None, **kw)
 
     def grid(self, max_restart=10, fp32=True):
         from paper_1412_1953_amd import mgcccs
-        g = mgcccs.Grid(self.n, self.L, self.R0, self.theta, self.levels, self.M,
+        g = mgcccs.Grid(self.n, self.L, self.R0, self.theta, self.levels, self.M, Lch=self.Lch,
                         pc_gamma=self.pc_gamma, pc_first_level=self.pc_first_level, pc_gamma0=self.pc_gamma0,
                         gamma=self.gamma, smoother=self.smoother, pc_order=self.pc_order,
-                        max_restart=max_restart, fp32=fp32)
-        g.set_potential(self.Z1, self.Z2, self.lam)
+                        max_restart=max_restart, fp32=fp32, pot_tables=1 if self.exp else 0)
+        if self.exp:
+            g.set_potential_exp(*self.exp)
+        else:
+            g.set_potential(self.Z1, self.Z2, self.lam)
         g.set_energy(self.E)
         return g
 
