@@ -104,11 +104,16 @@ class Hierarchy:
 
     ``gammas[l]`` is the interior contour rotation of level l (all zero: every
     level is the exterior-complex-scaled operator).  ``model`` (TPModel or
-    ExpModel) replaces the Temkin-Poet strengths Z1, Z2, lam when given."""
+    ExpModel) replaces the Temkin-Poet strengths Z1, Z2, lam when given.
+    With smoother = "gmres3", levels below ``gs_from`` keep omega-Jacobi and
+    the levels from it on take the GMRES(3) substitute (Jacobi where kh is
+    small, a Krylov smoother on the coarse levels where Jacobi amplifies the
+    near-resonant modes: the split of Elman, Ernst and O'Leary's Krylov-enhanced
+    Helmholtz multigrid, 2001)."""
 
     def __init__(self, g: Grid1D, Z1: float, Z2: float, lam: float, E: float,
                  levels: int, omega: float = 2.0 / 3.0, nu1: int = 1, nu2: int = 1,
-                 gammas=None, smoother: str = "jacobi", model=None):
+                 gammas=None, smoother: str = "jacobi", model=None, gs_from: int = 0):
         if levels < 1:
             raise ValueError("levels >= 1")
         gammas = [g.gamma] * levels if gammas is None else list(gammas)
@@ -122,10 +127,11 @@ class Hierarchy:
         if smoother not in ("jacobi", "gmres3"):
             raise ValueError("smoother: 'jacobi' or 'gmres3'")
         self.smoother = smoother
+        self.gs_from = gs_from
 
-    def smooth(self, op: Operator, u: np.ndarray, f: np.ndarray) -> np.ndarray:
-        """One smoothing step: omega-Jacobi, or one GMRES(3) cycle."""
-        if self.smoother == "gmres3":
+    def smooth(self, op: Operator, u: np.ndarray, f: np.ndarray, level: int = 0) -> np.ndarray:
+        """One smoothing step on ``level``: omega-Jacobi, or one GMRES(3) cycle."""
+        if self.smoother == "gmres3" and level >= self.gs_from:
             return gmres_smooth(op, u, f, 3)
         return jacobi(op, u, f, self.omega)
 
@@ -139,10 +145,10 @@ class Hierarchy:
         if level == self.levels - 1:
             return self.coarsest.solve(f)
         for _ in range(self.nu1):
-            u = self.smooth(op, u, f)
+            u = self.smooth(op, u, f, level)
         fc = restrict_fw(op.residual(u, f))
         ec = self.vcycle(np.zeros_like(fc), fc, level + 1)
         u = u + prolong_bilinear(ec)
         for _ in range(self.nu2):
-            u = self.smooth(op, u, f)
+            u = self.smooth(op, u, f, level)
         return u

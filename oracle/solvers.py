@@ -47,7 +47,7 @@ class MGCCCS:
     def __init__(self, n, L, R0, theta, Z1, Z2, lam, E, levels, M,
                  omega=2.0 / 3.0, nu1=1, nu2=1, Lch=None, refine_steps=2,
                  pc_gamma=0.0, pc_first_level=0, pc_gamma0=0.0, gamma=0.0, smoother="jacobi",
-                 pc_order="mg-cccs", model=None):
+                 pc_order="mg-cccs", model=None, gs_from=0):
         # gamma: contour angle of the system itself (Sec. 3.1; 0 = the
         # exterior-complex-scaled grid with a real interior); model: the
         # potentials (default: Temkin-Poet with Z1, Z2, lam)
@@ -55,7 +55,8 @@ class MGCCCS:
         self.Z1, self.Z2, self.lam, self.E = Z1, Z2, lam, E
         self.model = TPModel(Z1, Z2, lam) if model is None else model
         gammas = [pc_gamma if l >= pc_first_level else pc_gamma0 for l in range(levels)]
-        self.mg = Hierarchy(self.g, Z1, Z2, lam, E, levels, omega, nu1, nu2, gammas, smoother, self.model)
+        self.mg = Hierarchy(self.g, Z1, Z2, lam, E, levels, omega, nu1, nu2, gammas, smoother, self.model,
+                            gs_from)
         self.op = model_operator(self.g, self.model, E)     # exact operator
         self.pc_op = self.mg.ops[0]                         # level 0 of the hierarchy
         self.M = M

@@ -205,6 +205,36 @@ def test_gmres3_smoothed_cycle_preconditions_fgmres_to_the_direct_solution():
     assert np.linalg.norm(r.u[1:n, 1:n].ravel() - x) / np.linalg.norm(x) < 1e-10
 
 
+@pytest.mark.parametrize("gs_from", [1, 2])
+def test_split_smoother_cycle_preconditions_fgmres_to_the_direct_solution(gs_from):
+    """omega-Jacobi on the levels below gs_from, GMRES(3) from it on: still a
+    fixed preconditioner for FGMRES, which reaches the dense solve."""
+    n = 64
+    s = MGCCCS(n, 20.0, 15.0, math.pi / 6, 1.0, 1.0, 1.0, 0.9, 4, 2, pc_gamma=math.radians(10),
+               smoother="gmres3", gs_from=gs_from)
+    f = s.rhs()
+    x = spla.spsolve(s.op.sparse(), f[1:n, 1:n].ravel())
+    r = s.solve_fgmres(initial_guess(n, 3), f, 1e-12, restart=10, max_it=400)
+    assert r.relres <= 1e-12
+    assert np.linalg.norm(r.u[1:n, 1:n].ravel() - x) / np.linalg.norm(x) < 1e-10
+
+
+def test_split_smoother_reduces_to_the_single_smoother_cycles():
+    """gs_from = 0 is the all-GMRES(3) cycle; gs_from at or past the coarsest
+    level (which is solved, not smoothed) is the all-Jacobi cycle; between,
+    the fine levels' smoothing is Jacobi's and the cycle differs from both."""
+    n = 32
+    kw = dict(n=n, L=10.0, R0=7.5, theta=math.pi / 6, Z1=1.0, Z2=1.0, lam=1.0, E=0.6, levels=3, M=2,
+              pc_gamma=math.radians(10))
+    u, f = rng_field(n, 41), rng_field(n, 42)
+    gs = MGCCCS(smoother="gmres3", **kw).cycle(u, f)
+    jac = MGCCCS(**kw).cycle(u, f)
+    assert np.array_equal(MGCCCS(smoother="gmres3", gs_from=0, **kw).cycle(u, f), gs)
+    assert np.array_equal(MGCCCS(smoother="gmres3", gs_from=2, **kw).cycle(u, f), jac)
+    mid = MGCCCS(smoother="gmres3", gs_from=1, **kw).cycle(u, f)
+    assert np.abs(mid - gs).max() > 1e-6 and np.abs(mid - jac).max() > 1e-6
+
+
 # ---------------------------------------------------------------- transfers
 def test_full_weighting_is_quarter_transpose_of_bilinear_interpolation():
     n = 32
