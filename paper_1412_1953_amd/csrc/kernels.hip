@@ -16,26 +16,32 @@
 namespace mgc {
 
 // ----------------------------------------------------------------------------
-// complex helpers
+// complex helpers.  The library is built without implicit contraction, so a
+// product meets an add in one rounding only where an fma is written out here:
+// every kernel that evaluates one of these operations rounds it the same way.
 template <typename T> __device__ __forceinline__ v2<T> mk(T x, T y) { v2<T> r; r.x = x; r.y = y; return r; }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 #define MGC_CPLX_OPS(V, T)                                                                  \
   __device__ __forceinline__ V cadd(V a, V b) { return mk<T>(a.x + b.x, a.y + b.y); }        \
   __device__ __forceinline__ V csub(V a, V b) { return mk<T>(a.x - b.x, a.y - b.y); }        \
   __device__ __forceinline__ V cmul(V a, V b) {                                             \
-    return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);                             \
+    return mk<T>(fmaT(a.x, b.x, -(a.y * b.y)), fmaT(a.x, b.y, a.y * b.x));                  \
   }                                                                                         \
   /* acc + a*b */                                                                           \
   __device__ __forceinline__ V cfma(V acc, V a, V b) {                                      \
-    return mk<T>(acc.x + a.x * b.x - a.y * b.y, acc.y + a.x * b.y + a.y * b.x);             \
+    return mk<T>(fmaT(a.x, b.x, fmaT(-a.y, b.y, acc.x)), fmaT(a.x, b.y, fmaT(a.y, b.x, acc.y))); \
   }                                                                                         \
   __device__ __forceinline__ V cscale(V a, T s) { return mk<T>(a.x * s, a.y * s); }          \
+  /* |b|^2 */                                                                               \
+  __device__ __forceinline__ T cabs2(V b) { return fmaT(b.x, b.x, b.y * b.y); }              \
   __device__ __forceinline__ V cdiv(V a, V b) {                                             \
-    T inv = T(1) / (b.x * b.x + b.y * b.y);                                                 \
-    return mk<T>((a.x * b.x + a.y * b.y) * inv, (a.y * b.x - a.x * b.y) * inv);             \
+    T inv = T(1) / cabs2(b);                                                                \
+    return mk<T>(fmaT(a.x, b.x, a.y * b.y) * inv, fmaT(a.y, b.x, -(a.x * b.y)) * inv);      \
   }                                                                                         \
   /* a / b with inv = 1 / |b|^2 given (the same arithmetic as cdiv) */                      \
   __device__ __forceinline__ V cdiv_inv(V a, V b, T inv) {                                  \
-    return mk<T>((a.x * b.x + a.y * b.y) * inv, (a.y * b.x - a.x * b.y) * inv);             \
+    return mk<T>(fmaT(a.x, b.x, a.y * b.y) * inv, fmaT(a.y, b.x, -(a.x * b.y)) * inv);      \
   }
 MGC_CPLX_OPS(double2, double)
 MGC_CPLX_OPS(float2, float)
@@ -619,7 +625,7 @@ __global__ void __launch_bounds__(256) k_s2_zero(Level<T> L, const v2<T>* __rest
       const int Ja = (j >> 1) - J0, Jb = ((j + 1) >> 1) - J0, Ka = (k >> 1) - K0, Kb = ((k + 1) >> 1) - K0;
       const v2<T> s = cadd(cadd(el[Ka][Ja], el[Ka][Jb]), cadd(el[Kb][Ja], el[Kb][Jb]));
       d = tab_diag(tb, L, rr, cc, k, j);
-      inv = T(1) / (d.x * d.x + d.y * d.y);
+      inv = T(1) / cabs2(d);
       wv = cadd(cscale(cdiv_inv(fv, d, inv), omega), cscale(s, T(0.25)));
     }
     wl[rr][cc] = wv;
@@ -896,7 +902,7 @@ __global__ void __launch_bounds__(256) k_s2_pair(Level<T> Lf, Level<T> Lc, const
         const int Ja = (J >> 1) - Q0, Jb = ((J + 1) >> 1) - Q0, Ka = (K >> 1) - R0, Kb = ((K + 1) >> 1) - R0;
         const v2<T> s = cadd(cadd(e2[Ka][Ja], e2[Ka][Jb]), cadd(e2[Kb][Ja], e2[Kb][Jb]));
         dc[q] = tab_diag(tbc, Lc, rr, cc, K, J);
-        ic[q] = T(1) / (dc[q].x * dc[q].x + dc[q].y * dc[q].y);
+        ic[q] = T(1) / cabs2(dc[q]);
         wv = cadd(cscale(cdiv_inv(fcv[q], dc[q], ic[q]), omega), cscale(s, T(0.25)));
       }
       w1[rr][cc] = wv;
@@ -931,7 +937,7 @@ __global__ void __launch_bounds__(256) k_s2_pair(Level<T> Lf, Level<T> Lc, const
       const int Ja = (j >> 1) - J0, Jb = ((j + 1) >> 1) - J0, Ka = (k >> 1) - K0, Kb = ((k + 1) >> 1) - K0;
       const v2<T> s = cadd(cadd(e1[Ka][Ja], e1[Ka][Jb]), cadd(e1[Kb][Ja], e1[Kb][Jb]));
       d = tab_diag(tbf, Lf, rr, cc, k, j);
-      inv = T(1) / (d.x * d.x + d.y * d.y);
+      inv = T(1) / cabs2(d);
       wv = cadd(cscale(cdiv_inv(fv, d, inv), omega), cscale(s, T(0.25)));
     }
     wf[rr][cc] = wv;
