@@ -121,6 +121,12 @@ typedef struct mgc_grid_s* mgc_grid;   /* opaque, library-owned host object */
  *          applied from 1D tables; 1: the workspace also holds one general
  *          two-body table per level and precision (a field of V12 at the
  *          level's nodes), which mgc_set_potential_exp requires.
+ * gs_from  with MGC_SMOOTH_GMRES3: the first level that takes the GMRES(3)
+ *          substitute; the levels above it (finer) keep omega-Jacobi.  0 = every
+ *          level (Sec. 6.1).  Jacobi on the fine levels, where kh is small,
+ *          and a Krylov smoother on the coarse ones, where Jacobi amplifies the
+ *          near-resonant modes, is the split of Krylov-enhanced Helmholtz
+ *          multigrid (Elman, Ernst and O'Leary, 2001).  Must lie in [0, levels].
  * precisions   bit mask (1 << MGC_FP64) | (1 << MGC_FP32) of the cycle
  *          precisions the workspace must hold.                                */
 #define MGC_SMOOTH_JACOBI 0
@@ -143,6 +149,7 @@ typedef struct {
   int smoother;
   int pc_order;
   int pot_tables;
+  int gs_from;
 } mgc_grid_desc;
 
 typedef struct {

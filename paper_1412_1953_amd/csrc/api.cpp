@@ -226,7 +226,7 @@ void layout(mgc_grid g) {
       const size_t fb = g->field_bytes((int)l, p);
       if (l > 0) { L.fu[p] = take(fb); L.ff[p] = take(fb); }
       L.ft[p] = take(fb);
-      if (g->d.smoother == MGC_SMOOTH_GMRES3 && (int)l + 1 < (int)g->lv.size()) {
+      if (g->d.smoother == MGC_SMOOTH_GMRES3 && (int)l >= g->d.gs_from && (int)l + 1 < (int)g->lv.size()) {
         L.gsV[p] = take(4 * fb);
         L.gsst[p] = take(32 * sizeof(double));
       }
@@ -519,17 +519,22 @@ void kt_harvest(mgc_grid g, int slots, const std::vector<double>& bytes, const s
 // The schedule (mgc_set_schedule) decides the tile size per level, and
 // whether pairs and the tail are used; every choice gives the same results
 // bit for bit (the tests compare them).
+// GMRES(3) smoothing on level l (the levels from gs_from on, with the GMRES(3)
+// smoother selected); any_gs: some level above the coarsest takes it
+bool gs_level(mgc_grid g, int l) { return g->d.smoother == MGC_SMOOTH_GMRES3 && l >= g->d.gs_from; }
+bool any_gs(mgc_grid g) { return gs_level(g, g->coarsest() - 1); }
 bool small_tiles(mgc_grid g, int l) {
   if (g->sched.small_tiles >= 0) return l < 31 && ((g->sched.small_tiles >> l) & 1);
   const int n = g->lv[l].n;
   return (long long)((n - 1 + 63) / 64) * ((n - 1 + 15) / 16) < 512;
 }
 bool in_tail(mgc_grid g, int l) {
-  return g->sched.coarse_tail && g->lv[l].n <= TAIL_MAX_N && g->coarsest() - l <= TMAXL;
+  return g->sched.coarse_tail && !any_gs(g) && g->lv[l].n <= TAIL_MAX_N && g->coarsest() - l <= TMAXL;
 }
 bool pair_level(mgc_grid g, int l) {
   if (!g->sched.level_pairs) return false;
-  if (l + 1 >= g->coarsest() || in_tail(g, l) || in_tail(g, l + 1) || !small_tiles(g, l)) return false;
+  if (l + 1 >= g->coarsest() || in_tail(g, l) || in_tail(g, l + 1) || !small_tiles(g, l) || gs_level(g, l + 1))
+    return false;
   int s0 = l;
   while (s0 > 0 && small_tiles(g, s0 - 1)) --s0;
   return (l - s0) % 2 == 0;
@@ -547,7 +552,7 @@ void vcycle_level(mgc_grid g, int l, void* u, const void* f, bool zero_guess, co
   const LevelInfo& LI = g->lv[l];
   const LevelInfo& LC = g->lv[l + 1];
   const double om = g->d.omega;
-  if (g->d.smoother == MGC_SMOOTH_GMRES3) {
+  if (gs_level(g, l)) {
     // GMRES(3) smoothing substitute: in place on u, per level
     void* V = g->ws + LI.gsV[p];
     const size_t stride = g->field_bytes(l, p) / sizeof(v2<T>);
@@ -574,7 +579,7 @@ void vcycle_level(mgc_grid g, int l, void* u, const void* f, bool zero_guess, co
       kt_mark(g, s, kt.run, 0);
     }
     const int nl = g->coarsest() - l;
-    if (L.n <= TAIL_MAX_N && nl <= TMAXL && g->sched.coarse_tail) {
+    if (L.n <= TAIL_MAX_N && nl <= TMAXL && g->sched.coarse_tail && !any_gs(g)) {
       // coarse tail: every remaining level in two launches
       TailArgs<T> A{};
       double b1 = 0.0, b2 = 0.0;
@@ -724,7 +729,7 @@ void cccs_apply(mgc_grid g, void* u, const void* f, const double* fs = nullptr, 
 // zero-guess path applies it on the fly, otherwise f is scaled into scratch.
 template <typename T>
 void mgcccs_cycle(mgc_grid g, void* u, const void* f, bool zero_guess, const double* fs = nullptr) {
-  if (fs && !(zero_guess && g->d.nu1 == 1 && g->d.nu2 == 1 && g->d.smoother == MGC_SMOOTH_JACOBI)) {
+  if (fs && !(zero_guess && g->d.nu1 == 1 && g->d.nu2 == 1 && !gs_level(g, 0))) {
     const int p = sizeof(T) == 8 ? P64 : P32;
     void* tmp = p == P64 ? (void*)(g->ws + g->tw) : (void*)(g->ws + g->f32);
     launch_scale_copy<T, T>(g->stream, g->d.n, g->lv[0].pitch, g->lv[0].pitch, f, fs, tmp);
@@ -1193,6 +1198,7 @@ mgc_status mgc_create_grid(const mgc_grid_desc* d, void* hip_stream, mgc_grid* o
   if (d->pc_first_level < 0) return fail(MGC_EINVAL, "pc_first_level must be >= 0");
   if (d->smoother != MGC_SMOOTH_JACOBI && d->smoother != MGC_SMOOTH_GMRES3)
     return fail(MGC_EINVAL, "smoother must be MGC_SMOOTH_JACOBI or MGC_SMOOTH_GMRES3");
+  if (d->gs_from < 0 || d->gs_from > d->levels) return fail(MGC_EINVAL, "gs_from must lie in [0, levels]");
   if (d->pc_order != MGC_PC_MG_CCCS && d->pc_order != MGC_PC_DEFLATION)
     return fail(MGC_EINVAL, "pc_order must be MGC_PC_MG_CCCS or MGC_PC_DEFLATION");
   if (d->max_restart < 0 || d->max_restart > MGC_MAX_RESTART)

@@ -45,7 +45,7 @@ class GridDesc(ctypes.Structure):
                 ("nu2", ctypes.c_int), ("pc_gamma", ctypes.c_double), ("pc_first_level", ctypes.c_int),
                 ("max_restart", ctypes.c_int), ("precisions", ctypes.c_int), ("pc_gamma0", ctypes.c_double),
                 ("gamma", ctypes.c_double), ("smoother", ctypes.c_int), ("pc_order", ctypes.c_int),
-                ("pot_tables", ctypes.c_int)]
+                ("pot_tables", ctypes.c_int), ("gs_from", ctypes.c_int)]
 
 
 class Schedule(ctypes.Structure):
@@ -156,7 +156,7 @@ class Grid:
 
     def __init__(self, n, L, R0, theta, levels, M, Lch=None, omega=2.0 / 3.0, nu1=1, nu2=1,
                  pc_gamma=0.0, pc_first_level=0, max_restart=16, fp32=True, device="cuda:0",
-                 pc_gamma0=0.0, gamma=0.0, smoother=0, pc_order=0, pot_tables=0):
+                 pc_gamma0=0.0, gamma=0.0, smoother=0, pc_order=0, pot_tables=0, gs_from=0):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -164,7 +164,7 @@ class Grid:
         Lch = M if Lch is None else Lch
         self.desc = GridDesc(n, L, R0, theta, levels, M, Lch, omega, nu1, nu2, pc_gamma,
                              pc_first_level, max_restart, 1 | (2 if fp32 else 0), pc_gamma0, gamma, smoother,
-                             pc_order, pot_tables)
+                             pc_order, pot_tables, gs_from)
         self.n, self.levels, self.M, self.Lch = n, levels, M, Lch
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)

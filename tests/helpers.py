@@ -31,6 +31,7 @@ class Case:
     pc_gamma0: float = 0.0
     gamma: float = 0.0
     smoother: int = 0
+    gs_from: int = 0
     pc_order: int = 0
     pc_first_level: int = 0
     seed: int = 11
@@ -45,7 +46,7 @@ class Case:
     def oracle(self, **kw) -> MGCCCS:
         return MGCCCS(self.n, self.L, self.R0, self.theta, self.Z1, self.Z2, self.lam, self.E,
                       self.levels, self.M, pc_gamma=self.pc_gamma, pc_gamma0=self.pc_gamma0, gamma=self.gamma,
-                      smoother=("gmres3" if self.smoother else "jacobi"),
+                      smoother=("gmres3" if self.smoother else "jacobi"), gs_from=self.gs_from,
                       pc_order=("deflation" if self.pc_order else "mg-cccs"),
                       pc_first_level=self.pc_first_level, Lch=self.Lch,
                       model=ExpModel(*self.exp) if self.exp else None, **kw)
@@ -54,7 +55,7 @@ class Case:
         from paper_1412_1953_amd import mgcccs
         g = mgcccs.Grid(self.n, self.L, self.R0, self.theta, self.levels, self.M, Lch=self.Lch,
                         pc_gamma=self.pc_gamma, pc_first_level=self.pc_first_level, pc_gamma0=self.pc_gamma0,
-                        gamma=self.gamma, smoother=self.smoother, pc_order=self.pc_order,
+                        gamma=self.gamma, smoother=self.smoother, gs_from=self.gs_from, pc_order=self.pc_order,
                         max_restart=max_restart, fp32=fp32, pot_tables=1 if self.exp else 0)
         if self.exp:
             g.set_potential_exp(*self.exp)
