@@ -552,6 +552,27 @@ void vcycle_level(mgc_grid g, int l, void* u, const void* f, bool zero_guess, co
   const LevelInfo& LI = g->lv[l];
   const LevelInfo& LC = g->lv[l + 1];
   const double om = g->d.omega;
+  if (gs_level(g, l) && g->sched.coarse_tail && LI.n <= GT_MAX_N && g->coarsest() - l <= TMAXL) {
+    // this level and every coarser one in one single-workgroup launch
+    GsTailArgs<T> A{};
+    const int nl = g->coarsest() - l;
+    for (int i = 0; i < nl; ++i) A.L[i] = level_of<T>(g, l + i);
+    A.f0 = static_cast<const v2<T>*>(f);
+    A.u0 = static_cast<v2<T>*>(u);
+    for (int i = 1; i <= nl; ++i) {
+      A.f[i] = g->at<v2<T>>(g->lv[l + i].ff[p]);
+      A.u[i] = g->at<v2<T>>(g->lv[l + i].fu[p]);
+      A.pitch[i] = g->lv[l + i].pitch;
+    }
+    A.nl = nl;
+    A.nc = g->lv[g->coarsest()].n;
+    A.Ainv = g->at<const double2>(g->coarse_inv);
+    A.zero = zero_guess ? 1 : 0;
+    A.nu1 = g->d.nu1;
+    A.nu2 = g->d.nu2;
+    launch_gs_tail<T>(s, A);
+    return;
+  }
   if (gs_level(g, l)) {
     // GMRES(3) smoothing substitute: in place on u, per level
     void* V = g->ws + LI.gsV[p];

@@ -45,6 +45,24 @@ template <typename T> struct TailArgs {
   T omega;
 };
 
+// Coarse tail of a V-cycle whose levels all take the GMRES(3) smoother: the
+// levels lt .. lt+nl-1 (n <= GT_MAX_N, finest first) and the coarsest level,
+// run by one workgroup (k_gs_tail).
+constexpr int GT_MAX_N = 64;
+template <typename T> struct GsTailArgs {
+  Level<T> L[TMAXL];          // smoothing levels
+  const v2<T>* f0;            // right-hand side of the top level
+  v2<T>* u0;                  // iterate of the top level (in: unless zero; out)
+  v2<T>* f[TMAXL + 1];        // f[1..nl]: restricted right-hand sides
+  v2<T>* u[TMAXL + 1];        // u[1..nl-1]: iterates between the passes
+  int pitch[TMAXL + 1];
+  int nl;                     // number of smoothing levels, 1..TMAXL
+  int nc;                     // n of the coarsest level
+  const double2* Ainv;        // dense inverse on the coarsest level
+  int zero;                   // the top level starts from u = 0
+  int nu1, nu2;
+};
+
 // CCCS tables of one precision on level 0.
 template <typename T> struct ChanTab {
   const v2<T>* wphi;   // [M][n+1]  w_j phi_i(z_j)       (x1 channels)

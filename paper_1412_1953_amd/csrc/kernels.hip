@@ -3104,6 +3104,370 @@ __global__ void __launch_bounds__(256) k_gs_update(int n, int pitch, const v2<T>
 }
 
 // ----------------------------------------------------------------------------
+// GMRES(3)-smoothed coarse tail in one workgroup (512 threads): every level
+// from the top one (n <= GT_MAX_N) down to the coarsest.  The smoothing
+// vectors of a level live in registers (NP nodes per thread, node index
+// tid + 512 q in row-major interior order); the vector the operator is
+// applied to is written to one LDS tile X (stride GT_W, zero ring), the 1D
+// tables of the level to LDS.  Block-wide sums: wave sums, then the 8 wave
+// partials in a fixed order (deterministic).  Per level and step the
+// arithmetic is that of k_gs_* (classical Gram-Schmidt in one pass, norms of
+// the orthogonalised vectors, Givens least squares), k_resid_restrict,
+// k_coarse_solve and k_prolong_add; only the order of the dot-product sums
+// differs.
+constexpr int GT_THREADS = 512, GT_WAVES = GT_THREADS / 64, GT_W = GT_MAX_N + 1, GT_NR = 8;
+
+template <int NV>
+__device__ __forceinline__ void gt_reduce(double (&v)[NV], double* red) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
+  __syncthreads();                               // the previous sum's readers are done
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) red[w * GT_NR + q] = v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double t = 0.0;
+    for (int i = 0; i < GT_WAVES; ++i) t += red[i * GT_NR + q];
+    v[q] = t;
+  }
+}
+
+// stage the 1D tables of level L and zero the ring of an n-level tile in X
+template <typename T>
+__device__ __forceinline__ void gt_level_setup(const Level<T>& L, v2<T>* X, v2<T> (*tb)[GT_W]) {
+  const int n = L.n, tid = threadIdx.x;
+  __syncthreads();                               // X and the tables are free
+  for (int i = tid; i <= n; i += GT_THREADS) {
+    const bool in = i > 0 && i < n;
+    tb[0][i] = in ? L.a[i] : mk<T>(0, 0);
+    tb[1][i] = in ? L.c[i] : mk<T>(0, 0);
+    tb[2][i] = in ? L.px[i] : mk<T>(0, 0);
+    tb[3][i] = in ? L.py[i] : mk<T>(0, 0);
+    tb[4][i] = in ? L.tm[i] : mk<T>(0, 0);
+  }
+  for (int i = tid; i < 4 * (n + 1); i += GT_THREADS) {
+    const int side = i / (n + 1), t = i % (n + 1);
+    const int k = side == 0 ? 0 : (side == 1 ? n : t), j = side == 0 || side == 1 ? t : (side == 2 ? 0 : n);
+    X[k * GT_W + j] = mk<T>(0, 0);
+  }
+}
+
+// (A x)(k, j) with x in the tile X (the arithmetic of apply_at)
+template <typename T>
+__device__ __forceinline__ v2<T> gt_apply(const Level<T>& L, const v2<T>* X, const v2<T> (*tb)[GT_W], int k, int j) {
+  v2<T> d = cadd(cadd(tb[2][j], tb[3][k]), tb[4][j > k ? j : k]);
+  if (L.v12) d = cadd(d, v12_at(L, k, j));
+  d.x -= L.E;
+  v2<T> acc = cmul(d, X[k * GT_W + j]);
+  acc = cfma(acc, tb[0][j], X[k * GT_W + j - 1]);
+  acc = cfma(acc, tb[1][j], X[k * GT_W + j + 1]);
+  acc = cfma(acc, tb[0][k], X[(k - 1) * GT_W + j]);
+  acc = cfma(acc, tb[1][k], X[(k + 1) * GT_W + j]);
+  return acc;
+}
+
+// node q of this thread on a level with m = n - 1 interior points per row
+__device__ __forceinline__ bool gt_node(int q, int m, int& k, int& j) {
+  const int idx = threadIdx.x + GT_THREADS * q;
+  if (idx >= m * m) return false;
+  k = idx / m + 1;
+  j = idx - (k - 1) * m + 1;
+  return true;
+}
+
+template <typename T, int NP>
+__device__ __forceinline__ void gt_store(v2<T>* X, const v2<T> (&x)[NP], int m) {
+  __syncthreads();                               // the tile's readers are done
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    int k, j;
+    if (gt_node(q, m, k, j)) X[k * GT_W + j] = x[q];
+  }
+  __syncthreads();
+}
+
+// Least squares min ||beta e1 - H y|| by Givens rotations on the k x k+1
+// Hessenberg matrix (the arithmetic of k_gs_solve); H destroyed.
+__device__ void gt_lsq(double2 (*H)[GS_M], double beta, int kd, double2* y) {
+  double2 g[GS_M + 1];
+  for (int r = 0; r <= GS_M; ++r) g[r] = make_double2(0.0, 0.0);
+  g[0] = make_double2(beta, 0.0);
+  for (int i = 0; i < kd; ++i) {
+    const double2 a = H[i][i], b = H[i + 1][i];
+    const double den = sqrt(a.x * a.x + a.y * a.y + b.x * b.x + b.y * b.y);
+    const double2 c = make_double2(a.x / den, a.y / den), sn = make_double2(b.x / den, b.y / den);
+    for (int col = i; col < kd; ++col) {
+      const double2 x1 = H[i][col], x2 = H[i + 1][col];
+      H[i][col] = cadd(cmul(make_double2(c.x, -c.y), x1), cmul(make_double2(sn.x, -sn.y), x2));
+      H[i + 1][col] = csub(cmul(c, x2), cmul(sn, x1));
+    }
+    const double2 g1 = g[i], g2 = g[i + 1];
+    g[i] = cadd(cmul(make_double2(c.x, -c.y), g1), cmul(make_double2(sn.x, -sn.y), g2));
+    g[i + 1] = csub(cmul(c, g2), cmul(sn, g1));
+  }
+  for (int i = 0; i < GS_M; ++i) y[i] = make_double2(0.0, 0.0);
+  for (int i = kd - 1; i >= 0; --i) {
+    double2 acc = g[i];
+    for (int c = i + 1; c < kd; ++c) acc = csub(acc, cmul(H[i][c], y[c]));
+    y[i] = cdiv(acc, H[i][i]);
+  }
+}
+
+// One GMRES(3) smoothing step on level L, in place on u (global, pitch pu):
+// u += V y.  The basis V lives in registers; the operator is applied to the
+// tile X, and A V_j is formed twice (once for the projections, once for the
+// orthogonalised vector) rather than kept, to save registers.  The
+// Hessenberg matrix and y live in LDS, the least squares is solved by one
+// thread.
+template <typename T, int NP>
+__device__ void gt_gmres3(const Level<T>& L, v2<T>* X, const v2<T> (*tb)[GT_W], double* red, double2 (*H)[GS_M],
+                          double2* ys, v2<T>* __restrict__ u, int pu, const v2<T>* __restrict__ f, int pf) {
+  const int m = L.n - 1;
+  v2<T> V[GS_M][NP];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    int k, j;
+    if (gt_node(q, m, k, j)) X[k * GT_W + j] = u[(size_t)k * pu + j];
+  }
+  __syncthreads();
+  double nn[1] = {0.0};
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    int k, j;
+#pragma unroll
+    for (int i = 0; i < GS_M; ++i) V[i][q] = mk<T>(0, 0);
+    if (gt_node(q, m, k, j)) {
+      const v2<T> r = csub(f[(size_t)k * pf + j], gt_apply(L, X, tb, k, j));
+      V[0][q] = r;
+      nn[0] += (double)r.x * r.x + (double)r.y * r.y;
+    }
+  }
+  gt_reduce<1>(nn, red);
+  const double beta = sqrt(nn[0]);
+  if (!(beta > 0.0)) return;
+  {
+    const T sc = (T)(1.0 / beta);
+#pragma unroll
+    for (int q = 0; q < NP; ++q) V[0][q] = cscale(V[0][q], sc);
+  }
+  int kd = GS_M;
+#pragma unroll
+  for (int jj = 0; jj < GS_M; ++jj) {
+    gt_store<T, NP>(X, V[jj], m);
+    double hd[2 * GS_M];
+#pragma unroll
+    for (int t = 0; t < 2 * GS_M; ++t) hd[t] = 0.0;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      int k, j;
+      if (gt_node(q, m, k, j)) {
+        const v2<T> w = gt_apply(L, X, tb, k, j);
+#pragma unroll
+        for (int i = 0; i <= jj; ++i) {
+          const v2<T> v = V[i][q];
+          hd[2 * i] += (double)v.x * w.x + (double)v.y * w.y;
+          hd[2 * i + 1] += (double)v.x * w.y - (double)v.y * w.x;
+        }
+      }
+    }
+    gt_reduce<2 * GS_M>(hd, red);
+    double n2[1] = {0.0};
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      int k, j;
+      if (gt_node(q, m, k, j)) {
+        v2<T> w = gt_apply(L, X, tb, k, j);
+#pragma unroll
+        for (int i = 0; i <= jj; ++i) w = csub(w, cmul(mk<T>((T)hd[2 * i], (T)hd[2 * i + 1]), V[i][q]));
+        n2[0] += (double)w.x * w.x + (double)w.y * w.y;
+        if (jj + 1 < GS_M) V[jj + 1][q] = w;
+      }
+    }
+    gt_reduce<1>(n2, red);
+    const double hn = sqrt(n2[0]);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int i = 0; i <= GS_M; ++i) H[i][jj] = make_double2(i <= jj ? hd[2 * i] : 0.0, i <= jj ? hd[2 * i + 1] : 0.0);
+      H[jj + 1][jj] = make_double2(hn, 0.0);
+    }
+    if (hn == 0.0) {
+      kd = jj + 1;
+      break;
+    }
+    if (jj + 1 < GS_M) {
+      const T sc = (T)(1.0 / hn);
+#pragma unroll
+      for (int q = 0; q < NP; ++q) V[jj + 1][q] = cscale(V[jj + 1][q], sc);
+    }
+  }
+  if (threadIdx.x == 0) gt_lsq(H, beta, kd, ys);
+  __syncthreads();
+  v2<T> yv[GS_M];
+#pragma unroll
+  for (int i = 0; i < GS_M; ++i) yv[i] = mk<T>((T)ys[i].x, (T)ys[i].y);
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    int k, j;
+    if (gt_node(q, m, k, j)) {
+      v2<T> uv = u[(size_t)k * pu + j];
+#pragma unroll
+      for (int i = 0; i < GS_M; ++i)
+        if (i < kd) uv = cadd(uv, cmul(yv[i], V[i][q]));
+      u[(size_t)k * pu + j] = uv;
+    }
+  }
+}
+
+// member i of a kernel-argument array with a uniform runtime index, by
+// selects (no dynamic indexing, which would copy the arguments to scratch)
+template <typename X>
+__device__ __forceinline__ X gt_pick(const X (&a)[TMAXL], int i) {
+  static_assert(TMAXL == 4, "gt_pick covers four entries");
+  return i == 0 ? a[0] : (i == 1 ? a[1] : (i == 2 ? a[2] : a[3]));
+}
+template <typename X>
+__device__ __forceinline__ X gt_pick1(const X (&a)[TMAXL + 1], int i) {
+  static_assert(TMAXL == 4, "gt_pick1 covers five entries");
+  return i == 0 ? a[0] : (i == 1 ? a[1] : (i == 2 ? a[2] : (i == 3 ? a[3] : a[4])));
+}
+
+template <typename T, int NP>
+__global__ void __launch_bounds__(GT_THREADS) k_gs_tail(GsTailArgs<T> A) {
+  __shared__ v2<T> X[GT_W * GT_W];
+  __shared__ v2<T> tb[5][GT_W];
+  __shared__ double red[GT_WAVES * GT_NR];
+  __shared__ double2 H[GS_M + 1][GS_M];
+  __shared__ double2 ys[GS_M];
+  const int tid = threadIdx.x;
+  // down: pre-smoothing (iterate in its level's field), residual,
+  // full-weighting restriction
+  for (int i = 0; i < A.nl; ++i) {
+    const Level<T> L = gt_pick(A.L, i);
+    const int n = L.n, m = n - 1;
+    const v2<T>* f = i == 0 ? A.f0 : gt_pick1(A.f, i);
+    const int pf = i == 0 ? L.pitch : gt_pick1(A.pitch, i);
+    v2<T>* us = i == 0 ? A.u0 : gt_pick1(A.u, i);
+    const int pu = i == 0 ? L.pitch : gt_pick1(A.pitch, i);
+    gt_level_setup(L, X, tb);
+    if (i > 0 || A.zero) {
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        int k, j;
+        if (gt_node(q, m, k, j)) us[(size_t)k * pu + j] = mk<T>(0, 0);
+      }
+    }
+    for (int it = 0; it < A.nu1; ++it) gt_gmres3<T, NP>(L, X, tb, red, H, ys, us, pu, f, pf);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      int k, j;
+      if (gt_node(q, m, k, j)) X[k * GT_W + j] = us[(size_t)k * pu + j];
+    }
+    __syncthreads();
+    v2<T> r[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      int k, j;
+      r[q] = mk<T>(0, 0);
+      if (gt_node(q, m, k, j)) r[q] = csub(f[(size_t)k * pf + j], gt_apply(L, X, tb, k, j));
+    }
+    gt_store<T, NP>(X, r, m);
+    const int nc = n / 2, mc = nc - 1;
+    v2<T>* fc = gt_pick1(A.f, i + 1);
+    const int pcn = gt_pick1(A.pitch, i + 1);
+    for (int idx = tid; idx < mc * mc; idx += GT_THREADS) {
+      const int K = idx / mc + 1, J = idx % mc + 1;
+      v2<T> acc = mk<T>(0, 0);
+#pragma unroll
+      for (int a = -1; a <= 1; ++a)
+#pragma unroll
+        for (int b = -1; b <= 1; ++b) {
+          const v2<T> rv = X[(2 * K + a) * GT_W + 2 * J + b];
+          const T wgt = T((a == 0 ? 2 : 1) * (b == 0 ? 2 : 1));
+          acc = mk<T>(acc.x + wgt * rv.x, acc.y + wgt * rv.y);
+        }
+      fc[(size_t)K * pcn + J] = cscale(acc, T(1.0 / 16.0));
+    }
+  }
+  // coarsest level: u_c = Ainv f_c, one wave per row (k_coarse_solve), into X
+  {
+    const int nc = A.nc, mc = nc - 1, N = mc * mc;
+    const v2<T>* fc = gt_pick1(A.f, A.nl);
+    const int pc = gt_pick1(A.pitch, A.nl);
+    __syncthreads();                             // every restriction write of f_c is visible
+    const int w = tid >> 6, lane = tid & 63;
+    for (int i = tid; i < (nc + 1) * (nc + 1); i += GT_THREADS) {
+      const int k = i / (nc + 1), j = i % (nc + 1);
+      if (k == 0 || k == nc || j == 0 || j == nc) X[k * GT_W + j] = mk<T>(0, 0);
+    }
+    for (int row = w; row < N; row += GT_WAVES) {
+      double sr = 0, si = 0;
+      const double2* Ar = A.Ainv + (size_t)row * N;
+      for (int c = lane; c < N; c += 64) {
+        const int k = c / mc + 1, j = c % mc + 1;
+        v2<double> fv = cvt<double>(fc[(size_t)k * pc + j]);
+        double2 a = Ar[c];
+        sr += a.x * fv.x - a.y * fv.y;
+        si += a.x * fv.y + a.y * fv.x;
+      }
+      sr = wave_sum(sr);
+      si = wave_sum(si);
+      if (lane == 0) X[(row / mc + 1) * GT_W + row % mc + 1] = mk<T>((T)sr, (T)si);
+    }
+  }
+  // up: bilinear prolongation of the coarse correction, post-smoothing
+  for (int i = A.nl - 1; i >= 0; --i) {
+    const Level<T> L = gt_pick(A.L, i);
+    const int n = L.n, m = n - 1;
+    const v2<T>* f = i == 0 ? A.f0 : gt_pick1(A.f, i);
+    const int pf = i == 0 ? L.pitch : gt_pick1(A.pitch, i);
+    v2<T>* us = i == 0 ? A.u0 : gt_pick1(A.u, i);
+    const int pu = i == 0 ? L.pitch : gt_pick1(A.pitch, i);
+    __syncthreads();                             // the coarse correction in X is complete
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      int k, j;
+      if (gt_node(q, m, k, j)) {
+        const int J0 = j >> 1, J1 = (j + 1) >> 1, K0 = k >> 1, K1 = (k + 1) >> 1;
+        const v2<T> s = cadd(cadd(X[K0 * GT_W + J0], X[K0 * GT_W + J1]), cadd(X[K1 * GT_W + J0], X[K1 * GT_W + J1]));
+        const size_t idx = (size_t)k * pu + j;
+        us[idx] = cadd(us[idx], cscale(s, T(0.25)));
+      }
+    }
+    gt_level_setup(L, X, tb);
+    for (int it = 0; it < A.nu2; ++it) gt_gmres3<T, NP>(L, X, tb, red, H, ys, us, pu, f, pf);
+    if (i > 0) {
+      // the next finer level's coarse correction: this level's iterate in X
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        int k, j;
+        if (gt_node(q, m, k, j)) X[k * GT_W + j] = us[(size_t)k * pu + j];
+      }
+    }
+  }
+}
+
+template <typename T>
+void launch_gs_tail(hipStream_t s, const GsTailArgs<T>& A) {
+  // nodes per thread: enough for the top level (n = 64: 3969 nodes, 8 per
+  // thread; n <= 32: 961, 2 per thread)
+  const int m = A.L[0].n - 1;
+  if (m * m <= 2 * GT_THREADS)
+    hipLaunchKernelGGL((k_gs_tail<T, 2>), dim3(1), dim3(GT_THREADS), 0, s, A);
+  else
+    hipLaunchKernelGGL((k_gs_tail<T, (GT_MAX_N * GT_MAX_N + GT_THREADS - 1) / GT_THREADS>), dim3(1),
+                       dim3(GT_THREADS), 0, s, A);
+}
+template void launch_gs_tail<double>(hipStream_t, const GsTailArgs<double>&);
+template void launch_gs_tail<float>(hipStream_t, const GsTailArgs<float>&);
+
+// ----------------------------------------------------------------------------
 // BiCGSTAB outer loop (MGC_BICGSTAB), one iteration:
 //   p = r + beta (p - omega v)                              k_bicg_p
 //   p^ = B p  (one MG-CCCS cycle);  v = A p^, r~^H v        k_apply_dot (J = 1)

@@ -166,6 +166,10 @@ template <typename T>
 void launch_gmres3_smooth(hipStream_t s, const Level<T>& L, void* u, const void* f, void* V, size_t stride, double* st,
                           double* part);
 int gmres3_part_doubles(int n);
+// the V-cycle below and including a GMRES(3) level with n <= GT_MAX_N, in
+// one single-workgroup launch
+template <typename T>
+void launch_gs_tail(hipStream_t s, const GsTailArgs<T>& A);
 // u += e on the interior of a level-0 field
 template <typename T>
 void launch_add(hipStream_t s, int n, int pitch, const void* e, void* u);

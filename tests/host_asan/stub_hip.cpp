@@ -352,6 +352,10 @@ template void launch_gmres3_smooth<float>(hipStream_t, const Level<float>&, void
 int gmres3_part_doubles(int n) { return 8 * n; }
 template <typename T>
 void launch_add(hipStream_t s, int, int, const void*, void*) { MGC_NOP(s); }
+template <typename T>
+void launch_gs_tail(hipStream_t s, const GsTailArgs<T>&) { MGC_NOP(s); }
+template void launch_gs_tail<double>(hipStream_t, const GsTailArgs<double>&);
+template void launch_gs_tail<float>(hipStream_t, const GsTailArgs<float>&);
 template void launch_add<double>(hipStream_t, int, int, const void*, void*);
 template void launch_add<float>(hipStream_t, int, int, const void*, void*);
 void launch_bicg_p(hipStream_t s, int, int, const double2*, const double2*, double2*, const double*) { MGC_NOP(s); }
