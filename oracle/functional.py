@@ -7,6 +7,9 @@ with phi_k the regular solution of (-1/2 d^2/dx^2 + V1 - k^2/2) phi_k = 0
 asymptotic amplitude 1/sqrt(k), and
     sigma(k1,k2) = 8 pi^2 / k0^2 * |zeta|^2 / (k1 k2).
 
+Under the exponential model (Sec. 3.3 Fig. 4) the same definitions take that
+model's potentials (the *_model functions at the end).
+
 Readings (the paper leaves them open for an ECS grid): the integral runs over
 the real region x, y <= R0 with trapezoid weights (h, and h/2 at R0);
 phi_k comes from the 3-point recurrence of eq. testfunction on the real nodes
@@ -229,3 +232,96 @@ def sigma_total(g: Grid1D, Z1: float, lam: float, E: float, u: np.ndarray, chi: 
     zs = zeta_sweep(g, Z1, lam, u, chi, K * np.sin(a), K * np.cos(a))
     k0sq = 2.0 * (E + 0.5 * Z1 * Z1)
     return float(8.0 * math.pi ** 2 / k0sq * np.sum(wa * np.abs(np.array(zs)) ** 2))
+
+
+# ---------------------------------------------------------------------------
+# The same amplitudes under a general potential model (TPModel or ExpModel of
+# oracle.grid): the test functions take the model's x1 potential at the real
+# nodes, the source the model's V12, and the prefactor's k0^2 is twice the
+# energy of the incoming electron over the target's ground state,
+# 2 (E - lambda_1) with lambda_1 the lowest x1 bound state (Temkin-Poet:
+# lambda_1 = -Z1^2 / 2 in closed form, as above).
+def model_v1_real(g: Grid1D, model) -> np.ndarray:
+    """V1 at the real nodes x_j = j h, j = 1 .. n (entry 0 unused)."""
+    from .grid import ExpModel
+    V = np.zeros(g.n + 1)
+    x = g.h * np.arange(1, g.n + 1)
+    if isinstance(model, ExpModel):
+        V[1:] = -model.a1 * np.exp(-model.b1 * x * x)
+    else:
+        V[1:] = -model.Z1 / x
+    return V
+
+
+def test_function_v(g: Grid1D, V1: np.ndarray, k: float) -> np.ndarray:
+    """phi_k of eq. testfunction with the potential table V1 (real nodes):
+    the 3-point recurrence and the local-amplitude scaling of test_function."""
+    h, j0, n = g.h, g.j0, g.n
+    top = min(j0 + 1, n)
+    ph = np.zeros(top + 1)
+    ph[1] = h
+    for j in range(1, top):
+        ph[j + 1] = 2.0 * ph[j] - ph[j - 1] + 2.0 * h * h * (V1[j] - 0.5 * k * k) * ph[j]
+    jr = min(j0, top - 1)
+    p = math.sqrt(k * k - 2.0 * V1[jr])
+    dphi = (ph[jr + 1] - ph[jr - 1]) / (2.0 * h)
+    amp = math.sqrt(ph[jr] ** 2 + (dphi / p) ** 2)
+    return ph / (amp * math.sqrt(p))
+
+
+def model_k0sq(g: Grid1D, model, E: float) -> float:
+    from .cccs import bound_states
+    from .grid import ExpModel, exp_one_body
+    if not isinstance(model, ExpModel):
+        return 2.0 * (E + 0.5 * model.Z1 * model.Z1)
+    lam, _ = bound_states(g, exp_one_body(g, model.a1, model.b1), 1)
+    return 2.0 * (E - lam[0].real)
+
+
+def model_source(g: Grid1D, model, u: np.ndarray, chi: np.ndarray) -> np.ndarray:
+    """chi - V12 u with the model's two-body potential (zero on the ring)."""
+    return chi - model.potentials(g)[2] * u
+
+
+def _weights(g: Grid1D, vals: np.ndarray) -> np.ndarray:
+    n, top = g.n, min(g.j0, g.n - 1)
+    t = trapezoid_weights(g)
+    f = np.zeros(n + 1, vals.dtype)
+    f[1:top + 1] = t[1:top + 1] * vals[1:top + 1]
+    return f
+
+
+def zeta_model(g: Grid1D, model, u: np.ndarray, chi: np.ndarray, k1: float, k2: float) -> complex:
+    V1 = model_v1_real(g, model)
+    f1 = _weights(g, test_function_v(g, V1, k1))
+    f2 = _weights(g, test_function_v(g, V1, k2))
+    return complex(f2 @ model_source(g, model, u, chi) @ f1)
+
+
+def single_ionization_model(g: Grid1D, model, E: float, u: np.ndarray, chi: np.ndarray, nstates: int):
+    """(lambda_n, k_n, s_n) of eq. single-ionization under the model: phi_n the
+    bound states of the x2 one-body Hamiltonian, phi_{k_n} in x1."""
+    from .cccs import bound_states
+    V2 = model.potentials(g)[1]
+    lamB, vphi = bound_states(g, V2, nstates)
+    V1 = model_v1_real(g, model)
+    src = model_source(g, model, u, chi)
+    ks, out = [], []
+    for q in range(nstates):
+        kq = math.sqrt(2.0 * (E - lamB[q].real))
+        f1 = _weights(g, test_function_v(g, V1, kq))
+        f2 = _weights(g, vphi[q])
+        ks.append(kq)
+        out.append(complex(f2 @ src @ f1))
+    return lamB, np.array(ks), np.array(out)
+
+
+def sigma_total_model(g: Grid1D, model, E: float, u: np.ndarray, chi: np.ndarray, nodes: int = 32) -> float:
+    """sigma_tot of eq. total-double-ionization under the model (the
+    Gauss-Legendre form of sigma_total)."""
+    x, w = np.polynomial.legendre.leggauss(nodes)
+    a = (x + 1.0) * math.pi / 4.0
+    wa = w * math.pi / 4.0
+    K = math.sqrt(2.0 * E)
+    zs = np.array([zeta_model(g, model, u, chi, K * math.sin(t), K * math.cos(t)) for t in a])
+    return float(8.0 * math.pi ** 2 / model_k0sq(g, model, E) * np.sum(wa * np.abs(zs) ** 2))

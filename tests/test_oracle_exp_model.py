@@ -202,3 +202,75 @@ def test_channel_correction_improves_the_stationary_cycle_where_single_ionisatio
         st = s.solve_stationary(np.zeros_like(f), f, 1e-6, max_it=12)
         rates.append(st.relres ** (1 / st.iters))
     assert rates[0] > 0.8 and rates[1] < 0.6, rates
+
+
+# ---------------------------------------------------------------------------
+# amplitudes under the exponential model (Sec. 3.3, Fig. 4 setup)
+def test_exp_test_function_follows_the_continuous_solution_at_second_order():
+    """phi_k of the 3-point recurrence with V1 = -4.5 exp(-x^2) against the
+    regular solution of the ODE (-1/2 d2/dx2 + V1 - k^2/2) phi = 0 integrated
+    to 1e-12 (scipy's adaptive Runge-Kutta), both scaled to the local amplitude
+    1/sqrt(p) at R0: the nodal error falls by 4 per halving of h."""
+    from scipy.integrate import solve_ivp
+    from oracle import functional as fn
+    k, L, R0 = 1.3, 20.0, 15.0
+    V = lambda x: -4.5 * np.exp(-x * x)
+    sol = solve_ivp(lambda x, y: [y[1], 2.0 * (V(x) - 0.5 * k * k) * y[0]], (0.0, R0 + 1.0), [0.0, 1.0],
+                    rtol=1e-12, atol=1e-14, dense_output=True)
+    p = math.sqrt(k * k - 2.0 * V(R0))
+    yR = sol.sol(R0)
+    cont = lambda x: sol.sol(x)[0] / (math.sqrt(yR[0] ** 2 + (yR[1] / p) ** 2) * math.sqrt(p))
+    errs = []
+    for n in (256, 512, 1024):
+        g = Grid1D(n, L, R0, math.pi / 7)
+        ph = fn.test_function_v(g, fn.model_v1_real(g, ExpModel(4.5, 1.0, 4.5, 1.0, 2.0, 1.0)), k)
+        x = g.h * np.arange(g.j0 + 1)
+        errs.append(np.abs(ph[:g.j0 + 1] - cont(x)).max())
+    assert errs[2] < 2e-3
+    assert 3.6 < errs[0] / errs[1] < 4.4 and 3.8 < errs[1] / errs[2] < 4.2, errs
+
+
+def test_exp_prefactor_uses_the_printed_threshold():
+    """k0^2 = 2 (E - lambda_1): on the Fig. 4 spacing lambda_1 is the printed
+    threshold, so k0^2 = 2 (E + 1.02150069)."""
+    from oracle import functional as fn
+    g = Grid1D(512, 25.6, 12.8, math.pi / 7)
+    assert abs(fn.model_k0sq(g, ExpModel(4.5, 1.0, 4.5, 1.0, 2.0, 1.0), 0.7) - 2 * (0.7 - _printed_threshold())) < 1e-8
+
+
+def test_exp_total_cross_section_is_the_energy_integral_of_sigma():
+    """sigma_tot by Gauss-Legendre in the sharing angle against adaptive
+    quadrature of its definition int_0^E sigma(sqrt(2 eps), sqrt(2 (E - eps)))
+    d eps, on a separable field (u = 0, so the source is chi)."""
+    from scipy.integrate import quad
+    from oracle import functional as fn
+    n, E = 128, 0.6
+    g = Grid1D(n, 16.0, 12.0, math.pi / 7)
+    model = ExpModel(4.5, 1.0, 4.5, 1.0, 2.0, 1.0)
+    x = g.h * np.arange(n + 1)
+    chi = np.zeros((n + 1, n + 1), complex)
+    chi[1:n, 1:n] = np.exp(-3.0 * (x[1:n, None] + x[None, 1:n]) ** 2)
+    u = np.zeros_like(chi)
+    k0sq = fn.model_k0sq(g, model, E)
+    sig = lambda eps: (8 * math.pi ** 2 / k0sq * abs(fn.zeta_model(g, model, u, chi, math.sqrt(2 * eps),
+                                                                   math.sqrt(2 * (E - eps)))) ** 2
+                       / (math.sqrt(2 * eps) * math.sqrt(2 * (E - eps))))
+    ref, _ = quad(sig, 0.0, E, limit=200, epsabs=0.0, epsrel=1e-10)
+    got = fn.sigma_total_model(g, model, E, u, chi, nodes=48)
+    assert abs(got - ref) < 1e-8 * ref
+
+
+def test_exp_amplitudes_reduce_to_the_temkin_poet_ones_for_the_tp_model():
+    """The model-general functions with a TPModel give the Temkin-Poet
+    functions' values (same test functions, source and prefactor)."""
+    from oracle import functional as fn
+    from oracle.grid import TPModel, tp_rhs
+    n = 64
+    g = Grid1D(n, 20.0, 15.0, math.pi / 6)
+    u, chi = random_field(n, 51), tp_rhs(g, 1.0, 0.9, 1.1, 0.5)
+    m = TPModel(1.0, 0.9, 1.1)
+    assert abs(fn.zeta_model(g, m, u, chi, 0.7, 0.5) - fn.zeta(g, 1.0, 1.1, u, chi, 0.7, 0.5)) < 1e-13
+    a = fn.single_ionization_model(g, m, 0.5, u, chi, 2)[2]
+    b = fn.single_ionization(g, 1.0, 0.9, 1.1, 0.5, u, chi, 2)[2]
+    assert np.abs(a - b).max() < 1e-13 * np.abs(b).max()
+    assert abs(fn.sigma_total_model(g, m, 0.5, u, chi, 16) - fn.sigma_total(g, 1.0, 1.1, 0.5, u, chi, 16)) < 1e-12
