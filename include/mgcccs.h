@@ -229,9 +229,12 @@ mgc_status mgc_set_potential(mgc_grid g, double Z1, double Z2, double lambda);
  * a field.  Same setup as mgc_set_potential (bound states, channel potentials
  * summed directly over the nodes).  Needs a handle created with
  * pot_tables = 1 (MGC_EINVAL otherwise) and finite parameters with
- * b1, b2, d12 >= 0.  The right-hand side builder and the cross-section entry
- * points are defined for the Temkin-Poet model only and return MGC_EINVAL
- * under this model.  Invalidates the energy setup.                            */
+ * b1, b2, d12 >= 0.  The amplitude entry points (mgc_cross_section,
+ * mgc_cross_section_sweep, mgc_single_ionization, mgc_total_double_ionization
+ * and the batched call) take this model's potentials on an ECS grid with a
+ * real interior; the impact right-hand side builder and the gradient are
+ * Temkin-Poet only and return MGC_EINVAL under this model.  Invalidates the
+ * energy setup.                                                              */
 mgc_status mgc_set_potential_exp(mgc_grid g, double a1, double b1, double a2, double b2, double c12,
                                  double d12);
 
@@ -297,9 +300,14 @@ mgc_status mgc_solve_transpose(mgc_grid g, void* v, const void* gvec,
 /* Double-ionisation amplitude (Sec. 3.3 eq. double-ionization) on the real
  * region x1, x2 <= R0 with trapezoid weights:
  *   zeta = sum_{j,k<=j0} t_j t_k phi_{k1}(x1_j) phi_{k2}(x2_k) (chi - V12 u)_{kj}
- * with phi_k the regular solution of eq. testfunction (3-point recurrence)
- * normalised to asymptotic amplitude 1/sqrt(k) at R0, and
- * sigma = 8 pi^2 / k0^2 * |zeta|^2 / (k1 k2).  Synchronising.                 */
+ * with phi_k the regular solution of eq. testfunction (3-point recurrence
+ * with the x1 one-body potential of the model at the real nodes) normalised to
+ * asymptotic amplitude 1/sqrt(k) at R0, and
+ * sigma = 8 pi^2 / k0^2 * |zeta|^2 / (k1 k2), k0^2 twice the energy of the
+ * incoming electron over the target's ground state: 2 E + Z1^2 for the
+ * Temkin-Poet model, 2 (E - lambda_1) for the exponential model with lambda_1
+ * the lowest x1 bound state of the exact axis.  V12 is the model's two-body
+ * potential.  Needs gamma = 0 (a real interior).  Synchronising.              */
 mgc_status mgc_cross_section(mgc_grid g, const void* u, const void* chi,
                              double k1, double k2, double zeta[2], double* sigma);
 
@@ -321,7 +329,7 @@ mgc_status mgc_cross_section_sweep(mgc_grid g, const void* u, const void* chi, i
 /* Single-ionisation amplitudes (Sec. 3.3 eq. single-ionization):
  *   s_n = sum_{j,k<=j0} t_j t_k phi_{k_n}(x1_j) phi_n(x2_k) (chi - V12 u)_{kj},
  * n = 1 .. nstates, with phi_n the n-th lowest bound state of the exact x2
- * one-body Hamiltonian -1/2 d2/dz2 - Z2/z (eq. 1d_eigenstate on the
+ * one-body Hamiltonian -1/2 d2/dz2 + V2(z) of the model (eq. 1d_eigenstate on the
  * exterior-complex-scaled grid, bilinear normalisation, two shift-and-invert
  * refinement steps), k_n = sqrt(2 (E - Re lambda_n)) and phi_{k_n} the test
  * function of eq. testfunction in x1 (as in mgc_cross_section); t the

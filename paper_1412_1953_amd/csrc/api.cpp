@@ -146,6 +146,9 @@ struct mgc_grid_s {
   size_t zeta_f = 0, adj = 0;
   size_t sweep_f = 0, sweep_k = 0, sweep_part = 0, sweep_out = 0;   // mgc_cross_section_sweep
   size_t si_tab = 0;                       // bound states of the exact x2 Hamiltonian (single ionisation)
+  size_t v1r = 0, tm0 = 0;                 // V1 at the real nodes of the exact axis; a zero two-body table
+  std::vector<double> v1r_host;
+  double lam1x = 0;                        // lowest x1 bound state of the exact axis (exponential model)
   int si_count = 0;                        // states held in si_tab (0: none for this potential)
   std::vector<cd> si_lam;
   int nchunksB = 1;
@@ -287,6 +290,8 @@ void layout(mgc_grid g) {
   g->sweep_out = take((size_t)2 * MGC_SWEEP_MAX * sizeof(double));
   g->sweep_k = take((size_t)2 * MGC_SWEEP_MAX * sizeof(double));
   g->si_tab = take((size_t)MGC_SI_MAX * (n + 1) * 16);
+  g->v1r = take((size_t)(n + 1) * sizeof(double));
+  g->tm0 = take((size_t)(n + 1) * 16);
   g->need = off;
 }
 
@@ -1159,8 +1164,10 @@ inline Dual cst(double x) { return {x, 0.0}; }
 // recurrence on the real nodes, scaled to local amplitude 1/sqrt(p) at R0,
 // p = sqrt(k^2 - 2 V1(R0)); out[j] = t_j phi(x_j) with trapezoid weights t
 // (h, h/2 at j0) for 1 <= j <= min(j0, n-1), zero elsewhere; dout = d out / d Z1.
+// With `tab` (the potential at the real nodes, any model) the potential comes
+// from the table and the derivative part is zero.
 void test_function(const Axis& ax, double Z1, double k, std::vector<double>& out,
-                   std::vector<double>& dout) {
+                   std::vector<double>& dout, const std::vector<double>* tab = nullptr) {
   const int n = ax.n, j0 = ax.j0;
   const double h = ax.h;
   const Dual z1 = {Z1, 1.0};
@@ -1168,11 +1175,11 @@ void test_function(const Axis& ax, double Z1, double k, std::vector<double>& out
   std::vector<Dual> ph(top + 1, cst(0.0));
   ph[1] = cst(h);
   for (int j = 1; j < top; ++j) {
-    const Dual V1 = cst(0.0) - z1 / cst(j * h);
+    const Dual V1 = tab ? cst((*tab)[j]) : cst(0.0) - z1 / cst(j * h);
     ph[j + 1] = cst(2.0) * ph[j] - ph[j - 1] + cst(2.0 * h * h) * (V1 - cst(0.5 * k * k)) * ph[j];
   }
   const int jr = std::min(j0, top - 1);
-  const Dual p = dsqrt(cst(k * k) - cst(2.0) * (cst(0.0) - z1 / cst(jr * h)));
+  const Dual p = dsqrt(cst(k * k) - cst(2.0) * (tab ? cst((*tab)[jr]) : cst(0.0) - z1 / cst(jr * h)));
   const Dual dphi = (ph[jr + 1] - ph[jr - 1]) / cst(2.0 * h);
   const Dual q = dphi / p;
   const Dual amp = dsqrt(ph[jr] * ph[jr] + q * q);
@@ -1185,6 +1192,27 @@ void test_function(const Axis& ax, double Z1, double k, std::vector<double>& out
     out[j] = t * v.v;
     dout[j] = t * v.d;
   }
+}
+
+// k0^2 of the cross-section prefactor: twice the energy of the incoming
+// electron over the target's ground state (Temkin-Poet: E + Z1^2 / 2; a
+// general model: E minus the lowest x1 bound state of the exact axis).
+double k0sq_of(mgc_grid g) {
+  return g->pot.kind == POT_TP ? 2.0 * (g->E + 0.5 * g->Z1 * g->Z1) : 2.0 * (g->E - g->lam1x);
+}
+// The amplitude source chi - V12 u: for the Temkin-Poet form the kernels take
+// (tm, chi) as they are; for a general two-body table the source is formed in
+// r64 first and V12 is replaced by the zero table.
+void amp_source(mgc_grid g, hipStream_t st, const void* u, const void*& chi, const double2*& tm) {
+  if (g->pot.kind == POT_TP) {
+    tm = exact_level(g).tm;
+    return;
+  }
+  double2* s = g->at<double2>(g->r64);
+  launch_src_v12(st, g->d.n, g->lv[0].pitch, static_cast<const double2*>(chi), exact_level(g).v12,
+                 static_cast<const double2*>(u), s);
+  chi = s;
+  tm = g->at<const double2>(g->tm0);
 }
 
 }  // namespace
@@ -1340,6 +1368,26 @@ mgc_status apply_potential(mgc_grid g) {
       auto v = two_body_table(g->lv[l].ax, pm, g->lv[l].pitch);
       if ((rc = upload_cplx<double>(g, g->lv[l].v12[P64], v))) return rc;
       if (g->prec_on[P32] && (rc = upload_cplx<float>(g, g->lv[l].v12[P32], v))) return rc;
+    }
+  }
+  // the x1 potential at the real nodes of the exact axis (test functions of
+  // the amplitudes) and the zero table that stands for V12 once the source
+  // chi - V12 u has been formed with a general two-body table
+  {
+    const Axis& ex = g->exact;
+    g->v1r_host.assign(n + 1, 0.0);
+    for (int j = 1; j <= n; ++j) {
+      const double x = (double)j * ex.h;
+      g->v1r_host[j] = pm.kind == POT_TP ? 0.0 - pm.Z1 / x : -pm.a1 * std::exp(-pm.b1 * x * x);
+    }
+    if ((rc = upload(g, g->v1r, g->v1r_host.data(), (n + 1) * sizeof(double)))) return rc;
+    if ((rc = upload_cplx<double>(g, g->tm0, std::vector<cd>(n + 1, 0.0)))) return rc;
+    g->lam1x = -0.5 * pm.Z1 * pm.Z1;
+    if (pm.kind == POT_EXP) {
+      std::vector<cd> l1;
+      std::vector<std::vector<cd>> p1;
+      if (!bound_states(ex, one_body(ex, pm, 1), 1, 2, l1, p1, err)) return fail(MGC_ENUMERIC, err);
+      g->lam1x = l1[0].real();
     }
   }
   // bound states of the hierarchy's level-0 one-body Hamiltonians
@@ -1723,21 +1771,23 @@ mgc_status mgc_cross_section(mgc_grid g, const void* u, const void* chi, double 
                              double zeta[2], double* sigma) {
   mgc_status rc = check_ready(g);
   if (rc) return rc;
-  if (g->pot.kind != POT_TP) return fail(MGC_EINVAL, "defined for the Temkin-Poet model only");
   if (g->d.gamma != 0.0) return fail(MGC_EINVAL, "the amplitudes are defined on a real interior (gamma = 0)");
   if (!u || !chi || !zeta || !(k1 > 0) || !(k2 > 0)) return fail(MGC_EINVAL, "bad arguments");
   const Axis& ax = g->exact;
   const int n = ax.n, j0 = ax.j0;
   std::vector<double> f1, f2, d1v, d2v;
-  test_function(ax, g->Z1, k1, f1, d1v);
-  test_function(ax, g->Z1, k2, f2, d2v);
+  const std::vector<double>* tab = g->pot.kind == POT_TP ? nullptr : &g->v1r_host;
+  test_function(ax, g->Z1, k1, f1, d1v, tab);
+  test_function(ax, g->Z1, k2, f2, d2v, tab);
   std::vector<double> both(2 * (n + 1));
   for (int j = 0; j <= n; ++j) { both[j] = f1[j]; both[n + 1 + j] = f2[j]; }
   if ((rc = upload(g, g->zeta_f, both.data(), both.size() * sizeof(double)))) return rc;
   const double* d1 = g->at<const double>(g->zeta_f);
   double* part = g->at<double>(g->part);
   double* out = g->at<double>(g->scal);
-  launch_zeta_part(g->stream, n, g->lv[0].pitch, j0, exact_level(g).tm, d1, d1 + (n + 1), (const double2*)u,
+  const double2* tm = nullptr;
+  amp_source(g, g->stream, u, chi, tm);
+  launch_zeta_part(g->stream, n, g->lv[0].pitch, j0, tm, d1, d1 + (n + 1), (const double2*)u,
                    (const double2*)chi, part);
   launch_sum_partials(g->stream, launch_vec_blocks(n), 2, part, out);
   HIPCHK(g, hipGetLastError());
@@ -1746,7 +1796,7 @@ mgc_status mgc_cross_section(mgc_grid g, const void* u, const void* chi, double 
   HIPCHK(g, hipStreamSynchronize(g->stream));
   zeta[0] = hz[0];
   zeta[1] = hz[1];
-  const double k0sq = 2.0 * (g->E + 0.5 * g->Z1 * g->Z1);
+  const double k0sq = k0sq_of(g);
   if (sigma) *sigma = 8.0 * M_PI * M_PI / k0sq * (hz[0] * hz[0] + hz[1] * hz[1]) / (k1 * k2);
   return MGC_OK;
 }
@@ -1755,7 +1805,6 @@ mgc_status mgc_cross_section_sweep(mgc_grid g, const void* u, const void* chi, i
                                    const double* k2, double* zeta, double* sigma) {
   mgc_status rc = check_ready(g);
   if (rc) return rc;
-  if (g->pot.kind != POT_TP) return fail(MGC_EINVAL, "defined for the Temkin-Poet model only");
   if (g->d.gamma != 0.0) return fail(MGC_EINVAL, "the amplitudes are defined on a real interior (gamma = 0)");
   if (!u || !chi || !k1 || !k2 || !zeta) return fail(MGC_EINVAL, "null argument");
   if (npairs < 1 || npairs > MGC_SWEEP_MAX) return fail(MGC_EINVAL, "npairs must lie in [1, MGC_SWEEP_MAX]");
@@ -1771,16 +1820,19 @@ mgc_status mgc_cross_section_sweep(mgc_grid g, const void* u, const void* chi, i
   kk.insert(kk.end(), k2, k2 + npairs);
   if ((rc = upload(g, g->sweep_k, kk.data(), kk.size() * sizeof(double)))) return rc;
   double* F = g->at<double>(g->sweep_f);
-  launch_sweep_testfn(g->stream, n, ax.j0, ax.h, g->Z1, npairs, pp, g->at<const double>(g->sweep_k), F);
+  launch_sweep_testfn(g->stream, n, ax.j0, ax.h, g->at<const double>(g->v1r), npairs, pp,
+                      g->at<const double>(g->sweep_k), F);
   const double* F1T = F;
   double* out = g->at<double>(g->sweep_out);
-  launch_zeta_sweep(g->stream, n, g->lv[0].pitch, top, pp, exact_level(g).tm, F1T, F1T + (size_t)(n + 1) * pp,
+  const double2* tm = nullptr;
+  amp_source(g, g->stream, u, chi, tm);
+  launch_zeta_sweep(g->stream, n, g->lv[0].pitch, top, pp, tm, F1T, F1T + (size_t)(n + 1) * pp,
                     (const double2*)u, (const double2*)chi, g->at<double>(g->sweep_part), out);
   HIPCHK(g, hipGetLastError());
   std::vector<double> hz((size_t)2 * pp);
   HIPCHK(g, hipMemcpyAsync(hz.data(), out, hz.size() * sizeof(double), hipMemcpyDeviceToHost, g->stream));
   HIPCHK(g, hipStreamSynchronize(g->stream));
-  const double k0sq = 2.0 * (g->E + 0.5 * g->Z1 * g->Z1);
+  const double k0sq = k0sq_of(g);
   for (int a = 0; a < npairs; ++a) {
     zeta[2 * a] = hz[2 * a];
     zeta[2 * a + 1] = hz[2 * a + 1];
@@ -1890,7 +1942,7 @@ mgc_status ensure_si_states(mgc_grid g, int nstates) {
   const Axis& ax = g->exact;
   std::vector<std::vector<cd>> phi;
   std::string err;
-  if (!bound_states(ax, one_body(ax, g->Z2), nstates, 2, g->si_lam, phi, err)) return fail(MGC_ENUMERIC, err);
+  if (!bound_states(ax, one_body(ax, g->pot, 2), nstates, 2, g->si_lam, phi, err)) return fail(MGC_ENUMERIC, err);
   std::vector<cd> tab((size_t)nstates * (ax.n + 1));
   for (int q = 0; q < nstates; ++q)
     for (int k = 0; k <= ax.n; ++k) tab[(size_t)q * (ax.n + 1) + k] = phi[q][k];
@@ -1912,10 +1964,13 @@ mgc_status enqueue_sweep(mgc_grid g, const void* u, const void* chi, int npairs,
   const int pp = (npairs + 63) / 64 * 64;
   double* F = g->at<double>(g->sweep_f);
   HIPCHK(g, hipMemcpyAsync(g->ws + g->sweep_k, kk, (size_t)2 * npairs * sizeof(double), hipMemcpyHostToDevice, st));
-  launch_sweep_testfn(st, n, ax.j0, ax.h, g->Z1, npairs, pp, g->at<const double>(g->sweep_k), F);
+  launch_sweep_testfn(st, n, ax.j0, ax.h, g->at<const double>(g->v1r), npairs, pp, g->at<const double>(g->sweep_k),
+                      F);
   if (bound > 0)
     launch_bound_weights(st, n, top, ax.j0, ax.h, bound, pp, g->at<const double2>(g->si_tab), F + (size_t)(n + 1) * pp);
-  launch_zeta_sweep(st, n, g->lv[0].pitch, top, pp, exact_level(g).tm, F, F + (size_t)(n + 1) * pp,
+  const double2* tm = nullptr;
+  amp_source(g, st, u, chi, tm);
+  launch_zeta_sweep(st, n, g->lv[0].pitch, top, pp, tm, F, F + (size_t)(n + 1) * pp,
                     (const double2*)u, (const double2*)chi, g->at<double>(g->sweep_part), g->at<double>(g->sweep_out));
   HIPCHK(g, hipGetLastError());
   HIPCHK(g, hipMemcpyAsync(out, g->ws + g->sweep_out, (size_t)2 * pp * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1933,7 +1988,6 @@ struct XsecJob {
 mgc_status enqueue_xsec(mgc_grid g, const void* u, const void* chi, int nstates, int nodes, XsecJob& J,
                         hipStream_t st) {
   if (g->d.gamma != 0.0) return fail(MGC_EINVAL, "the amplitudes are defined on a real interior (gamma = 0)");
-  if (g->pot.kind != POT_TP) return fail(MGC_EINVAL, "defined for the Temkin-Poet model only");
   J.nstates = nstates;
   J.nodes = nodes;
   mgc_status rc;
@@ -1993,7 +2047,7 @@ void finish_xsec(mgc_grid g, const XsecJob& J, double* s, double* kn, double* si
         zeta[2 * q + 1] = zi;
       }
     }
-    const double k0sq = 2.0 * (g->E + 0.5 * g->Z1 * g->Z1);
+    const double k0sq = k0sq_of(g);
     if (sigma_tot) *sigma_tot = 8.0 * M_PI * M_PI / k0sq * acc;
   }
 }
@@ -2004,7 +2058,6 @@ extern "C" {
 mgc_status mgc_single_ionization(mgc_grid g, const void* u, const void* chi, int nstates, double* s, double* kn) {
   mgc_status rc = check_ready(g);
   if (rc) return rc;
-  if (g->pot.kind != POT_TP) return fail(MGC_EINVAL, "defined for the Temkin-Poet model only");
   if (!u || !chi || !s) return fail(MGC_EINVAL, "null argument");
   if (nstates < 1 || nstates > MGC_SI_MAX || nstates > g->d.n - 2)
     return fail(MGC_EINVAL, "nstates must lie in [1, MGC_SI_MAX] and below n - 1");
@@ -2019,7 +2072,6 @@ mgc_status mgc_total_double_ionization(mgc_grid g, const void* u, const void* ch
                                        double* zeta) {
   mgc_status rc = check_ready(g);
   if (rc) return rc;
-  if (g->pot.kind != POT_TP) return fail(MGC_EINVAL, "defined for the Temkin-Poet model only");
   if (!u || !chi || !sigma_tot) return fail(MGC_EINVAL, "null argument");
   if (nodes < 1 || nodes > MGC_SWEEP_MAX) return fail(MGC_EINVAL, "nodes must lie in [1, MGC_SWEEP_MAX]");
   XsecJob J;

@@ -2439,8 +2439,9 @@ __global__ void __launch_bounds__(256) k_zeta_sweep_part(int n, int pitch, int t
 // at j0) is folded in.  Nodes outside 1 .. min(j0, n - 1) and padding pairs
 // are zero.  Contraction is off so every value is the correctly rounded
 // sequence of operations of the host's single-pair test function.
-__global__ void __launch_bounds__(64) k_sweep_testfn(int n, int j0, double h, double Z1, int npairs, int pp,
-                                                     const double* __restrict__ kk, double* __restrict__ F) {
+__global__ void __launch_bounds__(64) k_sweep_testfn(int n, int j0, double h, const double* __restrict__ V1r,
+                                                     int npairs, int pp, const double* __restrict__ kk,
+                                                     double* __restrict__ F) {
 #pragma clang fp contract(off)
   constexpr int CH = 1024;                         // potential values staged per round
   __shared__ double V[CH];
@@ -2459,7 +2460,7 @@ __global__ void __launch_bounds__(64) k_sweep_testfn(int n, int j0, double h, do
   for (int jc = 1; jc < top; jc += CH) {
     const int cnt = top - jc < CH ? top - jc : CH;
     __syncthreads();
-    for (int i = threadIdx.x; i < cnt; i += 64) V[i] = 0.0 - Z1 / ((double)(jc + i) * h);
+    for (int i = threadIdx.x; i < cnt; i += 64) V[i] = V1r[jc + i];
     __syncthreads();
     for (int i = 0; i < cnt; ++i) {
       const double pn = (2.0 * p0 - pm) + (g2 * (V[i] - kh)) * p0;
@@ -2469,7 +2470,7 @@ __global__ void __launch_bounds__(64) k_sweep_testfn(int n, int j0, double h, do
     }
   }
   const int jr = j0 < top - 1 ? j0 : top - 1;
-  const double pr = sqrt(k * k - 2.0 * (0.0 - Z1 / ((double)jr * h)));
+  const double pr = sqrt(k * k - 2.0 * V1r[jr]);
   const double dphi = (col[(size_t)(jr + 1) * pp] - col[(size_t)(jr - 1) * pp]) / (2.0 * h);
   const double q = dphi / pr, f = col[(size_t)jr * pp];
   const double amp = sqrt(f * f + q * q);
@@ -2965,9 +2966,24 @@ void launch_zeta_part(hipStream_t s, int n, int pitch, int j0, const double2* tm
   hipLaunchKernelGGL(k_zeta_part, vec_grid(n), dim3(256), 0, s, n, pitch, j0, tm, f1, f2, u, chi, part);
 }
 int zeta_sweep_blocks(int top) { return ((top + SWR - 1) / SWR) * SWJ; }
-void launch_sweep_testfn(hipStream_t s, int n, int j0, double h, double Z1, int npairs, int pp, const double* kk,
-                         double* F) {
-  hipLaunchKernelGGL(k_sweep_testfn, dim3((2 * pp + 63) / 64), dim3(64), 0, s, n, j0, h, Z1, npairs, pp, kk, F);
+void launch_sweep_testfn(hipStream_t s, int n, int j0, double h, const double* V1r, int npairs, int pp,
+                         const double* kk, double* F) {
+  hipLaunchKernelGGL(k_sweep_testfn, dim3((2 * pp + 63) / 64), dim3(64), 0, s, n, j0, h, V1r, npairs, pp, kk, F);
+}
+
+// s = chi - V12 u with a general two-body table (the source of the amplitude
+// integrals under a potential model without the lambda / z_max form)
+__global__ void __launch_bounds__(256) k_src_v12(int n, int pitch, const double2* __restrict__ chi,
+                                                 const double2* __restrict__ v12, const double2* __restrict__ u,
+                                                 double2* __restrict__ out) {
+  MGC_NODE_LOOP(n, k, j) {
+    const size_t idx = (size_t)k * pitch + j;
+    out[idx] = csub(chi[idx], cmul(v12[idx], u[idx]));
+  }
+}
+void launch_src_v12(hipStream_t s, int n, int pitch, const double2* chi, const double2* v12, const double2* u,
+                    double2* out) {
+  hipLaunchKernelGGL(k_src_v12, vec_grid(n), dim3(256), 0, s, n, pitch, chi, v12, u, out);
 }
 // ----------------------------------------------------------------------------
 // GMRES(3) smoothing substitute of the V-cycle (Sec. 6.1), on one level:

@@ -156,9 +156,13 @@ void launch_zeta_part(hipStream_t s, int n, int pitch, int j0, const double2* tm
 int zeta_sweep_blocks(int top);
 // The sweep's weighted test functions on the device: F is [2][n+1][pp]
 // (x1 side with momenta kk[0 .. npairs), x2 side with kk[npairs .. 2 npairs)),
-// zero for the padding pairs npairs .. pp - 1.  Needs 1 <= j0 and n >= 2.
-void launch_sweep_testfn(hipStream_t s, int n, int j0, double h, double Z1, int npairs, int pp, const double* kk,
-                         double* F);
+// zero for the padding pairs npairs .. pp - 1; V1r[j]: the one-body potential
+// at the real node x_j = j h.  Needs 1 <= j0 and n >= 2.
+void launch_sweep_testfn(hipStream_t s, int n, int j0, double h, const double* V1r, int npairs, int pp,
+                         const double* kk, double* F);
+// out = chi - v12 u (FP64 fields, interior nodes)
+void launch_src_v12(hipStream_t s, int n, int pitch, const double2* chi, const double2* v12, const double2* u,
+                    double2* out);
 // One GMRES(3) smoothing step on a level (Sec. 6.1): u += V y minimising
 // ||f - A(u + V y)|| over K_3(A, f - A u).  V: 4 level fields `stride`
 // elements apart; st: 32 doubles of state; part: gmres3_part_doubles(n).

@@ -338,7 +338,8 @@ void launch_zeta_part(hipStream_t s, int, int, int, const double2*, const double
                       const double2*, double*) {
   MGC_NOP(s);
 }
-void launch_sweep_testfn(hipStream_t s, int, int, double, double, int, int, const double*, double*) { MGC_NOP(s); }
+void launch_sweep_testfn(hipStream_t s, int, int, double, const double*, int, int, const double*, double*) { MGC_NOP(s); }
+void launch_src_v12(hipStream_t s, int, int, const double2*, const double2*, const double2*, double2*) { MGC_NOP(s); }
 void launch_bound_weights(hipStream_t s, int, int, int, double, int, int, const double2*, double*) { MGC_NOP(s); }
 void launch_bicg_init(hipStream_t s, double*, const double*) { MGC_NOP(s); }
 template <typename T>

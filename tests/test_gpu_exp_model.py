@@ -148,7 +148,57 @@ def test_exp_model_rejections():
     with pytest.raises(mgcccs.MGCError) as e:
         g.build_rhs_tp(g.field())
     assert e.value.status == mgcccs.MGC_EINVAL
-    u, f = g.field(), g.field()
-    with pytest.raises(mgcccs.MGCError) as e:
-        g.single_ionization(u, f, 1)
-    assert e.value.status == mgcccs.MGC_EINVAL
+
+
+# ---------------------------------------------------------------------------
+# amplitudes of the exponential model on an ECS grid (the Fig. 4 setup of
+# Sec. 3.3: V12 = 2 exp(-(x1 + x2)^2), ECS at pi/7)
+FIG4 = (4.5, 1.0, 4.5, 1.0, 2.0, 1.0)
+
+
+@pytest.fixture(scope="module")
+def fig4_solution():
+    from paper_1412_1953_amd import mgcccs
+    c = Case(256, 25.6, 0.5, 5, 2, R0frac=0.75, theta=math.pi / 7, pc_gamma=GAM, pc_first_level=1, exp=FIG4)
+    g = c.grid()
+    o = c.oracle()
+    f = contour_source(c, o)
+    ut, ft = g.field(), g.from_numpy(f)
+    res = g.solve(ut, ft, outer=mgcccs.FGMRES, inner=mgcccs.FP64, restart=10, max_it=3000, tol=1e-11)
+    assert res.status == mgcccs.MGC_OK, res
+    return c, g, o, ut, ft, f
+
+
+def test_exp_amplitude_sweep_matches_oracle(fig4_solution):
+    from oracle import functional as fn
+    from oracle.grid import ExpModel
+    c, g, o, ut, ft, f = fig4_solution
+    K = math.sqrt(2 * c.E)
+    al = np.linspace(0.05, math.pi / 2 - 0.05, 20)
+    k1, k2 = K * np.cos(al), K * np.sin(al)
+    zs, sig = g.cross_section_sweep(ut, ft, k1, k2)
+    u = to_np(ut)
+    m = ExpModel(*FIG4)
+    ref = np.array([fn.zeta_model(o.g, m, u, f, a, b) for a, b in zip(k1, k2)])
+    zs = np.array(zs)
+    assert np.abs(zs - ref).max() < 1e-12 * np.abs(ref).max()
+    k0sq = fn.model_k0sq(o.g, m, c.E)
+    sref = 8 * math.pi ** 2 / k0sq * np.abs(ref) ** 2 / (k1 * k2)
+    assert np.abs(np.array(sig) - sref).max() < 1e-11 * sref.max()
+    z1, s1 = g.cross_section(ut, ft, k1[3], k2[3])
+    assert abs(z1 - zs[3]) < 1e-13 * abs(zs[3])
+
+
+def test_exp_total_and_single_ionisation_match_oracle(fig4_solution):
+    from oracle import functional as fn
+    from oracle.grid import ExpModel
+    c, g, o, ut, ft, f = fig4_solution
+    u = to_np(ut)
+    m = ExpModel(*FIG4)
+    st, _ = g.total_double_ionization(ut, ft, nodes=24)
+    sref = fn.sigma_total_model(o.g, m, c.E, u, f, nodes=24)
+    assert abs(st - sref) < 1e-11 * sref
+    s, kn = g.single_ionization(ut, ft, 2)
+    lam, kref, sref2 = fn.single_ionization_model(o.g, m, c.E, u, f, 2)
+    assert np.abs(np.array(kn) - kref).max() < 1e-12
+    assert np.abs(np.array(s) - sref2).max() < 1e-11 * np.abs(sref2).max()
