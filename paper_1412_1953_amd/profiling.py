@@ -2,6 +2,7 @@
 
     python3 -m paper_1412_1953_amd.profiling stats <kernel_stats.csv> <kernel_trace.csv> <out.txt> -- <command>
     python3 -m paper_1412_1953_amd.profiling traffic <kernel> <fetch.csv> <write.csv> <out.txt> [--largest] -- <command>
+    python3 -m paper_1412_1953_amd.profiling counters <counters.csv>[,<more.csv>] <out.txt> <kernel>... [--largest] -- <command>
 
 `stats` lists the kernels by total time (rocprofv3 --kernel-trace --stats)
 and, per kernel, the launch shapes (grid sizes) with their average duration.
@@ -11,6 +12,10 @@ scaled by what it reads for a plain device copy of known size (the 256 MiB
 copy that bench.py --copy-probe performs).  The record carries the SHA-256
 of the kernel source it was measured on; bench.py reports the traffic only
 while that source is unchanged.
+`counters` averages every counter of --pmc runs per dispatch of each named
+kernel class (a class of the library's timer or a kernel-name pattern):
+derived metrics such as VALUBusy, VALUUtilization, OccupancyPercent and
+LDSBankConflict, and raw ones such as SQ_WAVES or SQ_INSTS_VALU.
 """
 from __future__ import annotations
 
@@ -148,6 +153,44 @@ def traffic(kclass, fetch_csv, write_csv, out, command, largest=False, name=None
         fh.write("\n".join(lines) + "\n")
 
 
+def counters(csv_path, out, classes, command, largest=False):
+    """Mean value per dispatch of every counter in csv_path for each class."""
+    res = {}                               # kernel -> (VGPRs, AGPRs, SGPRs, LDS bytes, scratch bytes, workgroup)
+    rows = []
+    for r in (r for path in csv_path.split(",") for r in csv.DictReader(open(path))):
+        nm = short(r["Kernel_Name"])
+        rows.append((nm, r["Counter_Name"], float(r["Counter_Value"]), int(r["Grid_Size"]), r.get("Dispatch_Id", "")))
+        res[nm] = tuple(r.get(k, "?") for k in ("VGPR_Count", "Accum_VGPR_Count", "SGPR_Count", "LDS_Block_Size",
+                                                  "Scratch_Size", "Workgroup_Size"))
+    names = sorted({c for _, c, _, _, _ in rows})
+    lines = [f"command: {command}", f"kernels.hip sha256: {source_sha()}",
+             "mean per dispatch" + (" (largest grid of each class only)" if largest else ""), ""]
+    head = f"{'class':>14} {'dispatches':>10} " + " ".join(f"{c:>22}" for c in names)
+    lines.append(head)
+    for cl in classes:
+        pat = re.compile(CLASS_PATTERN.get(cl, cl))
+        sel = [r for r in rows if pat.search(r[0])]
+        if largest and sel:
+            gmax = max(r[3] for r in sel)
+            sel = [r for r in sel if r[3] == gmax]
+        if not sel:
+            lines.append(f"{cl:>14} {0:>10}")
+            continue
+        vals = collections.defaultdict(list)
+        for r in sel:
+            vals[r[1]].append(r[2])
+        nd = max(len(v) for v in vals.values())
+        cells = [f"{sum(vals[c]) / len(vals[c]):>22.4f}" if vals[c] else f"{'-':>22}" for c in names]
+        lines.append(f"{cl:>14} {nd:>10} " + " ".join(cells))
+    lines += ["", "resources per kernel (VGPRs, AGPRs, SGPRs, LDS bytes, scratch bytes, workgroup size):"]
+    for cl in classes:
+        pat = re.compile(CLASS_PATTERN.get(cl, cl))
+        for nm in sorted({r[0] for r in rows if pat.search(r[0])}):
+            lines.append(f"  {nm}: {', '.join(res[nm])}")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def main(argv):
     if "--" not in argv:
         raise SystemExit(__doc__)
@@ -157,6 +200,9 @@ def main(argv):
         stats(args[1], args[2], args[3], command)
     elif args[0] == "traffic":
         traffic(args[1], args[2], args[3], args[4], command, largest="--largest" in args)
+    elif args[0] == "counters":
+        counters(args[1], args[2], [a for a in args[3:] if a != "--largest"], command,
+                 largest="--largest" in args)
     else:
         raise SystemExit(__doc__)
 
