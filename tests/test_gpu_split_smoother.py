@@ -62,20 +62,27 @@ def test_split_smoother_fgmres(c, fp32):
 
 @pytest.mark.parametrize("fp32", [False, True], ids=["fp64", "fp32"])
 def test_split_smoother_schedules_agree_bitwise(fp32):
-    """Level pairs and the coarse tail never take a GMRES(3) level: every
-    launch schedule gives the same iterate bit for bit."""
+    """Level pairs and tile sizes never change the arithmetic: those
+    schedules give the same iterate bit for bit, with the
+    GMRES(3) levels in the single-workgroup tail and with per-level launches;
+    the tail itself sums its reductions in another order, so tail and
+    per-level launches agree to rounding."""
     from paper_1412_1953_amd import mgcccs
     c = case(256, 3)
     g = c.grid()
     chi = g.build_rhs_tp(g.field())
-    out = []
-    for sch in ((-1, 1, 1), (0, 0, 0), (0b11111, 1, 1)):
+    out = {}
+    for sch in ((-1, 1, 1), (0b11111, 0, 1), (0, 1, 1), (-1, 1, 0), (0, 0, 0), (0b11111, 1, 0)):
         g.set_schedule(*sch)
         u = g.from_numpy(c.u0())
         g.solve(u, chi, outer=mgcccs.FGMRES, inner=mgcccs.FP32 if fp32 else mgcccs.FP64, restart=10,
                 max_it=12, tol=1e-300)
-        out.append(to_np(u))
-    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+        out[sch] = to_np(u)
+    tail = [v for k, v in out.items() if k[2] == 1]
+    per_level = [v for k, v in out.items() if k[2] == 0]
+    assert all(np.array_equal(tail[0], v) for v in tail[1:])
+    assert all(np.array_equal(per_level[0], v) for v in per_level[1:])
+    assert rel2(tail[0], per_level[0]) < (1e-5 if fp32 else 1e-12)
 
 
 def test_gs_from_is_validated():
