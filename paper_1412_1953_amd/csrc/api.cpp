@@ -314,6 +314,7 @@ GmresState gmres_state(mgc_grid g) {
   s.beta = take(2);
   s.kstar = reinterpret_cast<int*>(take(2));
   s.kused = reinterpret_cast<int*>(take(2));
+  s.ticket = reinterpret_cast<unsigned*>(take(2));
   return s;
 }
 
@@ -906,6 +907,10 @@ void enqueue_fgmres_cycle(mgc_grid g, void* u, const mgc_solve_opts* o, double t
   g->kt.run = -1;
   const bool per_step = g->kt.which == MGC_KT_APPLY_DOT || g->kt.which == MGC_KT_AXPY;
   const double Nint = (double)(n - 1) * (n - 1);
+  // threshold of the selective second Gram-Schmidt pass; MGC_REORTH_ETA > 1
+  // forces the second pass in every step (a test of that path)
+  const char* eta_env = std::getenv("MGC_REORTH_ETA");
+  const double eta = eta_env && std::atof(eta_env) > 0 ? std::atof(eta_env) : REORTH_ETA;
   launch_gmres_begin(st, gs, m);
   for (int j = 0; j < mm; ++j) {
     g->kt.open = per_step || j == 0;
@@ -928,14 +933,12 @@ void enqueue_fgmres_cycle(mgc_grid g, void* u, const mgc_solve_opts* o, double t
     kt_mark(g, st, ta, 1);
     // classical Gram-Schmidt with a selective second pass, then the
     // Hessenberg column and its Givens rotation on the device
-    for (int pass = 0; pass < 2; ++pass) {
-      // timed: the first pass (the second one runs only when needed)
-      const int tx = pass == 0 ? kt_slot(g, MGC_KT_AXPY, Nint * (16.0 * (j + 1) + 32.0)) : -1;  // J in, Y in/out
-      kt_mark(g, st, tx, 0);
-      launch_axpy_pass(st, n, pitch, stride64, W, j + 1, Wn, pass ? p1 : p0, pass ? p2 : p1, gs, pass, p0);
-      kt_mark(g, st, tx, 1);
-    }
-    launch_gmres_step(st, n, pitch, p2, gs, j, m, tol_abs);
+    // timed: the first pass (the second one runs only when needed)
+    const int tx = kt_slot(g, MGC_KT_AXPY, Nint * (16.0 * (j + 1) + 32.0));    // J in, Y in/out
+    kt_mark(g, st, tx, 0);
+    launch_axpy_pass(st, n, pitch, stride64, W, j + 1, Wn, p0, p1, gs);
+    kt_mark(g, st, tx, 1);
+    launch_reorth_step(st, n, pitch, stride64, W, j + 1, Wn, p0, p1, p2, gs, m, tol_abs, eta);
   }
   g->kt.open = true;
   launch_gmres_solve(st, gs, m, mm);

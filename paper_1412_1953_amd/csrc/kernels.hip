@@ -1979,12 +1979,13 @@ __device__ __forceinline__ int flat_block() { return blockIdx.x + gridDim.x * bl
 // FGMRES bookkeeping on the device, by one block after the reductions
 // finished.  Loads go to LDS in parallel; only the short sequential Givens
 // arithmetic runs on one thread.
+template <int NT>
 __device__ void gmres_step_blk(const GmresState& st, int j, int m, double tol_abs, const double* __restrict__ part,
-                               int nb) {
+                               int nb, int ps) {
   // after the final norm: column j of H (= projections, then the norm),
   // earlier rotations, new rotation, residual estimate.  The state loads are
-  // issued together with the norm's partial loads.
-  __shared__ double col[2 * 34], rot[4 * 33], gg[4], red[4];
+  // issued together with the norm's partial loads (nb partials, ps apart).
+  __shared__ double col[2 * 34], rot[4 * 33], gg[4], red[NT / 64];
   const int tid = threadIdx.x + blockDim.x * threadIdx.y;
   const int R = m + 1;
   double h0 = 0, h1 = 0, r0 = 0, r1 = 0, r2 = 0, r3 = 0, g0 = 0, g1 = 0;
@@ -2002,9 +2003,10 @@ __device__ void gmres_step_blk(const GmresState& st, int j, int m, double tol_ab
     g0 = st.g[2 * j];
     g1 = st.g[2 * j + 1];
   }
-  // ||Y||^2: one partial per thread, wave sums added in wave order
+  // ||Y||^2: the partials strided over the threads, wave sums added in
+  // wave order
   double s = 0.0;
-  for (int b = tid; b < nb; b += 256) s += part[b];
+  for (int b = tid; b < nb; b += NT) s += part[(size_t)b * ps];
   s = wave_sum(s);
   if ((tid & 63) == 0) red[tid >> 6] = s;
   if (tid <= j) {
@@ -2019,7 +2021,8 @@ __device__ void gmres_step_blk(const GmresState& st, int j, int m, double tol_ab
   }
   __syncthreads();
   if (tid == 0) {
-    const double nrm2 = (red[0] + red[1]) + (red[2] + red[3]);
+    double nrm2 = 0.0;
+    for (int w = 0; w < NT / 64; ++w) nrm2 += red[w];
     st.nrm2[0] = nrm2;
     gg[0] = g0;
     gg[1] = g1;
@@ -2064,14 +2067,15 @@ __device__ void gmres_step_blk(const GmresState& st, int j, int m, double tol_ab
 // Fused Arnoldi passes of FGMRES step j (FP64 basis W_0..W_{J-1}, J = j+1,
 // new vector Y = W_{j+1}), classical Gram-Schmidt with one re-orthogonalisation:
 //   k_apply_dot  : Y = A z_j (exact operator)          per-block c_q = W_q^H Y
-//   k_axpy_pass 0: a_q = s_q^2 c_q, Y -= sum a_q W_q,   per-block c_q = W_q^H Y
-//   k_axpy_pass 1: same with the new c_q,               per-block ||Y||^2
+//   k_axpy_pass  : a_q = s_q^2 c_q, Y -= sum a_q W_q,   per-block c_q = W_q^H Y
+//   k_reorth_step: same with the new c_q (pass 1),      per-block ||Y||^2,
+//                  then ||Y||, Hessenberg column j and its Givens rotation
 // The re-orthogonalisation is selective: the operator pass and pass 0 also
-// accumulate ||Y||^2, and pass 1 skips its sweep (forwarding pass 0's norm)
-// when pass 0 kept more than REORTH_ETA of the norm, since one classical pass
-// then loses orthogonality only at the level of rounding / REORTH_ETA.
-//   k_gmres_step : ||Y||, Hessenberg column j and its Givens rotation
-// Three sweeps of (J + 2) vectors per step.  s_q = 1/||W_q|| (unscaled basis).
+// accumulate ||Y||^2, and pass 1 skips its sweep (taking pass 0's norm)
+// when pass 0 kept more than eta of the norm, since one classical pass then
+// loses orthogonality only at the level of rounding / eta.
+// Two sweeps of (J + 2) vectors per step, three with the second pass.
+// s_q = 1/||W_q|| (unscaled basis).
 // No pass finishes its own reduction: a per-block fence and ticket would cost
 // far more than the kernel boundary, so each consumer adds up the producer's
 // per-block partials itself (every block in the same fixed order; block 0
@@ -2084,7 +2088,6 @@ __device__ void gmres_step_blk(const GmresState& st, int j, int m, double tol_ab
 constexpr int AB = 512;          // threads per block of the Arnoldi passes
 constexpr int AD_SY = 8;         // k_apply_dot block: 64 columns x 8 row groups
 constexpr int AX_BLOCKS = 256;   // at most this many blocks per Arnoldi pass
-constexpr double REORTH_ETA = 0.05;
 
 #define MGC_JFOR(q) _Pragma("unroll") for (int q = 0; q < J; ++q)
 
@@ -2127,28 +2130,17 @@ __global__ void __launch_bounds__(AB) k_apply_dot(Level<double> L, const v2<TZ>*
   }
 }
 
-// Flat axpy pass over Nf = (n+1) * pitch nodes.  pin: nbin x (2J + 1)
+// Flat axpy sweep over Nf = (n+1) * pitch nodes.  pin: nbin x (2J + 1)
 // per-block dots and ||Y||^2 of the previous pass; pass 0 starts the
-// projections h, pass 1 adds.  Pass 1 (NORM) also reads the operator pass's
-// partials (p0, nb0 blocks) to decide whether it is needed at all.
+// projections h, pass 1 adds.  Pass 0 writes the new per-block dots and
+// ||Y||^2, pass 1 (NORM) ||Y||^2 only, to pout.
 template <int J, bool NORM>
-__global__ void __launch_bounds__(AB) k_axpy_pass(size_t Nf, size_t stride, const double2* __restrict__ W,
-                                                  double2* __restrict__ Y, const double* __restrict__ pin,
-                                                  int nbin, double* __restrict__ pout, GmresState st,
-                                                  int pass, const double* __restrict__ p0, int nb0) {
+__device__ __forceinline__ void axpy_sweep(size_t Nf, size_t stride, const double2* __restrict__ W,
+                                           double2* __restrict__ Y, const double* __restrict__ pin, int nbin,
+                                           double* __restrict__ pout, const GmresState& st, int pass) {
   constexpr int NV = NORM ? 1 : 2 * J + 1;
   __shared__ double dsum[2 * J + 1];
-  __shared__ double nn[2];
   __shared__ double2 cf[J];
-  if (NORM) {
-    // ||Y||^2 after pass 0 and before it decide whether pass 1 runs
-    finish_sum_pair<AB>(pin + 2 * J, nbin, 2 * J + 1, p0 + 2 * J, nb0, 2 * J + 1, nn);
-    if (nn[0] >= REORTH_ETA * REORTH_ETA * nn[1]) {
-      // pass 0 kept enough of the norm: its ||Y||^2 partials are the result
-      if (threadIdx.x == 0) pout[blockIdx.x] = pin[(size_t)blockIdx.x * (2 * J + 1) + 2 * J];
-      return;
-    }
-  }
   finish_sum_nt<AB>(pin, nbin, 2 * J + 1, dsum);
   if (threadIdx.x < J) {
     const int i = threadIdx.x;
@@ -2194,14 +2186,45 @@ __global__ void __launch_bounds__(AB) k_axpy_pass(size_t Nf, size_t stride, cons
     for (int q = 0; q < NV; ++q) pout[(size_t)blockIdx.x * NV + q] = tot[q];
   }
 }
-#undef MGC_JFOR
 
-// ||Y||^2 from the final pass's partials (one per thread, wave sums added in
-// wave order), then column j of H and its rotation.
-__global__ void __launch_bounds__(256) k_gmres_step(const double* __restrict__ part, int nb, GmresState st,
-                                                    int j, int m, double tol_abs) {
-  gmres_step_blk(st, j, m, tol_abs, part, nb);
+template <int J>
+__global__ void __launch_bounds__(AB) k_axpy_pass(size_t Nf, size_t stride, const double2* __restrict__ W,
+                                                  double2* __restrict__ Y, const double* __restrict__ pin,
+                                                  int nbin, double* __restrict__ pout, GmresState st) {
+  axpy_sweep<J, false>(Nf, stride, W, Y, pin, nbin, pout, st, 0);
 }
+
+// Pass 1 and the Givens step in one launch.  Every block first decides from
+// the ||Y||^2 partials of the operator pass (p0) and of pass 0 (pin) whether
+// the second sweep is needed.  Usually it is not: then block 0 alone forms
+// column j of H from pass 0's ||Y||^2 partials and the other blocks end at
+// once.  Otherwise every block sweeps, and the block that finishes last (a
+// device-scope fence and ticket per block, paid only on this rare path)
+// forms the column from the sweep's partials and clears the ticket.
+template <int J>
+__global__ void __launch_bounds__(AB) k_reorth_step(size_t Nf, size_t stride, const double2* __restrict__ W,
+                                                    double2* __restrict__ Y, const double* __restrict__ pin,
+                                                    int nbin, double* __restrict__ pout, GmresState st,
+                                                    const double* __restrict__ p0, int nb0, int j, int m,
+                                                    double tol_abs, double eta) {
+  __shared__ double nn[2];
+  __shared__ int last;
+  finish_sum_pair<AB>(pin + 2 * J, nbin, 2 * J + 1, p0 + 2 * J, nb0, 2 * J + 1, nn);
+  if (nn[0] >= eta * eta * nn[1]) {
+    // pass 0 kept enough of the norm: its ||Y||^2 partials are the result
+    if (blockIdx.x == 0) gmres_step_blk<AB>(st, j, m, tol_abs, pin + 2 * J, nbin, 2 * J + 1);
+    return;
+  }
+  axpy_sweep<J, true>(Nf, stride, W, Y, pin, nbin, pout, st, 1);
+  __threadfence();
+  if (threadIdx.x == 0) last = atomicAdd(st.ticket, 1u) == gridDim.x - 1 ? 1 : 0;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  if (threadIdx.x == 0) st.ticket[0] = 0u;
+  gmres_step_blk<AB>(st, j, m, tol_abs, pout, gridDim.x, 1);
+}
+#undef MGC_JFOR
 
 // u += sum_q coef_q Z_q with Z stored in precision TZ.
 template <typename TZ, int JMAX>
@@ -2861,33 +2884,30 @@ template void launch_apply_dot<float>(hipStream_t, const Level<double>&, const v
                                       int, double2*, double*);
 
 void launch_axpy_pass(hipStream_t s, int n, int pitch, size_t stride, const double2* W, int J,
-                      double2* Y, const double* part_in, double* part_out, const GmresState& st,
-                      int pass, const double* part0) {
+                      double2* Y, const double* part0, double* part1, const GmresState& st) {
   const size_t Nf = (size_t)(n + 1) * pitch;
   const int nb = axpy_blocks(n, pitch);
   const int nb0 = (int)(apply_dot_grid(n).grid.x * apply_dot_grid(n).grid.y);
-  const int nbin = pass == 0 ? nb0 : nb;
-#define MGC_AXN(JT)                                                                                \
-  hipLaunchKernelGGL((k_axpy_pass<JT, true>), dim3(nb), dim3(AB), 0, s, Nf, stride, W, Y, part_in,   \
-                     nbin, part_out, st, pass, part0, nb0)
 #define MGC_AXD(JT)                                                                                 \
-  hipLaunchKernelGGL((k_axpy_pass<JT, false>), dim3(nb), dim3(AB), 0, s, Nf, stride, W, Y, part_in,   \
-                     nbin, part_out, st, pass, part0, nb0)
-  if (pass == 1) {
-    MGC_JSWITCH(MGC_AXN)
-  } else {
-    MGC_JSWITCH(MGC_AXD)
-  }
-#undef MGC_AXN
+  hipLaunchKernelGGL((k_axpy_pass<JT>), dim3(nb), dim3(AB), 0, s, Nf, stride, W, Y, part0, nb0, part1, st)
+  MGC_JSWITCH(MGC_AXD)
 #undef MGC_AXD
 }
-#undef MGC_JSWITCH
 
-void launch_gmres_step(hipStream_t s, int n, int pitch, const double* part2, const GmresState& st,
-                       int j, int m, double tol_abs) {
-  hipLaunchKernelGGL(k_gmres_step, dim3(1), dim3(256), 0, s, part2, axpy_blocks(n, pitch), st, j, m,
-                     tol_abs);
+void launch_reorth_step(hipStream_t s, int n, int pitch, size_t stride, const double2* W, int J, double2* Y,
+                        const double* part0, const double* part1, double* part2, const GmresState& st, int m,
+                        double tol_abs, double eta) {
+  const size_t Nf = (size_t)(n + 1) * pitch;
+  const int nb = axpy_blocks(n, pitch);
+  const int nb0 = (int)(apply_dot_grid(n).grid.x * apply_dot_grid(n).grid.y);
+  const int j = J - 1;
+#define MGC_RS(JT)                                                                                  \
+  hipLaunchKernelGGL((k_reorth_step<JT>), dim3(nb), dim3(AB), 0, s, Nf, stride, W, Y, part1, nb, part2, st, \
+                     part0, nb0, j, m, tol_abs, eta)
+  MGC_JSWITCH(MGC_RS)
+#undef MGC_RS
 }
+#undef MGC_JSWITCH
 template <typename TZ>
 void launch_update(hipStream_t s, int n, int pitch, size_t stride, const void* Z, int J,
                    const double2* coef, double2* u) {

@@ -50,6 +50,7 @@ struct GmresState {
   double* beta;    // [1]
   int* kstar;      // [1]           first step meeting the tolerance (-1: none)
   int* kused;      // [1]
+  unsigned* ticket;  // [1]         blocks done in k_reorth_step's second sweep (0 between launches)
 };
 
 int launch_stencil_blocks(int n);
@@ -107,20 +108,22 @@ void launch_cccs(hipStream_t s, const Level<T>& L, void* u, const void* f, const
 
 // Arnoldi step j of FGMRES over the FP64 basis W_0..W_{J-1} (J = j+1 <= 16),
 // new vector Y = W_{j+1}; part0..part2 hold ARNOLDI_PART doubles each.
-//   apply_dot : Y = A z, per-block dots W^H Y and ||Y||^2                 -> part0
-//   axpy pass0: coefficients from part0, Y -= ..., dots W^H Y, ||Y||^2    -> part1
-//   axpy pass1: if needed (selective re-orthogonalisation) coefficients
-//               from part1, Y -= ..., ||Y||^2; else pass 0's ||Y||^2     -> part2
-//   gmres_step: ||Y|| from part2, Hessenberg column j, Givens rotation
+//   apply_dot  : Y = A z, per-block dots W^H Y and ||Y||^2                  -> part0
+//   axpy_pass  : coefficients from part0, Y -= ..., dots W^H Y, ||Y||^2     -> part1
+//   reorth_step: if pass 0 kept less than eta of ||Y|| (selective
+//                re-orthogonalisation) coefficients from part1, Y -= ...,
+//                ||Y||^2 -> part2; then ||Y|| (from part2, else from pass
+//                0's part1), Hessenberg column j and its Givens rotation
 constexpr int ARNOLDI_PART = 256 * 33;
 template <typename TZ>
 void launch_apply_dot(hipStream_t s, const Level<double>& L, const void* z, size_t stride,
                       const double2* W, int J, double2* Y, double* part0);
 void launch_axpy_pass(hipStream_t s, int n, int pitch, size_t stride, const double2* W, int J,
-                      double2* Y, const double* part_in, double* part_out, const GmresState& st,
-                      int pass, const double* part0);
-void launch_gmres_step(hipStream_t s, int n, int pitch, const double* part2, const GmresState& st,
-                       int j, int m, double tol_abs);
+                      double2* Y, const double* part0, double* part1, const GmresState& st);
+void launch_reorth_step(hipStream_t s, int n, int pitch, size_t stride, const double2* W, int J, double2* Y,
+                        const double* part0, const double* part1, double* part2, const GmresState& st, int m,
+                        double tol_abs, double eta);
+constexpr double REORTH_ETA = 0.05;     // default eta
 template <typename TZ>
 void launch_update(hipStream_t s, int n, int pitch, size_t stride, const void* Z, int J,
                    const double2* coef, double2* u);

@@ -32,7 +32,7 @@ COPY_BYTES = 1 << 28                       # bench.py --copy-probe
 # kernel classes of the library's timer -> kernel-name pattern
 CLASS_PATTERN = {
     "apply_dot": r"k_apply_dot<double",
-    "axpy": r"k_axpy_pass<\d+, false>",
+    "axpy": r"k_axpy_pass<\d+>",
     "s1": r"k_s1_zero<double\b|k_s1_pair<double>|k_tail_down<double>",
     "s2": r"k_s2_zero<double\b|k_s2_pair<double>|k_tail_up<double>",
     "cccs_project": r"k_cccs_project<double",

@@ -271,10 +271,13 @@ template void launch_apply_dot<double>(hipStream_t, const Level<double>&, const 
 template void launch_apply_dot<float>(hipStream_t, const Level<double>&, const void*, size_t, const double2*, int,
                                       double2*, double*);
 void launch_axpy_pass(hipStream_t s, int, int, size_t, const double2*, int, double2*, const double*, double*,
-                      const GmresState&, int, const double*) {
+                      const GmresState&) {
   MGC_NOP(s);
 }
-void launch_gmres_step(hipStream_t s, int, int, const double*, const GmresState&, int, int, double) { MGC_NOP(s); }
+void launch_reorth_step(hipStream_t s, int, int, size_t, const double2*, int, double2*, const double*, const double*,
+                        double*, const GmresState&, int, double, double) {
+  MGC_NOP(s);
+}
 template <typename TZ>
 void launch_update(hipStream_t s, int n, int, size_t, const void*, int, const double2*, double2* u) {
   const double q = shrink(n);
