@@ -36,6 +36,8 @@ CACHE_PATH = os.path.join(_HERE, "tuning_cache.json")
 HIERARCHIES = [(1, 0.0, 15.0), (1, 5.0, 15.0), (1, 10.0, 15.0), (0, 0.0, 10.0), (0, 0.0, 15.0)]
 SCHEDULE_ITERS = 30
 SCHEDULE_REPEATS = 3
+# FGMRES restart length of the tuning solves (the timed solves use the same)
+RESTART = 6
 
 _cache = None
 
@@ -101,7 +103,7 @@ def _solve_time(g, w, chi, inner, max_it, tol=None):
     u = g.from_numpy(initial_guess(w.n, w.seed))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    r = g.solve(u, chi, outer=mgcccs.FGMRES, inner=inner, restart=10, max_it=max_it,
+    r = g.solve(u, chi, outer=mgcccs.FGMRES, inner=inner, restart=RESTART, max_it=max_it,
                 tol=w.tol if tol is None else tol)
     torch.cuda.synchronize()
     return time.perf_counter() - t0, r
