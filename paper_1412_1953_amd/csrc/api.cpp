@@ -949,6 +949,9 @@ void enqueue_fgmres_cycle(mgc_grid g, void* u, const mgc_solve_opts* o, double t
 
 // True residual W_0 = f - A u with ||W_0||^2, ||f||^2 finished in-kernel into
 // scal[0..1] and ||W_0||^2 copied to the Krylov state (next cycle's start).
+// report slot in the handle's scalars: ||r||^2, ||f||^2, steps used
+constexpr int REPORT = 32;
+
 void enqueue_true_residual(mgc_grid g, const void* u, const void* f, hipStream_t st) {
   GmresState gs = gmres_state(g);
   Finish fin;
@@ -995,7 +998,11 @@ mgc_status solve_fgmres(mgc_grid g, void* u, const void* f, const mgc_solve_opts
         hipGraph_t graph;
         hipError_t e = hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
+          // the restart cycle, the true residual of the new iterate (the next
+          // cycle's W_0) and the report the host reads
           enqueue_fgmres_cycle(g, u, o, o->tol * fn, mm, g->cap);
+          enqueue_true_residual(g, u, f, g->cap);
+          launch_report(g->cap, g->at<double>(g->scal), gs.kused, g->at<double>(g->scal) + REPORT);
           e = hipStreamEndCapture(g->cap, &graph);
         }
         g->kt.which = sel;
@@ -1022,12 +1029,16 @@ mgc_status solve_fgmres(mgc_grid g, void* u, const void* f, const mgc_solve_opts
       g->kt.which = sel;
       if (g->failed) return MGC_EHIP;
       kt_slots = timed ? g->kt.used : 0;
+      enqueue_true_residual(g, u, f, s);
+      launch_report(s, g->at<double>(g->scal), gs.kused, g->at<double>(g->scal) + REPORT);
     }
-    rc = exact_residual(g, u, f, W, &rr, &ff, gs.nrm2);
-    if (rc) return rc;
-    int kused = mm;
-    HIPCHK(g, hipMemcpyAsync(&kused, gs.kused, sizeof(int), hipMemcpyDeviceToHost, s));
+    // one read-back per restart cycle: ||r||^2, ||f||^2 and the steps used
+    double rep[3];
+    HIPCHK(g, hipMemcpyAsync(rep, g->at<double>(g->scal) + REPORT, sizeof(rep), hipMemcpyDeviceToHost, s));
     HIPCHK(g, hipStreamSynchronize(s));
+    rr = rep[0];
+    ff = rep[1];
+    const int kused = (int)rep[2];
     if (kt_slots > 0)
       kt_harvest(g, kt_slots, use_graph ? g->graph.kt_bytes : g->kt.bytes,
                  use_graph ? g->graph.kt_count : g->kt.count);
@@ -2132,7 +2143,6 @@ struct mgc_batch_s {
 };
 
 namespace {
-constexpr int REPORT = 32;                 // report slot in the handle's scalars
 
 struct BatchSolve {
   void* u = nullptr;
