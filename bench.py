@@ -12,6 +12,8 @@ value = solved unknowns per second = 3 * 1023^2 / (seconds per step).
 Further legs of the same JSON line:
   mixed          the same step with the complex-FP32 MG-CCCS cycle inside the
                  FP64 FGMRES;
+  bicgstab       the same step with MG-CCCS-preconditioned BiCGSTAB instead of
+                 FGMRES, FP64 and FP32 cycles;
   batched        the step's solves run together through the batch entry point,
                  FP64 and FP32 cycles;
   c2             the 2049^2 workload (E = 0.1): one FP64 and one mixed solve;
@@ -59,6 +61,7 @@ def parse():
     p.add_argument("--max-it", type=int, default=20000)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-mixed", action="store_true")
+    p.add_argument("--no-bicgstab", action="store_true", help="skip the BiCGSTAB outer-solver leg")
     p.add_argument("--no-batch", action="store_true", help="skip the batched legs")
     p.add_argument("--no-sweep", action="store_true", help="skip the cross-section sweep leg")
     p.add_argument("--no-c2", action="store_true", help="skip the 2049^2 leg")
@@ -88,12 +91,13 @@ def make_problem(w, torch, fp32=True):
     return g, chi, u0, u
 
 
-def run_step(problems, inner, torch, max_it, tol=1e-10):
+def run_step(problems, inner, torch, max_it, tol=1e-10, outer=None):
     from paper_1412_1953_amd import mgcccs
+    outer = mgcccs.FGMRES if outer is None else outer
     out = []
     for g, chi, u0, u in problems:
         u.copy_(u0)
-        r = g.solve(u, chi, outer=mgcccs.FGMRES, inner=inner, restart=RESTART, max_it=max_it, tol=tol)
+        r = g.solve(u, chi, outer=outer, inner=inner, restart=RESTART, max_it=max_it, tol=tol)
         out.append(r)
     return out
 
@@ -105,7 +109,7 @@ def use_schedule(problems, inner, wls):
         g.set_schedule(*autotune.schedule_of(w, inner == mgcccs.FP32))
 
 
-def time_steps(problems, inner, torch, steps, warmup, max_it, kclass=0, tol=1e-10):
+def time_steps(problems, inner, torch, steps, warmup, max_it, kclass=0, tol=1e-10, outer=None):
     """Seconds per step; with kclass, the library's HIP-event timer brackets
     the launches of that kernel inside the timed steps (on the stream they
     run on), in every fourth restart cycle of each solve.
@@ -114,14 +118,14 @@ def time_steps(problems, inner, torch, steps, warmup, max_it, kclass=0, tol=1e-1
     for g, *_ in problems:
         g.set_kernel_timer(kclass)
     for _ in range(warmup):
-        run_step(problems, inner, torch, max_it, tol)
+        run_step(problems, inner, torch, max_it, tol, outer)
     torch.cuda.synchronize()
     for g, *_ in problems:
         g.read_kernel_timer()                      # drop the warmup's figures
     t0 = time.perf_counter()
     res = []
     for _ in range(steps):
-        res = run_step(problems, inner, torch, max_it, tol)
+        res = run_step(problems, inner, torch, max_it, tol, outer)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     ms = launches = nbytes = floor = 0
@@ -458,6 +462,16 @@ def main():
                          "iters": [r.iters for r in r32], "relres": [r.relres for r in r32],
                          "status": [r.status for r in r32],
                          "speedup_vs_fp64": dt64 / dt32}
+    if not a.no_bicgstab:
+        # the same step with MG-CCCS-preconditioned BiCGSTAB as the outer solver
+        # (two cycles per iteration), FP64 and FP32 cycle
+        line["bicgstab"] = {}
+        for name, inner in (("fp64", mgcccs.FP64), ("mixed", mgcccs.FP32)):
+            use_schedule(problems, inner, wls)
+            dtb, rb, _ = time_steps(problems, inner, torch, a.steps, a.warmup, a.max_it, outer=mgcccs.BICGSTAB)
+            line["bicgstab"][name] = {"value": unknowns / dtb, "ms_per_step": dtb * 1e3,
+                                      "iters": [r.iters for r in rb], "relres": [r.relres for r in rb],
+                                      "status": [r.status for r in rb], "speedup_vs_fp64_fgmres": dt64 / dtb}
     if not a.no_batch:
         for name, inner in (("batched", mgcccs.FP64), ("batched_mixed", mgcccs.FP32)):
             use_schedule(problems, inner, wls)
