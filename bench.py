@@ -339,6 +339,27 @@ def traffic_from_profile(kernel):
     return float(fields["traffic bytes per launch"])
 
 
+def profiler_duration(kclass):
+    """Mean kernel duration (us) of timer class `kclass` on the timed workload
+    from the committed rocprofv3 summary, or None when there is none or the
+    kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "kernels_tp1025_fp64_3energies.txt")
+    src = os.path.join(ROOT, "paper_1412_1953_amd", "csrc", "kernels.hip")
+    if not os.path.exists(path):
+        return None
+    with open(src, "rb") as fh:
+        sha = hashlib.sha256(fh.read()).hexdigest()
+    lines = open(path).read().splitlines()
+    if f"kernels.hip sha256: {sha}" not in lines:
+        return None
+    for ln in lines:
+        parts = ln.split()
+        if len(parts) >= 4 and parts[0] == kclass and parts[1].isdigit():
+            return float(parts[2])
+    return None
+
+
 def copy_probe(torch):
     """A plain 256 MiB device-to-device copy, the reference for the byte
     counters (read and write sizes known exactly)."""
@@ -455,6 +476,12 @@ def main():
                             "avg_us": fig["avg_us"], "avg_us_raw_events": fig["avg_us_raw_events"],
                             "event_floor_us_per_launch": fig["event_floor_us_per_launch"],
                             "bytes_per_launch": fig["bytes_per_launch"]}
+        # the same kernel's mean duration in the committed profiler summary of
+        # this step, and the fraction it gives (a cross-check of the events)
+        pd = profiler_duration(a.roofline_kernel)
+        line["roofline"]["profiler_avg_us"] = pd
+        line["roofline"]["profiler_frac"] = (fig["bytes_per_launch"] / (pd * 1e-6) / 1e9 / HBM_PEAK_GBS
+                                             if pd else None)
     if not a.no_mixed:
         use_schedule(problems, mgcccs.FP32, wls)
         dt32, r32, _ = time_steps(problems, mgcccs.FP32, torch, a.steps, a.warmup, a.max_it)

@@ -380,11 +380,11 @@ mgc_status mgc_cross_section_grad(mgc_grid g, const void* u, const void* chi, do
  * depend on the step (APPLY_DOT, AXPY), the first step of the cycle for the
  * others.  S1 and S2 launches of
  * all levels follow each other, so one event pair brackets each such run.
- * Right before each bracket a second event pair brackets one empty kernel
- * launch: its duration (floor_ms) is what the event nodes and a launch add
- * to a bracket, so that total_ms - floor_ms estimates the kernels' own time
- * (short by the empty kernel's own run time).  The empty launch is one more
- * kernel in the timed restart cycles.
+ * Right before each bracket a second event pair brackets nothing: its
+ * duration (floor_ms) is what the event nodes alone add to a bracket, and
+ * total_ms - floor_ms is the kernels' time as the events see it (on the
+ * timed 1025^2 workload a few microseconds per launch below the profiler's
+ * kernel duration: the bracket's start overlaps the kernel's dispatch).
  * The durations, the launch count and the kernels' algorithmic bytes
  * (compulsory loads and stores of their operands over the interior nodes)
  * accumulate until mgc_read_kernel_timer, which returns and clears them.

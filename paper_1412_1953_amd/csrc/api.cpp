@@ -481,9 +481,8 @@ int kt_slot(mgc_grid g, int kind, double bytes) {
 void kt_record(mgc_grid g, hipStream_t s, hipEvent_t ev);
 void kt_mark(mgc_grid g, hipStream_t s, int slot, int end) {
   if (slot < 0) return;
-  if (!end) {
+  if (!end) {                              // an event pair around nothing: the pair's own cost
     kt_record(g, s, g->kt.fev[2 * slot]);
-    launch_nop(s);
     kt_record(g, s, g->kt.fev[2 * slot + 1]);
   }
   kt_record(g, s, g->kt.ev[2 * slot + end]);

@@ -2953,8 +2953,6 @@ __global__ void k_report(const double* __restrict__ scal, const int* __restrict_
 }
 // An empty launch: the timer brackets it to measure what the event nodes and
 // one launch add around a bracketed run.
-__global__ void __launch_bounds__(64) k_nop() {}
-void launch_nop(hipStream_t s) { hipLaunchKernelGGL(k_nop, dim3(1), dim3(64), 0, s); }
 
 void launch_report(hipStream_t s, const double* scal, const int* kused, double* rep) {
   hipLaunchKernelGGL(k_report, dim3(1), dim3(64), 0, s, scal, kused, rep);

@@ -139,7 +139,6 @@ void launch_ir_scale(hipStream_t s, const double* nrm2, double Nn, double* sc);
 void launch_copy_scalar(hipStream_t s, const double* src, double* dst);
 // rep[0..1] = scal[0..1] (||r||^2, ||f||^2), rep[2] = kused (device memory)
 void launch_report(hipStream_t s, const double* scal, const int* kused, double* rep);
-void launch_nop(hipStream_t s);                                 // empty launch (timer floor)
 void launch_fill_zero(hipStream_t s, void* p, size_t bytes);   // bytes: multiple of 16
 void launch_rhs_tp(hipStream_t s, int n, int pitch, int j0, const double2* z, double Z1, double Z2,
                    double lam, double k0, double2* chi);

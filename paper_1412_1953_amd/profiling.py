@@ -70,13 +70,10 @@ def stats(stats_csv, trace_csv, out, command):
     # its runs of consecutive launches per launch (what one event pair around
     # such a run covers, inter-kernel gaps included)
     trace = sorted(csv.DictReader(open(trace_csv)), key=lambda r: int(r["Start_Timestamp"]))
-    # the profiler's own per-dispatch floor: the empty kernel that the event
-    # timer launches before each bracket (k_nop), when the run has one
-    nops = [r for r in rows if short(r["Name"]).endswith("k_nop")]
-    floor_us = float(nops[0]["AverageNs"]) / 1e3 if nops else 0.0
-    lines += ["", f"empty-kernel floor (k_nop mean duration): {floor_us:.2f} us",
-              "timer classes (mean per launch; 'net' = kernel us minus the empty-kernel floor):",
-              f"{'class':>13} {'launches':>8} {'kernel us':>10} {'net us':>8} {'run span us':>12}  kernels"]
+    lines += ["", f"kernels.hip sha256: {source_sha()}",
+              "timer classes (mean kernel duration per launch, and the mean span of its runs of consecutive",
+              "launches per launch):",
+              f"{'class':>13} {'launches':>8} {'kernel us':>10} {'run span us':>12}  kernels"]
     for kc, pat in CLASS_PATTERN.items():
         rx = re.compile(pat)
         n = busy = span = 0
@@ -93,8 +90,7 @@ def stats(stats_csv, trace_csv, out, command):
         if run is not None:
             span += run[1] - run[0]
         if n:
-            lines.append(f"{kc:>13} {n:8d} {busy / n / 1e3:10.2f} {busy / n / 1e3 - floor_us:8.2f} "
-                         f"{span / n / 1e3:12.2f}  {pat}")
+            lines.append(f"{kc:>13} {n:8d} {busy / n / 1e3:10.2f} {span / n / 1e3:12.2f}  {pat}")
     lines += ["", "launch shapes (grid x, grid y in work-items):",
               f"{'calls':>6} {'avg us':>8}  kernel [grid]"]
     for (nm, gx, gy), (c, d) in sorted(shapes.items(), key=lambda x: -x[1][1])[:40]:

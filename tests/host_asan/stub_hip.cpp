@@ -322,7 +322,6 @@ void launch_report(hipStream_t s, const double* scal, const int* kused, double* 
     rep[2] = (double)kused[0];
   });
 }
-void launch_nop(hipStream_t s) { MGC_NOP(s); }
 void launch_fill_zero(hipStream_t s, void* p, size_t bytes) {
   enqueue(s, [=] { std::memset(p, 0, bytes); });
 }
