@@ -886,7 +886,9 @@ mgc_status solve_ir(mgc_grid g, void* u, const void* f, const mgc_solve_opts* o,
 // ---- FGMRES -------------------------------------------------------------------
 // One FGMRES restart cycle of mm <= m steps enqueued on stream st: Arnoldi
 // with the MG-CCCS preconditioner, device-side Givens bookkeeping, the small
-// least-squares solve and the update of u.  No host synchronisation.
+// least-squares solve and the update of u.  No host synchronisation.  The
+// cycle's start (beta, g) is already on the device: launch_gmres_begin after
+// the first residual, launch_cycle_end after each cycle.
 void enqueue_fgmres_cycle(mgc_grid g, void* u, const mgc_solve_opts* o, double tol_abs, int mm,
                           hipStream_t st) {
   const int n = g->d.n, pitch = g->lv[0].pitch, m = o->restart;
@@ -910,7 +912,6 @@ void enqueue_fgmres_cycle(mgc_grid g, void* u, const mgc_solve_opts* o, double t
   // forces the second pass in every step (a test of that path)
   const char* eta_env = std::getenv("MGC_REORTH_ETA");
   const double eta = eta_env && std::atof(eta_env) > 0 ? std::atof(eta_env) : REORTH_ETA;
-  launch_gmres_begin(st, gs, m);
   for (int j = 0; j < mm; ++j) {
     g->kt.open = per_step || j == 0;
     double2* Wj = W + (size_t)j * stride64;
@@ -937,27 +938,28 @@ void enqueue_fgmres_cycle(mgc_grid g, void* u, const mgc_solve_opts* o, double t
     kt_mark(g, st, tx, 0);
     launch_axpy_pass(st, n, pitch, stride64, W, j + 1, Wn, p0, p1, gs);
     kt_mark(g, st, tx, 1);
-    launch_reorth_step(st, n, pitch, stride64, W, j + 1, Wn, p0, p1, p2, gs, m, tol_abs, eta);
+    launch_reorth_step(st, n, pitch, stride64, W, j + 1, Wn, p0, p1, p2, gs, m, mm, tol_abs, eta);
   }
   g->kt.open = true;
-  launch_gmres_solve(st, gs, m, mm);
   if (f32) launch_update<float>(st, n, pitch, stridez, Z, mm, gs.upcoef, (double2*)u);
   else launch_update<double>(st, n, pitch, stridez, Z, mm, gs.upcoef, (double2*)u);
   g->stream = saved;
 }
 
-// True residual W_0 = f - A u with ||W_0||^2, ||f||^2 finished in-kernel into
-// scal[0..1] and ||W_0||^2 copied to the Krylov state (next cycle's start).
 // report slot in the handle's scalars: ||r||^2, ||f||^2, steps used
 constexpr int REPORT = 32;
 
-void enqueue_true_residual(mgc_grid g, const void* u, const void* f, hipStream_t st) {
+// After a restart cycle: the true residual W_0 = f - A u of the new iterate
+// (the next cycle's first basis vector), its norm and ||f|| into scal[0..1]
+// and the Krylov state, the report the host reads (scal[REPORT..]) and the
+// next cycle's start, in two launches.
+void enqueue_cycle_end(mgc_grid g, const void* u, const void* f, int m, hipStream_t st) {
   GmresState gs = gmres_state(g);
-  Finish fin;
-  fin.out = g->at<double>(g->scal);
-  fin.copy_to = gs.nrm2;
-  launch_stencil<double, double, double, double>(st, exact_level(g), u, f, g->at<double2>(g->W), 0,
-                                                 g->at<double>(g->part), fin);
+  double* scal = g->at<double>(g->scal);
+  double* part = g->at<double>(g->part);
+  launch_stencil<double, double, double, double>(st, exact_level(g), u, f, g->at<double2>(g->W), 0, part,
+                                                 Finish{});
+  launch_cycle_end(st, g->d.n, part, scal, gs, m, scal + REPORT);
 }
 
 mgc_status solve_fgmres(mgc_grid g, void* u, const void* f, const mgc_solve_opts* o, mgc_stats* st) {
@@ -975,6 +977,7 @@ mgc_status solve_fgmres(mgc_grid g, void* u, const void* f, const mgc_solve_opts
   double rr, ff;
   mgc_status rc = exact_residual(g, u, f, W, &rr, &ff, gs.nrm2);
   if (rc) return rc;
+  launch_gmres_begin(s, gs, m);
   const double fn = std::sqrt(ff);
   double rel = std::sqrt(rr) / fn;
   record(st, 0, rel);
@@ -998,10 +1001,9 @@ mgc_status solve_fgmres(mgc_grid g, void* u, const void* f, const mgc_solve_opts
         hipError_t e = hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
           // the restart cycle, the true residual of the new iterate (the next
-          // cycle's W_0) and the report the host reads
+          // cycle's W_0), the report the host reads and the next start
           enqueue_fgmres_cycle(g, u, o, o->tol * fn, mm, g->cap);
-          enqueue_true_residual(g, u, f, g->cap);
-          launch_report(g->cap, g->at<double>(g->scal), gs.kused, g->at<double>(g->scal) + REPORT);
+          enqueue_cycle_end(g, u, f, m, g->cap);
           e = hipStreamEndCapture(g->cap, &graph);
         }
         g->kt.which = sel;
@@ -1028,8 +1030,7 @@ mgc_status solve_fgmres(mgc_grid g, void* u, const void* f, const mgc_solve_opts
       g->kt.which = sel;
       if (g->failed) return MGC_EHIP;
       kt_slots = timed ? g->kt.used : 0;
-      enqueue_true_residual(g, u, f, s);
-      launch_report(s, g->at<double>(g->scal), gs.kused, g->at<double>(g->scal) + REPORT);
+      enqueue_cycle_end(g, u, f, m, s);
     }
     // one read-back per restart cycle: ||r||^2, ||f||^2 and the steps used
     double rep[3];
@@ -2162,12 +2163,9 @@ mgc_status capture_cycle(mgc_grid g, BatchSolve& s, const mgc_solve_opts* o) {
     (void)hipGraphExecDestroy(s.exec);
     s.exec = nullptr;
   }
-  GmresState gs = gmres_state(g);
-  double* scal = g->at<double>(g->scal);
   HIPCHK(g, hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal));
   enqueue_fgmres_cycle(g, s.u, o, o->tol * s.fn, s.mm, g->cap);
-  enqueue_true_residual(g, s.u, s.f, g->cap);
-  launch_report(g->cap, scal, gs.kused, scal + REPORT);
+  enqueue_cycle_end(g, s.u, s.f, o->restart, g->cap);
   hipGraph_t graph = nullptr;
   HIPCHK(g, hipStreamEndCapture(g->cap, &graph));
   if (g->failed) {
@@ -2261,6 +2259,7 @@ mgc_status mgc_batch_solve(mgc_batch b, void* const* u, const void* const* f, co
       cleanup();
       return rc;
     }
+    launch_gmres_begin(s, gmres_state(g), o->restart);
     v[i].fn = std::sqrt(ff);
     v[i].rel = std::sqrt(rr) / v[i].fn;
     if (stats) record(&stats[i], 0, v[i].rel);

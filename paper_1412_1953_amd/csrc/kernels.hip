@@ -2075,6 +2075,44 @@ __device__ void gmres_step_blk(const GmresState& st, int j, int m, double tol_ab
   }
 }
 
+// Least squares of the cycle (one block of NT threads, after its last Givens
+// step): y = H(1:k,1:k)^{-1} g(1:k); k = first step meeting the tolerance,
+// else the mm <= m steps the cycle performed; update coefficients y_i.  H and
+// g are staged in LDS by all threads, the back substitution runs on one thread.
+template <int NT>
+__device__ void gmres_solve_blk(const GmresState& st, int m, int mm) {
+  __shared__ double Hs[2 * 33 * 32], gs[2 * 33], ys[2 * 32];
+  const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+  const int R = m + 1;
+  __syncthreads();                     // the block's own H and g stores are done
+  for (int q = tid; q < 2 * R * m; q += NT) Hs[q] = st.H[q];
+  for (int q = tid; q < 2 * R; q += NT) gs[q] = st.g[q];
+  __syncthreads();
+  if (tid == 0) {
+    const int k = (st.kstar[0] > 0 && st.kstar[0] <= mm) ? st.kstar[0] : mm;
+    st.kused[0] = k;
+    for (int i = k - 1; i >= 0; --i) {
+      double vr = gs[2 * i], vi = gs[2 * i + 1];
+      for (int c = i + 1; c < k; ++c) {
+        const double hr = Hs[2 * (c * R + i)], hi = Hs[2 * (c * R + i) + 1];
+        vr -= hr * ys[2 * c] - hi * ys[2 * c + 1];
+        vi -= hr * ys[2 * c + 1] + hi * ys[2 * c];
+      }
+      const double dr = Hs[2 * (i * R + i)], di = Hs[2 * (i * R + i) + 1];
+      const double den = dr * dr + di * di;
+      ys[2 * i] = (vr * dr + vi * di) / den;
+      ys[2 * i + 1] = (vi * dr - vr * di) / den;
+    }
+    for (int i = k; i < m; ++i) { ys[2 * i] = 0; ys[2 * i + 1] = 0; }
+  }
+  __syncthreads();
+  if (tid < m) {
+    st.y[2 * tid] = ys[2 * tid];
+    st.y[2 * tid + 1] = ys[2 * tid + 1];
+    st.upcoef[tid] = make_double2(ys[2 * tid], ys[2 * tid + 1]);
+  }
+}
+
 // ----------------------------------------------------------------------------
 // Fused Arnoldi passes of FGMRES step j (FP64 basis W_0..W_{J-1}, J = j+1,
 // new vector Y = W_{j+1}), classical Gram-Schmidt with one re-orthogonalisation:
@@ -2206,7 +2244,8 @@ __global__ void __launch_bounds__(AB) k_axpy_pass(size_t Nf, size_t stride, cons
   axpy_sweep<J, false>(Nf, stride, W, Y, pin, nbin, pout, st, 0);
 }
 
-// Pass 1 and the Givens step in one launch.  Every block first decides from
+// Pass 1 and the Givens step in one launch (after the cycle's last step, the
+// block that forms the column also solves the cycle's least squares).  Every block first decides from
 // the ||Y||^2 partials of the operator pass (p0) and of pass 0 (pin) whether
 // the second sweep is needed.  Usually it is not: then block 0 alone forms
 // column j of H from pass 0's ||Y||^2 partials and the other blocks end at
@@ -2218,13 +2257,16 @@ __global__ void __launch_bounds__(AB) k_reorth_step(size_t Nf, size_t stride, co
                                                     double2* __restrict__ Y, const double* __restrict__ pin,
                                                     int nbin, double* __restrict__ pout, GmresState st,
                                                     const double* __restrict__ p0, int nb0, int j, int m,
-                                                    double tol_abs, double eta) {
+                                                    int mm, double tol_abs, double eta) {
   __shared__ double nn[2];
   __shared__ int last;
   finish_sum_pair<AB>(pin + 2 * J, nbin, 2 * J + 1, p0 + 2 * J, nb0, 2 * J + 1, nn);
   if (nn[0] >= eta * eta * nn[1]) {
     // pass 0 kept enough of the norm: its ||Y||^2 partials are the result
-    if (blockIdx.x == 0) gmres_step_blk<AB>(st, j, m, tol_abs, pin + 2 * J, nbin, 2 * J + 1);
+    if (blockIdx.x == 0) {
+      gmres_step_blk<AB>(st, j, m, tol_abs, pin + 2 * J, nbin, 2 * J + 1);
+      if (j == mm - 1) gmres_solve_blk<AB>(st, m, mm);
+    }
     return;
   }
   axpy_sweep<J, true>(Nf, stride, W, Y, pin, nbin, pout, st, 1);
@@ -2235,6 +2277,7 @@ __global__ void __launch_bounds__(AB) k_reorth_step(size_t Nf, size_t stride, co
   __threadfence();
   if (threadIdx.x == 0) st.ticket[0] = 0u;
   gmres_step_blk<AB>(st, j, m, tol_abs, pout, gridDim.x, 1);
+  if (j == mm - 1) gmres_solve_blk<AB>(st, m, mm);
 }
 #undef MGC_JFOR
 
@@ -2295,9 +2338,9 @@ __global__ void __launch_bounds__(256) k_sum_partials(int nb, int nq, const doub
 // ----------------------------------------------------------------------------
 // FGMRES bookkeeping on the device (single thread).  State layout in `st`
 // (doubles):  see GmresState in launch.h.
-__global__ void k_gmres_begin(GmresState st, int m) {
-  // start of a restart cycle: beta = sqrt(nrm2), scale_0 = 1/beta, g = (beta, 0, ...)
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// start of a restart cycle (one thread): beta = sqrt(nrm2), scale_0 = 1/beta,
+// g = (beta, 0, ...)
+__device__ void gmres_begin_thread(const GmresState& st, int m) {
   double beta = sqrt(st.nrm2[0]);
   st.scale[0] = beta > 0 ? 1.0 / beta : 0.0;
   for (int i = 0; i <= m; ++i) { st.g[2 * i] = 0; st.g[2 * i + 1] = 0; }
@@ -2305,39 +2348,26 @@ __global__ void k_gmres_begin(GmresState st, int m) {
   st.kstar[0] = -1;
   st.beta[0] = beta;
 }
+__global__ void k_gmres_begin(GmresState st, int m) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  gmres_begin_thread(st, m);
+}
 
-__global__ void __launch_bounds__(256) k_gmres_solve(GmresState st, int m, int mm) {
-  // y = H(1:k,1:k)^{-1} g(1:k); k = first step meeting the tolerance, else the
-  // mm <= m steps this cycle performed; update coefficients y_i.  H and g are
-  // staged in LDS by all threads, the back substitution runs on one thread.
-  __shared__ double Hs[2 * 33 * 32], gs[2 * 33], ys[2 * 32];
-  const int tid = threadIdx.x;
-  const int R = m + 1;
-  for (int q = tid; q < 2 * R * m; q += 256) Hs[q] = st.H[q];
-  for (int q = tid; q < 2 * R; q += 256) gs[q] = st.g[q];
-  __syncthreads();
-  if (tid == 0) {
-    const int k = (st.kstar[0] > 0 && st.kstar[0] <= mm) ? st.kstar[0] : mm;
-    st.kused[0] = k;
-    for (int i = k - 1; i >= 0; --i) {
-      double vr = gs[2 * i], vi = gs[2 * i + 1];
-      for (int c = i + 1; c < k; ++c) {
-        const double hr = Hs[2 * (c * R + i)], hi = Hs[2 * (c * R + i) + 1];
-        vr -= hr * ys[2 * c] - hi * ys[2 * c + 1];
-        vi -= hr * ys[2 * c + 1] + hi * ys[2 * c];
-      }
-      const double dr = Hs[2 * (i * R + i)], di = Hs[2 * (i * R + i) + 1];
-      const double den = dr * dr + di * di;
-      ys[2 * i] = (vr * dr + vi * di) / den;
-      ys[2 * i + 1] = (vi * dr - vr * di) / den;
-    }
-    for (int i = k; i < m; ++i) { ys[2 * i] = 0; ys[2 * i + 1] = 0; }
-  }
-  __syncthreads();
-  if (tid < m) {
-    st.y[2 * tid] = ys[2 * tid];
-    st.y[2 * tid + 1] = ys[2 * tid + 1];
-    st.upcoef[tid] = make_double2(ys[2 * tid], ys[2 * tid + 1]);
+// End of a restart cycle (one block of 256): ||r||^2 and ||f||^2 of the true
+// residual from the residual pass's per-block partials (the fixed order of
+// k_sum_partials) into scal[0..1] and ||r||^2 into the Krylov state, the
+// host's report rep = (||r||^2, ||f||^2, steps used), then the next cycle's
+// start.
+__global__ void __launch_bounds__(256) k_cycle_end(int nb, const double* __restrict__ part,
+                                                   double* __restrict__ scal, GmresState st, int m,
+                                                   double* __restrict__ rep) {
+  finish_sum(part, nb, 2, scal);
+  if (threadIdx.x == 0) {
+    st.nrm2[0] = scal[0];
+    rep[0] = scal[0];
+    rep[1] = scal[1];
+    rep[2] = (double)st.kused[0];
+    gmres_begin_thread(st, m);
   }
 }
 
@@ -2908,14 +2938,14 @@ void launch_axpy_pass(hipStream_t s, int n, int pitch, size_t stride, const doub
 
 void launch_reorth_step(hipStream_t s, int n, int pitch, size_t stride, const double2* W, int J, double2* Y,
                         const double* part0, const double* part1, double* part2, const GmresState& st, int m,
-                        double tol_abs, double eta) {
+                        int mm, double tol_abs, double eta) {
   const size_t Nf = (size_t)(n + 1) * pitch;
   const int nb = axpy_blocks(n, pitch);
   const int nb0 = (int)(apply_dot_grid(n).grid.x * apply_dot_grid(n).grid.y);
   const int j = J - 1;
 #define MGC_RS(JT)                                                                                  \
   hipLaunchKernelGGL((k_reorth_step<JT>), dim3(nb), dim3(AB), 0, s, Nf, stride, W, Y, part1, nb, part2, st, \
-                     part0, nb0, j, m, tol_abs, eta)
+                     part0, nb0, j, m, mm, tol_abs, eta)
   MGC_JSWITCH(MGC_RS)
 #undef MGC_RS
 }
@@ -2950,24 +2980,12 @@ void launch_sum_partials(hipStream_t s, int nb, int nq, const double* part, doub
 void launch_gmres_begin(hipStream_t s, const GmresState& st, int m) {
   hipLaunchKernelGGL(k_gmres_begin, dim3(1), dim3(1), 0, s, st, m);
 }
-void launch_gmres_solve(hipStream_t s, const GmresState& st, int m, int mm) {
-  hipLaunchKernelGGL(k_gmres_solve, dim3(1), dim3(256), 0, s, st, m, mm);
-}
 void launch_ir_scale(hipStream_t s, const double* nrm2, double Nn, double* sc) {
   hipLaunchKernelGGL(k_ir_scale, dim3(1), dim3(1), 0, s, nrm2, Nn, sc);
 }
-__global__ void k_report(const double* __restrict__ scal, const int* __restrict__ kused, double* rep) {
-  if (threadIdx.x == 0) {
-    rep[0] = scal[0];
-    rep[1] = scal[1];
-    rep[2] = (double)kused[0];
-  }
-}
-// An empty launch: the timer brackets it to measure what the event nodes and
-// one launch add around a bracketed run.
-
-void launch_report(hipStream_t s, const double* scal, const int* kused, double* rep) {
-  hipLaunchKernelGGL(k_report, dim3(1), dim3(64), 0, s, scal, kused, rep);
+void launch_cycle_end(hipStream_t s, int n, const double* part, double* scal, const GmresState& st, int m,
+                      double* rep) {
+  hipLaunchKernelGGL(k_cycle_end, dim3(1), dim3(256), 0, s, stencil_blocks(n), part, scal, st, m, rep);
 }
 void launch_copy_scalar(hipStream_t s, const double* src, double* dst) {
   hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, s, src, dst);

@@ -113,7 +113,9 @@ void launch_cccs(hipStream_t s, const Level<T>& L, void* u, const void* f, const
 //   reorth_step: if pass 0 kept less than eta of ||Y|| (selective
 //                re-orthogonalisation) coefficients from part1, Y -= ...,
 //                ||Y||^2 -> part2; then ||Y|| (from part2, else from pass
-//                0's part1), Hessenberg column j and its Givens rotation
+//                0's part1), Hessenberg column j and its Givens rotation;
+//                after the cycle's last step (j = mm - 1) also the small
+//                least-squares solve (kused, y, update coefficients)
 constexpr int ARNOLDI_PART = 256 * 33;
 template <typename TZ>
 void launch_apply_dot(hipStream_t s, const Level<double>& L, const void* z, size_t stride,
@@ -122,7 +124,7 @@ void launch_axpy_pass(hipStream_t s, int n, int pitch, size_t stride, const doub
                       double2* Y, const double* part0, double* part1, const GmresState& st);
 void launch_reorth_step(hipStream_t s, int n, int pitch, size_t stride, const double2* W, int J, double2* Y,
                         const double* part0, const double* part1, double* part2, const GmresState& st, int m,
-                        double tol_abs, double eta);
+                        int mm, double tol_abs, double eta);
 constexpr double REORTH_ETA = 0.05;     // default eta
 template <typename TZ>
 void launch_update(hipStream_t s, int n, int pitch, size_t stride, const void* Z, int J,
@@ -134,11 +136,14 @@ void launch_weight(hipStream_t s, int n, int pitch, const double2* w, int divide
                    double2* out);
 void launch_sum_partials(hipStream_t s, int nb, int nq, const double* part, double* out);
 void launch_gmres_begin(hipStream_t s, const GmresState& st, int m);
-void launch_gmres_solve(hipStream_t s, const GmresState& st, int m, int mm);
 void launch_ir_scale(hipStream_t s, const double* nrm2, double Nn, double* sc);
 void launch_copy_scalar(hipStream_t s, const double* src, double* dst);
-// rep[0..1] = scal[0..1] (||r||^2, ||f||^2), rep[2] = kused (device memory)
-void launch_report(hipStream_t s, const double* scal, const int* kused, double* rep);
+// End of a restart cycle: the residual pass's per-block partials (two sums
+// over launch_stencil_blocks(n) blocks) into scal[0..1] = (||r||^2, ||f||^2)
+// and st.nrm2, the report rep[0..2] = (||r||^2, ||f||^2, kused), then the
+// next cycle's start (as launch_gmres_begin).  rep: device memory.
+void launch_cycle_end(hipStream_t s, int n, const double* part, double* scal, const GmresState& st, int m,
+                      double* rep);
 void launch_fill_zero(hipStream_t s, void* p, size_t bytes);   // bytes: multiple of 16
 void launch_rhs_tp(hipStream_t s, int n, int pitch, int j0, const double2* z, double Z1, double Z2,
                    double lam, double k0, double2* chi);

@@ -184,9 +184,16 @@ int launch_cccs_reduce_blocks(int n) { return (n - 1 + 31) / 32; }
 int zeta_sweep_blocks(int top) { return (top + 7) / 8; }
 
 template <typename T, typename TU, typename TF, typename TO>
-void launch_stencil(hipStream_t s, const Level<T>&, const void* u, const void*, void*, int, double*, Finish fin) {
+void launch_stencil(hipStream_t s, const Level<T>&, const void* u, const void*, void*, int, double* part,
+                    Finish fin) {
   if (!fin.out) {
-    enqueue(s, [] {});
+    // partials only: the model keeps the two sums in part[0..1]
+    enqueue(s, [part, u] {
+      if (!part) return;
+      auto it = g_res.find(u);
+      part[0] = it == g_res.end() ? 1.0 : it->second;
+      part[1] = 1.0;
+    });
     return;
   }
   enqueue(s, [fin, u] {
@@ -274,9 +281,11 @@ void launch_axpy_pass(hipStream_t s, int, int, size_t, const double2*, int, doub
                       const GmresState&) {
   MGC_NOP(s);
 }
-void launch_reorth_step(hipStream_t s, int, int, size_t, const double2*, int, double2*, const double*, const double*,
-                        double*, const GmresState&, int, double, double) {
-  MGC_NOP(s);
+void launch_reorth_step(hipStream_t s, int, int, size_t, const double2*, int J, double2*, const double*,
+                        const double*, double*, const GmresState& st, int, int mm, double, double) {
+  int* k = st.kused;
+  if (J == mm) enqueue(s, [k, mm] { k[0] = mm; });   // the cycle's least squares
+  else MGC_NOP(s);
 }
 template <typename TZ>
 void launch_update(hipStream_t s, int n, int, size_t, const void*, int, const double2*, double2* u) {
@@ -301,10 +310,6 @@ void launch_sum_partials(hipStream_t s, int, int nq, const double*, double* out)
   });
 }
 void launch_gmres_begin(hipStream_t s, const GmresState&, int) { MGC_NOP(s); }
-void launch_gmres_solve(hipStream_t s, const GmresState& st, int, int mm) {
-  int* k = st.kused;
-  enqueue(s, [k, mm] { k[0] = mm; });
-}
 void launch_ir_scale(hipStream_t s, const double*, double, double* sc) {
   enqueue(s, [sc] {
     sc[0] = 1.0;
@@ -315,8 +320,14 @@ void launch_ir_scale(hipStream_t s, const double*, double, double* sc) {
 void launch_copy_scalar(hipStream_t s, const double* src, double* dst) {
   enqueue(s, [=] { dst[0] = src[0]; });
 }
-void launch_report(hipStream_t s, const double* scal, const int* kused, double* rep) {
+void launch_cycle_end(hipStream_t s, int, const double* part, double* scal, const GmresState& st, int,
+                      double* rep) {
+  double* nrm2 = st.nrm2;
+  const int* kused = st.kused;
   enqueue(s, [=] {
+    scal[0] = part[0];
+    scal[1] = part[1];
+    nrm2[0] = part[0];
     rep[0] = scal[0];
     rep[1] = scal[1];
     rep[2] = (double)kused[0];
