@@ -921,8 +921,10 @@ void enqueue_fgmres_cycle(mgc_grid g, void* u, const mgc_solve_opts* o, double t
     // algorithmic bytes: z (inner precision), J basis vectors, Y written
     const int ta = kt_slot(g, MGC_KT_APPLY_DOT, Nint * ((f32 ? 8.0 : 16.0) + 16.0 * (j + 1) + 16.0));
     if (f32) {
-      launch_scale_copy<double, float>(st, n, pitch, pitch, Wj, gs.scale + j, g->ws + g->f32);
-      precondition<float>(g, Zj, g->ws + g->f32);
+      // the FP32 cycle's input: W_j rounded to FP32 (by the previous step's
+      // Gram-Schmidt passes for j > 0), scaled by s_j on the fly
+      if (j == 0) launch_scale_copy<double, float>(st, n, pitch, pitch, Wj, nullptr, g->ws + g->f32);
+      precondition<float>(g, Zj, g->ws + g->f32, gs.scale + j);
       kt_mark(g, st, ta, 0);
       launch_apply_dot<float>(st, EX, Zj, stride64, W, j + 1, Wn, p0);
     } else {
@@ -934,11 +936,13 @@ void enqueue_fgmres_cycle(mgc_grid g, void* u, const mgc_solve_opts* o, double t
     // classical Gram-Schmidt with a selective second pass, then the
     // Hessenberg column and its Givens rotation on the device
     // timed: the first pass (the second one runs only when needed)
-    const int tx = kt_slot(g, MGC_KT_AXPY, Nint * (16.0 * (j + 1) + 32.0));    // J in, Y in/out
+    // J in, Y in/out (and its FP32 copy out with the FP32 cycle)
+    float2* y32 = f32 ? (float2*)(g->ws + g->f32) : nullptr;
+    const int tx = kt_slot(g, MGC_KT_AXPY, Nint * (16.0 * (j + 1) + 32.0 + (f32 ? 8.0 : 0.0)));
     kt_mark(g, st, tx, 0);
-    launch_axpy_pass(st, n, pitch, stride64, W, j + 1, Wn, p0, p1, gs);
+    launch_axpy_pass(st, n, pitch, stride64, W, j + 1, Wn, y32, p0, p1, gs);
     kt_mark(g, st, tx, 1);
-    launch_reorth_step(st, n, pitch, stride64, W, j + 1, Wn, p0, p1, p2, gs, m, mm, tol_abs, eta);
+    launch_reorth_step(st, n, pitch, stride64, W, j + 1, Wn, y32, p0, p1, p2, gs, m, mm, tol_abs, eta);
   }
   g->kt.open = true;
   if (f32) launch_update<float>(st, n, pitch, stridez, Z, mm, gs.upcoef, (double2*)u);

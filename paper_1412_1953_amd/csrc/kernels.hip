@@ -2183,10 +2183,12 @@ __global__ void __launch_bounds__(AB) k_apply_dot(Level<double> L, const v2<TZ>*
 // Flat axpy sweep over Nf = (n+1) * pitch nodes.  pin: nbin x (2J + 1)
 // per-block dots and ||Y||^2 of the previous pass; pass 0 starts the
 // projections h, pass 1 adds.  Pass 0 writes the new per-block dots and
-// ||Y||^2, pass 1 (NORM) ||Y||^2 only, to pout.
+// ||Y||^2, pass 1 (NORM) ||Y||^2 only, to pout.  Y32 (nullable): the new
+// vector also rounded to FP32, unscaled (the FP32 cycle's input, same pitch).
 template <int J, bool NORM>
 __device__ __forceinline__ void axpy_sweep(size_t Nf, size_t stride, const double2* __restrict__ W,
-                                           double2* __restrict__ Y, const double* __restrict__ pin, int nbin,
+                                           double2* __restrict__ Y, float2* __restrict__ Y32,
+                                           const double* __restrict__ pin, int nbin,
                                            double* __restrict__ pout, const GmresState& st, int pass) {
   constexpr int NV = NORM ? 1 : 2 * J + 1;
   __shared__ double dsum[2 * J + 1];
@@ -2219,6 +2221,7 @@ __device__ __forceinline__ void axpy_sweep(size_t Nf, size_t stride, const doubl
       y.y -= c[q].x * w[q].y + c[q].y * w[q].x;
     }
     Y[i] = y;
+    if (Y32) Y32[i] = make_float2((float)y.x, (float)y.y);
     if (NORM) {
       acc[0] += y.x * y.x + y.y * y.y;
     } else {
@@ -2239,9 +2242,10 @@ __device__ __forceinline__ void axpy_sweep(size_t Nf, size_t stride, const doubl
 
 template <int J>
 __global__ void __launch_bounds__(AB) k_axpy_pass(size_t Nf, size_t stride, const double2* __restrict__ W,
-                                                  double2* __restrict__ Y, const double* __restrict__ pin,
-                                                  int nbin, double* __restrict__ pout, GmresState st) {
-  axpy_sweep<J, false>(Nf, stride, W, Y, pin, nbin, pout, st, 0);
+                                                  double2* __restrict__ Y, float2* __restrict__ Y32,
+                                                  const double* __restrict__ pin, int nbin,
+                                                  double* __restrict__ pout, GmresState st) {
+  axpy_sweep<J, false>(Nf, stride, W, Y, Y32, pin, nbin, pout, st, 0);
 }
 
 // Pass 1 and the Givens step in one launch (after the cycle's last step, the
@@ -2254,7 +2258,8 @@ __global__ void __launch_bounds__(AB) k_axpy_pass(size_t Nf, size_t stride, cons
 // forms the column from the sweep's partials and clears the ticket.
 template <int J>
 __global__ void __launch_bounds__(AB) k_reorth_step(size_t Nf, size_t stride, const double2* __restrict__ W,
-                                                    double2* __restrict__ Y, const double* __restrict__ pin,
+                                                    double2* __restrict__ Y, float2* __restrict__ Y32,
+                                                    const double* __restrict__ pin,
                                                     int nbin, double* __restrict__ pout, GmresState st,
                                                     const double* __restrict__ p0, int nb0, int j, int m,
                                                     int mm, double tol_abs, double eta) {
@@ -2269,7 +2274,7 @@ __global__ void __launch_bounds__(AB) k_reorth_step(size_t Nf, size_t stride, co
     }
     return;
   }
-  axpy_sweep<J, true>(Nf, stride, W, Y, pin, nbin, pout, st, 1);
+  axpy_sweep<J, true>(Nf, stride, W, Y, Y32, pin, nbin, pout, st, 1);
   __threadfence();
   if (threadIdx.x == 0) last = atomicAdd(st.ticket, 1u) == gridDim.x - 1 ? 1 : 0;
   __syncthreads();
@@ -2926,25 +2931,25 @@ template void launch_apply_dot<float>(hipStream_t, const Level<double>&, const v
                                       int, double2*, double*);
 
 void launch_axpy_pass(hipStream_t s, int n, int pitch, size_t stride, const double2* W, int J,
-                      double2* Y, const double* part0, double* part1, const GmresState& st) {
+                      double2* Y, float2* Y32, const double* part0, double* part1, const GmresState& st) {
   const size_t Nf = (size_t)(n + 1) * pitch;
   const int nb = axpy_blocks(n, pitch);
   const int nb0 = (int)(apply_dot_grid(n).grid.x * apply_dot_grid(n).grid.y);
 #define MGC_AXD(JT)                                                                                 \
-  hipLaunchKernelGGL((k_axpy_pass<JT>), dim3(nb), dim3(AB), 0, s, Nf, stride, W, Y, part0, nb0, part1, st)
+  hipLaunchKernelGGL((k_axpy_pass<JT>), dim3(nb), dim3(AB), 0, s, Nf, stride, W, Y, Y32, part0, nb0, part1, st)
   MGC_JSWITCH(MGC_AXD)
 #undef MGC_AXD
 }
 
 void launch_reorth_step(hipStream_t s, int n, int pitch, size_t stride, const double2* W, int J, double2* Y,
-                        const double* part0, const double* part1, double* part2, const GmresState& st, int m,
+                        float2* Y32, const double* part0, const double* part1, double* part2, const GmresState& st, int m,
                         int mm, double tol_abs, double eta) {
   const size_t Nf = (size_t)(n + 1) * pitch;
   const int nb = axpy_blocks(n, pitch);
   const int nb0 = (int)(apply_dot_grid(n).grid.x * apply_dot_grid(n).grid.y);
   const int j = J - 1;
 #define MGC_RS(JT)                                                                                  \
-  hipLaunchKernelGGL((k_reorth_step<JT>), dim3(nb), dim3(AB), 0, s, Nf, stride, W, Y, part1, nb, part2, st, \
+  hipLaunchKernelGGL((k_reorth_step<JT>), dim3(nb), dim3(AB), 0, s, Nf, stride, W, Y, Y32, part1, nb, part2, st, \
                      part0, nb0, j, m, mm, tol_abs, eta)
   MGC_JSWITCH(MGC_RS)
 #undef MGC_RS

@@ -120,10 +120,12 @@ constexpr int ARNOLDI_PART = 256 * 33;
 template <typename TZ>
 void launch_apply_dot(hipStream_t s, const Level<double>& L, const void* z, size_t stride,
                       const double2* W, int J, double2* Y, double* part0);
+// Y32 (nullable, both passes): the new vector also written rounded to FP32,
+// unscaled, with the FP64 fields' pitch (the FP32 cycle's input of the next step)
 void launch_axpy_pass(hipStream_t s, int n, int pitch, size_t stride, const double2* W, int J,
-                      double2* Y, const double* part0, double* part1, const GmresState& st);
+                      double2* Y, float2* Y32, const double* part0, double* part1, const GmresState& st);
 void launch_reorth_step(hipStream_t s, int n, int pitch, size_t stride, const double2* W, int J, double2* Y,
-                        const double* part0, const double* part1, double* part2, const GmresState& st, int m,
+                        float2* Y32, const double* part0, const double* part1, double* part2, const GmresState& st, int m,
                         int mm, double tol_abs, double eta);
 constexpr double REORTH_ETA = 0.05;     // default eta
 template <typename TZ>

@@ -277,11 +277,11 @@ template void launch_apply_dot<double>(hipStream_t, const Level<double>&, const 
                                        double2*, double*);
 template void launch_apply_dot<float>(hipStream_t, const Level<double>&, const void*, size_t, const double2*, int,
                                       double2*, double*);
-void launch_axpy_pass(hipStream_t s, int, int, size_t, const double2*, int, double2*, const double*, double*,
-                      const GmresState&) {
+void launch_axpy_pass(hipStream_t s, int, int, size_t, const double2*, int, double2*, float2*, const double*,
+                      double*, const GmresState&) {
   MGC_NOP(s);
 }
-void launch_reorth_step(hipStream_t s, int, int, size_t, const double2*, int J, double2*, const double*,
+void launch_reorth_step(hipStream_t s, int, int, size_t, const double2*, int J, double2*, float2*, const double*,
                         const double*, double*, const GmresState& st, int, int mm, double, double) {
   int* k = st.kused;
   if (J == mm) enqueue(s, [k, mm] { k[0] = mm; });   // the cycle's least squares
