@@ -102,6 +102,16 @@ def run_step(problems, inner, torch, max_it, tol=1e-10, outer=None):
     return out
 
 
+def rel_diff(problems, ref):
+    """Relative 2-norm difference of each handle's current solution from the
+    reference solution (the FP64 FGMRES step's), over the interior nodes."""
+    out = []
+    for (_, _, _, u), r in zip(problems, ref):
+        a, b = u[1:-1, 1:-1], r[1:-1, 1:-1]
+        out.append(float((a - b).norm() / b.norm()))
+    return out
+
+
 def use_schedule(problems, inner, wls):
     """The tuned launch schedule of each handle for the cycle precision."""
     from paper_1412_1953_amd import autotune, mgcccs
@@ -210,14 +220,19 @@ def c2_leg(torch, max_it):
     from paper_1412_1953_amd.workloads import TP2049 as w
     prob = make_problem(w, torch)
     out = {"workload": w.name, "n": w.n, "E": w.E, "tol": w.tol}
+    ref = None
     for name, inner in (("fp64", mgcccs.FP64), ("mixed", mgcccs.FP32)):
         use_schedule([prob], inner, [w])
         dt, res, _ = time_steps([prob], inner, torch, 1, 1, max_it)
         r = res[0]
         out[name] = {"value": w.unknowns / dt, "ms": dt * 1e3, "iters": r.iters, "relres": r.relres,
                      "status": r.status}
+        if ref is None:
+            ref = [prob[3].clone()]
+        else:
+            out[name]["rel_diff_vs_fp64"] = rel_diff([prob], ref)[0]
     out["speedup_mixed_vs_fp64"] = out["mixed"]["value"] / out["fp64"]["value"]
-    del prob
+    del prob, ref
     torch.cuda.empty_cache()
     return out
 
@@ -252,6 +267,7 @@ def c3_leg(torch, max_it):
     out["batched_mixed"] = {"value": unknowns / dtb, "s": dtb, "iters": sum(r.iters for r in rb),
                             "max_relres": max(r.relres for r in rb),
                             "converged": sum(r.status == mgcccs.MGC_OK for r in rb)}
+    mixed_sol = [p[3].clone() for p in probs]
     for (g, *_), w in zip(probs, wls):
         g.set_schedule(*autotune.schedule_of(w, False))
     for timed in (False, True):
@@ -263,8 +279,11 @@ def c3_leg(torch, max_it):
     out["sequential_fp64"] = {"value": unknowns / dts, "s": dts, "iters": sum(r.iters for r in rs),
                               "max_relres": max(r.relres for r in rs),
                               "converged": sum(r.status == mgcccs.MGC_OK for r in rs)}
+    # the batched mixed solutions against the FP64 ones (their largest difference)
+    out["batched_mixed"]["max_rel_diff_vs_fp64"] = max(
+        rel_diff([(None, None, None, m) for m in mixed_sol], [p[3] for p in probs]))
     out["speedup_batched_mixed_vs_fp64"] = dts / dtb
-    del batch, probs
+    del batch, probs, mixed_sol
     torch.cuda.empty_cache()
     return out
 
@@ -469,6 +488,8 @@ def main():
                  "status": [r.status for r in r64],
                  "vcycles_per_s": sum(r.vcycles for r in r64) / dt64},
     }
+    # the FP64 step's solutions: every other mode's error is stated against them
+    ref = [p[3].clone() for p in problems]
     fig = kernel_figure(kt)
     if fig is not None:
         line["roofline"] = {"bound": "hbm", "achieved": fig["achieved_gbs"], "peak": HBM_PEAK_GBS,
@@ -490,6 +511,7 @@ def main():
         line["mixed"] = {"value": unknowns / dt32, "ms_per_step": dt32 * 1e3,
                          "iters": [r.iters for r in r32], "relres": [r.relres for r in r32],
                          "status": [r.status for r in r32],
+                         "rel_diff_vs_fp64": rel_diff(problems, ref),
                          "speedup_vs_fp64": dt64 / dt32}
     if not a.no_bicgstab:
         # the same step with MG-CCCS-preconditioned BiCGSTAB as the outer solver
@@ -500,7 +522,8 @@ def main():
             dtb, rb, _ = time_steps(problems, inner, torch, a.steps, a.warmup, a.max_it, outer=mgcccs.BICGSTAB)
             line["bicgstab"][name] = {"value": unknowns / dtb, "ms_per_step": dtb * 1e3,
                                       "iters": [r.iters for r in rb], "relres": [r.relres for r in rb],
-                                      "status": [r.status for r in rb], "speedup_vs_fp64_fgmres": dt64 / dtb}
+                                      "status": [r.status for r in rb], "rel_diff_vs_fp64": rel_diff(problems, ref),
+                                      "speedup_vs_fp64_fgmres": dt64 / dtb}
     if not a.no_batch:
         for name, inner in (("batched", mgcccs.FP64), ("batched_mixed", mgcccs.FP32)):
             use_schedule(problems, inner, wls)
@@ -508,6 +531,7 @@ def main():
             line[name] = {"value": unknowns / dtb, "ms_per_step": dtb * 1e3,
                           "iters": [r.iters for r in rb], "relres": [r.relres for r in rb],
                           "status": [r.status for r in rb],
+                          "rel_diff_vs_fp64": rel_diff(problems, ref),
                           "speedup_vs_fp64": dt64 / dtb}
     if not a.no_sweep:
         line["sweep"] = time_sweep(problems[0], w0.E, torch)
@@ -515,7 +539,7 @@ def main():
         use_schedule(problems, mgcccs.FP64, wls)
         line["kernels"] = per_kernel(problems, mgcccs.FP64, torch, a.max_it, PROBE_KERNELS)
     iters_needed = [r.iters for r in r64]
-    del problems
+    del problems, ref
     torch.cuda.empty_cache()
     if not a.no_c2:
         line["c2"] = c2_leg(torch, a.max_it)
