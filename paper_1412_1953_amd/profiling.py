@@ -3,6 +3,7 @@
     python3 -m paper_1412_1953_amd.profiling stats <kernel_stats.csv> <kernel_trace.csv> <out.txt> -- <command>
     python3 -m paper_1412_1953_amd.profiling traffic <kernel> <fetch.csv> <write.csv> <out.txt> [--largest] -- <command>
     python3 -m paper_1412_1953_amd.profiling counters <counters.csv>[,<more.csv>] <out.txt> <kernel>... [--largest] -- <command>
+    python3 -m paper_1412_1953_amd.profiling gaps <kernel_trace.csv> <hip_api_trace.csv> <out.txt> -- <command>
 
 `stats` lists the kernels by total time (rocprofv3 --kernel-trace --stats)
 and, per kernel, the launch shapes (grid sizes) with their average duration.
@@ -16,6 +17,11 @@ while that source is unchanged.
 kernel class (a class of the library's timer or a kernel-name pattern):
 derived metrics such as VALUBusy, VALUUtilization, OccupancyPercent and
 LDSBankConflict, and raw ones such as SQ_WAVES or SQ_INSTS_VALU.
+`gaps` reads a kernel trace with the HIP runtime trace (rocprofv3
+--kernel-trace --hip-runtime-trace): the idle time of the GPU between one
+restart cycle's last kernel (k_cycle_end) and the next kernel, the idle
+time between consecutive kernels overall, and the host time spent in each
+HIP runtime call.
 """
 from __future__ import annotations
 
@@ -187,6 +193,35 @@ def counters(csv_path, out, classes, command, largest=False):
         fh.write("\n".join(lines) + "\n")
 
 
+def gaps(kernel_csv, api_csv, out, command):
+    with open(kernel_csv) as fh:
+        ks = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"])
+                    for r in csv.DictReader(fh))
+    after_cycle = sorted((ks[i + 1][0] - e) / 1e3 for i, (s, e, nm) in enumerate(ks[:-1]) if "k_cycle_end" in nm)
+    between = sorted(max(0, ks[i + 1][0] - ks[i][1]) / 1e3 for i in range(len(ks) - 1))
+    med = lambda v: v[len(v) // 2] if v else float("nan")
+    lines = [f"command: {command}", f"kernels.hip sha256: {source_sha()}",
+             f"kernels traced: {len(ks)}, span {(ks[-1][1] - ks[0][0]) / 1e6:.3f} ms, "
+             f"busy {sum(e - s for s, e, _ in ks) / 1e6:.3f} ms", "",
+             "GPU idle time (us)          count    median       min       max",
+             f"after k_cycle_end       {len(after_cycle):10d} {med(after_cycle):9.2f} "
+             f"{after_cycle[0] if after_cycle else float('nan'):9.2f} "
+             f"{after_cycle[-1] if after_cycle else float('nan'):9.2f}",
+             f"between kernels         {len(between):10d} {med(between):9.2f} "
+             f"{between[int(0.9 * len(between))] if between else float('nan'):9.2f} (p90) "
+             f"{between[-1] if between else float('nan'):9.2f}", "",
+             "host time in HIP runtime calls (us)", f"{'call':32s} {'count':>7s} {'total ms':>10s} {'median':>9s}"]
+    agg = collections.defaultdict(list)
+    with open(api_csv) as fh:
+        for r in csv.DictReader(fh):
+            agg[r["Function"]].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    for fn, v in sorted(agg.items(), key=lambda x: -sum(x[1]))[:12]:
+        v.sort()
+        lines.append(f"{fn:32s} {len(v):7d} {sum(v) / 1e3:10.2f} {med(v):9.2f}")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def main(argv):
     if "--" not in argv:
         raise SystemExit(__doc__)
@@ -199,6 +234,8 @@ def main(argv):
     elif args[0] == "counters":
         counters(args[1], args[2], [a for a in args[3:] if a != "--largest"], command,
                  largest="--largest" in args)
+    elif args[0] == "gaps":
+        gaps(args[1], args[2], args[3], command)
     else:
         raise SystemExit(__doc__)
 
