@@ -1078,19 +1078,18 @@ void enqueue_bicg_iteration(mgc_grid g, void* u, const mgc_solve_opts* o, double
   Level<double> EX = exact_level(g);
   hipStream_t saved = g->stream;
   g->stream = st;
+  // with the FP32 cycle, the p and s passes also write their vector rounded
+  // to FP32 into the cycle's input field
+  float2* in32 = f32 ? (float2*)(g->ws + g->f32) : nullptr;
   auto apply_pc = [&](const double2* in, void* out) {
-    if (f32) {
-      launch_scale_copy<double, float>(st, n, pitch, pitch, in, nullptr, g->ws + g->f32);
-      precondition<float>(g, out, g->ws + g->f32);
-    } else {
-      precondition<double>(g, out, in);
-    }
+    if (f32) precondition<float>(g, out, in32);
+    else precondition<double>(g, out, in);
   };
-  launch_bicg_p(st, n, pitch, r, v, p, bs);
+  launch_bicg_p(st, n, pitch, r, v, p, in32, bs);
   apply_pc(p, ph);
   if (f32) launch_apply_dot<float>(st, EX, ph, s64, rt, 1, v, p0);
   else launch_apply_dot<double>(st, EX, ph, s64, rt, 1, v, p0);
-  launch_bicg_s(st, n, pitch, p0, bs, r, v, sv, p1);
+  launch_bicg_s(st, n, pitch, p0, bs, r, v, sv, in32, p1);
   apply_pc(sv, sh);
   if (f32) launch_apply_dot<float>(st, EX, sh, s64, sv, 1, t, p2);
   else launch_apply_dot<double>(st, EX, sh, s64, sv, 1, t, p2);

@@ -3562,21 +3562,25 @@ __global__ void k_bicg_init(double* bs, const double* nrm2) {
   bs[BS_SS] = 0.0;
   bs[BS_CONV] = 0.0;
 }
+// p32, s32 (nullable): the new vector also rounded to FP32 (the FP32 cycle's
+// input, same pitch)
 __global__ void __launch_bounds__(AB) k_bicg_p(size_t Nf, const double2* __restrict__ r,
                                                const double2* __restrict__ v, double2* __restrict__ p,
-                                               const double* __restrict__ bs) {
+                                               float2* __restrict__ p32, const double* __restrict__ bs) {
   const double2 beta = make_double2(bs[BS_BETA], bs[BS_BETA + 1]);
   const double2 om = make_double2(bs[BS_OMEGA], bs[BS_OMEGA + 1]);
   for (size_t i = (size_t)blockIdx.x * AB + threadIdx.x; i < Nf; i += (size_t)gridDim.x * AB) {
     const double2 pv = p[i], vv = v[i], rv = r[i];
     const double2 d = make_double2(pv.x - (om.x * vv.x - om.y * vv.y), pv.y - (om.x * vv.y + om.y * vv.x));
-    p[i] = make_double2(rv.x + (beta.x * d.x - beta.y * d.y), rv.y + (beta.x * d.y + beta.y * d.x));
+    const double2 pn = make_double2(rv.x + (beta.x * d.x - beta.y * d.y), rv.y + (beta.x * d.y + beta.y * d.x));
+    p[i] = pn;
+    if (p32) p32[i] = make_float2((float)pn.x, (float)pn.y);
   }
 }
 __global__ void __launch_bounds__(AB) k_bicg_s(size_t Nf, const double* __restrict__ pin, int nbin,
                                                double* __restrict__ bs, const double2* __restrict__ r,
                                                const double2* __restrict__ v, double2* __restrict__ sv,
-                                               double* __restrict__ pout) {
+                                               float2* __restrict__ s32, double* __restrict__ pout) {
   __shared__ double dsum[3];
   finish_sum_nt<AB>(pin, nbin, 3, dsum);       // r~^H v, ||v||^2
   const double2 rho = make_double2(bs[BS_RHO], bs[BS_RHO + 1]);
@@ -3590,6 +3594,7 @@ __global__ void __launch_bounds__(AB) k_bicg_s(size_t Nf, const double* __restri
     const double2 rv = r[i], vv = v[i];
     const double2 sx = make_double2(rv.x - (alpha.x * vv.x - alpha.y * vv.y), rv.y - (alpha.x * vv.y + alpha.y * vv.x));
     sv[i] = sx;
+    if (s32) s32[i] = make_float2((float)sx.x, (float)sx.y);
     acc[0] += sx.x * sx.x + sx.y * sx.y;
   }
   double tot[1];
@@ -3741,14 +3746,15 @@ void launch_bicg_init(hipStream_t s, double* bs, const double* nrm2) {
   hipLaunchKernelGGL(k_bicg_init, dim3(1), dim3(1), 0, s, bs, nrm2);
 }
 void launch_bicg_p(hipStream_t s, int n, int pitch, const double2* r, const double2* v, double2* p,
-                   const double* bs) {
-  hipLaunchKernelGGL(k_bicg_p, dim3(axpy_blocks(n, pitch)), dim3(AB), 0, s, (size_t)(n + 1) * pitch, r, v, p, bs);
+                   float2* p32, const double* bs) {
+  hipLaunchKernelGGL(k_bicg_p, dim3(axpy_blocks(n, pitch)), dim3(AB), 0, s, (size_t)(n + 1) * pitch, r, v, p, p32,
+                     bs);
 }
 void launch_bicg_s(hipStream_t s, int n, int pitch, const double* part_ad, double* bs, const double2* r,
-                   const double2* v, double2* sv, double* part_s) {
+                   const double2* v, double2* sv, float2* s32, double* part_s) {
   const ApplyGrid ag = apply_dot_grid(n);
   hipLaunchKernelGGL(k_bicg_s, dim3(axpy_blocks(n, pitch)), dim3(AB), 0, s, (size_t)(n + 1) * pitch, part_ad,
-                     (int)(ag.grid.x * ag.grid.y), bs, r, v, sv, part_s);
+                     (int)(ag.grid.x * ag.grid.y), bs, r, v, sv, s32, part_s);
 }
 template <typename TZ>
 void launch_bicg_x(hipStream_t s, int n, int pitch, const double* part_ad, const double* part_s, double tol2,

@@ -189,10 +189,12 @@ void launch_add(hipStream_t s, int n, int pitch, const void* e, void* u);
 // BiCGSTAB (see kernels.hip): bs = device scalar state (11 doubles); the
 // partial buffers hold at most 3 x 512 doubles.
 void launch_bicg_init(hipStream_t s, double* bs, const double* nrm2);
+// p32 / s32 (nullable): the new p / s also written rounded to FP32 (the FP32
+// cycle's input), with the FP64 fields' pitch
 void launch_bicg_p(hipStream_t s, int n, int pitch, const double2* r, const double2* v, double2* p,
-                   const double* bs);
+                   float2* p32, const double* bs);
 void launch_bicg_s(hipStream_t s, int n, int pitch, const double* part_ad, double* bs, const double2* r,
-                   const double2* v, double2* sv, double* part_s);
+                   const double2* v, double2* sv, float2* s32, double* part_s);
 template <typename TZ>
 void launch_bicg_x(hipStream_t s, int n, int pitch, const double* part_ad, const double* part_s, double tol2,
                    double* bs, const void* ph, const void* sh, const double2* sv, const double2* t, const double2* rt,

@@ -372,8 +372,11 @@ template void launch_gs_tail<double>(hipStream_t, const GsTailArgs<double>&);
 template void launch_gs_tail<float>(hipStream_t, const GsTailArgs<float>&);
 template void launch_add<double>(hipStream_t, int, int, const void*, void*);
 template void launch_add<float>(hipStream_t, int, int, const void*, void*);
-void launch_bicg_p(hipStream_t s, int, int, const double2*, const double2*, double2*, const double*) { MGC_NOP(s); }
-void launch_bicg_s(hipStream_t s, int, int, const double*, double*, const double2*, const double2*, double2*, double*) {
+void launch_bicg_p(hipStream_t s, int, int, const double2*, const double2*, double2*, float2*, const double*) {
+  MGC_NOP(s);
+}
+void launch_bicg_s(hipStream_t s, int, int, const double*, double*, const double2*, const double2*, double2*, float2*,
+                   double*) {
   MGC_NOP(s);
 }
 template <typename TZ>
